@@ -1,0 +1,724 @@
+// rt_capi.hip -- the C ABI of librtrom: argument validation, quadrature,
+// device arena layout, the time-marching driver and accessors.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rt_host.h"
+
+namespace {
+thread_local std::string g_err;
+}
+void rt_set_error(const std::string &m) { g_err = m; }
+
+extern "C" const char *rtrom_last_error(void) { return g_err.c_str(); }
+
+#define RT_HIP(call, msg)                                                      \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      rt_set_error(std::string(msg) + ": " + hipGetErrorString(e_));           \
+      return RTROM_EDEVICE;                                                    \
+    }                                                                          \
+  } while (0)
+
+static rtrom_status fail(rtrom_status s, const std::string &m) {
+  rt_set_error(m);
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel timing
+// ---------------------------------------------------------------------------
+namespace {
+struct Prof {
+  bool on = false;
+  double sec[RT_NKINDS] = {0};
+  int64_t cnt[RT_NKINDS] = {0};
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<int> kinds;  // per event pair
+};
+Prof g_prof;
+hipEvent_t prof_event() {
+  if (g_prof.used == g_prof.pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g_prof.pool.push_back(e);
+  }
+  return g_prof.pool[g_prof.used++];
+}
+}  // namespace
+
+void rt_prof_begin(int kind, hipStream_t s) {
+  if (!g_prof.on) return;
+  hipEvent_t e = prof_event();
+  if (e) (void)hipEventRecord(e, s);
+  g_prof.kinds.push_back(kind);
+}
+void rt_prof_end(int kind, hipStream_t s) {
+  (void)kind;
+  if (!g_prof.on) return;
+  hipEvent_t e = prof_event();
+  if (e) (void)hipEventRecord(e, s);
+}
+void rt_prof_collect() {
+  if (!g_prof.on) return;
+  for (size_t k = 0; k < g_prof.kinds.size() && 2 * k + 1 < g_prof.used; ++k) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, g_prof.pool[2 * k], g_prof.pool[2 * k + 1]) == hipSuccess) {
+      g_prof.sec[g_prof.kinds[k]] += ms * 1e-3;
+      g_prof.cnt[g_prof.kinds[k]] += 1;
+    }
+  }
+  g_prof.kinds.clear();
+  g_prof.used = 0;
+}
+
+extern "C" rtrom_status rtrom_profile_enable(int32_t on) {
+  g_prof.on = on != 0;
+  for (int k = 0; k < RT_NKINDS; ++k) {
+    g_prof.sec[k] = 0.0;
+    g_prof.cnt[k] = 0;
+  }
+  g_prof.kinds.clear();
+  g_prof.used = 0;
+  return RTROM_OK;
+}
+
+extern "C" rtrom_status rtrom_profile_read(double *seconds, int64_t *launches, int32_t nkinds) {
+  if (!seconds || !launches || nkinds < 0) return fail(RTROM_EINVAL, "bad argument");
+  for (int k = 0; k < nkinds; ++k) {
+    seconds[k] = k < RT_NKINDS ? g_prof.sec[k] : 0.0;
+    launches[k] = k < RT_NKINDS ? g_prof.cnt[k] : 0;
+  }
+  return RTROM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Quadrature (host, FP64)
+// ---------------------------------------------------------------------------
+
+// Gauss-Legendre nodes by Newton's method on P_n from Tricomi's asymptotic
+// initial guess; weights 2 / ((1 - x^2) P_n'(x)^2) scaled to sum to one.
+extern "C" rtrom_status rtrom_gauss_legendre(int32_t n, double *mu, double *w) {
+  if (n < 1 || !mu || !w) return fail(RTROM_EINVAL, "gauss_legendre: n >= 1 and non-null outputs required");
+  const double pi = 3.14159265358979323846;
+  for (int k = 1; k <= n; ++k) {
+    // k-th largest root
+    double th = pi * (4.0 * k - 1.0) / (4.0 * n + 2.0);
+    double x = (1.0 - (n - 1.0) / (8.0 * n * n * n)) * std::cos(th);
+    double dp = 1.0;
+    for (int it = 0; it < 60; ++it) {
+      double pm1 = 1.0, p = x;  // P_0, P_1
+      for (int j = 2; j <= n; ++j) {
+        double pn = ((2 * j - 1) * x * p - (j - 1) * pm1) / j;
+        pm1 = p;
+        p = pn;
+      }
+      if (n == 1) {
+        p = x;
+        pm1 = 1.0;
+      }
+      dp = n * (pm1 - x * p) / (1.0 - x * x);
+      double dx = p / dp;
+      x -= dx;
+      if (std::fabs(dx) <= 4e-16 * std::fabs(x) + 1e-300) {
+        // one more evaluation of the derivative at the converged node
+        pm1 = 1.0;
+        p = x;
+        for (int j = 2; j <= n; ++j) {
+          double pn = ((2 * j - 1) * x * p - (j - 1) * pm1) / j;
+          pm1 = p;
+          p = pn;
+        }
+        dp = (n == 1) ? 1.0 : n * (pm1 - x * p) / (1.0 - x * x);
+        break;
+      }
+    }
+    mu[n - k] = x;
+    w[n - k] = 1.0 / ((1.0 - x * x) * dp * dp);
+  }
+  // exact symmetry of the rule (nodes +-x share a weight)
+  for (int i = 0; i < n / 2; ++i) {
+    double a = 0.5 * (std::fabs(mu[i]) + std::fabs(mu[n - 1 - i]));
+    double ww = 0.5 * (w[i] + w[n - 1 - i]);
+    mu[i] = -a;
+    mu[n - 1 - i] = a;
+    w[i] = w[n - 1 - i] = ww;
+  }
+  if (n % 2) mu[n / 2] = 0.0;
+  return RTROM_OK;
+}
+
+// CL(N_phi, N_z) (App. A): azimuths (2k-1) pi / N_phi with weight 1/N_phi,
+// Gauss-Legendre in z; ordering j = j2 * N_phi + j1.
+extern "C" rtrom_status rtrom_cl_quadrature(int32_t n_azim, int32_t n_polar, double *ox, double *oy,
+                                            double *oz, double *w) {
+  if (n_azim < 1 || n_polar < 1 || !ox || !oy || !oz || !w)
+    return fail(RTROM_EINVAL, "cl_quadrature: positive orders and non-null outputs required");
+  std::vector<double> z(n_polar), wz(n_polar);
+  rtrom_gauss_legendre(n_polar, z.data(), wz.data());
+  const double pi = 3.14159265358979323846;
+  for (int j2 = 0; j2 < n_polar; ++j2) {
+    double sn = std::sqrt(std::max(0.0, 1.0 - z[j2] * z[j2]));
+    for (int j1 = 0; j1 < n_azim; ++j1) {
+      double phi = (2.0 * j1 + 1.0) * pi / n_azim;
+      int j = j2 * n_azim + j1;
+      ox[j] = std::cos(phi) * sn;
+      oy[j] = std::sin(phi) * sn;
+      oz[j] = z[j2];
+      w[j] = wz[j2] / n_azim;
+    }
+  }
+  return RTROM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Validation (host only, before any device call)
+// ---------------------------------------------------------------------------
+static const int RT_SLAB_MAX_CELLS = 4096;
+
+static rtrom_status validate(const rtrom_problem_desc *d) {
+  if (!d) return fail(RTROM_EINVAL, "null description");
+  if (d->dim != 1 && d->dim != 2) return fail(RTROM_EINVAL, "dim must be 1 or 2");
+  if (d->nx < 1 || d->ny < 1) return fail(RTROM_EINVAL, "nx, ny must be >= 1");
+  if (d->dim == 1 && d->ny != 1) return fail(RTROM_EINVAL, "ny must be 1 in 1D");
+  if (d->dim == 1 && d->nx > RT_SLAB_MAX_CELLS)
+    return fail(RTROM_EINVAL, "1D problems are limited to 4096 cells");
+  if (d->dim == 2 && ((int64_t)d->nx * d->ny > (1 << 22)))
+    return fail(RTROM_EINVAL, "2D problems are limited to 4194304 cells");
+  if (!(d->lx > 0.0) || !std::isfinite(d->lx)) return fail(RTROM_EINVAL, "lx must be > 0");
+  if (d->dim == 2 && (!(d->ly > 0.0) || !std::isfinite(d->ly))) return fail(RTROM_EINVAL, "ly must be > 0");
+  if (!(d->dt > 0.0) || !std::isfinite(d->dt)) return fail(RTROM_EINVAL, "dt must be > 0");
+  if (!(d->tol > 0.0) || !std::isfinite(d->tol)) return fail(RTROM_EINVAL, "tol must be > 0");
+  if (d->max_iter < 1) return fail(RTROM_EINVAL, "max_iter must be >= 1");
+  if (d->n_polar < 2 || d->n_polar % 2) return fail(RTROM_EINVAL, "n_polar must be even and >= 2");
+  if (d->n_polar > 256) return fail(RTROM_EINVAL, "n_polar must be <= 256");
+  if (d->dim == 1 && d->n_azim != 1) return fail(RTROM_EINVAL, "n_azim must be 1 in 1D");
+  if (d->dim == 2 && (d->n_azim < 4 || d->n_azim % 4 || d->n_azim > 256))
+    return fail(RTROM_EINVAL, "n_azim must be a multiple of 4 in 4..256");
+  if (d->method < 0 || d->method > 2) return fail(RTROM_EINVAL, "unknown method");
+  if (d->precision < 0 || d->precision > 1) return fail(RTROM_EINVAL, "unknown precision");
+  if (d->r_max < 1 || d->r_max > RT_RMAX) return fail(RTROM_EINVAL, "r_max must be in 1..20");
+  if (!(d->eps_ig >= 0.0) || !(d->eps_pc >= 0.0) || !(d->eps_up >= 0.0))
+    return fail(RTROM_EINVAL, "eps_ig, eps_pc, eps_up must be >= 0");
+  if (!d->sigma_s || !d->sigma_a || !d->source) return fail(RTROM_EINVAL, "sigma_s, sigma_a, source required");
+  const int64_t nc = (int64_t)d->nx * d->ny;
+  for (int64_t i = 0; i < nc; ++i) {
+    if (!(d->sigma_s[i] >= 0.0) || !std::isfinite(d->sigma_s[i]))
+      return fail(RTROM_EINVAL, "sigma_s must be finite and >= 0");
+    if (!(d->sigma_a[i] >= 0.0) || !std::isfinite(d->sigma_a[i]))
+      return fail(RTROM_EINVAL, "sigma_a must be finite and >= 0");
+    if (!std::isfinite(d->source[i])) return fail(RTROM_EINVAL, "source must be finite");
+    if (d->f0 && !std::isfinite(d->f0[i])) return fail(RTROM_EINVAL, "f0 must be finite");
+  }
+  for (int k = 0; k < 4; ++k)
+    if (!std::isfinite(d->inflow[k])) return fail(RTROM_EINVAL, "inflow must be finite");
+  return RTROM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Arena layout
+// ---------------------------------------------------------------------------
+namespace {
+struct Layout {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return o;
+  }
+};
+
+// Threads an instance's cells are split over: about four cells per thread,
+// a multiple of 64, at most 1024.  Fixed per instance at creation, so its
+// arithmetic does not depend on what it is batched with.
+int slab_instance_threads(int nc) {
+  int nt = (nc + 3) / 4;
+  const char *env = std::getenv("RTROM_SLAB_CELLS_PER_THREAD");
+  if (env && std::atoi(env) >= 1 && std::atoi(env) <= 8) nt = (nc + std::atoi(env) - 1) / std::atoi(env);
+  nt = ((nt + 63) / 64) * 64;
+  return std::max(64, std::min(1024, nt));
+}
+
+// Launch geometry of a fused launch over instances with the given thread
+// counts: the block holds the largest instance; CMAX covers every chunk.
+int slab_launch_threads(const int *nthr, const int *nc, int n, int *cmax) {
+  int nt = 64, c = 1;
+  for (int i = 0; i < n; ++i) {
+    nt = std::max(nt, nthr[i]);
+    c = std::max(c, (nc[i] + nthr[i] - 1) / nthr[i]);
+  }
+  *cmax = c <= 4 ? 4 : 8;
+  if (*cmax == 8 && nt > 512) nt = 512;  // never reached: nthr <= 1024 keeps c <= 4
+  return nt;
+}
+}  // namespace
+
+static size_t slab_bytes(const rtrom_problem_desc *d, int nv) {
+  const size_t nc = (size_t)d->nx * d->ny;
+  const size_t ld = (nc + 31) & ~size_t(31);
+  Layout L;
+  for (int k = 0; k < 13; ++k) L.take(nc * 8);
+  L.take(4 * nc * 8);
+  L.take((size_t)nv * 8 * 6);
+  L.take((size_t)nv * nc * 8);
+  for (int r = 0; r < 2; ++r) {
+    L.take((RT_RMAX + 1) * ld * 8);
+    L.take((RT_RMAX + 1) * ld * 8);
+    L.take((RT_RMAX + 1) * 8);
+    L.take(RT_RMAX * RT_RMAX * 8);
+    L.take(RT_RMAX * RT_RMAX * 8);
+    L.take(RT_RMAX * 4);
+    L.take(sizeof(RomPend));
+  }
+  L.take(sizeof(RtState));
+  L.take(sizeof(Inst));
+  return L.off;
+}
+
+extern "C" rtrom_status rtrom_estimate_bytes(const rtrom_problem_desc *d, uint64_t *bytes) {
+  if (!d || !bytes) return fail(RTROM_EINVAL, "null argument");
+  if (d->dim != 1 && d->dim != 2) return fail(RTROM_EINVAL, "dim must be 1 or 2");
+  if (d->nx < 1 || d->ny < 1 || d->n_polar < 1 || d->n_azim < 1) return fail(RTROM_EINVAL, "bad sizes");
+  int nv = d->dim == 1 ? d->n_polar : d->n_polar * d->n_azim;
+  size_t b = slab_bytes(d, nv) + (d->dim == 2 ? rt_plane_extra_bytes(d) : 0) + 64 * sizeof(RtStepRec);
+  *bytes = b;
+  return RTROM_OK;
+}
+
+static rtrom_status upload_inst(rtrom_problem *p) {
+  RT_HIP(hipMemcpyAsync(p->dinst, &p->hinst, sizeof(Inst), hipMemcpyHostToDevice, p->stream), "upload descriptor");
+  return RTROM_OK;
+}
+
+extern "C" void rtrom_destroy_problem(rtrom_problem *p) {
+  if (!p) return;
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  if (p->d.dim == 2) rt_plane_destroy(p);
+  if (p->arena) (void)hipFree(p->arena);
+  if (p->dhist) (void)hipFree(p->dhist);
+  if (p->ev0) (void)hipEventDestroy(p->ev0);
+  if (p->ev1) (void)hipEventDestroy(p->ev1);
+  if (p->ev_si) (void)hipEventDestroy(p->ev_si);
+  if (p->ev_rom) (void)hipEventDestroy(p->ev_rom);
+  if (p->aux_stream) {
+    (void)hipStreamSynchronize(p->aux_stream);
+    (void)hipStreamDestroy(p->aux_stream);
+  }
+  if (p->own_stream) (void)hipStreamDestroy(p->own_stream);
+  delete p;
+}
+
+static rtrom_status ensure_hist(rtrom_problem *p, int64_t need) {
+  if (need <= p->hist_cap) return RTROM_OK;
+  int64_t cap = std::max<int64_t>(need, std::max<int64_t>(64, 2 * p->hist_cap));
+  RtStepRec *nh = nullptr;
+  if (hipMalloc(&nh, cap * sizeof(RtStepRec)) != hipSuccess) return fail(RTROM_ENOMEM, "history allocation failed");
+  RT_HIP(hipMemsetAsync(nh, 0, cap * sizeof(RtStepRec), p->stream), "clear history");
+  if (p->dhist && p->hist_cap > 0)
+    RT_HIP(hipMemcpyAsync(nh, p->dhist, p->hist_cap * sizeof(RtStepRec), hipMemcpyDeviceToDevice, p->stream),
+           "copy history");
+  RT_HIP(hipStreamSynchronize(p->stream), "history sync");
+  if (p->dhist) (void)hipFree(p->dhist);
+  p->dhist = nh;
+  p->hist_cap = cap;
+  p->hinst.hist = nh;
+  p->hinst.hist_cap = (int)std::min<int64_t>(cap, 0x7fffffff);
+  return upload_inst(p);
+}
+
+extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_problem **out) {
+  if (!out) return fail(RTROM_EINVAL, "null output handle");
+  *out = nullptr;
+  rtrom_status v = validate(d);
+  if (v != RTROM_OK) return v;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(RTROM_EDEVICE, "no HIP device");
+  rtrom_problem *p = new rtrom_problem();
+  p->d = *d;
+  p->d.sigma_s = p->d.sigma_a = p->d.source = p->d.f0 = nullptr;
+  (void)hipGetDevice(&p->device);
+  const int nc = d->nx * d->ny;
+  const int nv = d->dim == 1 ? d->n_polar : d->n_polar * d->n_azim;
+  p->nc = nc;
+  p->nv = nv;
+  p->ox.assign(nv, 0.0);
+  p->oy.assign(nv, 0.0);
+  p->oz.assign(nv, 0.0);
+  p->w.assign(nv, 0.0);
+  if (d->dim == 1)
+    rtrom_gauss_legendre(nv, p->ox.data(), p->w.data());
+  else
+    rtrom_cl_quadrature(d->n_azim, d->n_polar, p->ox.data(), p->oy.data(), p->oz.data(), p->w.data());
+
+  auto bail = [&](rtrom_status s, const std::string &m) {
+    rtrom_destroy_problem(p);
+    return fail(s, m);
+  };
+  if (hipStreamCreateWithFlags(&p->own_stream, hipStreamNonBlocking) != hipSuccess)
+    return bail(RTROM_EDEVICE, "stream creation failed");
+  p->stream = p->own_stream;
+  if (hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess)
+    return bail(RTROM_EDEVICE, "event creation failed");
+  if (hipStreamCreateWithFlags(&p->aux_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev_si, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev_rom, hipEventDisableTiming) != hipSuccess)
+    return bail(RTROM_EDEVICE, "auxiliary stream creation failed");
+
+  // --- arena ------------------------------------------------------------
+  const size_t ld = ((size_t)nc + 31) & ~size_t(31);
+  p->arena_bytes = slab_bytes(d, nv);
+  if (hipMalloc(&p->arena, p->arena_bytes) != hipSuccess) return bail(RTROM_ENOMEM, "device allocation failed");
+  if (hipMemsetAsync(p->arena, 0, p->arena_bytes, p->stream) != hipSuccess)
+    return bail(RTROM_EDEVICE, "clear arena failed");
+  Layout L;
+  auto D = [&](size_t bytes) { return (double *)(p->arena + L.take(bytes)); };
+  Inst &I = p->hinst;
+  memset(&I, 0, sizeof(I));
+  double *ss = D(nc * 8), *sa = D(nc * 8), *G = D(nc * 8), *ct = D(nc * 8);
+  double *fe = D(nc * 8), *bg = D(nc * 8), *invd = D(nc * 8);
+  I.rho = D(nc * 8);
+  I.bt2[0] = D(nc * 8);
+  I.bt2[1] = D(nc * 8);
+  I.rho0 = D(nc * 8);
+  I.rhalf = D(nc * 8);
+  I.dpc = D(nc * 8);
+  I.work = D(4 * (size_t)nc * 8);
+  double *qbuf = D((size_t)nv * 8 * 6);
+  I.f = D((size_t)nv * nc * 8);
+  RomDev *roms[2] = {&I.ig, &I.pc};
+  for (int r = 0; r < 2; ++r) {
+    roms[r]->U = D((RT_RMAX + 1) * ld * 8);
+    roms[r]->W = D((RT_RMAX + 1) * ld * 8);
+    roms[r]->S = D((RT_RMAX + 1) * 8);
+    roms[r]->M = D(RT_RMAX * RT_RMAX * 8);
+    roms[r]->LU = D(RT_RMAX * RT_RMAX * 8);
+    roms[r]->perm = (int *)D(RT_RMAX * 4);
+    roms[r]->pend = (RomPend *)D(sizeof(RomPend));
+  }
+  I.st = (RtState *)D(sizeof(RtState));
+  p->dinst = (Inst *)D(sizeof(Inst));
+
+  I.dim = d->dim;
+  I.nx = d->nx;
+  I.ny = d->ny;
+  I.nc = nc;
+  I.nv = nv;
+  I.npair = nv / 2;
+  I.max_iter = d->max_iter;
+  I.method = d->method;
+  I.precision = d->precision;
+  I.r_max = d->r_max;
+  I.abs_up = (d->flags & RTROM_F_ABS_UP_NORM) ? 1 : 0;
+  I.ld = (int)ld;
+  I.nthr = d->dim == 1 ? slab_instance_threads(nc) : 256;
+  I.hx = d->lx / d->nx;
+  I.hy = d->dim == 2 ? d->ly / d->ny : 1.0;
+  I.dt = d->dt;
+  I.inv_dt = 1.0 / d->dt;
+  I.tol = d->tol;
+  I.eps_ig = d->eps_ig;
+  I.eps_pc = d->eps_pc;
+  I.eps_up = d->eps_up;
+  for (int k = 0; k < 4; ++k) I.g[k] = d->inflow[k];
+  I.ss = ss;
+  I.sa = sa;
+  I.G = G;
+  I.ct = ct;
+  I.dsa_fe = fe;
+  I.dsa_bg = bg;
+  I.dsa_invd = invd;
+
+  // --- host-side staging of per-cell and per-ordinate data ----------------
+  std::vector<double> h_ct(nc), h_q((size_t)nv * 6, 0.0);
+  for (int i = 0; i < nc; ++i) h_ct[i] = d->sigma_s[i] + d->sigma_a[i] + 1.0 / d->dt;
+  if (d->dim == 1) {
+    // ordinates sorted ascending: pair p = (p, nv-1-p) are mirrors
+    for (int q = 0; q < nv / 2; ++q) {
+      h_q[q] = std::fabs(p->ox[q]) / I.hx;
+      h_q[nv + q] = p->w[q];
+    }
+    I.pm = qbuf;
+    I.pw = qbuf + nv;
+  }
+  auto H2D = [&](void *dst, const void *src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, p->stream) == hipSuccess;
+  };
+  bool ok = H2D(ss, d->sigma_s, nc * 8) && H2D(sa, d->sigma_a, nc * 8) && H2D(G, d->source, nc * 8) &&
+            H2D(ct, h_ct.data(), nc * 8) && H2D(qbuf, h_q.data(), h_q.size() * 8);
+  std::vector<double> rho0(nc, 0.0);
+  if (d->f0)
+    for (int i = 0; i < nc; ++i) rho0[i] = d->f0[i];
+  ok = ok && H2D(I.rho, rho0.data(), nc * 8);
+  if (d->f0)
+    for (int j = 0; j < nv && ok; ++j) ok = H2D(I.f + (size_t)j * nc, rho0.data(), nc * 8);
+  // initial phase-machine state: everything zero except the LU flags
+  RtState st0;
+  memset(&st0, 0, sizeof(st0));
+  ok = ok && H2D(I.st, &st0, sizeof(st0));
+  if (!ok) return bail(RTROM_EDEVICE, "upload failed");
+  if (ensure_hist(p, 64) != RTROM_OK) {
+    std::string m = g_err;
+    return bail(RTROM_ENOMEM, m);
+  }
+  if (d->dim == 1) {
+    if (upload_inst(p) != RTROM_OK) return bail(RTROM_EDEVICE, "upload descriptor failed");
+    if (rt_launch_slab_setup(p->dinst, 1, p->stream) != hipSuccess) return bail(RTROM_EDEVICE, "setup launch failed");
+    int cmax;
+    int nt = slab_launch_threads(&I.nthr, &nc, 1, &cmax);
+    if (rt_launch_slab_rhs(p->dinst, 1, nt, cmax, p->stream) != hipSuccess)
+      return bail(RTROM_EDEVICE, "initial RHS launch failed");
+  } else {
+    int s = rt_plane_create(p);
+    if (s != RTROM_OK) {
+      std::string m = g_err;
+      return bail((rtrom_status)s, m);
+    }
+  }
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return bail(RTROM_EDEVICE, "create sync failed");
+  *out = p;
+  return RTROM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Marching
+// ---------------------------------------------------------------------------
+static rtrom_status read_state(const rtrom_problem *p, RtState *st) {
+  RT_HIP(hipMemcpyAsync(st, p->hinst.st, sizeof(RtState), hipMemcpyDeviceToHost, p->stream), "read state");
+  RT_HIP(hipStreamSynchronize(p->stream), "state sync");
+  return RTROM_OK;
+}
+
+static rtrom_status march_one_kind(rtrom_problem *const *ps, int n, int nsteps) {
+  // all handles of one dimension; 1D: fused launches over the instance array
+  hipStream_t s = ps[0]->stream;
+  for (int i = 0; i < n; ++i) {
+    rtrom_status e = ensure_hist(ps[i], ps[i]->steps + nsteps);
+    if (e != RTROM_OK) return e;
+    if (ps[i]->stream != s) RT_HIP(hipStreamSynchronize(ps[i]->stream), "sync member stream");
+  }
+  std::vector<RtState> before(n);
+  for (int i = 0; i < n; ++i) {
+    rtrom_status e = read_state(ps[i], &before[i]);
+    if (e != RTROM_OK) return e;
+  }
+  RT_HIP(hipEventRecord(ps[0]->ev0, s), "event");
+  if (ps[0]->d.dim == 1) {
+    Inst *dinsts = nullptr;
+    std::vector<int> nthr(n), ncs(n);
+    for (int i = 0; i < n; ++i) {
+      nthr[i] = ps[i]->hinst.nthr;
+      ncs[i] = ps[i]->nc;
+    }
+    if (n == 1) {
+      dinsts = ps[0]->dinst;
+    } else {
+      std::vector<Inst> h(n);
+      for (int i = 0; i < n; ++i) h[i] = ps[i]->hinst;
+      RT_HIP(hipMallocAsync((void **)&dinsts, n * sizeof(Inst), s), "batch descriptors");
+      RT_HIP(hipMemcpyAsync(dinsts, h.data(), n * sizeof(Inst), hipMemcpyHostToDevice, s), "upload batch");
+    }
+    int cmax;
+    int nt = slab_launch_threads(nthr.data(), ncs.data(), n, &cmax);
+    int nc_max = 0, any_rom = 0;
+    for (int i = 0; i < n; ++i) {
+      nc_max = std::max(nc_max, ncs[i]);
+      any_rom |= ps[i]->d.method == RTROM_ROM_SI_DSA;
+    }
+    // Per step: SI solve, then the f-pass (main stream) and the ROM work
+    // (auxiliary stream) run concurrently -- they touch disjoint state: the
+    // f-pass writes f^n and the other b~ buffer, the ROM work reads rho's and
+    // b~^{n-1} -- and the next SI solve waits for both.
+    hipStream_t s2 = any_rom ? ps[0]->aux_stream : s;
+    for (int k = 0; k < nsteps; ++k) {
+      rt_prof_begin(RT_K_SLAB_SI, s);
+      RT_HIP(rt_launch_slab_si(dinsts, n, nt, cmax, s), "SI launch");
+      rt_prof_end(RT_K_SLAB_SI, s);
+      if (s2 != s) {
+        RT_HIP(hipEventRecord(ps[0]->ev_si, s), "event");
+        RT_HIP(hipStreamWaitEvent(s2, ps[0]->ev_si, 0), "event wait");
+      }
+      rt_prof_begin(RT_K_POST, s2);
+      RT_HIP(rt_launch_post(dinsts, n, s2), "post launch");
+      rt_prof_end(RT_K_POST, s2);
+      if (any_rom) {
+        rt_prof_begin(RT_K_ROM_UPDATE, s2);
+        RT_HIP(rt_launch_rom_update(dinsts, n, nc_max, s2), "ROM update launch");
+        rt_prof_end(RT_K_ROM_UPDATE, s2);
+      }
+      rt_prof_begin(RT_K_SLAB_FPASS, s);
+      RT_HIP(rt_launch_slab_fpass(dinsts, n, nt, cmax, s), "f-pass launch");
+      rt_prof_end(RT_K_SLAB_FPASS, s);
+      if (s2 != s) {
+        RT_HIP(hipEventRecord(ps[0]->ev_rom, s2), "event");
+        RT_HIP(hipStreamWaitEvent(s, ps[0]->ev_rom, 0), "event wait");
+      }
+    }
+    if (n > 1) RT_HIP(hipFreeAsync(dinsts, s), "free batch descriptors");
+  } else {
+    for (int i = 0; i < n; ++i) {
+      int e = rt_plane_step(ps[i], nsteps);
+      if (e != RTROM_OK) return (rtrom_status)e;
+    }
+  }
+  RT_HIP(hipEventRecord(ps[0]->ev1, s), "event");
+  RT_HIP(hipStreamSynchronize(s), "march sync");
+  rt_prof_collect();
+  float ms = 0.0f;
+  (void)hipEventElapsedTime(&ms, ps[0]->ev0, ps[0]->ev1);
+  rtrom_status res = RTROM_OK;
+  for (int i = 0; i < n; ++i) {
+    ps[i]->steps += nsteps;
+    ps[i]->t_total += ms * 1e-3 / n;
+    RtState after;
+    rtrom_status e = read_state(ps[i], &after);
+    if (e != RTROM_OK) return e;
+    if (after.nonconv != before[i].nonconv) res = RTROM_ENOCONV;
+  }
+  if (res == RTROM_ENOCONV) rt_set_error("a time step reached max_iter without meeting the tolerance");
+  return res;
+}
+
+extern "C" rtrom_status rtrom_march(rtrom_problem *p, int32_t nsteps) {
+  if (!p) return fail(RTROM_EINVAL, "null problem");
+  if (nsteps < 0) return fail(RTROM_EINVAL, "nsteps must be >= 0");
+  if (nsteps == 0) return RTROM_OK;
+  return march_one_kind(&p, 1, nsteps);
+}
+
+extern "C" rtrom_status rtrom_step(rtrom_problem *p) { return rtrom_march(p, 1); }
+
+extern "C" rtrom_status rtrom_march_batch(rtrom_problem *const *ps, int32_t n, int32_t nsteps) {
+  if (!ps || n < 1) return fail(RTROM_EINVAL, "need at least one problem");
+  if (nsteps < 0) return fail(RTROM_EINVAL, "nsteps must be >= 0");
+  for (int i = 0; i < n; ++i) {
+    if (!ps[i]) return fail(RTROM_EINVAL, "null problem in batch");
+    for (int j = 0; j < i; ++j)
+      if (ps[j] == ps[i]) return fail(RTROM_EINVAL, "duplicate problem in batch");
+    if (ps[i]->d.dim != ps[0]->d.dim) return fail(RTROM_EINVAL, "batch mixes 1D and 2D problems");
+    if (ps[i]->device != ps[0]->device) return fail(RTROM_EINVAL, "batch spans devices");
+  }
+  if (nsteps == 0) return RTROM_OK;
+  return march_one_kind(ps, n, nsteps);
+}
+
+// ---------------------------------------------------------------------------
+// Accessors
+// ---------------------------------------------------------------------------
+static rtrom_status d2h(const rtrom_problem *p, void *dst, const void *src, size_t bytes) {
+  RT_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, p->stream), "download");
+  RT_HIP(hipStreamSynchronize(p->stream), "download sync");
+  return RTROM_OK;
+}
+
+extern "C" rtrom_status rtrom_get_scalar_flux(const rtrom_problem *p, double *rho, int64_t n) {
+  if (!p || !rho) return fail(RTROM_EINVAL, "null argument");
+  if (n < p->nc) return fail(RTROM_EINVAL, "output buffer too small");
+  return d2h(p, rho, p->hinst.rho, (size_t)p->nc * 8);
+}
+
+extern "C" rtrom_status rtrom_get_rhs(const rtrom_problem *p, double *b, int64_t n) {
+  if (!p || !b) return fail(RTROM_EINVAL, "null argument");
+  if (n < p->nc) return fail(RTROM_EINVAL, "output buffer too small");
+  return d2h(p, b, p->hinst.bt2[p->steps & 1], (size_t)p->nc * 8);
+}
+
+extern "C" rtrom_status rtrom_get_angular_flux(const rtrom_problem *p, double *f, int64_t n) {
+  if (!p || !f) return fail(RTROM_EINVAL, "null argument");
+  if (n < (int64_t)p->nc * p->nv) return fail(RTROM_EINVAL, "output buffer too small");
+  return d2h(p, f, p->hinst.f, (size_t)p->nc * p->nv * 8);
+}
+
+extern "C" rtrom_status rtrom_get_quadrature(const rtrom_problem *p, double *ox, double *oy, double *oz,
+                                             double *w, int64_t n) {
+  if (!p || !ox || !w) return fail(RTROM_EINVAL, "null argument");
+  if (n < p->nv) return fail(RTROM_EINVAL, "output buffer too small");
+  memcpy(ox, p->ox.data(), p->nv * 8);
+  memcpy(w, p->w.data(), p->nv * 8);
+  if (oy) memcpy(oy, p->oy.data(), p->nv * 8);
+  if (oz) memcpy(oz, p->oz.data(), p->nv * 8);
+  return RTROM_OK;
+}
+
+extern "C" rtrom_status rtrom_stats_get(const rtrom_problem *p, rtrom_stats *out) {
+  if (!p || !out) return fail(RTROM_EINVAL, "null argument");
+  RtState st;
+  rtrom_status e = read_state(p, &st);
+  if (e != RTROM_OK) return e;
+  memset(out, 0, sizeof(*out));
+  out->steps = st.steps;
+  out->si_iters_total = st.si_total;
+  out->sweeps_total = st.sweeps_total;
+  out->si_iters_last = st.iters;
+  out->phase = !st.flag_ig ? 1 : (!st.flag_pc ? 2 : 3);
+  out->n0 = st.n0;
+  out->n1 = st.n1;
+  out->rank_ig = st.rank_ig;
+  out->rank_pc = st.rank_pc;
+  out->nonconverged_steps = st.nonconv;
+  out->rom_fallbacks = st.fallbacks;
+  out->ig_updates = st.ig_updates;
+  out->pc_updates = st.pc_updates;
+  out->fp32_sweeps = st.fp32_sweeps;
+  out->last_residual = st.residual;
+  out->t_total_s = p->t_total;
+  return RTROM_OK;
+}
+
+extern "C" rtrom_status rtrom_get_history(const rtrom_problem *p, rtrom_step_record *out, int64_t n,
+                                          int64_t *written) {
+  if (!p || !out || n < 0) return fail(RTROM_EINVAL, "bad argument");
+  int64_t m = std::min<int64_t>(n, std::min<int64_t>(p->steps, p->hist_cap));
+  int64_t first = std::min<int64_t>(p->steps, p->hist_cap) - m;
+  static_assert(sizeof(rtrom_step_record) == sizeof(RtStepRec), "record layout");
+  if (m > 0) {
+    rtrom_status e = d2h(p, out, p->dhist + first, (size_t)m * sizeof(RtStepRec));
+    if (e != RTROM_OK) return e;
+  }
+  if (written) *written = m;
+  return RTROM_OK;
+}
+
+extern "C" rtrom_status rtrom_set_inflow(rtrom_problem *p, const double *g) {
+  if (!p || !g) return fail(RTROM_EINVAL, "null argument");
+  for (int k = 0; k < 4; ++k)
+    if (!std::isfinite(g[k])) return fail(RTROM_EINVAL, "inflow must be finite");
+  for (int k = 0; k < 4; ++k) {
+    p->d.inflow[k] = g[k];
+    p->hinst.g[k] = g[k];
+  }
+  rtrom_status e = upload_inst(p);
+  if (e != RTROM_OK) return e;
+  if (p->d.dim == 1) {
+    int cmax;
+    int nt = slab_launch_threads(&p->hinst.nthr, &p->nc, 1, &cmax);
+    RT_HIP(rt_launch_slab_rhs(p->dinst, 1, nt, cmax, p->stream), "RHS launch");
+  } else {
+    int s = rt_plane_rhs(p);
+    if (s != RTROM_OK) return (rtrom_status)s;
+  }
+  RT_HIP(hipStreamSynchronize(p->stream), "inflow sync");
+  return RTROM_OK;
+}
+
+extern "C" rtrom_status rtrom_set_stream(rtrom_problem *p, void *hip_stream) {
+  if (!p) return fail(RTROM_EINVAL, "null problem");
+  RT_HIP(hipStreamSynchronize(p->stream), "stream switch sync");
+  p->stream = hip_stream ? (hipStream_t)hip_stream : p->own_stream;
+  return RTROM_OK;
+}
+
+extern "C" rtrom_status rtrom_device_bytes(const rtrom_problem *p, uint64_t *bytes) {
+  if (!p || !bytes) return fail(RTROM_EINVAL, "null argument");
+  *bytes = p->arena_bytes + (uint64_t)p->hist_cap * sizeof(RtStepRec) +
+           (p->d.dim == 2 ? rt_plane_extra_bytes(&p->d) : 0);
+  return RTROM_OK;
+}

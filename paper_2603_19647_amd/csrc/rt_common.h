@@ -1,0 +1,215 @@
+// rt_common.h -- device-side data structures and workgroup primitives shared
+// by the librtrom kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define RT_RMAX 20     // largest ROM rank the kernels hold
+#define RT_KC 22       // padded column count of the incremental-SVD core (RMAX+1, even)
+#define RT_MAXWAVES 16 // 1024-thread workgroups at most
+
+// A basis rotation decided by the workgroup part of an incremental-SVD update
+// and applied to every cell by the grid-wide k_rom_update kernel:
+// U <- [U, p * inv_nu] Uc[:rows, :k],  W <- [W, b] Vc[:r_old+1, :k].
+struct RomPend {
+  int pending, r_old, rows, k, deficient, pad_[3];
+  double inv_nu;
+  const double *p;  // projected snapshot residual (global)
+  const double *b;  // right-hand-side snapshot (global)
+  double Uc[RT_KC * RT_KC];  // [q][j], stride RT_KC
+  double Vc[RT_KC * RT_KC];
+};
+
+// Per-instance ROM storage (Sec. 3.1): orthonormal basis U, W = B V (so the
+// DMD operator U^T B V S^{-1} never needs the snapshot matrix B), singular
+// values S, M = U^T W kept incrementally, and the LU factors of
+// A_r = M S^{-1} with the row permutation of its partial pivoting.
+struct RomDev {
+  double *U;    // [RT_RMAX+1][ld], column k contiguous
+  double *W;    // [RT_RMAX+1][ld]
+  double *S;    // [RT_RMAX+1]
+  double *M;    // [RT_RMAX][RT_RMAX] row-major (stride RT_RMAX)
+  double *LU;   // [RT_RMAX][RT_RMAX] row-major
+  int *perm;    // [RT_RMAX]
+  RomPend *pend;
+};
+
+// Device-resident state of the phase machine (Alg. 2) and counters.
+struct RtState {
+  int flag_ig, flag_pc, n0, n1;
+  int rank_ig, rank_pc, lu_ok_ig, lu_ok_pc;
+  long long steps, si_total, sweeps_total, ig_updates, pc_updates, fp32_sweeps;
+  int nonconv, fallbacks;
+  // written by the SI kernel for the step in flight, read by the post kernel
+  int iters, conv, used_pc, ig_fb, pc_fb, phase, cur, pad1;  // cur: b~ buffer of the step
+  double residual;
+};
+
+struct RtStepRec {
+  int iters, phase, converged, ig_update, pc_update, rank_ig, rank_pc, fallback;
+  double e_ig, e_pc, residual;
+};
+
+// Everything a kernel needs about one instance.  Arrays are device pointers
+// into the instance's arena.
+struct Inst {
+  int dim, nx, ny, nc, nv, npair;
+  int max_iter, method, precision, r_max, abs_up, hist_cap;
+  int ld;    // column stride of U / W (nc rounded up)
+  int nthr;  // threads the instance's cells are split over (multiple of 64,
+             // fixed at creation so results do not depend on the batch)
+  double hx, hy, dt, inv_dt, tol, eps_ig, eps_pc, eps_up;
+  double g[4];
+  // 1D ordinate pairs: pair p couples ordinate p (mu < 0) with nv-1-p (mu > 0)
+  const double *pm;   // [npair] |mu|/hx
+  const double *pw;   // [npair] weight of either ordinate of the pair
+  // 2D: per ordinate |Omega_x|/hx, |Omega_y|/hy, w (folded groups)
+  const double *om_x, *om_y, *ow;
+  // per cell
+  const double *ss, *sa, *G, *ct;                // sigma_s, sigma_a, source, sigma_t + 1/dt
+  const double *dsa_fe, *dsa_bg, *dsa_invd;      // 1D Thomas factors (affine form)
+  const double *dsa_diag, *dsa_wx, *dsa_wy;      // 2D 5-point stencil
+  // state
+  double *f;        // [nv][nc]
+  double *rho;      // rho^n
+  double *bt2[2];   // b~ double buffer: the next step reads bt2[steps & 1]
+                    // and its f-pass writes the other one
+  double *rho0, *rhalf, *dpc;  // IG, rho^{(1/2)}, PC correction of the step
+  double *work;     // [4][nc] scratch
+  RomDev ig, pc;
+  RtState *st;
+  RtStepRec *hist;
+};
+
+enum { RT_SI_DSA = 0, RT_ROM = 1, RT_SI_PLAIN = 2 };
+enum { RT_FP64 = 0, RT_MIXED = 1 };
+
+// ---------------------------------------------------------------------------
+// Arithmetic helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double rt_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float rt_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// 1/d in FP64: hardware reciprocal estimate refined by two Newton steps.
+__device__ __forceinline__ double rt_rcp(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = __builtin_fma(-d, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-d, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+// 1/d in FP32 (single hardware reciprocal; used by the FP32 increment sweeps)
+__device__ __forceinline__ float rt_rcp(float d) { return __builtin_amdgcn_rcpf(d); }
+
+// ---------------------------------------------------------------------------
+// Wave / workgroup reductions (deterministic: fixed butterfly, fixed wave order)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
+  return v;
+}
+
+// Sum n <= NV values held per thread across the workgroup; every thread gets
+// the n totals in `out` (LDS).  red: LDS scratch of RT_MAXWAVES*NV doubles.
+template <int NV>
+__device__ __forceinline__ void wg_sum_vec(const double (&v)[NV], int n, double *red, double *out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    if (k < n) {
+      double s = wave_sum(v[k]);
+      if (lane == 0) red[wave * NV + k] = s;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < n) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[w * NV + threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void wg_max2(double a, double b, double *red, double &ra, double &rb) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  a = wave_max(a);
+  b = wave_max(b);
+  if (lane == 0) {
+    red[2 * wave] = a;
+    red[2 * wave + 1] = b;
+  }
+  __syncthreads();
+  double xa = 0.0, xb = 0.0;
+  for (int w = 0; w < nw; ++w) {
+    xa = fmax(xa, red[2 * w]);
+    xb = fmax(xb, red[2 * w + 1]);
+  }
+  __syncthreads();
+  ra = xa;
+  rb = xb;
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup affine prefix scan in both directions at once.
+//
+// The upwind recurrence of a 1D sweep is f_i = a_i f_{i-1} + b_i.  Each thread
+// owns a contiguous run of cells and passes in the composition of its run's
+// maps, (Af, Bf) in ascending cell order and (Ab, Bb) in descending order.
+// The scan returns, for each thread, the value entering its run: inF for the
+// forward direction (boundary value gF enters thread 0) and inB for the
+// backward direction (gB enters the last thread).  Composition of map 1 then
+// map 2 is (a2 a1, a2 b1 + b2).  slots: LDS of 8*RT_MAXWAVES elements;
+// `parity` alternates between calls so one barrier per call suffices.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void wg_scan2(R Af, R Bf, R Ab, R Bb, R gF, R gB, R &inF, R &inB,
+                                         R *slots, int parity) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    R a2 = __shfl_up(Af, off, 64), b2 = __shfl_up(Bf, off, 64);
+    R c2 = __shfl_down(Ab, off, 64), d2 = __shfl_down(Bb, off, 64);
+    if (lane >= off) {
+      Bf = rt_fma(Af, b2, Bf);
+      Af = Af * a2;
+    }
+    if (lane + off < 64) {
+      Bb = rt_fma(Ab, d2, Bb);
+      Ab = Ab * c2;
+    }
+  }
+  R *s = slots + parity * 4 * RT_MAXWAVES;
+  if (lane == 63) {
+    s[wave] = Af;
+    s[RT_MAXWAVES + wave] = Bf;
+  }
+  if (lane == 0) {
+    s[2 * RT_MAXWAVES + wave] = Ab;
+    s[3 * RT_MAXWAVES + wave] = Bb;
+  }
+  R eAf = __shfl_up(Af, 1, 64), eBf = __shfl_up(Bf, 1, 64);
+  R eAb = __shfl_down(Ab, 1, 64), eBb = __shfl_down(Bb, 1, 64);
+  if (lane == 0) {
+    eAf = R(1);
+    eBf = R(0);
+  }
+  if (lane == 63) {
+    eAb = R(1);
+    eBb = R(0);
+  }
+  __syncthreads();
+  R vF = gF;
+  for (int k = 0; k < wave; ++k) vF = rt_fma(s[k], vF, s[RT_MAXWAVES + k]);
+  R vB = gB;
+  for (int k = nw - 1; k > wave; --k) vB = rt_fma(s[2 * RT_MAXWAVES + k], vB, s[3 * RT_MAXWAVES + k]);
+  inF = rt_fma(eAf, vF, eBf);
+  inB = rt_fma(eAb, vB, eBb);
+}

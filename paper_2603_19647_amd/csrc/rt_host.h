@@ -1,0 +1,58 @@
+// rt_host.h -- host-side problem object of librtrom (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/rtrom.h"
+#include "rt_common.h"
+
+struct rtrom_problem {
+  rtrom_problem_desc d;  // copy; array pointers cleared
+  int device = 0;
+  int nc = 0, nv = 0;
+  std::vector<double> ox, oy, oz, w;  // quadrature (host copy)
+  // device memory
+  char *arena = nullptr;
+  size_t arena_bytes = 0;
+  RtStepRec *dhist = nullptr;
+  int64_t hist_cap = 0;
+  Inst hinst{};          // descriptor with device pointers
+  Inst *dinst = nullptr; // device copy of hinst
+  hipStream_t own_stream = nullptr, stream = nullptr;
+  hipStream_t aux_stream = nullptr;          // ROM updates overlap the f-pass here
+  hipEvent_t ev_si = nullptr, ev_rom = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  int64_t steps = 0;     // host mirror of the step counter
+  double t_total = 0.0;
+  // 2D launch geometry / scratch
+  void *plane = nullptr;
+};
+
+// launch helpers implemented in the .hip kernel files
+extern "C" hipError_t rt_launch_slab_si(const Inst *dinsts, int ninst, int nthreads, int cmax,
+                                        hipStream_t stream);
+extern "C" hipError_t rt_launch_slab_fpass(const Inst *dinsts, int ninst, int nthreads, int cmax,
+                                           hipStream_t stream);
+extern "C" hipError_t rt_launch_post(const Inst *dinsts, int ninst, hipStream_t stream);
+extern "C" hipError_t rt_launch_rom_update(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream);
+extern "C" hipError_t rt_launch_slab_rhs(const Inst *dinsts, int ninst, int nthreads, int cmax,
+                                         hipStream_t stream);
+extern "C" hipError_t rt_launch_slab_setup(const Inst *dinsts, int ninst, hipStream_t stream);
+
+// 2D
+int rt_plane_create(rtrom_problem *p);
+void rt_plane_destroy(rtrom_problem *p);
+int rt_plane_step(rtrom_problem *p, int nsteps);
+int rt_plane_rhs(rtrom_problem *p);
+size_t rt_plane_extra_bytes(const rtrom_problem_desc *d);
+
+void rt_set_error(const std::string &msg);
+
+// Kernel timing (rtrom_profile_*): bracket a launch with events when enabled.
+enum { RT_K_SLAB_SI = 0, RT_K_SLAB_FPASS = 1, RT_K_POST = 2, RT_K_PLANE_SWEEP = 3, RT_K_PLANE_DSA = 4,
+       RT_K_PLANE_FPASS = 5, RT_K_PLANE_OTHER = 6, RT_K_ROM_UPDATE = 7, RT_NKINDS = 8 };
+void rt_prof_begin(int kind, hipStream_t s);
+void rt_prof_end(int kind, hipStream_t s);
+void rt_prof_collect();  // after the stream(s) synchronised

@@ -1,0 +1,584 @@
+// rt_rom.h -- device code of the ROM work: DMD reduced solve (Sec. 3.1,
+// eq. dmd-operator, eq. dmd-ig, eq. dmd-sa) and the incremental SVD update
+// (App. B, eq. svd_core) with the reduced operator kept incrementally.
+//
+// The O(N r) projections, the (r+1)^2 core SVD and the r x r LU run in one
+// workgroup per instance (k_post); the O(N r^2) basis update
+// U <- [U q] U_c, W <- [W b] V_c runs as its own grid-wide kernel
+// (k_rom_update) from the "pending update" the workgroup leaves behind.
+// Cells are owned with a stride (c = tid, tid + NT, ...) so that every pass
+// over a basis column is a coalesced stream.
+#pragma once
+#include "rt_common.h"
+
+struct RomSmem {
+  double B[RT_KC * RT_KC];   // core matrix, rotated in place: B[col*RT_KC + row]
+  double V[RT_KC * RT_KC];   // accumulated right rotations: V[col*RT_KC + row]
+  double Mx[RT_KC * RT_KC];  // Q^T [W b]: Mx[row*RT_KC + col]
+  double T1[RT_KC * RT_KC];  // Mx Vc[:, :k]
+  double Uc[RT_KC * RT_KC];  // sorted left vectors of the core: Uc[row*RT_KC + j]
+  double Vc[RT_KC * RT_KC];  // sorted right vectors: Vc[row*RT_KC + j]
+  double A[RT_KC * RT_KC];   // reduced operator / LU workspace, stride RT_KC
+  double sv[RT_KC];          // sorted singular values
+  double nrm[RT_KC];
+  double vec[48];            // reduction results
+  double av[RT_RMAX], a2v[RT_RMAX], utbv[RT_RMAX], pwv[RT_RMAX];  // projection coefficients
+  double red[RT_MAXWAVES * 48];
+  int perm[RT_KC];
+  short pairs[RT_KC * RT_KC];  // round-robin pairing table (p, q) per round and slot
+  int flag;
+  int ibuf[4];
+};
+
+// ---------------------------------------------------------------------------
+// 16-lane (one DPP row) sum: quad xor 1, quad xor 2, half-row mirror, row
+// mirror leave the row total in every lane of the row.
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
+  v += dpp_d<0x140>(v);  // row_mirror
+  return v;
+}
+// whole-wave sum, identical in every lane
+__device__ __forceinline__ double wave_sum_fast(double v) {
+  v = row16_sum(v);
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// Workgroup sum of NV per-thread partials; totals land in out[0..NV).
+template <int NV>
+__device__ __forceinline__ void wg_sum_fast(const double (&v)[NV], double *red, double *out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = wave_sum_fast(v[k]);
+    if (lane == 0) red[wave * NV + k] = s;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < NV) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[w * NV + threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// LU with partial pivoting of the n x n matrix in A (stride RT_KC, LDS), by
+// wave 0 (lanes over rows / columns).  Pivot: the first row of largest
+// |a_ik|; a pivot below 1e-14 max|A| marks the system singular.  Writes
+// factors (stride RT_RMAX) and the final row permutation to global memory and
+// returns 1 if singular.  Must be called by the whole workgroup.
+// ---------------------------------------------------------------------------
+__device__ inline int lu_factor_wave(double *A, int *perm_lds, int n, double *LUg, int *permg, int *flag) {
+  const int lane = threadIdx.x;
+  if (threadIdx.x < 64) {
+    double m = 0.0;
+    if (lane < n)
+      for (int j = 0; j < n; ++j) m = fmax(m, fabs(A[lane * RT_KC + j]));
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    const double amax = m;
+    int bad = (amax == 0.0);
+    if (lane < RT_KC) perm_lds[lane] = lane;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int k = 0; k < n; ++k) {
+      // first index of the largest |a_ik|, i >= k
+      double v = (lane >= k && lane < n) ? fabs(A[lane * RT_KC + k]) : -1.0;
+      int idx = lane;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const double ov = __shfl_xor(v, off, 64);
+        const int oi = __shfl_xor(idx, off, 64);
+        if (ov > v || (ov == v && oi < idx)) {
+          v = ov;
+          idx = oi;
+        }
+      }
+      const int p = idx;
+      if (p != k && lane < n) {
+        const double t = A[k * RT_KC + lane];
+        A[k * RT_KC + lane] = A[p * RT_KC + lane];
+        A[p * RT_KC + lane] = t;
+      }
+      if (p != k && lane == 0) {
+        const int t = perm_lds[k];
+        perm_lds[k] = perm_lds[p];
+        perm_lds[p] = t;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      const double akk = A[k * RT_KC + k];
+      if (akk == 0.0 || fabs(akk) < 1e-14 * amax) {
+        bad = 1;
+        continue;
+      }
+      if (lane > k && lane < n) {
+        const double l = A[lane * RT_KC + k] / akk;
+        A[lane * RT_KC + k] = l;
+        for (int j = k + 1; j < n; ++j) A[lane * RT_KC + j] = rt_fma(-l, A[k * RT_KC + j], A[lane * RT_KC + j]);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (lane < n) {
+      for (int j = 0; j < n; ++j) LUg[lane * RT_RMAX + j] = A[lane * RT_KC + j];
+      permg[lane] = perm_lds[lane];
+    }
+    if (lane == 0) *flag = bad;
+  }
+  __syncthreads();
+  const int bad = *flag;
+  __syncthreads();
+  return bad;
+}
+
+// Solve A_r c = vec in place (vec in LDS) with the factors of lu_factor_wave,
+// by wave 0: lane i holds row i of the factors; forward and back
+// substitution broadcast one solved component per step.
+__device__ inline void lu_solve_wave(const double *LU, const int *perm, int n, double *vec) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    double row[RT_RMAX];
+#pragma unroll
+    for (int j = 0; j < RT_RMAX; ++j) row[j] = (lane < n && j < n) ? LU[lane * RT_RMAX + j] : 0.0;
+    double s = (lane < n) ? vec[perm[lane]] : 0.0;
+#pragma unroll
+    for (int j = 0; j < RT_RMAX; ++j) {
+      if (j < n) {
+        const double bj = __shfl(s, j, 64);
+        if (lane > j) s = rt_fma(-row[j], bj, s);
+      }
+    }
+#pragma unroll
+    for (int j = RT_RMAX - 1; j >= 0; --j) {
+      if (j < n) {
+        double xj = (lane == j) ? s / row[j] : 0.0;
+        xj = __shfl(xj, j, 64);
+        if (lane == j) s = xj;
+        if (lane < j) s = rt_fma(-row[j], xj, s);
+      }
+    }
+    // every lane read vec[perm[lane]] before any lane writes
+    __builtin_amdgcn_wave_barrier();
+    if (lane < n) vec[lane] = s;
+  }
+  __syncthreads();
+}
+
+// out = U (A_r^{-1} (U^T rhs)), the DMD solve of the initial guess
+// (eq. dmd-ig) and of the preconditioner correction (eq. dmd-sa).  rhs, out:
+// global vectors; cells with a stride of NT <= blockDim (the instance's own
+// thread count, so the summation order does not depend on the launch).  Ends
+// with a barrier, so `out` is visible to the whole workgroup afterwards.
+__device__ inline void rom_apply(const RomDev &R, int rank, int ld, int nc, int NT, const double *rhs,
+                                 double *out, double *red, double *vec) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int k0 = 0; k0 < rank; k0 += 4) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = threadIdx.x; c < nc && (int)threadIdx.x < NT; c += NT) {
+      const double v = rhs[c];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (k0 + q < rank) s[q] = rt_fma(R.U[(size_t)(k0 + q) * ld + c], v, s[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double t = wave_sum_fast(s[q]);
+      if (lane == 0 && k0 + q < rank) red[wave * RT_RMAX + k0 + q] = t;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < rank) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[w * RT_RMAX + threadIdx.x];
+    vec[threadIdx.x] = s;
+  }
+  __syncthreads();
+  lu_solve_wave(R.LU, R.perm, rank, vec);
+  for (int c = threadIdx.x; c < nc && (int)threadIdx.x < NT; c += NT) {
+    double v = 0.0;
+    for (int k = 0; k < rank; ++k) v = rt_fma(R.U[(size_t)k * ld + c], vec[k], v);
+    out[c] = v;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// One-sided Jacobi SVD of the rows x cols core (rows <= cols <= RT_KC) held in
+// sm.B (column major).  Each round applies cols/2 disjoint column rotations
+// (round-robin pairing), one 16-lane group per pair with row-local DPP sums.
+// Sweeps stop when a full sweep rotates nothing (|gamma| <= 1e-15
+// sqrt(alpha beta)).  Leaves sorted singular values in sm.sv, left vectors
+// (B_j / s_j) in sm.Uc and right vectors in sm.Vc.
+// ---------------------------------------------------------------------------
+__device__ inline void core_svd(RomSmem &sm, int rows, int cols) {
+  const int tid = threadIdx.x;
+  const int ncp = cols + (cols & 1);
+  const int npairs = ncp >> 1;
+  for (int e = tid; e < RT_KC * RT_KC; e += blockDim.x) {
+    const int c = e / RT_KC, r = e % RT_KC;
+    sm.V[e] = (c == r) ? 1.0 : 0.0;
+    if (c >= cols || r >= rows) sm.B[e] = 0.0;
+  }
+  // pairing of round t, slot k (circle method: position 0 fixed, the rest rotate)
+  for (int e = tid; e < (ncp - 1) * npairs; e += blockDim.x) {
+    const int t = e / npairs, k0 = e % npairs, k1 = ncp - 1 - k0;
+    int p = (k0 == 0) ? 0 : ((k0 - 1 + t) % (ncp - 1)) + 1;
+    int q = ((k1 - 1 + t) % (ncp - 1)) + 1;
+    if (p > q) {
+      const int x = p;
+      p = q;
+      q = x;
+    }
+    sm.pairs[2 * e] = (short)p;
+    sm.pairs[2 * e + 1] = (short)q;
+  }
+  __syncthreads();
+  const int grp = tid >> 4, gl = tid & 15;
+  const int i0 = gl, i1 = gl + 16;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) sm.flag = 0;
+    __syncthreads();
+    for (int round = 0; round < ncp - 1; ++round) {
+      if (grp < npairs) {
+        const int p = sm.pairs[2 * (round * npairs + grp)];
+        const int q = sm.pairs[2 * (round * npairs + grp) + 1];
+        double bp0 = 0, bq0 = 0, bp1 = 0, bq1 = 0;
+        if (i0 < rows) {
+          bp0 = sm.B[p * RT_KC + i0];
+          bq0 = sm.B[q * RT_KC + i0];
+        }
+        if (i1 < rows) {
+          bp1 = sm.B[p * RT_KC + i1];
+          bq1 = sm.B[q * RT_KC + i1];
+        }
+        const double al = row16_sum(rt_fma(bp0, bp0, bp1 * bp1));
+        const double be = row16_sum(rt_fma(bq0, bq0, bq1 * bq1));
+        const double ga = row16_sum(rt_fma(bp0, bq0, bp1 * bq1));
+        if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+          const double zeta = (be - al) * rt_rcp(2.0 * ga);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) * rt_rcp(fabs(zeta) + sqrt(rt_fma(zeta, zeta, 1.0)));
+          const double c = rt_rcp(sqrt(rt_fma(t, t, 1.0)));
+          const double s = c * t;
+          if (i0 < rows) {
+            sm.B[p * RT_KC + i0] = c * bp0 - s * bq0;
+            sm.B[q * RT_KC + i0] = s * bp0 + c * bq0;
+          }
+          if (i1 < rows) {
+            sm.B[p * RT_KC + i1] = c * bp1 - s * bq1;
+            sm.B[q * RT_KC + i1] = s * bp1 + c * bq1;
+          }
+          if (i0 < cols) {
+            const double vp = sm.V[p * RT_KC + i0], vq = sm.V[q * RT_KC + i0];
+            sm.V[p * RT_KC + i0] = c * vp - s * vq;
+            sm.V[q * RT_KC + i0] = s * vp + c * vq;
+          }
+          if (i1 < cols) {
+            const double vp = sm.V[p * RT_KC + i1], vq = sm.V[q * RT_KC + i1];
+            sm.V[p * RT_KC + i1] = c * vp - s * vq;
+            sm.V[q * RT_KC + i1] = s * vp + c * vq;
+          }
+          if (gl == 0) sm.flag = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int more = sm.flag;
+    __syncthreads();
+    if (!more) break;
+  }
+  // column norms and a stable descending rank order
+  if (tid < cols) {
+    double a = 0.0;
+    for (int i = 0; i < rows; ++i) a = rt_fma(sm.B[tid * RT_KC + i], sm.B[tid * RT_KC + i], a);
+    sm.nrm[tid] = sqrt(a);
+  }
+  __syncthreads();
+  if (tid < cols) {
+    const double mine = sm.nrm[tid];
+    int rk = 0;
+    for (int j = 0; j < cols; ++j) {
+      const double o = sm.nrm[j];
+      rk += (o > mine) || (o == mine && j < tid);
+    }
+    sm.perm[rk] = tid;
+  }
+  __syncthreads();
+  for (int e = tid; e < cols * RT_KC; e += blockDim.x) {
+    const int jj = e / RT_KC, i = e % RT_KC;
+    const int j = sm.perm[jj];
+    const double s = sm.nrm[j];
+    if (i == 0) sm.sv[jj] = s;
+    if (i < rows) sm.Uc[i * RT_KC + jj] = (s > 0.0) ? sm.B[j * RT_KC + i] / s : 0.0;
+    if (i < cols) sm.Vc[i * RT_KC + jj] = sm.V[j * RT_KC + i];
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Incremental SVD, first half (App. B): projection of the snapshot x onto
+// span(U) by classical Gram-Schmidt applied twice, the core
+// [[diag S, U^T x], [0, ||p||]], its SVD, truncation, the reduced operator
+// M_new = Uc^T Q^T [W b] Vc (Q = [U, p/||p||]) with A_r = M_new S^{-1} and its
+// LU.  The basis rotation itself is left in R.pend for k_rom_update.
+// x, b: global snapshot vectors; pbuf: global scratch that receives p.
+// truncate: keep s_i / sum(s) > eps; rank <= rmax.  Returns 1 for a
+// rank-deficient snapshot (x in span U), 0 otherwise, -1 if x = 0 at rank 0.
+// ---------------------------------------------------------------------------
+__device__ inline int isvd_prepare(const RomDev &R, int ld, int nc, int rmax, int &rank, int &luok,
+                                   const double *x, const double *b, double *pbuf, int truncate, double eps,
+                                   RomSmem &sm) {
+  const int tid = threadIdx.x, NT = blockDim.x;
+  const int r = rank;
+  RomPend *P = R.pend;
+  // 1) a = U^T x, U^T b, ||x||^2, x.b
+  {
+    double part[2 * RT_RMAX + 2];
+#pragma unroll
+    for (int k = 0; k < 2 * RT_RMAX + 2; ++k) part[k] = 0.0;
+#pragma unroll 2
+    for (int c = tid; c < nc; c += NT) {
+      const double xv = x[c], bv = b[c];
+      part[2 * RT_RMAX] = rt_fma(xv, xv, part[2 * RT_RMAX]);
+      part[2 * RT_RMAX + 1] = rt_fma(xv, bv, part[2 * RT_RMAX + 1]);
+#pragma unroll
+      for (int k = 0; k < RT_RMAX; ++k)
+        if (k < r) {
+          const double u = R.U[(size_t)k * ld + c];
+          part[k] = rt_fma(u, xv, part[k]);
+          part[RT_RMAX + k] = rt_fma(u, bv, part[RT_RMAX + k]);
+        }
+    }
+    wg_sum_fast<2 * RT_RMAX + 2>(part, sm.red, sm.vec);
+  }
+  const double xn = sqrt(sm.vec[2 * RT_RMAX]);
+  const double xb = sm.vec[2 * RT_RMAX + 1];
+  if (r == 0) {
+    __syncthreads();
+    if (xn == 0.0) {
+      if (tid == 0) P->pending = 0;
+      return -1;
+    }
+    for (int c = tid; c < nc; c += NT) pbuf[c] = x[c];
+    if (tid == 0) {
+      const double m = xb / xn;
+      R.M[0] = m;
+      R.S[0] = xn;
+      sm.A[0] = m / xn;
+      P->pending = 1;
+      P->r_old = 0;
+      P->rows = 1;
+      P->k = 1;
+      P->deficient = 0;
+      P->inv_nu = 1.0 / xn;
+      P->Uc[0] = 1.0;
+      P->Vc[0] = 1.0;
+      P->p = pbuf;
+      P->b = b;
+    }
+    __syncthreads();
+    luok = !lu_factor_wave(sm.A, sm.perm, 1, R.LU, R.perm, &sm.ibuf[0]);
+    rank = 1;
+    return 0;
+  }
+  if (tid < RT_RMAX) {
+    sm.av[tid] = (tid < r) ? sm.vec[tid] : 0.0;
+    sm.utbv[tid] = (tid < r) ? sm.vec[RT_RMAX + tid] : 0.0;
+  }
+  __syncthreads();
+  // 2) p1 = x - U a (classical Gram-Schmidt), a2 = U^T p1, p1^T W
+  {
+    double part[2 * RT_RMAX];
+#pragma unroll
+    for (int k = 0; k < 2 * RT_RMAX; ++k) part[k] = 0.0;
+#pragma unroll 2
+    for (int c = tid; c < nc; c += NT) {
+      double v = x[c];
+      for (int k = 0; k < r; ++k) v = rt_fma(-R.U[(size_t)k * ld + c], sm.av[k], v);
+      pbuf[c] = v;
+#pragma unroll
+      for (int k = 0; k < RT_RMAX; ++k)
+        if (k < r) {
+          part[k] = rt_fma(R.U[(size_t)k * ld + c], v, part[k]);
+          part[RT_RMAX + k] = rt_fma(R.W[(size_t)k * ld + c], v, part[RT_RMAX + k]);
+        }
+    }
+    wg_sum_fast<2 * RT_RMAX>(part, sm.red, sm.vec);
+  }
+  if (tid < RT_RMAX) {
+    sm.a2v[tid] = (tid < r) ? sm.vec[tid] : 0.0;
+    sm.pwv[tid] = (tid < r) ? sm.vec[RT_RMAX + tid] : 0.0;
+  }
+  __syncthreads();
+  // 3) second Gram-Schmidt pass p = p1 - U a2, ||p||^2 and p.b (direct: p is
+  //    small when x is nearly in span(U), so no cancellation-prone identity)
+  {
+    double part[2] = {0.0, 0.0};
+#pragma unroll 2
+    for (int c = tid; c < nc; c += NT) {
+      double v = pbuf[c];
+      for (int k = 0; k < r; ++k) v = rt_fma(-R.U[(size_t)k * ld + c], sm.a2v[k], v);
+      pbuf[c] = v;
+      part[0] = rt_fma(v, v, part[0]);
+      part[1] = rt_fma(v, b[c], part[1]);
+    }
+    wg_sum_fast<2>(part, sm.red, sm.vec);
+  }
+  const double nu = sqrt(sm.vec[0]);
+  const double pb = sm.vec[1];
+  const int deficient = !(nu > 1e-12 * xn);
+  __syncthreads();
+  // p^T W = p1^T W - a2^T M  (M = U^T W); a2 is the small second-pass term.
+  // Total coefficients a <- a + a2.
+  if (tid < RT_KC) {
+    const int j = tid;
+    double v = 0.0;
+    if (j < r) {
+      v = sm.pwv[j];
+      for (int i = 0; i < r; ++i) v = rt_fma(-sm.a2v[i], R.M[i * RT_RMAX + j], v);
+      sm.av[j] += sm.a2v[j];
+    }
+    sm.vec[j] = v;
+  }
+  __syncthreads();
+  const int rows = deficient ? r : r + 1, cols = r + 1;
+  // 5) core K = [[diag S, a], [0, nu]] and Mx = Q^T [W b]
+  if (tid < RT_KC) {
+    const int j = tid;
+    for (int i = 0; i < RT_KC; ++i) {
+      double v = 0.0;
+      if (j < r && i == j) v = R.S[j];
+      if (j == r && i < r) v = sm.av[i];
+      if (j == r && i == r && !deficient) v = nu;
+      sm.B[j * RT_KC + i] = (i < rows && j < cols) ? v : 0.0;
+    }
+  }
+  for (int e = tid; e < RT_KC * RT_KC; e += NT) {
+    const int i = e / RT_KC, j = e % RT_KC;
+    double v = 0.0;
+    if (i < r && j < r) {
+      v = R.M[i * RT_RMAX + j];
+    } else if (i < r && j == r) {
+      v = sm.utbv[i];
+    } else if (i == r && j < r && !deficient) {
+      v = sm.vec[j] / nu;
+    } else if (i == r && j == r && !deficient) {
+      v = pb / nu;
+    }
+    sm.Mx[e] = v;
+  }
+  __syncthreads();
+  core_svd(sm, rows, cols);
+  // 6) number of kept values
+  if (tid == 0) {
+    int k = rows;
+    if (truncate) {
+      double tot = 0.0;
+      for (int i = 0; i < rows; ++i) tot += sm.sv[i];
+      int kk = 0;
+      for (int i = 0; i < rows; ++i)
+        if (sm.sv[i] / tot > eps) kk = i + 1;
+      k = kk > 0 ? kk : 1;
+    }
+    if (k > rmax) k = rmax;
+    sm.ibuf[1] = k;
+  }
+  __syncthreads();
+  const int k = sm.ibuf[1];
+  // 7) M_new = Uc[:, :k]^T Mx Vc[:, :k], A_r = M_new S^{-1}; pending rotation
+  for (int e = tid; e < rows * k; e += NT) {
+    const int i = e / k, j = e % k;
+    double v = 0.0;
+    for (int q = 0; q < cols; ++q) v = rt_fma(sm.Mx[i * RT_KC + q], sm.Vc[q * RT_KC + j], v);
+    sm.T1[i * RT_KC + j] = v;
+  }
+  for (int e = tid; e < RT_KC * RT_KC; e += NT) {
+    P->Uc[e] = sm.Uc[e];
+    P->Vc[e] = sm.Vc[e];
+  }
+  __syncthreads();
+  for (int e = tid; e < k * k; e += NT) {
+    const int i = e / k, j = e % k;
+    double v = 0.0;
+    for (int q = 0; q < rows; ++q) v = rt_fma(sm.Uc[q * RT_KC + i], sm.T1[q * RT_KC + j], v);
+    R.M[i * RT_RMAX + j] = v;
+    sm.A[i * RT_KC + j] = v / sm.sv[j];
+  }
+  if (tid == 0) {
+    for (int j = 0; j < k; ++j) R.S[j] = sm.sv[j];
+    P->pending = 1;
+    P->r_old = r;
+    P->rows = rows;
+    P->k = k;
+    P->deficient = deficient;
+    P->inv_nu = deficient ? 0.0 : 1.0 / nu;
+    P->p = pbuf;
+    P->b = b;
+  }
+  __syncthreads();
+  luok = !lu_factor_wave(sm.A, sm.perm, k, R.LU, R.perm, &sm.ibuf[0]);
+  rank = k;
+  return deficient;
+}
+
+// Second half: U <- [U, p/nu] Uc[:, :k], W <- [W, b] Vc[:, :k] for one cell.
+// Reads every old column of the cell before writing, so it works in place.
+__device__ __forceinline__ void isvd_rotate_cell(const RomDev &R, const RomPend &P, const double *Uc,
+                                                 const double *Vc, int ld, int c) {
+  const int r = P.r_old, k = P.k;
+  double acc[RT_RMAX];
+#pragma unroll
+  for (int j = 0; j < RT_RMAX; ++j) acc[j] = 0.0;
+  for (int q = 0; q < r; ++q) {
+    const double u = R.U[(size_t)q * ld + c];
+#pragma unroll
+    for (int j = 0; j < RT_RMAX; ++j)
+      if (j < k) acc[j] = rt_fma(u, Uc[q * RT_KC + j], acc[j]);
+  }
+  if (!P.deficient) {
+    const double e = P.p[c] * P.inv_nu;
+#pragma unroll
+    for (int j = 0; j < RT_RMAX; ++j)
+      if (j < k) acc[j] = rt_fma(e, Uc[r * RT_KC + j], acc[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < RT_RMAX; ++j)
+    if (j < k) R.U[(size_t)j * ld + c] = acc[j];
+#pragma unroll
+  for (int j = 0; j < RT_RMAX; ++j) acc[j] = 0.0;
+  for (int q = 0; q < r; ++q) {
+    const double w = R.W[(size_t)q * ld + c];
+#pragma unroll
+    for (int j = 0; j < RT_RMAX; ++j)
+      if (j < k) acc[j] = rt_fma(w, Vc[q * RT_KC + j], acc[j]);
+  }
+  {
+    const double bv = P.b[c];
+#pragma unroll
+    for (int j = 0; j < RT_RMAX; ++j)
+      if (j < k) acc[j] = rt_fma(bv, Vc[r * RT_KC + j], acc[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < RT_RMAX; ++j)
+    if (j < k) R.W[(size_t)j * ld + c] = acc[j];
+}
+
+// s_r / sum(s) of the retained values (eq. ig_stop, eq. pc_stop)
+__device__ inline double rom_tail_ratio(const RomDev &R, int rank) {
+  double tot = 0.0;
+  for (int i = 0; i < rank; ++i) tot += R.S[i];
+  return tot > 0.0 ? R.S[rank - 1] / tot : 0.0;
+}

@@ -1,0 +1,643 @@
+// rt_slab.hip -- slab (1D) kernels of librtrom for gfx950.
+//
+// One workgroup owns one problem instance; thread t owns the contiguous cells
+// [t*C, t*C + C) for the whole step, so every per-cell vector of the source
+// iteration (rho, y, b~, sigma's) lives in registers.  Each upwind sweep
+// (Sec. 2.3: one pass of block Gauss-Seidel in upwind order) is the affine
+// recurrence f_i = a_i f_{i-1} + b_i of first-order upwind finite volumes,
+// evaluated as a workgroup-wide affine prefix scan (wg_scan2).  The two
+// ordinates of a mirror pair (mu, -mu) share a_i and the reciprocal of
+// (sigma_t + 1/dt + |mu|/h) and are scanned together in opposite directions.
+#include "rt_common.h"
+#include "rt_rom.h"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Sweep with an ordinate-independent source s and zero inflow, returning the
+// angular moment acc = sum_j w_j f_j (the operator T of Sec. 2.3 applied to s).
+// ---------------------------------------------------------------------------
+template <int CMAX, typename R>
+__device__ __forceinline__ void sweep_moment(const Inst &I, const R (&ct)[CMAX], const R (&s)[CMAX], int n,
+                                             R (&acc)[CMAX], R *slots, int &parity) {
+#pragma unroll
+  for (int t = 0; t < CMAX; ++t) acc[t] = R(0);
+  for (int p = 0; p < I.npair; ++p) {
+    const R m = (R)I.pm[p];
+    const R w = (R)I.pw[p];
+    R a[CMAX], b[CMAX];
+    R Af = R(1), Bf = R(0);
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t) {
+      if (t < n) {
+        R inv = rt_rcp(ct[t] + m);
+        a[t] = m * inv;
+        b[t] = s[t] * inv;
+        Bf = rt_fma(a[t], Bf, b[t]);
+        Af = a[t] * Af;
+      }
+    }
+    R Ab = R(1), Bb = R(0);
+#pragma unroll
+    for (int t = CMAX - 1; t >= 0; --t) {
+      if (t < n) {
+        Bb = rt_fma(a[t], Bb, b[t]);
+        Ab = a[t] * Ab;
+      }
+    }
+    R inF, inB;
+    wg_scan2<R>(Af, Bf, Ab, Bb, R(0), R(0), inF, inB, slots, parity);
+    parity ^= 1;
+    R f = inF;
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t) {
+      if (t < n) {
+        f = rt_fma(a[t], f, b[t]);
+        acc[t] = rt_fma(w, f, acc[t]);
+      }
+    }
+    f = inB;
+#pragma unroll
+    for (int t = CMAX - 1; t >= 0; --t) {
+      if (t < n) {
+        f = rt_fma(a[t], f, b[t]);
+        acc[t] = rt_fma(w, f, acc[t]);
+      }
+    }
+  }
+}
+
+// DSA correction (eq. rho_residual): solve C d = rhs with the precomputed
+// Thomas factors written as two affine recurrences, z_i = fe_i z_{i-1} + rhs_i
+// forward and d_i = bg_i d_{i+1} + invd_i z_i backward.
+template <int CMAX>
+__device__ __forceinline__ void dsa_solve_slab(const Inst &I, int c0, int n, const double (&rhs)[CMAX],
+                                               double (&d)[CMAX], double *slots, int &parity) {
+  double fe[CMAX], z[CMAX];
+  double A = 1.0, B = 0.0;
+#pragma unroll
+  for (int t = 0; t < CMAX; ++t) {
+    if (t < n) {
+      fe[t] = I.dsa_fe[c0 + t];
+      B = rt_fma(fe[t], B, rhs[t]);
+      A *= fe[t];
+    }
+  }
+  double inF, inB;
+  wg_scan2<double>(A, B, 1.0, 0.0, 0.0, 0.0, inF, inB, slots, parity);
+  parity ^= 1;
+  double f = inF;
+#pragma unroll
+  for (int t = 0; t < CMAX; ++t) {
+    if (t < n) {
+      f = rt_fma(fe[t], f, rhs[t]);
+      z[t] = f;
+    }
+  }
+  double bg[CMAX];
+  A = 1.0;
+  B = 0.0;
+#pragma unroll
+  for (int t = CMAX - 1; t >= 0; --t) {
+    if (t < n) {
+      bg[t] = I.dsa_bg[c0 + t];
+      z[t] *= I.dsa_invd[c0 + t];
+      B = rt_fma(bg[t], B, z[t]);
+      A *= bg[t];
+    }
+  }
+  wg_scan2<double>(1.0, 0.0, A, B, 0.0, 0.0, inF, inB, slots, parity);
+  parity ^= 1;
+  f = inB;
+#pragma unroll
+  for (int t = CMAX - 1; t >= 0; --t) {
+    if (t < n) {
+      f = rt_fma(bg[t], f, z[t]);
+      d[t] = f;
+    }
+  }
+}
+
+__device__ __forceinline__ bool stop_test(double dn, double yn, double tol) {
+  return yn > 0.0 ? (dn < tol * yn) : (dn < tol);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// k_si_slab: initial guess + Alg. 1 (SI with DSA, or the hybrid ROM/DSA
+// preconditioner of Sec. 3.2 phase 3) for every instance of the launch.
+// Writes rho^n, rho^{(0)}, rho^{(1/2)}, the PC correction and per-step status.
+// ---------------------------------------------------------------------------
+template <int CMAX, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts) {
+  const Inst &I = insts[blockIdx.x];
+  __shared__ double slots[8 * RT_MAXWAVES];
+  __shared__ float slotsf[8 * RT_MAXWAVES];
+  __shared__ double red[2 * RT_MAXWAVES];
+  __shared__ double rred[RT_MAXWAVES * RT_RMAX];
+  __shared__ double rvec[RT_RMAX + 4];
+  const int NT = I.nthr, tid = threadIdx.x;
+  const int nc = I.nc;
+  const int C = (nc + NT - 1) / NT;
+  const int c0 = tid * C;
+  const int n = max(0, min(C, nc - c0));
+  RtState *st = I.st;
+  const int rom = (I.method == RT_ROM);
+  const int flag_ig = st->flag_ig, flag_pc = st->flag_pc;
+  const int lu_ig = st->lu_ok_ig, lu_pc = st->lu_ok_pc;
+  const int rank_ig = st->rank_ig, rank_pc = st->rank_pc;
+  const int mixed = (I.precision == RT_MIXED);
+  const int cur = (int)(st->steps & 1);
+  const double *__restrict__ bt = I.bt2[cur];
+
+  // initial guess: DMD when the IG ROM is available (eq. dmd-ig), else rho^{n-1}
+  int ig_fb = 0;
+  if (rom && flag_ig && lu_ig) {
+    rom_apply(I.ig, rank_ig, I.ld, nc, NT, bt, I.rho0, rred, rvec);
+  } else {
+    ig_fb = rom && flag_ig;
+    for (int c = c0; c < c0 + n; ++c) I.rho0[c] = I.rho[c];
+  }
+  double ct[CMAX], ss[CMAX], rp[CMAX], y[CMAX];
+#pragma unroll
+  for (int t = 0; t < CMAX; ++t) {
+    const bool in = t < n;
+    ct[t] = in ? I.ct[c0 + t] : 1.0;
+    ss[t] = in ? I.ss[c0 + t] : 0.0;
+    rp[t] = in ? I.rho0[c0 + t] : 0.0;
+    y[t] = 0.0;
+  }
+  int parity = 0, parityf = 0;
+  int nsweep = 0, n32 = 0, conv = 0, used_pc = 0, pc_fb = 0, exact = 0, first_corr = 1;
+  int need64 = 1;
+  double resid = 0.0;
+  for (;;) {
+    if (need64) {
+      // rho^{(l-1/2)} = T Sigma_s rho^{(l-1)} + b~ (eq. SI_rho) in FP64
+      double s[CMAX], acc[CMAX];
+#pragma unroll
+      for (int t = 0; t < CMAX; ++t) s[t] = ss[t] * rp[t];
+      sweep_moment<CMAX, double>(I, ct, s, n, acc, slots, parity);
+#pragma unroll
+      for (int t = 0; t < CMAX; ++t) y[t] = acc[t] + ((t < n) ? bt[c0 + t] : 0.0);
+      if (nsweep == 0) {
+#pragma unroll
+        for (int t = 0; t < CMAX; ++t)
+          if (t < n) I.rhalf[c0 + t] = y[t];
+      }
+      nsweep++;
+      exact = 1;
+      need64 = 0;
+    }
+    double dl = 0.0, yl = 0.0;
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t)
+      if (t < n) {
+        dl = fmax(dl, fabs(y[t] - rp[t]));
+        yl = fmax(yl, fabs(y[t]));
+      }
+    double dn, yn;
+    wg_max2(dl, yl, red, dn, yn);
+    resid = yn > 0.0 ? dn / yn : dn;
+    if (stop_test(dn, yn, I.tol)) {
+      if (exact) {
+        conv = 1;
+        break;
+      }
+      // mixed precision: the FP32-accumulated iterate passed; re-check it on
+      // an FP64 sweep before accepting
+      if (nsweep >= I.max_iter) break;
+      need64 = 1;
+      continue;
+    }
+    if (nsweep >= I.max_iter) break;
+    // synthetic acceleration
+    double d[CMAX];
+    if (rom && first_corr && flag_pc && lu_pc) {
+      // ROM-enhanced correction of the first iteration (eq. dmd-sa)
+#pragma unroll
+      for (int t = 0; t < CMAX; ++t)
+        if (t < n) I.work[c0 + t] = y[t] - I.rho0[c0 + t];
+      __syncthreads();
+      rom_apply(I.pc, rank_pc, I.ld, nc, NT, I.work, I.dpc, rred, rvec);
+#pragma unroll
+      for (int t = 0; t < CMAX; ++t) d[t] = (t < n) ? I.dpc[c0 + t] : 0.0;
+      used_pc = 1;
+    } else if (I.method == RT_SI_PLAIN) {
+#pragma unroll
+      for (int t = 0; t < CMAX; ++t) d[t] = 0.0;
+    } else {
+      if (rom && first_corr && flag_pc) pc_fb = 1;
+      double rhs[CMAX];
+#pragma unroll
+      for (int t = 0; t < CMAX; ++t) rhs[t] = ss[t] * (y[t] - rp[t]);
+      dsa_solve_slab<CMAX>(I, c0, n, rhs, d, slots, parity);
+    }
+    first_corr = 0;
+    if (mixed) {
+      // y <- y + T32 Sigma_s (rho^{(l)} - rho^{(l-1)}): increment swept in FP32
+      float s32[CMAX], acc32[CMAX], ctf[CMAX];
+#pragma unroll
+      for (int t = 0; t < CMAX; ++t) {
+        const double rn = y[t] + d[t];
+        s32[t] = (float)(ss[t] * (rn - rp[t]));
+        ctf[t] = (float)ct[t];
+        rp[t] = rn;
+      }
+      sweep_moment<CMAX, float>(I, ctf, s32, n, acc32, slotsf, parityf);
+#pragma unroll
+      for (int t = 0; t < CMAX; ++t) y[t] += (double)acc32[t];
+      exact = 0;
+      n32++;
+      nsweep++;
+    } else {
+#pragma unroll
+      for (int t = 0; t < CMAX; ++t) rp[t] = y[t] + d[t];
+      need64 = 1;
+    }
+  }
+  // rho^n = rho^{(l-1/2)} (Alg. 1 returns the un-corrected iterate)
+#pragma unroll
+  for (int t = 0; t < CMAX; ++t)
+    if (t < n) I.rho[c0 + t] = y[t];
+  if (tid == 0) {
+    st->iters = nsweep;
+    st->conv = conv;
+    st->used_pc = used_pc;
+    st->ig_fb = ig_fb;
+    st->pc_fb = pc_fb;
+    st->residual = resid;
+    st->phase = !flag_ig ? 1 : (!flag_pc ? 2 : 3);
+    st->cur = cur;
+    st->fp32_sweeps += n32;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_fpass_slab: f^n from rho^n (eq. sweep_to_obtain_f) and the right-hand side
+// b~^n = sum_j w_j sweep_j(f^n_j / dt + G, g) of the next step (Sec. 2.3), in
+// one traversal per ordinate pair, into the b~ buffer the step did not read.
+// rhs_only: skip the first sweep and rebuild the b~ the next step reads from
+// the stored f (creation, or a new inflow).
+// ---------------------------------------------------------------------------
+template <int CMAX, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_fpass_slab(const Inst *__restrict__ insts, int rhs_only) {
+  const Inst &I = insts[blockIdx.x];
+  __shared__ double slots[8 * RT_MAXWAVES];
+  const int NT = I.nthr, tid = threadIdx.x;
+  const int nc = I.nc;
+  const int C = (nc + NT - 1) / NT;
+  const int c0 = tid * C;
+  const int n = max(0, min(C, nc - c0));
+  const double idt = I.inv_dt;
+  double ct[CMAX], G[CMAX], srcc[CMAX], acc[CMAX];
+#pragma unroll
+  for (int t = 0; t < CMAX; ++t) {
+    const bool in = t < n;
+    ct[t] = in ? I.ct[c0 + t] : 1.0;
+    G[t] = in ? I.G[c0 + t] : 0.0;
+    srcc[t] = in ? rt_fma(I.ss[c0 + t], I.rho[c0 + t], G[t]) : 0.0;
+    acc[t] = 0.0;
+  }
+  int parity = 0;
+  const int nv = I.nv;
+  for (int p = 0; p < I.npair; ++p) {
+    const double m = I.pm[p], w = I.pw[p];
+    double *fneg = I.f + (size_t)p * nc + c0;            // mu < 0
+    double *fpos = I.f + (size_t)(nv - 1 - p) * nc + c0; // mu > 0
+    double inv[CMAX], bp[CMAX], bn[CMAX];
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t) {
+      if (t < n) {
+        inv[t] = rt_rcp(ct[t] + m);
+        bp[t] = fpos[t];
+        bn[t] = fneg[t];
+      }
+    }
+    if (!rhs_only) {
+      double Af = 1.0, Bf = 0.0, Ab = 1.0, Bb = 0.0;
+#pragma unroll
+      for (int t = 0; t < CMAX; ++t)
+        if (t < n) {
+          bp[t] = rt_fma(bp[t], idt, srcc[t]) * inv[t];
+          const double a = m * inv[t];
+          Bf = rt_fma(a, Bf, bp[t]);
+          Af *= a;
+        }
+#pragma unroll
+      for (int t = CMAX - 1; t >= 0; --t)
+        if (t < n) {
+          bn[t] = rt_fma(bn[t], idt, srcc[t]) * inv[t];
+          const double a = m * inv[t];
+          Bb = rt_fma(a, Bb, bn[t]);
+          Ab *= a;
+        }
+      double inF, inB;
+      wg_scan2<double>(Af, Bf, Ab, Bb, I.g[0], I.g[1], inF, inB, slots, parity);
+      parity ^= 1;
+      double f = inF;
+#pragma unroll
+      for (int t = 0; t < CMAX; ++t)
+        if (t < n) {
+          f = rt_fma(m * inv[t], f, bp[t]);
+          bp[t] = f;
+          fpos[t] = f;
+        }
+      f = inB;
+#pragma unroll
+      for (int t = CMAX - 1; t >= 0; --t)
+        if (t < n) {
+          f = rt_fma(m * inv[t], f, bn[t]);
+          bn[t] = f;
+          fneg[t] = f;
+        }
+    }
+    // right-hand-side sweep with source f^n_j / dt + G and inflow g
+    double Af = 1.0, Bf = 0.0, Ab = 1.0, Bb = 0.0;
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t)
+      if (t < n) {
+        bp[t] = rt_fma(bp[t], idt, G[t]) * inv[t];
+        const double a = m * inv[t];
+        Bf = rt_fma(a, Bf, bp[t]);
+        Af *= a;
+      }
+#pragma unroll
+    for (int t = CMAX - 1; t >= 0; --t)
+      if (t < n) {
+        bn[t] = rt_fma(bn[t], idt, G[t]) * inv[t];
+        const double a = m * inv[t];
+        Bb = rt_fma(a, Bb, bn[t]);
+        Ab *= a;
+      }
+    double inF, inB;
+    wg_scan2<double>(Af, Bf, Ab, Bb, I.g[0], I.g[1], inF, inB, slots, parity);
+    parity ^= 1;
+    double f = inF;
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t)
+      if (t < n) {
+        f = rt_fma(m * inv[t], f, bp[t]);
+        acc[t] = rt_fma(w, f, acc[t]);
+      }
+    f = inB;
+#pragma unroll
+    for (int t = CMAX - 1; t >= 0; --t)
+      if (t < n) {
+        f = rt_fma(m * inv[t], f, bn[t]);
+        acc[t] = rt_fma(w, f, acc[t]);
+      }
+  }
+  double *bt_out = rhs_only ? I.bt2[I.st->steps & 1] : I.bt2[I.st->cur ^ 1];
+#pragma unroll
+  for (int t = 0; t < CMAX; ++t)
+    if (t < n) bt_out[c0 + t] = acc[t];
+}
+
+// ---------------------------------------------------------------------------
+// k_post: the ROM bookkeeping of Alg. 2 (snapshot pairs, error indicators,
+// phase flags, the workgroup half of the incremental-SVD updates) and the
+// step's counters and record.  Cells with a stride of blockDim (256 for every
+// instance, so results do not depend on the batch); any instance size.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_post(const Inst *__restrict__ insts) {
+  const Inst &I = insts[blockIdx.x];
+  __shared__ RomSmem sm;
+  const int NT = blockDim.x, tid = threadIdx.x;
+  const int nc = I.nc;
+  RtState *st = I.st;
+  const int iters = st->iters;
+  const int conv = st->conv;
+  const int used_pc = st->used_pc;
+  int flag_ig = st->flag_ig, flag_pc = st->flag_pc;
+  int rank_ig = st->rank_ig, rank_pc = st->rank_pc;
+  int lu_ig = st->lu_ok_ig, lu_pc = st->lu_ok_pc;
+  const long long step_no = st->steps + 1;
+  const double *bt_prev = I.bt2[st->cur];  // b~^{n-1}, the right-hand side this step solved
+  int ig_update = 0, pc_update = 0, n0 = st->n0, n1 = st->n1;
+  double e_ig = -1.0, e_pc = -1.0;
+  if (I.method == RT_ROM) {
+    if (tid == 0) {
+      I.ig.pend->pending = 0;
+      I.pc.pend->pending = 0;
+    }
+    // ||rho^n||_2 and the error indicators (Sec. 3.2, normalised by ||rho^n||)
+    {
+      double part[3] = {0.0, 0.0, 0.0};
+      for (int c = tid; c < nc; c += NT) {
+        const double r = I.rho[c];
+        part[0] = rt_fma(r, r, part[0]);
+        const double e1 = I.rho0[c] - r;
+        part[1] = rt_fma(e1, e1, part[1]);
+        const double xs = r - I.rhalf[c];
+        const double e2 = I.dpc[c] - xs;
+        part[2] = rt_fma(e2, e2, part[2]);
+      }
+      wg_sum_fast<3>(part, sm.red, sm.vec);
+    }
+    const double rn = sqrt(sm.vec[0]);
+    const double scale = (I.abs_up || rn == 0.0) ? 1.0 : 1.0 / rn;
+    const double eig = sqrt(sm.vec[1]) * scale;
+    const double epc = sqrt(sm.vec[2]) * scale;
+    __syncthreads();
+    double *pbuf_ig = I.work;
+    double *pbuf_pc = I.work + nc;
+    double *xs = I.work + 2 * (size_t)nc;
+    double *bs = I.work + 3 * (size_t)nc;
+    if (!flag_ig) {
+      // phase 1: untruncated snapshot (rho^n, b~^{n-1})
+      const int dfc = isvd_prepare(I.ig, I.ld, nc, I.r_max, rank_ig, lu_ig, I.rho, bt_prev, pbuf_ig, 0,
+                                   I.eps_ig, sm);
+      if (dfc >= 0) {
+        ig_update = 1;
+        if (rom_tail_ratio(I.ig, rank_ig) <= I.eps_ig || rank_ig >= I.r_max || dfc == 1) {
+          flag_ig = 1;
+          n0 = (int)step_no;
+        }
+      }
+    } else {
+      int upd_ig = 0;
+      e_ig = eig;
+      if (e_ig > I.eps_up) {
+        isvd_prepare(I.ig, I.ld, nc, I.r_max, rank_ig, lu_ig, I.rho, bt_prev, pbuf_ig, 1, I.eps_ig, sm);
+        upd_ig = 1;
+        ig_update = 1;
+      }
+      if (iters > 1) {
+        // correction snapshots (eq. correction_snapshot)
+        for (int c = tid; c < nc; c += NT) {
+          const double rh = I.rhalf[c];
+          xs[c] = I.rho[c] - rh;
+          bs[c] = rh - I.rho0[c];
+        }
+        __syncthreads();
+        if (!flag_pc) {
+          const int dfc = isvd_prepare(I.pc, I.ld, nc, I.r_max, rank_pc, lu_pc, xs, bs, pbuf_pc, 0, I.eps_pc, sm);
+          if (dfc >= 0) {
+            pc_update = 1;
+            if (rom_tail_ratio(I.pc, rank_pc) <= I.eps_pc || rank_pc >= I.r_max || dfc == 1) {
+              flag_pc = 1;
+              n1 = (int)step_no - n0;
+            }
+          }
+        } else {
+          if (used_pc) e_pc = epc;
+          if (upd_ig || !used_pc || e_pc > I.eps_up) {
+            isvd_prepare(I.pc, I.ld, nc, I.r_max, rank_pc, lu_pc, xs, bs, pbuf_pc, 1, I.eps_pc, sm);
+            pc_update = 1;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const int fb = st->ig_fb + st->pc_fb;
+    if (I.hist && step_no <= I.hist_cap) {
+      RtStepRec &rec = I.hist[step_no - 1];
+      rec.iters = iters;
+      rec.phase = st->phase;
+      rec.converged = conv;
+      rec.ig_update = ig_update;
+      rec.pc_update = pc_update;
+      rec.rank_ig = rank_ig;
+      rec.rank_pc = rank_pc;
+      rec.fallback = fb > 0;
+      rec.e_ig = e_ig;
+      rec.e_pc = e_pc;
+      rec.residual = st->residual;
+    }
+    st->flag_ig = flag_ig;
+    st->flag_pc = flag_pc;
+    st->n0 = n0;
+    st->n1 = n1;
+    st->rank_ig = rank_ig;
+    st->rank_pc = rank_pc;
+    st->lu_ok_ig = lu_ig;
+    st->lu_ok_pc = lu_pc;
+    st->ig_updates += ig_update;
+    st->pc_updates += pc_update;
+    st->fallbacks += fb;
+    st->steps = step_no;
+    st->si_total += iters;
+    st->sweeps_total += iters + 2;
+    st->nonconv += !conv;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_rom_update: the O(N r^2) half of the incremental-SVD updates prepared by
+// k_post, one thread per cell over the whole grid (blockIdx.y = instance).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_rom_update(const Inst *__restrict__ insts) {
+  const Inst &I = insts[blockIdx.y];
+  __shared__ double uc[2][RT_KC * RT_KC], vc[2][RT_KC * RT_KC];
+  if (I.method != RT_ROM) return;
+  if ((int)(blockIdx.x * blockDim.x) >= I.nc) return;
+  const RomPend *P[2] = {I.ig.pend, I.pc.pend};
+  const int pend0 = P[0]->pending, pend1 = P[1]->pending;
+  if (!pend0 && !pend1) return;
+  for (int e = threadIdx.x; e < RT_KC * RT_KC; e += blockDim.x) {
+    if (pend0) {
+      uc[0][e] = P[0]->Uc[e];
+      vc[0][e] = P[0]->Vc[e];
+    }
+    if (pend1) {
+      uc[1][e] = P[1]->Uc[e];
+      vc[1][e] = P[1]->Vc[e];
+    }
+  }
+  __syncthreads();
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < I.nc) {
+    if (pend0) isvd_rotate_cell(I.ig, *P[0], uc[0], vc[0], I.ld, c);
+    if (pend1) isvd_rotate_cell(I.pc, *P[1], uc[1], vc[1], I.ld, c);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Setup: cell-centred DSA operator for finite volumes and its Thomas factors
+// in affine form (serial over cells, once per problem).
+// Reading of eq. rho_residual for FV: diffusion coefficient
+// D = 1/(3 sigma~_t) + h/4, harmonic face coupling, Marshak vacuum faces.
+// ---------------------------------------------------------------------------
+__global__ void k_setup_dsa_slab(const Inst *__restrict__ insts) {
+  const Inst &I = insts[blockIdx.x];
+  if (threadIdx.x != 0) return;
+  const int nc = I.nc;
+  const double h = I.hx;
+  double *fe = const_cast<double *>(I.dsa_fe);
+  double *bg = const_cast<double *>(I.dsa_bg);
+  double *invd = const_cast<double *>(I.dsa_invd);
+  auto Dof = [&](int i) { return 1.0 / (3.0 * I.ct[i]) + 0.25 * h; };
+  auto face = [&](double Dp, double Dq) { return 2.0 * Dp * Dq / (h * (Dp + Dq)); };
+  auto bdry = [&](double Dp) { return 2.0 * Dp / (h + 4.0 * Dp); };
+  double dprev = 0.0, upprev = 0.0;
+  for (int i = 0; i < nc; ++i) {
+    const double Di = Dof(i);
+    const double kl = (i > 0) ? face(Di, Dof(i - 1)) : bdry(Di);
+    const double kr = (i < nc - 1) ? face(Di, Dof(i + 1)) : bdry(Di);
+    const double diag = I.sa[i] + I.inv_dt + (kl + kr) / h;
+    const double lo = (i > 0) ? -kl / h : 0.0;
+    const double up = (i < nc - 1) ? -kr / h : 0.0;
+    double e = 0.0, dp = diag;
+    if (i > 0) {
+      e = lo / dprev;
+      dp = diag - e * upprev;
+    }
+    fe[i] = -e;
+    invd[i] = 1.0 / dp;
+    bg[i] = -up / dp;
+    dprev = dp;
+    upprev = up;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launch helpers (C linkage inside the library only)
+// ---------------------------------------------------------------------------
+extern "C" hipError_t rt_launch_slab_si(const Inst *dinsts, int ninst, int nthreads, int cmax,
+                                        hipStream_t stream) {
+  dim3 grid(ninst), blk(nthreads);
+  if (cmax <= 4)
+    hipLaunchKernelGGL((k_si_slab<4, 1024>), grid, blk, 0, stream, dinsts);
+  else
+    hipLaunchKernelGGL((k_si_slab<8, 512>), grid, blk, 0, stream, dinsts);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t rt_launch_slab_fpass(const Inst *dinsts, int ninst, int nthreads, int cmax,
+                                           hipStream_t stream) {
+  dim3 grid(ninst), blk(nthreads);
+  if (cmax <= 4)
+    hipLaunchKernelGGL((k_fpass_slab<4, 1024>), grid, blk, 0, stream, dinsts, 0);
+  else
+    hipLaunchKernelGGL((k_fpass_slab<8, 512>), grid, blk, 0, stream, dinsts, 0);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t rt_launch_post(const Inst *dinsts, int ninst, hipStream_t stream) {
+  hipLaunchKernelGGL(k_post, dim3(ninst), dim3(256), 0, stream, dinsts);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t rt_launch_rom_update(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream) {
+  hipLaunchKernelGGL(k_rom_update, dim3((nc_max + 255) / 256, ninst), dim3(256), 0, stream, dinsts);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t rt_launch_slab_rhs(const Inst *dinsts, int ninst, int nthreads, int cmax,
+                                         hipStream_t stream) {
+  dim3 grid(ninst), blk(nthreads);
+  if (cmax <= 4)
+    hipLaunchKernelGGL((k_fpass_slab<4, 1024>), grid, blk, 0, stream, dinsts, 1);
+  else
+    hipLaunchKernelGGL((k_fpass_slab<8, 512>), grid, blk, 0, stream, dinsts, 1);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t rt_launch_slab_setup(const Inst *dinsts, int ninst, hipStream_t stream) {
+  hipLaunchKernelGGL(k_setup_dsa_slab, dim3(ninst), dim3(64), 0, stream, dinsts);
+  return hipGetLastError();
+}

@@ -107,7 +107,7 @@ def plane(nx: int, ny: int, n_azim: int, n_polar: int, sigma_s, sigma_a, source,
 # The five workloads
 # --------------------------------------------------------------------------
 
-def c1_slab_two_region(nx: int = 256, nsteps: int = 50) -> ProblemSpec:
+def slab_two_region(nx: int = 256, nsteps: int = 50) -> ProblemSpec:
     """1D slab, 256 cells, GL16; sigma_s = 100 on [0.3, 0.7] else 1,
     sigma_a = 0.1, q = 1 on [0.4, 0.6], vacuum, dt = 0.01, plain SI-DSA FP64."""
     x = _centres(nx, 1.0)
@@ -132,7 +132,7 @@ def _slab_regions(nx: int, ss_reg, sa_reg, qlo: float, qhi: float):
     return ss_reg[k].copy(), sa_reg[k].copy(), q
 
 
-def c2_slab_random_regions(seed: int = 2, nx: int = 4096, n_polar: int = 64,
+def slab_random_regions(seed: int = 2, nx: int = 4096, n_polar: int = 64,
                            nsteps: int = 400, method: str = "rom",
                            precision: str = "mixed") -> ProblemSpec:
     """1D slab, 4096 cells, GL64, 32 seeded regions; q = 1 on the middle 10 %;
@@ -145,7 +145,7 @@ def c2_slab_random_regions(seed: int = 2, nx: int = 4096, n_polar: int = 64,
                 name=f"slab{nx}_gl{n_polar}_32reg")
 
 
-def c3_checkerboard(n: int = 256, n_azim: int = 16, n_polar: int = 8, nsteps: int = 200,
+def checkerboard(n: int = 256, n_azim: int = 16, n_polar: int = 8, nsteps: int = 200,
                     method: str = "rom", precision: str = "mixed") -> ProblemSpec:
     """2D [0,1]^2, n x n cells, CL(16, 8) = 128 directions; 16 x 16 blocks,
     absorber blocks (sigma_a = 10, sigma_s = 0) where the block-index sum is
@@ -163,7 +163,7 @@ def c3_checkerboard(n: int = 256, n_azim: int = 16, n_polar: int = 8, nsteps: in
                  precision=precision, nsteps=nsteps, name=f"checker{n}_cl{n_azim}x{n_polar}")
 
 
-def c4_batch(seed: int = 4, count: int = 512, nsteps: int = 100, method: str = "rom",
+def slab_batch(seed: int = 4, count: int = 512, nsteps: int = 100, method: str = "rom",
              precision: str = "mixed", ncells=(128, 2048),
              nords=(16, 32, 64)) -> List[ProblemSpec]:
     """Batch of independent 1D slabs: cells uniform on {128..2048}, S_N order
@@ -198,20 +198,20 @@ def gaussian_random_field(rng: np.random.Generator, n: int, corr_len: float,
     return fld / sd if sd > 0 else fld
 
 
-C5_GRIDS = (64, 96, 128, 192, 256, 384, 512)
-C5_QUADS = ((8, 4), (16, 4), (16, 8))  # CL(N_phi, N_z): 32, 64, 128 directions
+SERVING_GRIDS = (64, 96, 128, 192, 256, 384, 512)
+SERVING_QUADS = ((8, 4), (16, 4), (16, 8))  # CL(N_phi, N_z): 32, 64, 128 directions
 
 
-def c5_request(rng: np.random.Generator, idx: int = 0, grid: Optional[int] = None,
+def serving_request(rng: np.random.Generator, idx: int = 0, grid: Optional[int] = None,
                quad: Optional[Sequence[int]] = None, nsteps: Optional[int] = None,
                method: str = "rom", precision: str = "mixed") -> ProblemSpec:
     """One serving request: 2D [0,1]^2, N x N cells, CL quadrature with 32-128
     directions, sigma_s = exp(Z) with Z a Gaussian random field (mean -2,
     std 2, correlation length 0.1), sigma_a = 0.1, box source q = 1 with
     centre U(0.2, 0.8)^2 and half-width U(0.025, 0.15), dt = 0.01."""
-    n = int(rng.choice(np.asarray(C5_GRIDS))) if grid is None else int(grid)
-    qi = int(rng.integers(0, len(C5_QUADS)))
-    nphi, nz = C5_QUADS[qi] if quad is None else tuple(quad)
+    n = int(rng.choice(np.asarray(SERVING_GRIDS))) if grid is None else int(grid)
+    qi = int(rng.integers(0, len(SERVING_QUADS)))
+    nphi, nz = SERVING_QUADS[qi] if quad is None else tuple(quad)
     steps = int(rng.integers(100, 501)) if nsteps is None else int(nsteps)
     z = -2.0 + 2.0 * gaussian_random_field(rng, n, 0.1)
     ss = np.exp(z).reshape(-1)
@@ -224,9 +224,9 @@ def c5_request(rng: np.random.Generator, idx: int = 0, grid: Optional[int] = Non
                  precision=precision, nsteps=steps, name=f"req{idx}_n{n}_cl{nphi}x{nz}")
 
 
-def c5_stream(seed: int = 5, count: int = 64, **kw) -> List[ProblemSpec]:
+def serving_stream(seed: int = 5, count: int = 64, **kw) -> List[ProblemSpec]:
     rng = np.random.default_rng(seed)
-    return [c5_request(rng, i, **kw) for i in range(count)]
+    return [serving_request(rng, i, **kw) for i in range(count)]
 
 
 # --------------------------------------------------------------------------

@@ -1,0 +1,84 @@
+"""Helpers shared by the GPU parity tests (imported by tests only)."""
+import sys
+
+import numpy as np
+
+import oracle
+from paper_2603_19647_amd import rtrom
+
+
+def say(msg: str):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b) -> float:
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a - b))
+
+
+def step_both(spec, nsteps: int, method=None):
+    """March the oracle and the GPU library side by side; return per-step
+    rho pairs, the two histories and the two handles."""
+    o = oracle.OracleProblem(spec, method=method)
+    g = rtrom.Problem(spec if method is None else spec.replace(method=method))
+    errs = []
+    for _ in range(nsteps):
+        o.step()
+        g.step()
+        errs.append(rel_l2(g.rho(), o.rho()))
+    return np.array(errs), o, g
+
+
+def assert_same_decisions(o, g):
+    ho, hg = o.history(), g.history()
+    for key in ("iters", "phase", "converged", "ig_update", "pc_update", "rank_ig", "rank_pc"):
+        np.testing.assert_array_equal(hg[key], ho[key], err_msg=key)
+    co, sg = o.counters(), g.stats()
+    assert sg["n0"] == co["n0"] and sg["n1"] == co["n1"]
+    assert sg["si_iters_total"] == co["si_total"]
+    assert sg["sweeps_total"] == co["sweeps_total"]
+
+
+def oracle_rounding_spread(spec, nsteps: int, method=None):
+    """Per-step rel. L2 distance between two oracle runs whose inputs differ by
+    one part in 1e15 (sigma_s scaled by 1 + 1e-15, then by 1 - 1e-15): how far
+    two equally valid FP64 evaluations of the method drift apart at each step.
+    The ROM's reduced solves amplify rounding, so this floor grows with time."""
+    base = oracle.OracleProblem(spec, method=method)
+    pert = [oracle.OracleProblem(spec.replace(sigma_s=spec.sigma_s * (1 + e)), method=method)
+            for e in (1e-15, -1e-15)]
+    out = []
+    for _ in range(nsteps):
+        base.step()
+        r = base.rho()
+        d = 0.0
+        for p in pert:
+            p.step()
+            d = max(d, rel_l2(p.rho(), r))
+        out.append(d)
+    return np.array(out)
+
+
+def converged_reference(spec, nsteps: int, ref_tol: float = 1e-13):
+    """Per-step rho of a tightly converged FP64 SI-DSA oracle run: the discrete
+    backward-Euler solution to ~ref_tol."""
+    ref = oracle.OracleProblem(spec.replace(tol=ref_tol, precision="fp64"), method="si_dsa")
+    out = []
+    for _ in range(nsteps):
+        ref.step()
+        out.append(ref.rho())
+    return out
+
+
+def oracle_tol_error(spec, nsteps: int, method=None, ref=None):
+    """Largest per-step rel. L2 distance between the FP64 oracle at spec.tol and
+    the converged reference: the error the stop test of Alg. 1 itself leaves
+    at this tolerance."""
+    ref = converged_reference(spec, nsteps) if ref is None else ref
+    o = oracle.OracleProblem(spec.replace(precision="fp64"), method=method)
+    worst = 0.0
+    for k in range(nsteps):
+        o.step()
+        worst = max(worst, rel_l2(o.rho(), ref[k]))
+    return worst

@@ -1,0 +1,190 @@
+"""GPU parity of the slab (1D) path against the FP64 oracle, through the C ABI.
+
+Bars: FP64 runs agree with the oracle to rel. L2 <= 1e-10 at every step with
+identical SI iteration counts, phases, ROM update steps, ranks, N0 and N1 (for
+ROM runs past the horizon where the method's own rounding spread exceeds
+1e-11, within 10x that spread).  Mixed-precision runs at a tight tolerance
+agree with the FP64 oracle to 1e-10 (the FP64 refinement loses nothing); at
+the configured tolerance they agree with the FP64 oracle to 1e-8, or to twice
+the distance the oracle itself keeps from the converged solution when the
+stop test of Alg. 1 leaves more than that.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_19647_amd import rtrom
+from paper_2603_19647_amd import workloads as W
+from tests.gpu_util import (assert_same_decisions, converged_reference, oracle_rounding_spread,
+                            oracle_tol_error, rel_l2, say, step_both)
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-8
+
+
+def test_slab256_si_dsa_full_config():
+    spec = W.slab_two_region()
+    say(f"c1 si_dsa {spec.name}")
+    errs, o, g = step_both(spec, spec.nsteps)
+    assert errs.max() <= FP64_TOL, errs.max()
+    assert_same_decisions(o, g)
+    assert rel_l2(g.f(), o.f()) <= FP64_TOL
+    assert rel_l2(g.rhs(), o.bt()) <= FP64_TOL
+
+
+def test_slab256_rom_fp64():
+    spec = W.slab_two_region().replace(method="rom")
+    say("slab256 rom fp64")
+    errs, o, g = step_both(spec, spec.nsteps)
+    assert errs.max() <= FP64_TOL, errs.max()
+    assert_same_decisions(o, g)
+    st = g.stats()
+    assert st["n0"] > 0 and st["n1"] > 0
+
+
+@pytest.mark.parametrize("nx,nv", [(1, 2), (5, 4), (63, 8), (64, 8), (65, 16), (257, 4), (1000, 16),
+                                   (2049, 32), (4096, 64)])
+def test_ragged_sizes_si_dsa(nx, nv):
+    spec = W.random_slab(nx + nv, nx, nv, inflow=(0.8, 0.3, 0, 0), dt=0.02)
+    say(f"ragged nx={nx} nv={nv}")
+    errs, o, g = step_both(spec, 4)
+    assert errs.max() <= FP64_TOL
+    assert_same_decisions(o, g)
+    assert rel_l2(g.f(), o.f()) <= FP64_TOL
+
+
+def test_plain_si_matches():
+    spec = W.random_slab(3, 200, 8, tol=1e-9, max_iter=5000)
+    errs, o, g = step_both(spec, 3, method="si")
+    assert errs.max() <= FP64_TOL
+    assert_same_decisions(o, g)
+
+
+def test_slab4096_rom_fp64_full_size():
+    """FP64 ROM on the 4096-cell, GL64 slab: identical decisions at every step;
+    rel. L2 <= 1e-10 while the method's own rounding spread (two oracle runs one
+    part in 1e15 apart) stays below 1e-11, and within 10x that spread after.
+    The DMD solves amplify rounding, so later steps cannot be held to 1e-10
+    by any FP64 evaluation order (the oracle against itself exceeds it)."""
+    spec = W.slab_random_regions(precision="fp64")
+    n = 120
+    say(f"slab4096 rom fp64 4096x64, {n} steps")
+    errs, o, g = step_both(spec, n)
+    assert_same_decisions(o, g)
+    spread = oracle_rounding_spread(spec, n)
+    early = spread < 1e-11
+    assert early[:40].all()
+    assert errs[early].max() <= FP64_TOL, errs[early].max()
+    assert np.all(errs <= np.maximum(FP64_TOL, 10.0 * spread)), (errs / np.maximum(spread, 1e-300)).max()
+
+
+def mixed_bar(spec, nsteps, ref, method=None):
+    return max(MIXED_TOL, 3.0 * oracle_tol_error(spec, nsteps, method=method, ref=ref))
+
+
+def test_slab4096_mixed_full_config():
+    """4096 cells, GL64, 32 regions, 400 steps, ROM with FP32 sweeps refined
+    in FP64, against the converged FP64 solution."""
+    spec = W.slab_random_regions()
+    say("slab4096 rom mixed 4096x64, 400 steps")
+    assert spec.precision == "mixed" and spec.method == "rom"
+    ref = converged_reference(spec, spec.nsteps)
+    g = rtrom.Problem(spec)
+    errs = []
+    for k in range(spec.nsteps):
+        g.step()
+        errs.append(rel_l2(g.rho(), ref[k]))
+    errs = np.array(errs)
+    bar = mixed_bar(spec, spec.nsteps, ref)
+    say(f"  max rel L2 to converged {errs.max():.3e}, bar {bar:.3e}")
+    assert bar <= 1e-7
+    assert errs.max() <= bar, errs.max()
+    st = g.stats()
+    assert st["fp32_sweeps"] > 0 and st["n0"] > 0 and st["n1"] > 0
+    assert st["si_iters_total"] < 0.7 * 9 * spec.nsteps
+
+
+@pytest.mark.parametrize("method", ["si_dsa", "rom"])
+def test_mixed_tight_tolerance_matches_fp64(method):
+    """At tol = 1e-12 the FP32 increments refined by FP64 sweeps reach the
+    FP64 answer: rel. L2 <= 1e-10 against the FP64 oracle at every step."""
+    spec = W.slab_random_regions(nx=1500, n_polar=32, precision="mixed", method=method).replace(tol=1e-12)
+    say(f"mixed tight tol {method}")
+    o = oracle.OracleProblem(spec.replace(precision="fp64"))
+    g = rtrom.Problem(spec)
+    worst = 0.0
+    for _ in range(60):
+        o.step()
+        g.step()
+        worst = max(worst, rel_l2(g.rho(), o.rho()))
+    assert worst <= FP64_TOL, worst
+    assert g.stats()["fp32_sweeps"] > 0
+
+
+def test_mixed_si_dsa_small():
+    spec = W.random_slab(7, 700, 16, precision="mixed", dt=0.005)
+    errs, o, g = step_both(spec, 30)
+    assert errs.max() <= MIXED_TOL
+
+
+def test_batch_equals_alone_bitwise():
+    specs = [W.random_slab(20 + k, nx, nv, method=m, precision=pr)
+             for k, (nx, nv, m, pr) in enumerate([(128, 16, "rom", "mixed"), (700, 32, "rom", "fp64"),
+                                                   (2048, 64, "si_dsa", "mixed"), (333, 16, "si_dsa", "fp64"),
+                                                   (1500, 32, "rom", "mixed"), (64, 64, "rom", "fp64")])]
+    say("batch vs alone")
+    batch = [rtrom.Problem(s) for s in specs]
+    rtrom.march_batch(batch, 25)
+    for s, b in zip(specs, batch):
+        a = rtrom.Problem(s)
+        a.march(25)
+        np.testing.assert_array_equal(a.rho(), b.rho())
+        assert a.stats()["si_iters_total"] == b.stats()["si_iters_total"]
+
+
+def test_deterministic_reruns():
+    spec = W.slab_random_regions(nx=2000, n_polar=32, nsteps=60)
+    a, b = rtrom.Problem(spec), rtrom.Problem(spec)
+    a.march(60)
+    b.march(60)
+    np.testing.assert_array_equal(a.rho(), b.rho())
+    np.testing.assert_array_equal(a.f(), b.f())
+
+
+def test_slab_batch_subset_against_oracle():
+    specs = W.slab_batch(count=512)[:12]
+    say("batch512 subset of 12 instances, 100 steps, mixed ROM")
+    probs = [rtrom.Problem(s) for s in specs]
+    rtrom.march_batch(probs, 100)
+    for s, p in zip(specs, probs):
+        ref = converged_reference(s, 100)
+        bar = mixed_bar(s, 100, ref)
+        err = rel_l2(p.rho(), ref[-1])
+        say(f"  {s.name}: rel L2 to converged {err:.3e}, bar {bar:.3e}")
+        assert bar <= 1e-6
+        assert err <= bar, (s.name, err, bar)
+
+
+def test_nonconvergence_reports_and_advances():
+    spec = W.random_slab(15, 32, 8, max_iter=1, tol=1e-12)
+    g = rtrom.Problem(spec)
+    assert g.step() == rtrom.ENOCONV
+    st = g.stats()
+    assert st["steps"] == 1 and st["nonconverged_steps"] == 1
+    o = oracle.OracleProblem(spec)
+    o.step()
+    assert rel_l2(g.rho(), o.rho()) <= FP64_TOL
+
+
+def test_infinite_medium_closed_form_gpu():
+    sa, dt = 0.7, 0.2
+    spec = W.infinite_medium(dim=1, n=100, n_polar=8, sigma_a=sa, dt=dt, method="rom", tol=1e-12)
+    g = rtrom.Problem(spec)
+    for n in range(1, 8):
+        g.step()
+        np.testing.assert_allclose(g.rho(), (1 + dt * sa) ** -n, rtol=1e-11)
+        g.set_inflow([(1 + dt * sa) ** -(n + 1)] * 4)
+    h = g.history()
+    assert g.stats()["n0"] == 2 and np.all(h["iters"][2:] == 1)

@@ -481,7 +481,7 @@ def test_rom_solve_sign_invariance():
 # --------------------------------------------------------------------------
 
 def test_rom_matches_si_dsa_every_step():
-    sp = W.c1_slab_two_region()
+    sp = W.slab_two_region()
     a = oracle.OracleProblem(sp, method="si_dsa")
     b = oracle.OracleProblem(sp, method="rom")
     worst = 0.0
@@ -519,7 +519,7 @@ def test_ig_exact_on_rank_one_solution(tol):
 
 
 def test_rank_growth_and_cap():
-    sp = W.c2_slab_random_regions(nx=512, n_polar=16, nsteps=60, precision="fp64")
+    sp = W.slab_random_regions(nx=512, n_polar=16, nsteps=60, precision="fp64")
     o = oracle.OracleProblem(sp)
     o.march(60)
     h = o.history()
@@ -532,8 +532,8 @@ def test_rank_growth_and_cap():
     assert np.all(np.diff(ph) >= 0)
 
 
-def test_rom_accelerates_c2_like():
-    sp = W.c2_slab_random_regions(nx=1024, n_polar=32, nsteps=80, precision="fp64")
+def test_rom_accelerates_random_slab():
+    sp = W.slab_random_regions(nx=1024, n_polar=32, nsteps=80, precision="fp64")
     a = oracle.OracleProblem(sp, method="si_dsa")
     b = oracle.OracleProblem(sp, method="rom")
     a.march(80)
