@@ -278,6 +278,8 @@ static size_t slab_bytes(const rtrom_problem_desc *d, int nv) {
     L.take(RT_RMAX * RT_RMAX * 8);
     L.take(RT_RMAX * 4);
     L.take(sizeof(RomPend));
+    L.take(sizeof(RomWork));
+    L.take(3 * ((nc + 255) / 256) * RT_NPART * 8);
   }
   L.take(sizeof(RtState));
   L.take(sizeof(Inst));
@@ -395,6 +397,7 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   double *qbuf = D((size_t)nv * 8 * 6);
   I.f = D((size_t)nv * nc * 8);
   RomDev *roms[2] = {&I.ig, &I.pc};
+  RomWork rom_work_init[2];
   for (int r = 0; r < 2; ++r) {
     roms[r]->U = D((RT_RMAX + 1) * ld * 8);
     roms[r]->W = D((RT_RMAX + 1) * ld * 8);
@@ -403,6 +406,17 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
     roms[r]->LU = D(RT_RMAX * RT_RMAX * 8);
     roms[r]->perm = (int *)D(RT_RMAX * 4);
     roms[r]->pend = (RomPend *)D(sizeof(RomPend));
+    roms[r]->work = (RomWork *)D(sizeof(RomWork));
+    {
+      const size_t nb = ((size_t)nc + 255) / 256;
+      double *parts = D(3 * nb * RT_NPART * 8);
+      RomWork wk;
+      memset(&wk, 0, sizeof(wk));
+      wk.part1 = parts;
+      wk.part2 = parts + nb * RT_NPART;
+      wk.part3 = parts + 2 * nb * RT_NPART;
+      rom_work_init[r] = wk;
+    }
   }
   I.st = (RtState *)D(sizeof(RtState));
   p->dinst = (Inst *)D(sizeof(Inst));
@@ -460,10 +474,11 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   ok = ok && H2D(I.rho, rho0.data(), nc * 8);
   if (d->f0)
     for (int j = 0; j < nv && ok; ++j) ok = H2D(I.f + (size_t)j * nc, rho0.data(), nc * 8);
-  // initial phase-machine state: everything zero except the LU flags
+  // initial phase-machine state: everything zero
   RtState st0;
   memset(&st0, 0, sizeof(st0));
   ok = ok && H2D(I.st, &st0, sizeof(st0));
+  ok = ok && H2D(I.ig.work, &rom_work_init[0], sizeof(RomWork)) && H2D(I.pc.work, &rom_work_init[1], sizeof(RomWork));
   if (!ok) return bail(RTROM_EDEVICE, "upload failed");
   if (ensure_hist(p, 64) != RTROM_OK) {
     std::string m = g_err;
@@ -471,7 +486,7 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   }
   if (d->dim == 1) {
     if (upload_inst(p) != RTROM_OK) return bail(RTROM_EDEVICE, "upload descriptor failed");
-    if (rt_launch_slab_setup(p->dinst, 1, p->stream) != hipSuccess) return bail(RTROM_EDEVICE, "setup launch failed");
+    if (rt_launch_slab_setup(p->dinst, 1, nc, p->stream) != hipSuccess) return bail(RTROM_EDEVICE, "setup launch failed");
     int cmax;
     int nt = slab_launch_threads(&I.nthr, &nc, 1, &cmax);
     if (rt_launch_slab_rhs(p->dinst, 1, nt, cmax, p->stream) != hipSuccess)
@@ -547,7 +562,7 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps, int n, int nsteps) 
         RT_HIP(hipStreamWaitEvent(s2, ps[0]->ev_si, 0), "event wait");
       }
       rt_prof_begin(RT_K_POST, s2);
-      RT_HIP(rt_launch_post(dinsts, n, s2), "post launch");
+      RT_HIP(rt_launch_rom(dinsts, n, nc_max, any_rom, s2), "ROM launch");
       rt_prof_end(RT_K_POST, s2);
       if (any_rom) {
         rt_prof_begin(RT_K_ROM_UPDATE, s2);

@@ -20,6 +20,21 @@ struct RomPend {
   double Vc[RT_KC * RT_KC];
 };
 
+// Work record of one incremental-SVD update in flight: what the decide
+// kernel asked for and the per-block partial sums of the projection passes.
+#define RT_NPART 48
+struct RomWork {
+  int active;    // this ROM takes a snapshot this step
+  int truncate;  // truncated update (phases 2/3) vs untruncated construction
+  int r;         // rank before the update
+  int nblk;      // 256-cell blocks of the instance
+  long long step_no;
+  double eps;
+  const double *x, *b;  // snapshot pair (global)
+  double *p;            // projected residual (global scratch)
+  double *part1, *part2, *part3;  // [nblk][RT_NPART] partial sums of the passes
+};
+
 // Per-instance ROM storage (Sec. 3.1): orthonormal basis U, W = B V (so the
 // DMD operator U^T B V S^{-1} never needs the snapshot matrix B), singular
 // values S, M = U^T W kept incrementally, and the LU factors of
@@ -32,6 +47,7 @@ struct RomDev {
   double *LU;   // [RT_RMAX][RT_RMAX] row-major
   int *perm;    // [RT_RMAX]
   RomPend *pend;
+  RomWork *work;
 };
 
 // Device-resident state of the phase machine (Alg. 2) and counters.

@@ -35,11 +35,11 @@ extern "C" hipError_t rt_launch_slab_si(const Inst *dinsts, int ninst, int nthre
                                         hipStream_t stream);
 extern "C" hipError_t rt_launch_slab_fpass(const Inst *dinsts, int ninst, int nthreads, int cmax,
                                            hipStream_t stream);
-extern "C" hipError_t rt_launch_post(const Inst *dinsts, int ninst, hipStream_t stream);
+extern "C" hipError_t rt_launch_rom(const Inst *dinsts, int ninst, int nc_max, int any_rom, hipStream_t s);
 extern "C" hipError_t rt_launch_rom_update(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream);
 extern "C" hipError_t rt_launch_slab_rhs(const Inst *dinsts, int ninst, int nthreads, int cmax,
                                          hipStream_t stream);
-extern "C" hipError_t rt_launch_slab_setup(const Inst *dinsts, int ninst, hipStream_t stream);
+extern "C" hipError_t rt_launch_slab_setup(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream);
 
 // 2D
 int rt_plane_create(rtrom_problem *p);

@@ -329,50 +329,45 @@ __device__ inline void core_svd(RomSmem &sm, int rows, int cols) {
 }
 
 // ---------------------------------------------------------------------------
-// Incremental SVD, first half (App. B): projection of the snapshot x onto
-// span(U) by classical Gram-Schmidt applied twice, the core
-// [[diag S, U^T x], [0, ||p||]], its SVD, truncation, the reduced operator
-// M_new = Uc^T Q^T [W b] Vc (Q = [U, p/||p||]) with A_r = M_new S^{-1} and its
-// LU.  The basis rotation itself is left in R.pend for k_rom_update.
-// x, b: global snapshot vectors; pbuf: global scratch that receives p.
-// truncate: keep s_i / sum(s) > eps; rank <= rmax.  Returns 1 for a
-// rank-deficient snapshot (x in span U), 0 otherwise, -1 if x = 0 at rank 0.
+// Incremental SVD, small dense part (App. B, eq. svd_core), one workgroup:
+// sums the projection partials of the three grid passes in a fixed order,
+// builds the core [[diag S, U^T x], [0, ||p||]] and Q^T [W b] (Q = [U, p/||p||]),
+// takes the core SVD, truncates, forms M_new = Uc^T Q^T [W b] Vc and
+// A_r = M_new S^{-1} with its LU, and leaves the basis rotation in R.pend for
+// k_rom_update.  Returns 1 for a rank-deficient snapshot (x in span U), 0
+// otherwise, -1 if x = 0 at rank 0 (nothing added).  rank / luok updated.
 // ---------------------------------------------------------------------------
-__device__ inline int isvd_prepare(const RomDev &R, int ld, int nc, int rmax, int &rank, int &luok,
-                                   const double *x, const double *b, double *pbuf, int truncate, double eps,
-                                   RomSmem &sm) {
+__device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, int &rank, int &luok,
+                                RomSmem &sm) {
   const int tid = threadIdx.x, NT = blockDim.x;
-  const int r = rank;
+  const int r = Wk.r, nb = Wk.nblk;
   RomPend *P = R.pend;
-  // 1) a = U^T x, U^T b, ||x||^2, x.b
-  {
-    double part[2 * RT_RMAX + 2];
-#pragma unroll
-    for (int k = 0; k < 2 * RT_RMAX + 2; ++k) part[k] = 0.0;
-#pragma unroll 2
-    for (int c = tid; c < nc; c += NT) {
-      const double xv = x[c], bv = b[c];
-      part[2 * RT_RMAX] = rt_fma(xv, xv, part[2 * RT_RMAX]);
-      part[2 * RT_RMAX + 1] = rt_fma(xv, bv, part[2 * RT_RMAX + 1]);
-#pragma unroll
-      for (int k = 0; k < RT_RMAX; ++k)
-        if (k < r) {
-          const double u = R.U[(size_t)k * ld + c];
-          part[k] = rt_fma(u, xv, part[k]);
-          part[RT_RMAX + k] = rt_fma(u, bv, part[RT_RMAX + k]);
-        }
+  // fixed-order block sums: pass 1 -> U^T x, U^T b, x.x, x.b; pass 2 -> a2, p1^T W;
+  // pass 3 -> p.p, p.b
+  for (int e = tid; e < 2 * RT_RMAX + 2 + 2 * RT_RMAX + 2; e += NT) {
+    double s = 0.0;
+    if (e < 2 * RT_RMAX + 2) {
+      for (int k = 0; k < nb; ++k) s += Wk.part1[k * RT_NPART + e];
+    } else if (e < 4 * RT_RMAX + 2) {
+      const int j = e - (2 * RT_RMAX + 2);
+      for (int k = 0; k < nb; ++k) s += Wk.part2[k * RT_NPART + j];
+    } else {
+      const int j = e - (4 * RT_RMAX + 2);
+      for (int k = 0; k < nb; ++k) s += Wk.part3[k * RT_NPART + j];
     }
-    wg_sum_fast<2 * RT_RMAX + 2>(part, sm.red, sm.vec);
+    sm.red[e] = s;
   }
-  const double xn = sqrt(sm.vec[2 * RT_RMAX]);
-  const double xb = sm.vec[2 * RT_RMAX + 1];
+  __syncthreads();
+  const double xn = sqrt(sm.red[2 * RT_RMAX]);
+  const double xb = sm.red[2 * RT_RMAX + 1];
+  const double nu = sqrt(sm.red[4 * RT_RMAX + 2]);
+  const double pb = sm.red[4 * RT_RMAX + 3];
   if (r == 0) {
-    __syncthreads();
     if (xn == 0.0) {
       if (tid == 0) P->pending = 0;
+      __syncthreads();
       return -1;
     }
-    for (int c = tid; c < nc; c += NT) pbuf[c] = x[c];
     if (tid == 0) {
       const double m = xb / xn;
       R.M[0] = m;
@@ -386,111 +381,55 @@ __device__ inline int isvd_prepare(const RomDev &R, int ld, int nc, int rmax, in
       P->inv_nu = 1.0 / xn;
       P->Uc[0] = 1.0;
       P->Vc[0] = 1.0;
-      P->p = pbuf;
-      P->b = b;
+      P->p = Wk.p;
+      P->b = Wk.b;
     }
     __syncthreads();
     luok = !lu_factor_wave(sm.A, sm.perm, 1, R.LU, R.perm, &sm.ibuf[0]);
     rank = 1;
     return 0;
   }
-  if (tid < RT_RMAX) {
-    sm.av[tid] = (tid < r) ? sm.vec[tid] : 0.0;
-    sm.utbv[tid] = (tid < r) ? sm.vec[RT_RMAX + tid] : 0.0;
-  }
-  __syncthreads();
-  // 2) p1 = x - U a (classical Gram-Schmidt), a2 = U^T p1, p1^T W
-  {
-    double part[2 * RT_RMAX];
-#pragma unroll
-    for (int k = 0; k < 2 * RT_RMAX; ++k) part[k] = 0.0;
-#pragma unroll 2
-    for (int c = tid; c < nc; c += NT) {
-      double v = x[c];
-      for (int k = 0; k < r; ++k) v = rt_fma(-R.U[(size_t)k * ld + c], sm.av[k], v);
-      pbuf[c] = v;
-#pragma unroll
-      for (int k = 0; k < RT_RMAX; ++k)
-        if (k < r) {
-          part[k] = rt_fma(R.U[(size_t)k * ld + c], v, part[k]);
-          part[RT_RMAX + k] = rt_fma(R.W[(size_t)k * ld + c], v, part[RT_RMAX + k]);
-        }
-    }
-    wg_sum_fast<2 * RT_RMAX>(part, sm.red, sm.vec);
-  }
-  if (tid < RT_RMAX) {
-    sm.a2v[tid] = (tid < r) ? sm.vec[tid] : 0.0;
-    sm.pwv[tid] = (tid < r) ? sm.vec[RT_RMAX + tid] : 0.0;
-  }
-  __syncthreads();
-  // 3) second Gram-Schmidt pass p = p1 - U a2, ||p||^2 and p.b (direct: p is
-  //    small when x is nearly in span(U), so no cancellation-prone identity)
-  {
-    double part[2] = {0.0, 0.0};
-#pragma unroll 2
-    for (int c = tid; c < nc; c += NT) {
-      double v = pbuf[c];
-      for (int k = 0; k < r; ++k) v = rt_fma(-R.U[(size_t)k * ld + c], sm.a2v[k], v);
-      pbuf[c] = v;
-      part[0] = rt_fma(v, v, part[0]);
-      part[1] = rt_fma(v, b[c], part[1]);
-    }
-    wg_sum_fast<2>(part, sm.red, sm.vec);
-  }
-  const double nu = sqrt(sm.vec[0]);
-  const double pb = sm.vec[1];
   const int deficient = !(nu > 1e-12 * xn);
-  __syncthreads();
-  // p^T W = p1^T W - a2^T M  (M = U^T W); a2 is the small second-pass term.
-  // Total coefficients a <- a + a2.
-  if (tid < RT_KC) {
+  const int rows = deficient ? r : r + 1, cols = r + 1;
+  // coefficient vectors: a (total), U^T b, a2, p^T W = p1^T W - a2^T M
+  if (tid < RT_RMAX) {
     const int j = tid;
+    sm.av[j] = (j < r) ? sm.red[j] + sm.red[2 * RT_RMAX + 2 + j] : 0.0;
+    sm.utbv[j] = (j < r) ? sm.red[RT_RMAX + j] : 0.0;
     double v = 0.0;
     if (j < r) {
-      v = sm.pwv[j];
-      for (int i = 0; i < r; ++i) v = rt_fma(-sm.a2v[i], R.M[i * RT_RMAX + j], v);
-      sm.av[j] += sm.a2v[j];
+      v = sm.red[3 * RT_RMAX + 2 + j];
+      for (int i = 0; i < r; ++i) v = rt_fma(-sm.red[2 * RT_RMAX + 2 + i], R.M[i * RT_RMAX + j], v);
     }
-    sm.vec[j] = v;
+    sm.pwv[j] = v;
   }
   __syncthreads();
-  const int rows = deficient ? r : r + 1, cols = r + 1;
-  // 5) core K = [[diag S, a], [0, nu]] and Mx = Q^T [W b]
-  if (tid < RT_KC) {
-    const int j = tid;
-    for (int i = 0; i < RT_KC; ++i) {
-      double v = 0.0;
-      if (j < r && i == j) v = R.S[j];
-      if (j == r && i < r) v = sm.av[i];
-      if (j == r && i == r && !deficient) v = nu;
-      sm.B[j * RT_KC + i] = (i < rows && j < cols) ? v : 0.0;
-    }
-  }
+  // core K = [[diag S, a], [0, nu]] and Mx = Q^T [W b]
   for (int e = tid; e < RT_KC * RT_KC; e += NT) {
-    const int i = e / RT_KC, j = e % RT_KC;
+    const int j = e / RT_KC, i = e % RT_KC;  // K column j, row i
     double v = 0.0;
-    if (i < r && j < r) {
-      v = R.M[i * RT_RMAX + j];
-    } else if (i < r && j == r) {
-      v = sm.utbv[i];
-    } else if (i == r && j < r && !deficient) {
-      v = sm.vec[j] / nu;
-    } else if (i == r && j == r && !deficient) {
-      v = pb / nu;
-    }
-    sm.Mx[e] = v;
+    if (j < r && i == j) v = R.S[j];
+    if (j == r && i < r) v = sm.av[i];
+    if (j == r && i == r && !deficient) v = nu;
+    sm.B[e] = (i < rows && j < cols) ? v : 0.0;
+    const int mi = e / RT_KC, mj = e % RT_KC;  // Mx row mi, column mj
+    double m = 0.0;
+    if (mi < r && mj < r) m = R.M[mi * RT_RMAX + mj];
+    else if (mi < r && mj == r) m = sm.utbv[mi];
+    else if (mi == r && mj < r && !deficient) m = sm.pwv[mj] / nu;
+    else if (mi == r && mj == r && !deficient) m = pb / nu;
+    sm.Mx[e] = m;
   }
   __syncthreads();
   core_svd(sm, rows, cols);
-  // 6) number of kept values
   if (tid == 0) {
     int k = rows;
-    if (truncate) {
+    if (Wk.truncate) {
       double tot = 0.0;
       for (int i = 0; i < rows; ++i) tot += sm.sv[i];
       int kk = 0;
       for (int i = 0; i < rows; ++i)
-        if (sm.sv[i] / tot > eps) kk = i + 1;
+        if (sm.sv[i] / tot > Wk.eps) kk = i + 1;
       k = kk > 0 ? kk : 1;
     }
     if (k > rmax) k = rmax;
@@ -498,7 +437,7 @@ __device__ inline int isvd_prepare(const RomDev &R, int ld, int nc, int rmax, in
   }
   __syncthreads();
   const int k = sm.ibuf[1];
-  // 7) M_new = Uc[:, :k]^T Mx Vc[:, :k], A_r = M_new S^{-1}; pending rotation
+  // M_new = Uc[:, :k]^T Mx Vc[:, :k], A_r = M_new S^{-1}; pending rotation
   for (int e = tid; e < rows * k; e += NT) {
     const int i = e / k, j = e % k;
     double v = 0.0;
@@ -525,8 +464,8 @@ __device__ inline int isvd_prepare(const RomDev &R, int ld, int nc, int rmax, in
     P->k = k;
     P->deficient = deficient;
     P->inv_nu = deficient ? 0.0 : 1.0 / nu;
-    P->p = pbuf;
-    P->b = b;
+    P->p = Wk.p;
+    P->b = Wk.b;
   }
   __syncthreads();
   luok = !lu_factor_wave(sm.A, sm.perm, k, R.LU, R.perm, &sm.ibuf[0]);

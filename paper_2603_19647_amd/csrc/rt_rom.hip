@@ -1,0 +1,310 @@
+// rt_rom.hip -- the per-step ROM work of Alg. 2 for every instance of a
+// launch (slab or plane): error indicators and decisions, the incremental-SVD
+// updates (App. B) split into grid-wide projection passes, a one-workgroup
+// small dense core per ROM, and the grid-wide basis rotation.
+#include "rt_common.h"
+#include "rt_rom.h"
+
+namespace {
+constexpr int BLK = 256;  // cells per block of the grid passes
+
+__device__ __forceinline__ const RomDev &rom_of(const Inst &I, int z) { return z ? I.pc : I.ig; }
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// k_rom_decide: step bookkeeping and, for the ROM method, the error
+// indicators (Sec. 3.2, normalised by ||rho^n||_2) and Alg. 2's decisions on
+// which ROM takes a snapshot this step.  One workgroup per instance.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_rom_decide(const Inst *__restrict__ insts) {
+  const Inst &I = insts[blockIdx.x];
+  __shared__ double red[RT_MAXWAVES * 4], vec[4];
+  const int NT = blockDim.x, tid = threadIdx.x;
+  const int nc = I.nc;
+  RtState *st = I.st;
+  const int iters = st->iters;
+  const long long step_no = st->steps + 1;
+  double e_ig = -1.0, e_pc = -1.0;
+  if (I.method == RT_ROM) {
+    const int flag_ig = st->flag_ig, flag_pc = st->flag_pc, used_pc = st->used_pc;
+    {
+      double part[3] = {0.0, 0.0, 0.0};
+      for (int c = tid; c < nc; c += NT) {
+        const double r = I.rho[c];
+        part[0] = rt_fma(r, r, part[0]);
+        const double e1 = I.rho0[c] - r;
+        part[1] = rt_fma(e1, e1, part[1]);
+        const double e2 = I.dpc[c] - (r - I.rhalf[c]);
+        part[2] = rt_fma(e2, e2, part[2]);
+      }
+      wg_sum_fast<3>(part, red, vec);
+    }
+    const double rn = sqrt(vec[0]);
+    const double scale = (I.abs_up || rn == 0.0) ? 1.0 : 1.0 / rn;
+    const double eig = sqrt(vec[1]) * scale, epc = sqrt(vec[2]) * scale;
+    int ig_on = 0, ig_trunc = 0, pc_on = 0, pc_trunc = 0;
+    if (!flag_ig) {
+      ig_on = 1;  // phase 1: untruncated snapshot (rho^n, b~^{n-1})
+    } else {
+      e_ig = eig;
+      ig_on = ig_trunc = e_ig > I.eps_up;
+      if (iters > 1) {  // no correction snapshot when the step converged at l = 1
+        if (!flag_pc) {
+          pc_on = 1;
+        } else {
+          if (used_pc) e_pc = epc;
+          pc_on = pc_trunc = ig_on || !used_pc || e_pc > I.eps_up;
+        }
+      }
+    }
+    if (pc_on) {  // correction snapshots (eq. correction_snapshot)
+      double *xs = I.work + 2 * (size_t)nc, *bs = I.work + 3 * (size_t)nc;
+      for (int c = tid; c < nc; c += NT) {
+        const double rh = I.rhalf[c];
+        xs[c] = I.rho[c] - rh;
+        bs[c] = rh - I.rho0[c];
+      }
+    }
+    if (tid == 0) {
+      RomWork &wi = *I.ig.work;
+      wi.active = ig_on;
+      wi.truncate = ig_trunc;
+      wi.r = st->rank_ig;
+      wi.nblk = (nc + BLK - 1) / BLK;
+      wi.step_no = step_no;
+      wi.eps = I.eps_ig;
+      wi.x = I.rho;
+      wi.b = I.bt2[st->cur];
+      wi.p = I.work;
+      RomWork &wp = *I.pc.work;
+      wp.active = pc_on;
+      wp.truncate = pc_trunc;
+      wp.r = st->rank_pc;
+      wp.nblk = (nc + BLK - 1) / BLK;
+      wp.step_no = step_no;
+      wp.eps = I.eps_pc;
+      wp.x = I.work + 2 * (size_t)nc;
+      wp.b = I.work + 3 * (size_t)nc;
+      wp.p = I.work + nc;
+      I.ig.pend->pending = 0;
+      I.pc.pend->pending = 0;
+    }
+  }
+  if (tid == 0) {
+    const int fb = st->ig_fb + st->pc_fb;
+    if (I.hist && step_no <= I.hist_cap) {
+      RtStepRec &rec = I.hist[step_no - 1];
+      rec.iters = iters;
+      rec.phase = st->phase;
+      rec.converged = st->conv;
+      rec.ig_update = 0;
+      rec.pc_update = 0;
+      rec.rank_ig = st->rank_ig;
+      rec.rank_pc = st->rank_pc;
+      rec.fallback = fb > 0;
+      rec.e_ig = e_ig;
+      rec.e_pc = e_pc;
+      rec.residual = st->residual;
+    }
+    st->fallbacks += fb;
+    st->steps = step_no;
+    st->si_total += iters;
+    st->sweeps_total += iters + 2;
+    st->nonconv += !st->conv;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Projection passes (classical Gram-Schmidt applied twice), one thread per
+// cell, grid (blocks of 256 cells, instance, ROM).  Each block writes its
+// partial sums; later stages add them in block order.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(BLK) k_rom_pass1(const Inst *__restrict__ insts) {
+  const Inst &I = insts[blockIdx.y];
+  if (I.method != RT_ROM) return;
+  const RomDev &R = rom_of(I, blockIdx.z);
+  const RomWork &W = *R.work;
+  if (!W.active || (int)blockIdx.x >= W.nblk) return;
+  __shared__ double red[(BLK / 64) * (2 * RT_RMAX + 2)], out[2 * RT_RMAX + 2];
+  const int r = W.r, ld = I.ld, c = blockIdx.x * BLK + threadIdx.x;
+  double part[2 * RT_RMAX + 2];
+#pragma unroll
+  for (int k = 0; k < 2 * RT_RMAX + 2; ++k) part[k] = 0.0;
+  if (c < I.nc) {
+    const double xv = W.x[c], bv = W.b[c];
+    part[2 * RT_RMAX] = xv * xv;
+    part[2 * RT_RMAX + 1] = xv * bv;
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k)
+      if (k < r) {
+        const double u = R.U[(size_t)k * ld + c];
+        part[k] = u * xv;
+        part[RT_RMAX + k] = u * bv;
+      }
+  }
+  wg_sum_fast<2 * RT_RMAX + 2>(part, red, out);
+  if (threadIdx.x < 2 * RT_RMAX + 2) W.part1[blockIdx.x * RT_NPART + threadIdx.x] = out[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(BLK) k_rom_pass2(const Inst *__restrict__ insts) {
+  const Inst &I = insts[blockIdx.y];
+  if (I.method != RT_ROM) return;
+  const RomDev &R = rom_of(I, blockIdx.z);
+  const RomWork &W = *R.work;
+  if (!W.active || (int)blockIdx.x >= W.nblk) return;
+  __shared__ double red[(BLK / 64) * 2 * RT_RMAX], out[2 * RT_RMAX], av[RT_RMAX];
+  const int r = W.r, ld = I.ld, c = blockIdx.x * BLK + threadIdx.x;
+  if ((int)threadIdx.x < r) {
+    double s = 0.0;
+    for (int k = 0; k < W.nblk; ++k) s += W.part1[k * RT_NPART + threadIdx.x];
+    av[threadIdx.x] = s;
+  }
+  __syncthreads();
+  double part[2 * RT_RMAX];
+#pragma unroll
+  for (int k = 0; k < 2 * RT_RMAX; ++k) part[k] = 0.0;
+  if (c < I.nc) {
+    double v = W.x[c];
+    for (int k = 0; k < r; ++k) v = rt_fma(-R.U[(size_t)k * ld + c], av[k], v);
+    W.p[c] = v;
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k)
+      if (k < r) {
+        part[k] = R.U[(size_t)k * ld + c] * v;
+        part[RT_RMAX + k] = R.W[(size_t)k * ld + c] * v;
+      }
+  }
+  wg_sum_fast<2 * RT_RMAX>(part, red, out);
+  if (threadIdx.x < 2 * RT_RMAX) W.part2[blockIdx.x * RT_NPART + threadIdx.x] = out[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(BLK) k_rom_pass3(const Inst *__restrict__ insts) {
+  const Inst &I = insts[blockIdx.y];
+  if (I.method != RT_ROM) return;
+  const RomDev &R = rom_of(I, blockIdx.z);
+  const RomWork &W = *R.work;
+  if (!W.active || (int)blockIdx.x >= W.nblk) return;
+  __shared__ double red[(BLK / 64) * 2], out[2], a2[RT_RMAX];
+  const int r = W.r, ld = I.ld, c = blockIdx.x * BLK + threadIdx.x;
+  if ((int)threadIdx.x < r) {
+    double s = 0.0;
+    for (int k = 0; k < W.nblk; ++k) s += W.part2[k * RT_NPART + threadIdx.x];
+    a2[threadIdx.x] = s;
+  }
+  __syncthreads();
+  double part[2] = {0.0, 0.0};
+  if (c < I.nc) {
+    double v = W.p[c];
+    for (int k = 0; k < r; ++k) v = rt_fma(-R.U[(size_t)k * ld + c], a2[k], v);
+    W.p[c] = v;
+    part[0] = v * v;
+    part[1] = v * W.b[c];
+  }
+  wg_sum_fast<2>(part, red, out);
+  if (threadIdx.x < 2) W.part3[blockIdx.x * RT_NPART + threadIdx.x] = out[threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
+// k_rom_core: small dense part of the update and Alg. 2's phase flags; one
+// workgroup per (instance, ROM).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_rom_core(const Inst *__restrict__ insts) {
+  const Inst &I = insts[blockIdx.x];
+  if (I.method != RT_ROM) return;
+  const int z = blockIdx.y;
+  const RomDev &R = rom_of(I, z);
+  const RomWork &W = *R.work;
+  if (!W.active) return;
+  __shared__ RomSmem sm;
+  RtState *st = I.st;
+  int rank = z ? st->rank_pc : st->rank_ig;
+  int luok = z ? st->lu_ok_pc : st->lu_ok_ig;
+  const int dfc = isvd_core(R, W, I.r_max, rank, luok, sm);
+  if (threadIdx.x == 0) {
+    const long long step_no = W.step_no;
+    int updated = 0;
+    if (!W.truncate) {
+      // construction phase: stop tests eq. ig_stop / eq. pc_stop, the rank
+      // cap, or a rank-deficient snapshot end it
+      if (dfc >= 0) {
+        updated = 1;
+        if (rom_tail_ratio(R, rank) <= W.eps || rank >= I.r_max || dfc == 1) {
+          if (z == 0) {
+            st->flag_ig = 1;
+            st->n0 = (int)step_no;
+          } else {
+            st->flag_pc = 1;
+            st->n1 = (int)step_no - st->n0;
+          }
+        }
+      }
+    } else {
+      updated = 1;
+    }
+    if (z == 0) {
+      st->rank_ig = rank;
+      st->lu_ok_ig = luok;
+      st->ig_updates += updated;
+    } else {
+      st->rank_pc = rank;
+      st->lu_ok_pc = luok;
+      st->pc_updates += updated;
+    }
+    if (I.hist && step_no <= I.hist_cap) {
+      RtStepRec &rec = I.hist[step_no - 1];
+      if (z == 0) {
+        rec.ig_update = updated;
+        rec.rank_ig = rank;
+      } else {
+        rec.pc_update = updated;
+        rec.rank_pc = rank;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_rom_update: U <- [U, p/nu] Uc, W <- [W, b] Vc, one thread per cell.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_rom_update(const Inst *__restrict__ insts) {
+  const Inst &I = insts[blockIdx.y];
+  __shared__ double uc[2][RT_KC * RT_KC], vc[2][RT_KC * RT_KC];
+  if (I.method != RT_ROM) return;
+  if ((int)(blockIdx.x * blockDim.x) >= I.nc) return;
+  const RomPend *P[2] = {I.ig.pend, I.pc.pend};
+  const int pend0 = P[0]->pending, pend1 = P[1]->pending;
+  if (!pend0 && !pend1) return;
+  for (int e = threadIdx.x; e < RT_KC * RT_KC; e += blockDim.x) {
+    if (pend0) {
+      uc[0][e] = P[0]->Uc[e];
+      vc[0][e] = P[0]->Vc[e];
+    }
+    if (pend1) {
+      uc[1][e] = P[1]->Uc[e];
+      vc[1][e] = P[1]->Vc[e];
+    }
+  }
+  __syncthreads();
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < I.nc) {
+    if (pend0) isvd_rotate_cell(I.ig, *P[0], uc[0], vc[0], I.ld, c);
+    if (pend1) isvd_rotate_cell(I.pc, *P[1], uc[1], vc[1], I.ld, c);
+  }
+}
+
+extern "C" hipError_t rt_launch_rom(const Inst *dinsts, int ninst, int nc_max, int any_rom, hipStream_t s) {
+  hipLaunchKernelGGL(k_rom_decide, dim3(ninst), dim3(256), 0, s, dinsts);
+  if (any_rom) {
+    const int nb = (nc_max + BLK - 1) / BLK;
+    hipLaunchKernelGGL(k_rom_pass1, dim3(nb, ninst, 2), dim3(BLK), 0, s, dinsts);
+    hipLaunchKernelGGL(k_rom_pass2, dim3(nb, ninst, 2), dim3(BLK), 0, s, dinsts);
+    hipLaunchKernelGGL(k_rom_pass3, dim3(nb, ninst, 2), dim3(BLK), 0, s, dinsts);
+    hipLaunchKernelGGL(k_rom_core, dim3(ninst, 2), dim3(256), 0, s, dinsts);
+  }
+  return hipGetLastError();
+}
+
+extern "C" hipError_t rt_launch_rom_update(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream) {
+  hipLaunchKernelGGL(k_rom_update, dim3((nc_max + 255) / 256, ninst), dim3(256), 0, stream, dinsts);
+  return hipGetLastError();
+}

@@ -396,201 +396,53 @@ __global__ void __launch_bounds__(MAXT) k_fpass_slab(const Inst *__restrict__ in
 }
 
 // ---------------------------------------------------------------------------
-// k_post: the ROM bookkeeping of Alg. 2 (snapshot pairs, error indicators,
-// phase flags, the workgroup half of the incremental-SVD updates) and the
-// step's counters and record.  Cells with a stride of blockDim (256 for every
-// instance, so results do not depend on the batch); any instance size.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_post(const Inst *__restrict__ insts) {
-  const Inst &I = insts[blockIdx.x];
-  __shared__ RomSmem sm;
-  const int NT = blockDim.x, tid = threadIdx.x;
-  const int nc = I.nc;
-  RtState *st = I.st;
-  const int iters = st->iters;
-  const int conv = st->conv;
-  const int used_pc = st->used_pc;
-  int flag_ig = st->flag_ig, flag_pc = st->flag_pc;
-  int rank_ig = st->rank_ig, rank_pc = st->rank_pc;
-  int lu_ig = st->lu_ok_ig, lu_pc = st->lu_ok_pc;
-  const long long step_no = st->steps + 1;
-  const double *bt_prev = I.bt2[st->cur];  // b~^{n-1}, the right-hand side this step solved
-  int ig_update = 0, pc_update = 0, n0 = st->n0, n1 = st->n1;
-  double e_ig = -1.0, e_pc = -1.0;
-  if (I.method == RT_ROM) {
-    if (tid == 0) {
-      I.ig.pend->pending = 0;
-      I.pc.pend->pending = 0;
-    }
-    // ||rho^n||_2 and the error indicators (Sec. 3.2, normalised by ||rho^n||)
-    {
-      double part[3] = {0.0, 0.0, 0.0};
-      for (int c = tid; c < nc; c += NT) {
-        const double r = I.rho[c];
-        part[0] = rt_fma(r, r, part[0]);
-        const double e1 = I.rho0[c] - r;
-        part[1] = rt_fma(e1, e1, part[1]);
-        const double xs = r - I.rhalf[c];
-        const double e2 = I.dpc[c] - xs;
-        part[2] = rt_fma(e2, e2, part[2]);
-      }
-      wg_sum_fast<3>(part, sm.red, sm.vec);
-    }
-    const double rn = sqrt(sm.vec[0]);
-    const double scale = (I.abs_up || rn == 0.0) ? 1.0 : 1.0 / rn;
-    const double eig = sqrt(sm.vec[1]) * scale;
-    const double epc = sqrt(sm.vec[2]) * scale;
-    __syncthreads();
-    double *pbuf_ig = I.work;
-    double *pbuf_pc = I.work + nc;
-    double *xs = I.work + 2 * (size_t)nc;
-    double *bs = I.work + 3 * (size_t)nc;
-    if (!flag_ig) {
-      // phase 1: untruncated snapshot (rho^n, b~^{n-1})
-      const int dfc = isvd_prepare(I.ig, I.ld, nc, I.r_max, rank_ig, lu_ig, I.rho, bt_prev, pbuf_ig, 0,
-                                   I.eps_ig, sm);
-      if (dfc >= 0) {
-        ig_update = 1;
-        if (rom_tail_ratio(I.ig, rank_ig) <= I.eps_ig || rank_ig >= I.r_max || dfc == 1) {
-          flag_ig = 1;
-          n0 = (int)step_no;
-        }
-      }
-    } else {
-      int upd_ig = 0;
-      e_ig = eig;
-      if (e_ig > I.eps_up) {
-        isvd_prepare(I.ig, I.ld, nc, I.r_max, rank_ig, lu_ig, I.rho, bt_prev, pbuf_ig, 1, I.eps_ig, sm);
-        upd_ig = 1;
-        ig_update = 1;
-      }
-      if (iters > 1) {
-        // correction snapshots (eq. correction_snapshot)
-        for (int c = tid; c < nc; c += NT) {
-          const double rh = I.rhalf[c];
-          xs[c] = I.rho[c] - rh;
-          bs[c] = rh - I.rho0[c];
-        }
-        __syncthreads();
-        if (!flag_pc) {
-          const int dfc = isvd_prepare(I.pc, I.ld, nc, I.r_max, rank_pc, lu_pc, xs, bs, pbuf_pc, 0, I.eps_pc, sm);
-          if (dfc >= 0) {
-            pc_update = 1;
-            if (rom_tail_ratio(I.pc, rank_pc) <= I.eps_pc || rank_pc >= I.r_max || dfc == 1) {
-              flag_pc = 1;
-              n1 = (int)step_no - n0;
-            }
-          }
-        } else {
-          if (used_pc) e_pc = epc;
-          if (upd_ig || !used_pc || e_pc > I.eps_up) {
-            isvd_prepare(I.pc, I.ld, nc, I.r_max, rank_pc, lu_pc, xs, bs, pbuf_pc, 1, I.eps_pc, sm);
-            pc_update = 1;
-          }
-        }
-      }
-    }
-  }
-  __syncthreads();
-  if (tid == 0) {
-    const int fb = st->ig_fb + st->pc_fb;
-    if (I.hist && step_no <= I.hist_cap) {
-      RtStepRec &rec = I.hist[step_no - 1];
-      rec.iters = iters;
-      rec.phase = st->phase;
-      rec.converged = conv;
-      rec.ig_update = ig_update;
-      rec.pc_update = pc_update;
-      rec.rank_ig = rank_ig;
-      rec.rank_pc = rank_pc;
-      rec.fallback = fb > 0;
-      rec.e_ig = e_ig;
-      rec.e_pc = e_pc;
-      rec.residual = st->residual;
-    }
-    st->flag_ig = flag_ig;
-    st->flag_pc = flag_pc;
-    st->n0 = n0;
-    st->n1 = n1;
-    st->rank_ig = rank_ig;
-    st->rank_pc = rank_pc;
-    st->lu_ok_ig = lu_ig;
-    st->lu_ok_pc = lu_pc;
-    st->ig_updates += ig_update;
-    st->pc_updates += pc_update;
-    st->fallbacks += fb;
-    st->steps = step_no;
-    st->si_total += iters;
-    st->sweeps_total += iters + 2;
-    st->nonconv += !conv;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// k_rom_update: the O(N r^2) half of the incremental-SVD updates prepared by
-// k_post, one thread per cell over the whole grid (blockIdx.y = instance).
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_rom_update(const Inst *__restrict__ insts) {
-  const Inst &I = insts[blockIdx.y];
-  __shared__ double uc[2][RT_KC * RT_KC], vc[2][RT_KC * RT_KC];
-  if (I.method != RT_ROM) return;
-  if ((int)(blockIdx.x * blockDim.x) >= I.nc) return;
-  const RomPend *P[2] = {I.ig.pend, I.pc.pend};
-  const int pend0 = P[0]->pending, pend1 = P[1]->pending;
-  if (!pend0 && !pend1) return;
-  for (int e = threadIdx.x; e < RT_KC * RT_KC; e += blockDim.x) {
-    if (pend0) {
-      uc[0][e] = P[0]->Uc[e];
-      vc[0][e] = P[0]->Vc[e];
-    }
-    if (pend1) {
-      uc[1][e] = P[1]->Uc[e];
-      vc[1][e] = P[1]->Vc[e];
-    }
-  }
-  __syncthreads();
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < I.nc) {
-    if (pend0) isvd_rotate_cell(I.ig, *P[0], uc[0], vc[0], I.ld, c);
-    if (pend1) isvd_rotate_cell(I.pc, *P[1], uc[1], vc[1], I.ld, c);
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Setup: cell-centred DSA operator for finite volumes and its Thomas factors
 // in affine form (serial over cells, once per problem).
 // Reading of eq. rho_residual for FV: diffusion coefficient
 // D = 1/(3 sigma~_t) + h/4, harmonic face coupling, Marshak vacuum faces.
 // ---------------------------------------------------------------------------
-__global__ void k_setup_dsa_slab(const Inst *__restrict__ insts) {
+__global__ void __launch_bounds__(1024) k_setup_dsa_slab(const Inst *__restrict__ insts) {
   const Inst &I = insts[blockIdx.x];
-  if (threadIdx.x != 0) return;
+  extern __shared__ double lds[];
   const int nc = I.nc;
   const double h = I.hx;
+  double *diag = lds;       // [nc] diagonal, then the Thomas pivots d'_i
+  double *q = lds + nc;     // [nc] lo_i * up_{i-1}
   double *fe = const_cast<double *>(I.dsa_fe);
   double *bg = const_cast<double *>(I.dsa_bg);
   double *invd = const_cast<double *>(I.dsa_invd);
   auto Dof = [&](int i) { return 1.0 / (3.0 * I.ct[i]) + 0.25 * h; };
   auto face = [&](double Dp, double Dq) { return 2.0 * Dp * Dq / (h * (Dp + Dq)); };
   auto bdry = [&](double Dp) { return 2.0 * Dp / (h + 4.0 * Dp); };
-  double dprev = 0.0, upprev = 0.0;
-  for (int i = 0; i < nc; ++i) {
+  // entries of row i: lo_i = -k_{i-1/2}/h, up_i = -k_{i+1/2}/h, in parallel
+  for (int i = threadIdx.x; i < nc; i += blockDim.x) {
     const double Di = Dof(i);
     const double kl = (i > 0) ? face(Di, Dof(i - 1)) : bdry(Di);
     const double kr = (i < nc - 1) ? face(Di, Dof(i + 1)) : bdry(Di);
-    const double diag = I.sa[i] + I.inv_dt + (kl + kr) / h;
-    const double lo = (i > 0) ? -kl / h : 0.0;
-    const double up = (i < nc - 1) ? -kr / h : 0.0;
-    double e = 0.0, dp = diag;
-    if (i > 0) {
-      e = lo / dprev;
-      dp = diag - e * upprev;
+    diag[i] = I.sa[i] + I.inv_dt + (kl + kr) / h;
+    // lo_i * up_{i-1}: both equal -k_{i-1/2}/h
+    q[i] = (i > 0) ? (kl / h) * (kl / h) : 0.0;
+    bg[i] = (i < nc - 1) ? -kr / h : 0.0;  // up_i for now
+  }
+  __syncthreads();
+  // pivots d'_i = diag_i - lo_i up_{i-1} / d'_{i-1} (sequential recurrence)
+  if (threadIdx.x == 0) {
+    double dp = diag[0];
+    for (int i = 1; i < nc; ++i) {
+      dp = diag[i] - q[i] / dp;
+      diag[i] = dp;
     }
-    fe[i] = -e;
-    invd[i] = 1.0 / dp;
-    bg[i] = -up / dp;
-    dprev = dp;
-    upprev = up;
+  }
+  __syncthreads();
+  // affine form: z_i = fe_i z_{i-1} + rhs_i, d_i = bg_i d_{i+1} + invd_i z_i
+  for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+    const double Di = Dof(i);
+    const double kl = (i > 0) ? face(Di, Dof(i - 1)) : bdry(Di);
+    const double lo = (i > 0) ? -kl / h : 0.0;
+    fe[i] = (i > 0) ? -lo / diag[i - 1] : 0.0;
+    const double id = 1.0 / diag[i];
+    invd[i] = id;
+    bg[i] = -bg[i] * id;
   }
 }
 
@@ -617,16 +469,6 @@ extern "C" hipError_t rt_launch_slab_fpass(const Inst *dinsts, int ninst, int nt
   return hipGetLastError();
 }
 
-extern "C" hipError_t rt_launch_post(const Inst *dinsts, int ninst, hipStream_t stream) {
-  hipLaunchKernelGGL(k_post, dim3(ninst), dim3(256), 0, stream, dinsts);
-  return hipGetLastError();
-}
-
-extern "C" hipError_t rt_launch_rom_update(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream) {
-  hipLaunchKernelGGL(k_rom_update, dim3((nc_max + 255) / 256, ninst), dim3(256), 0, stream, dinsts);
-  return hipGetLastError();
-}
-
 extern "C" hipError_t rt_launch_slab_rhs(const Inst *dinsts, int ninst, int nthreads, int cmax,
                                          hipStream_t stream) {
   dim3 grid(ninst), blk(nthreads);
@@ -637,7 +479,7 @@ extern "C" hipError_t rt_launch_slab_rhs(const Inst *dinsts, int ninst, int nthr
   return hipGetLastError();
 }
 
-extern "C" hipError_t rt_launch_slab_setup(const Inst *dinsts, int ninst, hipStream_t stream) {
-  hipLaunchKernelGGL(k_setup_dsa_slab, dim3(ninst), dim3(64), 0, stream, dinsts);
+extern "C" hipError_t rt_launch_slab_setup(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream) {
+  hipLaunchKernelGGL(k_setup_dsa_slab, dim3(ninst), dim3(1024), 2 * sizeof(double) * nc_max, stream, dinsts);
   return hipGetLastError();
 }
