@@ -492,6 +492,7 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
     if (rt_launch_slab_rhs(p->dinst, 1, nt, cmax, p->stream) != hipSuccess)
       return bail(RTROM_EDEVICE, "initial RHS launch failed");
   } else {
+    if (upload_inst(p) != RTROM_OK) return bail(RTROM_EDEVICE, "upload descriptor failed");
     int s = rt_plane_create(p);
     if (s != RTROM_OK) {
       std::string m = g_err;
@@ -649,6 +650,7 @@ extern "C" rtrom_status rtrom_get_rhs(const rtrom_problem *p, double *b, int64_t
 extern "C" rtrom_status rtrom_get_angular_flux(const rtrom_problem *p, double *f, int64_t n) {
   if (!p || !f) return fail(RTROM_EINVAL, "null argument");
   if (n < (int64_t)p->nc * p->nv) return fail(RTROM_EINVAL, "output buffer too small");
+  if (p->d.dim == 2) return (rtrom_status)rt_plane_unfold(p, f);
   return d2h(p, f, p->hinst.f, (size_t)p->nc * p->nv * 8);
 }
 

@@ -1,0 +1,139 @@
+"""GPU parity of the X-Y (2D) path against the FP64 oracle, through the C ABI.
+
+Same bars as the slab path: FP64 runs agree with the oracle to rel. L2 <=
+1e-10 per step with identical SI iteration counts, phases, ROM update steps
+and ranks; mixed precision at the configured tolerance agrees to 1e-8, or to
+three times the distance the FP64 oracle itself keeps from the converged
+solution when the stop test leaves more than that.  The 2D DSA on the device
+is an iterative solve accurate to ~1e-14 (the oracle factors the matrix), so
+the acceleration differs from the oracle's at rounding level only.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_19647_amd import rtrom
+from paper_2603_19647_amd import workloads as W
+from tests.gpu_util import (assert_same_decisions, converged_reference, oracle_rounding_spread,
+                            oracle_tol_error, rel_l2, say, step_both)
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-8
+
+
+def ragged_plane(nx, ny, n_azim, n_polar, seed=7, **kw):
+    rng = np.random.default_rng(seed)
+    n = nx * ny
+    ss = rng.uniform(0.2, 4.0, n)
+    sa = rng.uniform(0.01, 0.5, n)
+    q = rng.uniform(0.0, 1.0, n)
+    kw.setdefault("dt", 0.02)
+    return W.plane(nx, ny, n_azim, n_polar, ss, sa, q, lx=1.3, ly=0.7, name=f"ragged{nx}x{ny}", **kw)
+
+
+@pytest.mark.parametrize("nx,ny,na,npol", [(1, 1, 4, 2), (37, 21, 8, 4), (16, 16, 4, 2), (17, 33, 12, 6),
+                                           (64, 48, 16, 8)])
+def test_plane_ragged_si_dsa(nx, ny, na, npol):
+    spec = ragged_plane(nx, ny, na, npol, inflow=(0.7, 0.2, 0.4, 0.0))
+    say(f"plane si_dsa {nx}x{ny} CL({na},{npol})")
+    errs, o, g = step_both(spec, 4)
+    assert errs.max() <= FP64_TOL, errs
+    assert_same_decisions(o, g)
+    assert rel_l2(g.f(), o.f()) <= FP64_TOL
+    assert rel_l2(g.rhs(), o.bt()) <= FP64_TOL
+
+
+def test_plane_plain_si():
+    spec = ragged_plane(23, 19, 8, 4, tol=1e-9, max_iter=3000)
+    say("plane plain SI")
+    errs, o, g = step_both(spec, 3, method="si")
+    assert errs.max() <= FP64_TOL
+    assert_same_decisions(o, g)
+
+
+def test_plane_rom_fp64():
+    spec = W.random_plane(3, 40, 8, 4, method="rom", nsteps=40)
+    say("plane rom fp64 40x40 CL(8,4)")
+    errs, o, g = step_both(spec, spec.nsteps)
+    spread = oracle_rounding_spread(spec, spec.nsteps)
+    bar = np.maximum(FP64_TOL, 10.0 * spread)
+    assert np.all(errs <= bar), (errs, spread)
+    assert_same_decisions(o, g)
+    st = g.stats()
+    assert st["n0"] > 0
+
+
+@pytest.mark.parametrize("method", ["si_dsa", "rom"])
+def test_plane_mixed_vs_converged(method):
+    spec = W.random_plane(5, 48, 8, 4, method=method, precision="mixed", nsteps=30)
+    say(f"plane mixed {method}")
+    ref = converged_reference(spec, spec.nsteps)
+    bar = max(MIXED_TOL, 3.0 * oracle_tol_error(spec, spec.nsteps, ref=ref))
+    g = rtrom.Problem(spec)
+    worst = 0.0
+    for k in range(spec.nsteps):
+        g.step()
+        worst = max(worst, rel_l2(g.rho(), ref[k]))
+    assert worst <= bar, (worst, bar)
+    assert g.stats()["fp32_sweeps"] > 0
+
+
+def test_plane_mixed_tight_tol():
+    spec = W.random_plane(6, 32, 8, 4, method="si_dsa", precision="mixed", tol=1e-12, nsteps=5)
+    say("plane mixed tight")
+    o = oracle.OracleProblem(spec.replace(precision="fp64"))
+    g = rtrom.Problem(spec)
+    for _ in range(spec.nsteps):
+        o.step()
+        g.step()
+        assert rel_l2(g.rho(), o.rho()) <= FP64_TOL
+
+
+def test_plane_infinite_medium_closed_form():
+    dt, sa = 0.1, 0.5
+    spec = W.infinite_medium(dim=2, n=20, n_polar=4, n_azim=8, sigma_a=sa, dt=dt, tol=1e-12)
+    say("plane infinite medium")
+    g = rtrom.Problem(spec)
+    for n in range(1, 6):
+        exact = (1.0 / (1.0 + dt * sa)) ** n
+        nxt = exact / (1.0 + dt * sa)
+        g.step()
+        assert np.max(np.abs(g.rho() - exact)) <= 1e-11 * exact
+        g.set_inflow((nxt, nxt, nxt, nxt))
+
+
+def test_plane_set_inflow_rebuilds_rhs():
+    spec = ragged_plane(19, 13, 8, 4)
+    o = oracle.OracleProblem(spec)
+    g = rtrom.Problem(spec)
+    for _ in range(2):
+        o.step()
+        g.step()
+    o.set_inflow((0.1, 0.9, 0.3, 0.6))
+    g.set_inflow((0.1, 0.9, 0.3, 0.6))
+    assert rel_l2(g.rhs(), o.bt()) <= FP64_TOL
+    o.step()
+    g.step()
+    assert rel_l2(g.rho(), o.rho()) <= FP64_TOL
+
+
+def test_plane_determinism():
+    spec = W.random_plane(8, 40, 8, 4, method="rom", precision="mixed", nsteps=15)
+    a = rtrom.Problem(spec)
+    b = rtrom.Problem(spec)
+    a.march(spec.nsteps)
+    b.march(spec.nsteps)
+    assert np.array_equal(a.rho(), b.rho())
+    assert np.array_equal(a.f(), b.f())
+
+
+def test_checkerboard_full_size_sampled_steps():
+    """The 256^2 checkerboard with CL(16, 8): FP64 ROM against the oracle for
+    the first steps (the oracle's cost bounds the horizon)."""
+    spec = W.checkerboard(nsteps=6).replace(precision="fp64")
+    say("checkerboard 256^2 CL(16,8) rom fp64, 6 steps")
+    errs, o, g = step_both(spec, spec.nsteps)
+    assert errs.max() <= FP64_TOL, errs
+    assert_same_decisions(o, g)
