@@ -196,6 +196,8 @@ static rtrom_status validate(const rtrom_problem_desc *d) {
     return fail(RTROM_EINVAL, "2D problems are limited to 4194304 cells");
   if (!(d->lx > 0.0) || !std::isfinite(d->lx)) return fail(RTROM_EINVAL, "lx must be > 0");
   if (d->dim == 2 && (!(d->ly > 0.0) || !std::isfinite(d->ly))) return fail(RTROM_EINVAL, "ly must be > 0");
+  if (d->dim == 2 && rt_plane_needs_cyclic(d->ny) && d->nx > rt_plane_max_nx_cyclic())
+    return fail(RTROM_EINVAL, "2D grids with more than 1024 rows are limited to nx <= 3840");
   if (!(d->dt > 0.0) || !std::isfinite(d->dt)) return fail(RTROM_EINVAL, "dt must be > 0");
   if (!(d->tol > 0.0) || !std::isfinite(d->tol)) return fail(RTROM_EINVAL, "tol must be > 0");
   if (d->max_iter < 1) return fail(RTROM_EINVAL, "max_iter must be >= 1");

@@ -1,21 +1,20 @@
 // rt_plane.hip -- X-Y (2D) path of librtrom for gfx950.
 //
 // Ordinates: Omega_z = +-c pairs sweep identically in X-Y, so f is stored for
-// the upper hemisphere only with doubled weights (R's "folded" set).  The
-// folded ordinates are grouped by quadrant (sign of Omega_x, Omega_y) and
-// then in groups of four; one group is swept by one wave.
+// the upper hemisphere only, each with its pair's doubled weight ("folded"
+// set, nv / 2 ordinates).
 //
-// Sweep (Sec. 2.3: one upwind-ordered pass): in upwind coordinates (a, b),
-// f(a,b) = (s + m_x f(a-1,b) + m_y f(a,b-1)) / (sigma_t + 1/dt + m_x + m_y).
-// A wave owns a band of 16 rows for 4 ordinates of one quadrant (lane =
-// 16 * ordinate + row) and runs a skewed pipeline across the columns: at step
-// t, row j handles column t - j; the value from the row below arrives by a
-// DPP row shift and the band below hands over its top row through global
-// memory, published with epoch-tagged progress counters.  Waves take tickets
-// from an atomic counter, band-order major, so every wave a band waits for has
-// already started (no deadlock).  Each wave writes the moment of its four
-// ordinates to a per-group partial; a reduce kernel adds the groups in a
-// fixed order (deterministic).
+// Sweep (Sec. 2.3: one upwind-ordered pass per ordinate): in upwind
+// coordinates, f(a, b) = (s + m_x f(a-1, b) + m_y f(a, b-1)) / (sigma~_t +
+// m_x + m_y) with m = |Omega| / h.  One workgroup per folded ordinate; one
+// wave per band of 64 rows (lane = row), bands in flight on up to 16 waves.
+// A wave runs a skewed pipeline across the columns: at step t, row j handles
+// column t - j, the value from the row below arrives by a wave-wide DPP shift,
+// and the band below hands its top row over through an LDS ring with
+// producer / consumer counters (back-pressure keeps the ring bounded).  Cell
+// data are prefetched PD steps ahead.  Each workgroup writes its ordinate's
+// weighted flux to a per-ordinate partial; a reduce kernel adds the ordinates
+// in a fixed order, so results are deterministic.
 //
 // DSA (eq. rho_residual) uses the cell-centred 5-point operator with
 // Jacobi-preconditioned Chebyshev iteration on Gershgorin bounds: no dot
@@ -30,151 +29,215 @@
 
 namespace {
 
-constexpr int ROWS = 16;   // rows of a band
-constexpr int NDW = 4;     // ordinates per wave
+constexpr int BAND = 64;   // rows of a band: one wave, lane = row
+constexpr int MAXW = 16;   // bands in flight per workgroup (waves)
+constexpr int RING = 256;  // columns buffered between consecutive bands
+constexpr int PUB = 8;     // producers publish every PUB columns
+constexpr int CPUB = 16;   // consumers publish every CPUB columns
+constexpr int PD = 4;      // prefetch distance in steps (and loop unroll)
 constexpr int BLK = 256;   // cells per block of the element-wise kernels
 
 struct PlaneArgs {
-  int nx, ny, nc, ndf, ngroups, nbands, nblk;
-  int pad_;
+  int nx, ny, nc, ndf, nbands, nw, nblk, pad_;
   double inv_dt;
   double g[4];
-  const double *mx, *my, *w;  // per folded ordinate, group major
-  const int *gsx, *gsy;       // quadrant signs per group
-  const double *ss, *ct, *G, *sa;
+  const double *mx, *my, *w;  // per folded ordinate
+  const int *sx, *sy;         // upwind signs per folded ordinate
+  const double *ss, *ct, *G;
   double *f;                  // [ndf][nc]
-  double *partial;            // [ngroups][nc]
-  void *face;                 // [ngroups][nbands][NDW][2][nx] of the sweep type
-  long long *prog;            // [ngroups][nbands]
-  unsigned long long *ticket;
+  void *partial;              // [ndf][nc] of the sweep's partial type
+  double *dummy;              // 128 doubles: stores of idle lanes
 };
 
-__device__ __forceinline__ double row_shr1(double v) {
+__device__ __forceinline__ double wave_shr1(double v) {
   int lo = __double2loint(v), hi = __double2hiint(v);
-  lo = __builtin_amdgcn_update_dpp(0, lo, 0x111, 0xf, 0xf, false);
-  hi = __builtin_amdgcn_update_dpp(0, hi, 0x111, 0xf, 0xf, false);
+  lo = __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xf, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xf, 0xf, false);
   return __hiloint2double(hi, lo);
 }
-__device__ __forceinline__ float row_shr1(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, false));
+__device__ __forceinline__ float wave_shr1(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
 }
 
-__device__ __forceinline__ long long prog_load(long long *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ int lds_load(int *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_publish(int *p, int v, bool writer) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // earlier LDS traffic complete
+  if (writer) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// MODE 0: SI sweep of the source array src (zero inflow) -> moment partials.
+// per-step prefetched cell data
+template <typename R>
+struct Slot {
+  double ct, a1, a2, a3, a4;  // sigma~_t and the mode's other per-cell inputs
+  R s;                        // MODE 0 source
+  R fb, hb;                   // row-0 inputs from the band below
+};
+
+// MODE 0: SI sweep of the source src (zero inflow) -> per-ordinate w f.
 // MODE 1: f-pass: final f^n (source sigma_s rho^n + G + f^{n-1}/dt, inflow g)
 //         written over f, then the right-hand-side sweep (source f^n/dt + G,
-//         inflow g) -> moment partials.
+//         inflow g) -> per-ordinate w h.
 // MODE 2: right-hand-side sweep only, from the stored f.
 template <typename R, int MODE>
-__global__ void __launch_bounds__(64) k_plane_sweep(PlaneArgs A, const R *__restrict__ src,
-                                                    const double *__restrict__ rho, long long epoch) {
-  __shared__ long long tk;
-  const int lane = threadIdx.x;
-  // every launch takes exactly ngroups * nbands tickets, so the remainder is
-  // this launch's task index, handed out band-major
-  if (lane == 0) tk = (long long)(atomicAdd(A.ticket, 1ULL) % (unsigned long long)(A.ngroups * A.nbands));
+__global__ void __launch_bounds__(1024) k_plane_sweep(PlaneArgs A, const R *__restrict__ src,
+                                                      const double *__restrict__ rho) {
+  constexpr int NF = MODE == 0 ? 1 : 2;
+  typedef typename std::conditional<MODE == 0, R, double>::type PT;
+  __shared__ R ring[MAXW][RING][NF];
+  __shared__ int prod[MAXW], cons[MAXW];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (threadIdx.x < MAXW) {
+    prod[threadIdx.x] = 0;
+    cons[threadIdx.x] = 0;
+  }
   __syncthreads();
-  const int task = (int)tk;
-  const int bo = task / A.ngroups, grp = task % A.ngroups;
-  const int k = lane >> 4, j = lane & 15;
-  const int dir = NDW * grp + k;
-  const int sx = A.gsx[grp], sy = A.gsy[grp];
-  const int nx = A.nx, ny = A.ny, nc = A.nc;
-  const int b = bo * ROWS + j;
-  const bool rowok = b < ny;
-  const int iy = sy > 0 ? b : ny - 1 - b;
+  const int NW = A.nw, nx = A.nx, ny = A.ny, nc = A.nc;
+  const int dir = blockIdx.x;
+  const int sx = A.sx[dir], sy = A.sy[dir];
   const R mx = (R)A.mx[dir], my = (R)A.my[dir], w = (R)A.w[dir];
+  const double mxy = A.mx[dir] + A.my[dir];
   const R idt = (R)A.inv_dt;
-  R *faces = (R *)A.face;
-  const size_t fstride = (size_t)NDW * 2 * nx;
-  R *face_out = faces + ((size_t)grp * A.nbands + bo) * fstride;
-  const R *face_in = bo > 0 ? faces + ((size_t)grp * A.nbands + bo - 1) * fstride : nullptr;
-  long long *prog_out = A.prog + (size_t)grp * A.nbands + bo;
-  long long *prog_in = bo > 0 ? prog_out - 1 : nullptr;
-  const long long base = epoch << 20;
-  const R gx = (MODE == 0) ? R(0) : (R)(sx > 0 ? A.g[0] : A.g[1]);
-  const R gy = (MODE == 0) ? R(0) : (R)(sy > 0 ? A.g[2] : A.g[3]);
-  R fl = gx, hl = gx;      // left neighbours (same row, previous column)
-  R fprev = R(0), hprev = R(0);
-  int avail = 0;           // columns of the band below known to be published
+  const R gx = MODE == 0 ? R(0) : (R)(sx > 0 ? A.g[0] : A.g[1]);
+  const R gy = MODE == 0 ? R(0) : (R)(sy > 0 ? A.g[2] : A.g[3]);
   double *fdir = A.f + (size_t)dir * nc;
-  double *part = A.partial + (size_t)grp * nc;
-  for (int t = 0; t < nx + ROWS - 1; ++t) {
-    const int a = t - j;
-    const bool on = rowok && a >= 0 && a < nx;
-    R fb = row_shr1(fprev), hb = row_shr1(hprev);
-    if (j == 0) {
-      if (bo == 0) {
-        fb = gy;
-        hb = gy;
-      } else if (a >= 0 && a < nx) {
-        if (a >= avail) {
-          const long long need = base + min(nx, a + ROWS);
-          while (prog_load(prog_in) < need) __builtin_amdgcn_s_sleep(1);
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-          avail = min(nx, a + ROWS);
-        }
-        fb = face_in[(k * 2) * nx + a];
-        hb = face_in[(k * 2 + 1) * nx + a];
+  PT *part = (PT *)A.partial + (size_t)dir * nc;
+  double *dummy = A.dummy;
+  const int wout = wv, win = (wv + NW - 1) % NW;
+  int seen_prod = 0, seen_cons = 0;  // last counter values read (monotone)
+
+  for (int band = wv; band < A.nbands; band += NW) {
+    const int rows = min(BAND, ny - band * BAND);
+    const bool rowok = lane < rows;
+    const int b = band * BAND + lane;
+    const int iy = sy > 0 ? b : ny - 1 - b;
+    const int iyc = sy > 0 ? min(b, ny - 1) : max(ny - 1 - b, 0);  // clamped row for idle lanes
+    const int c0 = iy * nx + (sx > 0 ? 0 : nx - 1);    // cell of column 0; column a at c0 + sx a
+    const int cbase = iyc * nx + (sx > 0 ? 0 : nx - 1);
+    const bool has_in = band > 0, has_out = band + 1 < A.nbands;
+    const int pin0 = ((band - 1) / NW) * nx;          // ring positions of the band below
+    const int pout0 = (band / NW) * nx;               // ring positions of this band
+
+    // Every lane loads every step (clamped cell when idle) and every lane
+    // stores every step (to a per-lane dummy when idle): the memory counter
+    // then advances identically on all paths and the prefetched loads are
+    // waited for individually.
+    auto fetch = [&](Slot<R> &q, int t) {
+      const int a = min(max(t - lane, 0), nx - 1);
+      const int c = cbase + sx * a;
+      q.ct = A.ct[c];
+      if (MODE == 0) q.s = src[c];
+      if (MODE == 1) {
+        q.a1 = A.ss[c];
+        q.a2 = rho[c];
+        q.a3 = A.G[c];
+        q.a4 = fdir[c];
       }
-    }
-    R f = R(0), h = R(0);
-    double v = 0.0;
-    int c = 0;
-    if (on) {
-      const int ix = sx > 0 ? a : nx - 1 - a;
-      c = iy * nx + ix;
-      const R inv = rt_rcp((R)A.ct[c] + mx + my);
-      if (MODE == 0) {
-        f = (src[c] + mx * fl + my * fb) * inv;
-        v = (double)(w * f);
-      } else {
-        if (MODE == 1) {
-          const R s1 = (R)rt_fma(A.ss[c], rho[c], A.G[c]) + (R)fdir[c] * idt;
-          f = (s1 + mx * fl + my * fb) * inv;
-          fdir[c] = (double)f;
+      if (MODE == 2) {
+        q.a3 = A.G[c];
+        q.a4 = fdir[c];
+      }
+      if (t < nx) {  // row-0 input of column t (uniform)
+        if (has_in) {
+          const int pos = pin0 + t;
+          if (seen_prod <= pos) {
+            while ((seen_prod = lds_load(&prod[win])) <= pos) __builtin_amdgcn_s_sleep(1);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+          }
+          if (lane == 0) {
+            q.fb = ring[win][pos & (RING - 1)][0];
+            if (NF == 2) q.hb = ring[win][pos & (RING - 1)][NF - 1];
+          }
+          if (((t + 1) % CPUB) == 0 || t == nx - 1) lds_publish(&cons[win], pos + 1, lane == 0);
         } else {
-          f = (R)fdir[c];
+          q.fb = gy;
+          q.hb = gy;
         }
-        const R s2 = rt_fma(f, idt, (R)A.G[c]);
-        h = (s2 + mx * hl + my * hb) * inv;
-        v = (double)(w * h);
       }
-      fl = f;
-      hl = h;
+    };
+
+    Slot<R> q[PD];
+#pragma unroll
+    for (int k = 0; k < PD; ++k) {
+      q[k] = Slot<R>{0.0, 0.0, 0.0, 0.0, 0.0, R(0), R(0), R(0)};
+      fetch(q[k], k);
     }
-    // the four ordinates of the wave share the cell: add lanes j, j+16, j+32, j+48
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
-    if (on && k == 0) part[c] = v;
-    if (on && j == ROWS - 1) {
-      face_out[(k * 2) * nx + a] = f;
-      face_out[(k * 2 + 1) * nx + a] = h;
-    }
-    fprev = f;
-    hprev = h;
-    // the top row has finished column t - (ROWS - 1): publish in chunks of ROWS
-    const int done = t - (ROWS - 1) + 1;
-    if (done > 0 && ((done % ROWS) == 0 || done == nx)) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      if (lane == 0)
-        __hip_atomic_store(prog_out, base + done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    R fl = gx, hl = gx, fprev = R(0), hprev = R(0);
+    // steps of the band, rounded up to the unroll (the extra steps are idle)
+    const int T = ((nx + rows - 1 + PD - 1) / PD) * PD;
+    for (int t0 = 0; t0 < T; t0 += PD) {
+#pragma unroll
+      for (int k = 0; k < PD; ++k) {
+        const int t = t0 + k;
+        const int a = t - lane;
+        const bool on = rowok && a >= 0 && a < nx;
+        R fb = wave_shr1(fprev), hb = NF == 2 ? wave_shr1(hprev) : R(0);
+        if (lane == 0) {
+          fb = q[k].fb;
+          hb = q[k].hb;
+        }
+        const int c = c0 + sx * a;
+        const R inv = rt_rcp((R)(q[k].ct + mxy));
+        R f, h = R(0);
+        PT v;
+        if (MODE == 0) {
+          f = (q[k].s + my * fb + mx * fl) * inv;
+          v = (PT)(w * f);
+        } else {
+          if (MODE == 1) {
+            const R s1 = (R)(rt_fma(q[k].a1, q[k].a2, q[k].a3) + q[k].a4 * A.inv_dt);
+            f = (s1 + my * fb + mx * fl) * inv;
+            *(on ? fdir + c : dummy + lane) = (double)f;
+          } else {
+            f = (R)q[k].a4;
+          }
+          const R s2 = rt_fma(f, idt, (R)q[k].a3);
+          h = (s2 + my * hb + mx * hl) * inv;
+          v = (PT)(w * h);
+        }
+        *(on ? part + c : (PT *)(dummy + 64) + lane) = v;
+        if (!on) {
+          f = R(0);
+          h = R(0);
+        } else {
+          fl = f;
+          hl = h;
+        }
+        fprev = f;
+        hprev = h;
+        // the top row finished column t - (BAND - 1): hand it to the band above
+        const int ao = t - (BAND - 1);
+        if (has_out && ao >= 0 && ao < nx) {
+          const int pos = pout0 + ao;
+          if (seen_cons < pos - RING + 1) {
+            while ((seen_cons = lds_load(&cons[wout])) < pos - RING + 1) __builtin_amdgcn_s_sleep(1);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+          }
+          if (lane == BAND - 1) {
+            ring[wout][pos & (RING - 1)][0] = f;
+            if (NF == 2) ring[wout][pos & (RING - 1)][NF - 1] = h;
+          }
+          if (((ao + 1) % PUB) == 0 || ao == nx - 1) lds_publish(&prod[wout], pos + 1, lane == BAND - 1);
+        }
+        fetch(q[k], t + PD);
+      }
     }
   }
 }
 
-// out[c] = sum_g partial[g][c] (+ add[c]); optional residual maxima against
-// rp for the stop test of Alg. 1 (per block: max|out - rp|, max|out|).
+// out[c] = sum over ordinates of partial[d][c] (+ add[c], or + out[c] when
+// accumulating); optional per-block maxima for the stop test of Alg. 1:
+// max|out - rp| and max|out|.
+template <typename PT>
 __global__ void __launch_bounds__(BLK) k_plane_reduce(PlaneArgs A, double *out, const double *add,
                                                       int accumulate, const double *rp, double *blkmax) {
   const int c = blockIdx.x * BLK + threadIdx.x;
   double d = 0.0, y = 0.0;
   if (c < A.nc) {
+    const PT *pp = (const PT *)A.partial + c;
     double s = 0.0;
-    for (int g = 0; g < A.ngroups; ++g) s += A.partial[(size_t)g * A.nc + c];
+    for (int g = 0; g < A.ndf; ++g) s += (double)pp[(size_t)g * A.nc];
     if (accumulate) s += out[c];
     else if (add) s += add[c];
     out[c] = s;
@@ -408,13 +471,11 @@ __global__ void __launch_bounds__(BLK) k_romapply_expand(RomDev R, const int *ra
 struct PlaneHost {
   PlaneArgs A;
   DsaArgs D;
-  int ndf = 0;                    // folded ordinates incl. padding
-  std::vector<int> fold_of;       // CL ordinate -> folded index
+  int ndf = 0;                    // folded ordinates (nv / 2)
+  std::vector<int> fold_of;       // ordinate -> folded index
   double *dmx = nullptr;          // device: mx, my, w
-  int *dsign = nullptr;           // device: gsx, gsy
-  double *partial = nullptr, *face = nullptr;
-  long long *prog = nullptr;
-  unsigned long long *ticket = nullptr;
+  int *dsign = nullptr;           // device: sx, sy
+  double *partial = nullptr;
   double *y = nullptr, *rp = nullptr, *src = nullptr, *dvec = nullptr;
   float *src32 = nullptr;
   double *cr = nullptr, *cx = nullptr, *cd0 = nullptr, *cd1 = nullptr;
@@ -425,40 +486,35 @@ struct PlaneHost {
   int cheb_iters = 0;
   double cheb_theta = 1.0, cheb_delta = 0.0;
   std::vector<double> cheb_c1, cheb_c2;
-  long long epoch = 0;
   size_t bytes = 0;
 };
 
-static size_t plane_bytes_for(const rtrom_problem_desc *d, int *ndf_out, int *ngroups_out, int *nbands_out) {
+static size_t plane_bytes_for(const rtrom_problem_desc *d, int *ndf_out) {
   const size_t nv = (size_t)d->n_polar * d->n_azim;
-  const int per_quad = (d->n_azim / 4) * (d->n_polar / 2);
-  const int gpq = (per_quad + NDW - 1) / NDW;
-  const int ngroups = 4 * gpq, ndf = ngroups * NDW;
-  const int nbands = (d->ny + ROWS - 1) / ROWS;
+  const int ndf = (int)(nv / 2);
   const size_t nc = (size_t)d->nx * d->ny;
   const size_t nblk = (nc + BLK - 1) / BLK;
   if (ndf_out) *ndf_out = ndf;
-  if (ngroups_out) *ngroups_out = ngroups;
-  if (nbands_out) *nbands_out = nbands;
   size_t b = 0;
   auto take = [&](size_t x) { b += (x + 255) & ~size_t(255); };
-  take((size_t)ngroups * nc * 8);                          // partials
-  take((size_t)ngroups * nbands * NDW * 2 * d->nx * 8);    // faces
-  take((size_t)ngroups * nbands * 8 + 8);                  // progress, ticket
+  take((size_t)ndf * nc * 8);                              // per-ordinate partials
   take(nc * 8 * 8);                                        // y rp src dvec cr cx cd0 cd1
   take(nc * 4);                                            // src32
   take(nc * 8 * 3);                                        // diag ax ay
   take(nblk * 2 * 8 + 64);                                 // blkmax, res
   take(nblk * RT_NPART * 8 + RT_RMAX * 8);                 // rom apply partials, coef
-  take((size_t)ndf * 3 * 8 + ngroups * 2 * 4);
-  if ((size_t)ndf > nv) take((size_t)ndf * nc * 8);  // folded f (tiny quadratures)
+  take((size_t)ndf * 3 * 8 + (size_t)ndf * 2 * 4);         // mx my w, sx sy
+  take(128 * 8);                                           // idle-lane store target
   return b;
 }
 
-size_t rt_plane_extra_bytes(const rtrom_problem_desc *d) {
-  int ndf, ng, nb;
-  return plane_bytes_for(d, &ndf, &ng, &nb);
-}
+size_t rt_plane_extra_bytes(const rtrom_problem_desc *d) { return plane_bytes_for(d, nullptr); }
+
+// Largest nx for grids with more bands than waves: the bands then cycle
+// through the waves, and the band-to-band rings (RING columns, consumers
+// publishing every CPUB) must drain before a wave moves to its next band.
+int rt_plane_max_nx_cyclic() { return MAXW * (RING - CPUB); }
+int rt_plane_needs_cyclic(int ny) { return (ny + BAND - 1) / BAND > MAXW; }
 
 #define PH(call)                                                            \
   do {                                                                      \
@@ -469,19 +525,25 @@ size_t rt_plane_extra_bytes(const rtrom_problem_desc *d) {
     }                                                                       \
   } while (0)
 
+template <typename PT>
+static void launch_reduce(rtrom_problem *p, PlaneHost *H, double *out, const double *add, int accumulate,
+                          const double *rp, double *blkmax) {
+  hipLaunchKernelGGL((k_plane_reduce<PT>), dim3(H->A.nblk), dim3(BLK), 0, p->stream, H->A, out, add, accumulate,
+                     rp, blkmax);
+}
+
 static int launch_sweep(rtrom_problem *p, PlaneHost *H, int mode, int fp32, const void *src, const double *rho) {
   PlaneArgs &A = H->A;
-  const int nwg = A.ngroups * A.nbands;
+  const dim3 grid(A.ndf), block(64 * A.nw);
   hipStream_t s = p->stream;
-  const long long e = ++H->epoch;
   if (mode == 0 && fp32)
-    hipLaunchKernelGGL((k_plane_sweep<float, 0>), dim3(nwg), dim3(64), 0, s, A, (const float *)src, rho, e);
+    hipLaunchKernelGGL((k_plane_sweep<float, 0>), grid, block, 0, s, A, (const float *)src, rho);
   else if (mode == 0)
-    hipLaunchKernelGGL((k_plane_sweep<double, 0>), dim3(nwg), dim3(64), 0, s, A, (const double *)src, rho, e);
+    hipLaunchKernelGGL((k_plane_sweep<double, 0>), grid, block, 0, s, A, (const double *)src, rho);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_plane_sweep<double, 1>), dim3(nwg), dim3(64), 0, s, A, (const double *)nullptr, rho, e);
+    hipLaunchKernelGGL((k_plane_sweep<double, 1>), grid, block, 0, s, A, (const double *)nullptr, rho);
   else
-    hipLaunchKernelGGL((k_plane_sweep<double, 2>), dim3(nwg), dim3(64), 0, s, A, (const double *)nullptr, rho, e);
+    hipLaunchKernelGGL((k_plane_sweep<double, 2>), grid, block, 0, s, A, (const double *)nullptr, rho);
   PH(hipGetLastError());
   return RTROM_OK;
 }
@@ -490,57 +552,46 @@ int rt_plane_create(rtrom_problem *p) {
   const rtrom_problem_desc *d = &p->d;
   PlaneHost *H = new PlaneHost();
   p->plane = H;
-  int ndf, ngroups, nbands;
-  H->bytes = plane_bytes_for(d, &ndf, &ngroups, &nbands);
+  int ndf;
+  H->bytes = plane_bytes_for(d, &ndf);
   H->ndf = ndf;
   const int nx = d->nx, ny = d->ny, nc = nx * ny;
   const int nblk = (nc + BLK - 1) / BLK;
-  // folded ordinates: quadrant q (0:+x+y, 1:-x+y, 2:+x-y, 3:-x-y), classes in
-  // CL order of the upper hemisphere, padded per quadrant to a multiple of 4
+  const int nbands = (ny + BAND - 1) / BAND;
+  if (nbands > MAXW && nx > rt_plane_max_nx_cyclic()) {
+    rt_set_error("plane: grids with more than 1024 rows are limited to nx <= 3840");
+    return RTROM_EINVAL;
+  }
+  // folded ordinates: the upper hemisphere (Omega_z > 0) in ordinate order;
+  // Omega_z < 0 ordinates map to their mirror at the same azimuth
   const int nphi = d->n_azim, nz = d->n_polar;
-  const int per_quad = (nphi / 4) * (nz / 2);
-  const int gpq = ngroups / 4;
-  std::vector<double> hm(3 * (size_t)ndf, 0.0);
-  std::vector<int> hs(2 * (size_t)ngroups, 1);
-  H->fold_of.assign((size_t)nphi * nz, -1);
-  std::vector<int> fill(4, 0);
   const double hx = d->lx / nx, hy = d->ly / ny;
-  for (int q = 0; q < 4; ++q)
-    for (int gg = 0; gg < gpq; ++gg) {
-      hs[q * gpq + gg] = (q == 0 || q == 2) ? 1 : -1;
-      hs[ngroups + q * gpq + gg] = (q < 2) ? 1 : -1;
-    }
+  std::vector<double> hm(3 * (size_t)ndf, 0.0);
+  std::vector<int> hs(2 * (size_t)ndf, 1);
+  H->fold_of.assign((size_t)nphi * nz, -1);
+  int nf = 0;
   for (int j2 = 0; j2 < nz; ++j2)
     for (int j1 = 0; j1 < nphi; ++j1) {
       const int j = j2 * nphi + j1;
-      const double ox = p->ox[j], oy = p->oy[j], oz = p->oz[j];
-      const int q = (ox > 0 ? 0 : 1) + (oy > 0 ? 0 : 2);
-      if (oz > 0) {
-        const int slot = fill[q]++;
-        const int idx = q * gpq * NDW + slot;
-        hm[idx] = std::fabs(ox) / hx;
-        hm[ndf + idx] = std::fabs(oy) / hy;
-        hm[2 * ndf + idx] = 2.0 * p->w[j];
+      if (p->oz[j] > 0) {
+        const int idx = nf++;
+        hm[idx] = std::fabs(p->ox[j]) / hx;
+        hm[ndf + idx] = std::fabs(p->oy[j]) / hy;
+        hm[2 * (size_t)ndf + idx] = 2.0 * p->w[j];
+        hs[idx] = p->ox[j] > 0 ? 1 : -1;
+        hs[ndf + idx] = p->oy[j] > 0 ? 1 : -1;
         H->fold_of[j] = idx;
       }
     }
+  if (nf != ndf) {
+    rt_set_error("plane: quadrature is not symmetric in Omega_z");
+    return RTROM_EINVAL;
+  }
   for (int j2 = 0; j2 < nz; ++j2)
     for (int j1 = 0; j1 < nphi; ++j1) {
       const int j = j2 * nphi + j1;
-      if (p->oz[j] < 0) {
-        // the mirror of the same azimuth at level nz-1-j2 in the upper half
-        const int jm = (nz - 1 - j2) * nphi + j1;
-        H->fold_of[j] = H->fold_of[jm];
-      }
+      if (p->oz[j] < 0) H->fold_of[j] = H->fold_of[(size_t)(nz - 1 - j2) * nphi + j1];
     }
-  for (int q = 0; q < 4; ++q)
-    for (int s = fill[q]; s < gpq * NDW; ++s) {
-      const int idx = q * gpq * NDW + s;
-      hm[idx] = 1.0;  // padding ordinates: zero weight
-      hm[ndf + idx] = 1.0;
-      hm[2 * ndf + idx] = 0.0;
-    }
-  (void)per_quad;
   // device buffers
   char *mem = nullptr;
   PH(hipMalloc(&mem, H->bytes));
@@ -551,10 +602,7 @@ int rt_plane_create(rtrom_problem *p) {
     off += (x + 255) & ~size_t(255);
     return q;
   };
-  H->partial = (double *)take((size_t)ngroups * nc * 8);
-  H->face = (double *)take((size_t)ngroups * nbands * NDW * 2 * nx * 8);
-  H->prog = (long long *)take((size_t)ngroups * nbands * 8 + 8);
-  H->ticket = (unsigned long long *)(H->prog + (size_t)ngroups * nbands);
+  H->partial = (double *)take((size_t)ndf * nc * 8);
   char *vecs = take((size_t)nc * 8 * 8);
   H->y = (double *)vecs;
   H->rp = H->y + nc;
@@ -572,13 +620,11 @@ int rt_plane_create(rtrom_problem *p) {
   H->res = H->blkmax + 2 * (size_t)nblk;
   H->rpart = (double *)take((size_t)nblk * RT_NPART * 8 + RT_RMAX * 8);
   H->rcoef = H->rpart + (size_t)nblk * RT_NPART;
-  H->dmx = (double *)take((size_t)ndf * 3 * 8 + ngroups * 2 * 4);
+  H->dmx = (double *)take((size_t)ndf * 3 * 8 + (size_t)ndf * 2 * 4);
   H->dsign = (int *)(H->dmx + 3 * (size_t)ndf);
+  double *dummy = (double *)take(128 * 8);
   Inst &I = p->hinst;
-  // f^n of the folded set: in the arena's f unless the padded folded set is
-  // larger than the full one
-  double *fbuf = (size_t)ndf > (size_t)p->nv ? (double *)take((size_t)ndf * nc * 8) : I.f;
-  H->fbuf = fbuf;
+  H->fbuf = I.f;  // f^n of the folded set lives in the first nv/2 ordinate slots
   PH(hipMemcpyAsync(H->dmx, hm.data(), hm.size() * 8, hipMemcpyHostToDevice, p->stream));
   PH(hipMemcpyAsync(H->dsign, hs.data(), hs.size() * 4, hipMemcpyHostToDevice, p->stream));
   PH(hipHostMalloc((void **)&H->res_h, 64, hipHostMallocDefault));
@@ -588,25 +634,23 @@ int rt_plane_create(rtrom_problem *p) {
   A.ny = ny;
   A.nc = nc;
   A.ndf = ndf;
-  A.ngroups = ngroups;
   A.nbands = nbands;
+  A.nw = std::min(nbands, MAXW);
   A.nblk = nblk;
   A.inv_dt = 1.0 / d->dt;
   for (int k = 0; k < 4; ++k) A.g[k] = d->inflow[k];
   A.mx = H->dmx;
   A.my = H->dmx + ndf;
   A.w = H->dmx + 2 * (size_t)ndf;
-  A.gsx = H->dsign;
-  A.gsy = H->dsign + ngroups;
+  A.sx = H->dsign;
+  A.sy = H->dsign + ndf;
   A.ss = I.ss;
   A.ct = I.ct;
   A.G = I.G;
-  A.sa = I.sa;
-  A.f = fbuf;
+  A.f = H->fbuf;
   A.partial = H->partial;
-  A.face = H->face;
-  A.prog = H->prog;
-  A.ticket = H->ticket;
+  A.dummy = dummy;
+  double *fbuf = H->fbuf;
   // f^0 (isotropic) on every folded ordinate: rebuild from rho
   for (int j = 0; j < ndf; ++j)
     PH(hipMemcpyAsync(fbuf + (size_t)j * nc, I.rho, (size_t)nc * 8, hipMemcpyDeviceToDevice, p->stream));
@@ -668,8 +712,7 @@ int rt_plane_rhs(rtrom_problem *p) {
   const int nblk = H->A.nblk;
   int e = launch_sweep(p, H, 2, 0, nullptr, p->hinst.rho);
   if (e) return e;
-  hipLaunchKernelGGL(k_plane_reduce, dim3(nblk), dim3(BLK), 0, p->stream, H->A, p->hinst.bt2[p->steps & 1],
-                     (const double *)nullptr, 0, (const double *)nullptr, (double *)nullptr);
+  launch_reduce<double>(p, H, p->hinst.bt2[p->steps & 1], nullptr, 0, nullptr, nullptr);
   PH(hipGetLastError());
   return RTROM_OK;
 }
@@ -730,7 +773,9 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
   const double *bt = I.bt2[cur];
   int ig_fb = 0;
   if (rom && st.flag_ig && st.lu_ok_ig) {
+    rt_prof_begin(RT_K_PLANE_OTHER, s);
     int e = rom_apply_grid(p, H, I.ig, &I.st->rank_ig, bt, I.rho0);
+    rt_prof_end(RT_K_PLANE_OTHER, s);
     if (e) return e;
   } else {
     ig_fb = rom && st.flag_ig;
@@ -741,11 +786,12 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
   double resid = 0.0;
   for (;;) {
     if (need64) {
+      rt_prof_begin(RT_K_PLANE_SWEEP, s);
       hipLaunchKernelGGL(k_plane_src64, dim3(nblk), dim3(BLK), 0, s, nc, I.ss, (const double *)H->rp, H->src);
       int e = launch_sweep(p, H, 0, 0, H->src, nullptr);
       if (e) return e;
-      hipLaunchKernelGGL(k_plane_reduce, dim3(nblk), dim3(BLK), 0, s, H->A, H->y, bt, 0,
-                         (const double *)H->rp, H->blkmax);
+      launch_reduce<double>(p, H, H->y, bt, 0, H->rp, H->blkmax);
+      rt_prof_end(RT_K_PLANE_SWEEP, s);
       if (nsweep == 0)
         hipLaunchKernelGGL(k_plane_copy, dim3(nblk), dim3(BLK), 0, s, nc, (const double *)H->y, I.rhalf);
       nsweep++;
@@ -769,26 +815,31 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
     if (nsweep >= I.max_iter) break;
     const double *dcorr = nullptr;
     if (rom && first_corr && st.flag_pc && st.lu_ok_pc) {
+      rt_prof_begin(RT_K_PLANE_OTHER, s);
       hipLaunchKernelGGL(k_plane_sub, dim3(nblk), dim3(BLK), 0, s, nc, (const double *)H->y,
                          (const double *)I.rho0, I.work);
       e = rom_apply_grid(p, H, I.pc, &I.st->rank_pc, I.work, I.dpc);
+      rt_prof_end(RT_K_PLANE_OTHER, s);
       if (e) return e;
       dcorr = I.dpc;
       used_pc = 1;
     } else if (I.method != RT_SI_PLAIN) {
       if (rom && first_corr && st.flag_pc) pc_fb = 1;
+      rt_prof_begin(RT_K_PLANE_DSA, s);
       e = dsa_solve(p, H, H->y, H->rp, nullptr);
+      rt_prof_end(RT_K_PLANE_DSA, s);
       if (e) return e;
       dcorr = H->cx;
     }
     first_corr = 0;
     if (mixed) {
+      rt_prof_begin(RT_K_PLANE_SWEEP, s);
       hipLaunchKernelGGL(k_plane_increment, dim3(nblk), dim3(BLK), 0, s, nc, I.ss, (const double *)H->y, dcorr,
                          H->rp, H->src32);
       e = launch_sweep(p, H, 0, 1, H->src32, nullptr);
       if (e) return e;
-      hipLaunchKernelGGL(k_plane_reduce, dim3(nblk), dim3(BLK), 0, s, H->A, H->y, (const double *)nullptr, 1,
-                         (const double *)H->rp, H->blkmax);
+      launch_reduce<float>(p, H, H->y, nullptr, 1, H->rp, H->blkmax);
+      rt_prof_end(RT_K_PLANE_SWEEP, s);
       exact = 0;
       n32++;
       nsweep++;
@@ -818,8 +869,7 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
   {
     int e = launch_sweep(p, H, 1, 0, nullptr, I.rho);
     if (e) return e;
-    hipLaunchKernelGGL(k_plane_reduce, dim3(nblk), dim3(BLK), 0, s, H->A, I.bt2[cur ^ 1],
-                       (const double *)nullptr, 0, (const double *)nullptr, (double *)nullptr);
+    launch_reduce<double>(p, H, I.bt2[cur ^ 1], nullptr, 0, nullptr, nullptr);
     PH(hipGetLastError());
   }
   rt_prof_end(RT_K_PLANE_FPASS, s);
