@@ -271,7 +271,7 @@ static size_t slab_bytes(const rtrom_problem_desc *d, int nv) {
   for (int k = 0; k < 13; ++k) L.take(nc * 8);
   L.take(4 * nc * 8);
   L.take((size_t)nv * 8 * 6);
-  L.take((size_t)nv * nc * 8);
+  if (d->dim == 1) L.take((size_t)nv * nc * 8);  // 2D keeps its folded f in the plane buffers
   for (int r = 0; r < 2; ++r) {
     L.take((RT_RMAX + 1) * ld * 8);
     L.take((RT_RMAX + 1) * ld * 8);
@@ -397,7 +397,7 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   I.dpc = D(nc * 8);
   I.work = D(4 * (size_t)nc * 8);
   double *qbuf = D((size_t)nv * 8 * 6);
-  I.f = D((size_t)nv * nc * 8);
+  I.f = d->dim == 1 ? D((size_t)nv * nc * 8) : nullptr;
   RomDev *roms[2] = {&I.ig, &I.pc};
   RomWork rom_work_init[2];
   for (int r = 0; r < 2; ++r) {
@@ -475,7 +475,7 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
     for (int i = 0; i < nc; ++i) rho0[i] = d->f0[i];
   ok = ok && H2D(I.rho, rho0.data(), nc * 8);
   if (d->f0)
-    for (int j = 0; j < nv && ok; ++j) ok = H2D(I.f + (size_t)j * nc, rho0.data(), nc * 8);
+    for (int j = 0; j < nv && ok && d->dim == 1; ++j) ok = H2D(I.f + (size_t)j * nc, rho0.data(), nc * 8);
   // initial phase-machine state: everything zero
   RtState st0;
   memset(&st0, 0, sizeof(st0));

@@ -1,20 +1,26 @@
 // rt_plane.hip -- X-Y (2D) path of librtrom for gfx950.
 //
-// Ordinates: Omega_z = +-c pairs sweep identically in X-Y, so f is stored for
+// Ordinates: Omega_z = +-c pairs sweep identically in X-Y, so f is kept for
 // the upper hemisphere only, each with its pair's doubled weight ("folded"
-// set, nv / 2 ordinates).
+// set, nv / 2 ordinates), grouped by upwind quadrant.
 //
 // Sweep (Sec. 2.3: one upwind-ordered pass per ordinate): in upwind
-// coordinates, f(a, b) = (s + m_x f(a-1, b) + m_y f(a, b-1)) / (sigma~_t +
-// m_x + m_y) with m = |Omega| / h.  One workgroup per folded ordinate; one
-// wave per band of 64 rows (lane = row), bands in flight on up to 16 waves.
-// A wave runs a skewed pipeline across the columns: at step t, row j handles
-// column t - j, the value from the row below arrives by a wave-wide DPP shift,
-// and the band below hands its top row over through an LDS ring with
-// producer / consumer counters (back-pressure keeps the ring bounded).  Cell
-// data are prefetched PD steps ahead.  Each workgroup writes its ordinate's
-// weighted flux to a per-ordinate partial; a reduce kernel adds the ordinates
-// in a fixed order, so results are deterministic.
+// coordinates (column a, row u), f(a, u) = (s + m_x f(a-1, u) + m_y f(a, u-1))
+// / (sigma~_t + m_x + m_y) with m = |Omega| / h.  One workgroup per folded
+// ordinate, one wave per band of 64 rows (lane = row), up to 16 bands in
+// flight.  A wave runs a skewed pipeline: at step t, row j handles column
+// t - j; the row below arrives by a wave-wide DPP shift and the band below
+// hands its top row over through an LDS ring with producer / consumer
+// counters (back-pressure keeps the ring bounded).
+//
+// Skewed layout: every per-cell array a sweep touches is stored, per upwind
+// quadrant, at slot ((band * TT) + t) * 64 + j -- the order in which the
+// pipeline visits cells -- so each step of a wave reads and writes 64
+// consecutive elements.  Slots outside the grid are padding: idle lanes load
+// and store there, which keeps every lane's memory traffic identical and the
+// prefetched loads individually waited for.  Per-cell inputs are skewed by
+// small gather kernels; per-ordinate results are summed per quadrant in the
+// skewed layout and un-skewed once, in a fixed order (deterministic).
 //
 // DSA (eq. rho_residual) uses the cell-centred 5-point operator with
 // Jacobi-preconditioned Chebyshev iteration on Gershgorin bounds: no dot
@@ -22,6 +28,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "rt_host.h"
@@ -32,31 +39,66 @@ namespace {
 constexpr int BAND = 64;   // rows of a band: one wave, lane = row
 constexpr int MAXW = 16;   // bands in flight per workgroup (waves)
 constexpr int RING = 256;  // columns buffered between consecutive bands
-constexpr int PUB = 8;     // producers publish every PUB columns
-constexpr int CPUB = 16;   // consumers publish every CPUB columns
-constexpr int PD = 4;      // prefetch distance in steps (and loop unroll)
+constexpr int CH = 16;     // columns per ring transfer; the step loop is unrolled by CH
 constexpr int BLK = 256;   // cells per block of the element-wise kernels
 
 struct PlaneArgs {
-  int nx, ny, nc, ndf, nbands, nw, nblk, pad_;
+  int nx, ny, nc, ndf, nbands, nw, nblk, TT;  // TT: skewed steps per band
+  int SQ, nsblk;                              // slots per quadrant, blocks over SQ
+  int qstart[5];                              // folded ordinates of quadrant q: [qstart[q], qstart[q+1])
   double inv_dt;
   double g[4];
   const double *mx, *my, *w;  // per folded ordinate
-  const int *sx, *sy;         // upwind signs per folded ordinate
-  const double *ss, *ct, *G;
-  double *f;                  // [ndf][nc]
-  void *partial;              // [ndf][nc] of the sweep's partial type
-  double *dummy;              // 128 doubles: stores of idle lanes
+  const double *ctq, *Gq;     // [4][SQ] sigma~_t, G (skewed)
+  double *s1q;                // [4][SQ] sigma_s rho^n + G (skewed, f-pass)
+  void *srcq;                 // [4][SQ] SI sweep source (skewed, sweep type)
+  double *f;                  // [ndf][SQ] folded f, skewed in its quadrant
+  void *partial;              // [ndf][SQ] w f per ordinate (skewed)
+  double *quadsum;            // [4][SQ] per-quadrant sums (skewed)
 };
 
-__device__ __forceinline__ double wave_shr1(double v) {
-  int lo = __double2loint(v), hi = __double2hiint(v);
-  lo = __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xf, 0xf, false);
-  hi = __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xf, 0xf, false);
+__device__ __forceinline__ int quad_of(int dir, const PlaneArgs &A) {
+  return (dir >= A.qstart[1]) + (dir >= A.qstart[2]) + (dir >= A.qstart[3]);
+}
+// quadrant q: bit 0 set when the sweep runs in -x, bit 1 when in -y
+__device__ __forceinline__ int slot_cell(const PlaneArgs &A, int q, int slot) {
+  const int per_band = A.TT * BAND;
+  const int band = slot / per_band, rem = slot - band * per_band;
+  const int t = rem >> 6, j = rem & 63;
+  const int u = band * BAND + j, a = t - j;
+  if (u >= A.ny || a < 0 || a >= A.nx) return -1;
+  const int iy = (q & 2) ? A.ny - 1 - u : u;
+  const int ix = (q & 1) ? A.nx - 1 - a : a;
+  return iy * A.nx + ix;
+}
+__device__ __forceinline__ int cell_slot(const PlaneArgs &A, int q, int ix, int iy) {
+  const int u = (q & 2) ? A.ny - 1 - iy : iy;
+  const int a = (q & 1) ? A.nx - 1 - ix : ix;
+  const int band = u >> 6, j = u & 63;
+  return (band * A.TT + a + j) * BAND + j;
+}
+
+// lane i gets v of lane i-1; lane 0 gets in0
+__device__ __forceinline__ double shr1_in(double v, double in0) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(in0), __double2loint(v), 0x138, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(in0), __double2hiint(v), 0x138, 0xf, 0xf, false);
   return __hiloint2double(hi, lo);
 }
-__device__ __forceinline__ float wave_shr1(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+__device__ __forceinline__ float shr1_in(float v, float in0) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(in0), __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double rdlane(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ __forceinline__ float rdlane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+// lane l of acc takes the wave-uniform value s
+template <typename R>
+__device__ __forceinline__ R wrlane(R acc, R s, int l) {
+  return ((int)(threadIdx.x & 63) == l) ? s : acc;
 }
 
 __device__ __forceinline__ int lds_load(int *p) {
@@ -70,174 +112,200 @@ __device__ __forceinline__ void lds_publish(int *p, int v, bool writer) {
 // per-step prefetched cell data
 template <typename R>
 struct Slot {
-  double ct, a1, a2, a3, a4;  // sigma~_t and the mode's other per-cell inputs
-  R s;                        // MODE 0 source
-  R fb, hb;                   // row-0 inputs from the band below
+  double ct, a1, a2, a3;  // sigma~_t and the mode's other per-cell inputs
+  R s;                    // MODE 0 source
 };
 
-// MODE 0: SI sweep of the source src (zero inflow) -> per-ordinate w f.
+// MODE 0: SI sweep of the source srcq (zero inflow) -> per-ordinate w f.
 // MODE 1: f-pass: final f^n (source sigma_s rho^n + G + f^{n-1}/dt, inflow g)
 //         written over f, then the right-hand-side sweep (source f^n/dt + G,
 //         inflow g) -> per-ordinate w h.
 // MODE 2: right-hand-side sweep only, from the stored f.
-template <typename R, int MODE>
-__global__ void __launch_bounds__(1024) k_plane_sweep(PlaneArgs A, const R *__restrict__ src,
-                                                      const double *__restrict__ rho) {
+// Ring traffic moves CH columns at a time: the top row's values are gathered
+// into lanes 0..CH-1 of a register, the consumer reads a chunk into lanes
+// 0..CH-1 and feeds its lane 0 with readlane.
+template <typename R, int MODE, int PD>
+__global__ void __launch_bounds__(1024) k_plane_sweep(PlaneArgs A) {
+  static_assert(CH % PD == 0, "prefetch slots rotate within a chunk");
   constexpr int NF = MODE == 0 ? 1 : 2;
   typedef typename std::conditional<MODE == 0, R, double>::type PT;
   __shared__ R ring[MAXW][RING][NF];
   __shared__ int prod[MAXW], cons[MAXW];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   if (threadIdx.x < MAXW) {
     prod[threadIdx.x] = 0;
     cons[threadIdx.x] = 0;
   }
   __syncthreads();
-  const int NW = A.nw, nx = A.nx, ny = A.ny, nc = A.nc;
+  const int NW = A.nw, nx = A.nx, ny = A.ny;
+  const unsigned unx = (unsigned)nx;
   const int dir = blockIdx.x;
-  const int sx = A.sx[dir], sy = A.sy[dir];
+  const int q = quad_of(dir, A);
   const R mx = (R)A.mx[dir], my = (R)A.my[dir], w = (R)A.w[dir];
   const double mxy = A.mx[dir] + A.my[dir];
   const R idt = (R)A.inv_dt;
-  const R gx = MODE == 0 ? R(0) : (R)(sx > 0 ? A.g[0] : A.g[1]);
-  const R gy = MODE == 0 ? R(0) : (R)(sy > 0 ? A.g[2] : A.g[3]);
-  double *fdir = A.f + (size_t)dir * nc;
-  PT *part = (PT *)A.partial + (size_t)dir * nc;
-  double *dummy = A.dummy;
+  const R gx = MODE == 0 ? R(0) : (R)((q & 1) ? A.g[1] : A.g[0]);
+  const R gy = MODE == 0 ? R(0) : (R)((q & 2) ? A.g[3] : A.g[2]);
+  const size_t qoff = (size_t)q * A.SQ, doff = (size_t)dir * A.SQ;
+  const double *ctq = A.ctq + qoff, *Gq = A.Gq + qoff, *s1q = A.s1q + qoff;
+  const R *srcq = (const R *)A.srcq + qoff;
+  double *fd = A.f + doff;
+  PT *part = (PT *)A.partial + doff;
   const int wout = wv, win = (wv + NW - 1) % NW;
   int seen_prod = 0, seen_cons = 0;  // last counter values read (monotone)
 
   for (int band = wv; band < A.nbands; band += NW) {
     const int rows = min(BAND, ny - band * BAND);
     const bool rowok = lane < rows;
-    const int b = band * BAND + lane;
-    const int iy = sy > 0 ? b : ny - 1 - b;
-    const int iyc = sy > 0 ? min(b, ny - 1) : max(ny - 1 - b, 0);  // clamped row for idle lanes
-    const int c0 = iy * nx + (sx > 0 ? 0 : nx - 1);    // cell of column 0; column a at c0 + sx a
-    const int cbase = iyc * nx + (sx > 0 ? 0 : nx - 1);
     const bool has_in = band > 0, has_out = band + 1 < A.nbands;
-    const int pin0 = ((band - 1) / NW) * nx;          // ring positions of the band below
-    const int pout0 = (band / NW) * nx;               // ring positions of this band
+    const int pin0 = ((band - 1) / NW) * nx;   // ring positions of the band below
+    const int pout0 = (band / NW) * nx;        // ring positions of this band
+    const unsigned sbase = (unsigned)band * A.TT * BAND + lane;  // slot of step 0
 
-    // Every lane loads every step (clamped cell when idle) and every lane
-    // stores every step (to a per-lane dummy when idle): the memory counter
-    // then advances identically on all paths and the prefetched loads are
-    // waited for individually.
-    auto fetch = [&](Slot<R> &q, int t) {
-      const int a = min(max(t - lane, 0), nx - 1);
-      const int c = cbase + sx * a;
-      q.ct = A.ct[c];
-      if (MODE == 0) q.s = src[c];
+    auto fetch = [&](Slot<R> &sl, int t) {
+      const unsigned o = sbase + (unsigned)t * BAND;
+      sl.ct = ctq[o];
+      if (MODE == 0) sl.s = srcq[o];
       if (MODE == 1) {
-        q.a1 = A.ss[c];
-        q.a2 = rho[c];
-        q.a3 = A.G[c];
-        q.a4 = fdir[c];
+        sl.a1 = s1q[o];
+        sl.a2 = Gq[o];
+        sl.a3 = fd[o];
       }
       if (MODE == 2) {
-        q.a3 = A.G[c];
-        q.a4 = fdir[c];
-      }
-      if (t < nx) {  // row-0 input of column t (uniform)
-        if (has_in) {
-          const int pos = pin0 + t;
-          if (seen_prod <= pos) {
-            while ((seen_prod = lds_load(&prod[win])) <= pos) __builtin_amdgcn_s_sleep(1);
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-          }
-          if (lane == 0) {
-            q.fb = ring[win][pos & (RING - 1)][0];
-            if (NF == 2) q.hb = ring[win][pos & (RING - 1)][NF - 1];
-          }
-          if (((t + 1) % CPUB) == 0 || t == nx - 1) lds_publish(&cons[win], pos + 1, lane == 0);
-        } else {
-          q.fb = gy;
-          q.hb = gy;
-        }
+        sl.a2 = Gq[o];
+        sl.a3 = fd[o];
       }
     };
+    // hand columns [base, base + cnt) of the top row to the band above
+    auto flush = [&](int base, int cnt, R rout, R routh) {
+      const int pend = pout0 + base + cnt;
+      if (seen_cons < pend - RING) {
+        while ((seen_cons = lds_load(&cons[wout])) < pend - RING) __builtin_amdgcn_s_sleep(1);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      }
+      if (lane < cnt) {
+        ring[wout][(pout0 + base + lane) & (RING - 1)][0] = rout;
+        if (NF == 2) ring[wout][(pout0 + base + lane) & (RING - 1)][NF - 1] = routh;
+      }
+      lds_publish(&prod[wout], pend, lane == 0);
+    };
 
-    Slot<R> q[PD];
+    Slot<R> sl[PD];
 #pragma unroll
-    for (int k = 0; k < PD; ++k) {
-      q[k] = Slot<R>{0.0, 0.0, 0.0, 0.0, 0.0, R(0), R(0), R(0)};
-      fetch(q[k], k);
-    }
+    for (int k = 0; k < PD; ++k) fetch(sl[k], k);
     R fl = gx, hl = gx, fprev = R(0), hprev = R(0);
-    // steps of the band, rounded up to the unroll (the extra steps are idle)
-    const int T = ((nx + rows - 1 + PD - 1) / PD) * PD;
-    for (int t0 = 0; t0 < T; t0 += PD) {
-#pragma unroll
-      for (int k = 0; k < PD; ++k) {
-        const int t = t0 + k;
-        const int a = t - lane;
-        const bool on = rowok && a >= 0 && a < nx;
-        R fb = wave_shr1(fprev), hb = NF == 2 ? wave_shr1(hprev) : R(0);
-        if (lane == 0) {
-          fb = q[k].fb;
-          hb = q[k].hb;
+    R rin = gy, rinh = gy, rout = R(0), routh = R(0);
+    // steps of the band, rounded up to the chunk (the extra steps are idle)
+    const int T = ((nx + rows - 1 + CH - 1) / CH) * CH;
+    for (int t0 = 0; t0 < T; t0 += CH) {
+      if (has_in && t0 < nx) {  // row-0 inputs of columns t0 .. t0 + CH - 1
+        const int need = pin0 + min(t0 + CH, nx);
+        if (seen_prod < need) {
+          while ((seen_prod = lds_load(&prod[win])) < need) __builtin_amdgcn_s_sleep(1);
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         }
-        const int c = c0 + sx * a;
-        const R inv = rt_rcp((R)(q[k].ct + mxy));
+        if (lane < CH) {
+          rin = ring[win][(pin0 + t0 + lane) & (RING - 1)][0];
+          if (NF == 2) rinh = ring[win][(pin0 + t0 + lane) & (RING - 1)][NF - 1];
+        }
+        lds_publish(&cons[win], need, lane == 0);
+      }
+      const unsigned ob = sbase + (unsigned)t0 * BAND;
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const int t = t0 + k;
+        const bool on = rowok && (unsigned)(t - lane) < unx;
+        const Slot<R> &c = sl[k % PD];
+        const R fb = shr1_in(fprev, rdlane(rin, k));
+        const R hb = NF == 2 ? shr1_in(hprev, rdlane(rinh, k)) : R(0);
+        const R inv = rt_rcp((R)(c.ct + mxy));
         R f, h = R(0);
         PT v;
         if (MODE == 0) {
-          f = (q[k].s + my * fb + mx * fl) * inv;
+          f = (c.s + my * fb + mx * fl) * inv;
           v = (PT)(w * f);
         } else {
           if (MODE == 1) {
-            const R s1 = (R)(rt_fma(q[k].a1, q[k].a2, q[k].a3) + q[k].a4 * A.inv_dt);
+            const R s1 = (R)(c.a1 + c.a3 * A.inv_dt);
             f = (s1 + my * fb + mx * fl) * inv;
-            *(on ? fdir + c : dummy + lane) = (double)f;
+            fd[ob + k * BAND] = (double)f;
           } else {
-            f = (R)q[k].a4;
+            f = (R)c.a3;
           }
-          const R s2 = rt_fma(f, idt, (R)q[k].a3);
+          const R s2 = rt_fma(f, idt, (R)c.a2);
           h = (s2 + my * hb + mx * hl) * inv;
           v = (PT)(w * h);
         }
-        *(on ? part + c : (PT *)(dummy + 64) + lane) = v;
-        if (!on) {
-          f = R(0);
-          h = R(0);
-        } else {
-          fl = f;
-          hl = h;
-        }
+        part[ob + k * BAND] = v;
+        fl = on ? f : gx;
+        hl = on ? h : gx;
         fprev = f;
         hprev = h;
-        // the top row finished column t - (BAND - 1): hand it to the band above
-        const int ao = t - (BAND - 1);
-        if (has_out && ao >= 0 && ao < nx) {
-          const int pos = pout0 + ao;
-          if (seen_cons < pos - RING + 1) {
-            while ((seen_cons = lds_load(&cons[wout])) < pos - RING + 1) __builtin_amdgcn_s_sleep(1);
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (has_out) {
+          // the top row finished column ao = t - (BAND - 1)
+          const int ao = t - (BAND - 1);
+          rout = wrlane(rout, rdlane(f, BAND - 1), ao & (CH - 1));
+          if (NF == 2) routh = wrlane(routh, rdlane(h, BAND - 1), ao & (CH - 1));
+          if (k == (BAND - 1 + CH - 1) % CH) {  // ao closes a chunk
+            if (ao >= 0 && ao < nx) flush(ao - (CH - 1), CH, rout, routh);
+          } else if (ao == nx - 1) {
+            flush(ao & ~(CH - 1), (ao & (CH - 1)) + 1, rout, routh);
           }
-          if (lane == BAND - 1) {
-            ring[wout][pos & (RING - 1)][0] = f;
-            if (NF == 2) ring[wout][pos & (RING - 1)][NF - 1] = h;
-          }
-          if (((ao + 1) % PUB) == 0 || ao == nx - 1) lds_publish(&prod[wout], pos + 1, lane == BAND - 1);
         }
-        fetch(q[k], t + PD);
+        fetch(sl[k % PD], t + PD);
       }
     }
   }
 }
 
-// out[c] = sum over ordinates of partial[d][c] (+ add[c], or + out[c] when
+// Skew a per-cell quantity into the four quadrant layouts (padding slots 0):
+// KIND 0: x[c]; KIND 1: sigma_s[c] x[c]; KIND 2: sigma_s[c] x[c] + G[c].
+template <typename R, int KIND, typename X = double>
+__global__ void __launch_bounds__(BLK) k_skew(PlaneArgs A, const double *ss, const X *x, const double *G,
+                                              R *out) {
+  const int slot = blockIdx.x * BLK + threadIdx.x, q = blockIdx.y;
+  if (slot >= A.SQ) return;
+  const int c = slot_cell(A, q, slot);
+  double v = 0.0;
+  if (c >= 0) {
+    if (KIND == 0) v = (double)x[c];
+    if (KIND == 1) v = ss[c] * (double)x[c];
+    if (KIND == 2) v = rt_fma(ss[c], (double)x[c], G[c]);
+  }
+  out[(size_t)q * A.SQ + slot] = (R)v;
+}
+// f^0: the isotropic initial flux x on every folded ordinate
+__global__ void __launch_bounds__(BLK) k_skew_f(PlaneArgs A, const double *x) {
+  const int slot = blockIdx.x * BLK + threadIdx.x, dir = blockIdx.y;
+  if (slot >= A.SQ) return;
+  const int c = slot_cell(A, quad_of(dir, A), slot);
+  A.f[(size_t)dir * A.SQ + slot] = c >= 0 ? x[c] : 0.0;
+}
+
+// per-quadrant sums of the per-ordinate partials, ordinates in order
+template <typename PT>
+__global__ void __launch_bounds__(BLK) k_quad_sum(PlaneArgs A) {
+  const int slot = blockIdx.x * BLK + threadIdx.x, q = blockIdx.y;
+  if (slot >= A.SQ) return;
+  const PT *p = (const PT *)A.partial + slot;
+  double s = 0.0;
+  for (int d = A.qstart[q]; d < A.qstart[q + 1]; ++d) s += (double)p[(size_t)d * A.SQ];
+  A.quadsum[(size_t)q * A.SQ + slot] = s;
+}
+
+// out[c] = sum over the quadrants (in order) (+ add[c], or + out[c] when
 // accumulating); optional per-block maxima for the stop test of Alg. 1:
 // max|out - rp| and max|out|.
-template <typename PT>
-__global__ void __launch_bounds__(BLK) k_plane_reduce(PlaneArgs A, double *out, const double *add,
-                                                      int accumulate, const double *rp, double *blkmax) {
+__global__ void __launch_bounds__(BLK) k_unskew(PlaneArgs A, double *out, const double *add, int accumulate,
+                                                const double *rp, double *blkmax) {
   const int c = blockIdx.x * BLK + threadIdx.x;
   double d = 0.0, y = 0.0;
   if (c < A.nc) {
-    const PT *pp = (const PT *)A.partial + c;
+    const int ix = c % A.nx, iy = c / A.nx;
     double s = 0.0;
-    for (int g = 0; g < A.ndf; ++g) s += (double)pp[(size_t)g * A.nc];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s += A.quadsum[(size_t)q * A.SQ + cell_slot(A, q, ix, iy)];
     if (accumulate) s += out[c];
     else if (add) s += add[c];
     out[c] = s;
@@ -293,11 +361,6 @@ __global__ void __launch_bounds__(256) k_plane_maxreduce(const double *blkmax, i
 }
 
 // element-wise helpers ------------------------------------------------------
-// src = sigma_s * v (FP64)
-__global__ void k_plane_src64(int nc, const double *ss, const double *v, double *src) {
-  const int c = blockIdx.x * BLK + threadIdx.x;
-  if (c < nc) src[c] = ss[c] * v[c];
-}
 // rn = y + d; src32 = (float)(sigma_s (rn - rp)); rp = rn
 __global__ void k_plane_increment(int nc, const double *ss, const double *y, const double *d, double *rp,
                                   float *src32) {
@@ -339,31 +402,164 @@ __device__ __forceinline__ double dsa_Ax(const DsaArgs &D, const double *x, int 
   return v;
 }
 
-// Chebyshev start: r = rhs = sigma_s (y - rp), x = 0, d0 = r / (theta diag)
-__global__ void k_dsa_start(DsaArgs D, const double *ss, const double *y, const double *rp, double *r,
-                            double *x, double *d, double inv_theta) {
-  const int c = blockIdx.x * BLK + threadIdx.x;
-  if (c < D.nc) {
-    const double rhs = ss[c] * (y[c] - rp[c]);
-    r[c] = rhs;
-    x[c] = 0.0;
-    d[c] = inv_theta * rhs / D.diag[c];
+// Fused Chebyshev DSA solve (one cooperative launch per solve).  Tiles of
+// DT x DT cells, one workgroup of DTHR threads per tile (tiles beyond the
+// co-resident grid are taken in turn).  Every DS iterations the grid
+// synchronises once and each tile re-reads its neighbours' directions and
+// residuals over a halo of DS cells, then iterates DS times with the
+// directions in LDS and everything pointwise (residual, solution, operator
+// coefficients) in registers; the valid region shrinks by one cell per
+// iteration.  Each cell sees exactly the arithmetic of one global iteration,
+// so the result does not depend on the tiling.
+constexpr int DT = 32;               // interior tile edge
+constexpr int DS = 8;                // iterations per grid synchronisation (halo)
+constexpr int DE = DT + 2 * DS;      // extended tile edge
+constexpr int DTHR = 1024;           // threads per workgroup
+constexpr int DPT = (DE * DE + DTHR - 1) / DTHR;  // extended cells per thread
+
+struct DsaSolve {
+  DsaArgs D;
+  const double *ss, *y, *rp;
+  double *x;                      // solution, cell layout
+  double *r0, *r1, *d0, *d1;      // double-buffered residual / direction
+  const double *c1, *c2;          // Chebyshev coefficients per iteration
+  int K, ntx, ntiles, pad_;
+  double inv_theta;
+  unsigned long long *bar;        // [0]: arrivals, [1]: released generation
+  unsigned long long base;        // generations completed before this launch
+  int *fault;                     // set when a barrier wait gives up
+};
+
+// grid-wide barrier on a monotone arrival counter: generation g is released
+// when nblk * g arrivals have been counted.  The wait is bounded (a launch
+// that cannot make progress sets *fault and falls through instead of hanging).
+__device__ __forceinline__ void grid_sync(const DsaSolve &S, unsigned long long gen) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned long long nb = gridDim.x;
+    const unsigned long long prev =
+        __hip_atomic_fetch_add(&S.bar[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev + 1 == gen * nb) {
+      __hip_atomic_store(&S.bar[1], gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      unsigned spins = 0;
+      while (__hip_atomic_load(&S.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins == (1u << 26)) {
+          *S.fault = 1;
+          break;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
+  __syncthreads();
 }
-// one Chebyshev step: x += d; r -= A d; d' = c1 d + c2 r / diag
-__global__ void k_dsa_step(DsaArgs D, double *x, double *r, const double *d, double *dn, double c1, double c2) {
-  const int c = blockIdx.x * BLK + threadIdx.x;
-  if (c < D.nc) {
-    const double dc = d[c];
-    x[c] += dc;
-    const double rn = r[c] - dsa_Ax(D, d, c);
-    r[c] = rn;
-    dn[c] = c1 * dc + c2 * rn / D.diag[c];
+
+__global__ void __launch_bounds__(DTHR) k_dsa_cheb(DsaSolve S) {
+  __shared__ double sd[DE * DE];
+  const DsaArgs &D = S.D;
+  const int nx = D.nx, ny = D.ny;
+  unsigned long long gen = S.base;
+  // r = sigma_s (y - rp), x = 0, d = r / (theta diag)
+  for (int tile = blockIdx.x; tile < S.ntiles; tile += gridDim.x) {
+    const int tx = tile % S.ntx, ty = tile / S.ntx;
+    const int ix = tx * DT + (int)threadIdx.x % DT, iy = ty * DT + (int)threadIdx.x / DT;
+    if (ix < nx && iy < ny) {
+      const int c = iy * nx + ix;
+      const double rhs = S.ss[c] * (S.y[c] - S.rp[c]);
+      S.r0[c] = rhs;
+      S.x[c] = 0.0;
+      S.d0[c] = S.inv_theta * rhs / D.diag[c];
+    }
   }
-}
-__global__ void k_dsa_finish(int nc, double *x, const double *d) {
-  const int c = blockIdx.x * BLK + threadIdx.x;
-  if (c < nc) x[c] += d[c];
+  grid_sync(S, ++gen);
+  // per-thread cells of the extended tile and their (static) coefficients
+  double dg[DPT], ar[DPT], al[DPT], au[DPT], ad[DPT];
+  int loaded_tile = -1;
+  int done = 0, cur = 0;
+  while (done < S.K) {
+    const int nit = min(DS, S.K - done);
+    const bool last = done + nit >= S.K;
+    const double *din = cur ? S.d1 : S.d0, *rin = cur ? S.r1 : S.r0;
+    double *dout = cur ? S.d0 : S.d1, *rout = cur ? S.r0 : S.r1;
+    for (int tile = blockIdx.x; tile < S.ntiles; tile += gridDim.x) {
+      const int tx = tile % S.ntx, ty = tile / S.ntx;
+      const bool reload = tile != loaded_tile;
+      loaded_tile = tile;
+      double r[DPT], xr[DPT];
+#pragma unroll
+      for (int i = 0; i < DPT; ++i) {
+        const int e = threadIdx.x + DTHR * i;
+        const int ex = e % DE, ey = e / DE;
+        const int ix = tx * DT + ex - DS, iy = ty * DT + ey - DS;
+        const bool in = e < DE * DE && ix >= 0 && ix < nx && iy >= 0 && iy < ny;
+        const int c = in ? iy * nx + ix : 0;
+        if (reload) {
+          // links to out-of-grid neighbours are zero; those cells carry d = 0
+          dg[i] = in ? D.diag[c] : 1.0;
+          ar[i] = in ? D.ax[c] : 0.0;
+          au[i] = in ? D.ay[c] : 0.0;
+          al[i] = in && ix > 0 ? D.ax[c - 1] : 0.0;
+          ad[i] = in && iy > 0 ? D.ay[c - nx] : 0.0;
+        }
+        r[i] = in ? rin[c] : 0.0;
+        xr[i] = in && ex >= DS && ex < DS + DT && ey >= DS && ey < DS + DT ? S.x[c] : 0.0;
+        if (e < DE * DE) sd[e] = in ? din[c] : 0.0;
+      }
+      __syncthreads();
+      for (int it = 0; it < nit; ++it) {
+        const double c1 = S.c1[done + it], c2 = S.c2[done + it];
+        double dn[DPT];
+#pragma unroll
+        for (int i = 0; i < DPT; ++i) {
+          const int e = threadIdx.x + DTHR * i;
+          const int ex = e % DE, ey = e / DE;
+          dn[i] = 0.0;
+          if (e < DE * DE && ex > 0 && ex < DE - 1 && ey > 0 && ey < DE - 1) {
+            const double dc = sd[e];
+            xr[i] += dc;
+            double v = dg[i] * dc;
+            v -= ar[i] * sd[e + 1];
+            v -= al[i] * sd[e - 1];
+            v -= au[i] * sd[e + DE];
+            v -= ad[i] * sd[e - DE];
+            r[i] = r[i] - v;
+            dn[i] = c1 * dc + c2 * r[i] / dg[i];
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < DPT; ++i) {
+          const int e = threadIdx.x + DTHR * i;
+          const int ex = e % DE, ey = e / DE;
+          if (e < DE * DE && ex > 0 && ex < DE - 1 && ey > 0 && ey < DE - 1) sd[e] = dn[i];
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int i = 0; i < DPT; ++i) {
+        const int e = threadIdx.x + DTHR * i;
+        const int ex = e % DE, ey = e / DE;
+        const int ix = tx * DT + ex - DS, iy = ty * DT + ey - DS;
+        if (e < DE * DE && ex >= DS && ex < DS + DT && ey >= DS && ey < DS + DT && ix < nx && iy < ny) {
+          const int c = iy * nx + ix;
+          if (last) {
+            S.x[c] = xr[i] + sd[e];  // the closing update with the final direction
+          } else {
+            S.x[c] = xr[i];
+            dout[c] = sd[e];
+            rout[c] = r[i];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    done += nit;
+    cur ^= 1;
+    if (done < S.K) grid_sync(S, ++gen);
+  }
 }
 
 // setup: DSA coefficients (the same reading as the slab DSA, per face
@@ -473,47 +669,63 @@ struct PlaneHost {
   DsaArgs D;
   int ndf = 0;                    // folded ordinates (nv / 2)
   std::vector<int> fold_of;       // ordinate -> folded index
-  double *dmx = nullptr;          // device: mx, my, w
-  int *dsign = nullptr;           // device: sx, sy
-  double *partial = nullptr;
-  double *y = nullptr, *rp = nullptr, *src = nullptr, *dvec = nullptr;
+  std::vector<int> quad;          // folded index -> quadrant
+  char *mem = nullptr;            // one allocation for everything below
+  double *y = nullptr, *rp = nullptr, *dvec = nullptr;
   float *src32 = nullptr;
   double *cr = nullptr, *cx = nullptr, *cd0 = nullptr, *cd1 = nullptr;
   double *diag = nullptr, *ax = nullptr, *ay = nullptr;
-  double *fbuf = nullptr;
   double *blkmax = nullptr, *res = nullptr, *res_h = nullptr;
   double *rpart = nullptr, *rcoef = nullptr;
   int cheb_iters = 0;
   double cheb_theta = 1.0, cheb_delta = 0.0;
-  std::vector<double> cheb_c1, cheb_c2;
+  double *cheb_c = nullptr;                 // device: c1[K], c2[K]
+  unsigned long long *dsa_bar = nullptr;    // device barrier counters
+  unsigned long long dsa_gen = 0;           // barrier generations used so far
+  int dsa_grid = 1;                         // co-resident workgroups of the DSA solve
   size_t bytes = 0;
 };
 
-static size_t plane_bytes_for(const rtrom_problem_desc *d, int *ndf_out) {
-  const size_t nv = (size_t)d->n_polar * d->n_azim;
-  const int ndf = (int)(nv / 2);
-  const size_t nc = (size_t)d->nx * d->ny;
+namespace {
+struct PlaneGeom {
+  int ndf, nbands, TT, SQ;
+};
+PlaneGeom plane_geom(const rtrom_problem_desc *d) {
+  PlaneGeom g;
+  g.ndf = d->n_polar * d->n_azim / 2;
+  g.nbands = (d->ny + BAND - 1) / BAND;
+  // steps per band incl. the unroll round-up and the prefetch run-out
+  g.TT = ((d->nx + BAND - 1 + CH - 1) / CH) * CH + CH;
+  g.SQ = g.nbands * g.TT * BAND;
+  return g;
+}
+}  // namespace
+
+static size_t plane_bytes_for(const rtrom_problem_desc *d) {
+  const PlaneGeom g = plane_geom(d);
+  const size_t nc = (size_t)d->nx * d->ny, SQ = (size_t)g.SQ;
   const size_t nblk = (nc + BLK - 1) / BLK;
-  if (ndf_out) *ndf_out = ndf;
   size_t b = 0;
   auto take = [&](size_t x) { b += (x + 255) & ~size_t(255); };
-  take((size_t)ndf * nc * 8);                              // per-ordinate partials
-  take(nc * 8 * 8);                                        // y rp src dvec cr cx cd0 cd1
-  take(nc * 4);                                            // src32
-  take(nc * 8 * 3);                                        // diag ax ay
-  take(nblk * 2 * 8 + 64);                                 // blkmax, res
-  take(nblk * RT_NPART * 8 + RT_RMAX * 8);                 // rom apply partials, coef
-  take((size_t)ndf * 3 * 8 + (size_t)ndf * 2 * 4);         // mx my w, sx sy
-  take(128 * 8);                                           // idle-lane store target
+  take((size_t)g.ndf * SQ * 8);     // per-ordinate partials
+  take((size_t)g.ndf * SQ * 8);     // folded f
+  take(4 * SQ * 8 * 5);             // ctq, Gq, s1q, srcq, quadsum
+  take(nc * 8 * 7);                 // y rp dvec cr cx cd0 cd1
+  take(nc * 4);                     // src32
+  take(nc * 8 * 3);                 // diag ax ay
+  take(nblk * 2 * 8 + 64);          // blkmax, res, fault flag
+  take(2 * 2000 * 8 + 64);          // Chebyshev coefficients, barrier counters
+  take(nblk * RT_NPART * 8 + RT_RMAX * 8);  // DMD solve partials, coefficients
+  take((size_t)g.ndf * 3 * 8);      // mx my w
   return b;
 }
 
-size_t rt_plane_extra_bytes(const rtrom_problem_desc *d) { return plane_bytes_for(d, nullptr); }
+size_t rt_plane_extra_bytes(const rtrom_problem_desc *d) { return plane_bytes_for(d); }
 
 // Largest nx for grids with more bands than waves: the bands then cycle
-// through the waves, and the band-to-band rings (RING columns, consumers
-// publishing every CPUB) must drain before a wave moves to its next band.
-int rt_plane_max_nx_cyclic() { return MAXW * (RING - CPUB); }
+// through the waves, and the band-to-band rings (RING columns, moved CH at a
+// time) must drain before a wave moves to its next band.
+int rt_plane_max_nx_cyclic() { return MAXW * (RING - CH); }
 int rt_plane_needs_cyclic(int ny) { return (ny + BAND - 1) / BAND > MAXW; }
 
 #define PH(call)                                                            \
@@ -525,25 +737,22 @@ int rt_plane_needs_cyclic(int ny) { return (ny + BAND - 1) / BAND > MAXW; }
     }                                                                       \
   } while (0)
 
-template <typename PT>
-static void launch_reduce(rtrom_problem *p, PlaneHost *H, double *out, const double *add, int accumulate,
-                          const double *rp, double *blkmax) {
-  hipLaunchKernelGGL((k_plane_reduce<PT>), dim3(H->A.nblk), dim3(BLK), 0, p->stream, H->A, out, add, accumulate,
-                     rp, blkmax);
-}
-
-static int launch_sweep(rtrom_problem *p, PlaneHost *H, int mode, int fp32, const void *src, const double *rho) {
+// sweep + per-quadrant sums + un-skew into out
+static int sweep_moment(rtrom_problem *p, PlaneHost *H, int mode, int fp32, double *out, const double *add,
+                        int accumulate, const double *rp, double *blkmax) {
   PlaneArgs &A = H->A;
-  const dim3 grid(A.ndf), block(64 * A.nw);
   hipStream_t s = p->stream;
-  if (mode == 0 && fp32)
-    hipLaunchKernelGGL((k_plane_sweep<float, 0>), grid, block, 0, s, A, (const float *)src, rho);
-  else if (mode == 0)
-    hipLaunchKernelGGL((k_plane_sweep<double, 0>), grid, block, 0, s, A, (const double *)src, rho);
-  else if (mode == 1)
-    hipLaunchKernelGGL((k_plane_sweep<double, 1>), grid, block, 0, s, A, (const double *)nullptr, rho);
-  else
-    hipLaunchKernelGGL((k_plane_sweep<double, 2>), grid, block, 0, s, A, (const double *)nullptr, rho);
+  const dim3 grid(A.ndf), block(64 * A.nw), qgrid(A.nsblk, 4);
+  if (mode == 0 && fp32) {
+    hipLaunchKernelGGL((k_plane_sweep<float, 0, 8>), grid, block, 0, s, A);
+    hipLaunchKernelGGL(k_quad_sum<float>, qgrid, dim3(BLK), 0, s, A);
+  } else {
+    if (mode == 0) hipLaunchKernelGGL((k_plane_sweep<double, 0, 8>), grid, block, 0, s, A);
+    else if (mode == 1) hipLaunchKernelGGL((k_plane_sweep<double, 1, 4>), grid, block, 0, s, A);
+    else hipLaunchKernelGGL((k_plane_sweep<double, 2, 4>), grid, block, 0, s, A);
+    hipLaunchKernelGGL(k_quad_sum<double>, qgrid, dim3(BLK), 0, s, A);
+  }
+  hipLaunchKernelGGL(k_unskew, dim3(A.nblk), dim3(BLK), 0, s, A, out, add, accumulate, rp, blkmax);
   PH(hipGetLastError());
   return RTROM_OK;
 }
@@ -552,37 +761,46 @@ int rt_plane_create(rtrom_problem *p) {
   const rtrom_problem_desc *d = &p->d;
   PlaneHost *H = new PlaneHost();
   p->plane = H;
-  int ndf;
-  H->bytes = plane_bytes_for(d, &ndf);
+  const PlaneGeom g = plane_geom(d);
+  const int ndf = g.ndf;
+  H->bytes = plane_bytes_for(d);
   H->ndf = ndf;
   const int nx = d->nx, ny = d->ny, nc = nx * ny;
   const int nblk = (nc + BLK - 1) / BLK;
-  const int nbands = (ny + BAND - 1) / BAND;
-  if (nbands > MAXW && nx > rt_plane_max_nx_cyclic()) {
+  if (g.nbands > MAXW && nx > rt_plane_max_nx_cyclic()) {
     rt_set_error("plane: grids with more than 1024 rows are limited to nx <= 3840");
     return RTROM_EINVAL;
   }
-  // folded ordinates: the upper hemisphere (Omega_z > 0) in ordinate order;
-  // Omega_z < 0 ordinates map to their mirror at the same azimuth
+  // folded ordinates: the upper hemisphere (Omega_z > 0) grouped by upwind
+  // quadrant, ordinate order within a quadrant; Omega_z < 0 ordinates map to
+  // their mirror at the same azimuth
   const int nphi = d->n_azim, nz = d->n_polar;
   const double hx = d->lx / nx, hy = d->ly / ny;
   std::vector<double> hm(3 * (size_t)ndf, 0.0);
-  std::vector<int> hs(2 * (size_t)ndf, 1);
   H->fold_of.assign((size_t)nphi * nz, -1);
-  int nf = 0;
-  for (int j2 = 0; j2 < nz; ++j2)
-    for (int j1 = 0; j1 < nphi; ++j1) {
-      const int j = j2 * nphi + j1;
-      if (p->oz[j] > 0) {
-        const int idx = nf++;
-        hm[idx] = std::fabs(p->ox[j]) / hx;
-        hm[ndf + idx] = std::fabs(p->oy[j]) / hy;
-        hm[2 * (size_t)ndf + idx] = 2.0 * p->w[j];
-        hs[idx] = p->ox[j] > 0 ? 1 : -1;
-        hs[ndf + idx] = p->oy[j] > 0 ? 1 : -1;
-        H->fold_of[j] = idx;
+  H->quad.assign(ndf, 0);
+  int nf = 0, qstart[5] = {0, 0, 0, 0, 0};
+  for (int q = 0; q < 4; ++q) {
+    qstart[q] = nf;
+    for (int j2 = 0; j2 < nz; ++j2)
+      for (int j1 = 0; j1 < nphi; ++j1) {
+        const int j = j2 * nphi + j1;
+        const int qj = (p->ox[j] > 0 ? 0 : 1) + (p->oy[j] > 0 ? 0 : 2);
+        if (p->oz[j] > 0 && qj == q) {
+          if (nf >= ndf) {
+            rt_set_error("plane: quadrature is not symmetric in Omega_z");
+            return RTROM_EINVAL;
+          }
+          const int idx = nf++;
+          hm[idx] = std::fabs(p->ox[j]) / hx;
+          hm[ndf + idx] = std::fabs(p->oy[j]) / hy;
+          hm[2 * (size_t)ndf + idx] = 2.0 * p->w[j];
+          H->fold_of[j] = idx;
+          H->quad[idx] = q;
+        }
       }
-    }
+  }
+  qstart[4] = nf;
   if (nf != ndf) {
     rt_set_error("plane: quadrature is not symmetric in Omega_z");
     return RTROM_EINVAL;
@@ -593,21 +811,29 @@ int rt_plane_create(rtrom_problem *p) {
       if (p->oz[j] < 0) H->fold_of[j] = H->fold_of[(size_t)(nz - 1 - j2) * nphi + j1];
     }
   // device buffers
-  char *mem = nullptr;
-  PH(hipMalloc(&mem, H->bytes));
-  PH(hipMemsetAsync(mem, 0, H->bytes, p->stream));
+  PH(hipMalloc(&H->mem, H->bytes));
+  PH(hipMemsetAsync(H->mem, 0, H->bytes, p->stream));
   size_t off = 0;
   auto take = [&](size_t x) {
-    char *q = mem + off;
+    char *q = H->mem + off;
     off += (x + 255) & ~size_t(255);
     return q;
   };
-  H->partial = (double *)take((size_t)ndf * nc * 8);
-  char *vecs = take((size_t)nc * 8 * 8);
-  H->y = (double *)vecs;
+  const size_t SQ = (size_t)g.SQ;
+  PlaneArgs &A = H->A;
+  memset(&A, 0, sizeof(A));
+  A.partial = take((size_t)ndf * SQ * 8);
+  A.f = (double *)take((size_t)ndf * SQ * 8);
+  double *q5 = (double *)take(4 * SQ * 8 * 5);
+  A.ctq = q5;
+  A.Gq = q5 + 4 * SQ;
+  A.s1q = q5 + 8 * SQ;
+  A.srcq = q5 + 12 * SQ;
+  A.quadsum = q5 + 16 * SQ;
+  double *vecs = (double *)take((size_t)nc * 8 * 7);
+  H->y = vecs;
   H->rp = H->y + nc;
-  H->src = H->rp + nc;
-  H->dvec = H->src + nc;
+  H->dvec = H->rp + nc;
   H->cr = H->dvec + nc;
   H->cx = H->cr + nc;
   H->cd0 = H->cx + nc;
@@ -618,42 +844,38 @@ int rt_plane_create(rtrom_problem *p) {
   H->ay = H->ax + nc;
   H->blkmax = (double *)take((size_t)nblk * 2 * 8 + 64);
   H->res = H->blkmax + 2 * (size_t)nblk;
+  H->cheb_c = (double *)take(2 * 2000 * 8 + 64);
+  H->dsa_bar = (unsigned long long *)(H->cheb_c + 2 * 2000);
   H->rpart = (double *)take((size_t)nblk * RT_NPART * 8 + RT_RMAX * 8);
   H->rcoef = H->rpart + (size_t)nblk * RT_NPART;
-  H->dmx = (double *)take((size_t)ndf * 3 * 8 + (size_t)ndf * 2 * 4);
-  H->dsign = (int *)(H->dmx + 3 * (size_t)ndf);
-  double *dummy = (double *)take(128 * 8);
+  double *dmx = (double *)take((size_t)ndf * 3 * 8);
   Inst &I = p->hinst;
-  H->fbuf = I.f;  // f^n of the folded set lives in the first nv/2 ordinate slots
-  PH(hipMemcpyAsync(H->dmx, hm.data(), hm.size() * 8, hipMemcpyHostToDevice, p->stream));
-  PH(hipMemcpyAsync(H->dsign, hs.data(), hs.size() * 4, hipMemcpyHostToDevice, p->stream));
+  PH(hipMemcpyAsync(dmx, hm.data(), hm.size() * 8, hipMemcpyHostToDevice, p->stream));
   PH(hipHostMalloc((void **)&H->res_h, 64, hipHostMallocDefault));
-  PlaneArgs &A = H->A;
-  memset(&A, 0, sizeof(A));
   A.nx = nx;
   A.ny = ny;
   A.nc = nc;
   A.ndf = ndf;
-  A.nbands = nbands;
-  A.nw = std::min(nbands, MAXW);
+  A.nbands = g.nbands;
+  A.nw = std::min(g.nbands, MAXW);
   A.nblk = nblk;
+  A.TT = g.TT;
+  A.SQ = g.SQ;
+  A.nsblk = (g.SQ + BLK - 1) / BLK;
+  for (int k = 0; k < 5; ++k) A.qstart[k] = qstart[k];
   A.inv_dt = 1.0 / d->dt;
   for (int k = 0; k < 4; ++k) A.g[k] = d->inflow[k];
-  A.mx = H->dmx;
-  A.my = H->dmx + ndf;
-  A.w = H->dmx + 2 * (size_t)ndf;
-  A.sx = H->dsign;
-  A.sy = H->dsign + ndf;
-  A.ss = I.ss;
-  A.ct = I.ct;
-  A.G = I.G;
-  A.f = H->fbuf;
-  A.partial = H->partial;
-  A.dummy = dummy;
-  double *fbuf = H->fbuf;
-  // f^0 (isotropic) on every folded ordinate: rebuild from rho
-  for (int j = 0; j < ndf; ++j)
-    PH(hipMemcpyAsync(fbuf + (size_t)j * nc, I.rho, (size_t)nc * 8, hipMemcpyDeviceToDevice, p->stream));
+  A.mx = dmx;
+  A.my = dmx + ndf;
+  A.w = dmx + 2 * (size_t)ndf;
+  // static skewed inputs and f^0 (isotropic, from rho^0)
+  const dim3 qgrid(A.nsblk, 4);
+  hipLaunchKernelGGL((k_skew<double, 0>), qgrid, dim3(BLK), 0, p->stream, A, (const double *)nullptr, I.ct,
+                     (const double *)nullptr, (double *)A.ctq);
+  hipLaunchKernelGGL((k_skew<double, 0>), qgrid, dim3(BLK), 0, p->stream, A, (const double *)nullptr, I.G,
+                     (const double *)nullptr, (double *)A.Gq);
+  hipLaunchKernelGGL(k_skew_f, dim3(A.nsblk, ndf), dim3(BLK), 0, p->stream, A, (const double *)I.rho);
+  PH(hipGetLastError());
   // DSA setup and Chebyshev parameters
   H->D.nx = nx;
   H->D.ny = ny;
@@ -669,8 +891,8 @@ int rt_plane_create(rtrom_problem *p) {
   PH(hipStreamSynchronize(p->stream));
   double gmax = 0.0;
   for (double r : ratios) gmax = std::max(gmax, r);
-  // eigenvalues of diag^{-1} A lie in [1 - g, 1 + g] (Gershgorin, strict
-  // diagonal dominance because sigma_a + 1/dt > 0)
+  // eigenvalues of diag^{-1} A lie in [1 - g, 1 + g] (Gershgorin; strictly
+  // diagonally dominant because sigma_a + 1/dt > 0)
   const double lmin = std::max(1e-12, 1.0 - gmax), lmax = 1.0 + gmax;
   H->cheb_theta = 0.5 * (lmax + lmin);
   H->cheb_delta = 0.5 * (lmax - lmin);
@@ -682,15 +904,27 @@ int rt_plane_create(rtrom_problem *p) {
     K = std::max(1, std::min(K, 2000));
   }
   H->cheb_iters = K;
-  // coefficients of d_{k+1} = rho_{k+1} rho_k d_k + (2 rho_{k+1} / delta) diag^{-1} r_{k+1}
-  H->cheb_c1.assign(K, 0.0);
-  H->cheb_c2.assign(K, 0.0);
+  // d_{k+1} = rho_{k+1} rho_k d_k + (2 rho_{k+1} / delta) diag^{-1} r_{k+1}
+  std::vector<double> cc(2 * (size_t)K, 0.0);
   double rho_k = 1.0 / sigma1;
   for (int k = 0; k < K; ++k) {
     const double rho_n = 1.0 / (2.0 * sigma1 - rho_k);
-    H->cheb_c1[k] = rho_n * rho_k;
-    H->cheb_c2[k] = H->cheb_delta > 0.0 ? 2.0 * rho_n / H->cheb_delta : 0.0;
+    cc[k] = rho_n * rho_k;
+    cc[K + k] = H->cheb_delta > 0.0 ? 2.0 * rho_n / H->cheb_delta : 0.0;
     rho_k = rho_n;
+  }
+  PH(hipMemcpyAsync(H->cheb_c, cc.data(), cc.size() * 8, hipMemcpyHostToDevice, p->stream));
+  {
+    int coop = 0, ncu = 0, per_cu = 0;
+    PH(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, p->device));
+    if (!coop) {
+      rt_set_error("plane: the device does not support cooperative launches");
+      return RTROM_EDEVICE;
+    }
+    PH(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device));
+    PH(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(k_dsa_cheb), DTHR, 0));
+    const int ntiles = ((nx + DT - 1) / DT) * ((ny + DT - 1) / DT);
+    H->dsa_grid = std::max(1, std::min(ntiles, ncu * std::max(per_cu, 1)));
   }
   // b~^0 from f^0
   return rt_plane_rhs(p);
@@ -700,7 +934,7 @@ void rt_plane_destroy(rtrom_problem *p) {
   PlaneHost *H = (PlaneHost *)p->plane;
   if (!H) return;
   if (p->stream) (void)hipStreamSynchronize(p->stream);
-  if (H->partial) (void)hipFree(H->partial);
+  if (H->mem) (void)hipFree(H->mem);
   if (H->res_h) (void)hipHostFree(H->res_h);
   delete H;
   p->plane = nullptr;
@@ -709,28 +943,34 @@ void rt_plane_destroy(rtrom_problem *p) {
 int rt_plane_rhs(rtrom_problem *p) {
   PlaneHost *H = (PlaneHost *)p->plane;
   for (int k = 0; k < 4; ++k) H->A.g[k] = p->d.inflow[k];
-  const int nblk = H->A.nblk;
-  int e = launch_sweep(p, H, 2, 0, nullptr, p->hinst.rho);
-  if (e) return e;
-  launch_reduce<double>(p, H, p->hinst.bt2[p->steps & 1], nullptr, 0, nullptr, nullptr);
-  PH(hipGetLastError());
-  return RTROM_OK;
+  return sweep_moment(p, H, 2, 0, p->hinst.bt2[p->steps & 1], nullptr, 0, nullptr, nullptr);
 }
 
-static int dsa_solve(rtrom_problem *p, PlaneHost *H, const double *y, const double *rp, double *out) {
-  const int nblk = H->A.nblk, nc = H->A.nc;
-  hipStream_t s = p->stream;
-  hipLaunchKernelGGL(k_dsa_start, dim3(nblk), dim3(BLK), 0, s, H->D, p->hinst.ss, y, rp, H->cr, H->cx, H->cd0,
-                     1.0 / H->cheb_theta);
-  double *d0 = H->cd0, *d1 = H->cd1;
-  for (int k = 0; k < H->cheb_iters; ++k) {
-    hipLaunchKernelGGL(k_dsa_step, dim3(nblk), dim3(BLK), 0, s, H->D, H->cx, H->cr, (const double *)d0, d1,
-                       H->cheb_c1[k], H->cheb_c2[k]);
-    std::swap(d0, d1);
-  }
-  hipLaunchKernelGGL(k_dsa_finish, dim3(nblk), dim3(BLK), 0, s, nc, H->cx, (const double *)d0);
-  (void)out;
-  PH(hipGetLastError());
+static int dsa_solve(rtrom_problem *p, PlaneHost *H, const double *y, const double *rp) {
+  DsaSolve S;
+  memset(&S, 0, sizeof(S));
+  S.D = H->D;
+  S.ss = p->hinst.ss;
+  S.y = y;
+  S.rp = rp;
+  S.x = H->cx;
+  S.r0 = H->cr;
+  S.r1 = H->dvec;
+  S.d0 = H->cd0;
+  S.d1 = H->cd1;
+  S.K = H->cheb_iters;
+  S.c1 = H->cheb_c;
+  S.c2 = H->cheb_c + S.K;
+  S.ntx = (H->A.nx + DT - 1) / DT;
+  S.ntiles = S.ntx * ((H->A.ny + DT - 1) / DT);
+  S.inv_theta = 1.0 / H->cheb_theta;
+  S.bar = H->dsa_bar;
+  S.base = H->dsa_gen;
+  S.fault = (int *)(H->res + 2);
+  void *args[] = {&S};
+  PH(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_dsa_cheb), dim3(H->dsa_grid), dim3(DTHR), args, 0,
+                                p->stream));
+  H->dsa_gen += (unsigned long long)((S.K + DS - 1) / DS);  // barriers per solve
   return RTROM_OK;
 }
 
@@ -747,23 +987,32 @@ static int rom_apply_grid(rtrom_problem *p, PlaneHost *H, const RomDev &R, const
   return RTROM_OK;
 }
 
-// residual of the current y against rp: returns ||y - rp||_inf, ||y||_inf
+// residual of the current y against rp: ||y - rp||_inf, ||y||_inf
 static int read_residual(rtrom_problem *p, PlaneHost *H, double *dn, double *yn) {
   hipLaunchKernelGGL(k_plane_maxreduce, dim3(1), dim3(256), 0, p->stream, (const double *)H->blkmax, H->A.nblk,
                      H->res);
   PH(hipGetLastError());
-  PH(hipMemcpyAsync(H->res_h, H->res, 16, hipMemcpyDeviceToHost, p->stream));
+  PH(hipMemcpyAsync(H->res_h, H->res, 24, hipMemcpyDeviceToHost, p->stream));
   PH(hipStreamSynchronize(p->stream));
   *dn = H->res_h[0];
   *yn = H->res_h[1];
+  int fault;
+  memcpy(&fault, H->res_h + 2, sizeof(int));
+  if (fault) {
+    rt_set_error("plane: a DSA grid barrier timed out");
+    return RTROM_EDEVICE;
+  }
   return RTROM_OK;
 }
 
+// One backward-Euler step: Alg. 1 with the ROM hooks of Alg. 2 (initial guess
+// and first correction), the loop driven from the host on the residual norms.
 static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
   Inst &I = p->hinst;
-  const int nc = H->A.nc, nblk = H->A.nblk;
+  PlaneArgs &A = H->A;
+  const int nc = A.nc, nblk = A.nblk;
+  const dim3 qgrid(A.nsblk, 4);
   hipStream_t s = p->stream;
-  // state needed for this step's decisions
   RtState st;
   PH(hipMemcpyAsync(&st, I.st, sizeof(RtState), hipMemcpyDeviceToHost, s));
   PH(hipStreamSynchronize(s));
@@ -785,13 +1034,13 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
   int nsweep = 0, n32 = 0, conv = 0, used_pc = 0, pc_fb = 0, exact = 0, first_corr = 1, need64 = 1;
   double resid = 0.0;
   for (;;) {
-    if (need64) {
+    if (need64) {  // y = T (sigma_s rp) + b~ in FP64
       rt_prof_begin(RT_K_PLANE_SWEEP, s);
-      hipLaunchKernelGGL(k_plane_src64, dim3(nblk), dim3(BLK), 0, s, nc, I.ss, (const double *)H->rp, H->src);
-      int e = launch_sweep(p, H, 0, 0, H->src, nullptr);
-      if (e) return e;
-      launch_reduce<double>(p, H, H->y, bt, 0, H->rp, H->blkmax);
+      hipLaunchKernelGGL((k_skew<double, 1>), qgrid, dim3(BLK), 0, s, A, I.ss, (const double *)H->rp,
+                         (const double *)nullptr, (double *)A.srcq);
+      int e = sweep_moment(p, H, 0, 0, H->y, bt, 0, H->rp, H->blkmax);
       rt_prof_end(RT_K_PLANE_SWEEP, s);
+      if (e) return e;
       if (nsweep == 0)
         hipLaunchKernelGGL(k_plane_copy, dim3(nblk), dim3(BLK), 0, s, nc, (const double *)H->y, I.rhalf);
       nsweep++;
@@ -809,7 +1058,7 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
         break;
       }
       if (nsweep >= I.max_iter) break;
-      need64 = 1;
+      need64 = 1;  // certify the FP32-refined iterate with an FP64 sweep
       continue;
     }
     if (nsweep >= I.max_iter) break;
@@ -826,20 +1075,21 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
     } else if (I.method != RT_SI_PLAIN) {
       if (rom && first_corr && st.flag_pc) pc_fb = 1;
       rt_prof_begin(RT_K_PLANE_DSA, s);
-      e = dsa_solve(p, H, H->y, H->rp, nullptr);
+      e = dsa_solve(p, H, H->y, H->rp);
       rt_prof_end(RT_K_PLANE_DSA, s);
       if (e) return e;
       dcorr = H->cx;
     }
     first_corr = 0;
-    if (mixed) {
+    if (mixed) {  // y += T (sigma_s (rp_new - rp)) with the increment in FP32
       rt_prof_begin(RT_K_PLANE_SWEEP, s);
       hipLaunchKernelGGL(k_plane_increment, dim3(nblk), dim3(BLK), 0, s, nc, I.ss, (const double *)H->y, dcorr,
                          H->rp, H->src32);
-      e = launch_sweep(p, H, 0, 1, H->src32, nullptr);
-      if (e) return e;
-      launch_reduce<float>(p, H, H->y, nullptr, 1, H->rp, H->blkmax);
+      hipLaunchKernelGGL((k_skew<float, 0, float>), qgrid, dim3(BLK), 0, s, A, (const double *)nullptr,
+                         (const float *)H->src32, (const double *)nullptr, (float *)A.srcq);
+      e = sweep_moment(p, H, 0, 1, H->y, nullptr, 1, H->rp, H->blkmax);
       rt_prof_end(RT_K_PLANE_SWEEP, s);
+      if (e) return e;
       exact = 0;
       n32++;
       nsweep++;
@@ -866,13 +1116,10 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
     rt_prof_end(RT_K_ROM_UPDATE, s2);
   }
   rt_prof_begin(RT_K_PLANE_FPASS, s);
-  {
-    int e = launch_sweep(p, H, 1, 0, nullptr, I.rho);
-    if (e) return e;
-    launch_reduce<double>(p, H, I.bt2[cur ^ 1], nullptr, 0, nullptr, nullptr);
-    PH(hipGetLastError());
-  }
+  hipLaunchKernelGGL((k_skew<double, 2>), qgrid, dim3(BLK), 0, s, A, I.ss, (const double *)I.rho, I.G, A.s1q);
+  int e = sweep_moment(p, H, 1, 0, I.bt2[cur ^ 1], nullptr, 0, nullptr, nullptr);
   rt_prof_end(RT_K_PLANE_FPASS, s);
+  if (e) return e;
   if (s2 != s) {
     PH(hipEventRecord(p->ev_rom, s2));
     PH(hipStreamWaitEvent(s, p->ev_rom, 0));
@@ -889,13 +1136,24 @@ int rt_plane_step(rtrom_problem *p, int nsteps) {
   return RTROM_OK;
 }
 
-// folded f -> CL-ordered f for rtrom_get_angular_flux
+// folded, skewed f -> full ordinate order, cell layout (host)
 int rt_plane_unfold(const rtrom_problem *p, double *f_host) {
   const PlaneHost *H = (const PlaneHost *)p->plane;
-  const size_t nc = (size_t)p->nc;
-  std::vector<double> tmp((size_t)H->ndf * nc);
-  PH(hipMemcpyAsync(tmp.data(), H->fbuf, tmp.size() * 8, hipMemcpyDeviceToHost, p->stream));
+  const PlaneArgs &A = H->A;
+  const size_t nc = (size_t)p->nc, SQ = (size_t)A.SQ;
+  std::vector<double> tmp((size_t)H->ndf * SQ);
+  PH(hipMemcpyAsync(tmp.data(), A.f, tmp.size() * 8, hipMemcpyDeviceToHost, p->stream));
   PH(hipStreamSynchronize(p->stream));
-  for (int j = 0; j < p->nv; ++j) memcpy(f_host + (size_t)j * nc, tmp.data() + (size_t)H->fold_of[j] * nc, nc * 8);
+  for (int j = 0; j < p->nv; ++j) {
+    const int dir = H->fold_of[j], q = H->quad[dir];
+    const double *src = tmp.data() + (size_t)dir * SQ;
+    for (int iy = 0; iy < A.ny; ++iy)
+      for (int ix = 0; ix < A.nx; ++ix) {
+        const int u = (q & 2) ? A.ny - 1 - iy : iy;
+        const int a = (q & 1) ? A.nx - 1 - ix : ix;
+        const size_t slot = ((size_t)(u / BAND) * A.TT + a + (u % BAND)) * BAND + (u % BAND);
+        f_host[(size_t)j * nc + (size_t)iy * A.nx + ix] = src[slot];
+      }
+  }
   return RTROM_OK;
 }
