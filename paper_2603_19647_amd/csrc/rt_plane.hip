@@ -638,13 +638,8 @@ __global__ void __launch_bounds__(BLK) k_romapply_coef(RomDev R, const int *rank
 __global__ void __launch_bounds__(256) k_romapply_solve(RomDev R, const int *rankp, int nblk, const double *part,
                                                         double *coef) {
   const int rank = *rankp;
-  __shared__ double vec[RT_RMAX];
-  if ((int)threadIdx.x < rank) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[b * RT_NPART + threadIdx.x];
-    vec[threadIdx.x] = s;
-  }
-  __syncthreads();
+  __shared__ double vec[RT_RMAX], scratch[256];
+  sum_partials(part, nblk, rank, vec, scratch);
   lu_solve_wave(R.LU, R.perm, rank, vec);  // ends with a barrier
   if ((int)threadIdx.x < rank) coef[threadIdx.x] = vec[threadIdx.x];
 }

@@ -148,6 +148,31 @@ __device__ inline int lu_factor_wave(double *A, int *perm_lds, int n, double *LU
 // Solve A_r c = vec in place (vec in LDS) with the factors of lu_factor_wave,
 // by wave 0: lane i holds row i of the factors; forward and back
 // substitution broadcast one solved component per step.
+// out[k] = sum over blocks b < nb of part[b * RT_NPART + k], k < ncol.  The
+// blocks of a column are split into RT_SUMJ interleaved strands, each summed
+// in block order, and the strands are then added in order: a fixed order, so
+// the result is deterministic.  Needs blockDim.x a multiple of RT_SUMJ and
+// scratch of blockDim.x doubles in LDS; every thread must call; ends with a
+// barrier.
+constexpr int RT_SUMJ = 8;
+__device__ inline void sum_partials(const double *part, int nb, int ncol, double *out, double *scratch) {
+  const int tid = threadIdx.x, per = blockDim.x / RT_SUMJ;
+  for (int k0 = 0; k0 < ncol; k0 += per) {
+    const int k = k0 + tid % per, j = tid / per;
+    double s = 0.0;
+    if (k < ncol)
+      for (int b = j; b < nb; b += RT_SUMJ) s += part[b * RT_NPART + k];
+    scratch[tid] = s;
+    __syncthreads();
+    if (tid < per && k0 + tid < ncol) {
+      double t = 0.0;
+      for (int jj = 0; jj < RT_SUMJ; ++jj) t += scratch[jj * per + tid];
+      out[k0 + tid] = t;
+    }
+    __syncthreads();
+  }
+}
+
 __device__ inline void lu_solve_wave(const double *LU, const int *perm, int n, double *vec) {
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
@@ -344,20 +369,9 @@ __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, in
   RomPend *P = R.pend;
   // fixed-order block sums: pass 1 -> U^T x, U^T b, x.x, x.b; pass 2 -> a2, p1^T W;
   // pass 3 -> p.p, p.b
-  for (int e = tid; e < 2 * RT_RMAX + 2 + 2 * RT_RMAX + 2; e += NT) {
-    double s = 0.0;
-    if (e < 2 * RT_RMAX + 2) {
-      for (int k = 0; k < nb; ++k) s += Wk.part1[k * RT_NPART + e];
-    } else if (e < 4 * RT_RMAX + 2) {
-      const int j = e - (2 * RT_RMAX + 2);
-      for (int k = 0; k < nb; ++k) s += Wk.part2[k * RT_NPART + j];
-    } else {
-      const int j = e - (4 * RT_RMAX + 2);
-      for (int k = 0; k < nb; ++k) s += Wk.part3[k * RT_NPART + j];
-    }
-    sm.red[e] = s;
-  }
-  __syncthreads();
+  sum_partials(Wk.part1, nb, 2 * RT_RMAX + 2, sm.red, sm.red + 512);
+  sum_partials(Wk.part2, nb, 2 * RT_RMAX, sm.red + 2 * RT_RMAX + 2, sm.red + 512);
+  sum_partials(Wk.part3, nb, 2, sm.red + 4 * RT_RMAX + 2, sm.red + 512);
   const double xn = sqrt(sm.red[2 * RT_RMAX]);
   const double xb = sm.red[2 * RT_RMAX + 1];
   const double nu = sqrt(sm.red[4 * RT_RMAX + 2]);

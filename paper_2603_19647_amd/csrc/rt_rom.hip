@@ -12,14 +12,40 @@ __device__ __forceinline__ const RomDev &rom_of(const Inst &I, int z) { return z
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// k_rom_norms: per-block partial sums of ||rho^n||^2, ||rho^(0) - rho^n||^2
+// and ||dpc - (rho^n - rho^(1/2))||^2 for the error indicators of Sec. 3.2,
+// grid (blocks of BLK cells, instance).  Written to the IG ROM's third
+// partial buffer, which k_rom_pass3 reuses only after k_rom_decide.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(BLK) k_rom_norms(const Inst *__restrict__ insts) {
+  const Inst &I = insts[blockIdx.y];
+  if (I.method != RT_ROM || !I.st->flag_ig) return;
+  const int nb = (I.nc + BLK - 1) / BLK;
+  if ((int)blockIdx.x >= nb) return;
+  __shared__ double red[(BLK / 64) * 3], out[3];
+  const int c = blockIdx.x * BLK + threadIdx.x;
+  double part[3] = {0.0, 0.0, 0.0};
+  if (c < I.nc) {
+    const double r = I.rho[c];
+    part[0] = r * r;
+    const double e1 = I.rho0[c] - r;
+    part[1] = e1 * e1;
+    const double e2 = I.dpc[c] - (r - I.rhalf[c]);
+    part[2] = e2 * e2;
+  }
+  wg_sum_fast<3>(part, red, out);
+  if (threadIdx.x < 3) I.ig.work->part3[blockIdx.x * RT_NPART + threadIdx.x] = out[threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
 // k_rom_decide: step bookkeeping and, for the ROM method, the error
 // indicators (Sec. 3.2, normalised by ||rho^n||_2) and Alg. 2's decisions on
 // which ROM takes a snapshot this step.  One workgroup per instance.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_rom_decide(const Inst *__restrict__ insts) {
   const Inst &I = insts[blockIdx.x];
-  __shared__ double red[RT_MAXWAVES * 4], vec[4];
-  const int NT = blockDim.x, tid = threadIdx.x;
+  __shared__ double scratch[256], vec[4];
+  const int tid = threadIdx.x;
   const int nc = I.nc;
   RtState *st = I.st;
   const int iters = st->iters;
@@ -27,42 +53,23 @@ __global__ void __launch_bounds__(256) k_rom_decide(const Inst *__restrict__ ins
   double e_ig = -1.0, e_pc = -1.0;
   if (I.method == RT_ROM) {
     const int flag_ig = st->flag_ig, flag_pc = st->flag_pc, used_pc = st->used_pc;
-    {
-      double part[3] = {0.0, 0.0, 0.0};
-      for (int c = tid; c < nc; c += NT) {
-        const double r = I.rho[c];
-        part[0] = rt_fma(r, r, part[0]);
-        const double e1 = I.rho0[c] - r;
-        part[1] = rt_fma(e1, e1, part[1]);
-        const double e2 = I.dpc[c] - (r - I.rhalf[c]);
-        part[2] = rt_fma(e2, e2, part[2]);
-      }
-      wg_sum_fast<3>(part, red, vec);
-    }
-    const double rn = sqrt(vec[0]);
+    const int nb = (nc + BLK - 1) / BLK;
+    if (flag_ig) sum_partials(I.ig.work->part3, nb, 3, vec, scratch);
+    const double rn = flag_ig ? sqrt(vec[0]) : 0.0;
     const double scale = (I.abs_up || rn == 0.0) ? 1.0 : 1.0 / rn;
-    const double eig = sqrt(vec[1]) * scale, epc = sqrt(vec[2]) * scale;
     int ig_on = 0, ig_trunc = 0, pc_on = 0, pc_trunc = 0;
     if (!flag_ig) {
       ig_on = 1;  // phase 1: untruncated snapshot (rho^n, b~^{n-1})
     } else {
-      e_ig = eig;
+      e_ig = sqrt(vec[1]) * scale;
       ig_on = ig_trunc = e_ig > I.eps_up;
       if (iters > 1) {  // no correction snapshot when the step converged at l = 1
         if (!flag_pc) {
           pc_on = 1;
         } else {
-          if (used_pc) e_pc = epc;
+          if (used_pc) e_pc = sqrt(vec[2]) * scale;
           pc_on = pc_trunc = ig_on || !used_pc || e_pc > I.eps_up;
         }
-      }
-    }
-    if (pc_on) {  // correction snapshots (eq. correction_snapshot)
-      double *xs = I.work + 2 * (size_t)nc, *bs = I.work + 3 * (size_t)nc;
-      for (int c = tid; c < nc; c += NT) {
-        const double rh = I.rhalf[c];
-        xs[c] = I.rho[c] - rh;
-        bs[c] = rh - I.rho0[c];
       }
     }
     if (tid == 0) {
@@ -70,7 +77,7 @@ __global__ void __launch_bounds__(256) k_rom_decide(const Inst *__restrict__ ins
       wi.active = ig_on;
       wi.truncate = ig_trunc;
       wi.r = st->rank_ig;
-      wi.nblk = (nc + BLK - 1) / BLK;
+      wi.nblk = nb;
       wi.step_no = step_no;
       wi.eps = I.eps_ig;
       wi.x = I.rho;
@@ -80,9 +87,10 @@ __global__ void __launch_bounds__(256) k_rom_decide(const Inst *__restrict__ ins
       wp.active = pc_on;
       wp.truncate = pc_trunc;
       wp.r = st->rank_pc;
-      wp.nblk = (nc + BLK - 1) / BLK;
+      wp.nblk = nb;
       wp.step_no = step_no;
       wp.eps = I.eps_pc;
+      // correction snapshots (eq. correction_snapshot), formed by k_rom_pass1
       wp.x = I.work + 2 * (size_t)nc;
       wp.b = I.work + 3 * (size_t)nc;
       wp.p = I.work + nc;
@@ -131,7 +139,17 @@ __global__ void __launch_bounds__(BLK) k_rom_pass1(const Inst *__restrict__ inst
 #pragma unroll
   for (int k = 0; k < 2 * RT_RMAX + 2; ++k) part[k] = 0.0;
   if (c < I.nc) {
-    const double xv = W.x[c], bv = W.b[c];
+    double xv, bv;
+    if (blockIdx.z == 1) {  // x = rho^n - rho^(1/2), b = rho^(1/2) - rho^(0)
+      const double rh = I.rhalf[c];
+      xv = I.rho[c] - rh;
+      bv = rh - I.rho0[c];
+      const_cast<double *>(W.x)[c] = xv;  // the PC ROM's x, b live in the work arrays
+      const_cast<double *>(W.b)[c] = bv;
+    } else {
+      xv = W.x[c];
+      bv = W.b[c];
+    }
     part[2 * RT_RMAX] = xv * xv;
     part[2 * RT_RMAX + 1] = xv * bv;
 #pragma unroll
@@ -152,14 +170,9 @@ __global__ void __launch_bounds__(BLK) k_rom_pass2(const Inst *__restrict__ inst
   const RomDev &R = rom_of(I, blockIdx.z);
   const RomWork &W = *R.work;
   if (!W.active || (int)blockIdx.x >= W.nblk) return;
-  __shared__ double red[(BLK / 64) * 2 * RT_RMAX], out[2 * RT_RMAX], av[RT_RMAX];
+  __shared__ double red[(BLK / 64) * 2 * RT_RMAX], out[2 * RT_RMAX], av[RT_RMAX], scratch[BLK];
   const int r = W.r, ld = I.ld, c = blockIdx.x * BLK + threadIdx.x;
-  if ((int)threadIdx.x < r) {
-    double s = 0.0;
-    for (int k = 0; k < W.nblk; ++k) s += W.part1[k * RT_NPART + threadIdx.x];
-    av[threadIdx.x] = s;
-  }
-  __syncthreads();
+  sum_partials(W.part1, W.nblk, r, av, scratch);
   double part[2 * RT_RMAX];
 #pragma unroll
   for (int k = 0; k < 2 * RT_RMAX; ++k) part[k] = 0.0;
@@ -184,14 +197,9 @@ __global__ void __launch_bounds__(BLK) k_rom_pass3(const Inst *__restrict__ inst
   const RomDev &R = rom_of(I, blockIdx.z);
   const RomWork &W = *R.work;
   if (!W.active || (int)blockIdx.x >= W.nblk) return;
-  __shared__ double red[(BLK / 64) * 2], out[2], a2[RT_RMAX];
+  __shared__ double red[(BLK / 64) * 2], out[2], a2[RT_RMAX], scratch[BLK];
   const int r = W.r, ld = I.ld, c = blockIdx.x * BLK + threadIdx.x;
-  if ((int)threadIdx.x < r) {
-    double s = 0.0;
-    for (int k = 0; k < W.nblk; ++k) s += W.part2[k * RT_NPART + threadIdx.x];
-    a2[threadIdx.x] = s;
-  }
-  __syncthreads();
+  sum_partials(W.part2, W.nblk, r, a2, scratch);
   double part[2] = {0.0, 0.0};
   if (c < I.nc) {
     double v = W.p[c];
@@ -293,9 +301,10 @@ __global__ void __launch_bounds__(256) k_rom_update(const Inst *__restrict__ ins
 }
 
 extern "C" hipError_t rt_launch_rom(const Inst *dinsts, int ninst, int nc_max, int any_rom, hipStream_t s) {
+  const int nb = (nc_max + BLK - 1) / BLK;
+  if (any_rom) hipLaunchKernelGGL(k_rom_norms, dim3(nb, ninst), dim3(BLK), 0, s, dinsts);
   hipLaunchKernelGGL(k_rom_decide, dim3(ninst), dim3(256), 0, s, dinsts);
   if (any_rom) {
-    const int nb = (nc_max + BLK - 1) / BLK;
     hipLaunchKernelGGL(k_rom_pass1, dim3(nb, ninst, 2), dim3(BLK), 0, s, dinsts);
     hipLaunchKernelGGL(k_rom_pass2, dim3(nb, ninst, 2), dim3(BLK), 0, s, dinsts);
     hipLaunchKernelGGL(k_rom_pass3, dim3(nb, ninst, 2), dim3(BLK), 0, s, dinsts);
