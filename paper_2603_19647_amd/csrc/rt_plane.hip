@@ -50,6 +50,7 @@ struct PlaneArgs {
   double g[4];
   const double *mx, *my, *w;  // per folded ordinate
   const double *ctq, *Gq;     // [4][SQ] sigma~_t, G (skewed)
+  const float *ctf;           // [4][SQ] sigma~_t in FP32 (skewed)
   double *s1q;                // [4][SQ] sigma_s rho^n + G (skewed, f-pass)
   void *srcq;                 // [4][SQ] SI sweep source (skewed, sweep type)
   double *f;                  // [ndf][SQ] folded f, skewed in its quadrant
@@ -88,19 +89,21 @@ __device__ __forceinline__ float shr1_in(float v, float in0) {
   return __int_as_float(
       __builtin_amdgcn_update_dpp(__float_as_int(in0), __float_as_int(v), 0x138, 0xf, 0xf, false));
 }
-__device__ __forceinline__ double rdlane(double v, int l) {
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
-                          __builtin_amdgcn_readlane(__double2loint(v), l));
+// wave rotations: rol1 -- lane i gets lane i+1 (lane 63 gets lane 0);
+// ror1 -- lane i gets lane i-1 (lane 0 gets lane 63)
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  return __hiloint2double(__builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true),
+                          __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true));
 }
-__device__ __forceinline__ float rdlane(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
 }
-// lane l of acc takes the wave-uniform value s
 template <typename R>
-__device__ __forceinline__ R wrlane(R acc, R s, int l) {
-  return ((int)(threadIdx.x & 63) == l) ? s : acc;
-}
-
+__device__ __forceinline__ R rol1(R v) { return dpp_mov<0x134>(v); }
+template <typename R>
+__device__ __forceinline__ R ror1(R v) { return dpp_mov<0x13C>(v); }
 __device__ __forceinline__ int lds_load(int *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -112,8 +115,9 @@ __device__ __forceinline__ void lds_publish(int *p, int v, bool writer) {
 // per-step prefetched cell data
 template <typename R>
 struct Slot {
-  double ct, a1, a2, a3;  // sigma~_t and the mode's other per-cell inputs
-  R s;                    // MODE 0 source
+  R ct;               // sigma~_t
+  double a1, a2, a3;  // the mode's other per-cell inputs
+  R s;                // MODE 0 source
 };
 
 // MODE 0: SI sweep of the source srcq (zero inflow) -> per-ordinate w f.
@@ -149,6 +153,8 @@ __global__ void __launch_bounds__(1024) k_plane_sweep(PlaneArgs A) {
   const R gy = MODE == 0 ? R(0) : (R)((q & 2) ? A.g[3] : A.g[2]);
   const size_t qoff = (size_t)q * A.SQ, doff = (size_t)dir * A.SQ;
   const double *ctq = A.ctq + qoff, *Gq = A.Gq + qoff, *s1q = A.s1q + qoff;
+  const float *ctf = A.ctf + qoff;
+  const R mxyr = (R)mxy;
   const R *srcq = (const R *)A.srcq + qoff;
   double *fd = A.f + doff;
   PT *part = (PT *)A.partial + doff;
@@ -161,32 +167,39 @@ __global__ void __launch_bounds__(1024) k_plane_sweep(PlaneArgs A) {
     const bool has_in = band > 0, has_out = band + 1 < A.nbands;
     const int pin0 = ((band - 1) / NW) * nx;   // ring positions of the band below
     const int pout0 = (band / NW) * nx;        // ring positions of this band
-    const unsigned sbase = (unsigned)band * A.TT * BAND + lane;  // slot of step 0
+    const int sbase = band * A.TT * BAND + lane;  // slot of step 0
 
+    // per-lane pointers at step 0 of the band; step t is t * BAND further
+    const R *srcb = srcq + sbase;
+    const R *ctb = std::is_same<R, float>::value ? (const R *)(ctf + sbase) : (const R *)(ctq + sbase);
+    const double *s1b = s1q + sbase, *Gb = Gq + sbase;
+    double *fb0 = fd + sbase;
+    PT *pb0 = part + sbase;
     auto fetch = [&](Slot<R> &sl, int t) {
-      const unsigned o = sbase + (unsigned)t * BAND;
-      sl.ct = ctq[o];
-      if (MODE == 0) sl.s = srcq[o];
+      const int o = t * BAND;
+      sl.ct = ctb[o];
+      if (MODE == 0) sl.s = srcb[o];
       if (MODE == 1) {
-        sl.a1 = s1q[o];
-        sl.a2 = Gq[o];
-        sl.a3 = fd[o];
+        sl.a1 = s1b[o];
+        sl.a2 = Gb[o];
+        sl.a3 = fb0[o];
       }
       if (MODE == 2) {
-        sl.a2 = Gq[o];
-        sl.a3 = fd[o];
+        sl.a2 = Gb[o];
+        sl.a3 = fb0[o];
       }
     };
-    // hand columns [base, base + cnt) of the top row to the band above
-    auto flush = [&](int base, int cnt, R rout, R routh) {
-      const int pend = pout0 + base + cnt;
+    // hand the top row's columns (last - cnt, last] to the band above; lane i
+    // of rout holds column last - i
+    auto flush = [&](int last, int cnt, R rout, R routh) {
+      const int pend = pout0 + last + 1;
       if (seen_cons < pend - RING) {
         while ((seen_cons = lds_load(&cons[wout])) < pend - RING) __builtin_amdgcn_s_sleep(1);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
       }
       if (lane < cnt) {
-        ring[wout][(pout0 + base + lane) & (RING - 1)][0] = rout;
-        if (NF == 2) ring[wout][(pout0 + base + lane) & (RING - 1)][NF - 1] = routh;
+        ring[wout][(pout0 + last - lane) & (RING - 1)][0] = rout;
+        if (NF == 2) ring[wout][(pout0 + last - lane) & (RING - 1)][NF - 1] = routh;
       }
       lds_publish(&prod[wout], pend, lane == 0);
     };
@@ -211,49 +224,75 @@ __global__ void __launch_bounds__(1024) k_plane_sweep(PlaneArgs A) {
         }
         lds_publish(&cons[win], need, lane == 0);
       }
-      const unsigned ob = sbase + (unsigned)t0 * BAND;
+      // chunk-local pointers: the unrolled steps use constant offsets
+      const R *srcc = srcb + t0 * BAND, *ctc = ctb + t0 * BAND;
+      const double *s1c = s1b + t0 * BAND, *Gc = Gb + t0 * BAND;
+      double *fc = fb0 + t0 * BAND;
+      PT *pc = pb0 + t0 * BAND;
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
         const int t = t0 + k;
-        const bool on = rowok && (unsigned)(t - lane) < unx;
         const Slot<R> &c = sl[k % PD];
-        const R fb = shr1_in(fprev, rdlane(rin, k));
-        const R hb = NF == 2 ? shr1_in(hprev, rdlane(rinh, k)) : R(0);
-        const R inv = rt_rcp((R)(c.ct + mxy));
+        // lane 0 takes the band below's value of column t from rin, which
+        // rotates down one lane per step
+        const R fb = shr1_in(fprev, rin);
+        const R hb = NF == 2 ? shr1_in(hprev, rinh) : R(0);
+        rin = rol1(rin);
+        if (NF == 2) rinh = rol1(rinh);
+        const R inv = rt_rcp(c.ct + mxyr);
         R f, h = R(0);
         PT v;
         if (MODE == 0) {
+          // zero source in the padding keeps lanes that have not reached
+          // column 0 at exactly zero, which is the zero inflow
           f = (c.s + my * fb + mx * fl) * inv;
           v = (PT)(w * f);
+          fl = f;
         } else {
+          const bool on = rowok && (unsigned)(t - lane) < unx;
           if (MODE == 1) {
             const R s1 = (R)(c.a1 + c.a3 * A.inv_dt);
             f = (s1 + my * fb + mx * fl) * inv;
-            fd[ob + k * BAND] = (double)f;
+            fc[k * BAND] = (double)f;
           } else {
             f = (R)c.a3;
           }
           const R s2 = rt_fma(f, idt, (R)c.a2);
           h = (s2 + my * hb + mx * hl) * inv;
           v = (PT)(w * h);
+          fl = on ? f : gx;
+          hl = on ? h : gx;
         }
-        part[ob + k * BAND] = v;
-        fl = on ? f : gx;
-        hl = on ? h : gx;
+        pc[k * BAND] = v;
         fprev = f;
         hprev = h;
         if (has_out) {
-          // the top row finished column ao = t - (BAND - 1)
+          // the top row finished column ao = t - (BAND - 1); it enters rout at
+          // lane 0 while older columns move up one lane
           const int ao = t - (BAND - 1);
-          rout = wrlane(rout, rdlane(f, BAND - 1), ao & (CH - 1));
-          if (NF == 2) routh = wrlane(routh, rdlane(h, BAND - 1), ao & (CH - 1));
+          rout = ror1(lane == BAND - 1 ? f : rout);
+          if (NF == 2) routh = ror1(lane == BAND - 1 ? h : routh);
           if (k == (BAND - 1 + CH - 1) % CH) {  // ao closes a chunk
-            if (ao >= 0 && ao < nx) flush(ao - (CH - 1), CH, rout, routh);
+            if (ao >= 0 && ao < nx) flush(ao, CH, rout, routh);
           } else if (ao == nx - 1) {
-            flush(ao & ~(CH - 1), (ao & (CH - 1)) + 1, rout, routh);
+            flush(ao, (ao & (CH - 1)) + 1, rout, routh);
           }
         }
-        fetch(sl[k % PD], t + PD);
+        {  // prefetch step t + PD
+          Slot<R> &n = sl[k % PD];
+          const int o = (k + PD) * BAND;
+          n.ct = ctc[o];
+          if (MODE == 0) n.s = srcc[o];
+          if (MODE == 1) {
+            n.a1 = s1c[o];
+            n.a2 = Gc[o];
+            n.a3 = fc[o];
+          }
+          if (MODE == 2) {
+            n.a2 = Gc[o];
+            n.a3 = fc[o];
+          }
+        }
       }
     }
   }
@@ -705,6 +744,7 @@ static size_t plane_bytes_for(const rtrom_problem_desc *d) {
   take((size_t)g.ndf * SQ * 8);     // per-ordinate partials
   take((size_t)g.ndf * SQ * 8);     // folded f
   take(4 * SQ * 8 * 5);             // ctq, Gq, s1q, srcq, quadsum
+  take(4 * SQ * 4);                 // ctf
   take(nc * 8 * 7);                 // y rp dvec cr cx cd0 cd1
   take(nc * 4);                     // src32
   take(nc * 8 * 3);                 // diag ax ay
@@ -825,6 +865,7 @@ int rt_plane_create(rtrom_problem *p) {
   A.s1q = q5 + 8 * SQ;
   A.srcq = q5 + 12 * SQ;
   A.quadsum = q5 + 16 * SQ;
+  A.ctf = (const float *)take(4 * SQ * 4);
   double *vecs = (double *)take((size_t)nc * 8 * 7);
   H->y = vecs;
   H->rp = H->y + nc;
@@ -869,6 +910,8 @@ int rt_plane_create(rtrom_problem *p) {
                      (const double *)nullptr, (double *)A.ctq);
   hipLaunchKernelGGL((k_skew<double, 0>), qgrid, dim3(BLK), 0, p->stream, A, (const double *)nullptr, I.G,
                      (const double *)nullptr, (double *)A.Gq);
+  hipLaunchKernelGGL((k_skew<float, 0>), qgrid, dim3(BLK), 0, p->stream, A, (const double *)nullptr, I.ct,
+                     (const double *)nullptr, (float *)A.ctf);
   hipLaunchKernelGGL(k_skew_f, dim3(A.nsblk, ndf), dim3(BLK), 0, p->stream, A, (const double *)I.rho);
   PH(hipGetLastError());
   // DSA setup and Chebyshev parameters
