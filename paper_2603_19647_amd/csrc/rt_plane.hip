@@ -469,13 +469,24 @@ struct DsaSolve {
   int *fault;                     // set when a barrier wait gives up
 };
 
+// Directions and residuals cross tile boundaries only through agent-scope
+// relaxed atomic loads and stores, which are coherent across the chip's L2
+// slices; the barrier then needs no cache write-back or invalidation, only
+// the completion of this wave's stores before it arrives.
+__device__ __forceinline__ double xload(const double *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void xstore(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // grid-wide barrier on a monotone arrival counter: generation g is released
 // when nblk * g arrivals have been counted.  The wait is bounded (a launch
 // that cannot make progress sets *fault and falls through instead of hanging).
 __device__ __forceinline__ void grid_sync(const DsaSolve &S, unsigned long long gen) {
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's exchanged stores completed
   __syncthreads();
   if (threadIdx.x == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const unsigned long long nb = gridDim.x;
     const unsigned long long prev =
         __hip_atomic_fetch_add(&S.bar[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -484,14 +495,13 @@ __device__ __forceinline__ void grid_sync(const DsaSolve &S, unsigned long long 
     } else {
       unsigned spins = 0;
       while (__hip_atomic_load(&S.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(1);
         if (++spins == (1u << 26)) {
           *S.fault = 1;
           break;
         }
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
 }
@@ -508,9 +518,9 @@ __global__ void __launch_bounds__(DTHR) k_dsa_cheb(DsaSolve S) {
     if (ix < nx && iy < ny) {
       const int c = iy * nx + ix;
       const double rhs = S.ss[c] * (S.y[c] - S.rp[c]);
-      S.r0[c] = rhs;
+      xstore(S.r0 + c, rhs);
       S.x[c] = 0.0;
-      S.d0[c] = S.inv_theta * rhs / D.diag[c];
+      xstore(S.d0 + c, S.inv_theta * rhs / D.diag[c]);
     }
   }
   grid_sync(S, ++gen);
@@ -543,9 +553,9 @@ __global__ void __launch_bounds__(DTHR) k_dsa_cheb(DsaSolve S) {
           al[i] = in && ix > 0 ? D.ax[c - 1] : 0.0;
           ad[i] = in && iy > 0 ? D.ay[c - nx] : 0.0;
         }
-        r[i] = in ? rin[c] : 0.0;
+        r[i] = in ? xload(rin + c) : 0.0;
         xr[i] = in && ex >= DS && ex < DS + DT && ey >= DS && ey < DS + DT ? S.x[c] : 0.0;
-        if (e < DE * DE) sd[e] = in ? din[c] : 0.0;
+        if (e < DE * DE) sd[e] = in ? xload(din + c) : 0.0;
       }
       __syncthreads();
       for (int it = 0; it < nit; ++it) {
@@ -588,8 +598,8 @@ __global__ void __launch_bounds__(DTHR) k_dsa_cheb(DsaSolve S) {
             S.x[c] = xr[i] + sd[e];  // the closing update with the final direction
           } else {
             S.x[c] = xr[i];
-            dout[c] = sd[e];
-            rout[c] = r[i];
+            xstore(dout + c, sd[e]);
+            xstore(rout + c, r[i]);
           }
         }
       }
