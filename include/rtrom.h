@@ -106,6 +106,10 @@ typedef struct {
   int64_t fp32_sweeps;        /* mixed mode: SI sweeps done in FP32 */
   double last_residual;       /* ||y - rho||_inf / ||y||_inf of the last step */
   double t_total_s;           /* device time of all march/step calls (events) */
+  int32_t dsa_iters;          /* 2D: Chebyshev iterations per DSA solve (fixed
+                                 by the operator's Gershgorin bounds for a
+                                 1e-14 error bound); 1D: 0 (direct solve) */
+  int32_t reserved_;
 } rtrom_stats;
 
 /* Per-step record (rtrom_get_history). */

@@ -689,6 +689,7 @@ extern "C" rtrom_status rtrom_stats_get(const rtrom_problem *p, rtrom_stats *out
   out->fp32_sweeps = st.fp32_sweeps;
   out->last_residual = st.residual;
   out->t_total_s = p->t_total;
+  out->dsa_iters = p->d.dim == 2 ? rt_plane_dsa_iters(p) : 0;
   return RTROM_OK;
 }
 

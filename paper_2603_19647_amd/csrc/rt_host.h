@@ -48,6 +48,7 @@ int rt_plane_step(rtrom_problem *p, int nsteps);
 int rt_plane_rhs(rtrom_problem *p);
 size_t rt_plane_extra_bytes(const rtrom_problem_desc *d);
 int rt_plane_max_nx_cyclic();
+int rt_plane_dsa_iters(const rtrom_problem *p);
 int rt_plane_needs_cyclic(int ny);
 int rt_plane_unfold(const rtrom_problem *p, double *f_host);  // folded f -> full ordinate order
 

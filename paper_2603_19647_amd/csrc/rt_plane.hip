@@ -697,8 +697,13 @@ __global__ void __launch_bounds__(BLK) k_romapply_expand(RomDev R, const int *ra
   const int rank = *rankp;
   const int c = blockIdx.x * BLK + threadIdx.x;
   if (c < nc) {
+    double u[RT_RMAX];
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k) u[k] = k < rank ? R.U[(size_t)k * ld + c] : 0.0;
     double v = 0.0;
-    for (int k = 0; k < rank; ++k) v = rt_fma(R.U[(size_t)k * ld + c], coef[k], v);
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k)
+      if (k < rank) v = rt_fma(u[k], coef[k], v);
     out[c] = v;
   }
 }
@@ -788,16 +793,18 @@ static int sweep_moment(rtrom_problem *p, PlaneHost *H, int mode, int fp32, doub
   PlaneArgs &A = H->A;
   hipStream_t s = p->stream;
   const dim3 grid(A.ndf), block(64 * A.nw), qgrid(A.nsblk, 4);
-  if (mode == 0 && fp32) {
-    hipLaunchKernelGGL((k_plane_sweep<float, 0, 8>), grid, block, 0, s, A);
-    hipLaunchKernelGGL(k_quad_sum<float>, qgrid, dim3(BLK), 0, s, A);
-  } else {
-    if (mode == 0) hipLaunchKernelGGL((k_plane_sweep<double, 0, 8>), grid, block, 0, s, A);
-    else if (mode == 1) hipLaunchKernelGGL((k_plane_sweep<double, 1, 4>), grid, block, 0, s, A);
-    else hipLaunchKernelGGL((k_plane_sweep<double, 2, 4>), grid, block, 0, s, A);
-    hipLaunchKernelGGL(k_quad_sum<double>, qgrid, dim3(BLK), 0, s, A);
-  }
+  const int kind = mode == 0 ? RT_K_PLANE_SWEEP : RT_K_PLANE_FPASS;
+  rt_prof_begin(kind, s);
+  if (mode == 0 && fp32) hipLaunchKernelGGL((k_plane_sweep<float, 0, 8>), grid, block, 0, s, A);
+  else if (mode == 0) hipLaunchKernelGGL((k_plane_sweep<double, 0, 8>), grid, block, 0, s, A);
+  else if (mode == 1) hipLaunchKernelGGL((k_plane_sweep<double, 1, 4>), grid, block, 0, s, A);
+  else hipLaunchKernelGGL((k_plane_sweep<double, 2, 4>), grid, block, 0, s, A);
+  rt_prof_end(kind, s);
+  rt_prof_begin(RT_K_PLANE_OTHER, s);
+  if (mode == 0 && fp32) hipLaunchKernelGGL(k_quad_sum<float>, qgrid, dim3(BLK), 0, s, A);
+  else hipLaunchKernelGGL(k_quad_sum<double>, qgrid, dim3(BLK), 0, s, A);
   hipLaunchKernelGGL(k_unskew, dim3(A.nblk), dim3(BLK), 0, s, A, out, add, accumulate, rp, blkmax);
+  rt_prof_end(RT_K_PLANE_OTHER, s);
   PH(hipGetLastError());
   return RTROM_OK;
 }
@@ -1083,11 +1090,9 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
   double resid = 0.0;
   for (;;) {
     if (need64) {  // y = T (sigma_s rp) + b~ in FP64
-      rt_prof_begin(RT_K_PLANE_SWEEP, s);
       hipLaunchKernelGGL((k_skew<double, 1>), qgrid, dim3(BLK), 0, s, A, I.ss, (const double *)H->rp,
                          (const double *)nullptr, (double *)A.srcq);
       int e = sweep_moment(p, H, 0, 0, H->y, bt, 0, H->rp, H->blkmax);
-      rt_prof_end(RT_K_PLANE_SWEEP, s);
       if (e) return e;
       if (nsweep == 0)
         hipLaunchKernelGGL(k_plane_copy, dim3(nblk), dim3(BLK), 0, s, nc, (const double *)H->y, I.rhalf);
@@ -1130,13 +1135,11 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
     }
     first_corr = 0;
     if (mixed) {  // y += T (sigma_s (rp_new - rp)) with the increment in FP32
-      rt_prof_begin(RT_K_PLANE_SWEEP, s);
       hipLaunchKernelGGL(k_plane_increment, dim3(nblk), dim3(BLK), 0, s, nc, I.ss, (const double *)H->y, dcorr,
                          H->rp, H->src32);
       hipLaunchKernelGGL((k_skew<float, 0, float>), qgrid, dim3(BLK), 0, s, A, (const double *)nullptr,
                          (const float *)H->src32, (const double *)nullptr, (float *)A.srcq);
       e = sweep_moment(p, H, 0, 1, H->y, nullptr, 1, H->rp, H->blkmax);
-      rt_prof_end(RT_K_PLANE_SWEEP, s);
       if (e) return e;
       exact = 0;
       n32++;
@@ -1163,16 +1166,19 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
     PH(rt_launch_rom_update(p->dinst, 1, nc, s2));
     rt_prof_end(RT_K_ROM_UPDATE, s2);
   }
-  rt_prof_begin(RT_K_PLANE_FPASS, s);
   hipLaunchKernelGGL((k_skew<double, 2>), qgrid, dim3(BLK), 0, s, A, I.ss, (const double *)I.rho, I.G, A.s1q);
   int e = sweep_moment(p, H, 1, 0, I.bt2[cur ^ 1], nullptr, 0, nullptr, nullptr);
-  rt_prof_end(RT_K_PLANE_FPASS, s);
   if (e) return e;
   if (s2 != s) {
     PH(hipEventRecord(p->ev_rom, s2));
     PH(hipStreamWaitEvent(s, p->ev_rom, 0));
   }
   return RTROM_OK;
+}
+
+int rt_plane_dsa_iters(const rtrom_problem *p) {
+  const PlaneHost *H = (const PlaneHost *)p->plane;
+  return H ? H->cheb_iters : 0;
 }
 
 int rt_plane_step(rtrom_problem *p, int nsteps) {

@@ -492,15 +492,20 @@ __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, in
 __device__ __forceinline__ void isvd_rotate_cell(const RomDev &R, const RomPend &P, const double *Uc,
                                                  const double *Vc, int ld, int c) {
   const int r = P.r_old, k = P.k;
+  // the cell's old basis rows, loaded up front (one memory latency, not r)
+  double old[RT_RMAX];
+#pragma unroll
+  for (int q = 0; q < RT_RMAX; ++q) old[q] = q < r ? R.U[(size_t)q * ld + c] : 0.0;
   double acc[RT_RMAX];
 #pragma unroll
   for (int j = 0; j < RT_RMAX; ++j) acc[j] = 0.0;
-  for (int q = 0; q < r; ++q) {
-    const double u = R.U[(size_t)q * ld + c];
 #pragma unroll
-    for (int j = 0; j < RT_RMAX; ++j)
-      if (j < k) acc[j] = rt_fma(u, Uc[q * RT_KC + j], acc[j]);
-  }
+  for (int q = 0; q < RT_RMAX; ++q)
+    if (q < r) {
+#pragma unroll
+      for (int j = 0; j < RT_RMAX; ++j)
+        if (j < k) acc[j] = rt_fma(old[q], Uc[q * RT_KC + j], acc[j]);
+    }
   if (!P.deficient) {
     const double e = P.p[c] * P.inv_nu;
 #pragma unroll
@@ -511,13 +516,16 @@ __device__ __forceinline__ void isvd_rotate_cell(const RomDev &R, const RomPend 
   for (int j = 0; j < RT_RMAX; ++j)
     if (j < k) R.U[(size_t)j * ld + c] = acc[j];
 #pragma unroll
-  for (int j = 0; j < RT_RMAX; ++j) acc[j] = 0.0;
-  for (int q = 0; q < r; ++q) {
-    const double w = R.W[(size_t)q * ld + c];
+  for (int q = 0; q < RT_RMAX; ++q) old[q] = q < r ? R.W[(size_t)q * ld + c] : 0.0;
 #pragma unroll
-    for (int j = 0; j < RT_RMAX; ++j)
-      if (j < k) acc[j] = rt_fma(w, Vc[q * RT_KC + j], acc[j]);
-  }
+  for (int j = 0; j < RT_RMAX; ++j) acc[j] = 0.0;
+#pragma unroll
+  for (int q = 0; q < RT_RMAX; ++q)
+    if (q < r) {
+#pragma unroll
+      for (int j = 0; j < RT_RMAX; ++j)
+        if (j < k) acc[j] = rt_fma(old[q], Vc[q * RT_KC + j], acc[j]);
+    }
   {
     const double bv = P.b[c];
 #pragma unroll

@@ -177,14 +177,23 @@ __global__ void __launch_bounds__(BLK) k_rom_pass2(const Inst *__restrict__ inst
 #pragma unroll
   for (int k = 0; k < 2 * RT_RMAX; ++k) part[k] = 0.0;
   if (c < I.nc) {
+    // all loads issued up front; the arithmetic keeps its order
+    double u[RT_RMAX], wv[RT_RMAX];
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k) {
+      u[k] = k < r ? R.U[(size_t)k * ld + c] : 0.0;
+      wv[k] = k < r ? R.W[(size_t)k * ld + c] : 0.0;
+    }
     double v = W.x[c];
-    for (int k = 0; k < r; ++k) v = rt_fma(-R.U[(size_t)k * ld + c], av[k], v);
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k)
+      if (k < r) v = rt_fma(-u[k], av[k], v);
     W.p[c] = v;
 #pragma unroll
     for (int k = 0; k < RT_RMAX; ++k)
       if (k < r) {
-        part[k] = R.U[(size_t)k * ld + c] * v;
-        part[RT_RMAX + k] = R.W[(size_t)k * ld + c] * v;
+        part[k] = u[k] * v;
+        part[RT_RMAX + k] = wv[k] * v;
       }
   }
   wg_sum_fast<2 * RT_RMAX>(part, red, out);
@@ -202,8 +211,13 @@ __global__ void __launch_bounds__(BLK) k_rom_pass3(const Inst *__restrict__ inst
   sum_partials(W.part2, W.nblk, r, a2, scratch);
   double part[2] = {0.0, 0.0};
   if (c < I.nc) {
+    double u[RT_RMAX];
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k) u[k] = k < r ? R.U[(size_t)k * ld + c] : 0.0;
     double v = W.p[c];
-    for (int k = 0; k < r; ++k) v = rt_fma(-R.U[(size_t)k * ld + c], a2[k], v);
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k)
+      if (k < r) v = rt_fma(-u[k], a2[k], v);
     W.p[c] = v;
     part[0] = v * v;
     part[1] = v * W.b[c];

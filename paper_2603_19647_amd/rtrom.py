@@ -47,6 +47,7 @@ class Stats(ctypes.Structure):
         ("nonconverged_steps", ctypes.c_int32), ("rom_fallbacks", ctypes.c_int32),
         ("ig_updates", ctypes.c_int64), ("pc_updates", ctypes.c_int64), ("fp32_sweeps", ctypes.c_int64),
         ("last_residual", ctypes.c_double), ("t_total_s", ctypes.c_double),
+        ("dsa_iters", ctypes.c_int32), ("reserved_", ctypes.c_int32),
     ]
 
 
