@@ -275,6 +275,9 @@ __device__ inline void core_svd(RomSmem &sm, int rows, int cols) {
   const int grp = tid >> 4, gl = tid & 15;
   const int i0 = gl, i1 = gl + 16;
   for (int sweep = 0; sweep < 60; ++sweep) {
+    // flag bit 0: a rotation was applied; bit 1: some pair's cosine was
+    // above 1e-12.  A sweep whose pairs were all below 1e-12 leaves them
+    // below 1e-15 (quadratic convergence), so it is the last one.
     if (tid == 0) sm.flag = 0;
     __syncthreads();
     for (int round = 0; round < ncp - 1; ++round) {
@@ -293,10 +296,19 @@ __device__ inline void core_svd(RomSmem &sm, int rows, int cols) {
         const double al = row16_sum(rt_fma(bp0, bp0, bp1 * bp1));
         const double be = row16_sum(rt_fma(bq0, bq0, bq1 * bq1));
         const double ga = row16_sum(rt_fma(bp0, bq0, bp1 * bq1));
-        if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+        const double g2 = ga * ga, ab = al * be;
+        if (ga != 0.0 && g2 > 1e-30 * ab) {
+          // tangent of the rotation angle: any accurate-enough t gives a valid
+          // rotation; c = (1 + t^2)^(-1/2) to full precision keeps c^2 + s^2 = 1
           const double zeta = (be - al) * rt_rcp(2.0 * ga);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) * rt_rcp(fabs(zeta) + sqrt(rt_fma(zeta, zeta, 1.0)));
-          const double c = rt_rcp(sqrt(rt_fma(t, t, 1.0)));
+          const double z2 = rt_fma(zeta, zeta, 1.0);
+          double y = __builtin_amdgcn_rsq(z2);
+          y = y * rt_fma(-0.5 * z2 * y, y, 1.5);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) * rt_rcp(fabs(zeta) + z2 * y);
+          const double t2 = rt_fma(t, t, 1.0);
+          double c = __builtin_amdgcn_rsq(t2);
+          c = c * rt_fma(-0.5 * t2 * c, c, 1.5);  // two Newton steps for (1 + t^2)^(-1/2)
+          c = c * rt_fma(-0.5 * t2 * c, c, 1.5);
           const double s = c * t;
           if (i0 < rows) {
             sm.B[p * RT_KC + i0] = c * bp0 - s * bq0;
@@ -316,14 +328,14 @@ __device__ inline void core_svd(RomSmem &sm, int rows, int cols) {
             sm.V[p * RT_KC + i1] = c * vp - s * vq;
             sm.V[q * RT_KC + i1] = s * vp + c * vq;
           }
-          if (gl == 0) sm.flag = 1;
+          if (gl == 0) atomicOr(&sm.flag, g2 > 1e-24 * ab ? 3 : 1);
         }
       }
       __syncthreads();
     }
     const int more = sm.flag;
     __syncthreads();
-    if (!more) break;
+    if (!(more & 2)) break;
   }
   // column norms and a stable descending rank order
   if (tid < cols) {
@@ -405,6 +417,10 @@ __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, in
   }
   const int deficient = !(nu > 1e-12 * xn);
   const int rows = deficient ? r : r + 1, cols = r + 1;
+  // stage M (r x r, global) in LDS once: the products below read it repeatedly
+  double *Ms = sm.T1;  // free until the M_new products
+  for (int e = tid; e < RT_RMAX * RT_RMAX; e += NT) Ms[e] = R.M[e];
+  __syncthreads();
   // coefficient vectors: a (total), U^T b, a2, p^T W = p1^T W - a2^T M
   if (tid < RT_RMAX) {
     const int j = tid;
@@ -413,7 +429,7 @@ __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, in
     double v = 0.0;
     if (j < r) {
       v = sm.red[3 * RT_RMAX + 2 + j];
-      for (int i = 0; i < r; ++i) v = rt_fma(-sm.red[2 * RT_RMAX + 2 + i], R.M[i * RT_RMAX + j], v);
+      for (int i = 0; i < r; ++i) v = rt_fma(-sm.red[2 * RT_RMAX + 2 + i], Ms[i * RT_RMAX + j], v);
     }
     sm.pwv[j] = v;
   }
@@ -428,7 +444,7 @@ __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, in
     sm.B[e] = (i < rows && j < cols) ? v : 0.0;
     const int mi = e / RT_KC, mj = e % RT_KC;  // Mx row mi, column mj
     double m = 0.0;
-    if (mi < r && mj < r) m = R.M[mi * RT_RMAX + mj];
+    if (mi < r && mj < r) m = Ms[mi * RT_RMAX + mj];
     else if (mi < r && mj == r) m = sm.utbv[mi];
     else if (mi == r && mj < r && !deficient) m = sm.pwv[mj] / nu;
     else if (mi == r && mj == r && !deficient) m = pb / nu;

@@ -6,7 +6,13 @@
 #include "rt_rom.h"
 
 namespace {
-constexpr int BLK = 256;  // cells per block of the grid passes
+constexpr int BLK = 256;       // threads per block of the grid passes
+constexpr int MAX_PASS_BLK = 64;  // blocks per instance (cells are strided over them)
+
+__device__ __host__ __forceinline__ int pass_blocks(int nc) {
+  const int nb = (nc + BLK - 1) / BLK;
+  return nb < MAX_PASS_BLK ? nb : MAX_PASS_BLK;
+}
 
 __device__ __forceinline__ const RomDev &rom_of(const Inst &I, int z) { return z ? I.pc : I.ig; }
 }  // namespace
@@ -20,18 +26,17 @@ __device__ __forceinline__ const RomDev &rom_of(const Inst &I, int z) { return z
 __global__ void __launch_bounds__(BLK) k_rom_norms(const Inst *__restrict__ insts) {
   const Inst &I = insts[blockIdx.y];
   if (I.method != RT_ROM || !I.st->flag_ig) return;
-  const int nb = (I.nc + BLK - 1) / BLK;
+  const int nb = pass_blocks(I.nc);
   if ((int)blockIdx.x >= nb) return;
   __shared__ double red[(BLK / 64) * 3], out[3];
-  const int c = blockIdx.x * BLK + threadIdx.x;
   double part[3] = {0.0, 0.0, 0.0};
-  if (c < I.nc) {
+  for (int c = blockIdx.x * BLK + threadIdx.x; c < I.nc; c += nb * BLK) {
     const double r = I.rho[c];
-    part[0] = r * r;
+    part[0] = rt_fma(r, r, part[0]);
     const double e1 = I.rho0[c] - r;
-    part[1] = e1 * e1;
+    part[1] = rt_fma(e1, e1, part[1]);
     const double e2 = I.dpc[c] - (r - I.rhalf[c]);
-    part[2] = e2 * e2;
+    part[2] = rt_fma(e2, e2, part[2]);
   }
   wg_sum_fast<3>(part, red, out);
   if (threadIdx.x < 3) I.ig.work->part3[blockIdx.x * RT_NPART + threadIdx.x] = out[threadIdx.x];
@@ -53,7 +58,7 @@ __global__ void __launch_bounds__(256) k_rom_decide(const Inst *__restrict__ ins
   double e_ig = -1.0, e_pc = -1.0;
   if (I.method == RT_ROM) {
     const int flag_ig = st->flag_ig, flag_pc = st->flag_pc, used_pc = st->used_pc;
-    const int nb = (nc + BLK - 1) / BLK;
+    const int nb = pass_blocks(nc);
     if (flag_ig) sum_partials(I.ig.work->part3, nb, 3, vec, scratch);
     const double rn = flag_ig ? sqrt(vec[0]) : 0.0;
     const double scale = (I.abs_up || rn == 0.0) ? 1.0 : 1.0 / rn;
@@ -134,11 +139,11 @@ __global__ void __launch_bounds__(BLK) k_rom_pass1(const Inst *__restrict__ inst
   const RomWork &W = *R.work;
   if (!W.active || (int)blockIdx.x >= W.nblk) return;
   __shared__ double red[(BLK / 64) * (2 * RT_RMAX + 2)], out[2 * RT_RMAX + 2];
-  const int r = W.r, ld = I.ld, c = blockIdx.x * BLK + threadIdx.x;
+  const int r = W.r, ld = I.ld;
   double part[2 * RT_RMAX + 2];
 #pragma unroll
   for (int k = 0; k < 2 * RT_RMAX + 2; ++k) part[k] = 0.0;
-  if (c < I.nc) {
+  for (int c = blockIdx.x * BLK + threadIdx.x; c < I.nc; c += W.nblk * BLK) {
     double xv, bv;
     if (blockIdx.z == 1) {  // x = rho^n - rho^(1/2), b = rho^(1/2) - rho^(0)
       const double rh = I.rhalf[c];
@@ -150,14 +155,14 @@ __global__ void __launch_bounds__(BLK) k_rom_pass1(const Inst *__restrict__ inst
       xv = W.x[c];
       bv = W.b[c];
     }
-    part[2 * RT_RMAX] = xv * xv;
-    part[2 * RT_RMAX + 1] = xv * bv;
+    part[2 * RT_RMAX] = rt_fma(xv, xv, part[2 * RT_RMAX]);
+    part[2 * RT_RMAX + 1] = rt_fma(xv, bv, part[2 * RT_RMAX + 1]);
 #pragma unroll
     for (int k = 0; k < RT_RMAX; ++k)
       if (k < r) {
         const double u = R.U[(size_t)k * ld + c];
-        part[k] = u * xv;
-        part[RT_RMAX + k] = u * bv;
+        part[k] = rt_fma(u, xv, part[k]);
+        part[RT_RMAX + k] = rt_fma(u, bv, part[RT_RMAX + k]);
       }
   }
   wg_sum_fast<2 * RT_RMAX + 2>(part, red, out);
@@ -171,12 +176,12 @@ __global__ void __launch_bounds__(BLK) k_rom_pass2(const Inst *__restrict__ inst
   const RomWork &W = *R.work;
   if (!W.active || (int)blockIdx.x >= W.nblk) return;
   __shared__ double red[(BLK / 64) * 2 * RT_RMAX], out[2 * RT_RMAX], av[RT_RMAX], scratch[BLK];
-  const int r = W.r, ld = I.ld, c = blockIdx.x * BLK + threadIdx.x;
+  const int r = W.r, ld = I.ld;
   sum_partials(W.part1, W.nblk, r, av, scratch);
   double part[2 * RT_RMAX];
 #pragma unroll
   for (int k = 0; k < 2 * RT_RMAX; ++k) part[k] = 0.0;
-  if (c < I.nc) {
+  for (int c = blockIdx.x * BLK + threadIdx.x; c < I.nc; c += W.nblk * BLK) {
     // all loads issued up front; the arithmetic keeps its order
     double u[RT_RMAX], wv[RT_RMAX];
 #pragma unroll
@@ -192,8 +197,8 @@ __global__ void __launch_bounds__(BLK) k_rom_pass2(const Inst *__restrict__ inst
 #pragma unroll
     for (int k = 0; k < RT_RMAX; ++k)
       if (k < r) {
-        part[k] = u[k] * v;
-        part[RT_RMAX + k] = wv[k] * v;
+        part[k] = rt_fma(u[k], v, part[k]);
+        part[RT_RMAX + k] = rt_fma(wv[k], v, part[RT_RMAX + k]);
       }
   }
   wg_sum_fast<2 * RT_RMAX>(part, red, out);
@@ -207,10 +212,10 @@ __global__ void __launch_bounds__(BLK) k_rom_pass3(const Inst *__restrict__ inst
   const RomWork &W = *R.work;
   if (!W.active || (int)blockIdx.x >= W.nblk) return;
   __shared__ double red[(BLK / 64) * 2], out[2], a2[RT_RMAX], scratch[BLK];
-  const int r = W.r, ld = I.ld, c = blockIdx.x * BLK + threadIdx.x;
+  const int r = W.r, ld = I.ld;
   sum_partials(W.part2, W.nblk, r, a2, scratch);
   double part[2] = {0.0, 0.0};
-  if (c < I.nc) {
+  for (int c = blockIdx.x * BLK + threadIdx.x; c < I.nc; c += W.nblk * BLK) {
     double u[RT_RMAX];
 #pragma unroll
     for (int k = 0; k < RT_RMAX; ++k) u[k] = k < r ? R.U[(size_t)k * ld + c] : 0.0;
@@ -219,8 +224,8 @@ __global__ void __launch_bounds__(BLK) k_rom_pass3(const Inst *__restrict__ inst
     for (int k = 0; k < RT_RMAX; ++k)
       if (k < r) v = rt_fma(-u[k], a2[k], v);
     W.p[c] = v;
-    part[0] = v * v;
-    part[1] = v * W.b[c];
+    part[0] = rt_fma(v, v, part[0]);
+    part[1] = rt_fma(v, W.b[c], part[1]);
   }
   wg_sum_fast<2>(part, red, out);
   if (threadIdx.x < 2) W.part3[blockIdx.x * RT_NPART + threadIdx.x] = out[threadIdx.x];
@@ -315,7 +320,7 @@ __global__ void __launch_bounds__(256) k_rom_update(const Inst *__restrict__ ins
 }
 
 extern "C" hipError_t rt_launch_rom(const Inst *dinsts, int ninst, int nc_max, int any_rom, hipStream_t s) {
-  const int nb = (nc_max + BLK - 1) / BLK;
+  const int nb = pass_blocks(nc_max);
   if (any_rom) hipLaunchKernelGGL(k_rom_norms, dim3(nb, ninst), dim3(BLK), 0, s, dinsts);
   hipLaunchKernelGGL(k_rom_decide, dim3(ninst), dim3(256), 0, s, dinsts);
   if (any_rom) {
