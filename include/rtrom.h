@@ -198,35 +198,47 @@ rtrom_status rtrom_profile_read(double *seconds, int64_t *launches, int32_t nkin
 const char *rtrom_last_error(void);
 
 /* ---- serving: continuous batching of independent problems ---------------
- * A request is one time-marching problem (desc + nsteps).  The server admits
- * queued requests as slots and device memory (hbm_budget_bytes) free up,
- * advances every admitted request in fused launches each tick so their work
- * overlaps on the device, and keeps each one's state resident until fetched.
- * A result depends only on its own request: fixed per-problem launch shapes
- * and no cross-problem reductions. */
+ * (Sec. 4 runs one problem at a time; serving many is this library's.)
+ * A request is one time-marching problem (desc + nsteps).  Requests queue in
+ * submission order; max_slots worker threads admit the head of the queue as
+ * soon as a slot is free and its device footprint (rtrom_estimate_bytes plus
+ * its step history) fits the rest of hbm_budget_bytes.  Admitted problems
+ * march concurrently, each on its own streams, so their kernels overlap on
+ * the device; a finished march copies rho and the statistics to the host and
+ * releases the device state, freeing budget.  A result depends only on its
+ * own request (own state, fixed launch shapes, fixed-order reductions): it is
+ * the same alone and in the mix.  Handles are thread-safe; profiling
+ * (rtrom_profile_enable) must stay off while a server runs. */
 typedef struct rtrom_server rtrom_server;
 typedef struct {
   uint64_t hbm_budget_bytes; /* admission budget for problem state */
-  int32_t max_slots;         /* concurrent problems */
+  int32_t max_slots;         /* concurrent problems (worker threads), 1..256 */
   int32_t device;            /* HIP device ordinal */
-  int32_t steps_per_tick;    /* steps advanced per admitted request per tick */
+  int32_t steps_per_tick;    /* reserved (problems advance one step at a time) */
 } rtrom_server_desc;
 
 enum { RTROM_REQ_QUEUED = 0, RTROM_REQ_RUNNING = 1, RTROM_REQ_DONE = 2, RTROM_REQ_FAILED = 3 };
 
+/* Starts the worker threads; touches no device.  EINVAL on bad arguments. */
 rtrom_status rtrom_server_create(const rtrom_server_desc *d, rtrom_server **out);
-/* copies d; non-blocking.  ENOMEM if the request can never fit the budget. */
+/* Validates and copies d (the caller may free its arrays on return);
+ * non-blocking.  EINVAL for an invalid description, ENOMEM if the request can
+ * never fit the budget. */
 rtrom_status rtrom_server_submit(rtrom_server *s, const rtrom_problem_desc *d,
                                  int32_t nsteps, uint64_t *ticket);
+/* state = RTROM_REQ_*; EINVAL for an unknown (or already fetched) ticket. */
 rtrom_status rtrom_server_poll(rtrom_server *s, uint64_t ticket, int32_t *state);
-/* Drive the scheduler until every submitted request is done (blocking). */
+/* Blocks until every submitted request has finished. */
 rtrom_status rtrom_server_drain(rtrom_server *s);
-/* Copy out a finished request's rho (n >= cells), stats, per-step latencies
- * (seconds, up to nlat) and its march latency from admission to completion.
- * EBUSY if not finished.  Releases the request's device state. */
+/* Copies out a finished request's rho (n >= cells), stats, per-step latencies
+ * (seconds, up to nlat) and its march latency from admission to completion,
+ * then forgets the ticket.  EBUSY if not finished; a failed request returns
+ * its error.  Returns ENOCONV when some step hit max_iter (R8). */
 rtrom_status rtrom_server_fetch(rtrom_server *s, uint64_t ticket, double *rho, int64_t n,
                                 rtrom_stats *st, double *step_lat_s, int64_t nlat,
                                 double *march_lat_s);
+/* Stops admitting, ends running marches at their next step, joins the
+ * workers.  NULL is a no-op. */
 void rtrom_server_destroy(rtrom_server *s);
 
 #ifdef __cplusplus

@@ -185,6 +185,9 @@ extern "C" rtrom_status rtrom_cl_quadrature(int32_t n_azim, int32_t n_polar, dou
 // ---------------------------------------------------------------------------
 static const int RT_SLAB_MAX_CELLS = 4096;
 
+static rtrom_status validate(const rtrom_problem_desc *d);
+rtrom_status rt_validate(const rtrom_problem_desc *d) { return validate(d); }
+
 static rtrom_status validate(const rtrom_problem_desc *d) {
   if (!d) return fail(RTROM_EINVAL, "null description");
   if (d->dim != 1 && d->dim != 2) return fail(RTROM_EINVAL, "dim must be 1 or 2");

@@ -53,6 +53,7 @@ int rt_plane_needs_cyclic(int ny);
 int rt_plane_unfold(const rtrom_problem *p, double *f_host);  // folded f -> full ordinate order
 
 void rt_set_error(const std::string &msg);
+rtrom_status rt_validate(const rtrom_problem_desc *d);  // host-only checks of a description
 
 // Kernel timing (rtrom_profile_*): bracket a launch with events when enabled.
 enum { RT_K_SLAB_SI = 0, RT_K_SLAB_FPASS = 1, RT_K_POST = 2, RT_K_PLANE_SWEEP = 3, RT_K_PLANE_DSA = 4,

@@ -326,7 +326,7 @@ class Server:
         mlat = ctypes.c_double()
         st = Stats()
         _check(lib().rtrom_server_fetch(self.h, ticket, _p(rho), rho.size, ctypes.byref(st), _p(lat),
-                                        lat.size, ctypes.byref(mlat)))
+                                        lat.size, ctypes.byref(mlat)), allow=(OK, ENOCONV))
         del self._specs[ticket]
         return rho, {k: getattr(st, k) for k, _ in Stats._fields_}, lat[:n], mlat.value
 

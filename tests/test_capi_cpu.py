@@ -97,3 +97,37 @@ def test_estimate_bytes_scales_with_f():
     b = rtrom.estimate_bytes(W.random_slab(1, 1024, 64))
     assert b - a >= 48 * 1024 * 8
     assert a > 16 * 1024 * 8
+
+
+# ---- serving API: argument checks and failure paths (no device needed) ----
+
+def _small_plane_spec():
+    from paper_2603_19647_amd import workloads as W
+    return W.random_plane(1, 16, 8, 4, nsteps=3)
+
+
+def test_server_create_rejects_bad_arguments():
+    with pytest.raises(rtrom.RtromError):
+        rtrom.Server(hbm_budget_bytes=0)
+    with pytest.raises(rtrom.RtromError):
+        rtrom.Server(hbm_budget_bytes=1 << 30, max_slots=0)
+
+
+def test_server_submit_validates_and_budget():
+    s = rtrom.Server(hbm_budget_bytes=1 << 20, max_slots=1)
+    try:
+        spec = _small_plane_spec()
+        with pytest.raises(rtrom.RtromError) as e:
+            s.submit(spec.replace(dt=-1.0))
+        assert e.value.status == rtrom.EINVAL
+        big = spec.replace(nsteps=3)
+        need = rtrom.estimate_bytes(big)
+        assert need > (1 << 20)  # this small budget cannot hold the problem
+        with pytest.raises(rtrom.RtromError) as e:
+            s.submit(big)
+        assert e.value.status == rtrom.ENOMEM
+        with pytest.raises(rtrom.RtromError) as e:
+            s.poll(12345)
+        assert e.value.status == rtrom.EINVAL
+    finally:
+        s.close()
