@@ -142,12 +142,72 @@ def cpu_baseline_batch(specs, steps, seconds_budget=20.0):
             "sample": f"{len(sample)} of the {len(specs)} instances x {steps} steps, FP64 oracle, process pool"}
 
 
+def run_serving(rtrom, W, count, budget, slots, seed=5):
+    """C5: closed-loop saturation run (everything submitted at once) gives the
+    capacity; then Poisson arrivals at 80 % of it, with per-step and per-march
+    latencies and the queueing delay seen by the client."""
+    import numpy as np
+    specs = W.serving_stream(seed=seed, count=count)
+    # closed loop
+    srv = rtrom.Server(hbm_budget_bytes=budget, max_slots=slots)
+    t0 = time.perf_counter()
+    tickets = [srv.submit(s) for s in specs]
+    srv.drain()
+    t_sat = time.perf_counter() - t0
+    for t in tickets:
+        srv.fetch(t)
+    srv.close()
+    steps_total = sum(s.nsteps for s in specs)
+    capacity = count / t_sat
+    # open loop, Poisson arrivals at 0.8 x capacity
+    rng = np.random.default_rng(seed + 1000)
+    gaps = rng.exponential(1.0 / (0.8 * capacity), size=count)
+    srv = rtrom.Server(hbm_budget_bytes=budget, max_slots=slots)
+    sub_t, done_t, tickets = {}, {}, []
+    t0 = time.perf_counter()
+    nxt = 0
+    arrive = t0 + np.cumsum(gaps)
+    while len(done_t) < count:
+        now = time.perf_counter()
+        while nxt < count and arrive[nxt] <= now:
+            tk = srv.submit(specs[nxt])
+            tickets.append(tk)
+            sub_t[tk] = now
+            nxt += 1
+        for tk in tickets:
+            if tk not in done_t and srv.poll(tk) >= 2:
+                done_t[tk] = time.perf_counter()
+        time.sleep(0.0005)
+    t_open = time.perf_counter() - t0
+    step_lat, march_lat, e2e = [], [], []
+    for tk in tickets:
+        rho, st, lat, mlat = srv.fetch(tk)
+        step_lat.extend(lat.tolist())
+        march_lat.append(mlat)
+        e2e.append(done_t[tk] - sub_t[tk])
+    srv.close()
+    p = lambda a, q: float(np.percentile(np.asarray(a), q))
+    return {
+        "requests": count, "instance_steps": steps_total, "saturation_s": t_sat,
+        "capacity_requests_per_s": capacity, "saturation_instance_steps_per_s": steps_total / t_sat,
+        "open_loop_rate_requests_per_s": 0.8 * capacity, "open_loop_s": t_open,
+        "open_loop_instance_steps_per_s": steps_total / t_open,
+        "step_latency_ms": {"p50": p(step_lat, 50) * 1e3, "p99": p(step_lat, 99) * 1e3},
+        "march_latency_s": {"p50": p(march_lat, 50), "p99": p(march_lat, 99)},
+        "end_to_end_latency_s": {"p50": p(e2e, 50), "p99": p(e2e, 99)},
+        "hbm_budget_bytes": budget, "max_slots": slots,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", choices=("slab4096", "checker256", "batch512"), default="slab4096")
+    ap.add_argument("--workload", choices=("slab4096", "checker256", "batch512", "serving"), default="slab4096")
+    ap.add_argument("--requests", type=int, default=24, help="serving: requests in the stream")
+    ap.add_argument("--budget-gib", type=float, default=4.0, help="serving: HBM admission budget")
+    ap.add_argument("--slots", type=int, default=8, help="serving: concurrent problems")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -204,6 +264,28 @@ def main():
         metric = "time steps/s (ROM-SI-DSA, 1e-8 rel tol)"
         unit = "steps/s"
         cpu = None if args.no_cpu_baseline else cpu_baseline_single(spec)
+    elif args.workload == "serving":
+        # Disabled: a serving run on the GPU completed and printed its line,
+        # but the process then crashed during exit (status 139) with the cause
+        # not established; the serving tests under pytest pass.
+        print("bench.py: the serving workload is disabled until a process-exit crash after "
+              "the serving run is explained (see DESIGN.md)", file=sys.stderr)
+        sys.exit(3)
+        warm = 0
+        log(f"bench: serving stream of {args.requests} requests")
+        res = run_serving(rtrom, W, args.requests, int(args.budget_gib * (1 << 30)), args.slots)
+        steps = res["instance_steps"]
+        value = res["saturation_instance_steps_per_s"]
+        t_rom = res["saturation_s"]
+        roof = None
+        extra = {"serving": res}
+        config = {"workload": "serving_stream_grf_2d", "requests": args.requests,
+                  "grids": "64..512 squared", "ordinates": "32/64/128", "steps_each": "100..500",
+                  "method": "rom_si_dsa", "precision": "fp32 sweeps + fp64 refinement",
+                  "arrivals": "closed loop (value), then Poisson at 0.8 x capacity"}
+        metric = "instance time steps/s, serving (ROM-SI-DSA, 1e-8 rel tol)"
+        unit = "instance-steps/s"
+        cpu = None
     else:
         specs = W.slab_batch()
         steps = specs[0].nsteps if args.steps is None else args.steps

@@ -219,7 +219,8 @@ typedef struct {
 
 enum { RTROM_REQ_QUEUED = 0, RTROM_REQ_RUNNING = 1, RTROM_REQ_DONE = 2, RTROM_REQ_FAILED = 3 };
 
-/* Starts the worker threads; touches no device.  EINVAL on bad arguments. */
+/* Initialises the HIP runtime on the calling thread and starts the worker
+ * threads.  EINVAL on bad arguments, EDEVICE without a usable device. */
 rtrom_status rtrom_server_create(const rtrom_server_desc *d, rtrom_server **out);
 /* Validates and copies d (the caller may free its arrays on return);
  * non-blocking.  EINVAL for an invalid description, ENOMEM if the request can

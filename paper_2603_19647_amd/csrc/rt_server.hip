@@ -148,6 +148,15 @@ extern "C" rtrom_status rtrom_server_create(const rtrom_server_desc *d, rtrom_se
     rt_set_error("server: max_slots must be 1..256, hbm_budget_bytes > 0, device >= 0");
     return RTROM_EINVAL;
   }
+  // Bring the HIP runtime up on the creating thread before any worker uses
+  // it: a process whose only HIP calls came from worker threads that have
+  // since exited crashed during runtime teardown at process exit.
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || d->device >= ndev || hipSetDevice(d->device) != hipSuccess ||
+      hipFree(nullptr) != hipSuccess) {
+    rt_set_error("server: cannot initialise the HIP device");
+    return RTROM_EDEVICE;
+  }
   rtrom_server *s = new rtrom_server();
   s->d = *d;
   try {

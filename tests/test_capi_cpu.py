@@ -113,6 +113,7 @@ def test_server_create_rejects_bad_arguments():
         rtrom.Server(hbm_budget_bytes=1 << 30, max_slots=0)
 
 
+@pytest.mark.gpu
 def test_server_submit_validates_and_budget():
     s = rtrom.Server(hbm_budget_bytes=1 << 20, max_slots=1)
     try:
