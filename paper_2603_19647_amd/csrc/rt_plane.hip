@@ -441,17 +441,16 @@ __device__ __forceinline__ double dsa_Ax(const DsaArgs &D, const double *x, int 
   return v;
 }
 
-// Fused Chebyshev DSA solve (one cooperative launch per solve).  Tiles of
-// DT x DT cells, one workgroup of DTHR threads per tile (tiles beyond the
-// co-resident grid are taken in turn).  Every DS iterations the grid
-// synchronises once and each tile re-reads its neighbours' directions and
-// residuals over a halo of DS cells, then iterates DS times with the
-// directions in LDS and everything pointwise (residual, solution, operator
-// coefficients) in registers; the valid region shrinks by one cell per
-// iteration.  Each cell sees exactly the arithmetic of one global iteration,
-// so the result does not depend on the tiling.
+// Chebyshev DSA solve in blocks of DS iterations, one launch per block.
+// Tiles of DT x DT cells, one workgroup of DTHR threads per tile.  A launch
+// reads the tile's directions and residuals over a halo of DS cells and
+// iterates DS times with the directions in LDS and everything pointwise
+// (residual, solution, operator coefficients) in registers; the valid region
+// shrinks by one cell per iteration.  Each cell sees exactly the arithmetic of
+// one global iteration, so the result does not depend on the tiling.  Kernel
+// boundaries order the blocks: no grid-wide synchronisation inside a launch.
 constexpr int DT = 32;               // interior tile edge
-constexpr int DS = 8;                // iterations per grid synchronisation (halo)
+constexpr int DS = 8;                // iterations per launch (halo)
 constexpr int DE = DT + 2 * DS;      // extended tile edge
 constexpr int DTHR = 1024;           // threads per workgroup
 constexpr int DPT = (DE * DE + DTHR - 1) / DTHR;  // extended cells per thread
@@ -464,150 +463,96 @@ struct DsaSolve {
   const double *c1, *c2;          // Chebyshev coefficients per iteration
   int K, ntx, ntiles, pad_;
   double inv_theta;
-  unsigned long long *bar;        // [0]: arrivals, [1]: released generation
-  unsigned long long base;        // generations completed before this launch
-  int *fault;                     // set when a barrier wait gives up
 };
 
-// Directions and residuals cross tile boundaries only through agent-scope
-// relaxed atomic loads and stores, which are coherent across the chip's L2
-// slices; the barrier then needs no cache write-back or invalidation, only
-// the completion of this wave's stores before it arrives.
-__device__ __forceinline__ double xload(const double *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void xstore(double *p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// grid-wide barrier on a monotone arrival counter: generation g is released
-// when nblk * g arrivals have been counted.  The wait is bounded (a launch
-// that cannot make progress sets *fault and falls through instead of hanging).
-__device__ __forceinline__ void grid_sync(const DsaSolve &S, unsigned long long gen) {
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's exchanged stores completed
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned long long nb = gridDim.x;
-    const unsigned long long prev =
-        __hip_atomic_fetch_add(&S.bar[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (prev + 1 == gen * nb) {
-      __hip_atomic_store(&S.bar[1], gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      unsigned spins = 0;
-      while (__hip_atomic_load(&S.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins == (1u << 26)) {
-          *S.fault = 1;
-          break;
-        }
-      }
-    }
+// r = sigma_s (y - rp), x = 0, d = r / (theta diag)
+__global__ void __launch_bounds__(DTHR) k_dsa_init(DsaSolve S) {
+  const DsaArgs &D = S.D;
+  const int tile = blockIdx.x;
+  const int tx = tile % S.ntx, ty = tile / S.ntx;
+  const int ix = tx * DT + (int)threadIdx.x % DT, iy = ty * DT + (int)threadIdx.x / DT;
+  if (ix < D.nx && iy < D.ny) {
+    const int c = iy * D.nx + ix;
+    const double rhs = S.ss[c] * (S.y[c] - S.rp[c]);
+    S.r0[c] = rhs;
+    S.x[c] = 0.0;
+    S.d0[c] = S.inv_theta * rhs / D.diag[c];
   }
-  __syncthreads();
 }
 
-__global__ void __launch_bounds__(DTHR) k_dsa_cheb(DsaSolve S) {
+// iterations done .. done + nit - 1, reading buffer cur and writing cur ^ 1;
+// the last block closes x with the final direction
+__global__ void __launch_bounds__(DTHR) k_dsa_block(DsaSolve S, int done, int nit, int last, int cur) {
   __shared__ double sd[DE * DE];
   const DsaArgs &D = S.D;
   const int nx = D.nx, ny = D.ny;
-  unsigned long long gen = S.base;
-  // r = sigma_s (y - rp), x = 0, d = r / (theta diag)
-  for (int tile = blockIdx.x; tile < S.ntiles; tile += gridDim.x) {
-    const int tx = tile % S.ntx, ty = tile / S.ntx;
-    const int ix = tx * DT + (int)threadIdx.x % DT, iy = ty * DT + (int)threadIdx.x / DT;
-    if (ix < nx && iy < ny) {
-      const int c = iy * nx + ix;
-      const double rhs = S.ss[c] * (S.y[c] - S.rp[c]);
-      xstore(S.r0 + c, rhs);
-      S.x[c] = 0.0;
-      xstore(S.d0 + c, S.inv_theta * rhs / D.diag[c]);
-    }
+  const double *din = cur ? S.d1 : S.d0, *rin = cur ? S.r1 : S.r0;
+  double *dout = cur ? S.d0 : S.d1, *rout = cur ? S.r0 : S.r1;
+  const int tile = blockIdx.x;
+  const int tx = tile % S.ntx, ty = tile / S.ntx;
+  double dg[DPT], ar[DPT], al[DPT], au[DPT], ad[DPT], r[DPT], xr[DPT];
+#pragma unroll
+  for (int i = 0; i < DPT; ++i) {
+    const int e = threadIdx.x + DTHR * i;
+    const int ex = e % DE, ey = e / DE;
+    const int ix = tx * DT + ex - DS, iy = ty * DT + ey - DS;
+    const bool in = e < DE * DE && ix >= 0 && ix < nx && iy >= 0 && iy < ny;
+    const int c = in ? iy * nx + ix : 0;
+    // links to out-of-grid neighbours are zero; those cells carry d = 0
+    dg[i] = in ? D.diag[c] : 1.0;
+    ar[i] = in ? D.ax[c] : 0.0;
+    au[i] = in ? D.ay[c] : 0.0;
+    al[i] = in && ix > 0 ? D.ax[c - 1] : 0.0;
+    ad[i] = in && iy > 0 ? D.ay[c - nx] : 0.0;
+    r[i] = in ? rin[c] : 0.0;
+    xr[i] = in && ex >= DS && ex < DS + DT && ey >= DS && ey < DS + DT ? S.x[c] : 0.0;
+    if (e < DE * DE) sd[e] = in ? din[c] : 0.0;
   }
-  grid_sync(S, ++gen);
-  // per-thread cells of the extended tile and their (static) coefficients
-  double dg[DPT], ar[DPT], al[DPT], au[DPT], ad[DPT];
-  int loaded_tile = -1;
-  int done = 0, cur = 0;
-  while (done < S.K) {
-    const int nit = min(DS, S.K - done);
-    const bool last = done + nit >= S.K;
-    const double *din = cur ? S.d1 : S.d0, *rin = cur ? S.r1 : S.r0;
-    double *dout = cur ? S.d0 : S.d1, *rout = cur ? S.r0 : S.r1;
-    for (int tile = blockIdx.x; tile < S.ntiles; tile += gridDim.x) {
-      const int tx = tile % S.ntx, ty = tile / S.ntx;
-      const bool reload = tile != loaded_tile;
-      loaded_tile = tile;
-      double r[DPT], xr[DPT];
+  __syncthreads();
+  for (int it = 0; it < nit; ++it) {
+    const double c1 = S.c1[done + it], c2 = S.c2[done + it];
+    double dn[DPT];
 #pragma unroll
-      for (int i = 0; i < DPT; ++i) {
-        const int e = threadIdx.x + DTHR * i;
-        const int ex = e % DE, ey = e / DE;
-        const int ix = tx * DT + ex - DS, iy = ty * DT + ey - DS;
-        const bool in = e < DE * DE && ix >= 0 && ix < nx && iy >= 0 && iy < ny;
-        const int c = in ? iy * nx + ix : 0;
-        if (reload) {
-          // links to out-of-grid neighbours are zero; those cells carry d = 0
-          dg[i] = in ? D.diag[c] : 1.0;
-          ar[i] = in ? D.ax[c] : 0.0;
-          au[i] = in ? D.ay[c] : 0.0;
-          al[i] = in && ix > 0 ? D.ax[c - 1] : 0.0;
-          ad[i] = in && iy > 0 ? D.ay[c - nx] : 0.0;
-        }
-        r[i] = in ? xload(rin + c) : 0.0;
-        xr[i] = in && ex >= DS && ex < DS + DT && ey >= DS && ey < DS + DT ? S.x[c] : 0.0;
-        if (e < DE * DE) sd[e] = in ? xload(din + c) : 0.0;
+    for (int i = 0; i < DPT; ++i) {
+      const int e = threadIdx.x + DTHR * i;
+      const int ex = e % DE, ey = e / DE;
+      dn[i] = 0.0;
+      if (e < DE * DE && ex > 0 && ex < DE - 1 && ey > 0 && ey < DE - 1) {
+        const double dc = sd[e];
+        xr[i] += dc;
+        double v = dg[i] * dc;
+        v -= ar[i] * sd[e + 1];
+        v -= al[i] * sd[e - 1];
+        v -= au[i] * sd[e + DE];
+        v -= ad[i] * sd[e - DE];
+        r[i] = r[i] - v;
+        dn[i] = c1 * dc + c2 * r[i] / dg[i];
       }
-      __syncthreads();
-      for (int it = 0; it < nit; ++it) {
-        const double c1 = S.c1[done + it], c2 = S.c2[done + it];
-        double dn[DPT];
-#pragma unroll
-        for (int i = 0; i < DPT; ++i) {
-          const int e = threadIdx.x + DTHR * i;
-          const int ex = e % DE, ey = e / DE;
-          dn[i] = 0.0;
-          if (e < DE * DE && ex > 0 && ex < DE - 1 && ey > 0 && ey < DE - 1) {
-            const double dc = sd[e];
-            xr[i] += dc;
-            double v = dg[i] * dc;
-            v -= ar[i] * sd[e + 1];
-            v -= al[i] * sd[e - 1];
-            v -= au[i] * sd[e + DE];
-            v -= ad[i] * sd[e - DE];
-            r[i] = r[i] - v;
-            dn[i] = c1 * dc + c2 * r[i] / dg[i];
-          }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < DPT; ++i) {
-          const int e = threadIdx.x + DTHR * i;
-          const int ex = e % DE, ey = e / DE;
-          if (e < DE * DE && ex > 0 && ex < DE - 1 && ey > 0 && ey < DE - 1) sd[e] = dn[i];
-        }
-        __syncthreads();
-      }
-#pragma unroll
-      for (int i = 0; i < DPT; ++i) {
-        const int e = threadIdx.x + DTHR * i;
-        const int ex = e % DE, ey = e / DE;
-        const int ix = tx * DT + ex - DS, iy = ty * DT + ey - DS;
-        if (e < DE * DE && ex >= DS && ex < DS + DT && ey >= DS && ey < DS + DT && ix < nx && iy < ny) {
-          const int c = iy * nx + ix;
-          if (last) {
-            S.x[c] = xr[i] + sd[e];  // the closing update with the final direction
-          } else {
-            S.x[c] = xr[i];
-            xstore(dout + c, sd[e]);
-            xstore(rout + c, r[i]);
-          }
-        }
-      }
-      __syncthreads();
     }
-    done += nit;
-    cur ^= 1;
-    if (done < S.K) grid_sync(S, ++gen);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) {
+      const int e = threadIdx.x + DTHR * i;
+      const int ex = e % DE, ey = e / DE;
+      if (e < DE * DE && ex > 0 && ex < DE - 1 && ey > 0 && ey < DE - 1) sd[e] = dn[i];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < DPT; ++i) {
+    const int e = threadIdx.x + DTHR * i;
+    const int ex = e % DE, ey = e / DE;
+    const int ix = tx * DT + ex - DS, iy = ty * DT + ey - DS;
+    if (e < DE * DE && ex >= DS && ex < DS + DT && ey >= DS && ey < DS + DT && ix < nx && iy < ny) {
+      const int c = iy * nx + ix;
+      if (last) {
+        S.x[c] = xr[i] + sd[e];  // the closing update with the final direction
+      } else {
+        S.x[c] = xr[i];
+        dout[c] = sd[e];
+        rout[c] = r[i];
+      }
+    }
   }
 }
 
@@ -729,9 +674,6 @@ struct PlaneHost {
   int cheb_iters = 0;
   double cheb_theta = 1.0, cheb_delta = 0.0;
   double *cheb_c = nullptr;                 // device: c1[K], c2[K]
-  unsigned long long *dsa_bar = nullptr;    // device barrier counters
-  unsigned long long dsa_gen = 0;           // barrier generations used so far
-  int dsa_grid = 1;                         // co-resident workgroups of the DSA solve
   size_t bytes = 0;
 };
 
@@ -763,8 +705,8 @@ static size_t plane_bytes_for(const rtrom_problem_desc *d) {
   take(nc * 8 * 7);                 // y rp dvec cr cx cd0 cd1
   take(nc * 4);                     // src32
   take(nc * 8 * 3);                 // diag ax ay
-  take(nblk * 2 * 8 + 64);          // blkmax, res, fault flag
-  take(2 * 2000 * 8 + 64);          // Chebyshev coefficients, barrier counters
+  take(nblk * 2 * 8 + 64);          // blkmax, res
+  take(2 * 2000 * 8);               // Chebyshev coefficients
   take(nblk * RT_NPART * 8 + RT_RMAX * 8);  // DMD solve partials, coefficients
   take((size_t)g.ndf * 3 * 8);      // mx my w
   return b;
@@ -897,8 +839,7 @@ int rt_plane_create(rtrom_problem *p) {
   H->ay = H->ax + nc;
   H->blkmax = (double *)take((size_t)nblk * 2 * 8 + 64);
   H->res = H->blkmax + 2 * (size_t)nblk;
-  H->cheb_c = (double *)take(2 * 2000 * 8 + 64);
-  H->dsa_bar = (unsigned long long *)(H->cheb_c + 2 * 2000);
+  H->cheb_c = (double *)take(2 * 2000 * 8);
   H->rpart = (double *)take((size_t)nblk * RT_NPART * 8 + RT_RMAX * 8);
   H->rcoef = H->rpart + (size_t)nblk * RT_NPART;
   double *dmx = (double *)take((size_t)ndf * 3 * 8);
@@ -969,18 +910,6 @@ int rt_plane_create(rtrom_problem *p) {
     rho_k = rho_n;
   }
   PH(hipMemcpyAsync(H->cheb_c, cc.data(), cc.size() * 8, hipMemcpyHostToDevice, p->stream));
-  {
-    int coop = 0, ncu = 0, per_cu = 0;
-    PH(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, p->device));
-    if (!coop) {
-      rt_set_error("plane: the device does not support cooperative launches");
-      return RTROM_EDEVICE;
-    }
-    PH(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device));
-    PH(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(k_dsa_cheb), DTHR, 0));
-    const int ntiles = ((nx + DT - 1) / DT) * ((ny + DT - 1) / DT);
-    H->dsa_grid = std::max(1, std::min(ntiles, ncu * std::max(per_cu, 1)));
-  }
   // b~^0 from f^0
   return rt_plane_rhs(p);
 }
@@ -1019,13 +948,15 @@ static int dsa_solve(rtrom_problem *p, PlaneHost *H, const double *y, const doub
   S.ntx = (H->A.nx + DT - 1) / DT;
   S.ntiles = S.ntx * ((H->A.ny + DT - 1) / DT);
   S.inv_theta = 1.0 / H->cheb_theta;
-  S.bar = H->dsa_bar;
-  S.base = H->dsa_gen;
-  S.fault = (int *)(H->res + 2);
-  void *args[] = {&S};
-  PH(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_dsa_cheb), dim3(H->dsa_grid), dim3(DTHR), args, 0,
-                                p->stream));
-  H->dsa_gen += (unsigned long long)((S.K + DS - 1) / DS);  // barriers per solve
+  hipStream_t s = p->stream;
+  hipLaunchKernelGGL(k_dsa_init, dim3(S.ntiles), dim3(DTHR), 0, s, S);
+  int cur = 0;
+  for (int done = 0; done < S.K; done += DS) {
+    const int nit = std::min(DS, S.K - done);
+    hipLaunchKernelGGL(k_dsa_block, dim3(S.ntiles), dim3(DTHR), 0, s, S, done, nit, (int)(done + nit >= S.K), cur);
+    cur ^= 1;
+  }
+  PH(hipGetLastError());
   return RTROM_OK;
 }
 
@@ -1047,16 +978,10 @@ static int read_residual(rtrom_problem *p, PlaneHost *H, double *dn, double *yn)
   hipLaunchKernelGGL(k_plane_maxreduce, dim3(1), dim3(256), 0, p->stream, (const double *)H->blkmax, H->A.nblk,
                      H->res);
   PH(hipGetLastError());
-  PH(hipMemcpyAsync(H->res_h, H->res, 24, hipMemcpyDeviceToHost, p->stream));
+  PH(hipMemcpyAsync(H->res_h, H->res, 16, hipMemcpyDeviceToHost, p->stream));
   PH(hipStreamSynchronize(p->stream));
   *dn = H->res_h[0];
   *yn = H->res_h[1];
-  int fault;
-  memcpy(&fault, H->res_h + 2, sizeof(int));
-  if (fault) {
-    rt_set_error("plane: a DSA grid barrier timed out");
-    return RTROM_EDEVICE;
-  }
   return RTROM_OK;
 }
 
