@@ -296,7 +296,7 @@ extern "C" rtrom_status rtrom_estimate_bytes(const rtrom_problem_desc *d, uint64
   if (d->dim != 1 && d->dim != 2) return fail(RTROM_EINVAL, "dim must be 1 or 2");
   if (d->nx < 1 || d->ny < 1 || d->n_polar < 1 || d->n_azim < 1) return fail(RTROM_EINVAL, "bad sizes");
   int nv = d->dim == 1 ? d->n_polar : d->n_polar * d->n_azim;
-  size_t b = slab_bytes(d, nv) + (d->dim == 2 ? rt_plane_extra_bytes(d) : 0) + 64 * sizeof(RtStepRec);
+  size_t b = slab_bytes(d, nv) + (d->dim == 2 ? rt_plane_extra_bytes(d) : 0) + 1024 * sizeof(RtStepRec);
   *bytes = b;
   return RTROM_OK;
 }
@@ -324,22 +324,26 @@ extern "C" void rtrom_destroy_problem(rtrom_problem *p) {
   delete p;
 }
 
-static rtrom_status ensure_hist(rtrom_problem *p, int64_t need) {
+// Step history: grown in stream order on `s` (no device-wide synchronisation),
+// geometrically, so a long march reallocates a handful of times at most.
+static rtrom_status ensure_hist(rtrom_problem *p, int64_t need, hipStream_t s) {
   if (need <= p->hist_cap) return RTROM_OK;
-  int64_t cap = std::max<int64_t>(need, std::max<int64_t>(64, 2 * p->hist_cap));
+  int64_t cap = std::max<int64_t>(need, std::max<int64_t>(1024, 2 * p->hist_cap));
   RtStepRec *nh = nullptr;
-  if (hipMalloc(&nh, cap * sizeof(RtStepRec)) != hipSuccess) return fail(RTROM_ENOMEM, "history allocation failed");
-  RT_HIP(hipMemsetAsync(nh, 0, cap * sizeof(RtStepRec), p->stream), "clear history");
-  if (p->dhist && p->hist_cap > 0)
-    RT_HIP(hipMemcpyAsync(nh, p->dhist, p->hist_cap * sizeof(RtStepRec), hipMemcpyDeviceToDevice, p->stream),
+  if (hipMallocAsync((void **)&nh, cap * sizeof(RtStepRec), s) != hipSuccess)
+    return fail(RTROM_ENOMEM, "history allocation failed");
+  RT_HIP(hipMemsetAsync(nh, 0, cap * sizeof(RtStepRec), s), "clear history");
+  if (p->dhist && p->hist_cap > 0) {
+    RT_HIP(hipMemcpyAsync(nh, p->dhist, p->hist_cap * sizeof(RtStepRec), hipMemcpyDeviceToDevice, s),
            "copy history");
-  RT_HIP(hipStreamSynchronize(p->stream), "history sync");
-  if (p->dhist) (void)hipFree(p->dhist);
+    RT_HIP(hipFreeAsync(p->dhist, s), "free history");
+  }
   p->dhist = nh;
   p->hist_cap = cap;
   p->hinst.hist = nh;
   p->hinst.hist_cap = (int)std::min<int64_t>(cap, 0x7fffffff);
-  return upload_inst(p);
+  RT_HIP(hipMemcpyAsync(p->dinst, &p->hinst, sizeof(Inst), hipMemcpyHostToDevice, s), "upload descriptor");
+  return RTROM_OK;
 }
 
 extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_problem **out) {
@@ -485,7 +489,7 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   ok = ok && H2D(I.st, &st0, sizeof(st0));
   ok = ok && H2D(I.ig.work, &rom_work_init[0], sizeof(RomWork)) && H2D(I.pc.work, &rom_work_init[1], sizeof(RomWork));
   if (!ok) return bail(RTROM_EDEVICE, "upload failed");
-  if (ensure_hist(p, 64) != RTROM_OK) {
+  if (ensure_hist(p, 1024, p->stream) != RTROM_OK) {
     std::string m = g_err;
     return bail(RTROM_ENOMEM, m);
   }
@@ -521,32 +525,39 @@ static rtrom_status read_state(const rtrom_problem *p, RtState *st) {
 static rtrom_status march_one_kind(rtrom_problem *const *ps, int n, int nsteps) {
   // all handles of one dimension; 1D: fused launches over the instance array
   hipStream_t s = ps[0]->stream;
-  for (int i = 0; i < n; ++i) {
-    rtrom_status e = ensure_hist(ps[i], ps[i]->steps + nsteps);
-    if (e != RTROM_OK) return e;
+  for (int i = 0; i < n; ++i)
     if (ps[i]->stream != s) RT_HIP(hipStreamSynchronize(ps[i]->stream), "sync member stream");
-  }
-  std::vector<RtState> before(n);
   for (int i = 0; i < n; ++i) {
-    rtrom_status e = read_state(ps[i], &before[i]);
+    rtrom_status e = ensure_hist(ps[i], ps[i]->steps + nsteps, s);
     if (e != RTROM_OK) return e;
+  }
+  // phase-machine states before the march (for the non-convergence count)
+  std::vector<RtState> before(n);
+  Inst *dinsts = nullptr;
+  RtState *dstates = nullptr;
+  if (ps[0]->d.dim == 1 && n > 1) {
+    std::vector<Inst> h(n);
+    for (int i = 0; i < n; ++i) h[i] = ps[i]->hinst;
+    RT_HIP(hipMallocAsync((void **)&dinsts, n * sizeof(Inst), s), "batch descriptors");
+    RT_HIP(hipMallocAsync((void **)&dstates, n * sizeof(RtState), s), "batch states");
+    RT_HIP(hipMemcpyAsync(dinsts, h.data(), n * sizeof(Inst), hipMemcpyHostToDevice, s), "upload batch");
+    RT_HIP(rt_launch_gather_states(dinsts, n, dstates, s), "gather states");
+    RT_HIP(hipMemcpyAsync(before.data(), dstates, n * sizeof(RtState), hipMemcpyDeviceToHost, s), "read states");
+    RT_HIP(hipStreamSynchronize(s), "state sync");
+  } else {
+    for (int i = 0; i < n; ++i) {
+      rtrom_status e = read_state(ps[i], &before[i]);
+      if (e != RTROM_OK) return e;
+    }
   }
   RT_HIP(hipEventRecord(ps[0]->ev0, s), "event");
   if (ps[0]->d.dim == 1) {
-    Inst *dinsts = nullptr;
     std::vector<int> nthr(n), ncs(n);
     for (int i = 0; i < n; ++i) {
       nthr[i] = ps[i]->hinst.nthr;
       ncs[i] = ps[i]->nc;
     }
-    if (n == 1) {
-      dinsts = ps[0]->dinst;
-    } else {
-      std::vector<Inst> h(n);
-      for (int i = 0; i < n; ++i) h[i] = ps[i]->hinst;
-      RT_HIP(hipMallocAsync((void **)&dinsts, n * sizeof(Inst), s), "batch descriptors");
-      RT_HIP(hipMemcpyAsync(dinsts, h.data(), n * sizeof(Inst), hipMemcpyHostToDevice, s), "upload batch");
-    }
+    if (n == 1) dinsts = ps[0]->dinst;
     int cmax;
     int nt = slab_launch_threads(nthr.data(), ncs.data(), n, &cmax);
     int nc_max = 0, any_rom = 0;
@@ -583,7 +594,6 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps, int n, int nsteps) 
         RT_HIP(hipStreamWaitEvent(s, ps[0]->ev_rom, 0), "event wait");
       }
     }
-    if (n > 1) RT_HIP(hipFreeAsync(dinsts, s), "free batch descriptors");
   } else {
     for (int i = 0; i < n; ++i) {
       int e = rt_plane_step(ps[i], nsteps);
@@ -595,14 +605,24 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps, int n, int nsteps) 
   rt_prof_collect();
   float ms = 0.0f;
   (void)hipEventElapsedTime(&ms, ps[0]->ev0, ps[0]->ev1);
+  std::vector<RtState> after(n);
+  if (dstates) {
+    RT_HIP(rt_launch_gather_states(dinsts, n, dstates, s), "gather states");
+    RT_HIP(hipMemcpyAsync(after.data(), dstates, n * sizeof(RtState), hipMemcpyDeviceToHost, s), "read states");
+    RT_HIP(hipFreeAsync(dstates, s), "free batch states");
+    RT_HIP(hipFreeAsync(dinsts, s), "free batch descriptors");
+    RT_HIP(hipStreamSynchronize(s), "state sync");
+  } else {
+    for (int i = 0; i < n; ++i) {
+      rtrom_status e = read_state(ps[i], &after[i]);
+      if (e != RTROM_OK) return e;
+    }
+  }
   rtrom_status res = RTROM_OK;
   for (int i = 0; i < n; ++i) {
     ps[i]->steps += nsteps;
     ps[i]->t_total += ms * 1e-3 / n;
-    RtState after;
-    rtrom_status e = read_state(ps[i], &after);
-    if (e != RTROM_OK) return e;
-    if (after.nonconv != before[i].nonconv) res = RTROM_ENOCONV;
+    if (after[i].nonconv != before[i].nonconv) res = RTROM_ENOCONV;
   }
   if (res == RTROM_ENOCONV) rt_set_error("a time step reached max_iter without meeting the tolerance");
   return res;

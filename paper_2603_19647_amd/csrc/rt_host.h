@@ -40,6 +40,7 @@ extern "C" hipError_t rt_launch_rom_update(const Inst *dinsts, int ninst, int nc
 extern "C" hipError_t rt_launch_slab_rhs(const Inst *dinsts, int ninst, int nthreads, int cmax,
                                          hipStream_t stream);
 extern "C" hipError_t rt_launch_slab_setup(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream);
+extern "C" hipError_t rt_launch_gather_states(const Inst *dinsts, int ninst, RtState *out, hipStream_t stream);
 
 // 2D
 int rt_plane_create(rtrom_problem *p);

@@ -9,6 +9,7 @@
 // Cells are owned with a stride (c = tid, tid + NT, ...) so that every pass
 // over a basis column is a coalesced stream.
 #pragma once
+#include "rt_arrow.h"
 #include "rt_common.h"
 
 struct RomSmem {
@@ -25,6 +26,9 @@ struct RomSmem {
   double av[RT_RMAX], a2v[RT_RMAX], utbv[RT_RMAX], pwv[RT_RMAX];  // projection coefficients
   double red[RT_MAXWAVES * 48];
   int perm[RT_KC];
+  arrow::Problem ap;         // secular core SVD: non-deflated poles
+  double ap_tau[RT_KC], ap_zh[RT_KC];
+  int ap_K[RT_KC], ap_defl[RT_KC], ap_ok;
   short pairs[RT_KC * RT_KC];  // round-robin pairing table (p, q) per round and slot
   int flag;
   int ibuf[4];
@@ -366,6 +370,71 @@ __device__ inline void core_svd(RomSmem &sm, int rows, int cols) {
 }
 
 // ---------------------------------------------------------------------------
+// Core SVD by the secular equation (rt_arrow.h) for K = [[diag S, a], [0, nu]]
+// (rows = r + 1) or [diag S, a] (rows = r, rank-deficient snapshot).  Wave 0
+// does the work, lane = root.  Leaves the same outputs as core_svd: singular
+// values descending in sm.sv[0..rows), left vectors in sm.Uc, right vectors in
+// sm.Vc (columns < rows).  Returns false (outputs untouched) when two
+// singular values of S coincide to rounding or nu is at rounding level: the
+// secular equation is then degenerate and the caller runs one-sided Jacobi.
+// ---------------------------------------------------------------------------
+__device__ inline bool core_svd_secular(RomSmem &sm, const double *S, const double *a, double nu, int r,
+                                        int rows, int cols) {
+  const int tid = threadIdx.x;
+  if (tid == 0) sm.ap_ok = arrow::build(sm.ap, sm.ap_defl, S, a, nu, r, rows, cols);
+  __syncthreads();
+  if (!sm.ap_ok) return false;
+  const arrow::Problem &P = sm.ap;
+  const int m = P.m;
+  if (tid < m) {
+    int K;
+    double tau;
+    arrow::root(P, tid, K, tau);
+    sm.ap_K[tid] = K;
+    sm.ap_tau[tid] = tau;
+  }
+  __syncthreads();
+  if (tid < m) sm.ap_zh[tid] = arrow::zhat(P, tid, sm.ap_K, sm.ap_tau);
+  __syncthreads();
+  // columns: secular roots (unsorted), then deflated rows (s_j, e_j, e_j);
+  // B holds u, V holds v, nrm the singular values
+  if (tid < m)
+    sm.nrm[tid] = arrow::vectors(P, tid, sm.ap_K, sm.ap_tau, sm.ap_zh, r, &sm.B[tid * RT_KC], 1,
+                                 &sm.V[tid * RT_KC], 1);
+  if (tid == 0) {
+    int c = m;
+    for (int j = 0; j < r; ++j)
+      if (sm.ap_defl[j]) {
+        for (int i = 0; i < rows; ++i) sm.B[c * RT_KC + i] = (i == j) ? 1.0 : 0.0;
+        for (int i = 0; i < cols; ++i) sm.V[c * RT_KC + i] = (i == j) ? 1.0 : 0.0;
+        sm.nrm[c] = S[j];
+        ++c;
+      }
+  }
+  __syncthreads();
+  // descending order, ties by column
+  if (tid < rows) {
+    const double mine = sm.nrm[tid];
+    int rk = 0;
+    for (int j = 0; j < rows; ++j) {
+      const double o = sm.nrm[j];
+      rk += (o > mine) || (o == mine && j < tid);
+    }
+    sm.perm[rk] = tid;
+  }
+  __syncthreads();
+  for (int e = tid; e < rows * RT_KC; e += blockDim.x) {
+    const int jj = e / RT_KC, i = e % RT_KC;
+    const int j = sm.perm[jj];
+    if (i == 0) sm.sv[jj] = sm.nrm[j];
+    if (i < rows) sm.Uc[i * RT_KC + jj] = sm.B[j * RT_KC + i];
+    if (i < cols) sm.Vc[i * RT_KC + jj] = sm.V[j * RT_KC + i];
+  }
+  __syncthreads();
+  return true;
+}
+
+// ---------------------------------------------------------------------------
 // Incremental SVD, small dense part (App. B, eq. svd_core), one workgroup:
 // sums the projection partials of the three grid passes in a fixed order,
 // builds the core [[diag S, U^T x], [0, ||p||]] and Q^T [W b] (Q = [U, p/||p||]),
@@ -451,7 +520,10 @@ __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, in
     sm.Mx[e] = m;
   }
   __syncthreads();
-  core_svd(sm, rows, cols);
+  // S and a as the secular path reads them (LDS); B above is Jacobi's input
+  if (tid < RT_RMAX) sm.a2v[tid] = tid < r ? R.S[tid] : 0.0;
+  __syncthreads();
+  if (!core_svd_secular(sm, sm.a2v, sm.av, nu, r, rows, cols)) core_svd(sm, rows, cols);
   if (tid == 0) {
     int k = rows;
     if (Wk.truncate) {

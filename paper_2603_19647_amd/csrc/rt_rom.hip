@@ -6,11 +6,14 @@
 #include "rt_rom.h"
 
 namespace {
-constexpr int BLK = 256;       // threads per block of the grid passes
+constexpr int BLK = 256;          // threads per block of the grid passes
+constexpr int PASS_CELLS = 2048;  // cells per block before a second block is used
 constexpr int MAX_PASS_BLK = 64;  // blocks per instance (cells are strided over them)
 
+// Each block reduces up to 2 r + 2 sums across its threads; fewer, fuller
+// blocks keep that cost small next to the cell work.
 __device__ __host__ __forceinline__ int pass_blocks(int nc) {
-  const int nb = (nc + BLK - 1) / BLK;
+  const int nb = (nc + PASS_CELLS - 1) / PASS_CELLS;
   return nb < MAX_PASS_BLK ? nb : MAX_PASS_BLK;
 }
 
@@ -334,5 +337,16 @@ extern "C" hipError_t rt_launch_rom(const Inst *dinsts, int ninst, int nc_max, i
 
 extern "C" hipError_t rt_launch_rom_update(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream) {
   hipLaunchKernelGGL(k_rom_update, dim3((nc_max + 255) / 256, ninst), dim3(256), 0, stream, dinsts);
+  return hipGetLastError();
+}
+
+// copies of every instance's phase-machine state, for one host read per batch
+__global__ void __launch_bounds__(256) k_gather_states(const Inst *__restrict__ insts, int ninst, RtState *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ninst) out[i] = *insts[i].st;
+}
+
+extern "C" hipError_t rt_launch_gather_states(const Inst *dinsts, int ninst, RtState *out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_gather_states, dim3((ninst + 255) / 256), dim3(256), 0, stream, dinsts, ninst, out);
   return hipGetLastError();
 }
