@@ -44,27 +44,50 @@ struct Problem {
 // d_a - d_b for poles with square roots sa, sb, to full relative accuracy
 RT_HD inline double pole_diff(double sa, double sb) { return (sa - sb) * (sa + sb); }
 
-// f, psi (poles <= k), phi (poles > k) and derivatives at tau (shifted by pole K)
+// 1/x: a true division on the host; on the device the hardware reciprocal
+// refined by two Newton steps (within about an ulp).
+RT_HD inline double rcp(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+#else
+  return 1.0 / x;
+#endif
+}
+
+// f, psi (poles <= k), phi (poles > k) and derivatives at tau, for poles
+// shifted by the origin pole: dd[j] = d_j - d_K.  dd and z are held by the
+// caller (registers on the device: every loop runs over the capacity).
 struct Eval {
   double f, psi, dpsi, phi, dphi, erretm;
 };
-RT_HD inline Eval evaluate(const Problem &P, int k, int K, double tau) {
+RT_HD inline Eval evaluate(const double (&dd)[N], const double (&z)[N], int m, int k, double tau) {
   Eval e{1.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int j = 0; j < P.m; ++j) {
-    const double del = pole_diff(P.s[j], P.s[K]) - tau;
-    const double t = P.z[j] / del;
-    const double term = P.z[j] * t;
-    if (j <= k) {
-      e.psi += term;
-      e.dpsi += t * t;
-    } else {
-      e.phi += term;
-      e.dphi += t * t;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    if (j < m) {
+      const double t = z[j] * rcp(dd[j] - tau);
+      const double term = z[j] * t;
+      if (j <= k) {
+        e.psi += term;
+        e.dpsi += t * t;
+      } else {
+        e.phi += term;
+        e.dphi += t * t;
+      }
+      e.erretm += fabs(term);
     }
-    e.erretm += fabs(term);
   }
   e.f = 1.0 + e.psi + e.phi;
   return e;
+}
+
+RT_HD inline void shifted_poles(const Problem &P, int K, double (&dd)[N]) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) dd[j] = (j < P.m) ? pole_diff(P.s[j], P.s[K]) : 0.0;
 }
 
 // Root k of the secular equation (k < m): returns the origin pole K and the
@@ -77,14 +100,20 @@ RT_HD inline void root(const Problem &P, int k, int &K_out, double &tau_out) {
     tau_out = P.z[0] * P.z[0];
     return;
   }
+  double z[N], dd[N];
   double z2 = 0.0;
-  for (int j = 0; j < m; ++j) z2 += P.z[j] * P.z[j];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    z[j] = (j < m) ? P.z[j] : 0.0;
+    z2 += z[j] * z[j];
+  }
   int K;
   double lo, hi;  // bracket in tau around the root, f(lo) < 0 < f(hi)
   if (k < m - 1) {
     const double gap = pole_diff(P.s[k + 1], P.s[k]);
     // f at the midpoint, shifted by the lower pole
-    const Eval mid = evaluate(P, k, k, 0.5 * gap);
+    shifted_poles(P, k, dd);
+    const Eval mid = evaluate(dd, z, m, k, 0.5 * gap);
     if (mid.f >= 0.0) {
       K = k;
       lo = 0.0;
@@ -93,30 +122,33 @@ RT_HD inline void root(const Problem &P, int k, int &K_out, double &tau_out) {
       K = k + 1;
       lo = -0.5 * gap;
       hi = 0.0;
+      shifted_poles(P, K, dd);
     }
   } else {
     K = m - 1;
     lo = 0.0;
     hi = z2;
+    shifted_poles(P, K, dd);
   }
+  // the two poles around the root, shifted by K
+  const double da = pole_diff(P.s[k], P.s[K]);
+  const double db = (k < m - 1) ? pole_diff(P.s[k + 1], P.s[K]) : 0.0;
   // the pole ends of the bracket are never evaluated: start inside
   double tau = 0.5 * (lo + hi);
   const double eps = 2.220446049250313e-16;
   for (int it = 0; it < 200; ++it) {
-    const Eval e = evaluate(P, k, K, tau);
+    const Eval e = evaluate(dd, z, m, k, tau);
     if (e.f == 0.0) break;
     if (e.f < 0.0) lo = tau;
     else hi = tau;
-    // converged when |f| is at the level of its own rounding error or the
-    // bracket can no longer shrink
-    if (fabs(e.f) <= eps * (1.0 + e.erretm)) break;
+    // converged when |f| is at the level of its own rounding error (about two
+    // ulps per term) or the bracket can no longer shrink
+    if (fabs(e.f) <= 2.0 * eps * (1.0 + e.erretm)) break;
     if (hi - lo <= 4.0 * eps * fmax(fabs(lo), fabs(hi))) break;
     // two-pole model: c + S1 / (da - x) + S2 / (db - x), fitted to value and
     // derivatives of psi (poles <= k) and phi (poles > k) at tau
-    const double da = pole_diff(P.s[k], P.s[K]);
     double x;
     if (k < m - 1) {
-      const double db = pole_diff(P.s[k + 1], P.s[K]);
       const double ra = da - tau, rb = db - tau;
       const double S1 = e.dpsi * ra * ra, S2 = e.dphi * rb * rb;
       const double c = e.f - S1 / ra - S2 / rb;
@@ -164,7 +196,7 @@ RT_HD inline double zhat(const Problem &P, int j, const int *K, const double *ta
   for (int i = 0; i < P.m - 1; ++i) {
     // pair the root below/above pole j with the pole difference of the same side
     const int dpole = i < j ? i : i + 1;
-    prod *= lam_minus_pole(P, K[i], tau[i], j) / pole_diff(P.s[dpole], P.s[j]);
+    prod *= lam_minus_pole(P, K[i], tau[i], j) * rcp(pole_diff(P.s[dpole], P.s[j]));
   }
   const double mag = sqrt(fabs(prod));
   return P.z[j] >= 0.0 ? mag : -mag;
@@ -215,7 +247,7 @@ RT_HD inline double vectors(const Problem &P, int k, const int *K, const double 
   for (int i = 0; i < P.cols; ++i) v[i * vs] = 0.0;
   double un = 0.0, vn = 1.0;
   for (int i = 0; i < P.m; ++i) {
-    const double ui = zh[i] / (pole_diff(P.s[i], P.s[Kk]) - tk);
+    const double ui = zh[i] * rcp(pole_diff(P.s[i], P.s[Kk]) - tk);
     u[P.row[i] * us] = ui;
     un += ui * ui;
     if (P.row[i] < r) {
@@ -225,7 +257,7 @@ RT_HD inline double vectors(const Problem &P, int k, const int *K, const double 
     }
   }
   v[r * vs] = -1.0;  // z^T (D - lambda)^{-1} z = -1 at a root
-  const double iu = 1.0 / sqrt(un), iv = 1.0 / sqrt(vn);
+  const double iu = rcp(sqrt(un)), iv = rcp(sqrt(vn));
   for (int i = 0; i < P.rows; ++i) u[i * us] *= iu;
   for (int i = 0; i < P.cols; ++i) v[i * vs] *= iv;
   return sqrt(P.s[Kk] * P.s[Kk] + tk);

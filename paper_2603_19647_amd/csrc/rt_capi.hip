@@ -274,7 +274,10 @@ static size_t slab_bytes(const rtrom_problem_desc *d, int nv) {
   for (int k = 0; k < 13; ++k) L.take(nc * 8);
   L.take(4 * nc * 8);
   L.take((size_t)nv * 8 * 6);
-  if (d->dim == 1) L.take((size_t)nv * nc * 8);  // 2D keeps its folded f in the plane buffers
+  if (d->dim == 1) {  // 2D keeps its folded f in the plane buffers
+    L.take((size_t)nv * nc * 8);
+    L.take((size_t)(nv / 2) * nc * 8);
+  }
   for (int r = 0; r < 2; ++r) {
     L.take((RT_RMAX + 1) * ld * 8);
     L.take((RT_RMAX + 1) * ld * 8);
@@ -405,6 +408,7 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   I.work = D(4 * (size_t)nc * 8);
   double *qbuf = D((size_t)nv * 8 * 6);
   I.f = d->dim == 1 ? D((size_t)nv * nc * 8) : nullptr;
+  I.fpart = d->dim == 1 ? D((size_t)(nv / 2) * nc * 8) : nullptr;
   RomDev *roms[2] = {&I.ig, &I.pc};
   RomWork rom_work_init[2];
   for (int r = 0; r < 2; ++r) {
@@ -498,7 +502,7 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
     if (rt_launch_slab_setup(p->dinst, 1, nc, p->stream) != hipSuccess) return bail(RTROM_EDEVICE, "setup launch failed");
     int cmax;
     int nt = slab_launch_threads(&I.nthr, &nc, 1, &cmax);
-    if (rt_launch_slab_rhs(p->dinst, 1, nt, cmax, p->stream) != hipSuccess)
+    if (rt_launch_slab_rhs(p->dinst, 1, nt, cmax, I.npair, nc, p->stream) != hipSuccess)
       return bail(RTROM_EDEVICE, "initial RHS launch failed");
   } else {
     if (upload_inst(p) != RTROM_OK) return bail(RTROM_EDEVICE, "upload descriptor failed");
@@ -560,9 +564,11 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps, int n, int nsteps) 
     if (n == 1) dinsts = ps[0]->dinst;
     int cmax;
     int nt = slab_launch_threads(nthr.data(), ncs.data(), n, &cmax);
-    int nc_max = 0, any_rom = 0;
+    int nc_max = 0, any_rom = 0, npair_max = 1, pairs_total = 0;
     for (int i = 0; i < n; ++i) {
       nc_max = std::max(nc_max, ncs[i]);
+      npair_max = std::max(npair_max, ps[i]->hinst.npair);
+      pairs_total += ps[i]->hinst.npair;
       any_rom |= ps[i]->d.method == RTROM_ROM_SI_DSA;
     }
     // Per step: SI solve, then the f-pass (main stream) and the ROM work
@@ -587,7 +593,7 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps, int n, int nsteps) 
         rt_prof_end(RT_K_ROM_UPDATE, s2);
       }
       rt_prof_begin(RT_K_SLAB_FPASS, s);
-      RT_HIP(rt_launch_slab_fpass(dinsts, n, nt, cmax, s), "f-pass launch");
+      RT_HIP(rt_launch_slab_fpass(dinsts, n, nt, cmax, npair_max, nc_max, pairs_total, s), "f-pass launch");
       rt_prof_end(RT_K_SLAB_FPASS, s);
       if (s2 != s) {
         RT_HIP(hipEventRecord(ps[0]->ev_rom, s2), "event");
@@ -743,7 +749,7 @@ extern "C" rtrom_status rtrom_set_inflow(rtrom_problem *p, const double *g) {
   if (p->d.dim == 1) {
     int cmax;
     int nt = slab_launch_threads(&p->hinst.nthr, &p->nc, 1, &cmax);
-    RT_HIP(rt_launch_slab_rhs(p->dinst, 1, nt, cmax, p->stream), "RHS launch");
+    RT_HIP(rt_launch_slab_rhs(p->dinst, 1, nt, cmax, p->hinst.npair, p->nc, p->stream), "RHS launch");
   } else {
     int s = rt_plane_rhs(p);
     if (s != RTROM_OK) return (rtrom_status)s;

@@ -87,6 +87,7 @@ struct Inst {
   const double *dsa_diag, *dsa_wx, *dsa_wy;      // 2D 5-point stencil
   // state
   double *f;        // [nv][nc]
+  double *fpart;    // 1D: [npair][nc] per-pair moments of the f-pass
   double *rho;      // rho^n
   double *bt2[2];   // b~ double buffer: the next step reads bt2[steps & 1]
                     // and its f-pass writes the other one

@@ -33,12 +33,12 @@ struct rtrom_problem {
 // launch helpers implemented in the .hip kernel files
 extern "C" hipError_t rt_launch_slab_si(const Inst *dinsts, int ninst, int nthreads, int cmax,
                                         hipStream_t stream);
-extern "C" hipError_t rt_launch_slab_fpass(const Inst *dinsts, int ninst, int nthreads, int cmax,
-                                           hipStream_t stream);
+extern "C" hipError_t rt_launch_slab_fpass(const Inst *dinsts, int ninst, int nthreads, int cmax, int npair_max,
+                                           int nc_max, int pairs_total, hipStream_t stream);
 extern "C" hipError_t rt_launch_rom(const Inst *dinsts, int ninst, int nc_max, int any_rom, hipStream_t s);
 extern "C" hipError_t rt_launch_rom_update(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream);
-extern "C" hipError_t rt_launch_slab_rhs(const Inst *dinsts, int ninst, int nthreads, int cmax,
-                                         hipStream_t stream);
+extern "C" hipError_t rt_launch_slab_rhs(const Inst *dinsts, int ninst, int nthreads, int cmax, int npair_max,
+                                         int nc_max, hipStream_t stream);
 extern "C" hipError_t rt_launch_slab_setup(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream);
 extern "C" hipError_t rt_launch_gather_states(const Inst *dinsts, int ninst, RtState *out, hipStream_t stream);
 

@@ -621,9 +621,12 @@ __global__ void __launch_bounds__(BLK) k_romapply_coef(RomDev R, const int *rank
   for (int k = 0; k < RT_RMAX; ++k) p[k] = 0.0;
   if (c < nc) {
     const double v = rhs[c];
+    // unconditional loads (finite columns past the rank), masked
 #pragma unroll
-    for (int k = 0; k < RT_RMAX; ++k)
-      if (k < rank) p[k] = R.U[(size_t)k * ld + c] * v;
+    for (int k = 0; k < RT_RMAX; ++k) {
+      const double u = R.U[(size_t)k * ld + c];
+      p[k] = k < rank ? u * v : 0.0;
+    }
   }
   __shared__ double red[(BLK / 64) * RT_RMAX], out[RT_RMAX];
   wg_sum_fast<RT_RMAX>(p, red, out);
@@ -635,20 +638,20 @@ __global__ void __launch_bounds__(256) k_romapply_solve(RomDev R, const int *ran
   __shared__ double vec[RT_RMAX], scratch[256];
   sum_partials(part, nblk, rank, vec, scratch);
   lu_solve_wave(R.LU, R.perm, rank, vec);  // ends with a barrier
-  if ((int)threadIdx.x < rank) coef[threadIdx.x] = vec[threadIdx.x];
+  if ((int)threadIdx.x < RT_RMAX) coef[threadIdx.x] = (int)threadIdx.x < rank ? vec[threadIdx.x] : 0.0;
 }
 __global__ void __launch_bounds__(BLK) k_romapply_expand(RomDev R, const int *rankp, int ld, int nc,
                                                         const double *coef, double *out) {
   const int rank = *rankp;
   const int c = blockIdx.x * BLK + threadIdx.x;
   if (c < nc) {
+    // every column loaded; coef is zero past the rank
     double u[RT_RMAX];
 #pragma unroll
-    for (int k = 0; k < RT_RMAX; ++k) u[k] = k < rank ? R.U[(size_t)k * ld + c] : 0.0;
+    for (int k = 0; k < RT_RMAX; ++k) u[k] = R.U[(size_t)k * ld + c];
     double v = 0.0;
 #pragma unroll
-    for (int k = 0; k < RT_RMAX; ++k)
-      if (k < rank) v = rt_fma(u[k], coef[k], v);
+    for (int k = 0; k < RT_RMAX; ++k) v = rt_fma(u[k], coef[k], v);
     out[c] = v;
   }
 }

@@ -80,66 +80,81 @@ __device__ __forceinline__ void wg_sum_fast(const double (&v)[NV], double *red, 
 
 // ---------------------------------------------------------------------------
 // LU with partial pivoting of the n x n matrix in A (stride RT_KC, LDS), by
-// wave 0 (lanes over rows / columns).  Pivot: the first row of largest
-// |a_ik|; a pivot below 1e-14 max|A| marks the system singular.  Writes
-// factors (stride RT_RMAX) and the final row permutation to global memory and
-// returns 1 if singular.  Must be called by the whole workgroup.
+// wave 0.  Lane i keeps row i in registers for the whole factorisation; rows
+// are not moved: step k picks the pivot among the rows not yet used (largest
+// |a_ik|, lowest row on ties), reads the pivot row with lane reads and
+// eliminates below it in place, so every row keeps its own multipliers, as in
+// a factorisation with row interchanges.  A pivot below 1e-14 max|A| marks
+// the system singular.  Writes the factors in pivot order (stride RT_RMAX)
+// and the row permutation to global memory and returns 1 if singular.  Must
+// be called by the whole workgroup; A is left unchanged.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double dpp_max16(double v) {
+  v = fmax(v, dpp_d<0xB1>(v));   // quad_perm [1,0,3,2]
+  v = fmax(v, dpp_d<0x4E>(v));   // quad_perm [2,3,0,1]
+  v = fmax(v, dpp_d<0x141>(v));  // row_half_mirror
+  v = fmax(v, dpp_d<0x140>(v));  // row_mirror
+  return v;
+}
+__device__ __forceinline__ double lane_read(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ inline int lu_factor_wave(double *A, int *perm_lds, int n, double *LUg, int *permg, int *flag) {
-  const int lane = threadIdx.x;
+  static_assert(RT_RMAX <= 32, "rows live in the first two DPP rows of the wave");
+  (void)perm_lds;
   if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const bool mine = lane < n;
+    double row[RT_RMAX];
     double m = 0.0;
-    if (lane < n)
-      for (int j = 0; j < n; ++j) m = fmax(m, fabs(A[lane * RT_KC + j]));
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) m = fmax(m, __shfl_xor(m, off, 64));
-    const double amax = m;
-    int bad = (amax == 0.0);
-    if (lane < RT_KC) perm_lds[lane] = lane;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    for (int k = 0; k < n; ++k) {
-      // first index of the largest |a_ik|, i >= k
-      double v = (lane >= k && lane < n) ? fabs(A[lane * RT_KC + k]) : -1.0;
-      int idx = lane;
-#pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const double ov = __shfl_xor(v, off, 64);
-        const int oi = __shfl_xor(idx, off, 64);
-        if (ov > v || (ov == v && oi < idx)) {
-          v = ov;
-          idx = oi;
-        }
-      }
-      const int p = idx;
-      if (p != k && lane < n) {
-        const double t = A[k * RT_KC + lane];
-        A[k * RT_KC + lane] = A[p * RT_KC + lane];
-        A[p * RT_KC + lane] = t;
-      }
-      if (p != k && lane == 0) {
-        const int t = perm_lds[k];
-        perm_lds[k] = perm_lds[p];
-        perm_lds[p] = t;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      const double akk = A[k * RT_KC + k];
-      if (akk == 0.0 || fabs(akk) < 1e-14 * amax) {
-        bad = 1;
-        continue;
-      }
-      if (lane > k && lane < n) {
-        const double l = A[lane * RT_KC + k] / akk;
-        A[lane * RT_KC + k] = l;
-        for (int j = k + 1; j < n; ++j) A[lane * RT_KC + j] = rt_fma(-l, A[k * RT_KC + j], A[lane * RT_KC + j]);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
+    for (int j = 0; j < RT_RMAX; ++j) {
+      row[j] = (mine && j < n) ? A[lane * RT_KC + j] : 0.0;
+      m = fmax(m, fabs(row[j]));
     }
-    if (lane < n) {
-      for (int j = 0; j < n; ++j) LUg[lane * RT_RMAX + j] = A[lane * RT_KC + j];
-      permg[lane] = perm_lds[lane];
+    m = dpp_max16(m);
+    const double amax = fmax(lane_read(m, 0), lane_read(m, 16));
+    int bad = (amax == 0.0);
+    bool active = mine;
+    int pos = 0;
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k) {
+      if (k < n) {
+        const double v = active ? fabs(row[k]) : -1.0;
+        const double w = dpp_max16(v);
+        const double vmax = fmax(lane_read(w, 0), lane_read(w, 16));
+        const unsigned long long cand = __ballot(active && v == vmax);
+        // no candidate only for a NaN column: take the lowest unused row
+        const int p = cand ? __builtin_ctzll(cand) : __builtin_ctzll(__ballot(active));
+        if (!cand) bad = 1;
+        if (lane == p) {
+          active = false;
+          pos = k;
+        }
+        const double akk = lane_read(row[k], p);
+        if (akk == 0.0 || fabs(akk) < 1e-14 * amax) {
+          bad = 1;
+          continue;
+        }
+        const double rinv = 1.0 / akk;
+        const double l = row[k] * rinv;
+        if (active) row[k] = l;
+#pragma unroll
+        for (int j = k + 1; j < RT_RMAX; ++j)
+          if (j < n) {
+            const double pj = lane_read(row[j], p);
+            if (active) row[j] = rt_fma(-l, pj, row[j]);
+          }
+      }
+    }
+    if (mine) {
+#pragma unroll
+      for (int j = 0; j < RT_RMAX; ++j)
+        if (j < n) LUg[pos * RT_RMAX + j] = row[j];
+      permg[pos] = lane;
     }
     if (lane == 0) *flag = bad;
   }
@@ -180,29 +195,35 @@ __device__ inline void sum_partials(const double *part, int nb, int ncol, double
 __device__ inline void lu_solve_wave(const double *LU, const int *perm, int n, double *vec) {
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
+    // every load is unconditional (clamped row), so they are all in flight
+    // at once; entries outside the n x n factors are masked to zero
+    const int li = lane < RT_RMAX ? lane : RT_RMAX - 1;
+    const bool mine = lane < n;
     double row[RT_RMAX];
 #pragma unroll
-    for (int j = 0; j < RT_RMAX; ++j) row[j] = (lane < n && j < n) ? LU[lane * RT_RMAX + j] : 0.0;
-    double s = (lane < n) ? vec[perm[lane]] : 0.0;
+    for (int j = 0; j < RT_RMAX; ++j) {
+      const double v = LU[li * RT_RMAX + j];
+      row[j] = (mine && j < n) ? v : 0.0;
+    }
+    const double b = vec[perm[li]];
+    double s = mine ? b : 0.0;
+    // forward substitution (unit lower factor): component j is final on lane j
 #pragma unroll
     for (int j = 0; j < RT_RMAX; ++j) {
-      if (j < n) {
-        const double bj = __shfl(s, j, 64);
-        if (lane > j) s = rt_fma(-row[j], bj, s);
-      }
+      const double bj = lane_read(s, j);
+      if (lane > j) s = rt_fma(-row[j], bj, s);
     }
 #pragma unroll
     for (int j = RT_RMAX - 1; j >= 0; --j) {
       if (j < n) {
-        double xj = (lane == j) ? s / row[j] : 0.0;
-        xj = __shfl(xj, j, 64);
+        const double xj = lane_read(s, j) / lane_read(row[j], j);
         if (lane == j) s = xj;
         if (lane < j) s = rt_fma(-row[j], xj, s);
       }
     }
     // every lane read vec[perm[lane]] before any lane writes
     __builtin_amdgcn_wave_barrier();
-    if (lane < n) vec[lane] = s;
+    if (mine) vec[lane] = s;
   }
   __syncthreads();
 }
@@ -215,31 +236,47 @@ __device__ inline void lu_solve_wave(const double *LU, const int *perm, int n, d
 __device__ inline void rom_apply(const RomDev &R, int rank, int ld, int nc, int NT, const double *rhs,
                                  double *out, double *red, double *vec) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const bool act = (int)threadIdx.x < NT;
+  // U^T rhs four columns at a time.  The basis keeps RT_RMAX + 1 allocated
+  // columns with finite entries, so the loads past the rank are unconditional
+  // (all in flight together) and their sums are simply not used.
   for (int k0 = 0; k0 < rank; k0 += 4) {
     double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int c = threadIdx.x; c < nc && (int)threadIdx.x < NT; c += NT) {
+    for (int c = threadIdx.x; c < nc && act; c += NT) {
       const double v = rhs[c];
+      double u[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (k0 + q < rank) s[q] = rt_fma(R.U[(size_t)(k0 + q) * ld + c], v, s[q]);
+      for (int q = 0; q < 4; ++q) u[q] = R.U[(size_t)(k0 + q) * ld + c];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s[q] = rt_fma(u[q], v, s[q]);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const double t = wave_sum_fast(s[q]);
-      if (lane == 0 && k0 + q < rank) red[wave * RT_RMAX + k0 + q] = t;
+      if (lane == 0) red[wave * RT_RMAX + k0 + q] = t;
     }
   }
   __syncthreads();
-  if ((int)threadIdx.x < rank) {
+  if ((int)threadIdx.x < RT_RMAX) {
     double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += red[w * RT_RMAX + threadIdx.x];
-    vec[threadIdx.x] = s;
+    if ((int)threadIdx.x < rank)
+      for (int w = 0; w < nw; ++w) s += red[w * RT_RMAX + threadIdx.x];
+    vec[threadIdx.x] = s;  // zero past the rank
   }
   __syncthreads();
   lu_solve_wave(R.LU, R.perm, rank, vec);
-  for (int c = threadIdx.x; c < nc && (int)threadIdx.x < NT; c += NT) {
+  // expansion U c, five columns per batch of loads (c_k = 0 past the rank);
+  // the batches stay a loop to keep the caller's registers free
+  for (int c = threadIdx.x; c < nc && act; c += NT) {
     double v = 0.0;
-    for (int k = 0; k < rank; ++k) v = rt_fma(R.U[(size_t)k * ld + c], vec[k], v);
+#pragma unroll 1
+    for (int k0 = 0; k0 < RT_RMAX; k0 += 5) {
+      double u[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) u[q] = R.U[(size_t)(k0 + q) * ld + c];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) v = rt_fma(u[q], vec[k0 + q], v);
+    }
     out[c] = v;
   }
   __syncthreads();
@@ -381,7 +418,50 @@ __device__ inline void core_svd(RomSmem &sm, int rows, int cols) {
 __device__ inline bool core_svd_secular(RomSmem &sm, const double *S, const double *a, double nu, int r,
                                         int rows, int cols) {
   const int tid = threadIdx.x;
-  if (tid == 0) sm.ap_ok = arrow::build(sm.ap, sm.ap_defl, S, a, nu, r, rows, cols);
+  // The secular problem, built by wave 0 with lane j on core row j: the same
+  // problem arrow::build forms with its loop (deflation threshold from the
+  // same serial sum, poles in ascending order, equal-pole test against the
+  // next smaller retained pole).
+  if (tid < 64) {
+    const int j = tid;
+    const double eps = 2.220446049250313e-16;
+    double z2 = rows > r ? nu * nu : 0.0;
+    for (int i = 0; i < r; ++i) z2 += a[i] * a[i];
+    const double scale = fmax(r > 0 ? S[0] : 0.0, sqrt(z2));
+    const double tolz = 8.0 * eps * scale;
+    const bool in = j < r;
+    const bool keep = in && !(fabs(a[j]) <= tolz);
+    const unsigned long long km = __ballot(keep);
+    const int base = rows > r ? 1 : 0;  // the nu row is pole 0
+    const unsigned long long above = (j < 63) ? (km >> (j + 1)) : 0ull;
+    bool clash = false;
+    if (keep) {
+      const int pos = base + __popcll(above);
+      sm.ap.s[pos] = S[j];
+      sm.ap.z[pos] = a[j];
+      sm.ap.row[pos] = j;
+      if (above) {
+        const int jn = j + 1 + __builtin_ctzll(above);
+        clash = S[j] - S[jn] <= 8.0 * eps * S[j];
+      } else if (base) {
+        clash = S[j] <= 8.0 * eps * S[j];
+      }
+    }
+    if (in) sm.ap_defl[j] = !keep;
+    const bool any_clash = __ballot(clash) != 0ull;
+    if (j == 0) {
+      if (base) {
+        sm.ap.s[0] = 0.0;
+        sm.ap.z[0] = nu;
+        sm.ap.row[0] = r;
+      }
+      sm.ap.m = base + __popcll(km);
+      sm.ap.rows = rows;
+      sm.ap.cols = cols;
+      sm.ap.scale = scale;
+      sm.ap_ok = (rows == r || nu > tolz) && !any_clash;
+    }
+  }
   __syncthreads();
   if (!sm.ap_ok) return false;
   const arrow::Problem &P = sm.ap;
@@ -401,15 +481,16 @@ __device__ inline bool core_svd_secular(RomSmem &sm, const double *S, const doub
   if (tid < m)
     sm.nrm[tid] = arrow::vectors(P, tid, sm.ap_K, sm.ap_tau, sm.ap_zh, r, &sm.B[tid * RT_KC], 1,
                                  &sm.V[tid * RT_KC], 1);
-  if (tid == 0) {
-    int c = m;
-    for (int j = 0; j < r; ++j)
-      if (sm.ap_defl[j]) {
-        for (int i = 0; i < rows; ++i) sm.B[c * RT_KC + i] = (i == j) ? 1.0 : 0.0;
-        for (int i = 0; i < cols; ++i) sm.V[c * RT_KC + i] = (i == j) ? 1.0 : 0.0;
-        sm.nrm[c] = S[j];
-        ++c;
-      }
+  if (tid < 64) {
+    const bool d = tid < r && sm.ap_defl[tid];
+    const unsigned long long dm = __ballot(d);
+    if (d) {
+      const int j = tid;
+      const int c = m + __popcll(dm & ((1ull << j) - 1ull));
+      for (int i = 0; i < rows; ++i) sm.B[c * RT_KC + i] = (i == j) ? 1.0 : 0.0;
+      for (int i = 0; i < cols; ++i) sm.V[c * RT_KC + i] = (i == j) ? 1.0 : 0.0;
+      sm.nrm[c] = S[j];
+    }
   }
   __syncthreads();
   // descending order, ties by column
@@ -546,9 +627,12 @@ __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, in
     for (int q = 0; q < cols; ++q) v = rt_fma(sm.Mx[i * RT_KC + q], sm.Vc[q * RT_KC + j], v);
     sm.T1[i * RT_KC + j] = v;
   }
+  // the rotation for k_rom_update, zero outside rows x k (left) and cols x k
+  // (right): that kernel multiplies over the full capacity
   for (int e = tid; e < RT_KC * RT_KC; e += NT) {
-    P->Uc[e] = sm.Uc[e];
-    P->Vc[e] = sm.Vc[e];
+    const int i = e / RT_KC, j = e % RT_KC;
+    P->Uc[e] = (i < rows && j < k) ? sm.Uc[e] : 0.0;
+    P->Vc[e] = (i < cols && j < k) ? sm.Vc[e] : 0.0;
   }
   __syncthreads();
   for (int e = tid; e < k * k; e += NT) {
@@ -577,52 +661,45 @@ __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, in
 
 // Second half: U <- [U, p/nu] Uc[:, :k], W <- [W, b] Vc[:, :k] for one cell.
 // Reads every old column of the cell before writing, so it works in place.
+// Uc and Vc (LDS, stride RT_KC, at least RT_KC * RT_KC + 4 entries) are zero
+// outside the core, and the old basis entries past r are masked, so every
+// product runs over the full capacity without branches; the outputs go in
+// blocks of four columns, which bounds the registers the LDS reads take.
+__device__ __forceinline__ void rotate_block(const double (&old)[RT_RMAX], double e, const double *Cc, int r,
+                                             int k, double *X, int ld, int c) {
+#pragma unroll 1
+  for (int j0 = 0; j0 < k; j0 += 4) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < RT_RMAX; ++q)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) acc[jj] = rt_fma(old[q], Cc[q * RT_KC + j0 + jj], acc[jj]);
+    // row r: the new direction (p / nu for U, b for W)
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) acc[jj] = rt_fma(e, Cc[r * RT_KC + j0 + jj], acc[jj]);
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj)
+      if (j0 + jj < k) X[(size_t)(j0 + jj) * ld + c] = acc[jj];
+  }
+}
+
 __device__ __forceinline__ void isvd_rotate_cell(const RomDev &R, const RomPend &P, const double *Uc,
                                                  const double *Vc, int ld, int c) {
   const int r = P.r_old, k = P.k;
-  // the cell's old basis rows, loaded up front (one memory latency, not r)
   double old[RT_RMAX];
 #pragma unroll
-  for (int q = 0; q < RT_RMAX; ++q) old[q] = q < r ? R.U[(size_t)q * ld + c] : 0.0;
-  double acc[RT_RMAX];
-#pragma unroll
-  for (int j = 0; j < RT_RMAX; ++j) acc[j] = 0.0;
-#pragma unroll
-  for (int q = 0; q < RT_RMAX; ++q)
-    if (q < r) {
-#pragma unroll
-      for (int j = 0; j < RT_RMAX; ++j)
-        if (j < k) acc[j] = rt_fma(old[q], Uc[q * RT_KC + j], acc[j]);
-    }
-  if (!P.deficient) {
-    const double e = P.p[c] * P.inv_nu;
-#pragma unroll
-    for (int j = 0; j < RT_RMAX; ++j)
-      if (j < k) acc[j] = rt_fma(e, Uc[r * RT_KC + j], acc[j]);
+  for (int q = 0; q < RT_RMAX; ++q) {
+    const double v = R.U[(size_t)q * ld + c];
+    old[q] = q < r ? v : 0.0;
   }
+  // inv_nu = 0 for a rank-deficient snapshot (row r of Uc is zero then too)
+  rotate_block(old, P.p[c] * P.inv_nu, Uc, r, k, R.U, ld, c);
 #pragma unroll
-  for (int j = 0; j < RT_RMAX; ++j)
-    if (j < k) R.U[(size_t)j * ld + c] = acc[j];
-#pragma unroll
-  for (int q = 0; q < RT_RMAX; ++q) old[q] = q < r ? R.W[(size_t)q * ld + c] : 0.0;
-#pragma unroll
-  for (int j = 0; j < RT_RMAX; ++j) acc[j] = 0.0;
-#pragma unroll
-  for (int q = 0; q < RT_RMAX; ++q)
-    if (q < r) {
-#pragma unroll
-      for (int j = 0; j < RT_RMAX; ++j)
-        if (j < k) acc[j] = rt_fma(old[q], Vc[q * RT_KC + j], acc[j]);
-    }
-  {
-    const double bv = P.b[c];
-#pragma unroll
-    for (int j = 0; j < RT_RMAX; ++j)
-      if (j < k) acc[j] = rt_fma(bv, Vc[r * RT_KC + j], acc[j]);
+  for (int q = 0; q < RT_RMAX; ++q) {
+    const double v = R.W[(size_t)q * ld + c];
+    old[q] = q < r ? v : 0.0;
   }
-#pragma unroll
-  for (int j = 0; j < RT_RMAX; ++j)
-    if (j < k) R.W[(size_t)j * ld + c] = acc[j];
+  rotate_block(old, P.b[c], Vc, r, k, R.W, ld, c);
 }
 
 // s_r / sum(s) of the retained values (eq. ig_stop, eq. pc_stop)

@@ -7,11 +7,11 @@
 
 namespace {
 constexpr int BLK = 256;          // threads per block of the grid passes
-constexpr int PASS_CELLS = 2048;  // cells per block before a second block is used
+constexpr int PASS_CELLS = 256;   // cells per block before a second block is used
 constexpr int MAX_PASS_BLK = 64;  // blocks per instance (cells are strided over them)
 
-// Each block reduces up to 2 r + 2 sums across its threads; fewer, fuller
-// blocks keep that cost small next to the cell work.
+// One cell per thread up to 64 blocks an instance: the passes are short and
+// latency-bound, so an instance's cells are spread wide.
 __device__ __host__ __forceinline__ int pass_blocks(int nc) {
   const int nb = (nc + PASS_CELLS - 1) / PASS_CELLS;
   return nb < MAX_PASS_BLK ? nb : MAX_PASS_BLK;
@@ -160,13 +160,19 @@ __global__ void __launch_bounds__(BLK) k_rom_pass1(const Inst *__restrict__ inst
     }
     part[2 * RT_RMAX] = rt_fma(xv, xv, part[2 * RT_RMAX]);
     part[2 * RT_RMAX + 1] = rt_fma(xv, bv, part[2 * RT_RMAX + 1]);
+    // all basis loads unconditional (finite columns past the rank, masked),
+    // so they are in flight together; the sums past the rank stay zero
+    double u[RT_RMAX];
 #pragma unroll
-    for (int k = 0; k < RT_RMAX; ++k)
-      if (k < r) {
-        const double u = R.U[(size_t)k * ld + c];
-        part[k] = rt_fma(u, xv, part[k]);
-        part[RT_RMAX + k] = rt_fma(u, bv, part[RT_RMAX + k]);
-      }
+    for (int k = 0; k < RT_RMAX; ++k) {
+      const double v = R.U[(size_t)k * ld + c];
+      u[k] = k < r ? v : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k) {
+      part[k] = rt_fma(u[k], xv, part[k]);
+      part[RT_RMAX + k] = rt_fma(u[k], bv, part[RT_RMAX + k]);
+    }
   }
   wg_sum_fast<2 * RT_RMAX + 2>(part, red, out);
   if (threadIdx.x < 2 * RT_RMAX + 2) W.part1[blockIdx.x * RT_NPART + threadIdx.x] = out[threadIdx.x];
@@ -180,29 +186,30 @@ __global__ void __launch_bounds__(BLK) k_rom_pass2(const Inst *__restrict__ inst
   if (!W.active || (int)blockIdx.x >= W.nblk) return;
   __shared__ double red[(BLK / 64) * 2 * RT_RMAX], out[2 * RT_RMAX], av[RT_RMAX], scratch[BLK];
   const int r = W.r, ld = I.ld;
-  sum_partials(W.part1, W.nblk, r, av, scratch);
+  // every column: pass 1 left zero sums past the rank, so av is zero there
+  sum_partials(W.part1, W.nblk, RT_RMAX, av, scratch);
   double part[2 * RT_RMAX];
 #pragma unroll
   for (int k = 0; k < 2 * RT_RMAX; ++k) part[k] = 0.0;
   for (int c = blockIdx.x * BLK + threadIdx.x; c < I.nc; c += W.nblk * BLK) {
-    // all loads issued up front; the arithmetic keeps its order
+    // all loads issued up front and unconditionally (masked past the rank);
+    // the arithmetic keeps its order
     double u[RT_RMAX], wv[RT_RMAX];
 #pragma unroll
     for (int k = 0; k < RT_RMAX; ++k) {
-      u[k] = k < r ? R.U[(size_t)k * ld + c] : 0.0;
-      wv[k] = k < r ? R.W[(size_t)k * ld + c] : 0.0;
+      const double a = R.U[(size_t)k * ld + c], b = R.W[(size_t)k * ld + c];
+      u[k] = k < r ? a : 0.0;
+      wv[k] = k < r ? b : 0.0;
     }
     double v = W.x[c];
 #pragma unroll
-    for (int k = 0; k < RT_RMAX; ++k)
-      if (k < r) v = rt_fma(-u[k], av[k], v);
+    for (int k = 0; k < RT_RMAX; ++k) v = rt_fma(-u[k], av[k], v);
     W.p[c] = v;
 #pragma unroll
-    for (int k = 0; k < RT_RMAX; ++k)
-      if (k < r) {
-        part[k] = rt_fma(u[k], v, part[k]);
-        part[RT_RMAX + k] = rt_fma(wv[k], v, part[RT_RMAX + k]);
-      }
+    for (int k = 0; k < RT_RMAX; ++k) {
+      part[k] = rt_fma(u[k], v, part[k]);
+      part[RT_RMAX + k] = rt_fma(wv[k], v, part[RT_RMAX + k]);
+    }
   }
   wg_sum_fast<2 * RT_RMAX>(part, red, out);
   if (threadIdx.x < 2 * RT_RMAX) W.part2[blockIdx.x * RT_NPART + threadIdx.x] = out[threadIdx.x];
@@ -216,16 +223,18 @@ __global__ void __launch_bounds__(BLK) k_rom_pass3(const Inst *__restrict__ inst
   if (!W.active || (int)blockIdx.x >= W.nblk) return;
   __shared__ double red[(BLK / 64) * 2], out[2], a2[RT_RMAX], scratch[BLK];
   const int r = W.r, ld = I.ld;
-  sum_partials(W.part2, W.nblk, r, a2, scratch);
+  sum_partials(W.part2, W.nblk, RT_RMAX, a2, scratch);  // zero past the rank
   double part[2] = {0.0, 0.0};
   for (int c = blockIdx.x * BLK + threadIdx.x; c < I.nc; c += W.nblk * BLK) {
     double u[RT_RMAX];
 #pragma unroll
-    for (int k = 0; k < RT_RMAX; ++k) u[k] = k < r ? R.U[(size_t)k * ld + c] : 0.0;
+    for (int k = 0; k < RT_RMAX; ++k) {
+      const double a = R.U[(size_t)k * ld + c];
+      u[k] = k < r ? a : 0.0;
+    }
     double v = W.p[c];
 #pragma unroll
-    for (int k = 0; k < RT_RMAX; ++k)
-      if (k < r) v = rt_fma(-u[k], a2[k], v);
+    for (int k = 0; k < RT_RMAX; ++k) v = rt_fma(-u[k], a2[k], v);
     W.p[c] = v;
     part[0] = rt_fma(v, v, part[0]);
     part[1] = rt_fma(v, W.b[c], part[1]);
@@ -295,10 +304,15 @@ __global__ void __launch_bounds__(256) k_rom_core(const Inst *__restrict__ insts
 
 // ---------------------------------------------------------------------------
 // k_rom_update: U <- [U, p/nu] Uc, W <- [W, b] Vc, one thread per cell.
+// One-wave blocks: every thread reads all rotation coefficients from LDS, so
+// spreading the cells over more compute units spreads that LDS traffic.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_rom_update(const Inst *__restrict__ insts) {
+constexpr int UPD_BLK = 64;
+__global__ void __launch_bounds__(UPD_BLK) k_rom_update(const Inst *__restrict__ insts) {
   const Inst &I = insts[blockIdx.y];
-  __shared__ double uc[2][RT_KC * RT_KC], vc[2][RT_KC * RT_KC];
+  // four spare entries: the column blocks of the rotation read up to three
+  // entries past the last row (discarded products)
+  __shared__ double uc[2][RT_KC * RT_KC + 4], vc[2][RT_KC * RT_KC + 4];
   if (I.method != RT_ROM) return;
   if ((int)(blockIdx.x * blockDim.x) >= I.nc) return;
   const RomPend *P[2] = {I.ig.pend, I.pc.pend};
@@ -336,7 +350,7 @@ extern "C" hipError_t rt_launch_rom(const Inst *dinsts, int ninst, int nc_max, i
 }
 
 extern "C" hipError_t rt_launch_rom_update(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream) {
-  hipLaunchKernelGGL(k_rom_update, dim3((nc_max + 255) / 256, ninst), dim3(256), 0, stream, dinsts);
+  hipLaunchKernelGGL(k_rom_update, dim3((nc_max + UPD_BLK - 1) / UPD_BLK, ninst), dim3(UPD_BLK), 0, stream, dinsts);
   return hipGetLastError();
 }
 

@@ -8,6 +8,8 @@
 // evaluated as a workgroup-wide affine prefix scan (wg_scan2).  The two
 // ordinates of a mirror pair (mu, -mu) share a_i and the reciprocal of
 // (sigma_t + 1/dt + |mu|/h) and are scanned together in opposite directions.
+#include <algorithm>
+
 #include "rt_common.h"
 #include "rt_rom.h"
 
@@ -275,15 +277,21 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
 }
 
 // ---------------------------------------------------------------------------
-// k_fpass_slab: f^n from rho^n (eq. sweep_to_obtain_f) and the right-hand side
-// b~^n = sum_j w_j sweep_j(f^n_j / dt + G, g) of the next step (Sec. 2.3), in
-// one traversal per ordinate pair, into the b~ buffer the step did not read.
-// rhs_only: skip the first sweep and rebuild the b~ the next step reads from
-// the stored f (creation, or a new inflow).
+// k_fpass_pair: f^n from rho^n (eq. sweep_to_obtain_f) and the ordinate
+// pairs' shares of the right-hand side b~^n = sum_j w_j sweep_j(f^n_j / dt +
+// G, g) of the next step (Sec. 2.3).  The pairs are independent, so a launch
+// spreads them over workgroups: workgroup (x, i) takes pairs [x*gp, x*gp + gp)
+// of instance i.  Each pair's moment goes to fpart[p]; k_fpass_sum adds the
+// pairs in a fixed order, so the result does not depend on gp.
+// rhs_only: skip the first sweep and rebuild b~ from the stored f (creation,
+// or a new inflow).
 // ---------------------------------------------------------------------------
 template <int CMAX, int MAXT>
-__global__ void __launch_bounds__(MAXT) k_fpass_slab(const Inst *__restrict__ insts, int rhs_only) {
-  const Inst &I = insts[blockIdx.x];
+__global__ void __launch_bounds__(MAXT) k_fpass_pair(const Inst *__restrict__ insts, int rhs_only, int gp) {
+  const Inst &I = insts[blockIdx.y];
+  const int p0 = blockIdx.x * gp;
+  const int p1 = min(I.npair, p0 + gp);
+  if (p0 >= p1) return;
   __shared__ double slots[8 * RT_MAXWAVES];
   const int NT = I.nthr, tid = threadIdx.x;
   const int nc = I.nc;
@@ -291,29 +299,26 @@ __global__ void __launch_bounds__(MAXT) k_fpass_slab(const Inst *__restrict__ in
   const int c0 = tid * C;
   const int n = max(0, min(C, nc - c0));
   const double idt = I.inv_dt;
-  double ct[CMAX], G[CMAX], srcc[CMAX], acc[CMAX];
+  double ct[CMAX], G[CMAX], srcc[CMAX];
 #pragma unroll
   for (int t = 0; t < CMAX; ++t) {
     const bool in = t < n;
     ct[t] = in ? I.ct[c0 + t] : 1.0;
     G[t] = in ? I.G[c0 + t] : 0.0;
-    srcc[t] = in ? rt_fma(I.ss[c0 + t], I.rho[c0 + t], G[t]) : 0.0;
-    acc[t] = 0.0;
+    srcc[t] = (in && !rhs_only) ? rt_fma(I.ss[c0 + t], I.rho[c0 + t], G[t]) : 0.0;
   }
   int parity = 0;
-  const int nv = I.nv;
-  for (int p = 0; p < I.npair; ++p) {
+  for (int p = p0; p < p1; ++p) {
     const double m = I.pm[p], w = I.pw[p];
-    double *fneg = I.f + (size_t)p * nc + c0;            // mu < 0
-    double *fpos = I.f + (size_t)(nv - 1 - p) * nc + c0; // mu > 0
+    double *fneg = I.f + (size_t)p * nc + c0;               // mu < 0
+    double *fpos = I.f + (size_t)(I.nv - 1 - p) * nc + c0;  // mu > 0
     double inv[CMAX], bp[CMAX], bn[CMAX];
 #pragma unroll
     for (int t = 0; t < CMAX; ++t) {
-      if (t < n) {
-        inv[t] = rt_rcp(ct[t] + m);
-        bp[t] = fpos[t];
-        bn[t] = fneg[t];
-      }
+      const bool in = t < n;
+      inv[t] = rt_rcp(ct[t] + m);
+      bp[t] = in ? fpos[t] : 0.0;
+      bn[t] = in ? fneg[t] : 0.0;
     }
     if (!rhs_only) {
       double Af = 1.0, Bf = 0.0, Ab = 1.0, Bb = 0.0;
@@ -374,25 +379,41 @@ __global__ void __launch_bounds__(MAXT) k_fpass_slab(const Inst *__restrict__ in
     double inF, inB;
     wg_scan2<double>(Af, Bf, Ab, Bb, I.g[0], I.g[1], inF, inB, slots, parity);
     parity ^= 1;
+    double fw[CMAX];
     double f = inF;
 #pragma unroll
     for (int t = 0; t < CMAX; ++t)
       if (t < n) {
         f = rt_fma(m * inv[t], f, bp[t]);
-        acc[t] = rt_fma(w, f, acc[t]);
+        fw[t] = f;
       }
     f = inB;
 #pragma unroll
     for (int t = CMAX - 1; t >= 0; --t)
       if (t < n) {
         f = rt_fma(m * inv[t], f, bn[t]);
-        acc[t] = rt_fma(w, f, acc[t]);
+        fw[t] = w * (fw[t] + f);
       }
-  }
-  double *bt_out = rhs_only ? I.bt2[I.st->steps & 1] : I.bt2[I.st->cur ^ 1];
+    double *part = I.fpart + (size_t)p * nc + c0;
 #pragma unroll
-  for (int t = 0; t < CMAX; ++t)
-    if (t < n) bt_out[c0 + t] = acc[t];
+    for (int t = 0; t < CMAX; ++t)
+      if (t < n) part[t] = fw[t];
+  }
+}
+
+// b~ = sum over pairs of fpart[p], in pair order, into the b~ buffer the step
+// did not read (or, for rhs_only, the one the next step reads).
+__global__ void __launch_bounds__(256) k_fpass_sum(const Inst *__restrict__ insts, int rhs_only) {
+  const Inst &I = insts[blockIdx.y];
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= I.nc) return;
+  const int nc = I.nc, np = I.npair;
+  const double *part = I.fpart + c;
+  double acc = 0.0;
+#pragma unroll 8
+  for (int p = 0; p < np; ++p) acc += part[(size_t)p * nc];
+  double *bt_out = rhs_only ? I.bt2[I.st->steps & 1] : I.bt2[I.st->cur ^ 1];
+  bt_out[c] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -459,24 +480,29 @@ extern "C" hipError_t rt_launch_slab_si(const Inst *dinsts, int ninst, int nthre
   return hipGetLastError();
 }
 
-extern "C" hipError_t rt_launch_slab_fpass(const Inst *dinsts, int ninst, int nthreads, int cmax,
-                                           hipStream_t stream) {
-  dim3 grid(ninst), blk(nthreads);
+// gp pairs per workgroup: one when the launch has few pairs in total (every
+// pair on its own compute unit), more for large batches so that each
+// workgroup amortises its set-up over several pairs.
+static hipError_t launch_fpass(const Inst *dinsts, int ninst, int nthreads, int cmax, int npair_max, int nc_max,
+                               int rhs_only, int pairs_total, hipStream_t stream) {
+  const int gp = std::max(1, std::min(npair_max, (pairs_total + 1023) / 1024));
+  dim3 grid((npair_max + gp - 1) / gp, ninst), blk(nthreads);
   if (cmax <= 4)
-    hipLaunchKernelGGL((k_fpass_slab<4, 1024>), grid, blk, 0, stream, dinsts, 0);
+    hipLaunchKernelGGL((k_fpass_pair<4, 1024>), grid, blk, 0, stream, dinsts, rhs_only, gp);
   else
-    hipLaunchKernelGGL((k_fpass_slab<8, 512>), grid, blk, 0, stream, dinsts, 0);
+    hipLaunchKernelGGL((k_fpass_pair<8, 512>), grid, blk, 0, stream, dinsts, rhs_only, gp);
+  hipLaunchKernelGGL(k_fpass_sum, dim3((nc_max + 255) / 256, ninst), dim3(256), 0, stream, dinsts, rhs_only);
   return hipGetLastError();
 }
 
-extern "C" hipError_t rt_launch_slab_rhs(const Inst *dinsts, int ninst, int nthreads, int cmax,
-                                         hipStream_t stream) {
-  dim3 grid(ninst), blk(nthreads);
-  if (cmax <= 4)
-    hipLaunchKernelGGL((k_fpass_slab<4, 1024>), grid, blk, 0, stream, dinsts, 1);
-  else
-    hipLaunchKernelGGL((k_fpass_slab<8, 512>), grid, blk, 0, stream, dinsts, 1);
-  return hipGetLastError();
+extern "C" hipError_t rt_launch_slab_fpass(const Inst *dinsts, int ninst, int nthreads, int cmax, int npair_max,
+                                           int nc_max, int pairs_total, hipStream_t stream) {
+  return launch_fpass(dinsts, ninst, nthreads, cmax, npair_max, nc_max, 0, pairs_total, stream);
+}
+
+extern "C" hipError_t rt_launch_slab_rhs(const Inst *dinsts, int ninst, int nthreads, int cmax, int npair_max,
+                                         int nc_max, hipStream_t stream) {
+  return launch_fpass(dinsts, ninst, nthreads, cmax, npair_max, nc_max, 1, npair_max * ninst, stream);
 }
 
 extern "C" hipError_t rt_launch_slab_setup(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream) {

@@ -82,3 +82,17 @@ def oracle_tol_error(spec, nsteps: int, method=None, ref=None):
         o.step()
         worst = max(worst, rel_l2(o.rho(), ref[k]))
     return worst
+
+
+# A mixed-precision run and the FP64 oracle both stop when Alg. 1's test
+# passes, but once a ROM is involved their iterate paths differ (rounding of
+# the FP32 increments changes the snapshots, hence the DMD guesses and the
+# iteration at which the test passes), so each realises a different sample of
+# the error the stop test allows.  Across the batch and slab cases that error
+# ratio spans about 0.2x to 5x; the bar allows 10x the oracle's own distance
+# from the converged solution (never below 1e-8).
+MIXED_FACTOR = 10.0
+
+
+def mixed_bar(spec, nsteps: int, ref, method=None) -> float:
+    return max(1e-8, MIXED_FACTOR * oracle_tol_error(spec, nsteps, method=method, ref=ref))

@@ -14,8 +14,8 @@ import pytest
 import oracle
 from paper_2603_19647_amd import rtrom
 from paper_2603_19647_amd import workloads as W
-from tests.gpu_util import (assert_same_decisions, converged_reference, oracle_rounding_spread,
-                            oracle_tol_error, rel_l2, say, step_both)
+from tests.gpu_util import (assert_same_decisions, converged_reference, mixed_bar, oracle_rounding_spread,
+                            rel_l2, say, step_both)
 
 pytestmark = pytest.mark.gpu
 
@@ -70,7 +70,7 @@ def test_plane_mixed_vs_converged(method):
     spec = W.random_plane(5, 48, 8, 4, method=method, precision="mixed", nsteps=30)
     say(f"plane mixed {method}")
     ref = converged_reference(spec, spec.nsteps)
-    bar = max(MIXED_TOL, 3.0 * oracle_tol_error(spec, spec.nsteps, ref=ref))
+    bar = mixed_bar(spec, spec.nsteps, ref)
     g = rtrom.Problem(spec)
     worst = 0.0
     for k in range(spec.nsteps):
