@@ -440,6 +440,8 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   I.nc = nc;
   I.nv = nv;
   I.npair = nv / 2;
+  I.post_fused = d->dim == 1 && nc <= RT_POST_FUSED_NC;
+  I.post_nb = I.post_fused ? 1 : rt_pass_blocks(nc);
   I.max_iter = d->max_iter;
   I.method = d->method;
   I.precision = d->precision;
@@ -564,17 +566,21 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps, int n, int nsteps) 
     if (n == 1) dinsts = ps[0]->dinst;
     int cmax;
     int nt = slab_launch_threads(nthr.data(), ncs.data(), n, &cmax);
-    int nc_max = 0, any_rom = 0, npair_max = 1, pairs_total = 0;
+    int nc_max = 0, any_rom = 0, npair_max = 1, pairs_total = 0, any_fused = 0, nc_grid = 0;
     for (int i = 0; i < n; ++i) {
       nc_max = std::max(nc_max, ncs[i]);
       npair_max = std::max(npair_max, ps[i]->hinst.npair);
       pairs_total += ps[i]->hinst.npair;
-      any_rom |= ps[i]->d.method == RTROM_ROM_SI_DSA;
+      const int rom_i = ps[i]->d.method == RTROM_ROM_SI_DSA;
+      any_rom |= rom_i;
+      if (rom_i && ps[i]->hinst.post_fused) any_fused = 1;
+      if (rom_i && !ps[i]->hinst.post_fused) nc_grid = std::max(nc_grid, ncs[i]);
     }
-    // Per step: SI solve, then the f-pass (main stream) and the ROM work
-    // (auxiliary stream) run concurrently -- they touch disjoint state: the
-    // f-pass writes f^n and the other b~ buffer, the ROM work reads rho's and
-    // b~^{n-1} -- and the next SI solve waits for both.
+    // Per step: SI solve (which also takes the step's ROM decisions), then
+    // the f-pass (main stream) and the ROM work (auxiliary stream) run
+    // concurrently -- they touch disjoint state: the f-pass writes f^n and the
+    // other b~ buffer, the ROM work reads rho's and b~^{n-1} -- and the next
+    // SI solve waits for both.
     hipStream_t s2 = any_rom ? ps[0]->aux_stream : s;
     for (int k = 0; k < nsteps; ++k) {
       rt_prof_begin(RT_K_SLAB_SI, s);
@@ -584,10 +590,10 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps, int n, int nsteps) 
         RT_HIP(hipEventRecord(ps[0]->ev_si, s), "event");
         RT_HIP(hipStreamWaitEvent(s2, ps[0]->ev_si, 0), "event wait");
       }
-      rt_prof_begin(RT_K_POST, s2);
-      RT_HIP(rt_launch_rom(dinsts, n, nc_max, any_rom, s2), "ROM launch");
-      rt_prof_end(RT_K_POST, s2);
       if (any_rom) {
+        rt_prof_begin(RT_K_POST, s2);
+        RT_HIP(rt_launch_rom_slab(dinsts, n, any_fused, nc_grid, s2), "ROM launch");
+        rt_prof_end(RT_K_POST, s2);
         rt_prof_begin(RT_K_ROM_UPDATE, s2);
         RT_HIP(rt_launch_rom_update(dinsts, n, nc_max, s2), "ROM update launch");
         rt_prof_end(RT_K_ROM_UPDATE, s2);

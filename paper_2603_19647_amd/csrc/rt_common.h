@@ -23,6 +23,14 @@ struct RomPend {
 // Work record of one incremental-SVD update in flight: what the decide
 // kernel asked for and the per-block partial sums of the projection passes.
 #define RT_NPART 48
+// ROM passes: one 256-cell block per partial-sum row, at most 64 rows; slab
+// instances up to RT_POST_FUSED_NC cells run the whole post in one workgroup
+// per ROM (one partial row).
+#define RT_POST_FUSED_NC 2048
+__host__ __device__ inline int rt_pass_blocks(int nc) {
+  const int nb = (nc + 255) / 256;
+  return nb < 64 ? nb : 64;
+}
 struct RomWork {
   int active;    // this ROM takes a snapshot this step
   int truncate;  // truncated update (phases 2/3) vs untruncated construction
@@ -72,6 +80,8 @@ struct Inst {
   int dim, nx, ny, nc, nv, npair;
   int max_iter, method, precision, r_max, abs_up, hist_cap;
   int ld;    // column stride of U / W (nc rounded up)
+  int post_fused;  // ROM post in one workgroup per ROM (slab, nc <= RT_POST_FUSED_NC)
+  int post_nb;     // partial-sum rows of the ROM passes (1 when fused)
   int nthr;  // threads the instance's cells are split over (multiple of 64,
              // fixed at creation so results do not depend on the batch)
   double hx, hy, dt, inv_dt, tol, eps_ig, eps_pc, eps_up;

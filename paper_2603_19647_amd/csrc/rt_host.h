@@ -36,6 +36,7 @@ extern "C" hipError_t rt_launch_slab_si(const Inst *dinsts, int ninst, int nthre
 extern "C" hipError_t rt_launch_slab_fpass(const Inst *dinsts, int ninst, int nthreads, int cmax, int npair_max,
                                            int nc_max, int pairs_total, hipStream_t stream);
 extern "C" hipError_t rt_launch_rom(const Inst *dinsts, int ninst, int nc_max, int any_rom, hipStream_t s);
+extern "C" hipError_t rt_launch_rom_slab(const Inst *dinsts, int ninst, int any_fused, int nc_grid, hipStream_t s);
 extern "C" hipError_t rt_launch_rom_update(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream);
 extern "C" hipError_t rt_launch_slab_rhs(const Inst *dinsts, int ninst, int nthreads, int cmax, int npair_max,
                                          int nc_max, hipStream_t stream);

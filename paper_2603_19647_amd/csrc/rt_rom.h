@@ -702,6 +702,105 @@ __device__ __forceinline__ void isvd_rotate_cell(const RomDev &R, const RomPend 
   rotate_block(old, P.b[c], Vc, r, k, R.W, ld, c);
 }
 
+// ---------------------------------------------------------------------------
+// Per-thread partial sums of ||rho^n||^2, ||rho^(0) - rho^n||^2 and
+// ||dpc - (rho^n - rho^(1/2))||^2 (the error indicators of Sec. 3.2) over
+// cells c0, c0 + stride, ...
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void rom_norm_parts(const Inst &I, int c0, int stride, double (&part)[3]) {
+  part[0] = part[1] = part[2] = 0.0;
+  for (int c = c0; c < I.nc; c += stride) {
+    const double r = I.rho[c];
+    part[0] = rt_fma(r, r, part[0]);
+    const double e1 = I.rho0[c] - r;
+    part[1] = rt_fma(e1, e1, part[1]);
+    const double e2 = I.dpc[c] - (r - I.rhalf[c]);
+    part[2] = rt_fma(e2, e2, part[2]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// End-of-step bookkeeping and, for the ROM method, the error indicators
+// (Sec. 3.2, normalised by ||rho^n||_2) and Alg. 2's decisions on which ROM
+// takes a snapshot this step.  vec holds the three sums above (read only
+// for a ROM instance whose IG ROM exists); nb is the number of pass blocks
+// the ROM work will use.  Called by every thread of one workgroup after the
+// step's state is final; thread 0 writes.
+// ---------------------------------------------------------------------------
+__device__ inline void rom_decide(const Inst &I, const double *vec, int nb) {
+  RtState *st = I.st;
+  const int iters = st->iters;
+  const long long step_no = st->steps + 1;
+  double e_ig = -1.0, e_pc = -1.0;
+  if (I.method == RT_ROM) {
+    const int flag_ig = st->flag_ig, flag_pc = st->flag_pc, used_pc = st->used_pc;
+    const double rn = flag_ig ? sqrt(vec[0]) : 0.0;
+    const double scale = (I.abs_up || rn == 0.0) ? 1.0 : 1.0 / rn;
+    int ig_on = 0, ig_trunc = 0, pc_on = 0, pc_trunc = 0;
+    if (!flag_ig) {
+      ig_on = 1;  // phase 1: untruncated snapshot (rho^n, b~^{n-1})
+    } else {
+      e_ig = sqrt(vec[1]) * scale;
+      ig_on = ig_trunc = e_ig > I.eps_up;
+      if (iters > 1) {  // no correction snapshot when the step converged at l = 1
+        if (!flag_pc) {
+          pc_on = 1;
+        } else {
+          if (used_pc) e_pc = sqrt(vec[2]) * scale;
+          pc_on = pc_trunc = ig_on || !used_pc || e_pc > I.eps_up;
+        }
+      }
+    }
+    if (threadIdx.x == 0) {
+      RomWork &wi = *I.ig.work;
+      wi.active = ig_on;
+      wi.truncate = ig_trunc;
+      wi.r = st->rank_ig;
+      wi.nblk = nb;
+      wi.step_no = step_no;
+      wi.eps = I.eps_ig;
+      wi.x = I.rho;
+      wi.b = I.bt2[st->cur];
+      wi.p = I.work;
+      RomWork &wp = *I.pc.work;
+      wp.active = pc_on;
+      wp.truncate = pc_trunc;
+      wp.r = st->rank_pc;
+      wp.nblk = nb;
+      wp.step_no = step_no;
+      wp.eps = I.eps_pc;
+      // correction snapshots (eq. correction_snapshot), formed by pass 1
+      wp.x = I.work + 2 * (size_t)I.nc;
+      wp.b = I.work + 3 * (size_t)I.nc;
+      wp.p = I.work + I.nc;
+      I.ig.pend->pending = 0;
+      I.pc.pend->pending = 0;
+    }
+  }
+  if (threadIdx.x == 0) {
+    const int fb = st->ig_fb + st->pc_fb;
+    if (I.hist && step_no <= I.hist_cap) {
+      RtStepRec &rec = I.hist[step_no - 1];
+      rec.iters = iters;
+      rec.phase = st->phase;
+      rec.converged = st->conv;
+      rec.ig_update = 0;
+      rec.pc_update = 0;
+      rec.rank_ig = st->rank_ig;
+      rec.rank_pc = st->rank_pc;
+      rec.fallback = fb > 0;
+      rec.e_ig = e_ig;
+      rec.e_pc = e_pc;
+      rec.residual = st->residual;
+    }
+    st->fallbacks += fb;
+    st->steps = step_no;
+    st->si_total += iters;
+    st->sweeps_total += iters + 2;
+    st->nonconv += !st->conv;
+  }
+}
+
 // s_r / sum(s) of the retained values (eq. ig_stop, eq. pc_stop)
 __device__ inline double rom_tail_ratio(const RomDev &R, int rank) {
   double tot = 0.0;

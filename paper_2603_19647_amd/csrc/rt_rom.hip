@@ -6,16 +6,11 @@
 #include "rt_rom.h"
 
 namespace {
-constexpr int BLK = 256;          // threads per block of the grid passes
-constexpr int PASS_CELLS = 256;   // cells per block before a second block is used
-constexpr int MAX_PASS_BLK = 64;  // blocks per instance (cells are strided over them)
+constexpr int BLK = 256;  // threads per block of the grid passes
 
-// One cell per thread up to 64 blocks an instance: the passes are short and
-// latency-bound, so an instance's cells are spread wide.
-__device__ __host__ __forceinline__ int pass_blocks(int nc) {
-  const int nb = (nc + PASS_CELLS - 1) / PASS_CELLS;
-  return nb < MAX_PASS_BLK ? nb : MAX_PASS_BLK;
-}
+// One cell per thread up to 64 blocks an instance (rt_pass_blocks): the
+// passes are short and latency-bound, so an instance's cells are spread wide.
+__device__ __host__ __forceinline__ int pass_blocks(int nc) { return rt_pass_blocks(nc); }
 
 __device__ __forceinline__ const RomDev &rom_of(const Inst &I, int z) { return z ? I.pc : I.ig; }
 }  // namespace
@@ -32,123 +27,41 @@ __global__ void __launch_bounds__(BLK) k_rom_norms(const Inst *__restrict__ inst
   const int nb = pass_blocks(I.nc);
   if ((int)blockIdx.x >= nb) return;
   __shared__ double red[(BLK / 64) * 3], out[3];
-  double part[3] = {0.0, 0.0, 0.0};
-  for (int c = blockIdx.x * BLK + threadIdx.x; c < I.nc; c += nb * BLK) {
-    const double r = I.rho[c];
-    part[0] = rt_fma(r, r, part[0]);
-    const double e1 = I.rho0[c] - r;
-    part[1] = rt_fma(e1, e1, part[1]);
-    const double e2 = I.dpc[c] - (r - I.rhalf[c]);
-    part[2] = rt_fma(e2, e2, part[2]);
-  }
+  double part[3];
+  rom_norm_parts(I, blockIdx.x * BLK + threadIdx.x, nb * BLK, part);
   wg_sum_fast<3>(part, red, out);
   if (threadIdx.x < 3) I.ig.work->part3[blockIdx.x * RT_NPART + threadIdx.x] = out[threadIdx.x];
 }
 
 // ---------------------------------------------------------------------------
-// k_rom_decide: step bookkeeping and, for the ROM method, the error
-// indicators (Sec. 3.2, normalised by ||rho^n||_2) and Alg. 2's decisions on
-// which ROM takes a snapshot this step.  One workgroup per instance.
+// k_rom_decide: rom_decide (step bookkeeping, error indicators and Alg. 2's
+// decisions) for every instance, one workgroup each, from the partial sums
+// of k_rom_norms.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_rom_decide(const Inst *__restrict__ insts) {
   const Inst &I = insts[blockIdx.x];
   __shared__ double scratch[256], vec[4];
-  const int tid = threadIdx.x;
-  const int nc = I.nc;
-  RtState *st = I.st;
-  const int iters = st->iters;
-  const long long step_no = st->steps + 1;
-  double e_ig = -1.0, e_pc = -1.0;
-  if (I.method == RT_ROM) {
-    const int flag_ig = st->flag_ig, flag_pc = st->flag_pc, used_pc = st->used_pc;
-    const int nb = pass_blocks(nc);
-    if (flag_ig) sum_partials(I.ig.work->part3, nb, 3, vec, scratch);
-    const double rn = flag_ig ? sqrt(vec[0]) : 0.0;
-    const double scale = (I.abs_up || rn == 0.0) ? 1.0 : 1.0 / rn;
-    int ig_on = 0, ig_trunc = 0, pc_on = 0, pc_trunc = 0;
-    if (!flag_ig) {
-      ig_on = 1;  // phase 1: untruncated snapshot (rho^n, b~^{n-1})
-    } else {
-      e_ig = sqrt(vec[1]) * scale;
-      ig_on = ig_trunc = e_ig > I.eps_up;
-      if (iters > 1) {  // no correction snapshot when the step converged at l = 1
-        if (!flag_pc) {
-          pc_on = 1;
-        } else {
-          if (used_pc) e_pc = sqrt(vec[2]) * scale;
-          pc_on = pc_trunc = ig_on || !used_pc || e_pc > I.eps_up;
-        }
-      }
-    }
-    if (tid == 0) {
-      RomWork &wi = *I.ig.work;
-      wi.active = ig_on;
-      wi.truncate = ig_trunc;
-      wi.r = st->rank_ig;
-      wi.nblk = nb;
-      wi.step_no = step_no;
-      wi.eps = I.eps_ig;
-      wi.x = I.rho;
-      wi.b = I.bt2[st->cur];
-      wi.p = I.work;
-      RomWork &wp = *I.pc.work;
-      wp.active = pc_on;
-      wp.truncate = pc_trunc;
-      wp.r = st->rank_pc;
-      wp.nblk = nb;
-      wp.step_no = step_no;
-      wp.eps = I.eps_pc;
-      // correction snapshots (eq. correction_snapshot), formed by k_rom_pass1
-      wp.x = I.work + 2 * (size_t)nc;
-      wp.b = I.work + 3 * (size_t)nc;
-      wp.p = I.work + nc;
-      I.ig.pend->pending = 0;
-      I.pc.pend->pending = 0;
-    }
-  }
-  if (tid == 0) {
-    const int fb = st->ig_fb + st->pc_fb;
-    if (I.hist && step_no <= I.hist_cap) {
-      RtStepRec &rec = I.hist[step_no - 1];
-      rec.iters = iters;
-      rec.phase = st->phase;
-      rec.converged = st->conv;
-      rec.ig_update = 0;
-      rec.pc_update = 0;
-      rec.rank_ig = st->rank_ig;
-      rec.rank_pc = st->rank_pc;
-      rec.fallback = fb > 0;
-      rec.e_ig = e_ig;
-      rec.e_pc = e_pc;
-      rec.residual = st->residual;
-    }
-    st->fallbacks += fb;
-    st->steps = step_no;
-    st->si_total += iters;
-    st->sweeps_total += iters + 2;
-    st->nonconv += !st->conv;
-  }
+  const int nb = pass_blocks(I.nc);
+  if (I.method == RT_ROM && I.st->flag_ig) sum_partials(I.ig.work->part3, nb, 3, vec, scratch);
+  rom_decide(I, vec, I.post_nb);
 }
 
 // ---------------------------------------------------------------------------
-// Projection passes (classical Gram-Schmidt applied twice), one thread per
-// cell, grid (blocks of 256 cells, instance, ROM).  Each block writes its
-// partial sums; later stages add them in block order.
+// Projection passes (classical Gram-Schmidt applied twice).  Block b of nb
+// takes cells b*blockDim + t, strided by nb*blockDim, and writes its partial
+// sums to row b; later stages add the rows in block order.  The same bodies
+// serve the grid kernels (grid (blocks, instance, ROM)) and the one-block
+// fused post of small instances (nb = 1).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(BLK) k_rom_pass1(const Inst *__restrict__ insts) {
-  const Inst &I = insts[blockIdx.y];
-  if (I.method != RT_ROM) return;
-  const RomDev &R = rom_of(I, blockIdx.z);
-  const RomWork &W = *R.work;
-  if (!W.active || (int)blockIdx.x >= W.nblk) return;
-  __shared__ double red[(BLK / 64) * (2 * RT_RMAX + 2)], out[2 * RT_RMAX + 2];
-  const int r = W.r, ld = I.ld;
+__device__ __forceinline__ void rom_pass1(const Inst &I, const RomDev &R, const RomWork &W, int z, int b,
+                                          int nb, double *red, double *out) {
+  const int r = W.r, ld = I.ld, NT = blockDim.x;
   double part[2 * RT_RMAX + 2];
 #pragma unroll
   for (int k = 0; k < 2 * RT_RMAX + 2; ++k) part[k] = 0.0;
-  for (int c = blockIdx.x * BLK + threadIdx.x; c < I.nc; c += W.nblk * BLK) {
+  for (int c = b * NT + threadIdx.x; c < I.nc; c += nb * NT) {
     double xv, bv;
-    if (blockIdx.z == 1) {  // x = rho^n - rho^(1/2), b = rho^(1/2) - rho^(0)
+    if (z == 1) {  // x = rho^n - rho^(1/2), b = rho^(1/2) - rho^(0)
       const double rh = I.rhalf[c];
       xv = I.rho[c] - rh;
       bv = rh - I.rho0[c];
@@ -175,31 +88,26 @@ __global__ void __launch_bounds__(BLK) k_rom_pass1(const Inst *__restrict__ inst
     }
   }
   wg_sum_fast<2 * RT_RMAX + 2>(part, red, out);
-  if (threadIdx.x < 2 * RT_RMAX + 2) W.part1[blockIdx.x * RT_NPART + threadIdx.x] = out[threadIdx.x];
+  if (threadIdx.x < 2 * RT_RMAX + 2) W.part1[b * RT_NPART + threadIdx.x] = out[threadIdx.x];
 }
 
-__global__ void __launch_bounds__(BLK) k_rom_pass2(const Inst *__restrict__ insts) {
-  const Inst &I = insts[blockIdx.y];
-  if (I.method != RT_ROM) return;
-  const RomDev &R = rom_of(I, blockIdx.z);
-  const RomWork &W = *R.work;
-  if (!W.active || (int)blockIdx.x >= W.nblk) return;
-  __shared__ double red[(BLK / 64) * 2 * RT_RMAX], out[2 * RT_RMAX], av[RT_RMAX], scratch[BLK];
-  const int r = W.r, ld = I.ld;
+__device__ __forceinline__ void rom_pass2(const Inst &I, const RomDev &R, const RomWork &W, int b, int nb,
+                                          double *red, double *out, double *av, double *scratch) {
+  const int r = W.r, ld = I.ld, NT = blockDim.x;
   // every column: pass 1 left zero sums past the rank, so av is zero there
-  sum_partials(W.part1, W.nblk, RT_RMAX, av, scratch);
+  sum_partials(W.part1, nb, RT_RMAX, av, scratch);
   double part[2 * RT_RMAX];
 #pragma unroll
   for (int k = 0; k < 2 * RT_RMAX; ++k) part[k] = 0.0;
-  for (int c = blockIdx.x * BLK + threadIdx.x; c < I.nc; c += W.nblk * BLK) {
+  for (int c = b * NT + threadIdx.x; c < I.nc; c += nb * NT) {
     // all loads issued up front and unconditionally (masked past the rank);
     // the arithmetic keeps its order
     double u[RT_RMAX], wv[RT_RMAX];
 #pragma unroll
     for (int k = 0; k < RT_RMAX; ++k) {
-      const double a = R.U[(size_t)k * ld + c], b = R.W[(size_t)k * ld + c];
-      u[k] = k < r ? a : 0.0;
-      wv[k] = k < r ? b : 0.0;
+      const double x = R.U[(size_t)k * ld + c], y = R.W[(size_t)k * ld + c];
+      u[k] = k < r ? x : 0.0;
+      wv[k] = k < r ? y : 0.0;
     }
     double v = W.x[c];
 #pragma unroll
@@ -212,25 +120,20 @@ __global__ void __launch_bounds__(BLK) k_rom_pass2(const Inst *__restrict__ inst
     }
   }
   wg_sum_fast<2 * RT_RMAX>(part, red, out);
-  if (threadIdx.x < 2 * RT_RMAX) W.part2[blockIdx.x * RT_NPART + threadIdx.x] = out[threadIdx.x];
+  if (threadIdx.x < 2 * RT_RMAX) W.part2[b * RT_NPART + threadIdx.x] = out[threadIdx.x];
 }
 
-__global__ void __launch_bounds__(BLK) k_rom_pass3(const Inst *__restrict__ insts) {
-  const Inst &I = insts[blockIdx.y];
-  if (I.method != RT_ROM) return;
-  const RomDev &R = rom_of(I, blockIdx.z);
-  const RomWork &W = *R.work;
-  if (!W.active || (int)blockIdx.x >= W.nblk) return;
-  __shared__ double red[(BLK / 64) * 2], out[2], a2[RT_RMAX], scratch[BLK];
-  const int r = W.r, ld = I.ld;
-  sum_partials(W.part2, W.nblk, RT_RMAX, a2, scratch);  // zero past the rank
+__device__ __forceinline__ void rom_pass3(const Inst &I, const RomDev &R, const RomWork &W, int b, int nb,
+                                          double *red, double *out, double *a2, double *scratch) {
+  const int r = W.r, ld = I.ld, NT = blockDim.x;
+  sum_partials(W.part2, nb, RT_RMAX, a2, scratch);  // zero past the rank
   double part[2] = {0.0, 0.0};
-  for (int c = blockIdx.x * BLK + threadIdx.x; c < I.nc; c += W.nblk * BLK) {
+  for (int c = b * NT + threadIdx.x; c < I.nc; c += nb * NT) {
     double u[RT_RMAX];
 #pragma unroll
     for (int k = 0; k < RT_RMAX; ++k) {
-      const double a = R.U[(size_t)k * ld + c];
-      u[k] = k < r ? a : 0.0;
+      const double x = R.U[(size_t)k * ld + c];
+      u[k] = k < r ? x : 0.0;
     }
     double v = W.p[c];
 #pragma unroll
@@ -240,21 +143,46 @@ __global__ void __launch_bounds__(BLK) k_rom_pass3(const Inst *__restrict__ inst
     part[1] = rt_fma(v, W.b[c], part[1]);
   }
   wg_sum_fast<2>(part, red, out);
-  if (threadIdx.x < 2) W.part3[blockIdx.x * RT_NPART + threadIdx.x] = out[threadIdx.x];
+  if (threadIdx.x < 2) W.part3[b * RT_NPART + threadIdx.x] = out[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(BLK) k_rom_pass1(const Inst *__restrict__ insts) {
+  const Inst &I = insts[blockIdx.y];
+  if (I.method != RT_ROM || I.post_fused) return;
+  const RomDev &R = rom_of(I, blockIdx.z);
+  const RomWork &W = *R.work;
+  if (!W.active || (int)blockIdx.x >= W.nblk) return;
+  __shared__ double red[(BLK / 64) * (2 * RT_RMAX + 2)], out[2 * RT_RMAX + 2];
+  rom_pass1(I, R, W, blockIdx.z, blockIdx.x, W.nblk, red, out);
+}
+
+__global__ void __launch_bounds__(BLK) k_rom_pass2(const Inst *__restrict__ insts) {
+  const Inst &I = insts[blockIdx.y];
+  if (I.method != RT_ROM || I.post_fused) return;
+  const RomDev &R = rom_of(I, blockIdx.z);
+  const RomWork &W = *R.work;
+  if (!W.active || (int)blockIdx.x >= W.nblk) return;
+  __shared__ double red[(BLK / 64) * 2 * RT_RMAX], out[2 * RT_RMAX], av[RT_RMAX], scratch[BLK];
+  rom_pass2(I, R, W, blockIdx.x, W.nblk, red, out, av, scratch);
+}
+
+__global__ void __launch_bounds__(BLK) k_rom_pass3(const Inst *__restrict__ insts) {
+  const Inst &I = insts[blockIdx.y];
+  if (I.method != RT_ROM || I.post_fused) return;
+  const RomDev &R = rom_of(I, blockIdx.z);
+  const RomWork &W = *R.work;
+  if (!W.active || (int)blockIdx.x >= W.nblk) return;
+  __shared__ double red[(BLK / 64) * 2], out[2], a2[RT_RMAX], scratch[BLK];
+  rom_pass3(I, R, W, blockIdx.x, W.nblk, red, out, a2, scratch);
 }
 
 // ---------------------------------------------------------------------------
-// k_rom_core: small dense part of the update and Alg. 2's phase flags; one
-// workgroup per (instance, ROM).
+// Small dense part of the update (isvd_core) and Alg. 2's phase flags for
+// ROM z of one instance; every thread of the workgroup calls it.  Block z
+// writes only ROM z's state fields, so the two ROMs' workgroups may run at
+// once.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_rom_core(const Inst *__restrict__ insts) {
-  const Inst &I = insts[blockIdx.x];
-  if (I.method != RT_ROM) return;
-  const int z = blockIdx.y;
-  const RomDev &R = rom_of(I, z);
-  const RomWork &W = *R.work;
-  if (!W.active) return;
-  __shared__ RomSmem sm;
+__device__ __forceinline__ void rom_core(const Inst &I, const RomDev &R, const RomWork &W, int z, RomSmem &sm) {
   RtState *st = I.st;
   int rank = z ? st->rank_pc : st->rank_ig;
   int luok = z ? st->lu_ok_pc : st->lu_ok_ig;
@@ -272,6 +200,8 @@ __global__ void __launch_bounds__(256) k_rom_core(const Inst *__restrict__ insts
             st->flag_ig = 1;
             st->n0 = (int)step_no;
           } else {
+            // PC snapshots start only after the IG construction ended in an
+            // earlier step, so n0 is settled here
             st->flag_pc = 1;
             st->n1 = (int)step_no - st->n0;
           }
@@ -300,6 +230,44 @@ __global__ void __launch_bounds__(256) k_rom_core(const Inst *__restrict__ insts
       }
     }
   }
+}
+
+// k_rom_core: rom_core after the grid passes, grid (instance, ROM).
+__global__ void __launch_bounds__(256) k_rom_core(const Inst *__restrict__ insts) {
+  const Inst &I = insts[blockIdx.x];
+  if (I.method != RT_ROM || I.post_fused) return;
+  const int z = blockIdx.y;
+  const RomDev &R = rom_of(I, z);
+  const RomWork &W = *R.work;
+  if (!W.active) return;
+  __shared__ RomSmem sm;
+  rom_core(I, R, W, z, sm);
+}
+
+// ---------------------------------------------------------------------------
+// k_rom_post_small: the whole incremental-SVD update but the rotation for a
+// small instance (the slab path, whose SI kernel already took the step's
+// decisions), one workgroup per (instance, ROM): the three passes with
+// workgroup reductions (one partial row), then the core.  One launch instead
+// of four, and no grid-wide partial sums.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_rom_post_small(const Inst *__restrict__ insts) {
+  const Inst &I = insts[blockIdx.x];
+  if (I.method != RT_ROM || !I.post_fused) return;
+  const int z = blockIdx.y;
+  const RomDev &R = rom_of(I, z);
+  const RomWork &W = *R.work;
+  if (!W.active) return;
+  __shared__ double red[(256 / 64) * (2 * RT_RMAX + 2)], out[2 * RT_RMAX + 2], av[RT_RMAX], scratch[256];
+  __shared__ RomSmem sm;
+  // each stage reads the partial row the previous one wrote to global memory
+  rom_pass1(I, R, W, z, 0, 1, red, out);
+  __syncthreads();
+  rom_pass2(I, R, W, 0, 1, red, out, av, scratch);
+  __syncthreads();
+  rom_pass3(I, R, W, 0, 1, red, out, av, scratch);
+  __syncthreads();
+  rom_core(I, R, W, z, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -341,6 +309,21 @@ extern "C" hipError_t rt_launch_rom(const Inst *dinsts, int ninst, int nc_max, i
   if (any_rom) hipLaunchKernelGGL(k_rom_norms, dim3(nb, ninst), dim3(BLK), 0, s, dinsts);
   hipLaunchKernelGGL(k_rom_decide, dim3(ninst), dim3(256), 0, s, dinsts);
   if (any_rom) {
+    hipLaunchKernelGGL(k_rom_pass1, dim3(nb, ninst, 2), dim3(BLK), 0, s, dinsts);
+    hipLaunchKernelGGL(k_rom_pass2, dim3(nb, ninst, 2), dim3(BLK), 0, s, dinsts);
+    hipLaunchKernelGGL(k_rom_pass3, dim3(nb, ninst, 2), dim3(BLK), 0, s, dinsts);
+    hipLaunchKernelGGL(k_rom_core, dim3(ninst, 2), dim3(256), 0, s, dinsts);
+  }
+  return hipGetLastError();
+}
+
+// Slab instances: the SI kernel took the decisions.  Fused instances take
+// one launch; the others the grid passes and the core.  nc_grid: the largest
+// non-fused instance (0: none).
+extern "C" hipError_t rt_launch_rom_slab(const Inst *dinsts, int ninst, int any_fused, int nc_grid, hipStream_t s) {
+  if (any_fused) hipLaunchKernelGGL(k_rom_post_small, dim3(ninst, 2), dim3(256), 0, s, dinsts);
+  if (nc_grid > 0) {
+    const int nb = pass_blocks(nc_grid);
     hipLaunchKernelGGL(k_rom_pass1, dim3(nb, ninst, 2), dim3(BLK), 0, s, dinsts);
     hipLaunchKernelGGL(k_rom_pass2, dim3(nb, ninst, 2), dim3(BLK), 0, s, dinsts);
     hipLaunchKernelGGL(k_rom_pass3, dim3(nb, ninst, 2), dim3(BLK), 0, s, dinsts);

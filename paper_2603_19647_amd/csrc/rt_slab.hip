@@ -274,6 +274,24 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
     st->cur = cur;
     st->fp32_sweeps += n32;
   }
+  __syncthreads();
+  // end of step: error indicators from the final iterate and Alg. 2's
+  // decisions, so the ROM work that follows needs no launch of its own
+  if (rom && flag_ig) {
+    double part[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t)
+      if (t < n) {
+        const double r = y[t];
+        part[0] = rt_fma(r, r, part[0]);
+        const double e1 = I.rho0[c0 + t] - r;
+        part[1] = rt_fma(e1, e1, part[1]);
+        const double e2 = I.dpc[c0 + t] - (r - I.rhalf[c0 + t]);
+        part[2] = rt_fma(e2, e2, part[2]);
+      }
+    wg_sum_fast<3>(part, rred, rvec);
+  }
+  rom_decide(I, rvec, I.post_nb);
 }
 
 // ---------------------------------------------------------------------------
