@@ -58,62 +58,87 @@ RT_HD inline double rcp(double x) {
 #endif
 }
 
+// Identity combine: one lane evaluates all terms.
+struct Whole {
+  RT_HD double operator()(double v) const { return v; }
+};
+
 // f, psi (poles <= k), phi (poles > k) and derivatives at tau, for poles
-// shifted by the origin pole: dd[j] = d_j - d_K.  dd and z are held by the
+// shifted by the origin pole: dd[t] = d_j - d_K for the terms j = g + G t
+// this lane owns (G lanes share one root and comb adds their partial sums,
+// giving every lane of the group the same totals).  dd and z are held by the
 // caller (registers on the device: every loop runs over the capacity).
 struct Eval {
   double f, psi, dpsi, phi, dphi, erretm;
 };
-RT_HD inline Eval evaluate(const double (&dd)[N], const double (&z)[N], int m, int k, double tau) {
+template <int G, class Comb>
+RT_HD inline Eval evaluate(const double (&dd)[N / G], const double (&z)[N / G], int m, int k, int g, double tau,
+                           Comb comb) {
   Eval e{1.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int j = 0; j < N; ++j) {
+  for (int t = 0; t < N / G; ++t) {
+    const int j = g + G * t;
     if (j < m) {
-      const double t = z[j] * rcp(dd[j] - tau);
-      const double term = z[j] * t;
+      const double q = z[t] * rcp(dd[t] - tau);
+      const double term = z[t] * q;
       if (j <= k) {
         e.psi += term;
-        e.dpsi += t * t;
+        e.dpsi += q * q;
       } else {
         e.phi += term;
-        e.dphi += t * t;
+        e.dphi += q * q;
       }
       e.erretm += fabs(term);
     }
   }
+  e.psi = comb(e.psi);
+  e.dpsi = comb(e.dpsi);
+  e.phi = comb(e.phi);
+  e.dphi = comb(e.dphi);
+  e.erretm = comb(e.erretm);
   e.f = 1.0 + e.psi + e.phi;
   return e;
 }
 
-RT_HD inline void shifted_poles(const Problem &P, int K, double (&dd)[N]) {
+template <int G>
+RT_HD inline void shifted_poles(const Problem &P, int K, int g, double (&dd)[N / G]) {
 #pragma unroll
-  for (int j = 0; j < N; ++j) dd[j] = (j < P.m) ? pole_diff(P.s[j], P.s[K]) : 0.0;
+  for (int t = 0; t < N / G; ++t) {
+    const int j = g + G * t;
+    dd[t] = (j < P.m) ? pole_diff(P.s[j], P.s[K]) : 0.0;
+  }
 }
 
 // Root k of the secular equation (k < m): returns the origin pole K and the
 // shift tau, lambda_k = s_K^2 + tau.  Safeguarded two-pole rational Newton
-// iteration inside a bracket that shrinks with every evaluation.
-RT_HD inline void root(const Problem &P, int k, int &K_out, double &tau_out) {
+// iteration inside a bracket that shrinks with every evaluation.  G lanes
+// (g = 0..G-1) may work on one root, each summing every G-th term; all of
+// them take the same steps and return the same root.
+template <int G, class Comb>
+RT_HD inline void root_g(const Problem &P, int k, int g, Comb comb, int &K_out, double &tau_out) {
+  static_assert(N % G == 0, "terms split evenly over the group");
   const int m = P.m;
   if (m == 1) {  // one pole: lambda = d_0 + z_0^2
     K_out = 0;
     tau_out = P.z[0] * P.z[0];
     return;
   }
-  double z[N], dd[N];
+  double z[N / G], dd[N / G];
   double z2 = 0.0;
 #pragma unroll
-  for (int j = 0; j < N; ++j) {
-    z[j] = (j < m) ? P.z[j] : 0.0;
-    z2 += z[j] * z[j];
+  for (int t = 0; t < N / G; ++t) {
+    const int j = g + G * t;
+    z[t] = (j < m) ? P.z[j] : 0.0;
+    z2 += z[t] * z[t];
   }
+  z2 = comb(z2);
   int K;
   double lo, hi;  // bracket in tau around the root, f(lo) < 0 < f(hi)
   if (k < m - 1) {
     const double gap = pole_diff(P.s[k + 1], P.s[k]);
     // f at the midpoint, shifted by the lower pole
-    shifted_poles(P, k, dd);
-    const Eval mid = evaluate(dd, z, m, k, 0.5 * gap);
+    shifted_poles<G>(P, k, g, dd);
+    const Eval mid = evaluate<G>(dd, z, m, k, g, 0.5 * gap, comb);
     if (mid.f >= 0.0) {
       K = k;
       lo = 0.0;
@@ -122,13 +147,13 @@ RT_HD inline void root(const Problem &P, int k, int &K_out, double &tau_out) {
       K = k + 1;
       lo = -0.5 * gap;
       hi = 0.0;
-      shifted_poles(P, K, dd);
+      shifted_poles<G>(P, K, g, dd);
     }
   } else {
     K = m - 1;
     lo = 0.0;
     hi = z2;
-    shifted_poles(P, K, dd);
+    shifted_poles<G>(P, K, g, dd);
   }
   // the two poles around the root, shifted by K
   const double da = pole_diff(P.s[k], P.s[K]);
@@ -137,7 +162,7 @@ RT_HD inline void root(const Problem &P, int k, int &K_out, double &tau_out) {
   double tau = 0.5 * (lo + hi);
   const double eps = 2.220446049250313e-16;
   for (int it = 0; it < 200; ++it) {
-    const Eval e = evaluate(dd, z, m, k, tau);
+    const Eval e = evaluate<G>(dd, z, m, k, g, tau, comb);
     if (e.f == 0.0) break;
     if (e.f < 0.0) lo = tau;
     else hi = tau;
@@ -183,6 +208,11 @@ RT_HD inline void root(const Problem &P, int k, int &K_out, double &tau_out) {
   }
   K_out = K;
   tau_out = tau;
+}
+
+// Root k by one lane.
+RT_HD inline void root(const Problem &P, int k, int &K_out, double &tau_out) {
+  root_g<1>(P, k, 0, Whole(), K_out, tau_out);
 }
 
 // lambda_k - d_j = (d_K - d_j) + tau_k

@@ -52,6 +52,14 @@ __device__ __forceinline__ double row16_sum(double v) {
   v += dpp_d<0x140>(v);  // row_mirror
   return v;
 }
+// sum over a DPP quad (4 lanes), identical in every lane of the quad
+struct QuadSum {
+  __device__ double operator()(double v) const {
+    v += dpp_d<0xB1>(v);  // quad_perm [1,0,3,2]
+    v += dpp_d<0x4E>(v);  // quad_perm [2,3,0,1]
+    return v;
+  }
+};
 // whole-wave sum, identical in every lane
 __device__ __forceinline__ double wave_sum_fast(double v) {
   v = row16_sum(v);
@@ -87,7 +95,8 @@ __device__ __forceinline__ void wg_sum_fast(const double (&v)[NV], double *red, 
 // a factorisation with row interchanges.  A pivot below 1e-14 max|A| marks
 // the system singular.  Writes the factors in pivot order (stride RT_RMAX)
 // and the row permutation to global memory and returns 1 if singular.  Must
-// be called by the whole workgroup; A is left unchanged.
+// be called by the whole workgroup; A's first row is overwritten (it carries
+// the pivot rows once the matrix is in registers).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double dpp_max16(double v) {
   v = fmax(v, dpp_d<0xB1>(v));   // quad_perm [1,0,3,2]
@@ -134,7 +143,21 @@ __device__ inline int lu_factor_wave(double *A, int *perm_lds, int n, double *LU
           active = false;
           pos = k;
         }
-        const double akk = lane_read(row[k], p);
+        // the pivot row to every lane through LDS (A is free: rows live in
+        // registers), one write and one broadcast read per entry
+        if (lane == p) {
+#pragma unroll
+          for (int j = k; j < RT_RMAX; ++j) A[j] = row[j];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        double prow[RT_RMAX];
+#pragma unroll
+        for (int j = k; j < RT_RMAX; ++j) prow[j] = A[j];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const double akk = prow[k];
         if (akk == 0.0 || fabs(akk) < 1e-14 * amax) {
           bad = 1;
           continue;
@@ -144,10 +167,7 @@ __device__ inline int lu_factor_wave(double *A, int *perm_lds, int n, double *LU
         if (active) row[k] = l;
 #pragma unroll
         for (int j = k + 1; j < RT_RMAX; ++j)
-          if (j < n) {
-            const double pj = lane_read(row[j], p);
-            if (active) row[j] = rt_fma(-l, pj, row[j]);
-          }
+          if (active) row[j] = rt_fma(-l, prow[j], row[j]);
       }
     }
     if (mine) {
@@ -466,12 +486,17 @@ __device__ inline bool core_svd_secular(RomSmem &sm, const double *S, const doub
   if (!sm.ap_ok) return false;
   const arrow::Problem &P = sm.ap;
   const int m = P.m;
-  if (tid < m) {
+  // four lanes per root (a DPP quad; roots 0..15 on wave 0, the rest on
+  // wave 1), each summing every fourth term of the secular function
+  if (tid < 4 * m) {
+    const int kq = tid >> 2, g = tid & 3;
     int K;
     double tau;
-    arrow::root(P, tid, K, tau);
-    sm.ap_K[tid] = K;
-    sm.ap_tau[tid] = tau;
+    arrow::root_g<4>(P, kq, g, QuadSum(), K, tau);
+    if (g == 0) {
+      sm.ap_K[kq] = K;
+      sm.ap_tau[kq] = tau;
+    }
   }
   __syncthreads();
   if (tid < m) sm.ap_zh[tid] = arrow::zhat(P, tid, sm.ap_K, sm.ap_tau);
@@ -659,48 +684,48 @@ __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, in
   return deficient;
 }
 
-// Second half: U <- [U, p/nu] Uc[:, :k], W <- [W, b] Vc[:, :k] for one cell.
-// Reads every old column of the cell before writing, so it works in place.
-// Uc and Vc (LDS, stride RT_KC, at least RT_KC * RT_KC + 4 entries) are zero
-// outside the core, and the old basis entries past r are masked, so every
-// product runs over the full capacity without branches; the outputs go in
-// blocks of four columns, which bounds the registers the LDS reads take.
-__device__ __forceinline__ void rotate_block(const double (&old)[RT_RMAX], double e, const double *Cc, int r,
-                                             int k, double *X, int ld, int c) {
+// Second half: U <- [U, p/nu] Uc[:, :k] (or W <- [W, b] Vc[:, :k]) for the
+// cells c[0..NCELL) of one thread, given their old rows; works in place.  The
+// coefficients Cc (LDS, stride RT_KC, at least RT_KC * RT_KC + 4 entries) are
+// zero outside the core, and the old basis entries past r are masked, so
+// every product runs over the full capacity without branches.  Each
+// coefficient read from LDS serves NCELL cells, and the outputs go in blocks
+// of four columns, which bounds the registers the LDS reads take.
+template <int NCELL>
+__device__ __forceinline__ void rotate_block(const double (&old)[NCELL][RT_RMAX], const double (&e)[NCELL],
+                                             const double *Cc, int r, int k, double *X, int ld, const int (&c)[NCELL],
+                                             const bool (&ok)[NCELL]) {
 #pragma unroll 1
   for (int j0 = 0; j0 < k; j0 += 4) {
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double acc[NCELL][4];
+#pragma unroll
+    for (int i = 0; i < NCELL; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) acc[i][jj] = 0.0;
 #pragma unroll
     for (int q = 0; q < RT_RMAX; ++q)
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) acc[jj] = rt_fma(old[q], Cc[q * RT_KC + j0 + jj], acc[jj]);
+      for (int jj = 0; jj < 4; ++jj) {
+        const double cf = Cc[q * RT_KC + j0 + jj];
+#pragma unroll
+        for (int i = 0; i < NCELL; ++i) acc[i][jj] = rt_fma(old[i][q], cf, acc[i][jj]);
+      }
     // row r: the new direction (p / nu for U, b for W)
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) acc[jj] = rt_fma(e, Cc[r * RT_KC + j0 + jj], acc[jj]);
+    for (int jj = 0; jj < 4; ++jj) {
+      const double cf = Cc[r * RT_KC + j0 + jj];
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj)
-      if (j0 + jj < k) X[(size_t)(j0 + jj) * ld + c] = acc[jj];
+      for (int i = 0; i < NCELL; ++i) acc[i][jj] = rt_fma(e[i], cf, acc[i][jj]);
+    }
+#pragma unroll
+    for (int i = 0; i < NCELL; ++i)
+      if (ok[i])
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+          if (j0 + jj < k) X[(size_t)(j0 + jj) * ld + c[i]] = acc[i][jj];
   }
 }
 
-__device__ __forceinline__ void isvd_rotate_cell(const RomDev &R, const RomPend &P, const double *Uc,
-                                                 const double *Vc, int ld, int c) {
-  const int r = P.r_old, k = P.k;
-  double old[RT_RMAX];
-#pragma unroll
-  for (int q = 0; q < RT_RMAX; ++q) {
-    const double v = R.U[(size_t)q * ld + c];
-    old[q] = q < r ? v : 0.0;
-  }
-  // inv_nu = 0 for a rank-deficient snapshot (row r of Uc is zero then too)
-  rotate_block(old, P.p[c] * P.inv_nu, Uc, r, k, R.U, ld, c);
-#pragma unroll
-  for (int q = 0; q < RT_RMAX; ++q) {
-    const double v = R.W[(size_t)q * ld + c];
-    old[q] = q < r ? v : 0.0;
-  }
-  rotate_block(old, P.b[c], Vc, r, k, R.W, ld, c);
-}
 
 // ---------------------------------------------------------------------------
 // Per-thread partial sums of ||rho^n||^2, ||rho^(0) - rho^n||^2 and

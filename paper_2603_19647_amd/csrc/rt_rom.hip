@@ -271,37 +271,53 @@ __global__ void __launch_bounds__(256) k_rom_post_small(const Inst *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// k_rom_update: U <- [U, p/nu] Uc, W <- [W, b] Vc, one thread per cell.
-// One-wave blocks: every thread reads all rotation coefficients from LDS, so
-// spreading the cells over more compute units spreads that LDS traffic.
+// k_rom_update: U <- [U, p/nu] Uc, W <- [W, b] Vc (App. B), grid (cell
+// blocks, instance, 4) with z = 2 * ROM + (0: U, 1: W); each thread rotates
+// UPD_CPT cells (strided by the block width, so every load is coalesced).
+// Every cell's arithmetic is the same whatever UPD_CPT: one cell per thread
+// spreads a small launch over more compute units, four per thread cut the
+// LDS reads of the coefficients in a large one.
 // ---------------------------------------------------------------------------
 constexpr int UPD_BLK = 64;
+template <int UPD_CPT>
 __global__ void __launch_bounds__(UPD_BLK) k_rom_update(const Inst *__restrict__ insts) {
   const Inst &I = insts[blockIdx.y];
   // four spare entries: the column blocks of the rotation read up to three
   // entries past the last row (discarded products)
-  __shared__ double uc[2][RT_KC * RT_KC + 4], vc[2][RT_KC * RT_KC + 4];
+  __shared__ double cc[RT_KC * RT_KC + 4];
   if (I.method != RT_ROM) return;
-  if ((int)(blockIdx.x * blockDim.x) >= I.nc) return;
-  const RomPend *P[2] = {I.ig.pend, I.pc.pend};
-  const int pend0 = P[0]->pending, pend1 = P[1]->pending;
-  if (!pend0 && !pend1) return;
-  for (int e = threadIdx.x; e < RT_KC * RT_KC; e += blockDim.x) {
-    if (pend0) {
-      uc[0][e] = P[0]->Uc[e];
-      vc[0][e] = P[0]->Vc[e];
-    }
-    if (pend1) {
-      uc[1][e] = P[1]->Uc[e];
-      vc[1][e] = P[1]->Vc[e];
-    }
-  }
+  const int cb = blockIdx.x * UPD_BLK * UPD_CPT;
+  if (cb >= I.nc) return;
+  const int rom = blockIdx.z >> 1, mat = blockIdx.z & 1;
+  const RomDev &R = rom ? I.pc : I.ig;
+  const RomPend &P = *R.pend;
+  if (!P.pending) return;
+  const double *src = mat ? P.Vc : P.Uc;
+  for (int e = threadIdx.x; e < RT_KC * RT_KC; e += blockDim.x) cc[e] = src[e];
   __syncthreads();
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < I.nc) {
-    if (pend0) isvd_rotate_cell(I.ig, *P[0], uc[0], vc[0], I.ld, c);
-    if (pend1) isvd_rotate_cell(I.pc, *P[1], uc[1], vc[1], I.ld, c);
+  const int r = P.r_old, ld = I.ld;
+  double *X = mat ? R.W : R.U;
+  // the cells' old basis rows, all loads in flight together (masked past r;
+  // cells past nc read the padded tail of the column, ld >= nc rounded up,
+  // and are not written)
+  int c[UPD_CPT];
+  bool ok[UPD_CPT];
+  double old[UPD_CPT][RT_RMAX], e[UPD_CPT];
+#pragma unroll
+  for (int i = 0; i < UPD_CPT; ++i) {
+    c[i] = cb + i * UPD_BLK + threadIdx.x;
+    ok[i] = c[i] < I.nc;
+    const int cl = ok[i] ? c[i] : I.nc - 1;
+#pragma unroll
+    for (int q = 0; q < RT_RMAX; ++q) {
+      const double v = X[(size_t)q * ld + cl];
+      old[i][q] = q < r ? v : 0.0;
+    }
+    // row r: p / nu for U (inv_nu = 0 and a zero row when the snapshot was
+    // rank-deficient), b for W
+    e[i] = mat ? P.b[cl] : P.p[cl] * P.inv_nu;
   }
+  rotate_block<UPD_CPT>(old, e, cc, r, P.k, X, ld, c, ok);
 }
 
 extern "C" hipError_t rt_launch_rom(const Inst *dinsts, int ninst, int nc_max, int any_rom, hipStream_t s) {
@@ -333,7 +349,14 @@ extern "C" hipError_t rt_launch_rom_slab(const Inst *dinsts, int ninst, int any_
 }
 
 extern "C" hipError_t rt_launch_rom_update(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream) {
-  hipLaunchKernelGGL(k_rom_update, dim3((nc_max + UPD_BLK - 1) / UPD_BLK, ninst), dim3(UPD_BLK), 0, stream, dinsts);
+  if ((long long)nc_max * ninst <= 65536) {
+    hipLaunchKernelGGL(k_rom_update<1>, dim3((nc_max + UPD_BLK - 1) / UPD_BLK, ninst, 4), dim3(UPD_BLK), 0, stream,
+                       dinsts);
+  } else {
+    const int cells = UPD_BLK * 4;
+    hipLaunchKernelGGL(k_rom_update<4>, dim3((nc_max + cells - 1) / cells, ninst, 4), dim3(UPD_BLK), 0, stream,
+                       dinsts);
+  }
   return hipGetLastError();
 }
 

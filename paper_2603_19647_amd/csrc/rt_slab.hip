@@ -503,7 +503,9 @@ extern "C" hipError_t rt_launch_slab_si(const Inst *dinsts, int ninst, int nthre
 // workgroup amortises its set-up over several pairs.
 static hipError_t launch_fpass(const Inst *dinsts, int ninst, int nthreads, int cmax, int npair_max, int nc_max,
                                int rhs_only, int pairs_total, hipStream_t stream) {
-  const int gp = std::max(1, std::min(npair_max, (pairs_total + 1023) / 1024));
+  // large launches: one workgroup per instance, which computes the isotropic
+  // source once for all its pairs
+  const int gp = pairs_total > 4096 ? npair_max : std::max(1, std::min(npair_max, (pairs_total + 1023) / 1024));
   dim3 grid((npair_max + gp - 1) / gp, ninst), blk(nthreads);
   if (cmax <= 4)
     hipLaunchKernelGGL((k_fpass_pair<4, 1024>), grid, blk, 0, stream, dinsts, rhs_only, gp);
