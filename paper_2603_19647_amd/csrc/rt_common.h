@@ -196,22 +196,89 @@ __device__ __forceinline__ void wg_max2(double a, double b, double *red, double 
 // map 2 is (a2 a1, a2 b1 + b2).  slots: LDS of 8*RT_MAXWAVES elements;
 // `parity` alternates between calls so one barrier per call suffices.
 // ---------------------------------------------------------------------------
+// DPP lane move with a fill value: lanes whose source lane is outside the
+// pattern keep `old` (bound_ctrl off).
+template <int CTRL>
+__device__ __forceinline__ double dpp_fill(double old, double v) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_fill(float old, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_value(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// Composition helpers for maps x -> A x + B: (A, B) <- (A, B) o (a, b).
+template <typename R>
+__device__ __forceinline__ void compose_after(R &A, R &B, R a, R b) {
+  B = rt_fma(A, b, B);
+  A = A * a;
+}
+
+// Inclusive scans of affine maps inside the 16-lane DPP rows: forward takes
+// the maps of the lower lanes first (row_shr), backward those of the higher
+// lanes (row_shl).
+template <typename R>
+__device__ __forceinline__ void row_scan_fwd(R &A, R &B) {
+  compose_after(A, B, dpp_fill<0x111>(R(1), A), dpp_fill<0x111>(R(0), B));  // row_shr:1
+  compose_after(A, B, dpp_fill<0x112>(R(1), A), dpp_fill<0x112>(R(0), B));  // row_shr:2
+  compose_after(A, B, dpp_fill<0x114>(R(1), A), dpp_fill<0x114>(R(0), B));  // row_shr:4
+  compose_after(A, B, dpp_fill<0x118>(R(1), A), dpp_fill<0x118>(R(0), B));  // row_shr:8
+}
+template <typename R>
+__device__ __forceinline__ void row_scan_bwd(R &A, R &B) {
+  compose_after(A, B, dpp_fill<0x101>(R(1), A), dpp_fill<0x101>(R(0), B));  // row_shl:1
+  compose_after(A, B, dpp_fill<0x102>(R(1), A), dpp_fill<0x102>(R(0), B));  // row_shl:2
+  compose_after(A, B, dpp_fill<0x104>(R(1), A), dpp_fill<0x104>(R(0), B));  // row_shl:4
+  compose_after(A, B, dpp_fill<0x108>(R(1), A), dpp_fill<0x108>(R(0), B));  // row_shl:8
+}
+
 template <typename R>
 __device__ __forceinline__ void wg_scan2(R Af, R Bf, R Ab, R Bb, R gF, R gB, R &inF, R &inB,
                                          R *slots, int parity) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    R a2 = __shfl_up(Af, off, 64), b2 = __shfl_up(Bf, off, 64);
-    R c2 = __shfl_down(Ab, off, 64), d2 = __shfl_down(Bb, off, 64);
-    if (lane >= off) {
-      Bf = rt_fma(Af, b2, Bf);
-      Af = Af * a2;
-    }
-    if (lane + off < 64) {
-      Bb = rt_fma(Ab, d2, Bb);
-      Ab = Ab * c2;
-    }
+  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: lane reads below
+  const int row = lane >> 4;
+  // wave scans: inside each DPP row, then across the four rows with the row
+  // totals (lanes 15, 31, 47 forward; 48, 32, 16 backward)
+  row_scan_fwd(Af, Bf);
+  row_scan_bwd(Ab, Bb);
+  {
+    const R a0 = lane_value(Af, 15), b0 = lane_value(Bf, 15);
+    const R a1 = lane_value(Af, 31), b1 = lane_value(Bf, 31);
+    const R a2 = lane_value(Af, 47), b2 = lane_value(Bf, 47);
+    // prefixes of rows 0, 0..1, 0..2
+    R pA1 = a0, pB1 = b0;
+    R pA2 = a1, pB2 = b1;
+    compose_after(pA2, pB2, pA1, pB1);
+    R pA3 = a2, pB3 = b2;
+    compose_after(pA3, pB3, pA2, pB2);
+    const R pA = row == 1 ? pA1 : (row == 2 ? pA2 : (row == 3 ? pA3 : R(1)));
+    const R pB = row == 1 ? pB1 : (row == 2 ? pB2 : (row == 3 ? pB3 : R(0)));
+    compose_after(Af, Bf, pA, pB);
+  }
+  {
+    const R a3 = lane_value(Ab, 48), b3 = lane_value(Bb, 48);
+    const R a2 = lane_value(Ab, 32), b2 = lane_value(Bb, 32);
+    const R a1 = lane_value(Ab, 16), b1 = lane_value(Bb, 16);
+    // suffixes of rows 3, 2..3, 1..3
+    R qA2 = a3, qB2 = b3;
+    R qA1 = a2, qB1 = b2;
+    compose_after(qA1, qB1, qA2, qB2);
+    R qA0 = a1, qB0 = b1;
+    compose_after(qA0, qB0, qA1, qB1);
+    const R qA = row == 0 ? qA0 : (row == 1 ? qA1 : (row == 2 ? qA2 : R(1)));
+    const R qB = row == 0 ? qB0 : (row == 1 ? qB1 : (row == 2 ? qB2 : R(0)));
+    compose_after(Ab, Bb, qA, qB);
   }
   R *s = slots + parity * 4 * RT_MAXWAVES;
   if (lane == 63) {
@@ -222,21 +289,20 @@ __device__ __forceinline__ void wg_scan2(R Af, R Bf, R Ab, R Bb, R gF, R gB, R &
     s[2 * RT_MAXWAVES + wave] = Ab;
     s[3 * RT_MAXWAVES + wave] = Bb;
   }
-  R eAf = __shfl_up(Af, 1, 64), eBf = __shfl_up(Bf, 1, 64);
-  R eAb = __shfl_down(Ab, 1, 64), eBb = __shfl_down(Bb, 1, 64);
-  if (lane == 0) {
-    eAf = R(1);
-    eBf = R(0);
-  }
-  if (lane == 63) {
-    eAb = R(1);
-    eBb = R(0);
-  }
+  // exclusive values: the lane below (forward) / above (backward)
+  const R eAf = dpp_fill<0x138>(R(1), Af), eBf = dpp_fill<0x138>(R(0), Bf);  // wave_shr:1
+  const R eAb = dpp_fill<0x130>(R(1), Ab), eBb = dpp_fill<0x130>(R(0), Bb);  // wave_shl:1
   __syncthreads();
-  R vF = gF;
-  for (int k = 0; k < wave; ++k) vF = rt_fma(s[k], vF, s[RT_MAXWAVES + k]);
-  R vB = gB;
-  for (int k = nw - 1; k > wave; --k) vB = rt_fma(s[2 * RT_MAXWAVES + k], vB, s[3 * RT_MAXWAVES + k]);
+  // across waves: scan the wave totals in DPP row 0 (nw <= 16), every wave
+  // alike, and take the prefix of the waves before / suffix of those after
+  const bool w_ok = lane < nw;
+  R tAf = w_ok ? s[lane] : R(1), tBf = w_ok ? s[RT_MAXWAVES + lane] : R(0);
+  R tAb = w_ok ? s[2 * RT_MAXWAVES + lane] : R(1), tBb = w_ok ? s[3 * RT_MAXWAVES + lane] : R(0);
+  row_scan_fwd(tAf, tBf);
+  row_scan_bwd(tAb, tBb);
+  R vF = gF, vB = gB;
+  if (wave > 0) vF = rt_fma(lane_value(tAf, wave - 1), gF, lane_value(tBf, wave - 1));
+  if (wave + 1 < nw) vB = rt_fma(lane_value(tAb, wave + 1), gB, lane_value(tBb, wave + 1));
   inF = rt_fma(eAf, vF, eBf);
   inB = rt_fma(eAb, vB, eBb);
 }
