@@ -63,6 +63,14 @@ typedef enum {
 /* flags */
 #define RTROM_F_ABS_UP_NORM 0x1ull /* error indicators in the paper's absolute
                                       2-norm instead of relative to ||rho^n|| */
+#define RTROM_F_SINGLE_WG 0x2ull   /* 1D: run the SI loop on one workgroup even
+                                      when the problem is marched on its own
+                                      (by default such a march splits the
+                                      ordinate pairs over up to 16 co-resident
+                                      workgroups; batches and the server always
+                                      use one workgroup per problem).  Results
+                                      are deterministic either way; the two
+                                      modes differ at rounding level. */
 
 typedef struct rtrom_problem rtrom_problem; /* opaque */
 

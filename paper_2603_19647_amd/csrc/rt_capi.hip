@@ -267,6 +267,18 @@ int slab_launch_threads(const int *nthr, const int *nc, int n, int *cmax) {
 }
 }  // namespace
 
+// Pair groups of the cooperative slab SI: up to 16 workgroups, each sweeping
+// pg consecutive ordinate pairs.  ng = 0: one workgroup (no cooperation).
+static void slab_groups(const rtrom_problem_desc *d, int nv, int *ng, int *pg) {
+  const int npair = nv / 2;
+  *ng = 0;
+  *pg = npair;
+  if (d->dim != 1 || (d->flags & RTROM_F_SINGLE_WG) || npair < 2) return;
+  const int g = std::min(16, npair);
+  *pg = (npair + g - 1) / g;
+  *ng = (npair + *pg - 1) / *pg;
+}
+
 static size_t slab_bytes(const rtrom_problem_desc *d, int nv) {
   const size_t nc = (size_t)d->nx * d->ny;
   const size_t ld = (nc + 31) & ~size_t(31);
@@ -277,6 +289,14 @@ static size_t slab_bytes(const rtrom_problem_desc *d, int nv) {
   if (d->dim == 1) {  // 2D keeps its folded f in the plane buffers
     L.take((size_t)nv * nc * 8);
     L.take((size_t)(nv / 2) * nc * 8);
+    int ng, pg;
+    slab_groups(d, nv, &ng, &pg);
+    if (ng > 1) {
+      L.take(2 * (size_t)ng * nc * 8);
+      L.take(2 * (size_t)ng * nc * 4);
+      L.take(2 * (size_t)ng * RT_RMAX * 8);
+      L.take(4 * 8);
+    }
   }
   for (int r = 0; r < 2; ++r) {
     L.take((RT_RMAX + 1) * ld * 8);
@@ -409,6 +429,13 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   double *qbuf = D((size_t)nv * 8 * 6);
   I.f = d->dim == 1 ? D((size_t)nv * nc * 8) : nullptr;
   I.fpart = d->dim == 1 ? D((size_t)(nv / 2) * nc * 8) : nullptr;
+  slab_groups(d, nv, &I.ng, &I.pg);
+  if (I.ng > 1) {
+    I.sip = D(2 * (size_t)I.ng * nc * 8);
+    I.sip32 = (float *)D(2 * (size_t)I.ng * nc * 4);
+    I.apx = D(2 * (size_t)I.ng * RT_RMAX * 8);
+    I.bar = (unsigned long long *)D(4 * 8);
+  }
   RomDev *roms[2] = {&I.ig, &I.pc};
   RomWork rom_work_init[2];
   for (int r = 0; r < 2; ++r) {
@@ -584,7 +611,10 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps, int n, int nsteps) 
     hipStream_t s2 = any_rom ? ps[0]->aux_stream : s;
     for (int k = 0; k < nsteps; ++k) {
       rt_prof_begin(RT_K_SLAB_SI, s);
-      RT_HIP(rt_launch_slab_si(dinsts, n, nt, cmax, s), "SI launch");
+      if (n == 1 && ps[0]->hinst.ng > 1)
+        RT_HIP(rt_launch_slab_si_coop(dinsts, ps[0]->hinst.ng, nt, cmax, s), "cooperative SI launch");
+      else
+        RT_HIP(rt_launch_slab_si(dinsts, n, nt, cmax, s), "SI launch");
       rt_prof_end(RT_K_SLAB_SI, s);
       if (s2 != s) {
         RT_HIP(hipEventRecord(ps[0]->ev_si, s), "event");
@@ -635,6 +665,10 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps, int n, int nsteps) 
     ps[i]->steps += nsteps;
     ps[i]->t_total += ms * 1e-3 / n;
     if (after[i].nonconv != before[i].nonconv) res = RTROM_ENOCONV;
+    if (after[i].fault) {
+      rt_set_error("a cooperative grid barrier timed out; the problem's state is invalid");
+      return RTROM_EDEVICE;
+    }
   }
   if (res == RTROM_ENOCONV) rt_set_error("a time step reached max_iter without meeting the tolerance");
   return res;

@@ -65,7 +65,8 @@ struct RtState {
   long long steps, si_total, sweeps_total, ig_updates, pc_updates, fp32_sweeps;
   int nonconv, fallbacks;
   // written by the SI kernel for the step in flight, read by the post kernel
-  int iters, conv, used_pc, ig_fb, pc_fb, phase, cur, pad1;  // cur: b~ buffer of the step
+  int iters, conv, used_pc, ig_fb, pc_fb, phase, cur;  // cur: b~ buffer of the step
+  int fault;  // a cooperative grid barrier gave up waiting (sticky)
   double residual;
 };
 
@@ -98,6 +99,12 @@ struct Inst {
   // state
   double *f;        // [nv][nc]
   double *fpart;    // 1D: [npair][nc] per-pair moments of the f-pass
+  // 1D cooperative SI (ng > 1): pair group g = pairs [g*pg, g*pg + pg)
+  int ng, pg;
+  double *sip;      // [2][ng][nc] FP64 group moments (exchange double buffer)
+  float *sip32;     // [2][ng][nc] FP32 group moments
+  double *apx;      // [2][ng][RT_RMAX] DMD projection partials
+  unsigned long long *bar;  // grid barrier counters [3]
   double *rho;      // rho^n
   double *bt2[2];   // b~ double buffer: the next step reads bt2[steps & 1]
                     // and its f-pass writes the other one

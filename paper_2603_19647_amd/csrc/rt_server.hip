@@ -186,6 +186,11 @@ extern "C" rtrom_status rtrom_server_submit(rtrom_server *s, const rtrom_problem
     rt_set_error("server: nsteps must be >= 0");
     return RTROM_EINVAL;
   }
+  // served problems run one workgroup each (RTROM_F_SINGLE_WG): many march
+  // at once, so none may rely on co-resident workgroups of its own
+  rtrom_problem_desc dd = *d;
+  dd.flags |= RTROM_F_SINGLE_WG;
+  d = &dd;
   rtrom_status v = rt_validate(d);
   if (v != RTROM_OK) return v;
   uint64_t bytes = 0;

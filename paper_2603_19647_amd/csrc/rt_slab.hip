@@ -8,6 +8,14 @@
 // evaluated as a workgroup-wide affine prefix scan (wg_scan2).  The two
 // ordinates of a mirror pair (mu, -mu) share a_i and the reciprocal of
 // (sigma_t + 1/dt + |mu|/h) and are scanned together in opposite directions.
+//
+// A problem marched on its own may instead run its SI loop cooperatively on
+// ng workgroups (k_si_slab<..., true>): workgroup g sweeps ordinate-pair group
+// g and every workgroup keeps the full per-cell state, so after each sweep
+// the groups' moments are exchanged (agent-scope atomic stores and loads,
+// coherent across the L2 slices, then a grid barrier) and every workgroup
+// continues with the same data and takes the same decisions.  DMD guesses
+// are computed by cell slices and exchanged the same way.
 #include <algorithm>
 
 #include "rt_common.h"
@@ -16,15 +24,84 @@
 namespace {
 
 // ---------------------------------------------------------------------------
+// Cooperative execution: exchange through agent-scope relaxed atomics (no
+// cache maintenance needed) and a grid barrier on monotone counters.
+// bar[0] counts arrivals, bar[1] is the last released generation and bar[2]
+// the generations completed by earlier launches, so nothing is reset between
+// launches.  Every workgroup passes the same barriers (identical control
+// flow).  A wait is bounded: one that gives up sets the state's fault flag
+// and falls through (the host reports the step as failed) instead of hanging.
+// ---------------------------------------------------------------------------
+struct CoopSync {
+  unsigned long long *bar;
+  unsigned long long gen;
+  int *fault;
+  int buf;  // double buffer of the next exchange
+};
+
+__device__ __forceinline__ double xload(const double *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float xload(const float *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void xstore(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void xstore(float *p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void grid_sync(CoopSync &S) {
+  ++S.gen;
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's exchange stores are complete
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long nb = gridDim.x;
+    const unsigned long long prev =
+        __hip_atomic_fetch_add(&S.bar[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev + 1 == S.gen * nb) {
+      __hip_atomic_store(&S.bar[1], S.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      // after a fault the counters are out of step: no further waiting
+      unsigned spins = 0;
+      while (__hip_atomic_load(&S.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < S.gen &&
+             !__hip_atomic_load(S.fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins == (1u << 26)) {
+          __hip_atomic_store(S.fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <typename R>
+__device__ __forceinline__ R *coop_part(const Inst &I);
+template <>
+__device__ __forceinline__ double *coop_part<double>(const Inst &I) { return I.sip; }
+template <>
+__device__ __forceinline__ float *coop_part<float>(const Inst &I) { return I.sip32; }
+
+// ---------------------------------------------------------------------------
 // Sweep with an ordinate-independent source s and zero inflow, returning the
 // angular moment acc = sum_j w_j f_j (the operator T of Sec. 2.3 applied to s).
+// COOP: this workgroup sweeps its pair group only, then the groups' moments
+// are summed in group order (the same sum in every workgroup).
 // ---------------------------------------------------------------------------
-template <int CMAX, typename R>
-__device__ __forceinline__ void sweep_moment(const Inst &I, const R (&ct)[CMAX], const R (&s)[CMAX], int n,
-                                             R (&acc)[CMAX], R *slots, int &parity) {
+template <int CMAX, typename R, bool COOP>
+__device__ __forceinline__ void sweep_moment(const Inst &I, const R (&ct)[CMAX], const R (&s)[CMAX], int n, int c0,
+                                             R (&acc)[CMAX], R *slots, int &parity, CoopSync &cs) {
 #pragma unroll
   for (int t = 0; t < CMAX; ++t) acc[t] = R(0);
-  for (int p = 0; p < I.npair; ++p) {
+  int p0 = 0, p1 = I.npair;
+  if constexpr (COOP) {
+    p0 = blockIdx.x * I.pg;
+    p1 = min(I.npair, p0 + I.pg);
+  }
+  for (int p = p0; p < p1; ++p) {
     const R m = (R)I.pm[p];
     const R w = (R)I.pw[p];
     R a[CMAX], b[CMAX];
@@ -67,6 +144,92 @@ __device__ __forceinline__ void sweep_moment(const Inst &I, const R (&ct)[CMAX],
       }
     }
   }
+  if constexpr (COOP) {
+    const int nc = I.nc, ng = I.ng;
+    R *part = coop_part<R>(I) + (size_t)cs.buf * ng * nc;
+    cs.buf ^= 1;
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t)
+      if (t < n) xstore(&part[(size_t)blockIdx.x * nc + c0 + t], acc[t]);
+    grid_sync(cs);
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t) acc[t] = R(0);
+    // four groups per batch of loads (all in flight together; past ng the
+    // address is clamped and the value masked)
+    const int ct0 = min(c0, nc - 1);
+    for (int g0 = 0; g0 < ng; g0 += 4) {
+      R v[4][CMAX];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int g = min(g0 + q, ng - 1);
+#pragma unroll
+        for (int t = 0; t < CMAX; ++t) v[q][t] = xload(&part[(size_t)g * nc + min(ct0 + t, nc - 1)]);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int t = 0; t < CMAX; ++t)
+          if (g0 + q < ng && t < n) acc[t] += v[q][t];
+    }
+  }
+}
+
+// DMD application (eq. dmd-ig, eq. dmd-sa) by cell slices: workgroup g
+// projects and expands the cells [g*cs, g*cs + cs); the coefficient partials
+// and the expanded vector are exchanged like the sweep moments.  out is
+// written with agent-scope stores; read it with xload.
+__device__ inline void rom_apply_coop(const Inst &I, const RomDev &R, int rank, const double *rhs, double *out,
+                                      double *red, double *vec, CoopSync &cs) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int nc = I.nc, ng = I.ng, ld = I.ld, NT = blockDim.x;
+  const int csz = (nc + ng - 1) / ng;
+  const int lo = blockIdx.x * csz, hi = min(nc, lo + csz);
+  double *apx = I.apx + (size_t)cs.buf * ng * RT_RMAX;
+  cs.buf ^= 1;
+  for (int k0 = 0; k0 < rank; k0 += 4) {
+    double sacc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = lo + (int)threadIdx.x; c < hi; c += NT) {
+      const double v = rhs[c];
+      double u[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) u[q] = R.U[(size_t)(k0 + q) * ld + c];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sacc[q] = rt_fma(u[q], v, sacc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double t = wave_sum_fast(sacc[q]);
+      if (lane == 0) red[wave * RT_RMAX + k0 + q] = t;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < rank) {
+    double sv = 0.0;
+    for (int w = 0; w < nw; ++w) sv += red[w * RT_RMAX + threadIdx.x];
+    xstore(&apx[(size_t)blockIdx.x * RT_RMAX + threadIdx.x], sv);
+  }
+  grid_sync(cs);
+  if ((int)threadIdx.x < RT_RMAX) {
+    double sv = 0.0;
+    if ((int)threadIdx.x < rank)
+      for (int g = 0; g < ng; ++g) sv += xload(&apx[(size_t)g * RT_RMAX + threadIdx.x]);
+    vec[threadIdx.x] = sv;  // zero past the rank
+  }
+  __syncthreads();
+  lu_solve_wave(R.LU, R.perm, rank, vec);
+  for (int c = lo + (int)threadIdx.x; c < hi; c += NT) {
+    double v = 0.0;
+#pragma unroll 1
+    for (int k0 = 0; k0 < RT_RMAX; k0 += 5) {
+      double u[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) u[q] = R.U[(size_t)(k0 + q) * ld + c];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) v = rt_fma(u[q], vec[k0 + q], v);
+    }
+    xstore(&out[c], v);
+  }
+  grid_sync(cs);
 }
 
 // DSA correction (eq. rho_residual): solve C d = rhs with the precomputed
@@ -128,12 +291,15 @@ __device__ __forceinline__ bool stop_test(double dn, double yn, double tol) {
 
 // ---------------------------------------------------------------------------
 // k_si_slab: initial guess + Alg. 1 (SI with DSA, or the hybrid ROM/DSA
-// preconditioner of Sec. 3.2 phase 3) for every instance of the launch.
-// Writes rho^n, rho^{(0)}, rho^{(1/2)}, the PC correction and per-step status.
+// preconditioner of Sec. 3.2 phase 3) for every instance of the launch, then
+// the step's error indicators and Alg. 2's decisions (rom_decide).  Writes
+// rho^n, rho^{(0)}, rho^{(1/2)}, the PC correction and per-step status.
+// COOP: one instance on gridDim.x = ng workgroups (see the file comment);
+// workgroup 0 writes the state and results.
 // ---------------------------------------------------------------------------
-template <int CMAX, int MAXT>
+template <int CMAX, int MAXT, bool COOP>
 __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts) {
-  const Inst &I = insts[blockIdx.x];
+  const Inst &I = insts[COOP ? 0 : blockIdx.x];
   __shared__ double slots[8 * RT_MAXWAVES];
   __shared__ float slotsf[8 * RT_MAXWAVES];
   __shared__ double red[2 * RT_MAXWAVES];
@@ -144,6 +310,7 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
   const int C = (nc + NT - 1) / NT;
   const int c0 = tid * C;
   const int n = max(0, min(C, nc - c0));
+  const bool leader = !COOP || blockIdx.x == 0;
   RtState *st = I.st;
   const int rom = (I.method == RT_ROM);
   const int flag_ig = st->flag_ig, flag_pc = st->flag_pc;
@@ -152,14 +319,31 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
   const int mixed = (I.precision == RT_MIXED);
   const int cur = (int)(st->steps & 1);
   const double *__restrict__ bt = I.bt2[cur];
+  CoopSync cs{nullptr, 0ull, nullptr, 0};
+  if constexpr (COOP) {
+    // a barrier that gave up left the counters out of step: the state is
+    // invalid (the host reports it) and later launches do nothing
+    if (__hip_atomic_load(&st->fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    cs.bar = I.bar;
+    cs.gen = __hip_atomic_load(&I.bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    cs.fault = &st->fault;
+  }
+  // a vector the cooperative DMD apply wrote (other workgroups' slices)
+  auto rd = [&](const double *p) { return COOP ? xload(p) : *p; };
 
   // initial guess: DMD when the IG ROM is available (eq. dmd-ig), else rho^{n-1}
   int ig_fb = 0;
   if (rom && flag_ig && lu_ig) {
-    rom_apply(I.ig, rank_ig, I.ld, nc, NT, bt, I.rho0, rred, rvec);
+    if constexpr (COOP) rom_apply_coop(I, I.ig, rank_ig, bt, I.rho0, rred, rvec, cs);
+    else rom_apply(I.ig, rank_ig, I.ld, nc, NT, bt, I.rho0, rred, rvec);
   } else {
     ig_fb = rom && flag_ig;
-    for (int c = c0; c < c0 + n; ++c) I.rho0[c] = I.rho[c];
+    // every workgroup copies (the same values; agent-scope stores, like the
+    // cooperative DMD output, so later reads see them wherever they land)
+    for (int c = c0; c < c0 + n; ++c) {
+      if constexpr (COOP) xstore(&I.rho0[c], I.rho[c]);
+      else I.rho0[c] = I.rho[c];
+    }
   }
   double ct[CMAX], ss[CMAX], rp[CMAX], y[CMAX];
 #pragma unroll
@@ -167,7 +351,7 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
     const bool in = t < n;
     ct[t] = in ? I.ct[c0 + t] : 1.0;
     ss[t] = in ? I.ss[c0 + t] : 0.0;
-    rp[t] = in ? I.rho0[c0 + t] : 0.0;
+    rp[t] = in ? rd(&I.rho0[c0 + t]) : 0.0;
     y[t] = 0.0;
   }
   int parity = 0, parityf = 0;
@@ -180,10 +364,10 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
       double s[CMAX], acc[CMAX];
 #pragma unroll
       for (int t = 0; t < CMAX; ++t) s[t] = ss[t] * rp[t];
-      sweep_moment<CMAX, double>(I, ct, s, n, acc, slots, parity);
+      sweep_moment<CMAX, double, COOP>(I, ct, s, n, c0, acc, slots, parity, cs);
 #pragma unroll
       for (int t = 0; t < CMAX; ++t) y[t] = acc[t] + ((t < n) ? bt[c0 + t] : 0.0);
-      if (nsweep == 0) {
+      if (nsweep == 0 && leader) {
 #pragma unroll
         for (int t = 0; t < CMAX; ++t)
           if (t < n) I.rhalf[c0 + t] = y[t];
@@ -217,14 +401,16 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
     // synthetic acceleration
     double d[CMAX];
     if (rom && first_corr && flag_pc && lu_pc) {
-      // ROM-enhanced correction of the first iteration (eq. dmd-sa)
+      // ROM-enhanced correction of the first iteration (eq. dmd-sa); every
+      // workgroup writes the same right-hand side and reads its own copy
 #pragma unroll
       for (int t = 0; t < CMAX; ++t)
-        if (t < n) I.work[c0 + t] = y[t] - I.rho0[c0 + t];
+        if (t < n) I.work[c0 + t] = y[t] - rd(&I.rho0[c0 + t]);
       __syncthreads();
-      rom_apply(I.pc, rank_pc, I.ld, nc, NT, I.work, I.dpc, rred, rvec);
+      if constexpr (COOP) rom_apply_coop(I, I.pc, rank_pc, I.work, I.dpc, rred, rvec, cs);
+      else rom_apply(I.pc, rank_pc, I.ld, nc, NT, I.work, I.dpc, rred, rvec);
 #pragma unroll
-      for (int t = 0; t < CMAX; ++t) d[t] = (t < n) ? I.dpc[c0 + t] : 0.0;
+      for (int t = 0; t < CMAX; ++t) d[t] = (t < n) ? rd(&I.dpc[c0 + t]) : 0.0;
       used_pc = 1;
     } else if (I.method == RT_SI_PLAIN) {
 #pragma unroll
@@ -247,7 +433,7 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
         ctf[t] = (float)ct[t];
         rp[t] = rn;
       }
-      sweep_moment<CMAX, float>(I, ctf, s32, n, acc32, slotsf, parityf);
+      sweep_moment<CMAX, float, COOP>(I, ctf, s32, n, c0, acc32, slotsf, parityf, cs);
 #pragma unroll
       for (int t = 0; t < CMAX; ++t) y[t] += (double)acc32[t];
       exact = 0;
@@ -259,6 +445,7 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
       need64 = 1;
     }
   }
+  if (!leader) return;
   // rho^n = rho^{(l-1/2)} (Alg. 1 returns the un-corrected iterate)
 #pragma unroll
   for (int t = 0; t < CMAX; ++t)
@@ -273,6 +460,7 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
     st->phase = !flag_ig ? 1 : (!flag_pc ? 2 : 3);
     st->cur = cur;
     st->fp32_sweeps += n32;
+    if constexpr (COOP) __hip_atomic_store(&I.bar[2], cs.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
   // end of step: error indicators from the final iterate and Alg. 2's
@@ -284,9 +472,9 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
       if (t < n) {
         const double r = y[t];
         part[0] = rt_fma(r, r, part[0]);
-        const double e1 = I.rho0[c0 + t] - r;
+        const double e1 = rd(&I.rho0[c0 + t]) - r;
         part[1] = rt_fma(e1, e1, part[1]);
-        const double e2 = I.dpc[c0 + t] - (r - I.rhalf[c0 + t]);
+        const double e2 = rd(&I.dpc[c0 + t]) - (r - I.rhalf[c0 + t]);
         part[2] = rt_fma(e2, e2, part[2]);
       }
     wg_sum_fast<3>(part, rred, rvec);
@@ -492,10 +680,21 @@ extern "C" hipError_t rt_launch_slab_si(const Inst *dinsts, int ninst, int nthre
                                         hipStream_t stream) {
   dim3 grid(ninst), blk(nthreads);
   if (cmax <= 4)
-    hipLaunchKernelGGL((k_si_slab<4, 1024>), grid, blk, 0, stream, dinsts);
+    hipLaunchKernelGGL((k_si_slab<4, 1024, false>), grid, blk, 0, stream, dinsts);
   else
-    hipLaunchKernelGGL((k_si_slab<8, 512>), grid, blk, 0, stream, dinsts);
+    hipLaunchKernelGGL((k_si_slab<8, 512, false>), grid, blk, 0, stream, dinsts);
   return hipGetLastError();
+}
+
+// One instance on ng co-resident workgroups (a cooperative launch, which the
+// runtime rejects rather than start when they cannot all be resident).
+extern "C" hipError_t rt_launch_slab_si_coop(const Inst *dinst, int ng, int nthreads, int cmax, hipStream_t stream) {
+  void *args[] = {(void *)&dinst};
+  if (cmax <= 4)
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_si_slab<4, 1024, true>), dim3(ng),
+                                      dim3(nthreads), args, 0, stream);
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_si_slab<8, 512, true>), dim3(ng),
+                                    dim3(nthreads), args, 0, stream);
 }
 
 // gp pairs per workgroup: one when the launch has few pairs in total (every

@@ -20,6 +20,7 @@ OK, EINVAL, ENOMEM, ENOCONV, EDEVICE, EBUSY = 0, -1, -2, -3, -4, -5
 METHOD = {"si_dsa": 0, "rom": 1, "si": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
 F_ABS_UP_NORM = 0x1
+F_SINGLE_WG = 0x2
 
 _D = ctypes.POINTER(ctypes.c_double)
 
@@ -166,7 +167,7 @@ def make_desc(spec, keep: list) -> Desc:
     d.precision = PRECISION[spec.precision]
     d.eps_ig, d.eps_pc, d.eps_up = spec.eps_ig, spec.eps_pc, spec.eps_up
     d.r_max = spec.r_max
-    d.flags = F_ABS_UP_NORM if spec.abs_up_norm else 0
+    d.flags = (F_ABS_UP_NORM if spec.abs_up_norm else 0) | (F_SINGLE_WG if spec.single_wg else 0)
     return d
 
 

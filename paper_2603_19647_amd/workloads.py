@@ -53,6 +53,7 @@ class ProblemSpec:
     eps_up: float = 1e-6
     r_max: int = 20
     abs_up_norm: bool = False
+    single_wg: bool = False  # 1D: one workgroup even when marched alone (device mode only)
     nsteps: int = 1
     name: str = ""
 

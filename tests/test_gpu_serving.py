@@ -28,7 +28,7 @@ def _requests():
 
 
 def _alone(spec):
-    p = rtrom.Problem(spec)
+    p = rtrom.Problem(spec.replace(single_wg=True))  # as the server runs it
     p.march(spec.nsteps)
     rho, st = p.rho(), p.stats()
     p.close()

@@ -44,6 +44,31 @@ def test_slab256_rom_fp64():
     assert st["n0"] > 0 and st["n1"] > 0
 
 
+@pytest.mark.parametrize("nv", [16, 64])
+def test_single_workgroup_mode_rom_fp64(nv):
+    """The one-workgroup SI kernel (batches, served problems, RTROM_F_SINGLE_WG)
+    against the oracle.  A problem marched on its own by default splits its
+    ordinate pairs over workgroups; the other tests cover that mode."""
+    spec = W.random_slab(31, 700, nv, method="rom", precision="fp64", single_wg=True)
+    say(f"single-workgroup rom fp64 700x{nv}")
+    errs, o, g = step_both(spec, 30)
+    assert errs.max() <= FP64_TOL, errs.max()
+    assert_same_decisions(o, g)
+
+
+def test_cooperative_and_single_workgroup_agree():
+    """The two SI kernels sum the pair moments in different orders only."""
+    spec = W.random_slab(32, 1500, 64, method="rom", precision="fp64")
+    say("cooperative vs one workgroup, rom fp64 1500x64")
+    a = rtrom.Problem(spec)
+    b = rtrom.Problem(spec.replace(single_wg=True))
+    for _ in range(25):
+        a.step()
+        b.step()
+        assert rel_l2(a.rho(), b.rho()) <= FP64_TOL
+    np.testing.assert_array_equal(a.history()["iters"], b.history()["iters"])
+
+
 @pytest.mark.parametrize("nx,nv", [(1, 2), (5, 4), (63, 8), (64, 8), (65, 16), (257, 4), (1000, 16),
                                    (2049, 32), (4096, 64)])
 def test_ragged_sizes_si_dsa(nx, nv):
@@ -134,7 +159,7 @@ def test_batch_equals_alone_bitwise():
     batch = [rtrom.Problem(s) for s in specs]
     rtrom.march_batch(batch, 25)
     for s, b in zip(specs, batch):
-        a = rtrom.Problem(s)
+        a = rtrom.Problem(s.replace(single_wg=True))  # a batch runs one workgroup per problem
         a.march(25)
         np.testing.assert_array_equal(a.rho(), b.rho())
         assert a.stats()["si_iters_total"] == b.stats()["si_iters_total"]
