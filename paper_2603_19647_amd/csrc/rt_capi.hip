@@ -183,7 +183,6 @@ extern "C" rtrom_status rtrom_cl_quadrature(int32_t n_azim, int32_t n_polar, dou
 // ---------------------------------------------------------------------------
 // Validation (host only, before any device call)
 // ---------------------------------------------------------------------------
-static const int RT_SLAB_MAX_CELLS = 4096;
 
 static rtrom_status validate(const rtrom_problem_desc *d);
 rtrom_status rt_validate(const rtrom_problem_desc *d) { return validate(d); }
@@ -295,7 +294,7 @@ static size_t slab_bytes(const rtrom_problem_desc *d, int nv) {
       L.take(2 * (size_t)ng * nc * 8);
       L.take(2 * (size_t)ng * nc * 4);
       L.take(2 * (size_t)ng * RT_RMAX * 8);
-      L.take(4 * 8);
+      L.take(8 * 8);
     }
   }
   for (int r = 0; r < 2; ++r) {
@@ -434,7 +433,7 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
     I.sip = D(2 * (size_t)I.ng * nc * 8);
     I.sip32 = (float *)D(2 * (size_t)I.ng * nc * 4);
     I.apx = D(2 * (size_t)I.ng * RT_RMAX * 8);
-    I.bar = (unsigned long long *)D(4 * 8);
+    I.bar = (unsigned long long *)D(8 * 8);
   }
   RomDev *roms[2] = {&I.ig, &I.pc};
   RomWork rom_work_init[2];
@@ -609,12 +608,21 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps, int n, int nsteps) 
     // other b~ buffer, the ROM work reads rho's and b~^{n-1} -- and the next
     // SI solve waits for both.
     hipStream_t s2 = any_rom ? ps[0]->aux_stream : s;
-    for (int k = 0; k < nsteps; ++k) {
+    // A problem marched on its own with pair groups runs each step as two
+    // cooperative launches: the SI solve, then everything else (ROM passes,
+    // cores alongside the f-pass, rotation, b~).
+    const bool coop = n == 1 && ps[0]->hinst.ng > 1;
+    for (int k = 0; k < nsteps && coop; ++k) {
       rt_prof_begin(RT_K_SLAB_SI, s);
-      if (n == 1 && ps[0]->hinst.ng > 1)
-        RT_HIP(rt_launch_slab_si_coop(dinsts, ps[0]->hinst.ng, nt, cmax, s), "cooperative SI launch");
-      else
-        RT_HIP(rt_launch_slab_si(dinsts, n, nt, cmax, s), "SI launch");
+      RT_HIP(rt_launch_slab_si_coop(dinsts, ps[0]->hinst.ng, nt, cmax, s), "cooperative SI launch");
+      rt_prof_end(RT_K_SLAB_SI, s);
+      rt_prof_begin(RT_K_POST, s);
+      RT_HIP(rt_launch_slab_tail_coop(dinsts, ps[0]->hinst.npair, ps[0]->nc, nt, cmax, s), "cooperative tail launch");
+      rt_prof_end(RT_K_POST, s);
+    }
+    for (int k = 0; k < nsteps && !coop; ++k) {
+      rt_prof_begin(RT_K_SLAB_SI, s);
+      RT_HIP(rt_launch_slab_si(dinsts, n, nt, cmax, s), "SI launch");
       rt_prof_end(RT_K_SLAB_SI, s);
       if (s2 != s) {
         RT_HIP(hipEventRecord(ps[0]->ev_si, s), "event");

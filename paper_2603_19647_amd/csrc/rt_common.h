@@ -22,6 +22,7 @@ struct RomPend {
 
 // Work record of one incremental-SVD update in flight: what the decide
 // kernel asked for and the per-block partial sums of the projection passes.
+#define RT_SLAB_MAX_CELLS 4096  // 1D problems: at most this many cells
 #define RT_NPART 48
 // ROM passes: one 256-cell block per partial-sum row, at most 64 rows; slab
 // instances up to RT_POST_FUSED_NC cells run the whole post in one workgroup
@@ -104,7 +105,7 @@ struct Inst {
   double *sip;      // [2][ng][nc] FP64 group moments (exchange double buffer)
   float *sip32;     // [2][ng][nc] FP32 group moments
   double *apx;      // [2][ng][RT_RMAX] DMD projection partials
-  unsigned long long *bar;  // grid barrier counters [3]
+  unsigned long long *bar;  // grid barrier counters: [0..3) SI kernel, [4..7) step tail
   double *rho;      // rho^n
   double *bt2[2];   // b~ double buffer: the next step reads bt2[steps & 1]
                     // and its f-pass writes the other one
@@ -313,3 +314,65 @@ __device__ __forceinline__ void wg_scan2(R Af, R Bf, R Ab, R Bb, R gF, R gB, R &
   inF = rt_fma(eAf, vF, eBf);
   inB = rt_fma(eAb, vB, eBb);
 }
+
+// ---------------------------------------------------------------------------
+// Cooperative execution: exchange through agent-scope relaxed atomics (no
+// cache maintenance needed) and a grid barrier on monotone counters.
+// bar[0] counts arrivals, bar[1] is the last released generation and bar[2]
+// the generations completed by earlier launches, so nothing is reset between
+// launches; each kernel (one grid size) has its own three counters.  Every workgroup passes the same barriers (identical control
+// flow).  A wait is bounded: one that gives up sets the state's fault flag
+// and falls through (the host reports the step as failed) instead of hanging.
+// ---------------------------------------------------------------------------
+struct CoopSync {
+  unsigned long long *bar;
+  unsigned long long gen;
+  int *fault;
+  int buf;  // double buffer of the next exchange
+};
+
+__device__ __forceinline__ double xload(const double *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float xload(const float *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void xstore(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void xstore(float *p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int xload(const int *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void xstore(int *p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void grid_sync(CoopSync &S) {
+  ++S.gen;
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's exchange stores are complete
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long nb = gridDim.x;
+    const unsigned long long prev =
+        __hip_atomic_fetch_add(&S.bar[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev + 1 == S.gen * nb) {
+      __hip_atomic_store(&S.bar[1], S.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      // after a fault the counters are out of step: no further waiting
+      unsigned spins = 0;
+      while (__hip_atomic_load(&S.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < S.gen &&
+             !__hip_atomic_load(S.fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins == (1u << 26)) {
+          __hip_atomic_store(S.fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+

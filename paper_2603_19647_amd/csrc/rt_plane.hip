@@ -636,7 +636,7 @@ __global__ void __launch_bounds__(256) k_romapply_solve(RomDev R, const int *ran
                                                         double *coef) {
   const int rank = *rankp;
   __shared__ double vec[RT_RMAX], scratch[256];
-  sum_partials(part, nblk, rank, vec, scratch);
+  sum_partials<false>(part, nblk, rank, vec, scratch);
   lu_solve_wave(R.LU, R.perm, rank, vec);  // ends with a barrier
   if ((int)threadIdx.x < RT_RMAX) coef[threadIdx.x] = (int)threadIdx.x < rank ? vec[threadIdx.x] : 0.0;
 }

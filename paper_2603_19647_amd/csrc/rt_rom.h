@@ -25,6 +25,7 @@ struct RomSmem {
   double vec[48];            // reduction results
   double av[RT_RMAX], a2v[RT_RMAX], utbv[RT_RMAX], pwv[RT_RMAX];  // projection coefficients
   double red[RT_MAXWAVES * 48];
+  double scratch[1024];      // sum_partials: one entry per thread
   int perm[RT_KC];
   arrow::Problem ap;         // secular core SVD: non-deflated poles
   double ap_tau[RT_KC], ap_zh[RT_KC];
@@ -194,13 +195,25 @@ __device__ inline int lu_factor_wave(double *A, int *perm_lds, int n, double *LU
 // scratch of blockDim.x doubles in LDS; every thread must call; ends with a
 // barrier.
 constexpr int RT_SUMJ = 8;
+// partial rows: plain or (COH) agent-scope atomic accesses
+template <bool COH>
+__device__ __forceinline__ void part_store(double *p, double v) {
+  if constexpr (COH) xstore(p, v);
+  else *p = v;
+}
+template <bool COH>
+__device__ __forceinline__ double part_load(const double *p) {
+  if constexpr (COH) return xload(p);
+  else return *p;
+}
+template <bool COH>
 __device__ inline void sum_partials(const double *part, int nb, int ncol, double *out, double *scratch) {
   const int tid = threadIdx.x, per = blockDim.x / RT_SUMJ;
   for (int k0 = 0; k0 < ncol; k0 += per) {
     const int k = k0 + tid % per, j = tid / per;
     double s = 0.0;
     if (k < ncol)
-      for (int b = j; b < nb; b += RT_SUMJ) s += part[b * RT_NPART + k];
+      for (int b = j; b < nb; b += RT_SUMJ) s += part_load<COH>(&part[b * RT_NPART + k]);
     scratch[tid] = s;
     __syncthreads();
     if (tid < per && k0 + tid < ncol) {
@@ -549,6 +562,7 @@ __device__ inline bool core_svd_secular(RomSmem &sm, const double *S, const doub
 // k_rom_update.  Returns 1 for a rank-deficient snapshot (x in span U), 0
 // otherwise, -1 if x = 0 at rank 0 (nothing added).  rank / luok updated.
 // ---------------------------------------------------------------------------
+template <bool COH>
 __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, int &rank, int &luok,
                                 RomSmem &sm) {
   const int tid = threadIdx.x, NT = blockDim.x;
@@ -556,9 +570,9 @@ __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, in
   RomPend *P = R.pend;
   // fixed-order block sums: pass 1 -> U^T x, U^T b, x.x, x.b; pass 2 -> a2, p1^T W;
   // pass 3 -> p.p, p.b
-  sum_partials(Wk.part1, nb, 2 * RT_RMAX + 2, sm.red, sm.red + 512);
-  sum_partials(Wk.part2, nb, 2 * RT_RMAX, sm.red + 2 * RT_RMAX + 2, sm.red + 512);
-  sum_partials(Wk.part3, nb, 2, sm.red + 4 * RT_RMAX + 2, sm.red + 512);
+  sum_partials<COH>(Wk.part1, nb, 2 * RT_RMAX + 2, sm.red, sm.scratch);
+  sum_partials<COH>(Wk.part2, nb, 2 * RT_RMAX, sm.red + 2 * RT_RMAX + 2, sm.scratch);
+  sum_partials<COH>(Wk.part3, nb, 2, sm.red + 4 * RT_RMAX + 2, sm.scratch);
   const double xn = sqrt(sm.red[2 * RT_RMAX]);
   const double xb = sm.red[2 * RT_RMAX + 1];
   const double nu = sqrt(sm.red[4 * RT_RMAX + 2]);
@@ -832,3 +846,168 @@ __device__ inline double rom_tail_ratio(const RomDev &R, int rank) {
   for (int i = 0; i < rank; ++i) tot += R.S[i];
   return tot > 0.0 ? R.S[rank - 1] / tot : 0.0;
 }
+
+__device__ __forceinline__ const RomDev &rom_of(const Inst &I, int z) { return z ? I.pc : I.ig; }
+
+// ---------------------------------------------------------------------------
+// Projection passes (classical Gram-Schmidt applied twice).  Block b of nb
+// takes cells b*blockDim + t, strided by nb*blockDim, and writes its partial
+// sums to row b; later stages add the rows in block order.  The same bodies
+// serve the grid kernels (grid (blocks, instance, ROM)) and the one-block
+// fused post of small instances (nb = 1).  COH: the partial rows are written
+// and read with agent-scope atomics (workgroups of one cooperative launch on
+// different XCDs exchange them).
+// ---------------------------------------------------------------------------
+template <bool COH>
+__device__ __forceinline__ void rom_pass1(const Inst &I, const RomDev &R, const RomWork &W, int z, int b,
+                                          int nb, double *red, double *out) {
+  const int r = W.r, ld = I.ld, NT = blockDim.x;
+  double part[2 * RT_RMAX + 2];
+#pragma unroll
+  for (int k = 0; k < 2 * RT_RMAX + 2; ++k) part[k] = 0.0;
+  for (int c = b * NT + threadIdx.x; c < I.nc; c += nb * NT) {
+    double xv, bv;
+    if (z == 1) {  // x = rho^n - rho^(1/2), b = rho^(1/2) - rho^(0)
+      const double rh = I.rhalf[c];
+      xv = I.rho[c] - rh;
+      bv = rh - I.rho0[c];
+      const_cast<double *>(W.x)[c] = xv;  // the PC ROM's x, b live in the work arrays
+      const_cast<double *>(W.b)[c] = bv;
+    } else {
+      xv = W.x[c];
+      bv = W.b[c];
+    }
+    part[2 * RT_RMAX] = rt_fma(xv, xv, part[2 * RT_RMAX]);
+    part[2 * RT_RMAX + 1] = rt_fma(xv, bv, part[2 * RT_RMAX + 1]);
+    // all basis loads unconditional (finite columns past the rank, masked),
+    // so they are in flight together; the sums past the rank stay zero
+    double u[RT_RMAX];
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k) {
+      const double v = R.U[(size_t)k * ld + c];
+      u[k] = k < r ? v : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k) {
+      part[k] = rt_fma(u[k], xv, part[k]);
+      part[RT_RMAX + k] = rt_fma(u[k], bv, part[RT_RMAX + k]);
+    }
+  }
+  wg_sum_fast<2 * RT_RMAX + 2>(part, red, out);
+  if (threadIdx.x < 2 * RT_RMAX + 2) part_store<COH>(&W.part1[b * RT_NPART + threadIdx.x], out[threadIdx.x]);
+}
+
+template <bool COH>
+__device__ __forceinline__ void rom_pass2(const Inst &I, const RomDev &R, const RomWork &W, int b, int nb,
+                                          double *red, double *out, double *av, double *scratch) {
+  const int r = W.r, ld = I.ld, NT = blockDim.x;
+  // every column: pass 1 left zero sums past the rank, so av is zero there
+  sum_partials<COH>(W.part1, nb, RT_RMAX, av, scratch);
+  double part[2 * RT_RMAX];
+#pragma unroll
+  for (int k = 0; k < 2 * RT_RMAX; ++k) part[k] = 0.0;
+  for (int c = b * NT + threadIdx.x; c < I.nc; c += nb * NT) {
+    // all loads issued up front and unconditionally (masked past the rank);
+    // the arithmetic keeps its order
+    double u[RT_RMAX], wv[RT_RMAX];
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k) {
+      const double x = R.U[(size_t)k * ld + c], y = R.W[(size_t)k * ld + c];
+      u[k] = k < r ? x : 0.0;
+      wv[k] = k < r ? y : 0.0;
+    }
+    double v = W.x[c];
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k) v = rt_fma(-u[k], av[k], v);
+    W.p[c] = v;
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k) {
+      part[k] = rt_fma(u[k], v, part[k]);
+      part[RT_RMAX + k] = rt_fma(wv[k], v, part[RT_RMAX + k]);
+    }
+  }
+  wg_sum_fast<2 * RT_RMAX>(part, red, out);
+  if (threadIdx.x < 2 * RT_RMAX) part_store<COH>(&W.part2[b * RT_NPART + threadIdx.x], out[threadIdx.x]);
+}
+
+template <bool COH>
+__device__ __forceinline__ void rom_pass3(const Inst &I, const RomDev &R, const RomWork &W, int b, int nb,
+                                          double *red, double *out, double *a2, double *scratch) {
+  const int r = W.r, ld = I.ld, NT = blockDim.x;
+  sum_partials<COH>(W.part2, nb, RT_RMAX, a2, scratch);  // zero past the rank
+  double part[2] = {0.0, 0.0};
+  for (int c = b * NT + threadIdx.x; c < I.nc; c += nb * NT) {
+    double u[RT_RMAX];
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k) {
+      const double x = R.U[(size_t)k * ld + c];
+      u[k] = k < r ? x : 0.0;
+    }
+    double v = W.p[c];
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k) v = rt_fma(-u[k], a2[k], v);
+    W.p[c] = v;
+    part[0] = rt_fma(v, v, part[0]);
+    part[1] = rt_fma(v, W.b[c], part[1]);
+  }
+  wg_sum_fast<2>(part, red, out);
+  if (threadIdx.x < 2) part_store<COH>(&W.part3[b * RT_NPART + threadIdx.x], out[threadIdx.x]);
+}
+
+// ---------------------------------------------------------------------------
+// Small dense part of the update (isvd_core) and Alg. 2's phase flags for
+// ROM z of one instance; every thread of the workgroup calls it.  Block z
+// writes only ROM z's state fields, so the two ROMs' workgroups may run at
+// once.
+// ---------------------------------------------------------------------------
+template <bool COH>
+__device__ __forceinline__ void rom_core(const Inst &I, const RomDev &R, const RomWork &W, int z, RomSmem &sm) {
+  RtState *st = I.st;
+  int rank = z ? st->rank_pc : st->rank_ig;
+  int luok = z ? st->lu_ok_pc : st->lu_ok_ig;
+  const int dfc = isvd_core<COH>(R, W, I.r_max, rank, luok, sm);
+  if (threadIdx.x == 0) {
+    const long long step_no = W.step_no;
+    int updated = 0;
+    if (!W.truncate) {
+      // construction phase: stop tests eq. ig_stop / eq. pc_stop, the rank
+      // cap, or a rank-deficient snapshot end it
+      if (dfc >= 0) {
+        updated = 1;
+        if (rom_tail_ratio(R, rank) <= W.eps || rank >= I.r_max || dfc == 1) {
+          if (z == 0) {
+            st->flag_ig = 1;
+            st->n0 = (int)step_no;
+          } else {
+            // PC snapshots start only after the IG construction ended in an
+            // earlier step, so n0 is settled here
+            st->flag_pc = 1;
+            st->n1 = (int)step_no - st->n0;
+          }
+        }
+      }
+    } else {
+      updated = 1;
+    }
+    if (z == 0) {
+      st->rank_ig = rank;
+      st->lu_ok_ig = luok;
+      st->ig_updates += updated;
+    } else {
+      st->rank_pc = rank;
+      st->lu_ok_pc = luok;
+      st->pc_updates += updated;
+    }
+    if (I.hist && step_no <= I.hist_cap) {
+      RtStepRec &rec = I.hist[step_no - 1];
+      if (z == 0) {
+        rec.ig_update = updated;
+        rec.rank_ig = rank;
+      } else {
+        rec.pc_update = updated;
+        rec.rank_pc = rank;
+      }
+    }
+  }
+}
+

@@ -12,7 +12,6 @@ constexpr int BLK = 256;  // threads per block of the grid passes
 // passes are short and latency-bound, so an instance's cells are spread wide.
 __device__ __host__ __forceinline__ int pass_blocks(int nc) { return rt_pass_blocks(nc); }
 
-__device__ __forceinline__ const RomDev &rom_of(const Inst &I, int z) { return z ? I.pc : I.ig; }
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -42,108 +41,8 @@ __global__ void __launch_bounds__(256) k_rom_decide(const Inst *__restrict__ ins
   const Inst &I = insts[blockIdx.x];
   __shared__ double scratch[256], vec[4];
   const int nb = pass_blocks(I.nc);
-  if (I.method == RT_ROM && I.st->flag_ig) sum_partials(I.ig.work->part3, nb, 3, vec, scratch);
+  if (I.method == RT_ROM && I.st->flag_ig) sum_partials<false>(I.ig.work->part3, nb, 3, vec, scratch);
   rom_decide(I, vec, I.post_nb);
-}
-
-// ---------------------------------------------------------------------------
-// Projection passes (classical Gram-Schmidt applied twice).  Block b of nb
-// takes cells b*blockDim + t, strided by nb*blockDim, and writes its partial
-// sums to row b; later stages add the rows in block order.  The same bodies
-// serve the grid kernels (grid (blocks, instance, ROM)) and the one-block
-// fused post of small instances (nb = 1).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void rom_pass1(const Inst &I, const RomDev &R, const RomWork &W, int z, int b,
-                                          int nb, double *red, double *out) {
-  const int r = W.r, ld = I.ld, NT = blockDim.x;
-  double part[2 * RT_RMAX + 2];
-#pragma unroll
-  for (int k = 0; k < 2 * RT_RMAX + 2; ++k) part[k] = 0.0;
-  for (int c = b * NT + threadIdx.x; c < I.nc; c += nb * NT) {
-    double xv, bv;
-    if (z == 1) {  // x = rho^n - rho^(1/2), b = rho^(1/2) - rho^(0)
-      const double rh = I.rhalf[c];
-      xv = I.rho[c] - rh;
-      bv = rh - I.rho0[c];
-      const_cast<double *>(W.x)[c] = xv;  // the PC ROM's x, b live in the work arrays
-      const_cast<double *>(W.b)[c] = bv;
-    } else {
-      xv = W.x[c];
-      bv = W.b[c];
-    }
-    part[2 * RT_RMAX] = rt_fma(xv, xv, part[2 * RT_RMAX]);
-    part[2 * RT_RMAX + 1] = rt_fma(xv, bv, part[2 * RT_RMAX + 1]);
-    // all basis loads unconditional (finite columns past the rank, masked),
-    // so they are in flight together; the sums past the rank stay zero
-    double u[RT_RMAX];
-#pragma unroll
-    for (int k = 0; k < RT_RMAX; ++k) {
-      const double v = R.U[(size_t)k * ld + c];
-      u[k] = k < r ? v : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < RT_RMAX; ++k) {
-      part[k] = rt_fma(u[k], xv, part[k]);
-      part[RT_RMAX + k] = rt_fma(u[k], bv, part[RT_RMAX + k]);
-    }
-  }
-  wg_sum_fast<2 * RT_RMAX + 2>(part, red, out);
-  if (threadIdx.x < 2 * RT_RMAX + 2) W.part1[b * RT_NPART + threadIdx.x] = out[threadIdx.x];
-}
-
-__device__ __forceinline__ void rom_pass2(const Inst &I, const RomDev &R, const RomWork &W, int b, int nb,
-                                          double *red, double *out, double *av, double *scratch) {
-  const int r = W.r, ld = I.ld, NT = blockDim.x;
-  // every column: pass 1 left zero sums past the rank, so av is zero there
-  sum_partials(W.part1, nb, RT_RMAX, av, scratch);
-  double part[2 * RT_RMAX];
-#pragma unroll
-  for (int k = 0; k < 2 * RT_RMAX; ++k) part[k] = 0.0;
-  for (int c = b * NT + threadIdx.x; c < I.nc; c += nb * NT) {
-    // all loads issued up front and unconditionally (masked past the rank);
-    // the arithmetic keeps its order
-    double u[RT_RMAX], wv[RT_RMAX];
-#pragma unroll
-    for (int k = 0; k < RT_RMAX; ++k) {
-      const double x = R.U[(size_t)k * ld + c], y = R.W[(size_t)k * ld + c];
-      u[k] = k < r ? x : 0.0;
-      wv[k] = k < r ? y : 0.0;
-    }
-    double v = W.x[c];
-#pragma unroll
-    for (int k = 0; k < RT_RMAX; ++k) v = rt_fma(-u[k], av[k], v);
-    W.p[c] = v;
-#pragma unroll
-    for (int k = 0; k < RT_RMAX; ++k) {
-      part[k] = rt_fma(u[k], v, part[k]);
-      part[RT_RMAX + k] = rt_fma(wv[k], v, part[RT_RMAX + k]);
-    }
-  }
-  wg_sum_fast<2 * RT_RMAX>(part, red, out);
-  if (threadIdx.x < 2 * RT_RMAX) W.part2[b * RT_NPART + threadIdx.x] = out[threadIdx.x];
-}
-
-__device__ __forceinline__ void rom_pass3(const Inst &I, const RomDev &R, const RomWork &W, int b, int nb,
-                                          double *red, double *out, double *a2, double *scratch) {
-  const int r = W.r, ld = I.ld, NT = blockDim.x;
-  sum_partials(W.part2, nb, RT_RMAX, a2, scratch);  // zero past the rank
-  double part[2] = {0.0, 0.0};
-  for (int c = b * NT + threadIdx.x; c < I.nc; c += nb * NT) {
-    double u[RT_RMAX];
-#pragma unroll
-    for (int k = 0; k < RT_RMAX; ++k) {
-      const double x = R.U[(size_t)k * ld + c];
-      u[k] = k < r ? x : 0.0;
-    }
-    double v = W.p[c];
-#pragma unroll
-    for (int k = 0; k < RT_RMAX; ++k) v = rt_fma(-u[k], a2[k], v);
-    W.p[c] = v;
-    part[0] = rt_fma(v, v, part[0]);
-    part[1] = rt_fma(v, W.b[c], part[1]);
-  }
-  wg_sum_fast<2>(part, red, out);
-  if (threadIdx.x < 2) W.part3[b * RT_NPART + threadIdx.x] = out[threadIdx.x];
 }
 
 __global__ void __launch_bounds__(BLK) k_rom_pass1(const Inst *__restrict__ insts) {
@@ -153,7 +52,7 @@ __global__ void __launch_bounds__(BLK) k_rom_pass1(const Inst *__restrict__ inst
   const RomWork &W = *R.work;
   if (!W.active || (int)blockIdx.x >= W.nblk) return;
   __shared__ double red[(BLK / 64) * (2 * RT_RMAX + 2)], out[2 * RT_RMAX + 2];
-  rom_pass1(I, R, W, blockIdx.z, blockIdx.x, W.nblk, red, out);
+  rom_pass1<false>(I, R, W, blockIdx.z, blockIdx.x, W.nblk, red, out);
 }
 
 __global__ void __launch_bounds__(BLK) k_rom_pass2(const Inst *__restrict__ insts) {
@@ -163,7 +62,7 @@ __global__ void __launch_bounds__(BLK) k_rom_pass2(const Inst *__restrict__ inst
   const RomWork &W = *R.work;
   if (!W.active || (int)blockIdx.x >= W.nblk) return;
   __shared__ double red[(BLK / 64) * 2 * RT_RMAX], out[2 * RT_RMAX], av[RT_RMAX], scratch[BLK];
-  rom_pass2(I, R, W, blockIdx.x, W.nblk, red, out, av, scratch);
+  rom_pass2<false>(I, R, W, blockIdx.x, W.nblk, red, out, av, scratch);
 }
 
 __global__ void __launch_bounds__(BLK) k_rom_pass3(const Inst *__restrict__ insts) {
@@ -173,63 +72,7 @@ __global__ void __launch_bounds__(BLK) k_rom_pass3(const Inst *__restrict__ inst
   const RomWork &W = *R.work;
   if (!W.active || (int)blockIdx.x >= W.nblk) return;
   __shared__ double red[(BLK / 64) * 2], out[2], a2[RT_RMAX], scratch[BLK];
-  rom_pass3(I, R, W, blockIdx.x, W.nblk, red, out, a2, scratch);
-}
-
-// ---------------------------------------------------------------------------
-// Small dense part of the update (isvd_core) and Alg. 2's phase flags for
-// ROM z of one instance; every thread of the workgroup calls it.  Block z
-// writes only ROM z's state fields, so the two ROMs' workgroups may run at
-// once.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void rom_core(const Inst &I, const RomDev &R, const RomWork &W, int z, RomSmem &sm) {
-  RtState *st = I.st;
-  int rank = z ? st->rank_pc : st->rank_ig;
-  int luok = z ? st->lu_ok_pc : st->lu_ok_ig;
-  const int dfc = isvd_core(R, W, I.r_max, rank, luok, sm);
-  if (threadIdx.x == 0) {
-    const long long step_no = W.step_no;
-    int updated = 0;
-    if (!W.truncate) {
-      // construction phase: stop tests eq. ig_stop / eq. pc_stop, the rank
-      // cap, or a rank-deficient snapshot end it
-      if (dfc >= 0) {
-        updated = 1;
-        if (rom_tail_ratio(R, rank) <= W.eps || rank >= I.r_max || dfc == 1) {
-          if (z == 0) {
-            st->flag_ig = 1;
-            st->n0 = (int)step_no;
-          } else {
-            // PC snapshots start only after the IG construction ended in an
-            // earlier step, so n0 is settled here
-            st->flag_pc = 1;
-            st->n1 = (int)step_no - st->n0;
-          }
-        }
-      }
-    } else {
-      updated = 1;
-    }
-    if (z == 0) {
-      st->rank_ig = rank;
-      st->lu_ok_ig = luok;
-      st->ig_updates += updated;
-    } else {
-      st->rank_pc = rank;
-      st->lu_ok_pc = luok;
-      st->pc_updates += updated;
-    }
-    if (I.hist && step_no <= I.hist_cap) {
-      RtStepRec &rec = I.hist[step_no - 1];
-      if (z == 0) {
-        rec.ig_update = updated;
-        rec.rank_ig = rank;
-      } else {
-        rec.pc_update = updated;
-        rec.rank_pc = rank;
-      }
-    }
-  }
+  rom_pass3<false>(I, R, W, blockIdx.x, W.nblk, red, out, a2, scratch);
 }
 
 // k_rom_core: rom_core after the grid passes, grid (instance, ROM).
@@ -241,7 +84,7 @@ __global__ void __launch_bounds__(256) k_rom_core(const Inst *__restrict__ insts
   const RomWork &W = *R.work;
   if (!W.active) return;
   __shared__ RomSmem sm;
-  rom_core(I, R, W, z, sm);
+  rom_core<false>(I, R, W, z, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -261,13 +104,13 @@ __global__ void __launch_bounds__(256) k_rom_post_small(const Inst *__restrict__
   __shared__ double red[(256 / 64) * (2 * RT_RMAX + 2)], out[2 * RT_RMAX + 2], av[RT_RMAX], scratch[256];
   __shared__ RomSmem sm;
   // each stage reads the partial row the previous one wrote to global memory
-  rom_pass1(I, R, W, z, 0, 1, red, out);
+  rom_pass1<false>(I, R, W, z, 0, 1, red, out);
   __syncthreads();
-  rom_pass2(I, R, W, 0, 1, red, out, av, scratch);
+  rom_pass2<false>(I, R, W, 0, 1, red, out, av, scratch);
   __syncthreads();
-  rom_pass3(I, R, W, 0, 1, red, out, av, scratch);
+  rom_pass3<false>(I, R, W, 0, 1, red, out, av, scratch);
   __syncthreads();
-  rom_core(I, R, W, z, sm);
+  rom_core<false>(I, R, W, z, sm);
 }
 
 // ---------------------------------------------------------------------------

@@ -23,60 +23,9 @@
 
 namespace {
 
-// ---------------------------------------------------------------------------
-// Cooperative execution: exchange through agent-scope relaxed atomics (no
-// cache maintenance needed) and a grid barrier on monotone counters.
-// bar[0] counts arrivals, bar[1] is the last released generation and bar[2]
-// the generations completed by earlier launches, so nothing is reset between
-// launches.  Every workgroup passes the same barriers (identical control
-// flow).  A wait is bounded: one that gives up sets the state's fault flag
-// and falls through (the host reports the step as failed) instead of hanging.
-// ---------------------------------------------------------------------------
-struct CoopSync {
-  unsigned long long *bar;
-  unsigned long long gen;
-  int *fault;
-  int buf;  // double buffer of the next exchange
-};
-
-__device__ __forceinline__ double xload(const double *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ float xload(const float *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void xstore(double *p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void xstore(float *p, float v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void grid_sync(CoopSync &S) {
-  ++S.gen;
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's exchange stores are complete
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned long long nb = gridDim.x;
-    const unsigned long long prev =
-        __hip_atomic_fetch_add(&S.bar[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (prev + 1 == S.gen * nb) {
-      __hip_atomic_store(&S.bar[1], S.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      // after a fault the counters are out of step: no further waiting
-      unsigned spins = 0;
-      while (__hip_atomic_load(&S.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < S.gen &&
-             !__hip_atomic_load(S.fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins == (1u << 26)) {
-          __hip_atomic_store(S.fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
-      }
-    }
-  }
-  __syncthreads();
-}
+// Threads per workgroup of the cooperative step tail (k_tail_coop); its ROM
+// passes use one partial row per TAIL_NT cells.
+constexpr int TAIL_NT = 512;
 
 template <typename R>
 __device__ __forceinline__ R *coop_part(const Inst &I);
@@ -211,8 +160,17 @@ __device__ inline void rom_apply_coop(const Inst &I, const RomDev &R, int rank, 
   grid_sync(cs);
   if ((int)threadIdx.x < RT_RMAX) {
     double sv = 0.0;
-    if ((int)threadIdx.x < rank)
-      for (int g = 0; g < ng; ++g) sv += xload(&apx[(size_t)g * RT_RMAX + threadIdx.x]);
+    if ((int)threadIdx.x < rank) {
+      // groups in order, eight loads in flight per batch (clamped, masked)
+      for (int g0 = 0; g0 < ng; g0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = xload(&apx[(size_t)min(g0 + q, ng - 1) * RT_RMAX + threadIdx.x]);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (g0 + q < ng) sv += v[q];
+      }
+    }
     vec[threadIdx.x] = sv;  // zero past the rank
   }
   __syncthreads();
@@ -479,7 +437,8 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
       }
     wg_sum_fast<3>(part, rred, rvec);
   }
-  rom_decide(I, rvec, I.post_nb);
+  // the cooperative tail's passes use one partial row per TAIL_NT cells
+  rom_decide(I, rvec, COOP ? (nc + TAIL_NT - 1) / TAIL_NT : I.post_nb);
 }
 
 // ---------------------------------------------------------------------------
@@ -492,84 +451,32 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
 // rhs_only: skip the first sweep and rebuild b~ from the stored f (creation,
 // or a new inflow).
 // ---------------------------------------------------------------------------
-template <int CMAX, int MAXT>
-__global__ void __launch_bounds__(MAXT) k_fpass_pair(const Inst *__restrict__ insts, int rhs_only, int gp) {
-  const Inst &I = insts[blockIdx.y];
-  const int p0 = blockIdx.x * gp;
-  const int p1 = min(I.npair, p0 + gp);
-  if (p0 >= p1) return;
-  __shared__ double slots[8 * RT_MAXWAVES];
-  const int NT = I.nthr, tid = threadIdx.x;
+// One ordinate pair of the f-pass for the calling workgroup's cells: ct, G
+// and srcc = sigma_s rho^n + G are the thread's cells; the pair's moment goes
+// to fpart[p] (COH: agent-scope stores, for a cooperative launch).
+template <int CMAX, bool COH>
+__device__ __forceinline__ void fpass_one_pair(const Inst &I, int p, int c0, int n, const double (&ct)[CMAX],
+                                               const double (&G)[CMAX], const double (&srcc)[CMAX], int rhs_only,
+                                               double *slots, int &parity) {
   const int nc = I.nc;
-  const int C = (nc + NT - 1) / NT;
-  const int c0 = tid * C;
-  const int n = max(0, min(C, nc - c0));
   const double idt = I.inv_dt;
-  double ct[CMAX], G[CMAX], srcc[CMAX];
+  const double m = I.pm[p], w = I.pw[p];
+  double *fneg = I.f + (size_t)p * nc + c0;               // mu < 0
+  double *fpos = I.f + (size_t)(I.nv - 1 - p) * nc + c0;  // mu > 0
+  double inv[CMAX], bp[CMAX], bn[CMAX];
 #pragma unroll
   for (int t = 0; t < CMAX; ++t) {
     const bool in = t < n;
-    ct[t] = in ? I.ct[c0 + t] : 1.0;
-    G[t] = in ? I.G[c0 + t] : 0.0;
-    srcc[t] = (in && !rhs_only) ? rt_fma(I.ss[c0 + t], I.rho[c0 + t], G[t]) : 0.0;
+    inv[t] = rt_rcp(ct[t] + m);
+    bp[t] = in ? fpos[t] : 0.0;
+    bn[t] = in ? fneg[t] : 0.0;
   }
-  int parity = 0;
-  for (int p = p0; p < p1; ++p) {
-    const double m = I.pm[p], w = I.pw[p];
-    double *fneg = I.f + (size_t)p * nc + c0;               // mu < 0
-    double *fpos = I.f + (size_t)(I.nv - 1 - p) * nc + c0;  // mu > 0
-    double inv[CMAX], bp[CMAX], bn[CMAX];
-#pragma unroll
-    for (int t = 0; t < CMAX; ++t) {
-      const bool in = t < n;
-      inv[t] = rt_rcp(ct[t] + m);
-      bp[t] = in ? fpos[t] : 0.0;
-      bn[t] = in ? fneg[t] : 0.0;
-    }
-    if (!rhs_only) {
-      double Af = 1.0, Bf = 0.0, Ab = 1.0, Bb = 0.0;
-#pragma unroll
-      for (int t = 0; t < CMAX; ++t)
-        if (t < n) {
-          bp[t] = rt_fma(bp[t], idt, srcc[t]) * inv[t];
-          const double a = m * inv[t];
-          Bf = rt_fma(a, Bf, bp[t]);
-          Af *= a;
-        }
-#pragma unroll
-      for (int t = CMAX - 1; t >= 0; --t)
-        if (t < n) {
-          bn[t] = rt_fma(bn[t], idt, srcc[t]) * inv[t];
-          const double a = m * inv[t];
-          Bb = rt_fma(a, Bb, bn[t]);
-          Ab *= a;
-        }
-      double inF, inB;
-      wg_scan2<double>(Af, Bf, Ab, Bb, I.g[0], I.g[1], inF, inB, slots, parity);
-      parity ^= 1;
-      double f = inF;
-#pragma unroll
-      for (int t = 0; t < CMAX; ++t)
-        if (t < n) {
-          f = rt_fma(m * inv[t], f, bp[t]);
-          bp[t] = f;
-          fpos[t] = f;
-        }
-      f = inB;
-#pragma unroll
-      for (int t = CMAX - 1; t >= 0; --t)
-        if (t < n) {
-          f = rt_fma(m * inv[t], f, bn[t]);
-          bn[t] = f;
-          fneg[t] = f;
-        }
-    }
-    // right-hand-side sweep with source f^n_j / dt + G and inflow g
+  if (!rhs_only) {
     double Af = 1.0, Bf = 0.0, Ab = 1.0, Bb = 0.0;
 #pragma unroll
     for (int t = 0; t < CMAX; ++t)
       if (t < n) {
-        bp[t] = rt_fma(bp[t], idt, G[t]) * inv[t];
+        bp[t] = rt_fma(bp[t], idt, srcc[t]) * inv[t];
         const double a = m * inv[t];
         Bf = rt_fma(a, Bf, bp[t]);
         Af *= a;
@@ -577,7 +484,7 @@ __global__ void __launch_bounds__(MAXT) k_fpass_pair(const Inst *__restrict__ in
 #pragma unroll
     for (int t = CMAX - 1; t >= 0; --t)
       if (t < n) {
-        bn[t] = rt_fma(bn[t], idt, G[t]) * inv[t];
+        bn[t] = rt_fma(bn[t], idt, srcc[t]) * inv[t];
         const double a = m * inv[t];
         Bb = rt_fma(a, Bb, bn[t]);
         Ab *= a;
@@ -585,26 +492,229 @@ __global__ void __launch_bounds__(MAXT) k_fpass_pair(const Inst *__restrict__ in
     double inF, inB;
     wg_scan2<double>(Af, Bf, Ab, Bb, I.g[0], I.g[1], inF, inB, slots, parity);
     parity ^= 1;
-    double fw[CMAX];
     double f = inF;
 #pragma unroll
     for (int t = 0; t < CMAX; ++t)
       if (t < n) {
         f = rt_fma(m * inv[t], f, bp[t]);
-        fw[t] = f;
+        bp[t] = f;
+        fpos[t] = f;
       }
     f = inB;
 #pragma unroll
     for (int t = CMAX - 1; t >= 0; --t)
       if (t < n) {
         f = rt_fma(m * inv[t], f, bn[t]);
-        fw[t] = w * (fw[t] + f);
+        bn[t] = f;
+        fneg[t] = f;
       }
-    double *part = I.fpart + (size_t)p * nc + c0;
-#pragma unroll
-    for (int t = 0; t < CMAX; ++t)
-      if (t < n) part[t] = fw[t];
   }
+  // right-hand-side sweep with source f^n_j / dt + G and inflow g
+  double Af = 1.0, Bf = 0.0, Ab = 1.0, Bb = 0.0;
+#pragma unroll
+  for (int t = 0; t < CMAX; ++t)
+    if (t < n) {
+      bp[t] = rt_fma(bp[t], idt, G[t]) * inv[t];
+      const double a = m * inv[t];
+      Bf = rt_fma(a, Bf, bp[t]);
+      Af *= a;
+    }
+#pragma unroll
+  for (int t = CMAX - 1; t >= 0; --t)
+    if (t < n) {
+      bn[t] = rt_fma(bn[t], idt, G[t]) * inv[t];
+      const double a = m * inv[t];
+      Bb = rt_fma(a, Bb, bn[t]);
+      Ab *= a;
+    }
+  double inF, inB;
+  wg_scan2<double>(Af, Bf, Ab, Bb, I.g[0], I.g[1], inF, inB, slots, parity);
+  parity ^= 1;
+  double fw[CMAX];
+  double f = inF;
+#pragma unroll
+  for (int t = 0; t < CMAX; ++t)
+    if (t < n) {
+      f = rt_fma(m * inv[t], f, bp[t]);
+      fw[t] = f;
+    }
+  f = inB;
+#pragma unroll
+  for (int t = CMAX - 1; t >= 0; --t)
+    if (t < n) {
+      f = rt_fma(m * inv[t], f, bn[t]);
+      fw[t] = w * (fw[t] + f);
+    }
+  double *part = I.fpart + (size_t)p * nc + c0;
+#pragma unroll
+  for (int t = 0; t < CMAX; ++t)
+    if (t < n) {
+      if constexpr (COH) xstore(&part[t], fw[t]);
+      else part[t] = fw[t];
+    }
+}
+
+// The thread's cells (the instance's cells split over NT threads) and the
+// f-pass inputs ct, G, srcc = sigma_s rho^n + G.
+template <int CMAX>
+__device__ __forceinline__ void fpass_inputs(const Inst &I, int NT, int rhs_only, int &c0, int &n,
+                                             double (&ct)[CMAX], double (&G)[CMAX], double (&srcc)[CMAX]) {
+  const int nc = I.nc;
+  const int C = (nc + NT - 1) / NT;
+  c0 = threadIdx.x * C;
+  n = max(0, min(C, nc - c0));
+#pragma unroll
+  for (int t = 0; t < CMAX; ++t) {
+    const bool in = t < n;
+    ct[t] = in ? I.ct[c0 + t] : 1.0;
+    G[t] = in ? I.G[c0 + t] : 0.0;
+    srcc[t] = (in && !rhs_only) ? rt_fma(I.ss[c0 + t], I.rho[c0 + t], G[t]) : 0.0;
+  }
+}
+
+template <int CMAX, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_fpass_pair(const Inst *__restrict__ insts, int rhs_only, int gp) {
+  const Inst &I = insts[blockIdx.y];
+  const int p0 = blockIdx.x * gp;
+  const int p1 = min(I.npair, p0 + gp);
+  if (p0 >= p1) return;
+  __shared__ double slots[8 * RT_MAXWAVES];
+  int c0, n;
+  double ct[CMAX], G[CMAX], srcc[CMAX];
+  fpass_inputs<CMAX>(I, I.nthr, rhs_only, c0, n, ct, G, srcc);
+  int parity = 0;
+  for (int p = p0; p < p1; ++p) fpass_one_pair<CMAX, false>(I, p, c0, n, ct, G, srcc, rhs_only, slots, parity);
+}
+
+// ---------------------------------------------------------------------------
+// k_tail_coop: everything after the SI solve of a problem marched on its own,
+// in one cooperative launch of max(2 + min(npair, 32), nc / TAIL_NT rounded
+// up) workgroups of TAIL_NT threads (up to eight cells per thread for the
+// f-pass scans: no register spills):
+//   1. the ROM projection passes (both ROMs at once; workgroup g < nbp takes
+//      cells g*nthr + t, the partial rows are exchanged coherently);
+//   2. workgroups 0 and 1 run the IG and PC cores (App. B) while the others
+//      run the f-pass, ordinate pairs dealt round-robin;
+//   3. the basis rotation and the pair sum of b~, by cells.
+// The decisions were taken by the SI kernel (RomWork.nblk = nbp).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void publish_pend(RomPend *P) {
+  // the rotation is read by workgroups on other XCDs: store it again with
+  // agent-scope atomics (same values) once the core has written it
+  __syncthreads();
+  for (int e = threadIdx.x; e < RT_KC * RT_KC; e += blockDim.x) {
+    xstore(&P->Uc[e], P->Uc[e]);
+    xstore(&P->Vc[e], P->Vc[e]);
+  }
+  if (threadIdx.x == 0) {
+    xstore(&P->r_old, P->r_old);
+    xstore(&P->k, P->k);
+    xstore(&P->inv_nu, P->inv_nu);
+    xstore(&P->pending, P->pending);
+  }
+}
+
+template <int CMAX, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_tail_coop(const Inst *__restrict__ insts) {
+  static_assert(MAXT == TAIL_NT && CMAX * TAIL_NT >= RT_SLAB_MAX_CELLS, "tail layout");
+  const Inst &I = insts[0];
+  RtState *st = I.st;
+  if (xload(&st->fault)) return;
+  __shared__ double slots[8 * RT_MAXWAVES];
+  __shared__ double red[RT_MAXWAVES * (2 * RT_RMAX + 2)], out[2 * RT_RMAX + 2], av[RT_RMAX];
+  __shared__ double cc[RT_KC * RT_KC + 4];
+  __shared__ RomSmem sm;
+  // the tail's own barrier counters (the SI kernel's use another grid size)
+  unsigned long long *bar = I.bar + 4;
+  CoopSync cs{bar, __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), &st->fault, 0};
+  const int g = blockIdx.x, G = gridDim.x, NT = blockDim.x;
+  const int nc = I.nc;
+  const int nbp = (nc + NT - 1) / NT;
+  const int rom = I.method == RT_ROM;
+  const RomWork &Wi = *I.ig.work, &Wp = *I.pc.work;
+  const int act0 = rom && Wi.active, act1 = rom && Wp.active;
+  // 1. projection passes
+  if (act0 || act1) {
+    if (g < nbp) {
+      if (act0) rom_pass1<true>(I, I.ig, Wi, 0, g, nbp, red, out);
+      if (act1) rom_pass1<true>(I, I.pc, Wp, 1, g, nbp, red, out);
+    }
+    grid_sync(cs);
+    if (g < nbp) {
+      if (act0) rom_pass2<true>(I, I.ig, Wi, g, nbp, red, out, av, sm.scratch);
+      if (act1) rom_pass2<true>(I, I.pc, Wp, g, nbp, red, out, av, sm.scratch);
+    }
+    grid_sync(cs);
+    if (g < nbp) {
+      if (act0) rom_pass3<true>(I, I.ig, Wi, g, nbp, red, out, av, sm.scratch);
+      if (act1) rom_pass3<true>(I, I.pc, Wp, g, nbp, red, out, av, sm.scratch);
+    }
+    grid_sync(cs);
+  }
+  // 2. cores on workgroups 0 and 1, f-pass on the others
+  if (g < 2) {
+    if (g == 0 && act0) {
+      rom_core<true>(I, I.ig, Wi, 0, sm);
+      publish_pend(I.ig.pend);
+    }
+    if (g == 1 && act1) {
+      rom_core<true>(I, I.pc, Wp, 1, sm);
+      publish_pend(I.pc.pend);
+    }
+  } else {
+    int c0, n, parity = 0;
+    double ct[CMAX], Gs[CMAX], srcc[CMAX];
+    fpass_inputs<CMAX>(I, NT, 0, c0, n, ct, Gs, srcc);
+    for (int p = g - 2; p < I.npair; p += G - 2)
+      fpass_one_pair<CMAX, true>(I, p, c0, n, ct, Gs, srcc, 0, slots, parity);
+  }
+  grid_sync(cs);
+  // 3. rotation (ROM z, matrix mat) and b~ by cells c = g*NT + t
+  const int c = g * NT + threadIdx.x;
+  if (rom) {
+    for (int zm = 0; zm < 4; ++zm) {
+      const int z = zm >> 1, mat = zm & 1;
+      const RomDev &R = z ? I.pc : I.ig;
+      RomPend *P = R.pend;
+      if (!xload(&P->pending)) continue;  // uniform
+      if (g >= nbp) continue;             // uniform: no cells here
+      const double *src = mat ? P->Vc : P->Uc;
+      __syncthreads();  // cc of the previous matrix fully used
+      for (int e = threadIdx.x; e < RT_KC * RT_KC; e += NT) cc[e] = xload(&src[e]);
+      __syncthreads();
+      const int r = xload(&P->r_old), k = xload(&P->k);
+      if (c < nc) {
+        const RomWork &W = z ? Wp : Wi;
+        double *X = mat ? R.W : R.U;
+        double old[1][RT_RMAX], e[1];
+        int cv[1] = {c};
+        bool ok[1] = {true};
+#pragma unroll
+        for (int q = 0; q < RT_RMAX; ++q) {
+          const double v = X[(size_t)q * I.ld + c];
+          old[0][q] = q < r ? v : 0.0;
+        }
+        e[0] = mat ? W.b[c] : W.p[c] * xload(&P->inv_nu);
+        rotate_block<1>(old, e, cc, r, k, X, I.ld, cv, ok);
+      }
+    }
+  }
+  if (c < nc) {
+    // pairs in order, eight loads in flight per batch (clamped, masked)
+    double acc = 0.0;
+    const double *part = I.fpart + c;
+    const int np = I.npair;
+    for (int p0 = 0; p0 < np; p0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = xload(&part[(size_t)min(p0 + q, np - 1) * nc]);
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (p0 + q < np) acc += v[q];
+    }
+    I.bt2[st->cur ^ 1][c] = acc;
+  }
+  if (g == 0 && threadIdx.x == 0) __hip_atomic_store(&bar[2], cs.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // b~ = sum over pairs of fpart[p], in pair order, into the b~ buffer the step
@@ -722,6 +832,19 @@ extern "C" hipError_t rt_launch_slab_fpass(const Inst *dinsts, int ninst, int nt
 extern "C" hipError_t rt_launch_slab_rhs(const Inst *dinsts, int ninst, int nthreads, int cmax, int npair_max,
                                          int nc_max, hipStream_t stream) {
   return launch_fpass(dinsts, ninst, nthreads, cmax, npair_max, nc_max, 1, npair_max * ninst, stream);
+}
+
+// The step's tail for a problem marched on its own (cooperative).
+extern "C" hipError_t rt_launch_slab_tail_coop(const Inst *dinst, int npair, int nc, int nthreads, int cmax,
+                                               hipStream_t stream) {
+  (void)nthreads;
+  (void)cmax;
+  void *args[] = {(void *)&dinst};
+  // two core workgroups + the f-pass ones, and at least one per TAIL_NT cells
+  // (the passes, the rotation and the b~ sum take one cell per thread)
+  const dim3 grid(std::max(2 + std::min(npair, 32), (nc + TAIL_NT - 1) / TAIL_NT));
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_tail_coop<8, TAIL_NT>), grid, dim3(TAIL_NT),
+                                    args, 0, stream);
 }
 
 extern "C" hipError_t rt_launch_slab_setup(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream) {
