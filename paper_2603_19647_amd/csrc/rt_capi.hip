@@ -475,6 +475,11 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   I.abs_up = (d->flags & RTROM_F_ABS_UP_NORM) ? 1 : 0;
   I.ld = (int)ld;
   I.nthr = d->dim == 1 ? slab_instance_threads(nc) : 256;
+  if (I.ng > 1) {  // the pair-group kernels need all their workgroups resident at once
+    int cmax;
+    const int nt = slab_launch_threads(&I.nthr, &nc, 1, &cmax);
+    if (!rt_slab_coop_fits(p->device, I.ng, nt, cmax, I.npair, nc)) I.ng = 0;
+  }
   I.hx = d->lx / d->nx;
   I.hy = d->dim == 2 ? d->ly / d->ny : 1.0;
   I.dt = d->dt;

@@ -32,6 +32,7 @@ struct rtrom_problem {
 
 // launch helpers implemented in the .hip kernel files
 extern "C" hipError_t rt_launch_slab_si_coop(const Inst *dinst, int ng, int nthreads, int cmax, hipStream_t stream);
+extern "C" int rt_slab_coop_fits(int device, int ng, int nthreads, int cmax, int npair, int nc);
 extern "C" hipError_t rt_launch_slab_tail_coop(const Inst *dinst, int npair, int nc, int nthreads, int cmax,
                                                hipStream_t stream);
 extern "C" hipError_t rt_launch_slab_si(const Inst *dinsts, int ninst, int nthreads, int cmax,

@@ -871,8 +871,10 @@ __device__ __forceinline__ void rom_pass1(const Inst &I, const RomDev &R, const 
       const double rh = I.rhalf[c];
       xv = I.rho[c] - rh;
       bv = rh - I.rho0[c];
-      const_cast<double *>(W.x)[c] = xv;  // the PC ROM's x, b live in the work arrays
-      const_cast<double *>(W.b)[c] = bv;
+      // the PC ROM's x, b live in the work arrays (COH: read later by
+      // workgroups on other XCDs)
+      part_store<COH>(const_cast<double *>(W.x) + c, xv);
+      part_store<COH>(const_cast<double *>(W.b) + c, bv);
     } else {
       xv = W.x[c];
       bv = W.b[c];
@@ -916,7 +918,7 @@ __device__ __forceinline__ void rom_pass2(const Inst &I, const RomDev &R, const 
       u[k] = k < r ? x : 0.0;
       wv[k] = k < r ? y : 0.0;
     }
-    double v = W.x[c];
+    double v = part_load<COH>(W.x + c);
 #pragma unroll
     for (int k = 0; k < RT_RMAX; ++k) v = rt_fma(-u[k], av[k], v);
     W.p[c] = v;
@@ -948,7 +950,7 @@ __device__ __forceinline__ void rom_pass3(const Inst &I, const RomDev &R, const 
     for (int k = 0; k < RT_RMAX; ++k) v = rt_fma(-u[k], a2[k], v);
     W.p[c] = v;
     part[0] = rt_fma(v, v, part[0]);
-    part[1] = rt_fma(v, W.b[c], part[1]);
+    part[1] = rt_fma(v, part_load<COH>(W.b + c), part[1]);
   }
   wg_sum_fast<2>(part, red, out);
   if (threadIdx.x < 2) part_store<COH>(&W.part3[b * RT_NPART + threadIdx.x], out[threadIdx.x]);

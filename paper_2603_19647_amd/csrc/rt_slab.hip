@@ -135,27 +135,56 @@ __device__ inline void rom_apply_coop(const Inst &I, const RomDev &R, int rank, 
   const int lo = blockIdx.x * csz, hi = min(nc, lo + csz);
   double *apx = I.apx + (size_t)cs.buf * ng * RT_RMAX;
   cs.buf ^= 1;
-  for (int k0 = 0; k0 < rank; k0 += 4) {
-    double sacc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int c = lo + (int)threadIdx.x; c < hi; c += NT) {
+  static_assert(RT_RMAX == 20, "four column groups of five");
+  if (nw % 4 == 0) {
+    // the waves split into four column groups of five columns: every thread
+    // has its five loads in flight at once (columns past the rank hold finite
+    // values; their sums are not used)
+    const int cg = wave & 3, sub = wave >> 2, nsub = nw >> 2;
+    double sacc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int c = lo + sub * 64 + lane; c < hi; c += nsub * 64) {
       const double v = rhs[c];
-      double u[4];
+      double u[5];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) u[q] = R.U[(size_t)(k0 + q) * ld + c];
+      for (int q = 0; q < 5; ++q) u[q] = R.U[(size_t)(cg * 5 + q) * ld + c];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) sacc[q] = rt_fma(u[q], v, sacc[q]);
+      for (int q = 0; q < 5; ++q) sacc[q] = rt_fma(u[q], v, sacc[q]);
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 5; ++q) {
       const double t = wave_sum_fast(sacc[q]);
-      if (lane == 0) red[wave * RT_RMAX + k0 + q] = t;
+      if (lane == 0) red[wave * 5 + q] = t;
     }
-  }
-  __syncthreads();
-  if ((int)threadIdx.x < rank) {
-    double sv = 0.0;
-    for (int w = 0; w < nw; ++w) sv += red[w * RT_RMAX + threadIdx.x];
-    xstore(&apx[(size_t)blockIdx.x * RT_RMAX + threadIdx.x], sv);
+    __syncthreads();
+    if ((int)threadIdx.x < rank) {
+      const int k = threadIdx.x, kg = k / 5, kq = k % 5;
+      double sv = 0.0;
+      for (int sb = 0; sb < nsub; ++sb) sv += red[(sb * 4 + kg) * 5 + kq];
+      xstore(&apx[(size_t)blockIdx.x * RT_RMAX + k], sv);
+    }
+  } else {
+    for (int k0 = 0; k0 < rank; k0 += 4) {
+      double sacc[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int c = lo + (int)threadIdx.x; c < hi; c += NT) {
+        const double v = rhs[c];
+        double u[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) u[q] = R.U[(size_t)(k0 + q) * ld + c];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sacc[q] = rt_fma(u[q], v, sacc[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double t = wave_sum_fast(sacc[q]);
+        if (lane == 0) red[wave * RT_RMAX + k0 + q] = t;
+      }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < rank) {
+      double sv = 0.0;
+      for (int w = 0; w < nw; ++w) sv += red[w * RT_RMAX + threadIdx.x];
+      xstore(&apx[(size_t)blockIdx.x * RT_RMAX + threadIdx.x], sv);
+    }
   }
   grid_sync(cs);
   if ((int)threadIdx.x < RT_RMAX) {
@@ -178,12 +207,12 @@ __device__ inline void rom_apply_coop(const Inst &I, const RomDev &R, int rank, 
   for (int c = lo + (int)threadIdx.x; c < hi; c += NT) {
     double v = 0.0;
 #pragma unroll 1
-    for (int k0 = 0; k0 < RT_RMAX; k0 += 5) {
-      double u[5];
+    for (int k0 = 0; k0 < RT_RMAX; k0 += 10) {
+      double u[10];
 #pragma unroll
-      for (int q = 0; q < 5; ++q) u[q] = R.U[(size_t)(k0 + q) * ld + c];
+      for (int q = 0; q < 10; ++q) u[q] = R.U[(size_t)(k0 + q) * ld + c];
 #pragma unroll
-      for (int q = 0; q < 5; ++q) v = rt_fma(u[q], vec[k0 + q], v);
+      for (int q = 0; q < 10; ++q) v = rt_fma(u[q], vec[k0 + q], v);
     }
     xstore(&out[c], v);
   }
@@ -588,14 +617,15 @@ __global__ void __launch_bounds__(MAXT) k_fpass_pair(const Inst *__restrict__ in
 
 // ---------------------------------------------------------------------------
 // k_tail_coop: everything after the SI solve of a problem marched on its own,
-// in one cooperative launch of max(2 + min(npair, 32), nc / TAIL_NT rounded
-// up) workgroups of TAIL_NT threads (up to eight cells per thread for the
-// f-pass scans: no register spills):
-//   1. the ROM projection passes (both ROMs at once; workgroup g < nbp takes
-//      cells g*nthr + t, the partial rows are exchanged coherently);
+// in one cooperative launch of max(2 + min(npair, 32), 4 nbp) workgroups of
+// TAIL_NT threads, nbp = nc / TAIL_NT rounded up (up to eight cells per
+// thread for the f-pass scans: no register spills):
+//   1. the ROM projection passes, each ROM on its own nbp workgroups (one
+//      cell per thread; the partial rows are exchanged coherently);
 //   2. workgroups 0 and 1 run the IG and PC cores (App. B) while the others
 //      run the f-pass, ordinate pairs dealt round-robin;
-//   3. the basis rotation and the pair sum of b~, by cells.
+//   3. the basis rotation, U and W of each ROM on their own nbp workgroups,
+//      and the pair sum of b~, by cells.
 // The decisions were taken by the SI kernel (RomWork.nblk = nbp).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void publish_pend(RomPend *P) {
@@ -633,22 +663,18 @@ __global__ void __launch_bounds__(MAXT) k_tail_coop(const Inst *__restrict__ ins
   const int rom = I.method == RT_ROM;
   const RomWork &Wi = *I.ig.work, &Wp = *I.pc.work;
   const int act0 = rom && Wi.active, act1 = rom && Wp.active;
-  // 1. projection passes
+  // 1. projection passes: ROM z on workgroups [z*nbp, z*nbp + nbp), block
+  // gb = g - z*nbp of nbp taking cells gb*NT + t
+  const int zs = g / nbp, gb = g - zs * nbp;
   if (act0 || act1) {
-    if (g < nbp) {
-      if (act0) rom_pass1<true>(I, I.ig, Wi, 0, g, nbp, red, out);
-      if (act1) rom_pass1<true>(I, I.pc, Wp, 1, g, nbp, red, out);
-    }
+    if (zs == 0 && act0) rom_pass1<true>(I, I.ig, Wi, 0, gb, nbp, red, out);
+    if (zs == 1 && act1) rom_pass1<true>(I, I.pc, Wp, 1, gb, nbp, red, out);
     grid_sync(cs);
-    if (g < nbp) {
-      if (act0) rom_pass2<true>(I, I.ig, Wi, g, nbp, red, out, av, sm.scratch);
-      if (act1) rom_pass2<true>(I, I.pc, Wp, g, nbp, red, out, av, sm.scratch);
-    }
+    if (zs == 0 && act0) rom_pass2<true>(I, I.ig, Wi, gb, nbp, red, out, av, sm.scratch);
+    if (zs == 1 && act1) rom_pass2<true>(I, I.pc, Wp, gb, nbp, red, out, av, sm.scratch);
     grid_sync(cs);
-    if (g < nbp) {
-      if (act0) rom_pass3<true>(I, I.ig, Wi, g, nbp, red, out, av, sm.scratch);
-      if (act1) rom_pass3<true>(I, I.pc, Wp, g, nbp, red, out, av, sm.scratch);
-    }
+    if (zs == 0 && act0) rom_pass3<true>(I, I.ig, Wi, gb, nbp, red, out, av, sm.scratch);
+    if (zs == 1 && act1) rom_pass3<true>(I, I.pc, Wp, gb, nbp, red, out, av, sm.scratch);
     grid_sync(cs);
   }
   // 2. cores on workgroups 0 and 1, f-pass on the others
@@ -669,20 +695,18 @@ __global__ void __launch_bounds__(MAXT) k_tail_coop(const Inst *__restrict__ ins
       fpass_one_pair<CMAX, true>(I, p, c0, n, ct, Gs, srcc, 0, slots, parity);
   }
   grid_sync(cs);
-  // 3. rotation (ROM z, matrix mat) and b~ by cells c = g*NT + t
-  const int c = g * NT + threadIdx.x;
-  if (rom) {
-    for (int zm = 0; zm < 4; ++zm) {
-      const int z = zm >> 1, mat = zm & 1;
-      const RomDev &R = z ? I.pc : I.ig;
-      RomPend *P = R.pend;
-      if (!xload(&P->pending)) continue;  // uniform
-      if (g >= nbp) continue;             // uniform: no cells here
+  // 3. rotation: matrix mat of ROM z on workgroups [s*nbp, s*nbp + nbp) with
+  // s = z for U (the workgroups that wrote p there) and s = 2 + z for W
+  if (rom && zs < 4) {
+    const int z = zs & 1, mat = zs >> 1;
+    const RomDev &R = z ? I.pc : I.ig;
+    RomPend *P = R.pend;
+    if (xload(&P->pending)) {  // uniform
       const double *src = mat ? P->Vc : P->Uc;
-      __syncthreads();  // cc of the previous matrix fully used
       for (int e = threadIdx.x; e < RT_KC * RT_KC; e += NT) cc[e] = xload(&src[e]);
       __syncthreads();
       const int r = xload(&P->r_old), k = xload(&P->k);
+      const int c = gb * NT + threadIdx.x;
       if (c < nc) {
         const RomWork &W = z ? Wp : Wi;
         double *X = mat ? R.W : R.U;
@@ -694,13 +718,15 @@ __global__ void __launch_bounds__(MAXT) k_tail_coop(const Inst *__restrict__ ins
           const double v = X[(size_t)q * I.ld + c];
           old[0][q] = q < r ? v : 0.0;
         }
-        e[0] = mat ? W.b[c] : W.p[c] * xload(&P->inv_nu);
+        e[0] = mat ? xload(W.b + c) : W.p[c] * xload(&P->inv_nu);
         rotate_block<1>(old, e, cc, r, k, X, I.ld, cv, ok);
       }
     }
   }
+  // b~: the pairs' moments in pair order, by cells c = g*NT + t
+  const int c = g * NT + threadIdx.x;
   if (c < nc) {
-    // pairs in order, eight loads in flight per batch (clamped, masked)
+    // eight loads in flight per batch (clamped, masked)
     double acc = 0.0;
     const double *part = I.fpart + c;
     const int np = I.npair;
@@ -796,15 +822,36 @@ extern "C" hipError_t rt_launch_slab_si(const Inst *dinsts, int ninst, int nthre
   return hipGetLastError();
 }
 
-// One instance on ng co-resident workgroups (a cooperative launch, which the
-// runtime rejects rather than start when they cannot all be resident).
+// One instance on ng workgroups that wait for each other at grid barriers.
+// They are launched as an ordinary grid: a cooperative launch guarantees
+// co-residency but costs ~17 us more per launch here.  Co-residency holds
+// because rt_slab_coop_fits checked at creation that the device holds every
+// workgroup of both cooperative kernels at once (with ng <= 16 and tails of
+// <= 34 workgroups, a small fraction of the device); should other work keep
+// some of them from starting for ~2 s, the barrier waits give up, the state
+// is flagged and the march reports an error instead of hanging.
 extern "C" hipError_t rt_launch_slab_si_coop(const Inst *dinst, int ng, int nthreads, int cmax, hipStream_t stream) {
-  void *args[] = {(void *)&dinst};
-  if (cmax <= 4)
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_si_slab<4, 1024, true>), dim3(ng),
-                                      dim3(nthreads), args, 0, stream);
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_si_slab<8, 512, true>), dim3(ng),
-                                    dim3(nthreads), args, 0, stream);
+  if (cmax <= 4) hipLaunchKernelGGL((k_si_slab<4, 1024, true>), dim3(ng), dim3(nthreads), 0, stream, dinst);
+  else hipLaunchKernelGGL((k_si_slab<8, 512, true>), dim3(ng), dim3(nthreads), 0, stream, dinst);
+  return hipGetLastError();
+}
+
+static int tail_grid(int npair, int nc) {
+  return std::max(2 + std::min(npair, 32), 4 * ((nc + TAIL_NT - 1) / TAIL_NT));
+}
+
+// Whether the device holds all workgroups of the SI kernel (ng x nthreads)
+// and of the step tail at once.
+extern "C" int rt_slab_coop_fits(int device, int ng, int nthreads, int cmax, int npair, int nc) {
+  int cus = 0, a = 0, b = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+  const void *si = cmax <= 4 ? reinterpret_cast<const void *>(&k_si_slab<4, 1024, true>)
+                             : reinterpret_cast<const void *>(&k_si_slab<8, 512, true>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, si, nthreads, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, reinterpret_cast<const void *>(&k_tail_coop<8, TAIL_NT>),
+                                                   TAIL_NT, 0) != hipSuccess)
+    return 0;
+  return (long long)a * cus >= ng && (long long)b * cus >= tail_grid(npair, nc);
 }
 
 // gp pairs per workgroup: one when the launch has few pairs in total (every
@@ -834,17 +881,16 @@ extern "C" hipError_t rt_launch_slab_rhs(const Inst *dinsts, int ninst, int nthr
   return launch_fpass(dinsts, ninst, nthreads, cmax, npair_max, nc_max, 1, npair_max * ninst, stream);
 }
 
-// The step's tail for a problem marched on its own (cooperative).
+// The step's tail for a problem marched on its own.
 extern "C" hipError_t rt_launch_slab_tail_coop(const Inst *dinst, int npair, int nc, int nthreads, int cmax,
                                                hipStream_t stream) {
   (void)nthreads;
   (void)cmax;
-  void *args[] = {(void *)&dinst};
-  // two core workgroups + the f-pass ones, and at least one per TAIL_NT cells
-  // (the passes, the rotation and the b~ sum take one cell per thread)
-  const dim3 grid(std::max(2 + std::min(npair, 32), (nc + TAIL_NT - 1) / TAIL_NT));
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_tail_coop<8, TAIL_NT>), grid, dim3(TAIL_NT),
-                                    args, 0, stream);
+  // two core workgroups + the f-pass ones, and four sets of one workgroup per
+  // TAIL_NT cells (the passes of the two ROMs, the rotation of U and W of
+  // each: one cell per thread); an ordinary grid, as for the SI kernel
+  hipLaunchKernelGGL((k_tail_coop<8, TAIL_NT>), dim3(tail_grid(npair, nc)), dim3(TAIL_NT), 0, stream, dinst);
+  return hipGetLastError();
 }
 
 extern "C" hipError_t rt_launch_slab_setup(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream) {
