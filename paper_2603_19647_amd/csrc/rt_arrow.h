@@ -223,10 +223,13 @@ RT_HD inline double lam_minus_pole(const Problem &P, int K, double tau, int j) {
 // Recomputed coupling for pole j from all the roots (Gu-Eisenstat), sign of z_j.
 RT_HD inline double zhat(const Problem &P, int j, const int *K, const double *tau) {
   double prod = lam_minus_pole(P, K[P.m - 1], tau[P.m - 1], j);
-  for (int i = 0; i < P.m - 1; ++i) {
-    // pair the root below/above pole j with the pole difference of the same side
-    const int dpole = i < j ? i : i + 1;
-    prod *= lam_minus_pole(P, K[i], tau[i], j) * rcp(pole_diff(P.s[dpole], P.s[j]));
+#pragma unroll
+  for (int i = 0; i < N - 1; ++i) {
+    if (i < P.m - 1) {
+      // pair the root below/above pole j with the pole difference of the same side
+      const int dpole = i < j ? i : i + 1;
+      prod *= lam_minus_pole(P, K[i], tau[i], j) * rcp(pole_diff(P.s[dpole], P.s[j]));
+    }
   }
   const double mag = sqrt(fabs(prod));
   return P.z[j] >= 0.0 ? mag : -mag;
@@ -273,23 +276,38 @@ RT_HD inline double vectors(const Problem &P, int k, const int *K, const double 
                             double *u, int us, double *v, int vs) {
   const int Kk = K[k];
   const double tk = tau[k];
-  for (int i = 0; i < P.rows; ++i) u[i * us] = 0.0;
-  for (int i = 0; i < P.cols; ++i) v[i * vs] = 0.0;
+  // components in registers first (loops over the capacity), then every
+  // store at once: zeros for the deflated rows, the normalised entries
+  double ur[N], vr[N];
   double un = 0.0, vn = 1.0;
-  for (int i = 0; i < P.m; ++i) {
-    const double ui = zh[i] * rcp(pole_diff(P.s[i], P.s[Kk]) - tk);
-    u[P.row[i] * us] = ui;
-    un += ui * ui;
-    if (P.row[i] < r) {
-      const double vi = P.s[i] * ui;
-      v[P.row[i] * vs] = vi;
-      vn += vi * vi;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    ur[i] = vr[i] = 0.0;
+    if (i < P.m) {
+      const double ui = zh[i] * rcp(pole_diff(P.s[i], P.s[Kk]) - tk);
+      ur[i] = ui;
+      un += ui * ui;
+      if (P.row[i] < r) {
+        const double vi = P.s[i] * ui;
+        vr[i] = vi;
+        vn += vi * vi;
+      }
     }
   }
-  v[r * vs] = -1.0;  // z^T (D - lambda)^{-1} z = -1 at a root
   const double iu = rcp(sqrt(un)), iv = rcp(sqrt(vn));
-  for (int i = 0; i < P.rows; ++i) u[i * us] *= iu;
-  for (int i = 0; i < P.cols; ++i) v[i * vs] *= iv;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    if (i < P.rows) u[i * us] = 0.0;
+    if (i < P.cols) v[i * vs] = 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    if (i < P.m) {
+      const int row = P.row[i];
+      u[row * us] = ur[i] * iu;
+      if (row < r) v[row * vs] = vr[i] * iv;
+    }
+  v[r * vs] = -iv;  // z^T (D - lambda)^{-1} z = -1 at a root, normalised
   return sqrt(P.s[Kk] * P.s[Kk] + tk);
 }
 
