@@ -14,8 +14,9 @@
 struct RomPend {
   int pending, r_old, rows, k, deficient, pad_[3];
   double inv_nu;
-  const double *p;  // projected snapshot residual (global)
+  const double *p;  // first Gram-Schmidt residual v = x - U a (global)
   const double *b;  // right-hand-side snapshot (global)
+  double a2[RT_RMAX];  // second Gram-Schmidt coefficients: the new direction is v - U a2
   double Uc[RT_KC * RT_KC];  // [q][j], stride RT_KC
   double Vc[RT_KC * RT_KC];
 };

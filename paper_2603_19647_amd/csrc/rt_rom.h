@@ -568,15 +568,25 @@ __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, in
   const int tid = threadIdx.x, NT = blockDim.x;
   const int r = Wk.r, nb = Wk.nblk;
   RomPend *P = R.pend;
-  // fixed-order block sums: pass 1 -> U^T x, U^T b, x.x, x.b; pass 2 -> a2, p1^T W;
-  // pass 3 -> p.p, p.b
+  // fixed-order block sums: pass 1 -> a = U^T x, U^T b, x.x, x.b; pass 2 ->
+  // a2 = U^T v, W^T v, v.v, v.b for the first residual v = x - U a.  The
+  // second Gram-Schmidt step p = v - U a2 is applied by the rotation; its
+  // norm and p.b follow from pass 2 (U^T v = a2, U^T U = I to rounding, and
+  // a2 is at rounding level, so neither difference cancels):
+  //   ||p||^2 = v.v - a2.a2,   p.b = v.b - a2 . U^T b
   sum_partials<COH>(Wk.part1, nb, 2 * RT_RMAX + 2, sm.red, sm.scratch);
-  sum_partials<COH>(Wk.part2, nb, 2 * RT_RMAX, sm.red + 2 * RT_RMAX + 2, sm.scratch);
-  sum_partials<COH>(Wk.part3, nb, 2, sm.red + 4 * RT_RMAX + 2, sm.scratch);
+  sum_partials<COH>(Wk.part2, nb, 2 * RT_RMAX + 2, sm.red + 2 * RT_RMAX + 2, sm.scratch);
   const double xn = sqrt(sm.red[2 * RT_RMAX]);
   const double xb = sm.red[2 * RT_RMAX + 1];
-  const double nu = sqrt(sm.red[4 * RT_RMAX + 2]);
-  const double pb = sm.red[4 * RT_RMAX + 3];
+  double nu2 = sm.red[4 * RT_RMAX + 2], pb = sm.red[4 * RT_RMAX + 3];
+  for (int j = 0; j < r; ++j) {
+    const double a2 = sm.red[2 * RT_RMAX + 2 + j];
+    nu2 = rt_fma(-a2, a2, nu2);
+    pb = rt_fma(-a2, sm.red[RT_RMAX + j], pb);
+  }
+  const double nu = sqrt(fmax(nu2, 0.0));
+  // a2 for the rotation, zero past the rank
+  if (tid < RT_RMAX) P->a2[tid] = tid < r ? sm.red[2 * RT_RMAX + 2 + tid] : 0.0;
   if (r == 0) {
     if (xn == 0.0) {
       if (tid == 0) P->pending = 0;
@@ -705,6 +715,14 @@ __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, in
 // every product runs over the full capacity without branches.  Each
 // coefficient read from LDS serves NCELL cells, and the outputs go in blocks
 // of four columns, which bounds the registers the LDS reads take.
+// p = v - U a2 for one cell from its old basis row (the second Gram-Schmidt
+// step, in the order the passes use).
+__device__ __forceinline__ double second_residual(double v, const double (&old)[RT_RMAX], const double *a2) {
+#pragma unroll
+  for (int k = 0; k < RT_RMAX; ++k) v = rt_fma(-old[k], a2[k], v);
+  return v;
+}
+
 template <int NCELL>
 __device__ __forceinline__ void rotate_block(const double (&old)[NCELL][RT_RMAX], const double (&e)[NCELL],
                                              const double *Cc, int r, int k, double *X, int ld, const int (&c)[NCELL],
@@ -905,9 +923,9 @@ __device__ __forceinline__ void rom_pass2(const Inst &I, const RomDev &R, const 
   const int r = W.r, ld = I.ld, NT = blockDim.x;
   // every column: pass 1 left zero sums past the rank, so av is zero there
   sum_partials<COH>(W.part1, nb, RT_RMAX, av, scratch);
-  double part[2 * RT_RMAX];
+  double part[2 * RT_RMAX + 2];
 #pragma unroll
-  for (int k = 0; k < 2 * RT_RMAX; ++k) part[k] = 0.0;
+  for (int k = 0; k < 2 * RT_RMAX + 2; ++k) part[k] = 0.0;
   for (int c = b * NT + threadIdx.x; c < I.nc; c += nb * NT) {
     // all loads issued up front and unconditionally (masked past the rank);
     // the arithmetic keeps its order
@@ -919,42 +937,22 @@ __device__ __forceinline__ void rom_pass2(const Inst &I, const RomDev &R, const 
       wv[k] = k < r ? y : 0.0;
     }
     double v = part_load<COH>(W.x + c);
+    const double bv = part_load<COH>(W.b + c);
 #pragma unroll
     for (int k = 0; k < RT_RMAX; ++k) v = rt_fma(-u[k], av[k], v);
-    W.p[c] = v;
+    W.p[c] = v;  // first Gram-Schmidt residual; the rotation subtracts U a2
 #pragma unroll
     for (int k = 0; k < RT_RMAX; ++k) {
       part[k] = rt_fma(u[k], v, part[k]);
       part[RT_RMAX + k] = rt_fma(wv[k], v, part[RT_RMAX + k]);
     }
+    part[2 * RT_RMAX] = rt_fma(v, v, part[2 * RT_RMAX]);
+    part[2 * RT_RMAX + 1] = rt_fma(v, bv, part[2 * RT_RMAX + 1]);
   }
-  wg_sum_fast<2 * RT_RMAX>(part, red, out);
-  if (threadIdx.x < 2 * RT_RMAX) part_store<COH>(&W.part2[b * RT_NPART + threadIdx.x], out[threadIdx.x]);
+  wg_sum_fast<2 * RT_RMAX + 2>(part, red, out);
+  if (threadIdx.x < 2 * RT_RMAX + 2) part_store<COH>(&W.part2[b * RT_NPART + threadIdx.x], out[threadIdx.x]);
 }
 
-template <bool COH>
-__device__ __forceinline__ void rom_pass3(const Inst &I, const RomDev &R, const RomWork &W, int b, int nb,
-                                          double *red, double *out, double *a2, double *scratch) {
-  const int r = W.r, ld = I.ld, NT = blockDim.x;
-  sum_partials<COH>(W.part2, nb, RT_RMAX, a2, scratch);  // zero past the rank
-  double part[2] = {0.0, 0.0};
-  for (int c = b * NT + threadIdx.x; c < I.nc; c += nb * NT) {
-    double u[RT_RMAX];
-#pragma unroll
-    for (int k = 0; k < RT_RMAX; ++k) {
-      const double x = R.U[(size_t)k * ld + c];
-      u[k] = k < r ? x : 0.0;
-    }
-    double v = W.p[c];
-#pragma unroll
-    for (int k = 0; k < RT_RMAX; ++k) v = rt_fma(-u[k], a2[k], v);
-    W.p[c] = v;
-    part[0] = rt_fma(v, v, part[0]);
-    part[1] = rt_fma(v, part_load<COH>(W.b + c), part[1]);
-  }
-  wg_sum_fast<2>(part, red, out);
-  if (threadIdx.x < 2) part_store<COH>(&W.part3[b * RT_NPART + threadIdx.x], out[threadIdx.x]);
-}
 
 // ---------------------------------------------------------------------------
 // Small dense part of the update (isvd_core) and Alg. 2's phase flags for

@@ -18,7 +18,7 @@ __device__ __host__ __forceinline__ int pass_blocks(int nc) { return rt_pass_blo
 // k_rom_norms: per-block partial sums of ||rho^n||^2, ||rho^(0) - rho^n||^2
 // and ||dpc - (rho^n - rho^(1/2))||^2 for the error indicators of Sec. 3.2,
 // grid (blocks of BLK cells, instance).  Written to the IG ROM's third
-// partial buffer, which k_rom_pass3 reuses only after k_rom_decide.
+// partial buffer, which the ROM passes do not use.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(BLK) k_rom_norms(const Inst *__restrict__ insts) {
   const Inst &I = insts[blockIdx.y];
@@ -61,19 +61,10 @@ __global__ void __launch_bounds__(BLK) k_rom_pass2(const Inst *__restrict__ inst
   const RomDev &R = rom_of(I, blockIdx.z);
   const RomWork &W = *R.work;
   if (!W.active || (int)blockIdx.x >= W.nblk) return;
-  __shared__ double red[(BLK / 64) * 2 * RT_RMAX], out[2 * RT_RMAX], av[RT_RMAX], scratch[BLK];
+  __shared__ double red[(BLK / 64) * (2 * RT_RMAX + 2)], out[2 * RT_RMAX + 2], av[RT_RMAX], scratch[BLK];
   rom_pass2<false>(I, R, W, blockIdx.x, W.nblk, red, out, av, scratch);
 }
 
-__global__ void __launch_bounds__(BLK) k_rom_pass3(const Inst *__restrict__ insts) {
-  const Inst &I = insts[blockIdx.y];
-  if (I.method != RT_ROM || I.post_fused) return;
-  const RomDev &R = rom_of(I, blockIdx.z);
-  const RomWork &W = *R.work;
-  if (!W.active || (int)blockIdx.x >= W.nblk) return;
-  __shared__ double red[(BLK / 64) * 2], out[2], a2[RT_RMAX], scratch[BLK];
-  rom_pass3<false>(I, R, W, blockIdx.x, W.nblk, red, out, a2, scratch);
-}
 
 // k_rom_core: rom_core after the grid passes, grid (instance, ROM).
 __global__ void __launch_bounds__(256) k_rom_core(const Inst *__restrict__ insts) {
@@ -108,8 +99,6 @@ __global__ void __launch_bounds__(256) k_rom_post_small(const Inst *__restrict__
   __syncthreads();
   rom_pass2<false>(I, R, W, 0, 1, red, out, av, scratch);
   __syncthreads();
-  rom_pass3<false>(I, R, W, 0, 1, red, out, av, scratch);
-  __syncthreads();
   rom_core<false>(I, R, W, z, sm);
 }
 
@@ -127,7 +116,7 @@ __global__ void __launch_bounds__(UPD_BLK) k_rom_update(const Inst *__restrict__
   const Inst &I = insts[blockIdx.y];
   // four spare entries: the column blocks of the rotation read up to three
   // entries past the last row (discarded products)
-  __shared__ double cc[RT_KC * RT_KC + 4];
+  __shared__ double cc[RT_KC * RT_KC + 4], a2[RT_RMAX];
   if (I.method != RT_ROM) return;
   const int cb = blockIdx.x * UPD_BLK * UPD_CPT;
   if (cb >= I.nc) return;
@@ -137,6 +126,7 @@ __global__ void __launch_bounds__(UPD_BLK) k_rom_update(const Inst *__restrict__
   if (!P.pending) return;
   const double *src = mat ? P.Vc : P.Uc;
   for (int e = threadIdx.x; e < RT_KC * RT_KC; e += blockDim.x) cc[e] = src[e];
+  if (threadIdx.x < RT_RMAX) a2[threadIdx.x] = P.a2[threadIdx.x];
   __syncthreads();
   const int r = P.r_old, ld = I.ld;
   double *X = mat ? R.W : R.U;
@@ -156,9 +146,9 @@ __global__ void __launch_bounds__(UPD_BLK) k_rom_update(const Inst *__restrict__
       const double v = X[(size_t)q * ld + cl];
       old[i][q] = q < r ? v : 0.0;
     }
-    // row r: p / nu for U (inv_nu = 0 and a zero row when the snapshot was
-    // rank-deficient), b for W
-    e[i] = mat ? P.b[cl] : P.p[cl] * P.inv_nu;
+    // row r: the new direction, (v - U a2) / nu for U (inv_nu = 0 and a zero
+    // row when the snapshot was rank-deficient), b for W
+    e[i] = mat ? P.b[cl] : second_residual(P.p[cl], old[i], a2) * P.inv_nu;
   }
   rotate_block<UPD_CPT>(old, e, cc, r, P.k, X, ld, c, ok);
 }
@@ -170,7 +160,6 @@ extern "C" hipError_t rt_launch_rom(const Inst *dinsts, int ninst, int nc_max, i
   if (any_rom) {
     hipLaunchKernelGGL(k_rom_pass1, dim3(nb, ninst, 2), dim3(BLK), 0, s, dinsts);
     hipLaunchKernelGGL(k_rom_pass2, dim3(nb, ninst, 2), dim3(BLK), 0, s, dinsts);
-    hipLaunchKernelGGL(k_rom_pass3, dim3(nb, ninst, 2), dim3(BLK), 0, s, dinsts);
     hipLaunchKernelGGL(k_rom_core, dim3(ninst, 2), dim3(256), 0, s, dinsts);
   }
   return hipGetLastError();
@@ -185,7 +174,6 @@ extern "C" hipError_t rt_launch_rom_slab(const Inst *dinsts, int ninst, int any_
     const int nb = pass_blocks(nc_grid);
     hipLaunchKernelGGL(k_rom_pass1, dim3(nb, ninst, 2), dim3(BLK), 0, s, dinsts);
     hipLaunchKernelGGL(k_rom_pass2, dim3(nb, ninst, 2), dim3(BLK), 0, s, dinsts);
-    hipLaunchKernelGGL(k_rom_pass3, dim3(nb, ninst, 2), dim3(BLK), 0, s, dinsts);
     hipLaunchKernelGGL(k_rom_core, dim3(ninst, 2), dim3(256), 0, s, dinsts);
   }
   return hipGetLastError();

@@ -620,7 +620,8 @@ __global__ void __launch_bounds__(MAXT) k_fpass_pair(const Inst *__restrict__ in
 // in one cooperative launch of max(2 + min(npair, 32), 4 nbp) workgroups of
 // TAIL_NT threads, nbp = nc / TAIL_NT rounded up (up to eight cells per
 // thread for the f-pass scans: no register spills):
-//   1. the ROM projection passes, each ROM on its own nbp workgroups (one
+//   1. the ROM projection passes (two: the second Gram-Schmidt step is
+//      applied by the rotation), each ROM on its own nbp workgroups (one
 //      cell per thread; the partial rows are exchanged coherently);
 //   2. workgroups 0 and 1 run the IG and PC cores (App. B) while the others
 //      run the f-pass, ordinate pairs dealt round-robin;
@@ -636,6 +637,7 @@ __device__ __forceinline__ void publish_pend(RomPend *P) {
     xstore(&P->Uc[e], P->Uc[e]);
     xstore(&P->Vc[e], P->Vc[e]);
   }
+  if (threadIdx.x < RT_RMAX) xstore(&P->a2[threadIdx.x], P->a2[threadIdx.x]);
   if (threadIdx.x == 0) {
     xstore(&P->r_old, P->r_old);
     xstore(&P->k, P->k);
@@ -652,7 +654,7 @@ __global__ void __launch_bounds__(MAXT) k_tail_coop(const Inst *__restrict__ ins
   if (xload(&st->fault)) return;
   __shared__ double slots[8 * RT_MAXWAVES];
   __shared__ double red[RT_MAXWAVES * (2 * RT_RMAX + 2)], out[2 * RT_RMAX + 2], av[RT_RMAX];
-  __shared__ double cc[RT_KC * RT_KC + 4];
+  __shared__ double cc[RT_KC * RT_KC + 4], a2s[RT_RMAX];
   __shared__ RomSmem sm;
   // the tail's own barrier counters (the SI kernel's use another grid size)
   unsigned long long *bar = I.bar + 4;
@@ -672,9 +674,6 @@ __global__ void __launch_bounds__(MAXT) k_tail_coop(const Inst *__restrict__ ins
     grid_sync(cs);
     if (zs == 0 && act0) rom_pass2<true>(I, I.ig, Wi, gb, nbp, red, out, av, sm.scratch);
     if (zs == 1 && act1) rom_pass2<true>(I, I.pc, Wp, gb, nbp, red, out, av, sm.scratch);
-    grid_sync(cs);
-    if (zs == 0 && act0) rom_pass3<true>(I, I.ig, Wi, gb, nbp, red, out, av, sm.scratch);
-    if (zs == 1 && act1) rom_pass3<true>(I, I.pc, Wp, gb, nbp, red, out, av, sm.scratch);
     grid_sync(cs);
   }
   // 2. cores on workgroups 0 and 1, f-pass on the others
@@ -704,6 +703,7 @@ __global__ void __launch_bounds__(MAXT) k_tail_coop(const Inst *__restrict__ ins
     if (xload(&P->pending)) {  // uniform
       const double *src = mat ? P->Vc : P->Uc;
       for (int e = threadIdx.x; e < RT_KC * RT_KC; e += NT) cc[e] = xload(&src[e]);
+      if (threadIdx.x < RT_RMAX) a2s[threadIdx.x] = xload(&P->a2[threadIdx.x]);
       __syncthreads();
       const int r = xload(&P->r_old), k = xload(&P->k);
       const int c = gb * NT + threadIdx.x;
@@ -718,7 +718,8 @@ __global__ void __launch_bounds__(MAXT) k_tail_coop(const Inst *__restrict__ ins
           const double v = X[(size_t)q * I.ld + c];
           old[0][q] = q < r ? v : 0.0;
         }
-        e[0] = mat ? xload(W.b + c) : W.p[c] * xload(&P->inv_nu);
+        // the new direction (v - U a2) / nu for U, b for W
+        e[0] = mat ? xload(W.b + c) : second_residual(W.p[c], old[0], a2s) * xload(&P->inv_nu);
         rotate_block<1>(old, e, cc, r, k, X, I.ld, cv, ok);
       }
     }
