@@ -79,6 +79,55 @@ def run_batch(specs, warmup, steps, rtrom):
     return t1 - t0, stats, prof
 
 
+def copy_probe(mib: int):
+    """A plain device-to-device copy of known size (read and write mib MiB each
+    time), for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"bench: copy probe {mib} MiB x 5")
+
+
+# Sources of the dominant kernels: a stored counter measurement is used only
+# while these files are unchanged.
+KERNEL_SOURCES = {
+    "k_si_slab": ["rt_slab.hip", "rt_common.h", "rt_rom.h", "rt_arrow.h"],
+    "k_plane_sweep": ["rt_plane.hip", "rt_common.h"],
+}
+
+
+def sources_digest(kernel: str) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2603_19647_amd", "csrc")
+    for f in KERNEL_SOURCES.get(kernel, []):
+        with open(os.path.join(base, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel: str, workload: str):
+    """HBM bytes per dispatch from profiles/<kernel>_<workload>_traffic.md (two
+    rocprofv3 --pmc runs, FETCH_SIZE and WRITE_SIZE, scaled by the same
+    counters on a copy of known size), or None when absent or when the
+    kernel's sources changed since the counters were taken."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", f"{kernel}_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    digest, value = None, None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("sources sha256:"):
+                digest = line.split(":", 1)[1].strip()
+            if line.startswith("HBM bytes per dispatch:"):
+                value = float(line.split(":", 1)[1].strip())
+    return value if digest == sources_digest(kernel) and value is not None else None
+
+
 def kernel_ms(prof):
     return {k: v[0] / v[1] * 1e3 for k, v in prof.items() if v[1]}
 
@@ -103,7 +152,7 @@ def roofline_dsa(prof, nc, cheb_iters):
     bytes_ = 72.0 * nc * cheb_iters * launches
     ach = bytes_ / sec / 1e9
     return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": "k_dsa_cheb", "kind": "plane_dsa",
+            "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": "k_dsa_block", "kind": "plane_dsa",
             "launches": launches, "avg_launch_ms": sec / launches * 1e3,
             "bytes_per_launch": bytes_ / launches}
 
@@ -209,6 +258,9 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=4.0, help="serving: HBM admission budget")
     ap.add_argument("--slots", type=int, default=8, help="serving: concurrent problems")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device five times (a plain copy of known size, "
+                         "against which hardware byte counters are scaled)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -218,6 +270,8 @@ def main():
     from paper_2603_19647_amd import rtrom
     from paper_2603_19647_amd import workloads as W
 
+    if args.copy_probe > 0:
+        copy_probe(args.copy_probe)
     extra = {}
     if args.workload in ("slab4096", "checker256"):
         spec = W.slab_random_regions() if args.workload == "slab4096" else W.checkerboard()
@@ -316,6 +370,10 @@ def main():
         unit = "instance-steps/s"
         cpu = None if args.no_cpu_baseline else cpu_baseline_batch(specs, steps)
 
+    if roof is not None:
+        wl_name = {"slab4096_gl64_32regions": "slab4096", "checkerboard256_cl16x8": "checker256",
+                   "batch512_slabs": "batch512"}.get(config.get("workload"), "")
+        roof["traffic"] = stored_traffic(roof["kernel"], wl_name)
     out = {
         "metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warm,
         "ms_per_step": t_rom / steps * 1e3, "higher_is_better": True, "scaling": "weak",
