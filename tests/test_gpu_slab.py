@@ -56,6 +56,19 @@ def test_single_workgroup_mode_rom_fp64(nv):
     assert_same_decisions(o, g)
 
 
+@pytest.mark.parametrize("nx,nv,method", [(300, 128, "rom"), (513, 256, "si_dsa"), (90, 6, "rom")])
+def test_pair_groups_wide_quadratures(nx, nv, method):
+    """Pair groups of several pairs (GL128: 16 groups of 4; GL256: 16 of 8) and
+    an odd split (GL6: 3 groups of 1), step tail with pairs dealt over its
+    workgroups, against the oracle."""
+    spec = W.random_slab(40 + nv, nx, nv, method=method, precision="fp64", dt=0.02)
+    say(f"pair groups {method} {nx}x{nv}")
+    errs, o, g = step_both(spec, 8)
+    assert errs.max() <= FP64_TOL, errs.max()
+    assert_same_decisions(o, g)
+    assert rel_l2(g.f(), o.f()) <= FP64_TOL
+
+
 def test_cooperative_and_single_workgroup_agree():
     """The two SI kernels sum the pair moments in different orders only."""
     spec = W.random_slab(32, 1500, 64, method="rom", precision="fp64")
