@@ -562,7 +562,10 @@ __device__ inline bool core_svd_secular(RomSmem &sm, const double *S, const doub
 // k_rom_update.  Returns 1 for a rank-deficient snapshot (x in span U), 0
 // otherwise, -1 if x = 0 at rank 0 (nothing added).  rank / luok updated.
 // ---------------------------------------------------------------------------
-template <bool COH>
+// DEFER_LU: leave the LU of A_r to isvd_lu (the order of the factorised
+// matrix in sm.ibuf[2]), so that a caller can factorise while other
+// workgroups rotate the basis; luok is then not touched.
+template <bool COH, bool DEFER_LU = false>
 __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, int &rank, int &luok,
                                 RomSmem &sm) {
   const int tid = threadIdx.x, NT = blockDim.x;
@@ -610,7 +613,11 @@ __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, in
       P->b = Wk.b;
     }
     __syncthreads();
-    luok = !lu_factor_wave(sm.A, sm.perm, 1, R.LU, R.perm, &sm.ibuf[0]);
+    if constexpr (DEFER_LU) {
+      if (tid == 0) sm.ibuf[2] = 1;
+    } else {
+      luok = !lu_factor_wave(sm.A, sm.perm, 1, R.LU, R.perm, &sm.ibuf[0]);
+    }
     rank = 1;
     return 0;
   }
@@ -703,9 +710,20 @@ __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, in
     P->b = Wk.b;
   }
   __syncthreads();
-  luok = !lu_factor_wave(sm.A, sm.perm, k, R.LU, R.perm, &sm.ibuf[0]);
+  if constexpr (DEFER_LU) {
+    if (tid == 0) sm.ibuf[2] = k;
+  } else {
+    luok = !lu_factor_wave(sm.A, sm.perm, k, R.LU, R.perm, &sm.ibuf[0]);
+  }
   rank = k;
   return deficient;
+}
+
+// The LU of A_r that isvd_core<., true> left in sm; returns luok.
+__device__ inline int isvd_lu(const RomDev &R, RomSmem &sm) {
+  __syncthreads();
+  const int n = sm.ibuf[2];
+  return !lu_factor_wave(sm.A, sm.perm, n, R.LU, R.perm, &sm.ibuf[0]);
 }
 
 // Second half: U <- [U, p/nu] Uc[:, :k] (or W <- [W, b] Vc[:, :k]) for the
@@ -940,7 +958,7 @@ __device__ __forceinline__ void rom_pass2(const Inst &I, const RomDev &R, const 
     const double bv = part_load<COH>(W.b + c);
 #pragma unroll
     for (int k = 0; k < RT_RMAX; ++k) v = rt_fma(-u[k], av[k], v);
-    W.p[c] = v;  // first Gram-Schmidt residual; the rotation subtracts U a2
+    part_store<COH>(W.p + c, v);  // first Gram-Schmidt residual; the rotation subtracts U a2
 #pragma unroll
     for (int k = 0; k < RT_RMAX; ++k) {
       part[k] = rt_fma(u[k], v, part[k]);
@@ -960,12 +978,12 @@ __device__ __forceinline__ void rom_pass2(const Inst &I, const RomDev &R, const 
 // writes only ROM z's state fields, so the two ROMs' workgroups may run at
 // once.
 // ---------------------------------------------------------------------------
-template <bool COH>
+template <bool COH, bool DEFER_LU = false>
 __device__ __forceinline__ void rom_core(const Inst &I, const RomDev &R, const RomWork &W, int z, RomSmem &sm) {
   RtState *st = I.st;
   int rank = z ? st->rank_pc : st->rank_ig;
   int luok = z ? st->lu_ok_pc : st->lu_ok_ig;
-  const int dfc = isvd_core<COH>(R, W, I.r_max, rank, luok, sm);
+  const int dfc = isvd_core<COH, DEFER_LU>(R, W, I.r_max, rank, luok, sm);
   if (threadIdx.x == 0) {
     const long long step_no = W.step_no;
     int updated = 0;
@@ -991,11 +1009,11 @@ __device__ __forceinline__ void rom_core(const Inst &I, const RomDev &R, const R
     }
     if (z == 0) {
       st->rank_ig = rank;
-      st->lu_ok_ig = luok;
+      if (!DEFER_LU) st->lu_ok_ig = luok;
       st->ig_updates += updated;
     } else {
       st->rank_pc = rank;
-      st->lu_ok_pc = luok;
+      if (!DEFER_LU) st->lu_ok_pc = luok;
       st->pc_updates += updated;
     }
     if (I.hist && step_no <= I.hist_cap) {
@@ -1011,3 +1029,11 @@ __device__ __forceinline__ void rom_core(const Inst &I, const RomDev &R, const R
   }
 }
 
+// The deferred LU of rom_core<., true> and its flag (every thread calls).
+__device__ __forceinline__ void rom_core_lu(const Inst &I, const RomDev &R, int z, RomSmem &sm) {
+  const int luok = isvd_lu(R, sm);
+  if (threadIdx.x == 0) {
+    if (z == 0) I.st->lu_ok_ig = luok;
+    else I.st->lu_ok_pc = luok;
+  }
+}

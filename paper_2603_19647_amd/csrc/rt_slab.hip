@@ -617,16 +617,18 @@ __global__ void __launch_bounds__(MAXT) k_fpass_pair(const Inst *__restrict__ in
 
 // ---------------------------------------------------------------------------
 // k_tail_coop: everything after the SI solve of a problem marched on its own,
-// in one cooperative launch of max(2 + min(npair, 32), 4 nbp) workgroups of
-// TAIL_NT threads, nbp = nc / TAIL_NT rounded up (up to eight cells per
-// thread for the f-pass scans: no register spills):
+// in one launch of 2 + max(min(npair, 32), 4 nbp) workgroups of TAIL_NT
+// threads, nbp = nc / TAIL_NT rounded up (up to eight cells per thread for
+// the f-pass scans: no register spills), waiting for each other at grid
+// barriers:
 //   1. the ROM projection passes (two: the second Gram-Schmidt step is
 //      applied by the rotation), each ROM on its own nbp workgroups (one
 //      cell per thread; the partial rows are exchanged coherently);
 //   2. workgroups 0 and 1 run the IG and PC cores (App. B) while the others
 //      run the f-pass, ordinate pairs dealt round-robin;
-//   3. the basis rotation, U and W of each ROM on their own nbp workgroups,
-//      and the pair sum of b~, by cells.
+//   3. workgroups 0 and 1 factorise the reduced operators while the others
+//      rotate the bases (U and W of each ROM on their own nbp workgroups) and
+//      form b~ (the pairs' sum), by cells.
 // The decisions were taken by the SI kernel (RomWork.nblk = nbp).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void publish_pend(RomPend *P) {
@@ -676,14 +678,15 @@ __global__ void __launch_bounds__(MAXT) k_tail_coop(const Inst *__restrict__ ins
     if (zs == 1 && act1) rom_pass2<true>(I, I.pc, Wp, gb, nbp, red, out, av, sm.scratch);
     grid_sync(cs);
   }
-  // 2. cores on workgroups 0 and 1, f-pass on the others
+  // 2. cores on workgroups 0 and 1 (all but the LU of A_r), f-pass on the
+  // others
   if (g < 2) {
     if (g == 0 && act0) {
-      rom_core<true>(I, I.ig, Wi, 0, sm);
+      rom_core<true, true>(I, I.ig, Wi, 0, sm);
       publish_pend(I.ig.pend);
     }
     if (g == 1 && act1) {
-      rom_core<true>(I, I.pc, Wp, 1, sm);
+      rom_core<true, true>(I, I.pc, Wp, 1, sm);
       publish_pend(I.pc.pend);
     }
   } else {
@@ -694,10 +697,14 @@ __global__ void __launch_bounds__(MAXT) k_tail_coop(const Inst *__restrict__ ins
       fpass_one_pair<CMAX, true>(I, p, c0, n, ct, Gs, srcc, 0, slots, parity);
   }
   grid_sync(cs);
-  // 3. rotation: matrix mat of ROM z on workgroups [s*nbp, s*nbp + nbp) with
-  // s = z for U (the workgroups that wrote p there) and s = 2 + z for W
-  if (rom && zs < 4) {
-    const int z = zs & 1, mat = zs >> 1;
+  // 3. workgroups 0 and 1 factorise A_r; the others rotate the bases (matrix
+  // mat of ROM z on workgroups 2 + [s*nbp, s*nbp + nbp), s = 2*mat + z) and
+  // form b~
+  if (g == 0 && act0) rom_core_lu(I, I.ig, 0, sm);
+  if (g == 1 && act1) rom_core_lu(I, I.pc, 1, sm);
+  const int zr = g >= 2 ? (g - 2) / nbp : 4, gr = g >= 2 ? g - 2 - zr * nbp : 0;
+  if (rom && zr < 4) {
+    const int z = zr & 1, mat = zr >> 1;
     const RomDev &R = z ? I.pc : I.ig;
     RomPend *P = R.pend;
     if (xload(&P->pending)) {  // uniform
@@ -706,7 +713,7 @@ __global__ void __launch_bounds__(MAXT) k_tail_coop(const Inst *__restrict__ ins
       if (threadIdx.x < RT_RMAX) a2s[threadIdx.x] = xload(&P->a2[threadIdx.x]);
       __syncthreads();
       const int r = xload(&P->r_old), k = xload(&P->k);
-      const int c = gb * NT + threadIdx.x;
+      const int c = gr * NT + threadIdx.x;
       if (c < nc) {
         const RomWork &W = z ? Wp : Wi;
         double *X = mat ? R.W : R.U;
@@ -718,15 +725,16 @@ __global__ void __launch_bounds__(MAXT) k_tail_coop(const Inst *__restrict__ ins
           const double v = X[(size_t)q * I.ld + c];
           old[0][q] = q < r ? v : 0.0;
         }
-        // the new direction (v - U a2) / nu for U, b for W
-        e[0] = mat ? xload(W.b + c) : second_residual(W.p[c], old[0], a2s) * xload(&P->inv_nu);
+        // the new direction (v - U a2) / nu for U, b for W (both written by
+        // other workgroups: coherent loads)
+        e[0] = mat ? xload(W.b + c) : second_residual(xload(W.p + c), old[0], a2s) * xload(&P->inv_nu);
         rotate_block<1>(old, e, cc, r, k, X, I.ld, cv, ok);
       }
     }
   }
-  // b~: the pairs' moments in pair order, by cells c = g*NT + t
-  const int c = g * NT + threadIdx.x;
-  if (c < nc) {
+  // b~: the pairs' moments in pair order, by cells c = (g - 2)*NT + t
+  const int c = (g - 2) * NT + threadIdx.x;
+  if (g >= 2 && c < nc) {
     // eight loads in flight per batch (clamped, masked)
     double acc = 0.0;
     const double *part = I.fpart + c;
@@ -838,7 +846,7 @@ extern "C" hipError_t rt_launch_slab_si_coop(const Inst *dinst, int ng, int nthr
 }
 
 static int tail_grid(int npair, int nc) {
-  return std::max(2 + std::min(npair, 32), 4 * ((nc + TAIL_NT - 1) / TAIL_NT));
+  return 2 + std::max(std::min(npair, 32), 4 * ((nc + TAIL_NT - 1) / TAIL_NT));
 }
 
 // Whether the device holds all workgroups of the SI kernel (ng x nthreads)
