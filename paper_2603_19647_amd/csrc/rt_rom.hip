@@ -81,9 +81,9 @@ __global__ void __launch_bounds__(256) k_rom_core(const Inst *__restrict__ insts
 // ---------------------------------------------------------------------------
 // k_rom_post_small: the whole incremental-SVD update but the rotation for a
 // small instance (the slab path, whose SI kernel already took the step's
-// decisions), one workgroup per (instance, ROM): the three passes with
+// decisions), one workgroup per (instance, ROM): the two passes with
 // workgroup reductions (one partial row), then the core.  One launch instead
-// of four, and no grid-wide partial sums.
+// of three, and no grid-wide partial sums.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_rom_post_small(const Inst *__restrict__ insts) {
   const Inst &I = insts[blockIdx.x];
