@@ -278,12 +278,17 @@ static void slab_groups(const rtrom_problem_desc *d, int nv, int *ng, int *pg) {
   *ng = (npair + *pg - 1) / *pg;
 }
 
+// Partial-sum rows of each ROM's projection passes: 2D instances use
+// 256-cell blocks, the cooperative 1D passes blocks of 64 cells per wave pair
+// (at least 64 cells).
+static size_t part_rows(int dim, size_t nc) { return dim == 1 ? (nc + 63) / 64 : (nc + 255) / 256; }
+
 static size_t slab_bytes(const rtrom_problem_desc *d, int nv) {
   const size_t nc = (size_t)d->nx * d->ny;
   const size_t ld = (nc + 31) & ~size_t(31);
   Layout L;
   for (int k = 0; k < 13; ++k) L.take(nc * 8);
-  L.take(4 * nc * 8);
+  L.take(5 * nc * 8);
   L.take((size_t)nv * 8 * 6);
   if (d->dim == 1) {  // 2D keeps its folded f in the plane buffers
     L.take((size_t)nv * nc * 8);
@@ -306,7 +311,7 @@ static size_t slab_bytes(const rtrom_problem_desc *d, int nv) {
     L.take(RT_RMAX * 4);
     L.take(sizeof(RomPend));
     L.take(sizeof(RomWork));
-    L.take(3 * ((nc + 255) / 256) * RT_NPART * 8);
+    L.take(3 * part_rows(d->dim, nc) * RT_NPART * 8);
   }
   L.take(sizeof(RtState));
   L.take(sizeof(Inst));
@@ -424,7 +429,7 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   I.rho0 = D(nc * 8);
   I.rhalf = D(nc * 8);
   I.dpc = D(nc * 8);
-  I.work = D(4 * (size_t)nc * 8);
+  I.work = D(5 * (size_t)nc * 8);
   double *qbuf = D((size_t)nv * 8 * 6);
   I.f = d->dim == 1 ? D((size_t)nv * nc * 8) : nullptr;
   I.fpart = d->dim == 1 ? D((size_t)(nv / 2) * nc * 8) : nullptr;
@@ -447,7 +452,7 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
     roms[r]->pend = (RomPend *)D(sizeof(RomPend));
     roms[r]->work = (RomWork *)D(sizeof(RomWork));
     {
-      const size_t nb = ((size_t)nc + 255) / 256;
+      const size_t nb = part_rows(d->dim, nc);
       double *parts = D(3 * nb * RT_NPART * 8);
       RomWork wk;
       memset(&wk, 0, sizeof(wk));
@@ -614,8 +619,9 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps, int n, int nsteps) 
     // SI solve waits for both.
     hipStream_t s2 = any_rom ? ps[0]->aux_stream : s;
     // A problem marched on its own with pair groups runs each step as two
-    // cooperative launches: the SI solve, then everything else (ROM passes,
-    // cores alongside the f-pass, rotation, b~).
+    // cooperative launches: the SI solve with the ROM decisions and
+    // projection passes, then everything else (cores alongside the f-pass,
+    // LU alongside the rotation and b~).
     const bool coop = n == 1 && ps[0]->hinst.ng > 1;
     for (int k = 0; k < nsteps && coop; ++k) {
       rt_prof_begin(RT_K_SLAB_SI, s);

@@ -37,7 +37,7 @@ struct RomWork {
   int active;    // this ROM takes a snapshot this step
   int truncate;  // truncated update (phases 2/3) vs untruncated construction
   int r;         // rank before the update
-  int nblk;      // 256-cell blocks of the instance
+  int nblk;      // pass blocks (partial rows) of this step's passes
   long long step_no;
   double eps;
   const double *x, *b;  // snapshot pair (global)
@@ -111,7 +111,7 @@ struct Inst {
   double *bt2[2];   // b~ double buffer: the next step reads bt2[steps & 1]
                     // and its f-pass writes the other one
   double *rho0, *rhalf, *dpc;  // IG, rho^{(1/2)}, PC correction of the step
-  double *work;     // [4][nc] scratch
+  double *work;     // [5][nc] scratch: PC right-hand side, PC residual, PC x, PC b, IG residual
   RomDev ig, pc;
   RtState *st;
   RtStepRec *hist;
@@ -318,12 +318,15 @@ __device__ __forceinline__ void wg_scan2(R Af, R Bf, R Ab, R Bb, R gF, R gB, R &
 
 // ---------------------------------------------------------------------------
 // Cooperative execution: exchange through agent-scope relaxed atomics (no
-// cache maintenance needed) and a grid barrier on monotone counters.
-// bar[0] counts arrivals, bar[1] is the last released generation and bar[2]
-// the generations completed by earlier launches, so nothing is reset between
-// launches; each kernel (one grid size) has its own three counters.  Every workgroup passes the same barriers (identical control
-// flow).  A wait is bounded: one that gives up sets the state's fault flag
-// and falls through (the host reports the step as failed) instead of hanging.
+// cache maintenance needed) and a grid barrier on a monotone counter.
+// bar[0] counts arrivals and bar[2] holds the generations completed by
+// earlier launches, so nothing is reset between launches; each kernel (one
+// grid size) has its own counters.  Every workgroup passes the same barriers
+// (identical control flow).  Generation g is complete once bar[0] reaches
+// g * gridDim.x; a waiter polls that counter alone and looks at the fault
+// flag only every 256 polls.  A wait is bounded (2^22 polls, seconds): one
+// that gives up sets the state's fault flag and falls through (the host
+// reports the step as failed) instead of hanging.
 // ---------------------------------------------------------------------------
 struct CoopSync {
   unsigned long long *bar;
@@ -356,20 +359,20 @@ __device__ __forceinline__ void grid_sync(CoopSync &S) {
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's exchange stores are complete
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned long long nb = gridDim.x;
+    const unsigned long long target = S.gen * gridDim.x;
     const unsigned long long prev =
         __hip_atomic_fetch_add(&S.bar[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (prev + 1 == S.gen * nb) {
-      __hip_atomic_store(&S.bar[1], S.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      // after a fault the counters are out of step: no further waiting
-      unsigned spins = 0;
-      while (__hip_atomic_load(&S.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < S.gen &&
-             !__hip_atomic_load(S.fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+    if (prev + 1 != target) {
+      for (unsigned spins = 1;; ++spins) {
+        if (__hip_atomic_load(&S.bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
         __builtin_amdgcn_s_sleep(1);
-        if (++spins == (1u << 26)) {
-          __hip_atomic_store(S.fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
+        if ((spins & 255u) == 0) {
+          // after a fault the counters are out of step: no further waiting
+          if (__hip_atomic_load(S.fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+          if (spins >= (1u << 22)) {
+            __hip_atomic_store(S.fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
         }
       }
     }

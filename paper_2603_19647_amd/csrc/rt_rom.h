@@ -185,9 +185,6 @@ __device__ inline int lu_factor_wave(double *A, int *perm_lds, int n, double *LU
   return bad;
 }
 
-// Solve A_r c = vec in place (vec in LDS) with the factors of lu_factor_wave,
-// by wave 0: lane i holds row i of the factors; forward and back
-// substitution broadcast one solved component per step.
 // out[k] = sum over blocks b < nb of part[b * RT_NPART + k], k < ncol.  The
 // blocks of a column are split into RT_SUMJ interleaved strands, each summed
 // in block order, and the strands are then added in order: a fixed order, so
@@ -225,6 +222,10 @@ __device__ inline void sum_partials(const double *part, int nb, int ncol, double
   }
 }
 
+// Solve A_r c = vec in place (vec in LDS) with the factors of lu_factor_wave
+// (global or LDS), by wave 0: lane i holds row i of the factors; forward and
+// back substitution broadcast one solved component per step, the back
+// substitution multiplying by the pivots' reciprocals.
 __device__ inline void lu_solve_wave(const double *LU, const int *perm, int n, double *vec) {
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
@@ -239,6 +240,8 @@ __device__ inline void lu_solve_wave(const double *LU, const int *perm, int n, d
       row[j] = (mine && j < n) ? v : 0.0;
     }
     const double b = vec[perm[li]];
+    // every lane inverts its own pivot at once, off the substitution chain
+    const double rpiv = mine ? 1.0 / LU[li * RT_RMAX + li] : 0.0;
     double s = mine ? b : 0.0;
     // forward substitution (unit lower factor): component j is final on lane j
 #pragma unroll
@@ -249,7 +252,7 @@ __device__ inline void lu_solve_wave(const double *LU, const int *perm, int n, d
 #pragma unroll
     for (int j = RT_RMAX - 1; j >= 0; --j) {
       if (j < n) {
-        const double xj = lane_read(s, j) / lane_read(row[j], j);
+        const double xj = lane_read(s, j) * lane_read(rpiv, j);
         if (lane == j) s = xj;
         if (lane < j) s = rt_fma(-row[j], xj, s);
       }
@@ -795,12 +798,43 @@ __device__ __forceinline__ void rom_norm_parts(const Inst &I, int c0, int stride
 }
 
 // ---------------------------------------------------------------------------
-// End-of-step bookkeeping and, for the ROM method, the error indicators
-// (Sec. 3.2, normalised by ||rho^n||_2) and Alg. 2's decisions on which ROM
-// takes a snapshot this step.  vec holds the three sums above (read only
-// for a ROM instance whose IG ROM exists); nb is the number of pass blocks
-// the ROM work will use.  Called by every thread of one workgroup after the
-// step's state is final; thread 0 writes.
+// Alg. 2's decisions for a ROM instance from the error indicators (Sec. 3.2,
+// normalised by ||rho^n||_2): which ROM takes a snapshot this step and
+// whether it is truncated.  vec holds ||rho^n||^2, ||rho^(0) - rho^n||^2 and
+// ||dpc - (rho^n - rho^(1/2))||^2 (read only when the IG ROM exists).  Pure:
+// the workgroups of a cooperative launch call it on identical data.
+// ---------------------------------------------------------------------------
+struct RomPlan {
+  int ig_on, ig_trunc, pc_on, pc_trunc;
+  double e_ig, e_pc;
+};
+__device__ __forceinline__ RomPlan rom_plan(const Inst &I, int flag_ig, int flag_pc, int used_pc, int iters,
+                                            const double *vec) {
+  RomPlan P{0, 0, 0, 0, -1.0, -1.0};
+  const double rn = flag_ig ? sqrt(vec[0]) : 0.0;
+  const double scale = (I.abs_up || rn == 0.0) ? 1.0 : 1.0 / rn;
+  if (!flag_ig) {
+    P.ig_on = 1;  // phase 1: untruncated snapshot (rho^n, b~^{n-1})
+  } else {
+    P.e_ig = sqrt(vec[1]) * scale;
+    P.ig_on = P.ig_trunc = P.e_ig > I.eps_up;
+    if (iters > 1) {  // no correction snapshot when the step converged at l = 1
+      if (!flag_pc) {
+        P.pc_on = 1;
+      } else {
+        if (used_pc) P.e_pc = sqrt(vec[2]) * scale;
+        P.pc_on = P.pc_trunc = P.ig_on || !used_pc || P.e_pc > I.eps_up;
+      }
+    }
+  }
+  return P;
+}
+
+// ---------------------------------------------------------------------------
+// End-of-step bookkeeping and, for the ROM method, the decisions of rom_plan
+// written to the ROMs' work records.  vec: as for rom_plan; nb is the number
+// of pass blocks the ROM work will use.  Called by every thread of one
+// workgroup after the step's state is final; thread 0 writes.
 // ---------------------------------------------------------------------------
 __device__ inline void rom_decide(const Inst &I, const double *vec, int nb) {
   RtState *st = I.st;
@@ -808,24 +842,10 @@ __device__ inline void rom_decide(const Inst &I, const double *vec, int nb) {
   const long long step_no = st->steps + 1;
   double e_ig = -1.0, e_pc = -1.0;
   if (I.method == RT_ROM) {
-    const int flag_ig = st->flag_ig, flag_pc = st->flag_pc, used_pc = st->used_pc;
-    const double rn = flag_ig ? sqrt(vec[0]) : 0.0;
-    const double scale = (I.abs_up || rn == 0.0) ? 1.0 : 1.0 / rn;
-    int ig_on = 0, ig_trunc = 0, pc_on = 0, pc_trunc = 0;
-    if (!flag_ig) {
-      ig_on = 1;  // phase 1: untruncated snapshot (rho^n, b~^{n-1})
-    } else {
-      e_ig = sqrt(vec[1]) * scale;
-      ig_on = ig_trunc = e_ig > I.eps_up;
-      if (iters > 1) {  // no correction snapshot when the step converged at l = 1
-        if (!flag_pc) {
-          pc_on = 1;
-        } else {
-          if (used_pc) e_pc = sqrt(vec[2]) * scale;
-          pc_on = pc_trunc = ig_on || !used_pc || e_pc > I.eps_up;
-        }
-      }
-    }
+    const RomPlan P = rom_plan(I, st->flag_ig, st->flag_pc, st->used_pc, iters, vec);
+    const int ig_on = P.ig_on, ig_trunc = P.ig_trunc, pc_on = P.pc_on, pc_trunc = P.pc_trunc;
+    e_ig = P.e_ig;
+    e_pc = P.e_pc;
     if (threadIdx.x == 0) {
       RomWork &wi = *I.ig.work;
       wi.active = ig_on;
@@ -836,7 +856,11 @@ __device__ inline void rom_decide(const Inst &I, const double *vec, int nb) {
       wi.eps = I.eps_ig;
       wi.x = I.rho;
       wi.b = I.bt2[st->cur];
-      wi.p = I.work;
+      // its own row: the cooperative SI kernel stores the PC right-hand side
+      // in row 0 with plain stores (cached per XCD) and this residual with
+      // agent-scope stores in the same launch, and the two must not share
+      // addresses
+      wi.p = I.work + 4 * (size_t)I.nc;
       RomWork &wp = *I.pc.work;
       wp.active = pc_on;
       wp.truncate = pc_trunc;

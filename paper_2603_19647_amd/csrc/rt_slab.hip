@@ -128,7 +128,10 @@ __device__ __forceinline__ void sweep_moment(const Inst &I, const R (&ct)[CMAX],
 // and the expanded vector are exchanged like the sweep moments.  out is
 // written with agent-scope stores; read it with xload.
 __device__ inline void rom_apply_coop(const Inst &I, const RomDev &R, int rank, const double *rhs, double *out,
-                                      double *red, double *vec, CoopSync &cs) {
+                                      double *red, double *vec, double *luS, int *permS, CoopSync &cs) {
+  // the LU factors go to LDS first: their loads overlap the projection
+  for (int e = threadIdx.x; e < RT_RMAX * RT_RMAX; e += blockDim.x) luS[e] = R.LU[e];
+  if ((int)threadIdx.x < RT_RMAX) permS[threadIdx.x] = R.perm[threadIdx.x];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int nc = I.nc, ng = I.ng, ld = I.ld, NT = blockDim.x;
   const int csz = (nc + ng - 1) / ng;
@@ -190,33 +193,226 @@ __device__ inline void rom_apply_coop(const Inst &I, const RomDev &R, int rank, 
   if ((int)threadIdx.x < RT_RMAX) {
     double sv = 0.0;
     if ((int)threadIdx.x < rank) {
-      // groups in order, eight loads in flight per batch (clamped, masked)
-      for (int g0 = 0; g0 < ng; g0 += 8) {
-        double v[8];
+      // groups in order, sixteen loads in flight per batch (clamped, masked)
+      for (int g0 = 0; g0 < ng; g0 += 16) {
+        double v[16];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = xload(&apx[(size_t)min(g0 + q, ng - 1) * RT_RMAX + threadIdx.x]);
+        for (int q = 0; q < 16; ++q) v[q] = xload(&apx[(size_t)min(g0 + q, ng - 1) * RT_RMAX + threadIdx.x]);
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
+        for (int q = 0; q < 16; ++q)
           if (g0 + q < ng) sv += v[q];
       }
     }
     vec[threadIdx.x] = sv;  // zero past the rank
   }
   __syncthreads();
-  lu_solve_wave(R.LU, R.perm, rank, vec);
-  for (int c = lo + (int)threadIdx.x; c < hi; c += NT) {
-    double v = 0.0;
-#pragma unroll 1
-    for (int k0 = 0; k0 < RT_RMAX; k0 += 10) {
-      double u[10];
+  lu_solve_wave(luS, permS, rank, vec);
+  // expansion: four lanes of a quad per cell, five columns each (all loads
+  // in flight at once), the quad's partial sums added in a fixed order
+  static_assert(RT_RMAX == 20, "four quarters of five columns");
+  {
+    const int q4 = threadIdx.x & 3, k0 = 5 * q4;
+    double y5[5];
 #pragma unroll
-      for (int q = 0; q < 10; ++q) u[q] = R.U[(size_t)(k0 + q) * ld + c];
+    for (int q = 0; q < 5; ++q) y5[q] = vec[k0 + q];
+    for (int cb = lo; cb < hi; cb += NT / 4) {
+      const int c = cb + (int)(threadIdx.x >> 2);
+      const int cc = min(c, hi - 1);
+      double u[5];
 #pragma unroll
-      for (int q = 0; q < 10; ++q) v = rt_fma(u[q], vec[k0 + q], v);
+      for (int q = 0; q < 5; ++q) u[q] = R.U[(size_t)(k0 + q) * ld + cc];
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) v = rt_fma(u[q], y5[q], v);
+      v = QuadSum()(v);
+      if (q4 == 0 && c < hi) xstore(&out[c], v);
     }
-    xstore(&out[c], v);
   }
   grid_sync(cs);
+}
+
+// ---------------------------------------------------------------------------
+// The incremental SVD's two projection passes (App. B: classical
+// Gram-Schmidt applied twice; the rotation applies the second step's
+// correction) run at the end of the cooperative SI kernel, so the step tail
+// starts with the small dense cores.  Unit (z, blk): ROM z over the cells
+// [blk*H, blk*H + H), H = 64*hw cells with hw = nw/2 waves per half; the
+// units are dealt over the ng workgroups.  The first hw waves take basis
+// columns 0..9 of the block's cells, the next hw waves columns 10..19 (a
+// wave past 2*hw idles), so a thread keeps 22 partial sums: the 1024-thread
+// kernel's register budget.  A one-wave workgroup (hw = 0, H = 64) takes the
+// two halves in turn.  Row blk of part1 / part2 gets the same sums as
+// rom_pass1 / rom_pass2 (layout [U^T x | U^T b | x.x | x.b] and
+// [U^T v | W^T v | v.v | v.b]), stored with agent-scope atomics.
+// ---------------------------------------------------------------------------
+constexpr int PASS_COLS = RT_RMAX / 2;
+constexpr int PASS_NACC = 2 * PASS_COLS + 2;
+
+struct PassGeom {
+  int hw;   // waves per half (0: one wave takes both halves)
+  int H;    // cells per block
+  int h;    // this thread's half (2: idle), when hw > 0
+  int cl;   // this thread's cell in the block
+  int nit;  // halves per thread: 1, or 2 when hw = 0
+};
+__device__ __forceinline__ PassGeom pass_geom() {
+  const int hw = (int)(blockDim.x >> 7), wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (hw == 0) return {0, 64, 0, lane, 2};
+  const int h = min(2, wave / hw);
+  return {hw, 64 * hw, h, (wave - h * hw) * 64 + lane, 1};
+}
+__host__ __device__ inline int coop_pass_blocks(int nc, int nthr) {
+  const int H = 64 * (nthr >= 128 ? nthr / 128 : 1);
+  return (nc + H - 1) / H;
+}
+
+// one half's accumulators: the four 16-lane row sums of each (DPP) into slot
+// vw of red (4 * PASS_NACC doubles per slot)
+__device__ __forceinline__ void pass_wave_sums(const double (&acc)[PASS_NACC], int vw, double *red) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < PASS_NACC; ++k) {
+    const double t = row16_sum(acc[k]);
+    if ((lane & 15) == 0) red[(vw * 4 + (lane >> 4)) * PASS_NACC + k] = t;
+  }
+}
+// Row blk of part: entry k of the 2R+2 sums is the sum over its half's slots
+// and their rows (in order) of that half's accumulator.
+__device__ __forceinline__ void pass_rows(int hw, double *red, double *part, int blk) {
+  __syncthreads();
+  const int k = threadIdx.x, nv = 4 * max(hw, 1);
+  if (k < 2 * RT_RMAX + 2) {
+    int hh, ai;
+    if (k < 2 * RT_RMAX) {
+      const int j = k % RT_RMAX;  // column
+      hh = j / PASS_COLS;
+      ai = (k < RT_RMAX ? 0 : PASS_COLS) + j % PASS_COLS;
+    } else {
+      hh = 0;
+      ai = 2 * PASS_COLS + (k - 2 * RT_RMAX);
+    }
+    double s = 0.0;
+    for (int w = hh * nv; w < hh * nv + nv; ++w) s += red[w * PASS_NACC + ai];
+    xstore(&part[blk * RT_NPART + k], s);
+  }
+  __syncthreads();
+}
+// columns k0..k0+9 of X at cell cc, zero past the rank or outside the block
+__device__ __forceinline__ void pass_cols(const double *X, int ld, int cc, int k0, bool in, int rank,
+                                          double (&u)[PASS_COLS]) {
+#pragma unroll
+  for (int q = 0; q < PASS_COLS; ++q) {
+    const double v = X[(size_t)(k0 + q) * ld + cc];
+    u[q] = (in && k0 + q < rank) ? v : 0.0;
+  }
+}
+
+// Pass 1 of unit (z, blk): U^T x, U^T b, x.x, x.b of ROM z's snapshot pair
+// (IG: x = rho^n, b = b~^{n-1}; PC: x = rho^n - rho^(1/2), b = rho^(1/2) -
+// rho^(0), eq. correction_snapshot, also stored for pass 2 and the rotation).
+// rho^n and rho^(1/2) were written by this workgroup; rho^(0) by any.
+__device__ inline void coop_pass1(const Inst &I, int z, int blk, int rank, const double *bt, double *red) {
+  const PassGeom G = pass_geom();
+  const int nc = I.nc, ld = I.ld;
+  const int c = blk * G.H + G.cl;
+  const bool in = G.h < 2 && c < nc;
+  const int cc = min(c, nc - 1);
+  const RomDev &R = z ? I.pc : I.ig;
+  double xv, bv;
+  if (z == 0) {
+    xv = I.rho[cc];
+    bv = bt[cc];
+  } else {
+    const double rh = I.rhalf[cc];
+    xv = I.rho[cc] - rh;
+    bv = rh - xload(&I.rho0[cc]);
+    if (in && G.h == 0) {
+      xstore(I.work + 2 * (size_t)nc + c, xv);
+      xstore(I.work + 3 * (size_t)nc + c, bv);
+    }
+  }
+  if (!in) xv = bv = 0.0;
+  for (int i = 0; i < G.nit; ++i) {
+    const int hh = G.hw ? min(G.h, 1) : i;
+    double u[PASS_COLS], acc[PASS_NACC];
+    pass_cols(R.U, ld, cc, hh * PASS_COLS, in, rank, u);
+#pragma unroll
+    for (int q = 0; q < PASS_COLS; ++q) {
+      acc[q] = u[q] * xv;
+      acc[PASS_COLS + q] = u[q] * bv;
+    }
+    acc[2 * PASS_COLS] = xv * xv;
+    acc[2 * PASS_COLS + 1] = xv * bv;
+    pass_wave_sums(acc, G.hw ? (int)(threadIdx.x >> 6) : i, red);
+  }
+  pass_rows(G.hw, red, R.work->part1, blk);
+}
+
+// Pass 2 of unit (z, blk): v = x - U a1 (a1 = U^T x from pass 1's rows,
+// columns in order), stored as the ROM's projected residual, and U^T v,
+// W^T v, v.v, v.b.  The loads are issued before a1 is summed.  scr:
+// blockDim doubles of LDS.
+__device__ inline void coop_pass2(const Inst &I, int z, int blk, int nb, int rank, const double *bt, double *red,
+                                  double *av, double *scr) {
+  const PassGeom G = pass_geom();
+  const int nc = I.nc, ld = I.ld;
+  const RomDev &R = z ? I.pc : I.ig;
+  const int c = blk * G.H + G.cl;
+  const bool in = G.h < 2 && c < nc;
+  const int cc = min(c, nc - 1);
+  double xv = z ? xload(I.work + 2 * (size_t)nc + cc) : I.rho[cc];
+  double bv = z ? xload(I.work + 3 * (size_t)nc + cc) : bt[cc];
+  if (!in) xv = bv = 0.0;
+  const int kh = min(G.h, 1) * PASS_COLS;
+  double u[PASS_COLS], w[PASS_COLS];
+  if (G.hw) {
+    pass_cols(R.U, ld, cc, kh, in, rank, u);
+    pass_cols(R.W, ld, cc, kh, in, rank, w);
+  }
+  sum_partials<true>(R.work->part1, nb, RT_RMAX, av, scr);  // zero past the rank
+  // v = x - sum_k u_k a1_k, columns in order (the second half continues
+  // from the first half's value)
+  double v = xv;
+  if (G.hw) {
+    if (G.h == 0) {
+#pragma unroll
+      for (int q = 0; q < PASS_COLS; ++q) v = rt_fma(-u[q], av[q], v);
+      scr[G.cl] = v;
+    }
+    __syncthreads();
+    if (G.h == 1) {
+      v = scr[G.cl];
+#pragma unroll
+      for (int q = 0; q < PASS_COLS; ++q) v = rt_fma(-u[q], av[PASS_COLS + q], v);
+      scr[G.cl] = v;
+    }
+    __syncthreads();
+    v = G.h < 2 ? scr[G.cl] : 0.0;
+  } else {
+    for (int hh = 0; hh < 2; ++hh) {
+      pass_cols(R.U, ld, cc, hh * PASS_COLS, in, rank, u);
+#pragma unroll
+      for (int q = 0; q < PASS_COLS; ++q) v = rt_fma(-u[q], av[hh * PASS_COLS + q], v);
+    }
+  }
+  const double *p = I.work + (size_t)(z ? 1 : 4) * nc;  // as rom_decide sets RomWork.p
+  if (in && G.h == 0) xstore(const_cast<double *>(p) + c, v);  // first Gram-Schmidt residual
+  for (int i = 0; i < G.nit; ++i) {
+    if (!G.hw) {
+      pass_cols(R.U, ld, cc, i * PASS_COLS, in, rank, u);
+      pass_cols(R.W, ld, cc, i * PASS_COLS, in, rank, w);
+    }
+    double acc[PASS_NACC];
+#pragma unroll
+    for (int q = 0; q < PASS_COLS; ++q) {
+      acc[q] = u[q] * v;
+      acc[PASS_COLS + q] = w[q] * v;
+    }
+    acc[2 * PASS_COLS] = v * v;
+    acc[2 * PASS_COLS + 1] = v * bv;
+    pass_wave_sums(acc, G.hw ? (int)(threadIdx.x >> 6) : i, red);
+  }
+  pass_rows(G.hw, red, R.work->part2, blk);
 }
 
 // DSA correction (eq. rho_residual): solve C d = rhs with the precomputed
@@ -292,6 +488,8 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
   __shared__ double red[2 * RT_MAXWAVES];
   __shared__ double rred[RT_MAXWAVES * RT_RMAX];
   __shared__ double rvec[RT_RMAX + 4];
+  __shared__ double luS[COOP ? RT_RMAX * RT_RMAX : 1];
+  __shared__ int permS[COOP ? RT_RMAX : 1];
   const int NT = I.nthr, tid = threadIdx.x;
   const int nc = I.nc;
   const int C = (nc + NT - 1) / NT;
@@ -321,7 +519,7 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
   // initial guess: DMD when the IG ROM is available (eq. dmd-ig), else rho^{n-1}
   int ig_fb = 0;
   if (rom && flag_ig && lu_ig) {
-    if constexpr (COOP) rom_apply_coop(I, I.ig, rank_ig, bt, I.rho0, rred, rvec, cs);
+    if constexpr (COOP) rom_apply_coop(I, I.ig, rank_ig, bt, I.rho0, rred, rvec, luS, permS, cs);
     else rom_apply(I.ig, rank_ig, I.ld, nc, NT, bt, I.rho0, rred, rvec);
   } else {
     ig_fb = rom && flag_ig;
@@ -354,7 +552,7 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
       sweep_moment<CMAX, double, COOP>(I, ct, s, n, c0, acc, slots, parity, cs);
 #pragma unroll
       for (int t = 0; t < CMAX; ++t) y[t] = acc[t] + ((t < n) ? bt[c0 + t] : 0.0);
-      if (nsweep == 0 && leader) {
+      if (nsweep == 0) {  // COOP: every workgroup (the same values), for its passes
 #pragma unroll
         for (int t = 0; t < CMAX; ++t)
           if (t < n) I.rhalf[c0 + t] = y[t];
@@ -394,7 +592,7 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
       for (int t = 0; t < CMAX; ++t)
         if (t < n) I.work[c0 + t] = y[t] - rd(&I.rho0[c0 + t]);
       __syncthreads();
-      if constexpr (COOP) rom_apply_coop(I, I.pc, rank_pc, I.work, I.dpc, rred, rvec, cs);
+      if constexpr (COOP) rom_apply_coop(I, I.pc, rank_pc, I.work, I.dpc, rred, rvec, luS, permS, cs);
       else rom_apply(I.pc, rank_pc, I.ld, nc, NT, I.work, I.dpc, rred, rvec);
 #pragma unroll
       for (int t = 0; t < CMAX; ++t) d[t] = (t < n) ? rd(&I.dpc[c0 + t]) : 0.0;
@@ -432,12 +630,12 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
       need64 = 1;
     }
   }
-  if (!leader) return;
-  // rho^n = rho^{(l-1/2)} (Alg. 1 returns the un-corrected iterate)
+  // rho^n = rho^{(l-1/2)} (Alg. 1 returns the un-corrected iterate); COOP:
+  // every workgroup writes it (the same values), for its passes
 #pragma unroll
   for (int t = 0; t < CMAX; ++t)
     if (t < n) I.rho[c0 + t] = y[t];
-  if (tid == 0) {
+  if (leader && tid == 0) {
     st->iters = nsweep;
     st->conv = conv;
     st->used_pc = used_pc;
@@ -447,11 +645,11 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
     st->phase = !flag_ig ? 1 : (!flag_pc ? 2 : 3);
     st->cur = cur;
     st->fp32_sweeps += n32;
-    if constexpr (COOP) __hip_atomic_store(&I.bar[2], cs.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
   // end of step: error indicators from the final iterate and Alg. 2's
   // decisions, so the ROM work that follows needs no launch of its own
+  // (COOP: every workgroup computes the same sums and decisions)
   if (rom && flag_ig) {
     double part[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -466,8 +664,26 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
       }
     wg_sum_fast<3>(part, rred, rvec);
   }
-  // the cooperative tail's passes use one partial row per TAIL_NT cells
-  rom_decide(I, rvec, COOP ? (nc + TAIL_NT - 1) / TAIL_NT : I.post_nb);
+  const int nbp = COOP ? coop_pass_blocks(nc, NT) : I.post_nb;
+  if (leader) rom_decide(I, rvec, nbp);
+  if constexpr (COOP) {
+    // the snapshot projections of the ROMs that take one (units dealt over
+    // the workgroups), so the step tail starts with the cores
+    const RomPlan P = rom ? rom_plan(I, flag_ig, flag_pc, used_pc, nsweep, rvec) : RomPlan{0, 0, 0, 0, -1.0, -1.0};
+    if (P.ig_on || P.pc_on) {
+      __shared__ double pred[4 * RT_MAXWAVES * PASS_NACC], pav[RT_RMAX], pscr[MAXT];
+      for (int it = blockIdx.x; it < 2 * nbp; it += gridDim.x) {
+        const int z = it / nbp;
+        if (z ? P.pc_on : P.ig_on) coop_pass1(I, z, it - z * nbp, z ? rank_pc : rank_ig, bt, pred);
+      }
+      grid_sync(cs);
+      for (int it = blockIdx.x; it < 2 * nbp; it += gridDim.x) {
+        const int z = it / nbp;
+        if (z ? P.pc_on : P.ig_on) coop_pass2(I, z, it - z * nbp, nbp, z ? rank_pc : rank_ig, bt, pred, pav, pscr);
+      }
+    }
+    if (leader && tid == 0) __hip_atomic_store(&I.bar[2], cs.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -619,17 +835,15 @@ __global__ void __launch_bounds__(MAXT) k_fpass_pair(const Inst *__restrict__ in
 // k_tail_coop: everything after the SI solve of a problem marched on its own,
 // in one launch of 2 + max(min(npair, 32), 4 nbp) workgroups of TAIL_NT
 // threads, nbp = nc / TAIL_NT rounded up (up to eight cells per thread for
-// the f-pass scans: no register spills), waiting for each other at grid
-// barriers:
-//   1. the ROM projection passes (two: the second Gram-Schmidt step is
-//      applied by the rotation), each ROM on its own nbp workgroups (one
-//      cell per thread; the partial rows are exchanged coherently);
-//   2. workgroups 0 and 1 run the IG and PC cores (App. B) while the others
+// the f-pass scans: no register spills), waiting for each other at one grid
+// barrier:
+//   1. workgroups 0 and 1 run the IG and PC cores (App. B) while the others
 //      run the f-pass, ordinate pairs dealt round-robin;
-//   3. workgroups 0 and 1 factorise the reduced operators while the others
+//   2. workgroups 0 and 1 factorise the reduced operators while the others
 //      rotate the bases (U and W of each ROM on their own nbp workgroups) and
 //      form b~ (the pairs' sum), by cells.
-// The decisions were taken by the SI kernel (RomWork.nblk = nbp).
+// The SI kernel took the decisions and ran the projection passes (their
+// partial rows and the projected residuals are read coherently).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void publish_pend(RomPend *P) {
   // the rotation is read by workgroups on other XCDs: store it again with
@@ -655,7 +869,6 @@ __global__ void __launch_bounds__(MAXT) k_tail_coop(const Inst *__restrict__ ins
   RtState *st = I.st;
   if (xload(&st->fault)) return;
   __shared__ double slots[8 * RT_MAXWAVES];
-  __shared__ double red[RT_MAXWAVES * (2 * RT_RMAX + 2)], out[2 * RT_RMAX + 2], av[RT_RMAX];
   __shared__ double cc[RT_KC * RT_KC + 4], a2s[RT_RMAX];
   __shared__ RomSmem sm;
   // the tail's own barrier counters (the SI kernel's use another grid size)
@@ -667,18 +880,7 @@ __global__ void __launch_bounds__(MAXT) k_tail_coop(const Inst *__restrict__ ins
   const int rom = I.method == RT_ROM;
   const RomWork &Wi = *I.ig.work, &Wp = *I.pc.work;
   const int act0 = rom && Wi.active, act1 = rom && Wp.active;
-  // 1. projection passes: ROM z on workgroups [z*nbp, z*nbp + nbp), block
-  // gb = g - z*nbp of nbp taking cells gb*NT + t
-  const int zs = g / nbp, gb = g - zs * nbp;
-  if (act0 || act1) {
-    if (zs == 0 && act0) rom_pass1<true>(I, I.ig, Wi, 0, gb, nbp, red, out);
-    if (zs == 1 && act1) rom_pass1<true>(I, I.pc, Wp, 1, gb, nbp, red, out);
-    grid_sync(cs);
-    if (zs == 0 && act0) rom_pass2<true>(I, I.ig, Wi, gb, nbp, red, out, av, sm.scratch);
-    if (zs == 1 && act1) rom_pass2<true>(I, I.pc, Wp, gb, nbp, red, out, av, sm.scratch);
-    grid_sync(cs);
-  }
-  // 2. cores on workgroups 0 and 1 (all but the LU of A_r), f-pass on the
+  // 1. cores on workgroups 0 and 1 (all but the LU of A_r), f-pass on the
   // others
   if (g < 2) {
     if (g == 0 && act0) {
@@ -697,7 +899,7 @@ __global__ void __launch_bounds__(MAXT) k_tail_coop(const Inst *__restrict__ ins
       fpass_one_pair<CMAX, true>(I, p, c0, n, ct, Gs, srcc, 0, slots, parity);
   }
   grid_sync(cs);
-  // 3. workgroups 0 and 1 factorise A_r; the others rotate the bases (matrix
+  // 2. workgroups 0 and 1 factorise A_r; the others rotate the bases (matrix
   // mat of ROM z on workgroups 2 + [s*nbp, s*nbp + nbp), s = 2*mat + z) and
   // form b~
   if (g == 0 && act0) rom_core_lu(I, I.ig, 0, sm);
