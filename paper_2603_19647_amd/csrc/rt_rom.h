@@ -229,32 +229,29 @@ __device__ inline void sum_partials(const double *part, int nb, int ncol, double
 __device__ inline void lu_solve_wave(const double *LU, const int *perm, int n, double *vec) {
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
-    // every load is unconditional (clamped row), so they are all in flight
-    // at once; entries outside the n x n factors are masked to zero
     const int li = lane < RT_RMAX ? lane : RT_RMAX - 1;
     const bool mine = lane < n;
-    double row[RT_RMAX];
-#pragma unroll
-    for (int j = 0; j < RT_RMAX; ++j) {
-      const double v = LU[li * RT_RMAX + j];
-      row[j] = (mine && j < n) ? v : 0.0;
-    }
+    // the row is read element by element as the substitution reaches it
+    // (factors in LDS or cache): no register array of the whole row
+    const double *row = LU + li * RT_RMAX;
     const double b = vec[perm[li]];
     // every lane inverts its own pivot at once, off the substitution chain
-    const double rpiv = mine ? 1.0 / LU[li * RT_RMAX + li] : 0.0;
+    const double rpiv = mine ? 1.0 / row[li] : 0.0;
     double s = mine ? b : 0.0;
     // forward substitution (unit lower factor): component j is final on lane j
-#pragma unroll
+#pragma unroll 4
     for (int j = 0; j < RT_RMAX; ++j) {
       const double bj = lane_read(s, j);
-      if (lane > j) s = rt_fma(-row[j], bj, s);
+      const double l = row[j];
+      if (mine && lane > j && j < n) s = rt_fma(-l, bj, s);
     }
-#pragma unroll
+#pragma unroll 4
     for (int j = RT_RMAX - 1; j >= 0; --j) {
       if (j < n) {
+        const double u = row[j];
         const double xj = lane_read(s, j) * lane_read(rpiv, j);
         if (lane == j) s = xj;
-        if (lane < j) s = rt_fma(-row[j], xj, s);
+        if (mine && lane < j) s = rt_fma(-u, xj, s);
       }
     }
     // every lane read vec[perm[lane]] before any lane writes
@@ -830,41 +827,56 @@ __device__ __forceinline__ RomPlan rom_plan(const Inst &I, int flag_ig, int flag
   return P;
 }
 
+// What the end-of-step bookkeeping needs about the step just solved and the
+// state's counters as they were when it started.  The slab SI kernel fills it
+// from registers (no reloads of what it just wrote); step_in() reads it back
+// from the state for kernels that run after the solve.
+struct StepIn {
+  int iters, conv, used_pc, ig_fb, pc_fb, phase, cur;
+  int flag_ig, flag_pc, rank_ig, rank_pc, nonconv, fallbacks;
+  double residual;
+  long long steps, si_total, sweeps_total;
+};
+__device__ inline StepIn step_in(const RtState *st) {
+  return {st->iters,   st->conv,    st->used_pc, st->ig_fb,   st->pc_fb,    st->phase,    st->cur,
+          st->flag_ig, st->flag_pc, st->rank_ig, st->rank_pc, st->nonconv, st->fallbacks, st->residual,
+          st->steps,   st->si_total, st->sweeps_total};
+}
+
 // ---------------------------------------------------------------------------
 // End-of-step bookkeeping and, for the ROM method, the decisions of rom_plan
 // written to the ROMs' work records.  vec: as for rom_plan; nb is the number
 // of pass blocks the ROM work will use.  Called by every thread of one
 // workgroup after the step's state is final; thread 0 writes.
 // ---------------------------------------------------------------------------
-__device__ inline void rom_decide(const Inst &I, const double *vec, int nb) {
+__device__ inline void rom_decide(const Inst &I, const double *vec, int nb, const StepIn &S) {
   RtState *st = I.st;
-  const int iters = st->iters;
-  const long long step_no = st->steps + 1;
+  const int iters = S.iters;
+  const long long step_no = S.steps + 1;
   double e_ig = -1.0, e_pc = -1.0;
   if (I.method == RT_ROM) {
-    const RomPlan P = rom_plan(I, st->flag_ig, st->flag_pc, st->used_pc, iters, vec);
-    const int ig_on = P.ig_on, ig_trunc = P.ig_trunc, pc_on = P.pc_on, pc_trunc = P.pc_trunc;
+    const RomPlan P = rom_plan(I, S.flag_ig, S.flag_pc, S.used_pc, iters, vec);
     e_ig = P.e_ig;
     e_pc = P.e_pc;
     if (threadIdx.x == 0) {
       RomWork &wi = *I.ig.work;
-      wi.active = ig_on;
-      wi.truncate = ig_trunc;
-      wi.r = st->rank_ig;
+      wi.active = P.ig_on;
+      wi.truncate = P.ig_trunc;
+      wi.r = S.rank_ig;
       wi.nblk = nb;
       wi.step_no = step_no;
       wi.eps = I.eps_ig;
       wi.x = I.rho;
-      wi.b = I.bt2[st->cur];
+      wi.b = I.bt2[S.cur];
       // its own row: the cooperative SI kernel stores the PC right-hand side
       // in row 0 with plain stores (cached per XCD) and this residual with
       // agent-scope stores in the same launch, and the two must not share
       // addresses
       wi.p = I.work + 4 * (size_t)I.nc;
       RomWork &wp = *I.pc.work;
-      wp.active = pc_on;
-      wp.truncate = pc_trunc;
-      wp.r = st->rank_pc;
+      wp.active = P.pc_on;
+      wp.truncate = P.pc_trunc;
+      wp.r = S.rank_pc;
       wp.nblk = nb;
       wp.step_no = step_no;
       wp.eps = I.eps_pc;
@@ -877,26 +889,26 @@ __device__ inline void rom_decide(const Inst &I, const double *vec, int nb) {
     }
   }
   if (threadIdx.x == 0) {
-    const int fb = st->ig_fb + st->pc_fb;
+    const int fb = S.ig_fb + S.pc_fb;
     if (I.hist && step_no <= I.hist_cap) {
       RtStepRec &rec = I.hist[step_no - 1];
       rec.iters = iters;
-      rec.phase = st->phase;
-      rec.converged = st->conv;
+      rec.phase = S.phase;
+      rec.converged = S.conv;
       rec.ig_update = 0;
       rec.pc_update = 0;
-      rec.rank_ig = st->rank_ig;
-      rec.rank_pc = st->rank_pc;
+      rec.rank_ig = S.rank_ig;
+      rec.rank_pc = S.rank_pc;
       rec.fallback = fb > 0;
       rec.e_ig = e_ig;
       rec.e_pc = e_pc;
-      rec.residual = st->residual;
+      rec.residual = S.residual;
     }
-    st->fallbacks += fb;
+    st->fallbacks = S.fallbacks + fb;
     st->steps = step_no;
-    st->si_total += iters;
-    st->sweeps_total += iters + 2;
-    st->nonconv += !st->conv;
+    st->si_total = S.si_total + iters;
+    st->sweeps_total = S.sweeps_total + iters + 2;
+    st->nonconv = S.nonconv + !S.conv;
   }
 }
 

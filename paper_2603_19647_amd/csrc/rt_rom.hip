@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(256) k_rom_decide(const Inst *__restrict__ ins
   __shared__ double scratch[256], vec[4];
   const int nb = pass_blocks(I.nc);
   if (I.method == RT_ROM && I.st->flag_ig) sum_partials<false>(I.ig.work->part3, nb, 3, vec, scratch);
-  rom_decide(I, vec, I.post_nb);
+  rom_decide(I, vec, I.post_nb, step_in(I.st));
 }
 
 __global__ void __launch_bounds__(BLK) k_rom_pass1(const Inst *__restrict__ insts) {

@@ -502,15 +502,20 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
   const int lu_ig = st->lu_ok_ig, lu_pc = st->lu_ok_pc;
   const int rank_ig = st->rank_ig, rank_pc = st->rank_pc;
   const int mixed = (I.precision == RT_MIXED);
-  const int cur = (int)(st->steps & 1);
+  // counters as the step starts (the end-of-step bookkeeping adds to them
+  // without reading back what this launch writes)
+  const long long steps0 = st->steps, si0 = st->si_total, sw0 = st->sweeps_total, f32_0 = st->fp32_sweeps;
+  const int nonconv0 = st->nonconv, fb0 = st->fallbacks;
+  const int cur = (int)(steps0 & 1);
   const double *__restrict__ bt = I.bt2[cur];
   CoopSync cs{nullptr, 0ull, nullptr, 0};
   if constexpr (COOP) {
     // a barrier that gave up left the counters out of step: the state is
     // invalid (the host reports it) and later launches do nothing
-    if (__hip_atomic_load(&st->fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    // (plain loads: both were written by earlier launches)
+    if (st->fault) return;
     cs.bar = I.bar;
-    cs.gen = __hip_atomic_load(&I.bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    cs.gen = I.bar[2];
     cs.fault = &st->fault;
   }
   // a vector the cooperative DMD apply wrote (other workgroups' slices)
@@ -644,7 +649,7 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
     st->residual = resid;
     st->phase = !flag_ig ? 1 : (!flag_pc ? 2 : 3);
     st->cur = cur;
-    st->fp32_sweeps += n32;
+    st->fp32_sweeps = f32_0 + n32;
   }
   __syncthreads();
   // end of step: error indicators from the final iterate and Alg. 2's
@@ -665,7 +670,10 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
     wg_sum_fast<3>(part, rred, rvec);
   }
   const int nbp = COOP ? coop_pass_blocks(nc, NT) : I.post_nb;
-  if (leader) rom_decide(I, rvec, nbp);
+  if (leader)
+    rom_decide(I, rvec, nbp,
+               StepIn{nsweep, conv, used_pc, ig_fb, pc_fb, !flag_ig ? 1 : (!flag_pc ? 2 : 3), cur, flag_ig, flag_pc,
+                      rank_ig, rank_pc, nonconv0, fb0, resid, steps0, si0, sw0});
   if constexpr (COOP) {
     // the snapshot projections of the ROMs that take one (units dealt over
     // the workgroups), so the step tail starts with the cores
@@ -867,13 +875,13 @@ __global__ void __launch_bounds__(MAXT) k_tail_coop(const Inst *__restrict__ ins
   static_assert(MAXT == TAIL_NT && CMAX * TAIL_NT >= RT_SLAB_MAX_CELLS, "tail layout");
   const Inst &I = insts[0];
   RtState *st = I.st;
-  if (xload(&st->fault)) return;
+  if (st->fault) return;  // written by an earlier launch
   __shared__ double slots[8 * RT_MAXWAVES];
   __shared__ double cc[RT_KC * RT_KC + 4], a2s[RT_RMAX];
   __shared__ RomSmem sm;
   // the tail's own barrier counters (the SI kernel's use another grid size)
   unsigned long long *bar = I.bar + 4;
-  CoopSync cs{bar, __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), &st->fault, 0};
+  CoopSync cs{bar, bar[2], &st->fault, 0};
   const int g = blockIdx.x, G = gridDim.x, NT = blockDim.x;
   const int nc = I.nc;
   const int nbp = (nc + NT - 1) / NT;
@@ -1023,14 +1031,22 @@ __global__ void __launch_bounds__(1024) k_setup_dsa_slab(const Inst *__restrict_
 // ---------------------------------------------------------------------------
 // Host-side launch helpers (C linkage inside the library only)
 // ---------------------------------------------------------------------------
+// The SI kernel's instantiation for a launch.  The thread bound sets the
+// register budget (1024 threads: 128 VGPRs, 512: 256): a launch of one
+// instance with at most 512 threads takes the 512-thread build, whose state
+// stays in registers (no spills); batches keep the 1024-thread build, whose
+// smaller register file lets two 512-thread workgroups share a compute unit.
+template <bool COOP>
+static const void *si_kernel(int nthreads, int cmax, bool single) {
+  if (cmax <= 4 && nthreads <= 512 && single) return reinterpret_cast<const void *>(&k_si_slab<4, 512, COOP>);
+  if (cmax <= 4) return reinterpret_cast<const void *>(&k_si_slab<4, 1024, COOP>);
+  return reinterpret_cast<const void *>(&k_si_slab<8, 512, COOP>);
+}
+
 extern "C" hipError_t rt_launch_slab_si(const Inst *dinsts, int ninst, int nthreads, int cmax,
                                         hipStream_t stream) {
-  dim3 grid(ninst), blk(nthreads);
-  if (cmax <= 4)
-    hipLaunchKernelGGL((k_si_slab<4, 1024, false>), grid, blk, 0, stream, dinsts);
-  else
-    hipLaunchKernelGGL((k_si_slab<8, 512, false>), grid, blk, 0, stream, dinsts);
-  return hipGetLastError();
+  void *args[] = {const_cast<Inst **>(&dinsts)};
+  return hipLaunchKernel(si_kernel<false>(nthreads, cmax, ninst == 1), dim3(ninst), dim3(nthreads), args, 0, stream);
 }
 
 // One instance on ng workgroups that wait for each other at grid barriers.
@@ -1042,9 +1058,8 @@ extern "C" hipError_t rt_launch_slab_si(const Inst *dinsts, int ninst, int nthre
 // some of them from starting for ~2 s, the barrier waits give up, the state
 // is flagged and the march reports an error instead of hanging.
 extern "C" hipError_t rt_launch_slab_si_coop(const Inst *dinst, int ng, int nthreads, int cmax, hipStream_t stream) {
-  if (cmax <= 4) hipLaunchKernelGGL((k_si_slab<4, 1024, true>), dim3(ng), dim3(nthreads), 0, stream, dinst);
-  else hipLaunchKernelGGL((k_si_slab<8, 512, true>), dim3(ng), dim3(nthreads), 0, stream, dinst);
-  return hipGetLastError();
+  void *args[] = {const_cast<Inst **>(&dinst)};
+  return hipLaunchKernel(si_kernel<true>(nthreads, cmax, true), dim3(ng), dim3(nthreads), args, 0, stream);
 }
 
 static int tail_grid(int npair, int nc) {
@@ -1056,8 +1071,7 @@ static int tail_grid(int npair, int nc) {
 extern "C" int rt_slab_coop_fits(int device, int ng, int nthreads, int cmax, int npair, int nc) {
   int cus = 0, a = 0, b = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
-  const void *si = cmax <= 4 ? reinterpret_cast<const void *>(&k_si_slab<4, 1024, true>)
-                             : reinterpret_cast<const void *>(&k_si_slab<8, 512, true>);
+  const void *si = si_kernel<true>(nthreads, cmax, true);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, si, nthreads, 0) != hipSuccess) return 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, reinterpret_cast<const void *>(&k_tail_coop<8, TAIL_NT>),
                                                    TAIL_NT, 0) != hipSuccess)
