@@ -298,12 +298,13 @@ __device__ inline void rom_apply(const RomDev &R, int rank, int ld, int nc, int 
   }
   __syncthreads();
   lu_solve_wave(R.LU, R.perm, rank, vec);
-  // expansion U c, five columns per batch of loads (c_k = 0 past the rank);
-  // the batches stay a loop to keep the caller's registers free
+  // expansion U c, five columns per batch of loads (batches up to the rank;
+  // c_k = 0 past it); the batches stay a loop to keep the caller's
+  // registers free
   for (int c = threadIdx.x; c < nc && act; c += NT) {
     double v = 0.0;
 #pragma unroll 1
-    for (int k0 = 0; k0 < RT_RMAX; k0 += 5) {
+    for (int k0 = 0; k0 < rank; k0 += 5) {
       double u[5];
 #pragma unroll
       for (int q = 0; q < 5; ++q) u[q] = R.U[(size_t)(k0 + q) * ld + c];
@@ -953,14 +954,11 @@ __device__ __forceinline__ void rom_pass1(const Inst &I, const RomDev &R, const 
     }
     part[2 * RT_RMAX] = rt_fma(xv, xv, part[2 * RT_RMAX]);
     part[2 * RT_RMAX + 1] = rt_fma(xv, bv, part[2 * RT_RMAX + 1]);
-    // all basis loads unconditional (finite columns past the rank, masked),
-    // so they are in flight together; the sums past the rank stay zero
+    // basis columns up to the rank only (uniform branches: the loads are
+    // still in flight together); the sums past the rank stay zero
     double u[RT_RMAX];
 #pragma unroll
-    for (int k = 0; k < RT_RMAX; ++k) {
-      const double v = R.U[(size_t)k * ld + c];
-      u[k] = k < r ? v : 0.0;
-    }
+    for (int k = 0; k < RT_RMAX; ++k) u[k] = k < r ? R.U[(size_t)k * ld + c] : 0.0;
 #pragma unroll
     for (int k = 0; k < RT_RMAX; ++k) {
       part[k] = rt_fma(u[k], xv, part[k]);
@@ -981,14 +979,12 @@ __device__ __forceinline__ void rom_pass2(const Inst &I, const RomDev &R, const 
 #pragma unroll
   for (int k = 0; k < 2 * RT_RMAX + 2; ++k) part[k] = 0.0;
   for (int c = b * NT + threadIdx.x; c < I.nc; c += nb * NT) {
-    // all loads issued up front and unconditionally (masked past the rank);
-    // the arithmetic keeps its order
+    // loads up to the rank, issued up front; the arithmetic keeps its order
     double u[RT_RMAX], wv[RT_RMAX];
 #pragma unroll
     for (int k = 0; k < RT_RMAX; ++k) {
-      const double x = R.U[(size_t)k * ld + c], y = R.W[(size_t)k * ld + c];
-      u[k] = k < r ? x : 0.0;
-      wv[k] = k < r ? y : 0.0;
+      u[k] = k < r ? R.U[(size_t)k * ld + c] : 0.0;
+      wv[k] = k < r ? R.W[(size_t)k * ld + c] : 0.0;
     }
     double v = part_load<COH>(W.x + c);
     const double bv = part_load<COH>(W.b + c);

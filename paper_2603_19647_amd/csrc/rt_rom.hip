@@ -130,9 +130,8 @@ __global__ void __launch_bounds__(UPD_BLK) k_rom_update(const Inst *__restrict__
   __syncthreads();
   const int r = P.r_old, ld = I.ld;
   double *X = mat ? R.W : R.U;
-  // the cells' old basis rows, all loads in flight together (masked past r;
-  // cells past nc read the padded tail of the column, ld >= nc rounded up,
-  // and are not written)
+  // the cells' old basis rows up to r, all loads in flight together (zero
+  // past r; cells past nc read the last cell and are not written)
   int c[UPD_CPT];
   bool ok[UPD_CPT];
   double old[UPD_CPT][RT_RMAX], e[UPD_CPT];
@@ -142,10 +141,7 @@ __global__ void __launch_bounds__(UPD_BLK) k_rom_update(const Inst *__restrict__
     ok[i] = c[i] < I.nc;
     const int cl = ok[i] ? c[i] : I.nc - 1;
 #pragma unroll
-    for (int q = 0; q < RT_RMAX; ++q) {
-      const double v = X[(size_t)q * ld + cl];
-      old[i][q] = q < r ? v : 0.0;
-    }
+    for (int q = 0; q < RT_RMAX; ++q) old[i][q] = q < r ? X[(size_t)q * ld + cl] : 0.0;
     // row r: the new direction, (v - U a2) / nu for U (inv_nu = 0 and a zero
     // row when the snapshot was rank-deficient), b for W
     e[i] = mat ? P.b[cl] : second_residual(P.p[cl], old[i], a2) * P.inv_nu;
