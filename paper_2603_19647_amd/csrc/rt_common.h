@@ -335,23 +335,52 @@ struct CoopSync {
   int buf;  // double buffer of the next exchange
 };
 
+// Global memory through address-space-1 pointers.  The arena's arrays are
+// reached through plain pointers held in Inst, so without a cast the
+// compiler emits flat_* instructions; those count against lgkmcnt as well as
+// vmcnt, and every wait for a scalar load or an LDS result then also waits
+// for all global accesses in flight.  global_* instructions count against
+// vmcnt only.
+#define RT_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ T ldg(const T *p) {
+  return *(const RT_GLOBAL T *)p;
+}
+template <typename T>
+struct rt_same {
+  using type = T;
+};
+template <typename T>
+__device__ __forceinline__ void stg(T *p, typename rt_same<T>::type v) {
+  *(RT_GLOBAL T *)p = v;
+}
+
 __device__ __forceinline__ double xload(const double *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load((const RT_GLOBAL double *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ float xload(const float *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load((const RT_GLOBAL float *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void xstore(double *p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store((RT_GLOBAL double *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void xstore(float *p, float v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store((RT_GLOBAL float *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ int xload(const int *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load((const RT_GLOBAL int *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void xstore(int *p, int v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store((RT_GLOBAL int *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long xload(const unsigned long long *p) {
+  return __hip_atomic_load((const RT_GLOBAL unsigned long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void xstore(unsigned long long *p, unsigned long long v) {
+  __hip_atomic_store((RT_GLOBAL unsigned long long *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long xadd(unsigned long long *p, unsigned long long v) {
+  return __hip_atomic_fetch_add((RT_GLOBAL unsigned long long *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void grid_sync(CoopSync &S) {
@@ -360,17 +389,16 @@ __device__ __forceinline__ void grid_sync(CoopSync &S) {
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned long long target = S.gen * gridDim.x;
-    const unsigned long long prev =
-        __hip_atomic_fetch_add(&S.bar[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long prev = xadd(&S.bar[0], 1ull);
     if (prev + 1 != target) {
       for (unsigned spins = 1;; ++spins) {
-        if (__hip_atomic_load(&S.bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+        if (xload(&S.bar[0]) >= target) break;
         __builtin_amdgcn_s_sleep(1);
         if ((spins & 255u) == 0) {
           // after a fault the counters are out of step: no further waiting
-          if (__hip_atomic_load(S.fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+          if (xload(S.fault)) break;
           if (spins >= (1u << 22)) {
-            __hip_atomic_store(S.fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            xstore(S.fault, 1);
             break;
           }
         }

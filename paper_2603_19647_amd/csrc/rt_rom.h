@@ -174,8 +174,8 @@ __device__ inline int lu_factor_wave(double *A, int *perm_lds, int n, double *LU
     if (mine) {
 #pragma unroll
       for (int j = 0; j < RT_RMAX; ++j)
-        if (j < n) LUg[pos * RT_RMAX + j] = row[j];
-      permg[pos] = lane;
+        if (j < n) stg(&LUg[pos * RT_RMAX + j], row[j]);
+      stg(&permg[pos], lane);
     }
     if (lane == 0) *flag = bad;
   }
@@ -196,12 +196,12 @@ constexpr int RT_SUMJ = 8;
 template <bool COH>
 __device__ __forceinline__ void part_store(double *p, double v) {
   if constexpr (COH) xstore(p, v);
-  else *p = v;
+  else stg(p, v);
 }
 template <bool COH>
 __device__ __forceinline__ double part_load(const double *p) {
   if constexpr (COH) return xload(p);
-  else return *p;
+  else return ldg(p);
 }
 template <bool COH>
 __device__ inline void sum_partials(const double *part, int nb, int ncol, double *out, double *scratch) {
@@ -276,10 +276,10 @@ __device__ inline void rom_apply(const RomDev &R, int rank, int ld, int nc, int 
   for (int k0 = 0; k0 < rank; k0 += 4) {
     double s[4] = {0.0, 0.0, 0.0, 0.0};
     for (int c = threadIdx.x; c < nc && act; c += NT) {
-      const double v = rhs[c];
+      const double v = ldg(&rhs[c]);
       double u[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) u[q] = R.U[(size_t)(k0 + q) * ld + c];
+      for (int q = 0; q < 4; ++q) u[q] = ldg(&R.U[(size_t)(k0 + q) * ld + c]);
 #pragma unroll
       for (int q = 0; q < 4; ++q) s[q] = rt_fma(u[q], v, s[q]);
     }
@@ -307,11 +307,11 @@ __device__ inline void rom_apply(const RomDev &R, int rank, int ld, int nc, int 
     for (int k0 = 0; k0 < rank; k0 += 5) {
       double u[5];
 #pragma unroll
-      for (int q = 0; q < 5; ++q) u[q] = R.U[(size_t)(k0 + q) * ld + c];
+      for (int q = 0; q < 5; ++q) u[q] = ldg(&R.U[(size_t)(k0 + q) * ld + c]);
 #pragma unroll
       for (int q = 0; q < 5; ++q) v = rt_fma(u[q], vec[k0 + q], v);
     }
-    out[c] = v;
+    stg(&out[c], v);
   }
   __syncthreads();
 }
@@ -590,28 +590,28 @@ __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, in
   }
   const double nu = sqrt(fmax(nu2, 0.0));
   // a2 for the rotation, zero past the rank
-  if (tid < RT_RMAX) P->a2[tid] = tid < r ? sm.red[2 * RT_RMAX + 2 + tid] : 0.0;
+  if (tid < RT_RMAX) stg(&P->a2[tid], tid < r ? sm.red[2 * RT_RMAX + 2 + tid] : 0.0);
   if (r == 0) {
     if (xn == 0.0) {
-      if (tid == 0) P->pending = 0;
+      if (tid == 0) stg(&P->pending, 0);
       __syncthreads();
       return -1;
     }
     if (tid == 0) {
       const double m = xb / xn;
-      R.M[0] = m;
-      R.S[0] = xn;
+      stg(&R.M[0], m);
+      stg(&R.S[0], xn);
       sm.A[0] = m / xn;
-      P->pending = 1;
-      P->r_old = 0;
-      P->rows = 1;
-      P->k = 1;
-      P->deficient = 0;
-      P->inv_nu = 1.0 / xn;
-      P->Uc[0] = 1.0;
-      P->Vc[0] = 1.0;
-      P->p = Wk.p;
-      P->b = Wk.b;
+      stg(&P->pending, 1);
+      stg(&P->r_old, 0);
+      stg(&P->rows, 1);
+      stg(&P->k, 1);
+      stg(&P->deficient, 0);
+      stg(&P->inv_nu, 1.0 / xn);
+      stg(&P->Uc[0], 1.0);
+      stg(&P->Vc[0], 1.0);
+      stg(&P->p, Wk.p);
+      stg(&P->b, Wk.b);
     }
     __syncthreads();
     if constexpr (DEFER_LU) {
@@ -626,7 +626,7 @@ __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, in
   const int rows = deficient ? r : r + 1, cols = r + 1;
   // stage M (r x r, global) in LDS once: the products below read it repeatedly
   double *Ms = sm.T1;  // free until the M_new products
-  for (int e = tid; e < RT_RMAX * RT_RMAX; e += NT) Ms[e] = R.M[e];
+  for (int e = tid; e < RT_RMAX * RT_RMAX; e += NT) Ms[e] = ldg(&R.M[e]);
   __syncthreads();
   // coefficient vectors: a (total), U^T b, a2, p^T W = p1^T W - a2^T M
   if (tid < RT_RMAX) {
@@ -645,7 +645,7 @@ __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, in
   for (int e = tid; e < RT_KC * RT_KC; e += NT) {
     const int j = e / RT_KC, i = e % RT_KC;  // K column j, row i
     double v = 0.0;
-    if (j < r && i == j) v = R.S[j];
+    if (j < r && i == j) v = ldg(&R.S[j]);
     if (j == r && i < r) v = sm.av[i];
     if (j == r && i == r && !deficient) v = nu;
     sm.B[e] = (i < rows && j < cols) ? v : 0.0;
@@ -659,7 +659,7 @@ __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, in
   }
   __syncthreads();
   // S and a as the secular path reads them (LDS); B above is Jacobi's input
-  if (tid < RT_RMAX) sm.a2v[tid] = tid < r ? R.S[tid] : 0.0;
+  if (tid < RT_RMAX) sm.a2v[tid] = tid < r ? ldg(&R.S[tid]) : 0.0;
   __syncthreads();
   if (!core_svd_secular(sm, sm.a2v, sm.av, nu, r, rows, cols)) core_svd(sm, rows, cols);
   if (tid == 0) {
@@ -688,27 +688,27 @@ __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, in
   // (right): that kernel multiplies over the full capacity
   for (int e = tid; e < RT_KC * RT_KC; e += NT) {
     const int i = e / RT_KC, j = e % RT_KC;
-    P->Uc[e] = (i < rows && j < k) ? sm.Uc[e] : 0.0;
-    P->Vc[e] = (i < cols && j < k) ? sm.Vc[e] : 0.0;
+    stg(&P->Uc[e], (i < rows && j < k) ? sm.Uc[e] : 0.0);
+    stg(&P->Vc[e], (i < cols && j < k) ? sm.Vc[e] : 0.0);
   }
   __syncthreads();
   for (int e = tid; e < k * k; e += NT) {
     const int i = e / k, j = e % k;
     double v = 0.0;
     for (int q = 0; q < rows; ++q) v = rt_fma(sm.Uc[q * RT_KC + i], sm.T1[q * RT_KC + j], v);
-    R.M[i * RT_RMAX + j] = v;
+    stg(&R.M[i * RT_RMAX + j], v);
     sm.A[i * RT_KC + j] = v / sm.sv[j];
   }
   if (tid == 0) {
-    for (int j = 0; j < k; ++j) R.S[j] = sm.sv[j];
-    P->pending = 1;
-    P->r_old = r;
-    P->rows = rows;
-    P->k = k;
-    P->deficient = deficient;
-    P->inv_nu = deficient ? 0.0 : 1.0 / nu;
-    P->p = Wk.p;
-    P->b = Wk.b;
+    for (int j = 0; j < k; ++j) stg(&R.S[j], sm.sv[j]);
+    stg(&P->pending, 1);
+    stg(&P->r_old, r);
+    stg(&P->rows, rows);
+    stg(&P->k, k);
+    stg(&P->deficient, deficient);
+    stg(&P->inv_nu, deficient ? 0.0 : 1.0 / nu);
+    stg(&P->p, Wk.p);
+    stg(&P->b, Wk.b);
   }
   __syncthreads();
   if constexpr (DEFER_LU) {
@@ -773,7 +773,7 @@ __device__ __forceinline__ void rotate_block(const double (&old)[NCELL][RT_RMAX]
       if (ok[i])
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj)
-          if (j0 + jj < k) X[(size_t)(j0 + jj) * ld + c[i]] = acc[i][jj];
+          if (j0 + jj < k) stg(&X[(size_t)(j0 + jj) * ld + c[i]], acc[i][jj]);
   }
 }
 
@@ -916,8 +916,8 @@ __device__ inline void rom_decide(const Inst &I, const double *vec, int nb, cons
 // s_r / sum(s) of the retained values (eq. ig_stop, eq. pc_stop)
 __device__ inline double rom_tail_ratio(const RomDev &R, int rank) {
   double tot = 0.0;
-  for (int i = 0; i < rank; ++i) tot += R.S[i];
-  return tot > 0.0 ? R.S[rank - 1] / tot : 0.0;
+  for (int i = 0; i < rank; ++i) tot += ldg(&R.S[i]);
+  return tot > 0.0 ? ldg(&R.S[rank - 1]) / tot : 0.0;
 }
 
 __device__ __forceinline__ const RomDev &rom_of(const Inst &I, int z) { return z ? I.pc : I.ig; }
@@ -941,16 +941,16 @@ __device__ __forceinline__ void rom_pass1(const Inst &I, const RomDev &R, const 
   for (int c = b * NT + threadIdx.x; c < I.nc; c += nb * NT) {
     double xv, bv;
     if (z == 1) {  // x = rho^n - rho^(1/2), b = rho^(1/2) - rho^(0)
-      const double rh = I.rhalf[c];
-      xv = I.rho[c] - rh;
-      bv = rh - I.rho0[c];
+      const double rh = ldg(&I.rhalf[c]);
+      xv = ldg(&I.rho[c]) - rh;
+      bv = rh - ldg(&I.rho0[c]);
       // the PC ROM's x, b live in the work arrays (COH: read later by
       // workgroups on other XCDs)
       part_store<COH>(const_cast<double *>(W.x) + c, xv);
       part_store<COH>(const_cast<double *>(W.b) + c, bv);
     } else {
-      xv = W.x[c];
-      bv = W.b[c];
+      xv = ldg(&W.x[c]);
+      bv = ldg(&W.b[c]);
     }
     part[2 * RT_RMAX] = rt_fma(xv, xv, part[2 * RT_RMAX]);
     part[2 * RT_RMAX + 1] = rt_fma(xv, bv, part[2 * RT_RMAX + 1]);
@@ -958,7 +958,7 @@ __device__ __forceinline__ void rom_pass1(const Inst &I, const RomDev &R, const 
     // still in flight together); the sums past the rank stay zero
     double u[RT_RMAX];
 #pragma unroll
-    for (int k = 0; k < RT_RMAX; ++k) u[k] = k < r ? R.U[(size_t)k * ld + c] : 0.0;
+    for (int k = 0; k < RT_RMAX; ++k) u[k] = k < r ? ldg(&R.U[(size_t)k * ld + c]) : 0.0;
 #pragma unroll
     for (int k = 0; k < RT_RMAX; ++k) {
       part[k] = rt_fma(u[k], xv, part[k]);
@@ -983,8 +983,8 @@ __device__ __forceinline__ void rom_pass2(const Inst &I, const RomDev &R, const 
     double u[RT_RMAX], wv[RT_RMAX];
 #pragma unroll
     for (int k = 0; k < RT_RMAX; ++k) {
-      u[k] = k < r ? R.U[(size_t)k * ld + c] : 0.0;
-      wv[k] = k < r ? R.W[(size_t)k * ld + c] : 0.0;
+      u[k] = k < r ? ldg(&R.U[(size_t)k * ld + c]) : 0.0;
+      wv[k] = k < r ? ldg(&R.W[(size_t)k * ld + c]) : 0.0;
     }
     double v = part_load<COH>(W.x + c);
     const double bv = part_load<COH>(W.b + c);

@@ -51,8 +51,8 @@ __device__ __forceinline__ void sweep_moment(const Inst &I, const R (&ct)[CMAX],
     p1 = min(I.npair, p0 + I.pg);
   }
   for (int p = p0; p < p1; ++p) {
-    const R m = (R)I.pm[p];
-    const R w = (R)I.pw[p];
+    const R m = (R)ldg(&I.pm[p]);
+    const R w = (R)ldg(&I.pw[p]);
     R a[CMAX], b[CMAX];
     R Af = R(1), Bf = R(0);
 #pragma unroll
@@ -130,8 +130,8 @@ __device__ __forceinline__ void sweep_moment(const Inst &I, const R (&ct)[CMAX],
 __device__ inline void rom_apply_coop(const Inst &I, const RomDev &R, int rank, const double *rhs, double *out,
                                       double *red, double *vec, double *luS, int *permS, CoopSync &cs) {
   // the LU factors go to LDS first: their loads overlap the projection
-  for (int e = threadIdx.x; e < RT_RMAX * RT_RMAX; e += blockDim.x) luS[e] = R.LU[e];
-  if ((int)threadIdx.x < RT_RMAX) permS[threadIdx.x] = R.perm[threadIdx.x];
+  for (int e = threadIdx.x; e < RT_RMAX * RT_RMAX; e += blockDim.x) luS[e] = ldg(&R.LU[e]);
+  if ((int)threadIdx.x < RT_RMAX) permS[threadIdx.x] = ldg(&R.perm[threadIdx.x]);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int nc = I.nc, ng = I.ng, ld = I.ld, NT = blockDim.x;
   const int csz = (nc + ng - 1) / ng;
@@ -146,10 +146,10 @@ __device__ inline void rom_apply_coop(const Inst &I, const RomDev &R, int rank, 
     const int cg = wave & 3, sub = wave >> 2, nsub = nw >> 2;
     double sacc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int c = lo + sub * 64 + lane; c < hi; c += nsub * 64) {
-      const double v = rhs[c];
+      const double v = ldg(&rhs[c]);
       double u[5];
 #pragma unroll
-      for (int q = 0; q < 5; ++q) u[q] = R.U[(size_t)(cg * 5 + q) * ld + c];
+      for (int q = 0; q < 5; ++q) u[q] = ldg(&R.U[(size_t)(cg * 5 + q) * ld + c]);
 #pragma unroll
       for (int q = 0; q < 5; ++q) sacc[q] = rt_fma(u[q], v, sacc[q]);
     }
@@ -169,10 +169,10 @@ __device__ inline void rom_apply_coop(const Inst &I, const RomDev &R, int rank, 
     for (int k0 = 0; k0 < rank; k0 += 4) {
       double sacc[4] = {0.0, 0.0, 0.0, 0.0};
       for (int c = lo + (int)threadIdx.x; c < hi; c += NT) {
-        const double v = rhs[c];
+        const double v = ldg(&rhs[c]);
         double u[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) u[q] = R.U[(size_t)(k0 + q) * ld + c];
+        for (int q = 0; q < 4; ++q) u[q] = ldg(&R.U[(size_t)(k0 + q) * ld + c]);
 #pragma unroll
         for (int q = 0; q < 4; ++q) sacc[q] = rt_fma(u[q], v, sacc[q]);
       }
@@ -220,7 +220,7 @@ __device__ inline void rom_apply_coop(const Inst &I, const RomDev &R, int rank, 
       const int cc = min(c, hi - 1);
       double u[5];
 #pragma unroll
-      for (int q = 0; q < 5; ++q) u[q] = R.U[(size_t)(k0 + q) * ld + cc];
+      for (int q = 0; q < 5; ++q) u[q] = ldg(&R.U[(size_t)(k0 + q) * ld + cc]);
       double v = 0.0;
 #pragma unroll
       for (int q = 0; q < 5; ++q) v = rt_fma(u[q], y5[q], v);
@@ -302,7 +302,7 @@ __device__ __forceinline__ void pass_cols(const double *X, int ld, int cc, int k
                                           double (&u)[PASS_COLS]) {
 #pragma unroll
   for (int q = 0; q < PASS_COLS; ++q) {
-    const double v = X[(size_t)(k0 + q) * ld + cc];
+    const double v = ldg(&X[(size_t)(k0 + q) * ld + cc]);
     u[q] = (in && k0 + q < rank) ? v : 0.0;
   }
 }
@@ -320,11 +320,11 @@ __device__ inline void coop_pass1(const Inst &I, int z, int blk, int rank, const
   const RomDev &R = z ? I.pc : I.ig;
   double xv, bv;
   if (z == 0) {
-    xv = I.rho[cc];
-    bv = bt[cc];
+    xv = ldg(&I.rho[cc]);
+    bv = ldg(&bt[cc]);
   } else {
-    const double rh = I.rhalf[cc];
-    xv = I.rho[cc] - rh;
+    const double rh = ldg(&I.rhalf[cc]);
+    xv = ldg(&I.rho[cc]) - rh;
     bv = rh - xload(&I.rho0[cc]);
     if (in && G.h == 0) {
       xstore(I.work + 2 * (size_t)nc + c, xv);
@@ -360,8 +360,8 @@ __device__ inline void coop_pass2(const Inst &I, int z, int blk, int nb, int ran
   const int c = blk * G.H + G.cl;
   const bool in = G.h < 2 && c < nc;
   const int cc = min(c, nc - 1);
-  double xv = z ? xload(I.work + 2 * (size_t)nc + cc) : I.rho[cc];
-  double bv = z ? xload(I.work + 3 * (size_t)nc + cc) : bt[cc];
+  double xv = z ? xload(I.work + 2 * (size_t)nc + cc) : ldg(&I.rho[cc]);
+  double bv = z ? xload(I.work + 3 * (size_t)nc + cc) : ldg(&bt[cc]);
   if (!in) xv = bv = 0.0;
   const int kh = min(G.h, 1) * PASS_COLS;
   double u[PASS_COLS], w[PASS_COLS];
@@ -426,7 +426,7 @@ __device__ __forceinline__ void dsa_solve_slab(const Inst &I, int c0, int n, con
 #pragma unroll
   for (int t = 0; t < CMAX; ++t) {
     if (t < n) {
-      fe[t] = I.dsa_fe[c0 + t];
+      fe[t] = ldg(&I.dsa_fe[c0 + t]);
       B = rt_fma(fe[t], B, rhs[t]);
       A *= fe[t];
     }
@@ -448,8 +448,8 @@ __device__ __forceinline__ void dsa_solve_slab(const Inst &I, int c0, int n, con
 #pragma unroll
   for (int t = CMAX - 1; t >= 0; --t) {
     if (t < n) {
-      bg[t] = I.dsa_bg[c0 + t];
-      z[t] *= I.dsa_invd[c0 + t];
+      bg[t] = ldg(&I.dsa_bg[c0 + t]);
+      z[t] *= ldg(&I.dsa_invd[c0 + t]);
       B = rt_fma(bg[t], B, z[t]);
       A *= bg[t];
     }
@@ -531,16 +531,16 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
     // every workgroup copies (the same values; agent-scope stores, like the
     // cooperative DMD output, so later reads see them wherever they land)
     for (int c = c0; c < c0 + n; ++c) {
-      if constexpr (COOP) xstore(&I.rho0[c], I.rho[c]);
-      else I.rho0[c] = I.rho[c];
+      if constexpr (COOP) xstore(&I.rho0[c], ldg(&I.rho[c]));
+      else stg(&I.rho0[c], ldg(&I.rho[c]));
     }
   }
   double ct[CMAX], ss[CMAX], rp[CMAX], y[CMAX];
 #pragma unroll
   for (int t = 0; t < CMAX; ++t) {
     const bool in = t < n;
-    ct[t] = in ? I.ct[c0 + t] : 1.0;
-    ss[t] = in ? I.ss[c0 + t] : 0.0;
+    ct[t] = in ? ldg(&I.ct[c0 + t]) : 1.0;
+    ss[t] = in ? ldg(&I.ss[c0 + t]) : 0.0;
     rp[t] = in ? rd(&I.rho0[c0 + t]) : 0.0;
     y[t] = 0.0;
   }
@@ -556,11 +556,11 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
       for (int t = 0; t < CMAX; ++t) s[t] = ss[t] * rp[t];
       sweep_moment<CMAX, double, COOP>(I, ct, s, n, c0, acc, slots, parity, cs);
 #pragma unroll
-      for (int t = 0; t < CMAX; ++t) y[t] = acc[t] + ((t < n) ? bt[c0 + t] : 0.0);
+      for (int t = 0; t < CMAX; ++t) y[t] = acc[t] + ((t < n) ? ldg(&bt[c0 + t]) : 0.0);
       if (nsweep == 0) {  // COOP: every workgroup (the same values), for its passes
 #pragma unroll
         for (int t = 0; t < CMAX; ++t)
-          if (t < n) I.rhalf[c0 + t] = y[t];
+          if (t < n) stg(&I.rhalf[c0 + t], y[t]);
       }
       nsweep++;
       exact = 1;
@@ -595,7 +595,7 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
       // workgroup writes the same right-hand side and reads its own copy
 #pragma unroll
       for (int t = 0; t < CMAX; ++t)
-        if (t < n) I.work[c0 + t] = y[t] - rd(&I.rho0[c0 + t]);
+        if (t < n) stg(&I.work[c0 + t], y[t] - rd(&I.rho0[c0 + t]));
       __syncthreads();
       if constexpr (COOP) rom_apply_coop(I, I.pc, rank_pc, I.work, I.dpc, rred, rvec, luS, permS, cs);
       else rom_apply(I.pc, rank_pc, I.ld, nc, NT, I.work, I.dpc, rred, rvec);
@@ -639,7 +639,7 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
   // every workgroup writes it (the same values), for its passes
 #pragma unroll
   for (int t = 0; t < CMAX; ++t)
-    if (t < n) I.rho[c0 + t] = y[t];
+    if (t < n) stg(&I.rho[c0 + t], y[t]);
   if (leader && tid == 0) {
     st->iters = nsweep;
     st->conv = conv;
@@ -664,7 +664,7 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
         part[0] = rt_fma(r, r, part[0]);
         const double e1 = rd(&I.rho0[c0 + t]) - r;
         part[1] = rt_fma(e1, e1, part[1]);
-        const double e2 = rd(&I.dpc[c0 + t]) - (r - I.rhalf[c0 + t]);
+        const double e2 = rd(&I.dpc[c0 + t]) - (r - ldg(&I.rhalf[c0 + t]));
         part[2] = rt_fma(e2, e2, part[2]);
       }
     wg_sum_fast<3>(part, rred, rvec);
@@ -690,7 +690,7 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
         if (z ? P.pc_on : P.ig_on) coop_pass2(I, z, it - z * nbp, nbp, z ? rank_pc : rank_ig, bt, pred, pav, pscr);
       }
     }
-    if (leader && tid == 0) __hip_atomic_store(&I.bar[2], cs.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (leader && tid == 0) xstore(&I.bar[2], cs.gen);
   }
 }
 
@@ -713,7 +713,7 @@ __device__ __forceinline__ void fpass_one_pair(const Inst &I, int p, int c0, int
                                                double *slots, int &parity) {
   const int nc = I.nc;
   const double idt = I.inv_dt;
-  const double m = I.pm[p], w = I.pw[p];
+  const double m = ldg(&I.pm[p]), w = ldg(&I.pw[p]);
   double *fneg = I.f + (size_t)p * nc + c0;               // mu < 0
   double *fpos = I.f + (size_t)(I.nv - 1 - p) * nc + c0;  // mu > 0
   double inv[CMAX], bp[CMAX], bn[CMAX];
@@ -721,8 +721,8 @@ __device__ __forceinline__ void fpass_one_pair(const Inst &I, int p, int c0, int
   for (int t = 0; t < CMAX; ++t) {
     const bool in = t < n;
     inv[t] = rt_rcp(ct[t] + m);
-    bp[t] = in ? fpos[t] : 0.0;
-    bn[t] = in ? fneg[t] : 0.0;
+    bp[t] = in ? ldg(&fpos[t]) : 0.0;
+    bn[t] = in ? ldg(&fneg[t]) : 0.0;
   }
   if (!rhs_only) {
     double Af = 1.0, Bf = 0.0, Ab = 1.0, Bb = 0.0;
@@ -751,7 +751,7 @@ __device__ __forceinline__ void fpass_one_pair(const Inst &I, int p, int c0, int
       if (t < n) {
         f = rt_fma(m * inv[t], f, bp[t]);
         bp[t] = f;
-        fpos[t] = f;
+        stg(&fpos[t], f);
       }
     f = inB;
 #pragma unroll
@@ -759,7 +759,7 @@ __device__ __forceinline__ void fpass_one_pair(const Inst &I, int p, int c0, int
       if (t < n) {
         f = rt_fma(m * inv[t], f, bn[t]);
         bn[t] = f;
-        fneg[t] = f;
+        stg(&fneg[t], f);
       }
   }
   // right-hand-side sweep with source f^n_j / dt + G and inflow g
@@ -803,7 +803,7 @@ __device__ __forceinline__ void fpass_one_pair(const Inst &I, int p, int c0, int
   for (int t = 0; t < CMAX; ++t)
     if (t < n) {
       if constexpr (COH) xstore(&part[t], fw[t]);
-      else part[t] = fw[t];
+      else stg(&part[t], fw[t]);
     }
 }
 
@@ -819,9 +819,9 @@ __device__ __forceinline__ void fpass_inputs(const Inst &I, int NT, int rhs_only
 #pragma unroll
   for (int t = 0; t < CMAX; ++t) {
     const bool in = t < n;
-    ct[t] = in ? I.ct[c0 + t] : 1.0;
-    G[t] = in ? I.G[c0 + t] : 0.0;
-    srcc[t] = (in && !rhs_only) ? rt_fma(I.ss[c0 + t], I.rho[c0 + t], G[t]) : 0.0;
+    ct[t] = in ? ldg(&I.ct[c0 + t]) : 1.0;
+    G[t] = in ? ldg(&I.G[c0 + t]) : 0.0;
+    srcc[t] = (in && !rhs_only) ? rt_fma(ldg(&I.ss[c0 + t]), ldg(&I.rho[c0 + t]), G[t]) : 0.0;
   }
 }
 
@@ -932,7 +932,7 @@ __global__ void __launch_bounds__(MAXT) k_tail_coop(const Inst *__restrict__ ins
         bool ok[1] = {true};
 #pragma unroll
         for (int q = 0; q < RT_RMAX; ++q) {
-          const double v = X[(size_t)q * I.ld + c];
+          const double v = ldg(&X[(size_t)q * I.ld + c]);
           old[0][q] = q < r ? v : 0.0;
         }
         // the new direction (v - U a2) / nu for U, b for W (both written by
@@ -957,9 +957,9 @@ __global__ void __launch_bounds__(MAXT) k_tail_coop(const Inst *__restrict__ ins
       for (int q = 0; q < 8; ++q)
         if (p0 + q < np) acc += v[q];
     }
-    I.bt2[st->cur ^ 1][c] = acc;
+    stg(&I.bt2[st->cur ^ 1][c], acc);
   }
-  if (g == 0 && threadIdx.x == 0) __hip_atomic_store(&bar[2], cs.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (g == 0 && threadIdx.x == 0) xstore(&bar[2], cs.gen);
 }
 
 // b~ = sum over pairs of fpart[p], in pair order, into the b~ buffer the step
@@ -972,9 +972,9 @@ __global__ void __launch_bounds__(256) k_fpass_sum(const Inst *__restrict__ inst
   const double *part = I.fpart + c;
   double acc = 0.0;
 #pragma unroll 8
-  for (int p = 0; p < np; ++p) acc += part[(size_t)p * nc];
+  for (int p = 0; p < np; ++p) acc += ldg(&part[(size_t)p * nc]);
   double *bt_out = rhs_only ? I.bt2[I.st->steps & 1] : I.bt2[I.st->cur ^ 1];
-  bt_out[c] = acc;
+  stg(&bt_out[c], acc);
 }
 
 // ---------------------------------------------------------------------------
