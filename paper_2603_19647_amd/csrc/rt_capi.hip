@@ -298,6 +298,8 @@ static size_t slab_bytes(const rtrom_problem_desc *d, int nv) {
     if (ng > 1) {
       L.take(2 * (size_t)ng * nc * 8);
       L.take(2 * (size_t)ng * nc * 4);
+      L.take(2 * nc * 8);
+      L.take(2 * nc * 4);
       L.take(2 * (size_t)ng * RT_RMAX * 8);
       L.take(8 * 8);
     }
@@ -437,6 +439,8 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   if (I.ng > 1) {
     I.sip = D(2 * (size_t)I.ng * nc * 8);
     I.sip32 = (float *)D(2 * (size_t)I.ng * nc * 4);
+    I.sips = D(2 * (size_t)nc * 8);
+    I.sips32 = (float *)D(2 * (size_t)nc * 4);
     I.apx = D(2 * (size_t)I.ng * RT_RMAX * 8);
     I.bar = (unsigned long long *)D(8 * 8);
   }

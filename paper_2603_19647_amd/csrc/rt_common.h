@@ -105,6 +105,8 @@ struct Inst {
   int ng, pg;
   double *sip;      // [2][ng][nc] FP64 group moments (exchange double buffer)
   float *sip32;     // [2][ng][nc] FP32 group moments
+  double *sips;     // [2][nc] FP64 moment sums (each workgroup's slice)
+  float *sips32;    // [2][nc] FP32 moment sums
   double *apx;      // [2][ng][RT_RMAX] DMD projection partials
   unsigned long long *bar;  // grid barrier counters: [0..3) SI kernel, [4..7) step tail
   double *rho;      // rho^n

@@ -33,6 +33,12 @@ template <>
 __device__ __forceinline__ double *coop_part<double>(const Inst &I) { return I.sip; }
 template <>
 __device__ __forceinline__ float *coop_part<float>(const Inst &I) { return I.sip32; }
+template <typename R>
+__device__ __forceinline__ R *coop_sums(const Inst &I);
+template <>
+__device__ __forceinline__ double *coop_sums<double>(const Inst &I) { return I.sips; }
+template <>
+__device__ __forceinline__ float *coop_sums<float>(const Inst &I) { return I.sips32; }
 
 // ---------------------------------------------------------------------------
 // Sweep with an ordinate-independent source s and zero inflow, returning the
@@ -94,32 +100,32 @@ __device__ __forceinline__ void sweep_moment(const Inst &I, const R (&ct)[CMAX],
     }
   }
   if constexpr (COOP) {
+    // the groups' moments are added in group order by a reduce-scatter
+    // (workgroup g adds the cells [g*S, g*S + S)) and an all-gather of the
+    // sums: each workgroup reads 2 nc values instead of ng * nc
     const int nc = I.nc, ng = I.ng;
     R *part = coop_part<R>(I) + (size_t)cs.buf * ng * nc;
+    R *sums = coop_sums<R>(I) + (size_t)cs.buf * nc;
     cs.buf ^= 1;
 #pragma unroll
     for (int t = 0; t < CMAX; ++t)
       if (t < n) xstore(&part[(size_t)blockIdx.x * nc + c0 + t], acc[t]);
     grid_sync(cs);
+    const int S = (nc + ng - 1) / ng, lo = blockIdx.x * S, hi = min(nc, lo + S);
+    for (int c = lo + (int)threadIdx.x; c < hi; c += blockDim.x) {
+      // every group's partial in flight together (past ng clamped, masked)
+      R v[16];
 #pragma unroll
-    for (int t = 0; t < CMAX; ++t) acc[t] = R(0);
-    // four groups per batch of loads (all in flight together; past ng the
-    // address is clamped and the value masked)
-    const int ct0 = min(c0, nc - 1);
-    for (int g0 = 0; g0 < ng; g0 += 4) {
-      R v[4][CMAX];
+      for (int q = 0; q < 16; ++q) v[q] = xload(&part[(size_t)min(q, ng - 1) * nc + c]);
+      R sv = R(0);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int g = min(g0 + q, ng - 1);
-#pragma unroll
-        for (int t = 0; t < CMAX; ++t) v[q][t] = xload(&part[(size_t)g * nc + min(ct0 + t, nc - 1)]);
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int t = 0; t < CMAX; ++t)
-          if (g0 + q < ng && t < n) acc[t] += v[q][t];
+      for (int q = 0; q < 16; ++q)
+        if (q < ng) sv += v[q];
+      xstore(&sums[c], sv);
     }
+    grid_sync(cs);
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t) acc[t] = (t < n) ? xload(&sums[c0 + t]) : R(0);
   }
 }
 
