@@ -125,8 +125,8 @@ __global__ void __launch_bounds__(UPD_BLK) k_rom_update(const Inst *__restrict__
   const RomPend &P = *R.pend;
   if (!P.pending) return;
   const double *src = mat ? P.Vc : P.Uc;
-  for (int e = threadIdx.x; e < RT_KC * RT_KC; e += blockDim.x) cc[e] = src[e];
-  if (threadIdx.x < RT_RMAX) a2[threadIdx.x] = P.a2[threadIdx.x];
+  for (int e = threadIdx.x; e < RT_KC * RT_KC; e += blockDim.x) cc[e] = ldg(&src[e]);
+  if (threadIdx.x < RT_RMAX) a2[threadIdx.x] = ldg(&P.a2[threadIdx.x]);
   __syncthreads();
   const int r = P.r_old, ld = I.ld;
   double *X = mat ? R.W : R.U;
@@ -141,10 +141,10 @@ __global__ void __launch_bounds__(UPD_BLK) k_rom_update(const Inst *__restrict__
     ok[i] = c[i] < I.nc;
     const int cl = ok[i] ? c[i] : I.nc - 1;
 #pragma unroll
-    for (int q = 0; q < RT_RMAX; ++q) old[i][q] = q < r ? X[(size_t)q * ld + cl] : 0.0;
+    for (int q = 0; q < RT_RMAX; ++q) old[i][q] = q < r ? ldg(&X[(size_t)q * ld + cl]) : 0.0;
     // row r: the new direction, (v - U a2) / nu for U (inv_nu = 0 and a zero
     // row when the snapshot was rank-deficient), b for W
-    e[i] = mat ? P.b[cl] : second_residual(P.p[cl], old[i], a2) * P.inv_nu;
+    e[i] = mat ? ldg(&P.b[cl]) : second_residual(ldg(&P.p[cl]), old[i], a2) * P.inv_nu;
   }
   rotate_block<UPD_CPT>(old, e, cc, r, P.k, X, ld, c, ok);
 }

@@ -864,15 +864,15 @@ __device__ __forceinline__ void publish_pend(RomPend *P) {
   // agent-scope atomics (same values) once the core has written it
   __syncthreads();
   for (int e = threadIdx.x; e < RT_KC * RT_KC; e += blockDim.x) {
-    xstore(&P->Uc[e], P->Uc[e]);
-    xstore(&P->Vc[e], P->Vc[e]);
+    xstore(&P->Uc[e], ldg(&P->Uc[e]));
+    xstore(&P->Vc[e], ldg(&P->Vc[e]));
   }
-  if (threadIdx.x < RT_RMAX) xstore(&P->a2[threadIdx.x], P->a2[threadIdx.x]);
+  if (threadIdx.x < RT_RMAX) xstore(&P->a2[threadIdx.x], ldg(&P->a2[threadIdx.x]));
   if (threadIdx.x == 0) {
-    xstore(&P->r_old, P->r_old);
-    xstore(&P->k, P->k);
-    xstore(&P->inv_nu, P->inv_nu);
-    xstore(&P->pending, P->pending);
+    xstore(&P->r_old, ldg(&P->r_old));
+    xstore(&P->k, ldg(&P->k));
+    xstore(&P->inv_nu, ldg(&P->inv_nu));
+    xstore(&P->pending, ldg(&P->pending));
   }
 }
 
