@@ -61,6 +61,16 @@ struct QuadSum {
     return v;
   }
 };
+// sum over 8 lanes (two quads), identical in every lane of the eight:
+// the quads' sums, then each half-row lane adds its mirror's (the other quad)
+struct OctSum {
+  __device__ double operator()(double v) const {
+    v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_d<0x141>(v);  // row_half_mirror
+    return v;
+  }
+};
 // whole-wave sum, identical in every lane
 __device__ __forceinline__ double wave_sum_fast(double v) {
   v = row16_sum(v);
@@ -500,13 +510,14 @@ __device__ inline bool core_svd_secular(RomSmem &sm, const double *S, const doub
   if (!sm.ap_ok) return false;
   const arrow::Problem &P = sm.ap;
   const int m = P.m;
-  // four lanes per root (a DPP quad; roots 0..15 on wave 0, the rest on
-  // wave 1), each summing every fourth term of the secular function
-  if (tid < 4 * m) {
-    const int kq = tid >> 2, g = tid & 3;
+  // eight lanes per root (half a DPP row; roots 0..7 on wave 0, 8..15 on
+  // wave 1, the rest on wave 2), each summing every eighth term of the
+  // secular function
+  if (tid < 8 * m) {
+    const int kq = tid >> 3, g = tid & 7;
     int K;
     double tau;
-    arrow::root_g<4>(P, kq, g, QuadSum(), K, tau);
+    arrow::root_g<8>(P, kq, g, OctSum(), K, tau);
     if (g == 0) {
       sm.ap_K[kq] = K;
       sm.ap_tau[kq] = tau;
@@ -938,6 +949,7 @@ __device__ __forceinline__ void rom_pass1(const Inst &I, const RomDev &R, const 
   double part[2 * RT_RMAX + 2];
 #pragma unroll
   for (int k = 0; k < 2 * RT_RMAX + 2; ++k) part[k] = 0.0;
+#pragma unroll 2
   for (int c = b * NT + threadIdx.x; c < I.nc; c += nb * NT) {
     double xv, bv;
     if (z == 1) {  // x = rho^n - rho^(1/2), b = rho^(1/2) - rho^(0)
@@ -978,6 +990,7 @@ __device__ __forceinline__ void rom_pass2(const Inst &I, const RomDev &R, const 
   double part[2 * RT_RMAX + 2];
 #pragma unroll
   for (int k = 0; k < 2 * RT_RMAX + 2; ++k) part[k] = 0.0;
+#pragma unroll 2
   for (int c = b * NT + threadIdx.x; c < I.nc; c += nb * NT) {
     // loads up to the rank, issued up front; the arithmetic keeps its order
     double u[RT_RMAX], wv[RT_RMAX];
