@@ -738,24 +738,27 @@ __device__ inline int isvd_lu(const RomDev &R, RomSmem &sm) {
   return !lu_factor_wave(sm.A, sm.perm, n, R.LU, R.perm, &sm.ibuf[0]);
 }
 
-// Second half: U <- [U, p/nu] Uc[:, :k] (or W <- [W, b] Vc[:, :k]) for the
-// cells c[0..NCELL) of one thread, given their old rows; works in place.  The
-// coefficients Cc (LDS, stride RT_KC, at least RT_KC * RT_KC + 4 entries) are
-// zero outside the core, and the old basis entries past r are masked, so
-// every product runs over the full capacity without branches.  Each
-// coefficient read from LDS serves NCELL cells, and the outputs go in blocks
-// of four columns, which bounds the registers the LDS reads take.
 // p = v - U a2 for one cell from its old basis row (the second Gram-Schmidt
-// step, in the order the passes use).
-__device__ __forceinline__ double second_residual(double v, const double (&old)[RT_RMAX], const double *a2) {
+// step, in the order the passes use).  a2: LDS or constant-space pointer.
+template <typename CP>
+__device__ __forceinline__ double second_residual(double v, const double (&old)[RT_RMAX], CP a2) {
 #pragma unroll
   for (int k = 0; k < RT_RMAX; ++k) v = rt_fma(-old[k], a2[k], v);
   return v;
 }
 
-template <int NCELL>
-__device__ __forceinline__ void rotate_block(const double (&old)[NCELL][RT_RMAX], const double (&e)[NCELL],
-                                             const double *Cc, int r, int k, double *X, int ld, const int (&c)[NCELL],
+// Second half: U <- [U, p/nu] Uc[:, :k] (or W <- [W, b] Vc[:, :k]) for the
+// cells c[0..NCELL) of one thread, given their old rows; works in place.  The
+// coefficients Cc (stride RT_KC, at least RT_KC * RT_KC + 4 entries) are zero
+// outside the core, and the old basis entries past r are masked, so every
+// product runs over the full capacity without branches.  Cc is either LDS
+// (each read serves NCELL cells) or the constant address space (uniform
+// addresses: scalar loads, the products take them as scalar operands); the
+// outputs go in blocks of four columns, which bounds the registers the
+// coefficients take.
+template <int NCELL, typename CP>
+__device__ __forceinline__ void rotate_block(const double (&old)[NCELL][RT_RMAX], const double (&e)[NCELL], CP Cc,
+                                             int r, int k, double *X, int ld, const int (&c)[NCELL],
                                              const bool (&ok)[NCELL]) {
 #pragma unroll 1
   for (int j0 = 0; j0 < k; j0 += 4) {

@@ -106,17 +106,15 @@ __global__ void __launch_bounds__(256) k_rom_post_small(const Inst *__restrict__
 // k_rom_update: U <- [U, p/nu] Uc, W <- [W, b] Vc (App. B), grid (cell
 // blocks, instance, 4) with z = 2 * ROM + (0: U, 1: W); each thread rotates
 // UPD_CPT cells (strided by the block width, so every load is coalesced).
-// Every cell's arithmetic is the same whatever UPD_CPT: one cell per thread
-// spreads a small launch over more compute units, four per thread cut the
-// LDS reads of the coefficients in a large one.
+// The coefficients are the same for every cell of a block and were written
+// by an earlier launch, so they are read through the constant address space:
+// scalar loads into scalar registers, which leaves the vector registers to
+// the cells' basis rows (occupancy) and needs no LDS staging.
 // ---------------------------------------------------------------------------
-constexpr int UPD_BLK = 64;
-template <int UPD_CPT>
+#define RT_CONST __attribute__((address_space(4)))
+template <int UPD_BLK, int UPD_CPT>
 __global__ void __launch_bounds__(UPD_BLK) k_rom_update(const Inst *__restrict__ insts) {
   const Inst &I = insts[blockIdx.y];
-  // four spare entries: the column blocks of the rotation read up to three
-  // entries past the last row (discarded products)
-  __shared__ double cc[RT_KC * RT_KC + 4], a2[RT_RMAX];
   if (I.method != RT_ROM) return;
   const int cb = blockIdx.x * UPD_BLK * UPD_CPT;
   if (cb >= I.nc) return;
@@ -124,10 +122,8 @@ __global__ void __launch_bounds__(UPD_BLK) k_rom_update(const Inst *__restrict__
   const RomDev &R = rom ? I.pc : I.ig;
   const RomPend &P = *R.pend;
   if (!P.pending) return;
-  const double *src = mat ? P.Vc : P.Uc;
-  for (int e = threadIdx.x; e < RT_KC * RT_KC; e += blockDim.x) cc[e] = ldg(&src[e]);
-  if (threadIdx.x < RT_RMAX) a2[threadIdx.x] = ldg(&P.a2[threadIdx.x]);
-  __syncthreads();
+  const RT_CONST double *cc = (const RT_CONST double *)(mat ? P.Vc : P.Uc);
+  const RT_CONST double *a2 = (const RT_CONST double *)P.a2;
   const int r = P.r_old, ld = I.ld;
   double *X = mat ? R.W : R.U;
   // the cells' old basis rows up to r, all loads in flight together (zero
@@ -177,12 +173,10 @@ extern "C" hipError_t rt_launch_rom_slab(const Inst *dinsts, int ninst, int any_
 
 extern "C" hipError_t rt_launch_rom_update(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream) {
   if ((long long)nc_max * ninst <= 65536) {
-    hipLaunchKernelGGL(k_rom_update<1>, dim3((nc_max + UPD_BLK - 1) / UPD_BLK, ninst, 4), dim3(UPD_BLK), 0, stream,
-                       dinsts);
+    // small: one cell per thread in narrow blocks, spread over many CUs
+    hipLaunchKernelGGL((k_rom_update<64, 1>), dim3((nc_max + 63) / 64, ninst, 4), dim3(64), 0, stream, dinsts);
   } else {
-    const int cells = UPD_BLK * 4;
-    hipLaunchKernelGGL(k_rom_update<4>, dim3((nc_max + cells - 1) / cells, ninst, 4), dim3(UPD_BLK), 0, stream,
-                       dinsts);
+    hipLaunchKernelGGL((k_rom_update<256, 1>), dim3((nc_max + 255) / 256, ninst, 4), dim3(256), 0, stream, dinsts);
   }
   return hipGetLastError();
 }
