@@ -647,9 +647,11 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps, int n, int nsteps) 
         rt_prof_begin(RT_K_POST, s2);
         RT_HIP(rt_launch_rom_slab(dinsts, n, any_fused, nc_grid, s2), "ROM launch");
         rt_prof_end(RT_K_POST, s2);
-        rt_prof_begin(RT_K_ROM_UPDATE, s2);
-        RT_HIP(rt_launch_rom_update(dinsts, n, nc_max, s2), "ROM update launch");
-        rt_prof_end(RT_K_ROM_UPDATE, s2);
+        if (nc_grid > 0) {  // instances without a fused post
+          rt_prof_begin(RT_K_ROM_UPDATE, s2);
+          RT_HIP(rt_launch_rom_update(dinsts, n, nc_grid, s2), "ROM update launch");
+          rt_prof_end(RT_K_ROM_UPDATE, s2);
+        }
       }
       rt_prof_begin(RT_K_SLAB_FPASS, s);
       RT_HIP(rt_launch_slab_fpass(dinsts, n, nt, cmax, npair_max, nc_max, pairs_total, s), "f-pass launch");

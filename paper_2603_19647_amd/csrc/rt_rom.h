@@ -754,30 +754,30 @@ __device__ __forceinline__ double second_residual(double v, const double (&old)[
 // product runs over the full capacity without branches.  Cc is either LDS
 // (each read serves NCELL cells) or the constant address space (uniform
 // addresses: scalar loads, the products take them as scalar operands); the
-// outputs go in blocks of four columns, which bounds the registers the
+// outputs go in blocks of JB columns, which bounds the registers the
 // coefficients take.
-template <int NCELL, typename CP>
+template <int NCELL, typename CP, int JB = 4>
 __device__ __forceinline__ void rotate_block(const double (&old)[NCELL][RT_RMAX], const double (&e)[NCELL], CP Cc,
                                              int r, int k, double *X, int ld, const int (&c)[NCELL],
                                              const bool (&ok)[NCELL]) {
 #pragma unroll 1
-  for (int j0 = 0; j0 < k; j0 += 4) {
-    double acc[NCELL][4];
+  for (int j0 = 0; j0 < k; j0 += JB) {
+    double acc[NCELL][JB];
 #pragma unroll
     for (int i = 0; i < NCELL; ++i)
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) acc[i][jj] = 0.0;
+      for (int jj = 0; jj < JB; ++jj) acc[i][jj] = 0.0;
 #pragma unroll
     for (int q = 0; q < RT_RMAX; ++q)
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
+      for (int jj = 0; jj < JB; ++jj) {
         const double cf = Cc[q * RT_KC + j0 + jj];
 #pragma unroll
         for (int i = 0; i < NCELL; ++i) acc[i][jj] = rt_fma(old[i][q], cf, acc[i][jj]);
       }
     // row r: the new direction (p / nu for U, b for W)
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
+    for (int jj = 0; jj < JB; ++jj) {
       const double cf = Cc[r * RT_KC + j0 + jj];
 #pragma unroll
       for (int i = 0; i < NCELL; ++i) acc[i][jj] = rt_fma(e[i], cf, acc[i][jj]);
@@ -786,11 +786,44 @@ __device__ __forceinline__ void rotate_block(const double (&old)[NCELL][RT_RMAX]
     for (int i = 0; i < NCELL; ++i)
       if (ok[i])
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj)
+        for (int jj = 0; jj < JB; ++jj)
           if (j0 + jj < k) stg(&X[(size_t)(j0 + jj) * ld + c[i]], acc[i][jj]);
   }
 }
 
+
+// The pending rotation of ROM R's two bases, applied by the workgroup whose
+// core just decided it (the fused post of a small instance): every cell of
+// the instance, U then W, with the same per-cell arithmetic as k_rom_update.
+// The rotation record was written by this workgroup in this launch, so it is
+// read with vector loads and the coefficients staged in LDS (sm.Mx, sm.av:
+// free once the core is done).
+__device__ inline void rom_rotate_own(const Inst &I, const RomDev &R, const RomWork &W, RomSmem &sm) {
+  const RomPend *P = R.pend;
+  __syncthreads();
+  if (!xload(&P->pending)) return;  // uniform
+  const int r = xload(&P->r_old), k = xload(&P->k), nc = I.nc, ld = I.ld, NT = blockDim.x;
+  const double inv_nu = xload(&P->inv_nu);
+  double *cc = sm.Mx, *a2 = sm.av;
+  for (int mat = 0; mat < 2; ++mat) {
+    const double *src = mat ? P->Vc : P->Uc;
+    for (int e = threadIdx.x; e < RT_KC * RT_KC; e += NT) cc[e] = ldg(&src[e]);
+    if (threadIdx.x < RT_RMAX) a2[threadIdx.x] = ldg(&P->a2[threadIdx.x]);
+    __syncthreads();
+    double *X = mat ? R.W : R.U;
+    for (int c0 = 0; c0 < nc; c0 += NT) {
+      int cv[1] = {c0 + (int)threadIdx.x};
+      bool ok[1] = {cv[0] < nc};
+      const int cl = ok[0] ? cv[0] : nc - 1;
+      double old[1][RT_RMAX], e[1];
+#pragma unroll
+      for (int q = 0; q < RT_RMAX; ++q) old[0][q] = q < r ? ldg(&X[(size_t)q * ld + cl]) : 0.0;
+      e[0] = mat ? ldg(&W.b[cl]) : second_residual(ldg(&W.p[cl]), old[0], a2) * inv_nu;
+      rotate_block<1, double *, 2>(old, e, cc, r, k, X, ld, cv, ok);  // two columns a block: registers
+    }
+    __syncthreads();
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Per-thread partial sums of ||rho^n||^2, ||rho^(0) - rho^n||^2 and

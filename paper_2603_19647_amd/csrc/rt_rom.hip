@@ -79,13 +79,16 @@ __global__ void __launch_bounds__(256) k_rom_core(const Inst *__restrict__ insts
 }
 
 // ---------------------------------------------------------------------------
-// k_rom_post_small: the whole incremental-SVD update but the rotation for a
-// small instance (the slab path, whose SI kernel already took the step's
-// decisions), one workgroup per (instance, ROM): the two passes with
-// workgroup reductions (one partial row), then the core.  One launch instead
-// of three, and no grid-wide partial sums.
+// k_rom_post_small: the whole incremental-SVD update of a small instance (the
+// slab path, whose SI kernel already took the step's decisions), one
+// workgroup per (instance, ROM): the two passes with workgroup reductions
+// (one partial row), the core, then the rotation of the ROM's two bases.  One
+// launch instead of four, no grid-wide partial sums, and the rotation's
+// traffic overlaps the f-pass that runs beside this launch.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_rom_post_small(const Inst *__restrict__ insts) {
+// two workgroups per CU: the registers stay within half the file
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_rom_post_small(
+    const Inst *__restrict__ insts) {
   const Inst &I = insts[blockIdx.x];
   if (I.method != RT_ROM || !I.post_fused) return;
   const int z = blockIdx.y;
@@ -100,6 +103,7 @@ __global__ void __launch_bounds__(256) k_rom_post_small(const Inst *__restrict__
   rom_pass2<false>(I, R, W, 0, 1, red, out, av, scratch);
   __syncthreads();
   rom_core<false>(I, R, W, z, sm);
+  rom_rotate_own(I, R, W, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -115,7 +119,7 @@ __global__ void __launch_bounds__(256) k_rom_post_small(const Inst *__restrict__
 template <int UPD_BLK, int UPD_CPT>
 __global__ void __launch_bounds__(UPD_BLK) k_rom_update(const Inst *__restrict__ insts) {
   const Inst &I = insts[blockIdx.y];
-  if (I.method != RT_ROM) return;
+  if (I.method != RT_ROM || I.post_fused) return;  // fused posts rotate their own bases
   const int cb = blockIdx.x * UPD_BLK * UPD_CPT;
   if (cb >= I.nc) return;
   const int rom = blockIdx.z >> 1, mat = blockIdx.z & 1;
