@@ -797,7 +797,9 @@ __device__ __forceinline__ void rotate_block(const double (&old)[NCELL][RT_RMAX]
 // the instance, U then W, with the same per-cell arithmetic as k_rom_update.
 // The rotation record was written by this workgroup in this launch, so it is
 // read with vector loads and the coefficients staged in LDS (sm.Mx, sm.av:
-// free once the core is done).
+// free once the core is done).  Each coefficient read from LDS serves two
+// cells of a thread (LDS bandwidth bounds this loop), in blocks of two
+// columns (registers).
 __device__ inline void rom_rotate_own(const Inst &I, const RomDev &R, const RomWork &W, RomSmem &sm) {
   const RomPend *P = R.pend;
   __syncthreads();
@@ -811,15 +813,20 @@ __device__ inline void rom_rotate_own(const Inst &I, const RomDev &R, const RomW
     if (threadIdx.x < RT_RMAX) a2[threadIdx.x] = ldg(&P->a2[threadIdx.x]);
     __syncthreads();
     double *X = mat ? R.W : R.U;
-    for (int c0 = 0; c0 < nc; c0 += NT) {
-      int cv[1] = {c0 + (int)threadIdx.x};
-      bool ok[1] = {cv[0] < nc};
-      const int cl = ok[0] ? cv[0] : nc - 1;
-      double old[1][RT_RMAX], e[1];
+    for (int c0 = 0; c0 < nc; c0 += 2 * NT) {
+      int cv[2];
+      bool ok[2];
+      double old[2][RT_RMAX], e[2];
 #pragma unroll
-      for (int q = 0; q < RT_RMAX; ++q) old[0][q] = q < r ? ldg(&X[(size_t)q * ld + cl]) : 0.0;
-      e[0] = mat ? ldg(&W.b[cl]) : second_residual(ldg(&W.p[cl]), old[0], a2) * inv_nu;
-      rotate_block<1, double *, 2>(old, e, cc, r, k, X, ld, cv, ok);  // two columns a block: registers
+      for (int i = 0; i < 2; ++i) {
+        cv[i] = c0 + i * NT + (int)threadIdx.x;
+        ok[i] = cv[i] < nc;
+        const int cl = ok[i] ? cv[i] : nc - 1;
+#pragma unroll
+        for (int q = 0; q < RT_RMAX; ++q) old[i][q] = q < r ? ldg(&X[(size_t)q * ld + cl]) : 0.0;
+        e[i] = mat ? ldg(&W.b[cl]) : second_residual(ldg(&W.p[cl]), old[i], a2) * inv_nu;
+      }
+      rotate_block<2, double *, 2>(old, e, cc, r, k, X, ld, cv, ok);
     }
     __syncthreads();
   }
