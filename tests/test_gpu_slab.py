@@ -44,13 +44,15 @@ def test_slab256_rom_fp64():
     assert st["n0"] > 0 and st["n1"] > 0
 
 
-@pytest.mark.parametrize("nv", [16, 64])
-def test_single_workgroup_mode_rom_fp64(nv):
+@pytest.mark.parametrize("nx,nv", [(700, 16), (700, 64), (3000, 16)])
+def test_single_workgroup_mode_rom_fp64(nx, nv):
     """The one-workgroup SI kernel (batches, served problems, RTROM_F_SINGLE_WG)
     against the oracle.  A problem marched on its own by default splits its
-    ordinate pairs over workgroups; the other tests cover that mode."""
-    spec = W.random_slab(31, 700, nv, method="rom", precision="fp64", single_wg=True)
-    say(f"single-workgroup rom fp64 700x{nv}")
+    ordinate pairs over workgroups; the other tests cover that mode.  Up to
+    2048 cells the ROM post (passes, core, rotation) is one workgroup per
+    ROM; 3000 cells takes the grid-wide passes and rotation."""
+    spec = W.random_slab(31, nx, nv, method="rom", precision="fp64", single_wg=True)
+    say(f"single-workgroup rom fp64 {nx}x{nv}")
     errs, o, g = step_both(spec, 30)
     assert errs.max() <= FP64_TOL, errs.max()
     assert_same_decisions(o, g)
@@ -167,7 +169,8 @@ def test_batch_equals_alone_bitwise():
     specs = [W.random_slab(20 + k, nx, nv, method=m, precision=pr)
              for k, (nx, nv, m, pr) in enumerate([(128, 16, "rom", "mixed"), (700, 32, "rom", "fp64"),
                                                    (2048, 64, "si_dsa", "mixed"), (333, 16, "si_dsa", "fp64"),
-                                                   (1500, 32, "rom", "mixed"), (64, 64, "rom", "fp64")])]
+                                                   (1500, 32, "rom", "mixed"), (64, 64, "rom", "fp64"),
+                                                   (2500, 16, "rom", "mixed")])]
     say("batch vs alone")
     batch = [rtrom.Problem(s) for s in specs]
     rtrom.march_batch(batch, 25)
