@@ -568,8 +568,18 @@ static rtrom_status read_state(const rtrom_problem *p, RtState *st) {
   return RTROM_OK;
 }
 
-static rtrom_status march_one_kind(rtrom_problem *const *ps, int n, int nsteps) {
-  // all handles of one dimension; 1D: fused launches over the instance array
+static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nsteps) {
+  // all handles of one dimension; 1D: fused launches over the instance array.
+  // A 1D batch is laid out largest first (cells x ordinate pairs): workgroups
+  // are dispatched in instance order, so the longest ones start first and
+  // the launches' tails shorten.  Every instance computes the same thing
+  // wherever it sits.
+  std::vector<rtrom_problem *> order(ps_in, ps_in + n);
+  if (n > 1 && ps_in[0]->d.dim == 1)
+    std::stable_sort(order.begin(), order.end(), [](const rtrom_problem *a, const rtrom_problem *b) {
+      return (long long)a->nc * a->hinst.npair > (long long)b->nc * b->hinst.npair;
+    });
+  rtrom_problem *const *ps = order.data();
   hipStream_t s = ps[0]->stream;
   for (int i = 0; i < n; ++i)
     if (ps[i]->stream != s) RT_HIP(hipStreamSynchronize(ps[i]->stream), "sync member stream");
