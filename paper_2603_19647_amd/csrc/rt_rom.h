@@ -2,12 +2,15 @@
 // eq. dmd-operator, eq. dmd-ig, eq. dmd-sa) and the incremental SVD update
 // (App. B, eq. svd_core) with the reduced operator kept incrementally.
 //
-// The O(N r) projections, the (r+1)^2 core SVD and the r x r LU run in one
-// workgroup per instance (k_post); the O(N r^2) basis update
-// U <- [U q] U_c, W <- [W b] V_c runs as its own grid-wide kernel
-// (k_rom_update) from the "pending update" the workgroup leaves behind.
-// Cells are owned with a stride (c = tid, tid + NT, ...) so that every pass
-// over a basis column is a coalesced stream.
+// The O(N r) projection passes run grid-wide (k_rom_pass1/2, or at the end
+// of the cooperative SI kernel) or, for a small slab, inside one workgroup
+// per (instance, ROM) (k_rom_post_small); the (r+1)^2 core SVD and the r x r
+// LU run in one workgroup per ROM.  The O(N r^2) basis rotation
+// U <- [U q] U_c, W <- [W b] V_c applies the "pending update" the core leaves
+// behind: grid-wide (k_rom_update, the cooperative step tail) or, for a
+// small slab, by the same post workgroup (rom_rotate_own).  Cells are owned
+// with a stride (c = tid, tid + NT, ...) so that every pass over a basis
+// column is a coalesced stream.
 #pragma once
 #include "rt_arrow.h"
 #include "rt_common.h"
