@@ -143,8 +143,11 @@ rtrom_status rtrom_march(rtrom_problem *p, int32_t nsteps);
 
 /* Advance every problem of `ps` (n >= 1 distinct handles, any mix of sizes
  * and ordinate counts of the same dimension) by nsteps, fusing them into
- * shared launches (one workgroup per 1D instance).  All handles must live on
- * the same device.  ENOCONV if any step of any problem hit max_iter. */
+ * shared launches (one workgroup per 1D instance, the largest dispatched
+ * first).  Each problem's result is bitwise what it gets marched alone in
+ * one-workgroup mode, whatever it is batched with and wherever it sits in
+ * `ps`.  All handles must live on the same device.  ENOCONV if any step of
+ * any problem hit max_iter. */
 rtrom_status rtrom_march_batch(rtrom_problem *const *ps, int32_t n, int32_t nsteps);
 
 /* rho^n (the converged density of the last step, Alg. 1's returned iterate),
