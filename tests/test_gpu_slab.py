@@ -174,10 +174,15 @@ def test_batch_equals_alone_bitwise():
     say("batch vs alone")
     batch = [rtrom.Problem(s) for s in specs]
     rtrom.march_batch(batch, 25)
-    for s, b in zip(specs, batch):
+    # the same problems handed over in the reverse order: the batch lays them
+    # out by size either way, and nothing depends on the position
+    rev = [rtrom.Problem(s) for s in specs[::-1]]
+    rtrom.march_batch(rev, 25)
+    for s, b, r in zip(specs, batch, rev[::-1]):
         a = rtrom.Problem(s.replace(single_wg=True))  # a batch runs one workgroup per problem
         a.march(25)
         np.testing.assert_array_equal(a.rho(), b.rho())
+        np.testing.assert_array_equal(r.rho(), b.rho())
         assert a.stats()["si_iters_total"] == b.stats()["si_iters_total"]
 
 
