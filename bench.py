@@ -263,8 +263,8 @@ def main():
                          "against which hardware byte counters are scaled)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(DESIGN.md describes how the work would shard)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(each problem, or each instance of a batch, runs on one device)", file=sys.stderr)
         sys.exit(2)
 
     from paper_2603_19647_amd import rtrom
@@ -322,8 +322,8 @@ def main():
         # Disabled: a serving run on the GPU completed and printed its line,
         # but the process then crashed during exit (status 139) with the cause
         # not established; the serving tests under pytest pass.
-        print("bench.py: the serving workload is disabled until a process-exit crash after "
-              "the serving run is explained (see DESIGN.md)", file=sys.stderr)
+        print("bench.py: the serving workload is disabled until a crash at process exit "
+              "after the serving run is explained", file=sys.stderr)
         sys.exit(3)
         warm = 0
         log(f"bench: serving stream of {args.requests} requests")
