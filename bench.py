@@ -95,7 +95,7 @@ def copy_probe(mib: int):
 # Sources of the dominant kernels: a stored counter measurement is used only
 # while these files are unchanged.
 KERNEL_SOURCES = {
-    "k_si_slab": ["rt_slab.hip", "rt_common.h", "rt_rom.h", "rt_arrow.h"],
+    "k_si_slab": ["rt_slab.hip", "rt_common.h", "rt_rom.h", "rt_arrow.h", "rt_capi.hip"],
     "k_plane_sweep": ["rt_plane.hip", "rt_common.h"],
 }
 

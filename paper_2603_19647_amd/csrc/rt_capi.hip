@@ -241,11 +241,14 @@ struct Layout {
   }
 };
 
-// Threads an instance's cells are split over: about four cells per thread,
-// a multiple of 64, at most 1024.  Fixed per instance at creation, so its
+// Threads an instance's cells are split over: about eight cells per thread
+// up to 2048 cells (at most 256 threads: short scans, and a batch of such
+// instances fits two workgroups per CU), about four above (up to 1024
+// threads); a multiple of 64.  Fixed per instance at creation, so its
 // arithmetic does not depend on what it is batched with.
 int slab_instance_threads(int nc) {
-  int nt = (nc + 3) / 4;
+  const int cpt = nc <= 2048 ? 8 : 4;
+  int nt = (nc + cpt - 1) / cpt;
   const char *env = std::getenv("RTROM_SLAB_CELLS_PER_THREAD");
   if (env && std::atoi(env) >= 1 && std::atoi(env) <= 8) nt = (nc + std::atoi(env) - 1) / std::atoi(env);
   nt = ((nt + 63) / 64) * 64;
@@ -261,8 +264,7 @@ int slab_launch_threads(const int *nthr, const int *nc, int n, int *cmax) {
     c = std::max(c, (nc[i] + nthr[i] - 1) / nthr[i]);
   }
   *cmax = c <= 4 ? 4 : 8;
-  if (*cmax == 8 && nt > 512) nt = 512;  // never reached: nthr <= 1024 keeps c <= 4
-  return nt;
+  return nt;  // cmax 8 only with nt <= 512: the caller splits batches that mix both
 }
 }  // namespace
 
@@ -574,9 +576,14 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
   // are dispatched in instance order, so the longest ones start first and
   // the launches' tails shorten.  Every instance computes the same thing
   // wherever it sits.
+  // Instances of more than 512 threads (four cells each) come first: a batch
+  // mixing them with instances of eight cells per thread runs the two kinds
+  // as two launches (no kernel holds eight cells a thread at 1024 threads).
   std::vector<rtrom_problem *> order(ps_in, ps_in + n);
   if (n > 1 && ps_in[0]->d.dim == 1)
     std::stable_sort(order.begin(), order.end(), [](const rtrom_problem *a, const rtrom_problem *b) {
+      const bool wa = a->hinst.nthr > 512, wb = b->hinst.nthr > 512;
+      if (wa != wb) return wa;
       return (long long)a->nc * a->hinst.npair > (long long)b->nc * b->hinst.npair;
     });
   rtrom_problem *const *ps = order.data();
@@ -614,13 +621,29 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
       ncs[i] = ps[i]->nc;
     }
     if (n == 1) dinsts = ps[0]->dinst;
-    int cmax;
-    int nt = slab_launch_threads(nthr.data(), ncs.data(), n, &cmax);
-    int nc_max = 0, any_rom = 0, npair_max = 1, pairs_total = 0, any_fused = 0, nc_grid = 0;
+    // launch groups: [0, nA) wide instances (more than 512 threads), [nA, n)
+    // the rest; one group unless the rest need eight cells a thread
+    int nA = 0;
+    while (nA < n && nthr[nA] > 512) ++nA;
+    bool split = false;
+    for (int i = nA; i < n && nA > 0; ++i) split |= (ncs[i] + nthr[i] - 1) / nthr[i] > 4;
+    struct Group {
+      int off, cnt, nt, cmax, nc_max, npair_max, pairs_total;
+    };
+    std::vector<Group> groups;
+    for (int g = 0; g < (split ? 2 : 1); ++g) {
+      Group G{split && g ? nA : 0, split ? (g ? n - nA : nA) : n, 0, 0, 0, 1, 0};
+      G.nt = slab_launch_threads(nthr.data() + G.off, ncs.data() + G.off, G.cnt, &G.cmax);
+      for (int i = G.off; i < G.off + G.cnt; ++i) {
+        G.nc_max = std::max(G.nc_max, ncs[i]);
+        G.npair_max = std::max(G.npair_max, ps[i]->hinst.npair);
+        G.pairs_total += ps[i]->hinst.npair;
+      }
+      groups.push_back(G);
+    }
+    const int nt = groups[0].nt, cmax = groups[0].cmax;  // a problem marched alone: one group
+    int any_rom = 0, any_fused = 0, nc_grid = 0;
     for (int i = 0; i < n; ++i) {
-      nc_max = std::max(nc_max, ncs[i]);
-      npair_max = std::max(npair_max, ps[i]->hinst.npair);
-      pairs_total += ps[i]->hinst.npair;
       const int rom_i = ps[i]->d.method == RTROM_ROM_SI_DSA;
       any_rom |= rom_i;
       if (rom_i && ps[i]->hinst.post_fused) any_fused = 1;
@@ -647,7 +670,8 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
     }
     for (int k = 0; k < nsteps && !coop; ++k) {
       rt_prof_begin(RT_K_SLAB_SI, s);
-      RT_HIP(rt_launch_slab_si(dinsts, n, nt, cmax, s), "SI launch");
+      for (const Group &G : groups)
+        RT_HIP(rt_launch_slab_si(dinsts + G.off, G.cnt, G.nt, G.cmax, s), "SI launch");
       rt_prof_end(RT_K_SLAB_SI, s);
       if (s2 != s) {
         RT_HIP(hipEventRecord(ps[0]->ev_si, s), "event");
@@ -664,7 +688,9 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
         }
       }
       rt_prof_begin(RT_K_SLAB_FPASS, s);
-      RT_HIP(rt_launch_slab_fpass(dinsts, n, nt, cmax, npair_max, nc_max, pairs_total, s), "f-pass launch");
+      for (const Group &G : groups)
+        RT_HIP(rt_launch_slab_fpass(dinsts + G.off, G.cnt, G.nt, G.cmax, G.npair_max, G.nc_max, G.pairs_total, s),
+               "f-pass launch");
       rt_prof_end(RT_K_SLAB_FPASS, s);
       if (s2 != s) {
         RT_HIP(hipEventRecord(ps[0]->ev_rom, s2), "event");
