@@ -87,6 +87,8 @@ def lib():
     L.orc_jacobi_svd.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, _D]
     L.orc_lu_factor.argtypes = [ctypes.c_int, _D, ctypes.POINTER(ctypes.c_int)]
     L.orc_lu_solve.argtypes = [ctypes.c_int, _D, ctypes.POINTER(ctypes.c_int), _D]
+    L.orc_get_step_vectors.argtypes = [vp, _D, _D, _D, _D]
+    L.orc_get_rom.argtypes = [vp, ctypes.c_int, _D, _D, _D]
     L.orc_rom_new.restype = vp
     L.orc_rom_new.argtypes = [ctypes.c_int, ctypes.c_int]
     L.orc_rom_delete.argtypes = [vp]
@@ -255,6 +257,25 @@ class OracleProblem:
         m = lib().orc_get_history(self.h, arr, n)
         keys = [k for k, _ in StepRec._fields_]
         return {k: np.array([getattr(arr[i], k) for i in range(m)]) for k in keys}
+
+    def step_vectors(self) -> dict:
+        """rho^{(0)}, rho^{(1/2)}, the ROM correction delta rho^{(1)}_DMD (zero
+        unless applied), b~^{n-1} and whether the correction was applied, for
+        the last step."""
+        v = [np.zeros(self.nc) for _ in range(4)]
+        used = lib().orc_get_step_vectors(self.h, *(_p(a) for a in v))
+        return dict(rho0=v[0], rhalf=v[1], dpc=v[2], bt_prev=v[3], used_pc=bool(used))
+
+    def rom(self, which: str):
+        """(U, S, W) of the problem's IG (``"ig"``) or PC (``"pc"``) ROM, with
+        the basis and W = B V as columns."""
+        z = {"ig": 0, "pc": 1}[which]
+        r = lib().orc_get_rom(self.h, z, _D(), _D(), _D())
+        U = np.zeros((max(r, 1), self.nc))
+        Wm = np.zeros((max(r, 1), self.nc))
+        S = np.zeros(max(r, 1))
+        lib().orc_get_rom(self.h, z, _p(U), _p(S), _p(Wm))
+        return U[:r].T.copy(), S[:r].copy(), Wm[:r].T.copy()
 
     def set_inflow(self, g):
         g = np.ascontiguousarray(g, dtype=np.float64)

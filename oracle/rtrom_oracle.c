@@ -496,6 +496,11 @@ typedef struct {
   int64_t ig_updates, pc_updates;
   orc_step_rec *hist;
   int64_t hist_cap;
+  /* vectors of the last step, kept for the pins of Alg. 2: rho^{(0)},
+   * rho^{(1/2)}, the ROM correction delta rho^{(1)}_DMD (zero when the step
+   * did not apply it) and b~^{n-1} */
+  double *last_rho0, *last_rhalf, *last_dpc, *last_bt;
+  int last_used_pc;
   /* work */
   double *w0, *w1, *w2, *w3, *w4, *w5, *w6, *fcol;
 } orc_problem;
@@ -760,6 +765,14 @@ void *orc_create(const orc_desc *d) {
   P->w5 = (double *)malloc(sizeof(double) * nc);
   P->w6 = (double *)malloc(sizeof(double) * nc);
   P->fcol = (double *)malloc(sizeof(double) * nc);
+  P->last_rho0 = (double *)calloc(nc, sizeof(double));
+  P->last_rhalf = (double *)calloc(nc, sizeof(double));
+  P->last_dpc = (double *)calloc(nc, sizeof(double));
+  P->last_bt = (double *)calloc(nc, sizeof(double));
+  if (!P->last_rho0 || !P->last_rhalf || !P->last_dpc || !P->last_bt) {
+    orc_destroy(P);
+    return NULL;
+  }
   if (!P->ox || !P->oy || !P->oz || !P->w || !P->ss || !P->sa || !P->G || !P->ct ||
       !P->f || !P->rho || !P->bt || !P->w0 || !P->w1 || !P->w2 || !P->w3 || !P->w4 ||
       !P->w5 || !P->w6 || !P->fcol) {
@@ -804,6 +817,7 @@ void orc_destroy(void *h) {
   rom_free(&P->ig);
   rom_free(&P->pc);
   free(P->hist);
+  free(P->last_rho0); free(P->last_rhalf); free(P->last_dpc); free(P->last_bt);
   free(P);
 }
 
@@ -977,6 +991,11 @@ int orc_step(void *h) {
     }
   }
   if (P->steps <= P->hist_cap) P->hist[P->steps - 1] = rec;
+  memcpy(P->last_rho0, rho0, sizeof(double) * nc);
+  memcpy(P->last_rhalf, rhalf, sizeof(double) * nc);
+  memcpy(P->last_dpc, dpc_keep, sizeof(double) * nc);
+  memcpy(P->last_bt, bt_prev, sizeof(double) * nc);
+  P->last_used_pc = used_pc;
   free(bt_prev);
   free(dpc_keep);
   free(scratch);
@@ -1068,4 +1087,25 @@ double orc_dsa_entry(void *h, int r, int c) { return dsa_entry((orc_problem *)h,
 /* one sweep of ordinate j with an arbitrary per-cell source */
 void orc_sweep(void *h, int j, const double *s, int zero_inflow, double *out) {
   sweep_one((orc_problem *)h, j, s, zero_inflow, out);
+}
+/* rho^{(0)}, rho^{(1/2)}, delta rho^{(1)}_DMD and b~^{n-1} of the last step;
+ * returns 1 if that step applied the ROM correction (eq. dmd-sa) */
+int orc_get_step_vectors(void *h, double *rho0, double *rhalf, double *dpc, double *bt_prev) {
+  orc_problem *P = (orc_problem *)h;
+  size_t bytes = sizeof(double) * P->nc;
+  memcpy(rho0, P->last_rho0, bytes);
+  memcpy(rhalf, P->last_rhalf, bytes);
+  memcpy(dpc, P->last_dpc, bytes);
+  memcpy(bt_prev, P->last_bt, bytes);
+  return P->last_used_pc;
+}
+/* the problem's ROM (which = 0: initial guess, 1: preconditioner): returns
+ * its rank; U, W get rank columns of nc values each, S rank values */
+int orc_get_rom(void *h, int which, double *U, double *S, double *W) {
+  orc_problem *P = (orc_problem *)h;
+  const orc_rom *m = which ? &P->pc : &P->ig;
+  if (U) memcpy(U, m->U, sizeof(double) * (size_t)m->rank * m->nc);
+  if (W) memcpy(W, m->W, sizeof(double) * (size_t)m->rank * m->nc);
+  if (S) memcpy(S, m->S, sizeof(double) * m->rank);
+  return m->rank;
 }
