@@ -2,27 +2,37 @@
 """Benchmark: time steps/s of ROM-accelerated SI-DSA against plain SI-DSA at a
 1e-8 relative tolerance on one MI355X, printed as one JSON line.
 
-A "step" is one backward-Euler time step of the whole hot path: initial
-guess, source iterations (sweeps + moments + DSA / ROM correction), the final
-f and right-hand-side sweeps, and the ROM bookkeeping (snapshots, incremental
-SVD, DMD operators).  Inputs are synthetic and seeded
-(paper_2603_19647_amd.workloads) and resident on the device before the timed
-region starts.  Both methods run the same kernels at the same precision
-(FP32 sweeps refined by FP64 sweeps, FP64 everything else).
+A "step" is one backward-Euler time step of the whole hot path for every
+instance of the workload: initial guess, source iterations (sweeps + moments
++ DSA / ROM correction), the final f and right-hand-side sweeps, and the ROM
+bookkeeping (snapshots, incremental SVD, DMD operators).  Inputs are synthetic
+and seeded (paper_2603_19647_amd.workloads) and resident on the device before
+the timed region starts.  Both methods run the same kernels at the same
+precision (FP32 sweeps refined by FP64 sweeps, FP64 everything else).
+
+The W warmup steps are the first W steps of the same march (untimed); the K
+timed steps follow them.  A "full_march" block times, on fresh problems, the
+whole configured march of each method (phases I-III inside the timed value).
 
 Workloads (--workload):
+  batch512    512 independent slabs (128..2048 cells, S_16/32/64, 8 regions),
+              dt = 0.01, 100 steps each, fused launches; instance-steps/s
+              (default: the largest single-GPU workload).
   slab4096    4096-cell slab, 64-point Gauss-Legendre, 32 seeded regions,
-              dt = 0.005, 400 steps (default).
+              dt = 0.005, 400 steps.
   checker256  256 x 256 checkerboard, CL(16, 8) = 128 directions, dt = 0.01,
               200 steps.
-  batch512    512 independent slabs (128..2048 cells, S_16/32/64, 8 regions),
-              dt = 0.01, 100 steps each, fused launches; instance-steps/s.
+  serving     stream of 2D requests (grids 64..512 squared, 32..128
+              directions, 100..500 steps): closed-loop capacity, then Poisson
+              arrivals at 80 % of it with per-step, per-march and end-to-end
+              latency percentiles.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -36,106 +46,53 @@ VALU_PEAK_TFLOPS = 78.6     # MI355X FP64 vector; FP32 without packed math issue
 # moment accumulation: 1D  f = (s + m f_in) / (ct + m), rho += w f
 #                       2D  f = (s + mx f_l + my f_b) / (ct + mx + my), rho += w f
 SWEEP_FLOPS = {1: 6, 2: 8}
+# algorithmic HBM bytes (FP64):
+FPASS_BYTES_PER_CELL_ANGLE = 16   # f^{n-1} read, f^n written
+FPASS_BYTES_PER_CELL = 40         # sigma_t, sigma_s, rho^n, G read; b~^n written
+SI_BYTES_PER_CELL = 80            # per step: sigma_t, sigma_s, b~, rho^{n-1}, three DSA factors read;
+                                  # rho^n, rho^(1/2) and the initial guess written
+ROM_BYTES_PER_CELL_COLUMN = 32    # per update and basis column: U and W read and written once
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_single(spec, warmup, steps, rtrom):
-    if warmup > 0:
-        w = rtrom.Problem(spec)
-        w.march(warmup)
-        w.close()
-    p = rtrom.Problem(spec)
-    p.march(0)
-    rtrom.profile_enable(True)
-    t0 = time.perf_counter()
-    p.march(steps)          # returns after the device finished the march
-    t1 = time.perf_counter()
-    prof = rtrom.profile_read()
-    rtrom.profile_enable(False)
-    st = p.stats()
-    p.close()
-    return t1 - t0, st, prof
-
-
-def run_batch(specs, warmup, steps, rtrom):
-    if warmup > 0:
-        ws = [rtrom.Problem(s) for s in specs[:64]]
-        rtrom.march_batch(ws, warmup)
-        for w in ws:
-            w.close()
-    probs = [rtrom.Problem(s) for s in specs]
-    rtrom.profile_enable(True)
-    t0 = time.perf_counter()
-    rtrom.march_batch(probs, steps)
-    t1 = time.perf_counter()
-    prof = rtrom.profile_read()
-    rtrom.profile_enable(False)
-    stats = [p.stats() for p in probs]
-    for p in probs:
-        p.close()
-    return t1 - t0, stats, prof
-
-
-def copy_probe(mib: int):
-    """A plain device-to-device copy of known size (read and write mib MiB each
-    time), for scaling the FETCH_SIZE / WRITE_SIZE counters."""
-    import torch
-    n = mib * (1 << 20) // 8
-    src = torch.ones(n, dtype=torch.float64, device="cuda")
-    dst = torch.empty_like(src)
-    for _ in range(5):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    log(f"bench: copy probe {mib} MiB x 5")
-
-
-# Sources of the dominant kernels: a stored counter measurement is used only
-# while these files are unchanged.
-KERNEL_SOURCES = {
-    "k_si_slab": ["rt_slab.hip", "rt_common.h", "rt_rom.h", "rt_arrow.h", "rt_capi.hip"],
-    "k_plane_sweep": ["rt_plane.hip", "rt_common.h"],
-}
-
-
-def sources_digest(kernel: str) -> str:
-    import hashlib
-    h = hashlib.sha256()
-    base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2603_19647_amd", "csrc")
-    for f in KERNEL_SOURCES.get(kernel, []):
-        with open(os.path.join(base, f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
-
-
-def stored_traffic(kernel: str, workload: str):
-    """HBM bytes per dispatch from profiles/<kernel>_<workload>_traffic.md (two
-    rocprofv3 --pmc runs, FETCH_SIZE and WRITE_SIZE, scaled by the same
-    counters on a copy of known size), or None when absent or when the
-    kernel's sources changed since the counters were taken."""
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", f"{kernel}_{workload}_traffic.md")
-    if not os.path.exists(path):
-        return None
-    digest, value = None, None
-    with open(path) as fh:
-        for line in fh:
-            if line.startswith("sources sha256:"):
-                digest = line.split(":", 1)[1].strip()
-            if line.startswith("HBM bytes per dispatch:"):
-                value = float(line.split(":", 1)[1].strip())
-    return value if digest == sources_digest(kernel) and value is not None else None
+def cpu_info():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
 
 
 def kernel_ms(prof):
     return {k: v[0] / v[1] * 1e3 for k, v in prof.items() if v[1]}
 
 
+def kernel_table(prof, fpass_bytes, si_bytes, rom_bytes):
+    """Per kernel kind: launches, mean duration (HIP events on the launch's
+    stream) and algorithmic HBM GB/s against the 8 TB/s peak."""
+    out = {}
+    for kind, nbytes in (("slab_fpass", fpass_bytes), ("slab_si", si_bytes), ("post", rom_bytes)):
+        sec, n = prof.get(kind, (0.0, 0))
+        if not n:
+            continue
+        gbs = nbytes / sec / 1e9 if sec > 0 else 0.0
+        out[kind] = {"launches": n, "avg_launch_ms": sec / n * 1e3, "algorithmic_bytes_per_launch": nbytes / n,
+                     "achieved_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+    return out
+
+
 def roofline_sweep(prof, kind, dim, updates, kernel):
-    """The dominant kernel is a sweep-bound kernel: FLOP rate of its cell-angle
-    updates (algorithmic FLOPs / event-timed launch duration) against the
-    vector ALU peak."""
+    """The SI sweep kernel is bound by the vector ALU: FLOP rate of its
+    cell-angle updates (algorithmic FLOPs / event-timed launch duration)
+    against the FP64 vector peak."""
     sec, launches = prof[kind]
     flops = SWEEP_FLOPS[dim] * updates
     ach = flops / sec / 1e12
@@ -157,10 +114,228 @@ def roofline_dsa(prof, nc, cheb_iters):
             "bytes_per_launch": bytes_ / launches}
 
 
+# Sources of the dominant kernels: a stored counter measurement is used only
+# while these files are unchanged.
+KERNEL_SOURCES = {
+    "k_si_slab": ["rt_slab.hip", "rt_common.h", "rt_rom.h", "rt_arrow.h", "rt_capi.hip"],
+    "k_plane_sweep": ["rt_plane.hip", "rt_common.h"],
+}
+
+
+def sources_digest(kernel: str) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    base = os.path.join(ROOT, "paper_2603_19647_amd", "csrc")
+    for f in KERNEL_SOURCES.get(kernel, []):
+        with open(os.path.join(base, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel: str, workload: str):
+    """HBM bytes per dispatch from profiles/<kernel>_<workload>_traffic.md (two
+    rocprofv3 --pmc runs, FETCH_SIZE and WRITE_SIZE, scaled by the same
+    counters on a copy of known size), or None when absent or when the
+    kernel's sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    digest, value = None, None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("sources sha256:"):
+                digest = line.split(":", 1)[1].strip()
+            if line.startswith("HBM bytes per dispatch:"):
+                value = float(line.split(":", 1)[1].strip())
+    return value if digest == sources_digest(kernel) and value is not None else None
+
+
+def copy_probe(mib: int):
+    """A plain device-to-device copy of known size (read and write mib MiB each
+    time), for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"bench: copy probe {mib} MiB x 5")
+
+
+# --------------------------------------------------------------------------
+# marches
+# --------------------------------------------------------------------------
+
+def timed_batch(rtrom, specs, warmup, steps, profile=True):
+    """Create the problems, march `warmup` steps untimed, then time `steps`
+    further steps of the same march (fused launches over all instances)."""
+    probs = [rtrom.Problem(s) for s in specs]
+    if warmup > 0:
+        rtrom.march_batch(probs, warmup)
+    if profile:
+        rtrom.profile_enable(True)
+    t0 = time.perf_counter()
+    rtrom.march_batch(probs, steps)   # returns after the device finished
+    t1 = time.perf_counter()
+    prof = rtrom.profile_read() if profile else {}
+    rtrom.profile_enable(False)
+    return t1 - t0, probs, prof
+
+
+def window_updates(probs, ca, first, steps):
+    """Cell-angle SI updates, f-pass and SI bytes, and ROM update columns x
+    cells of steps [first, first + steps) of every problem."""
+    si_upd = 0
+    rom_cell_cols = 0
+    for p, c in zip(probs, ca):
+        h = p.history()
+        it = h["iters"][first:first + steps]
+        si_upd += int(it.sum()) * c
+        for key_u, key_r in (("ig_update", "rank_ig"), ("pc_update", "rank_pc")):
+            upd, rank = h[key_u], h[key_r]
+            for i in range(first, min(first + steps, len(upd))):
+                if upd[i]:
+                    r_old = int(rank[i - 1]) if i > 0 else 0
+                    rom_cell_cols += (r_old + 1) * p.nc
+    return si_upd, rom_cell_cols
+
+
+def bench_batch(rtrom, W, args):
+    specs = W.slab_batch()
+    cfg_steps = specs[0].nsteps
+    steps = cfg_steps if args.steps is None else args.steps
+    warm = 5 if args.warmup is None else args.warmup
+    n = len(specs)
+    res = {}
+    for method in ("rom", "si_dsa"):
+        ms = [s.replace(method=method) for s in specs]
+        log(f"bench: batch512 {method} mixed: {warm} warmup + {steps} timed steps")
+        t, probs, prof = timed_batch(rtrom, ms, warm, steps)
+        ca = [p.nc * p.nv for p in probs]
+        si_upd, rom_cc = window_updates(probs, ca, warm, steps)
+        hist = [p.history() for p in probs]
+        si_sw = sum(int(h["iters"][warm:warm + steps].sum()) for h in hist)
+        res[method] = {"t": t, "prof": prof, "si_upd": si_upd, "rom_cc": rom_cc, "si_sw": si_sw,
+                       "ca": sum(ca), "cells": sum(p.nc for p in probs),
+                       "fp32": sum(p.stats()["fp32_sweeps"] for p in probs)}
+        for p in probs:
+            p.close()
+    R, S = res["rom"], res["si_dsa"]
+    value = n * steps / R["t"]
+    si_val = n * steps / S["t"]
+    roof = roofline_sweep(R["prof"], "slab_si", 1, R["si_upd"], "k_si_slab")
+    kernels = kernel_table(R["prof"], steps * (FPASS_BYTES_PER_CELL_ANGLE * R["ca"] + FPASS_BYTES_PER_CELL * R["cells"]),
+                           steps * SI_BYTES_PER_CELL * R["cells"], ROM_BYTES_PER_CELL_COLUMN * R["rom_cc"])
+    # the whole configured march of both methods, on fresh problems
+    full = {}
+    for method in ("rom", "si_dsa"):
+        ms = [s.replace(method=method) for s in specs]
+        log(f"bench: batch512 {method} mixed: full {cfg_steps}-step march")
+        t, probs, _ = timed_batch(rtrom, ms, 0, cfg_steps, profile=False)
+        hist = [p.history() for p in probs]
+        sts = [p.stats() for p in probs]
+        full[method] = {"instance_steps_per_s": n * cfg_steps / t, "ms_per_step": t / cfg_steps * 1e3,
+                        "si_sweeps_per_step": sum(int(h["iters"].sum()) for h in hist) / (n * cfg_steps),
+                        "fp32_sweeps_per_step": sum(st["fp32_sweeps"] for st in sts) / (n * cfg_steps),
+                        "phase3_instances": sum(1 for st in sts if st["phase"] == 3),
+                        "nonconverged_steps": sum(st["nonconverged_steps"] for st in sts)}
+        for p in probs:
+            p.close()
+    full["speedup_vs_si_dsa"] = full["rom"]["instance_steps_per_s"] / full["si_dsa"]["instance_steps_per_s"]
+    full["steps"] = cfg_steps
+    extra = {
+        "si_dsa_instance_steps_per_s": si_val,
+        "speedup_vs_si_dsa": value / si_val,
+        "cell_angle_updates_per_s": (R["si_upd"] + 2 * steps * R["ca"]) / R["t"],
+        "si_sweeps_per_step": R["si_sw"] / (n * steps),
+        "si_dsa_si_sweeps_per_step": S["si_sw"] / (n * steps),
+        "kernel_ms": kernel_ms(R["prof"]), "si_dsa_kernel_ms": kernel_ms(S["prof"]),
+        "kernels": kernels,
+        "full_march": full,
+    }
+    config = {"workload": "batch512_slabs", "instances": n, "steps": steps, "timed_steps": f"{warm + 1}..{warm + steps}",
+              "cells": "128..2048", "ordinates": "16/32/64", "dt": 0.01, "tol": 1e-8,
+              "method": "rom_si_dsa", "precision": "fp32 sweeps + fp64 refinement",
+              "baseline_method": "si_dsa, same kernels and precision"}
+    metric = "instance time steps/s (ROM-SI-DSA, 1e-8 rel tol)"
+    cpu = None if args.no_cpu_baseline else cpu_baseline_batch(specs, min(steps, 20))
+    return metric, "instance-steps/s", value, R["t"], steps, warm, config, roof, extra, cpu
+
+
+def bench_single(rtrom, W, args):
+    spec = W.slab_random_regions() if args.workload == "slab4096" else W.checkerboard()
+    cfg_steps = spec.nsteps
+    steps = cfg_steps if args.steps is None else args.steps
+    warm = 5 if args.warmup is None else args.warmup
+    nc, nv = spec.ncells, spec.nord
+    res = {}
+    for method in ("rom", "si_dsa"):
+        log(f"bench: {args.workload} {method} mixed: {warm} warmup + {steps} timed steps")
+        p = rtrom.Problem(spec.replace(method=method))
+        if warm:
+            p.march(warm)
+        rtrom.profile_enable(True)
+        t0 = time.perf_counter()
+        p.march(steps)
+        t1 = time.perf_counter()
+        prof = rtrom.profile_read()
+        rtrom.profile_enable(False)
+        h = p.history()
+        st = p.stats()
+        res[method] = {"t": t1 - t0, "prof": prof, "si": int(h["iters"][warm:warm + steps].sum()), "st": st}
+        p.close()
+    full = {}
+    for method in ("rom", "si_dsa"):
+        log(f"bench: {args.workload} {method} mixed: full {cfg_steps}-step march")
+        p = rtrom.Problem(spec.replace(method=method))
+        t0 = time.perf_counter()
+        p.march(cfg_steps)
+        t = time.perf_counter() - t0
+        st = p.stats()
+        full[method] = {"steps_per_s": cfg_steps / t, "si_sweeps_per_step": st["si_iters_total"] / cfg_steps,
+                        "fp32_sweeps_per_step": st["fp32_sweeps"] / cfg_steps, "n0": st["n0"], "n1": st["n1"]}
+        p.close()
+    full["speedup_vs_si_dsa"] = full["rom"]["steps_per_s"] / full["si_dsa"]["steps_per_s"]
+    full["steps"] = cfg_steps
+    R, S = res["rom"], res["si_dsa"]
+    value = steps / R["t"]
+    nfold = nv if spec.dim == 1 else nv // 2   # 2D sweeps the Omega_z > 0 half
+    if spec.dim == 1:
+        roof = roofline_sweep(R["prof"], "slab_si", 1, R["si"] * nc * nv, "k_si_slab")
+    else:
+        kinds = {k: v[0] for k, v in R["prof"].items() if v[1]}
+        if max(kinds, key=kinds.get) == "plane_dsa":
+            roof = roofline_dsa(R["prof"], nc, R["st"]["dsa_iters"])
+        else:
+            roof = roofline_sweep(R["prof"], "plane_sweep", 2, R["si"] * nc * nfold, "k_plane_sweep")
+    extra = {
+        "si_dsa_steps_per_s": steps / S["t"],
+        "speedup_vs_si_dsa": S["t"] / R["t"],
+        "cell_angle_updates_per_s": (R["si"] + 2 * steps) * nc * nv / R["t"],
+        "si_sweeps_per_step": R["si"] / steps,
+        "si_dsa_si_sweeps_per_step": S["si"] / steps,
+        "kernel_ms": kernel_ms(R["prof"]), "si_dsa_kernel_ms": kernel_ms(S["prof"]),
+        "full_march": full,
+    }
+    name = "slab4096_gl64_32regions" if spec.dim == 1 else "checkerboard256_cl16x8"
+    config = {"workload": name, "cells": nc, "ordinates": nv, "dt": spec.dt, "steps": steps,
+              "timed_steps": f"{warm + 1}..{warm + steps}", "tol": spec.tol, "method": "rom_si_dsa",
+              "precision": "fp32 sweeps + fp64 refinement",
+              "baseline_method": "si_dsa, same kernels and precision", "instances": 1}
+    cpu = None if args.no_cpu_baseline else cpu_baseline_single(spec)
+    return "time steps/s (ROM-SI-DSA, 1e-8 rel tol)", "steps/s", value, R["t"], steps, warm, config, roof, extra, cpu
+
+
+# --------------------------------------------------------------------------
+# CPU baseline: the oracle as it stands, on a bounded sample
+# --------------------------------------------------------------------------
+
 def cpu_baseline_single(spec, seconds_budget=20.0):
     """The FP64 oracle (same method) on the host, one core, the first steps of
     the same problem within a time budget."""
     import oracle
+    model, ncpu = cpu_info()
     o = oracle.OracleProblem(spec.replace(precision="fp64"))
     n, t0 = 0, time.perf_counter()
     while n < spec.nsteps and time.perf_counter() - t0 < seconds_budget:
@@ -168,7 +343,8 @@ def cpu_baseline_single(spec, seconds_budget=20.0):
         n += 1
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n} of {spec.nsteps} steps of the same problem, FP64 oracle, one thread"}
+            "sample": f"first {n} of {spec.nsteps} steps of the same problem, FP64 oracle, one thread",
+            "host_cpu": model, "host_cpu_count": ncpu}
 
 
 def _oracle_instance(args):
@@ -179,17 +355,24 @@ def _oracle_instance(args):
     return steps
 
 
-def cpu_baseline_batch(specs, steps, seconds_budget=20.0):
+def cpu_baseline_batch(specs, steps):
     import multiprocessing as mp
-    cores = min(16, os.cpu_count() or 1)
+    model, ncpu = cpu_info()
+    cores = min(16, ncpu)
     sample = specs[: cores * 2]
     t0 = time.perf_counter()
     with mp.get_context("spawn").Pool(cores) as pool:
         done = sum(pool.map(_oracle_instance, [(s, steps) for s in sample]))
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "instance-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(sample)} of the {len(specs)} instances x {steps} steps, FP64 oracle, process pool"}
+            "sample": f"{len(sample)} of the {len(specs)} instances x their first {steps} steps, "
+                      f"FP64 oracle, process pool of {cores}",
+            "host_cpu": model, "host_cpu_count": ncpu}
 
+
+# --------------------------------------------------------------------------
+# serving
+# --------------------------------------------------------------------------
 
 def run_serving(rtrom, W, count, budget, slots, seed=5):
     """C5: closed-loop saturation run (everything submitted at once) gives the
@@ -197,7 +380,6 @@ def run_serving(rtrom, W, count, budget, slots, seed=5):
     latencies and the queueing delay seen by the client."""
     import numpy as np
     specs = W.serving_stream(seed=seed, count=count)
-    # closed loop
     srv = rtrom.Server(hbm_budget_bytes=budget, max_slots=slots)
     t0 = time.perf_counter()
     tickets = [srv.submit(s) for s in specs]
@@ -206,9 +388,9 @@ def run_serving(rtrom, W, count, budget, slots, seed=5):
     for t in tickets:
         srv.fetch(t)
     srv.close()
+    log(f"bench: serving closed loop {t_sat:.2f} s")
     steps_total = sum(s.nsteps for s in specs)
     capacity = count / t_sat
-    # open loop, Poisson arrivals at 0.8 x capacity
     rng = np.random.default_rng(seed + 1000)
     gaps = rng.exponential(1.0 / (0.8 * capacity), size=count)
     srv = rtrom.Server(hbm_budget_bytes=budget, max_slots=slots)
@@ -228,6 +410,7 @@ def run_serving(rtrom, W, count, budget, slots, seed=5):
                 done_t[tk] = time.perf_counter()
         time.sleep(0.0005)
     t_open = time.perf_counter() - t0
+    log(f"bench: serving open loop {t_open:.2f} s")
     step_lat, march_lat, e2e = [], [], []
     for tk in tickets:
         rho, st, lat, mlat = srv.fetch(tk)
@@ -248,12 +431,24 @@ def run_serving(rtrom, W, count, budget, slots, seed=5):
     }
 
 
+def bench_serving(rtrom, W, args):
+    log(f"bench: serving stream of {args.requests} requests")
+    res = run_serving(rtrom, W, args.requests, int(args.budget_gib * (1 << 30)), args.slots)
+    config = {"workload": "serving_stream_grf_2d", "requests": args.requests,
+              "grids": "64..512 squared", "ordinates": "32/64/128", "steps_each": "100..500",
+              "method": "rom_si_dsa", "precision": "fp32 sweeps + fp64 refinement",
+              "arrivals": "closed loop (value), then Poisson at 0.8 x capacity"}
+    return ("instance time steps/s, serving (ROM-SI-DSA, 1e-8 rel tol)", "instance-steps/s",
+            res["saturation_instance_steps_per_s"], res["saturation_s"], res["instance_steps"], 0, config, None,
+            {"serving": res}, None)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", choices=("slab4096", "checker256", "batch512", "serving"), default="slab4096")
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the configured march)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps before them (default 5)")
+    ap.add_argument("--workload", choices=("batch512", "slab4096", "checker256", "serving"), default="batch512")
     ap.add_argument("--requests", type=int, default=24, help="serving: requests in the stream")
     ap.add_argument("--budget-gib", type=float, default=4.0, help="serving: HBM admission budget")
     ap.add_argument("--slots", type=int, default=8, help="serving: concurrent problems")
@@ -263,8 +458,8 @@ def main():
                          "against which hardware byte counters are scaled)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the library has no multi-GPU path "
-              "(each problem, or each instance of a batch, runs on one device)", file=sys.stderr)
+        print("bench.py measures one GPU: every problem, and every instance of a batch, runs on one "
+              "device; runs on several GPUs are not part of this library", file=sys.stderr)
         sys.exit(2)
 
     from paper_2603_19647_amd import rtrom
@@ -272,111 +467,20 @@ def main():
 
     if args.copy_probe > 0:
         copy_probe(args.copy_probe)
-    extra = {}
-    if args.workload in ("slab4096", "checker256"):
-        spec = W.slab_random_regions() if args.workload == "slab4096" else W.checkerboard()
-        steps = spec.nsteps if args.steps is None else args.steps
-        warm = (20 if args.workload == "slab4096" else 5) if args.warmup is None else args.warmup
-        spec = spec.replace(nsteps=steps)
-        nc, nv = spec.ncells, spec.nord
-        log(f"bench: {args.workload} ROM-SI-DSA mixed, {steps} steps")
-        t_rom, st_rom, prof_rom = run_single(spec, warm, steps, rtrom)
-        log(f"bench: {args.workload} SI-DSA mixed, {steps} steps")
-        t_si, st_si, prof_si = run_single(spec.replace(method="si_dsa"), warm, steps, rtrom)
-        value = steps / t_rom
-        si_val = steps / t_si
-        nfold = nv if spec.dim == 1 else nv // 2   # 2D sweeps the Omega_z > 0 half
-        if spec.dim == 1:
-            roof = roofline_sweep(prof_rom, "slab_si", 1, st_rom["si_iters_total"] * nc * nv,
-                                  "k_si_slab")
-        else:
-            kinds = {k: v[0] for k, v in prof_rom.items() if v[1]}
-            if max(kinds, key=kinds.get) == "plane_dsa":
-                roof = roofline_dsa(prof_rom, nc, st_rom["dsa_iters"])
-            else:
-                roof = roofline_sweep(prof_rom, "plane_sweep", 2, st_rom["si_iters_total"] * nc * nfold,
-                                      "k_plane_sweep")
-        extra = {
-            "si_dsa_steps_per_s": si_val,
-            "speedup_vs_si_dsa": value / si_val,
-            "cell_angle_updates_per_s": st_rom["sweeps_total"] * nc * nv / t_rom,
-            "si_sweeps_per_step": st_rom["si_iters_total"] / steps,
-            "si_dsa_si_sweeps_per_step": st_si["si_iters_total"] / steps,
-            "fp32_sweeps": st_rom["fp32_sweeps"], "n0": st_rom["n0"], "n1": st_rom["n1"],
-            "rank_ig": st_rom["rank_ig"], "rank_pc": st_rom["rank_pc"],
-            "nonconverged_steps": st_rom["nonconverged_steps"],
-            "kernel_ms": kernel_ms(prof_rom), "si_dsa_kernel_ms": kernel_ms(prof_si),
-        }
-        if spec.dim == 1:
-            config = {"workload": "slab4096_gl64_32regions", "cells": nc, "ordinates": nv, "dt": spec.dt,
-                      "steps": steps, "tol": spec.tol}
-        else:
-            config = {"workload": "checkerboard256_cl16x8", "cells": nc, "ordinates": nv, "dt": spec.dt,
-                      "steps": steps, "tol": spec.tol}
-        config.update({"method": "rom_si_dsa", "precision": "fp32 sweeps + fp64 refinement",
-                       "baseline_method": "si_dsa, same kernels and precision", "instances": 1})
-        metric = "time steps/s (ROM-SI-DSA, 1e-8 rel tol)"
-        unit = "steps/s"
-        cpu = None if args.no_cpu_baseline else cpu_baseline_single(spec)
+    if args.workload == "batch512":
+        r = bench_batch(rtrom, W, args)
     elif args.workload == "serving":
-        # Disabled: a serving run on the GPU completed and printed its line,
-        # but the process then crashed during exit (status 139) with the cause
-        # not established; the serving tests under pytest pass.
-        print("bench.py: the serving workload is disabled until a crash at process exit "
-              "after the serving run is explained", file=sys.stderr)
-        sys.exit(3)
-        warm = 0
-        log(f"bench: serving stream of {args.requests} requests")
-        res = run_serving(rtrom, W, args.requests, int(args.budget_gib * (1 << 30)), args.slots)
-        steps = res["instance_steps"]
-        value = res["saturation_instance_steps_per_s"]
-        t_rom = res["saturation_s"]
-        roof = None
-        extra = {"serving": res}
-        config = {"workload": "serving_stream_grf_2d", "requests": args.requests,
-                  "grids": "64..512 squared", "ordinates": "32/64/128", "steps_each": "100..500",
-                  "method": "rom_si_dsa", "precision": "fp32 sweeps + fp64 refinement",
-                  "arrivals": "closed loop (value), then Poisson at 0.8 x capacity"}
-        metric = "instance time steps/s, serving (ROM-SI-DSA, 1e-8 rel tol)"
-        unit = "instance-steps/s"
-        cpu = None
+        r = bench_serving(rtrom, W, args)
     else:
-        specs = W.slab_batch()
-        steps = specs[0].nsteps if args.steps is None else args.steps
-        warm = 5 if args.warmup is None else args.warmup
-        log(f"bench: batch512 ROM-SI-DSA mixed, {steps} steps")
-        t_rom, sts, prof_rom = run_batch(specs, warm, steps, rtrom)
-        log(f"bench: batch512 SI-DSA mixed, {steps} steps")
-        t_si, sts_si, prof_si = run_batch([s.replace(method="si_dsa") for s in specs], warm, steps, rtrom)
-        n = len(specs)
-        value = n * steps / t_rom
-        si_val = n * steps / t_si
-        ca = [s.ncells * s.nord for s in specs]
-        si_upd = sum(st["si_iters_total"] * c for st, c in zip(sts, ca))
-        roof = roofline_sweep(prof_rom, "slab_si", 1, si_upd, "k_si_slab")
-        extra = {
-            "si_dsa_instance_steps_per_s": si_val,
-            "speedup_vs_si_dsa": value / si_val,
-            "cell_angle_updates_per_s": sum(st["sweeps_total"] * c for st, c in zip(sts, ca)) / t_rom,
-            "si_sweeps_per_step": sum(st["si_iters_total"] for st in sts) / (n * steps),
-            "si_dsa_si_sweeps_per_step": sum(st["si_iters_total"] for st in sts_si) / (n * steps),
-            "kernel_ms": kernel_ms(prof_rom), "si_dsa_kernel_ms": kernel_ms(prof_si),
-        }
-        config = {"workload": "batch512_slabs", "instances": n, "steps": steps,
-                  "cells": "128..2048", "ordinates": "16/32/64", "dt": 0.01, "tol": 1e-8,
-                  "method": "rom_si_dsa", "precision": "fp32 sweeps + fp64 refinement",
-                  "baseline_method": "si_dsa, same kernels and precision"}
-        metric = "instance time steps/s (ROM-SI-DSA, 1e-8 rel tol)"
-        unit = "instance-steps/s"
-        cpu = None if args.no_cpu_baseline else cpu_baseline_batch(specs, steps)
-
+        r = bench_single(rtrom, W, args)
+    metric, unit, value, t_timed, steps, warm, config, roof, extra, cpu = r
     if roof is not None:
         wl_name = {"slab4096_gl64_32regions": "slab4096", "checkerboard256_cl16x8": "checker256",
                    "batch512_slabs": "batch512"}.get(config.get("workload"), "")
         roof["traffic"] = stored_traffic(roof["kernel"], wl_name)
     out = {
         "metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warm,
-        "ms_per_step": t_rom / steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "ms_per_step": t_timed / steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": config, "roofline": roof, "cpu_baseline": cpu, **extra,
     }

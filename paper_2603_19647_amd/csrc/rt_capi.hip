@@ -268,6 +268,25 @@ int slab_launch_threads(const int *nthr, const int *nc, int n, int *cmax) {
 }
 }  // namespace
 
+// Certification factor of mixed precision: the FP32-refined iterate and its
+// FP64 certification sweep must pass Alg. 1's stop test at theta * tol.  An
+// FP64 run that stops at tol leaves an error anywhere between about the
+// contraction factor times tol and tol itself (in the stop test's own
+// measure), depending on how far below tol its last residual fell; the FP32
+// loop instead stops as soon as its (rounded) residual drops below the
+// threshold, which puts the accepted iterate at the top of that range.
+// Tightening the threshold by theta = 1/8 keeps a mixed result within the
+// distance the FP64 run keeps from the converged solution.  Overridden by
+// RTROM_MIXED_CERT (a factor in (0, 1]) for experiments.
+double rt_mixed_cert_factor() {
+  const char *env = std::getenv("RTROM_MIXED_CERT");
+  if (env) {
+    const double v = std::atof(env);
+    if (v > 0.0 && v <= 1.0) return v;
+  }
+  return 0.125;
+}
+
 // Pair groups of the cooperative slab SI: up to 16 workgroups, each sweeping
 // pg consecutive ordinate pairs.  ng = 0: one workgroup (no cooperation).
 static void slab_groups(const rtrom_problem_desc *d, int nv, int *ng, int *pg) {
@@ -355,19 +374,23 @@ extern "C" void rtrom_destroy_problem(rtrom_problem *p) {
   delete p;
 }
 
-// Step history: grown in stream order on `s` (no device-wide synchronisation),
-// geometrically, so a long march reallocates a handful of times at most.
+// Step history: grown geometrically, so a long march reallocates a handful
+// of times at most.  Plain hipMalloc / hipFree only: no stream-ordered pool
+// allocations anywhere in the library, so nothing is left in a pool tied to
+// streams that problems destroy (served problems create and destroy theirs
+// on worker threads).
 static rtrom_status ensure_hist(rtrom_problem *p, int64_t need, hipStream_t s) {
   if (need <= p->hist_cap) return RTROM_OK;
   int64_t cap = std::max<int64_t>(need, std::max<int64_t>(1024, 2 * p->hist_cap));
   RtStepRec *nh = nullptr;
-  if (hipMallocAsync((void **)&nh, cap * sizeof(RtStepRec), s) != hipSuccess)
+  if (hipMalloc((void **)&nh, cap * sizeof(RtStepRec)) != hipSuccess)
     return fail(RTROM_ENOMEM, "history allocation failed");
   RT_HIP(hipMemsetAsync(nh, 0, cap * sizeof(RtStepRec), s), "clear history");
   if (p->dhist && p->hist_cap > 0) {
     RT_HIP(hipMemcpyAsync(nh, p->dhist, p->hist_cap * sizeof(RtStepRec), hipMemcpyDeviceToDevice, s),
            "copy history");
-    RT_HIP(hipFreeAsync(p->dhist, s), "free history");
+    RT_HIP(hipStreamSynchronize(s), "history copy sync");
+    RT_HIP(hipFree(p->dhist), "free history");
   }
   p->dhist = nh;
   p->hist_cap = cap;
@@ -496,6 +519,11 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   I.dt = d->dt;
   I.inv_dt = 1.0 / d->dt;
   I.tol = d->tol;
+  {
+    const double theta = d->precision == RTROM_MIXED ? rt_mixed_cert_factor() : 1.0;
+    I.tol_cert = theta * d->tol;
+    I.tol32 = theta * d->tol;
+  }
   I.eps_ig = d->eps_ig;
   I.eps_pc = d->eps_pc;
   I.eps_up = d->eps_up;
@@ -598,11 +626,26 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
   std::vector<RtState> before(n);
   Inst *dinsts = nullptr;
   RtState *dstates = nullptr;
+  // batch descriptor and state buffers, released on every return path (after
+  // the stream has drained on the normal one)
+  struct BatchBufs {
+    hipStream_t s;
+    void *a = nullptr, *b = nullptr;
+    ~BatchBufs() {
+      if (a || b) (void)hipStreamSynchronize(s);
+      if (a) (void)hipFree(a);
+      if (b) (void)hipFree(b);
+    }
+  } bufs{s};
   if (ps[0]->d.dim == 1 && n > 1) {
     std::vector<Inst> h(n);
     for (int i = 0; i < n; ++i) h[i] = ps[i]->hinst;
-    RT_HIP(hipMallocAsync((void **)&dinsts, n * sizeof(Inst), s), "batch descriptors");
-    RT_HIP(hipMallocAsync((void **)&dstates, n * sizeof(RtState), s), "batch states");
+    if (hipMalloc((void **)&dinsts, n * sizeof(Inst)) != hipSuccess)
+      return fail(RTROM_ENOMEM, "batch descriptor allocation failed");
+    bufs.a = dinsts;
+    if (hipMalloc((void **)&dstates, n * sizeof(RtState)) != hipSuccess)
+      return fail(RTROM_ENOMEM, "batch states allocation failed");
+    bufs.b = dstates;
     RT_HIP(hipMemcpyAsync(dinsts, h.data(), n * sizeof(Inst), hipMemcpyHostToDevice, s), "upload batch");
     RT_HIP(rt_launch_gather_states(dinsts, n, dstates, s), "gather states");
     RT_HIP(hipMemcpyAsync(before.data(), dstates, n * sizeof(RtState), hipMemcpyDeviceToHost, s), "read states");
@@ -712,8 +755,6 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
   if (dstates) {
     RT_HIP(rt_launch_gather_states(dinsts, n, dstates, s), "gather states");
     RT_HIP(hipMemcpyAsync(after.data(), dstates, n * sizeof(RtState), hipMemcpyDeviceToHost, s), "read states");
-    RT_HIP(hipFreeAsync(dstates, s), "free batch states");
-    RT_HIP(hipFreeAsync(dinsts, s), "free batch descriptors");
     RT_HIP(hipStreamSynchronize(s), "state sync");
   } else {
     for (int i = 0; i < n; ++i) {

@@ -88,6 +88,12 @@ struct Inst {
   int nthr;  // threads the instance's cells are split over (multiple of 64,
              // fixed at creation so results do not depend on the batch)
   double hx, hy, dt, inv_dt, tol, eps_ig, eps_pc, eps_up;
+  // stop-test tolerances of an iterate whose y came from an FP64 sweep
+  // (tol_cert) or was accumulated from FP32 increments (tol32): both tol in
+  // FP64 mode; in mixed mode both tighter than tol by the certification
+  // factor, so that the accepted iterate carries no more error than an FP64
+  // run stopped at tol
+  double tol_cert, tol32;
   double g[4];
   // 1D ordinate pairs: pair p couples ordinate p (mu < 0) with nv-1-p (mu > 0)
   const double *pm;   // [npair] |mu|/hx

@@ -1032,7 +1032,8 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
     int e = read_residual(p, H, &dn, &yn);
     if (e) return e;
     resid = yn > 0.0 ? dn / yn : dn;
-    const bool pass = yn > 0.0 ? (dn < I.tol * yn) : (dn < I.tol);
+    const double tt = exact ? I.tol_cert : I.tol32;
+    const bool pass = yn > 0.0 ? (dn < tt * yn) : (dn < tt);
     if (pass) {
       if (exact) {
         conv = 1;

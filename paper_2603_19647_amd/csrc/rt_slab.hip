@@ -582,7 +582,7 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
     double dn, yn;
     wg_max2(dl, yl, red, dn, yn);
     resid = yn > 0.0 ? dn / yn : dn;
-    if (stop_test(dn, yn, I.tol)) {
+    if (stop_test(dn, yn, exact ? I.tol_cert : I.tol32)) {
       if (exact) {
         conv = 1;
         break;

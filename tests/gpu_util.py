@@ -71,28 +71,57 @@ def converged_reference(spec, nsteps: int, ref_tol: float = 1e-13):
     return out
 
 
-def oracle_tol_error(spec, nsteps: int, method=None, ref=None):
-    """Largest per-step rel. L2 distance between the FP64 oracle at spec.tol and
-    the converged reference: the error the stop test of Alg. 1 itself leaves
-    at this tolerance."""
+def rel_inf(a, b) -> float:
+    """max_i |a_i - b_i| / max_i |b_i|: the norm of Alg. 1's stop test."""
+    nb = np.abs(b).max() if np.size(b) else 0.0
+    d = np.abs(np.asarray(a) - np.asarray(b)).max() if np.size(b) else 0.0
+    return float(d / nb) if nb > 0 else float(d)
+
+
+def oracle_tol_errors(spec, nsteps: int, method=None, ref=None, norm=rel_l2):
+    """Per-step distance (rel. L2, or another norm) between the FP64 oracle at
+    spec.tol and the converged reference: the error the stop test of Alg. 1
+    itself leaves at this tolerance."""
     ref = converged_reference(spec, nsteps) if ref is None else ref
     o = oracle.OracleProblem(spec.replace(precision="fp64"), method=method)
-    worst = 0.0
+    out = []
     for k in range(nsteps):
         o.step()
-        worst = max(worst, rel_l2(o.rho(), ref[k]))
-    return worst
+        out.append(norm(o.rho(), ref[k]))
+    return np.array(out)
 
 
-# A mixed-precision run and the FP64 oracle both stop when Alg. 1's test
-# passes, but once a ROM is involved their iterate paths differ (rounding of
-# the FP32 increments changes the snapshots, hence the DMD guesses and the
-# iteration at which the test passes), so each realises a different sample of
-# the error the stop test allows.  Across the batch and slab cases that error
-# ratio spans about 0.2x to 5x; the bar allows 10x the oracle's own distance
-# from the converged solution (never below 1e-8).
-MIXED_FACTOR = 10.0
+def mixed_bars(spec, nsteps: int, ref, method=None, norm=rel_l2):
+    """Per-step bar of a mixed-precision run against the converged FP64
+    solution: the FP64 tolerance of the configuration (1e-8) or, where the
+    stop test of Alg. 1 leaves more at that step, the distance the FP64 oracle
+    itself keeps from the converged solution.  The mixed mode certifies its
+    iterates on FP64 sweeps at a tighter threshold than tol, so it must meet
+    this bar with no factor.  With norm=rel_inf the bar is cell by cell in the
+    stop test's own measure (relative to the largest value): the stop test
+    bounds every cell's error by a fraction of max |rho|, not of its own
+    value, so the FP64 oracle itself is no closer than that in cells where rho
+    is small."""
+    return np.maximum(1e-8, oracle_tol_errors(spec, nsteps, method=method, ref=ref, norm=norm))
 
 
-def mixed_bar(spec, nsteps: int, ref, method=None) -> float:
-    return max(1e-8, MIXED_FACTOR * oracle_tol_error(spec, nsteps, method=method, ref=ref))
+def _refs_worker(args):
+    spec, nsteps = args
+    ref = converged_reference(spec, nsteps)
+    return ref, mixed_bars(spec, nsteps, ref), mixed_bars(spec, nsteps, ref, norm=rel_inf)
+
+
+def references_parallel(specs, nsteps: int, workers: int = 8):
+    """converged_reference and mixed_bars of every spec, in a process pool."""
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(max(1, min(workers, len(specs)))) as pool:
+        return pool.map(_refs_worker, [(s, nsteps) for s in specs])
+
+
+def elementwise_err(a, b, floor: float = 1e-6) -> float:
+    """Largest cell-wise error relative to the local value, with an absolute
+    floor of `floor` times the largest value (regions where rho is negligible
+    are held to that absolute level)."""
+    a, b = np.asarray(a), np.asarray(b)
+    scale = np.abs(b) + floor * np.abs(b).max()
+    return float(np.max(np.abs(a - b) / scale)) if b.size else 0.0

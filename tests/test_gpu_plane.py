@@ -2,9 +2,10 @@
 
 Same bars as the slab path: FP64 runs agree with the oracle to rel. L2 <=
 1e-10 per step with identical SI iteration counts, phases, ROM update steps
-and ranks; mixed precision at the configured tolerance agrees to 1e-8, or to
-three times the distance the FP64 oracle itself keeps from the converged
-solution when the stop test leaves more than that.  The 2D DSA on the device
+and ranks; mixed precision at the configured tolerance stays, at every step,
+within 1e-8 of the converged FP64 solution, or within the distance the FP64
+oracle itself keeps from it at that step when the stop test leaves more
+(gpu_util.mixed_bars, no factor).  The 2D DSA on the device
 is an iterative solve accurate to ~1e-14 (the oracle factors the matrix), so
 the acceleration differs from the oracle's at rounding level only.
 """
@@ -14,8 +15,8 @@ import pytest
 import oracle
 from paper_2603_19647_amd import rtrom
 from paper_2603_19647_amd import workloads as W
-from tests.gpu_util import (assert_same_decisions, converged_reference, mixed_bar, oracle_rounding_spread,
-                            rel_l2, say, step_both)
+from tests.gpu_util import (assert_same_decisions, converged_reference, elementwise_err, mixed_bars,
+                            oracle_rounding_spread, rel_inf, rel_l2, say, step_both)
 
 pytestmark = pytest.mark.gpu
 
@@ -70,13 +71,12 @@ def test_plane_mixed_vs_converged(method):
     spec = W.random_plane(5, 48, 8, 4, method=method, precision="mixed", nsteps=30)
     say(f"plane mixed {method}")
     ref = converged_reference(spec, spec.nsteps)
-    bar = mixed_bar(spec, spec.nsteps, ref)
+    bars = mixed_bars(spec, spec.nsteps, ref)
     g = rtrom.Problem(spec)
-    worst = 0.0
     for k in range(spec.nsteps):
         g.step()
-        worst = max(worst, rel_l2(g.rho(), ref[k]))
-    assert worst <= bar, (worst, bar)
+        e = rel_l2(g.rho(), ref[k])
+        assert e <= bars[k], (k, e, bars[k])
     assert g.stats()["fp32_sweeps"] > 0
 
 
@@ -129,11 +129,61 @@ def test_plane_determinism():
     assert np.array_equal(a.f(), b.f())
 
 
-def test_checkerboard_full_size_sampled_steps():
+@pytest.mark.timeout(600)
+def test_checkerboard_full_size_fp64_past_phase_two():
     """The 256^2 checkerboard with CL(16, 8): FP64 ROM against the oracle for
-    the first steps (the oracle's cost bounds the horizon)."""
-    spec = W.checkerboard(nsteps=6).replace(precision="fp64")
-    say("checkerboard 256^2 CL(16,8) rom fp64, 6 steps")
+    40 steps, past N0 + N1 (the 2D initial-guess and preconditioner ROMs at
+    full size), with identical decisions at every step."""
+    spec = W.checkerboard(nsteps=40).replace(precision="fp64")
+    say("checkerboard 256^2 CL(16,8) rom fp64, 40 steps")
     errs, o, g = step_both(spec, spec.nsteps)
-    assert errs.max() <= FP64_TOL, errs
     assert_same_decisions(o, g)
+    spread = oracle_rounding_spread(spec, spec.nsteps)
+    assert np.all(errs <= np.maximum(FP64_TOL, 10.0 * spread)), errs
+    st = g.stats()
+    assert st["n0"] > 0 and st["n1"] > 0 and st["n0"] + st["n1"] < spec.nsteps, st
+    say(f"  n0 {st['n0']} n1 {st['n1']}, max rel L2 {errs.max():.3e}, "
+        f"element-wise {elementwise_err(g.rho(), o.rho()):.3e}")
+    assert elementwise_err(g.rho(), o.rho()) <= 1e-6
+
+
+@pytest.mark.timeout(600)
+def test_checkerboard_full_size_mixed_window():
+    """The configured 256^2 checkerboard in mixed precision: its first 60
+    steps (phases I-III) against the converged FP64 solution, per step."""
+    spec = W.checkerboard(nsteps=60)
+    say("checkerboard 256^2 CL(16,8) rom mixed, 60 steps vs converged")
+    ref = converged_reference(spec, spec.nsteps)
+    bars = mixed_bars(spec, spec.nsteps, ref)
+    bars_inf = mixed_bars(spec, spec.nsteps, ref, norm=rel_inf)
+    g = rtrom.Problem(spec)
+    worst, ew = 0.0, 0.0
+    for k in range(spec.nsteps):
+        g.step()
+        rho = g.rho()
+        e = rel_l2(rho, ref[k])
+        ei = rel_inf(rho, ref[k])
+        worst = max(worst, e / bars[k])
+        ew = max(ew, ei / bars_inf[k])
+        assert e <= bars[k], (k, e, bars[k])
+        assert ei <= bars_inf[k], (k, ei, bars_inf[k])
+    say(f"  worst ratio to the per-step bar: rel L2 {worst:.3f}, cell-wise (inf) {ew:.3f}")
+    say(f"  phase after {spec.nsteps} steps: {g.stats()['phase']}")
+
+
+@pytest.mark.timeout(900)
+def test_serving_size_request_512():
+    """The largest serving request size: 512^2 cells, CL(16, 8), mixed ROM,
+    against the converged FP64 solution, within the configured 1e-8 (first 4
+    steps: the oracle's banded factorisation and sweeps bound the horizon at
+    this size, and one oracle run is all the test affords)."""
+    rng = np.random.default_rng(5)
+    spec = W.serving_request(rng, 0, grid=512, quad=(16, 8), nsteps=4)
+    say("serving-size request 512^2 CL(16,8) mixed, 4 steps vs converged")
+    ref = converged_reference(spec, spec.nsteps)
+    g = rtrom.Problem(spec)
+    for k in range(spec.nsteps):
+        g.step()
+        e = rel_l2(g.rho(), ref[k])
+        say(f"  step {k + 1}: rel L2 {e:.3e}")
+        assert e <= 1e-8

@@ -12,7 +12,7 @@ import pytest
 
 from paper_2603_19647_amd import rtrom
 from paper_2603_19647_amd import workloads as W
-from tests.gpu_util import converged_reference, mixed_bar, rel_l2, say
+from tests.gpu_util import converged_reference, mixed_bars, rel_l2, say
 
 pytestmark = pytest.mark.gpu
 
@@ -85,7 +85,7 @@ def test_serving_sampled_request_meets_mixed_bar():
     spec = W.serving_request(rng, 0, grid=64, quad=(8, 4), nsteps=10)
     say(f"serving sampled {spec.name} vs oracle")
     ref = converged_reference(spec, spec.nsteps)
-    bar = mixed_bar(spec, spec.nsteps, ref)
+    bar = mixed_bars(spec, spec.nsteps, ref)[-1]
     srv = rtrom.Server(hbm_budget_bytes=4 << 30, max_slots=2)
     try:
         t = srv.submit(spec)
