@@ -150,6 +150,22 @@ rtrom_status rtrom_march(rtrom_problem *p, int32_t nsteps);
  * any problem hit max_iter. */
 rtrom_status rtrom_march_batch(rtrom_problem *const *ps, int32_t n, int32_t nsteps);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same as
+ * rtrom_march_batch (same kernels, bitwise the same results) but it allocates
+ * nothing: the batch's descriptor table and state copies live in a static
+ * device array of the library, sized for RTROM_NOALLOC_MAX_BATCH problems
+ * (about 1 MiB, one copy per device, held until the process ends), and the
+ * problems' step histories are never grown.
+ * Errors: EINVAL for n > RTROM_NOALLOC_MAX_BATCH, or when a problem's step
+ * history cannot hold steps + nsteps records (histories hold 1024 steps from
+ * creation and grow only in rtrom_march / rtrom_march_batch); nothing is
+ * marched then.  Every call on a device shares that device's array: calls
+ * that overlap on one device (several host threads) race and must be
+ * serialised by the caller. */
+#define RTROM_NOALLOC_MAX_BATCH 1024
+rtrom_status rtrom_march_batch_noalloc(rtrom_problem *const *ps, int32_t n, int32_t nsteps);
+
 /* rho^n (the converged density of the last step, Alg. 1's returned iterate),
  * n >= nx*ny doubles. */
 rtrom_status rtrom_get_scalar_flux(const rtrom_problem *p, double *rho, int64_t n);

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -598,7 +599,38 @@ static rtrom_status read_state(const rtrom_problem *p, RtState *st) {
   return RTROM_OK;
 }
 
-static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nsteps) {
+// Device scratch of the allocation-free batch march: the batch's descriptor
+// table and the gathered per-instance states, in a file-scope device array
+// (one copy per device, held until the process ends).  Host code never
+// passes the array's name to a kernel or a copy: it takes the array's device
+// address from hipGetSymbolAddress once per device and uses that.
+#define RT_NOALLOC_BYTES (RTROM_NOALLOC_MAX_BATCH * (sizeof(Inst) + sizeof(RtState)) + 512)
+static __device__ __align__(256) unsigned char scratch[RT_NOALLOC_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {nullptr};
+}  // namespace
+
+// The scratch array's device address on `device` (the current device).
+static rtrom_status scratch_address(int device, void **out) {
+  if (device < 0 || device >= kMaxDevices) return fail(RTROM_EDEVICE, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(RTROM_EDEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return RTROM_OK;
+}
+
+// noalloc: take the descriptor table and states from the device scratch array
+// instead of allocating them, and never grow a step history.
+static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nsteps, bool noalloc = false) {
   // all handles of one dimension; 1D: fused launches over the instance array.
   // A 1D batch is laid out largest first (cells x ordinate pairs): workgroups
   // are dispatched in instance order, so the longest ones start first and
@@ -619,6 +651,12 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
   for (int i = 0; i < n; ++i)
     if (ps[i]->stream != s) RT_HIP(hipStreamSynchronize(ps[i]->stream), "sync member stream");
   for (int i = 0; i < n; ++i) {
+    if (noalloc) {
+      if (ps[i]->steps + nsteps > ps[i]->hist_cap)
+        return fail(RTROM_EINVAL, "march_batch_noalloc: the march would outgrow a problem's step history "
+                                  "(capacity " + std::to_string(ps[i]->hist_cap) + " steps); it never allocates");
+      continue;
+    }
     rtrom_status e = ensure_hist(ps[i], ps[i]->steps + nsteps, s);
     if (e != RTROM_OK) return e;
   }
@@ -640,12 +678,20 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
   if (ps[0]->d.dim == 1 && n > 1) {
     std::vector<Inst> h(n);
     for (int i = 0; i < n; ++i) h[i] = ps[i]->hinst;
-    if (hipMalloc((void **)&dinsts, n * sizeof(Inst)) != hipSuccess)
-      return fail(RTROM_ENOMEM, "batch descriptor allocation failed");
-    bufs.a = dinsts;
-    if (hipMalloc((void **)&dstates, n * sizeof(RtState)) != hipSuccess)
-      return fail(RTROM_ENOMEM, "batch states allocation failed");
-    bufs.b = dstates;
+    if (noalloc) {
+      void *base = nullptr;
+      rtrom_status e = scratch_address(ps[0]->device, &base);
+      if (e != RTROM_OK) return e;
+      dinsts = (Inst *)base;
+      dstates = (RtState *)((char *)base + (((size_t)n * sizeof(Inst) + 255) & ~size_t(255)));
+    } else {
+      if (hipMalloc((void **)&dinsts, n * sizeof(Inst)) != hipSuccess)
+        return fail(RTROM_ENOMEM, "batch descriptor allocation failed");
+      bufs.a = dinsts;
+      if (hipMalloc((void **)&dstates, n * sizeof(RtState)) != hipSuccess)
+        return fail(RTROM_ENOMEM, "batch states allocation failed");
+      bufs.b = dstates;
+    }
     RT_HIP(hipMemcpyAsync(dinsts, h.data(), n * sizeof(Inst), hipMemcpyHostToDevice, s), "upload batch");
     RT_HIP(rt_launch_gather_states(dinsts, n, dstates, s), "gather states");
     RT_HIP(hipMemcpyAsync(before.data(), dstates, n * sizeof(RtState), hipMemcpyDeviceToHost, s), "read states");
@@ -784,6 +830,35 @@ extern "C" rtrom_status rtrom_march(rtrom_problem *p, int32_t nsteps) {
 }
 
 extern "C" rtrom_status rtrom_step(rtrom_problem *p) { return rtrom_march(p, 1); }
+
+static rtrom_status check_batch(rtrom_problem *const *ps, int32_t n, int32_t nsteps) {
+  if (!ps || n < 1) return fail(RTROM_EINVAL, "need at least one problem");
+  if (nsteps < 0) return fail(RTROM_EINVAL, "nsteps must be >= 0");
+  for (int i = 0; i < n; ++i) {
+    if (!ps[i]) return fail(RTROM_EINVAL, "null problem in batch");
+    for (int j = 0; j < i; ++j)
+      if (ps[j] == ps[i]) return fail(RTROM_EINVAL, "duplicate problem in batch");
+    if (ps[i]->d.dim != ps[0]->d.dim) return fail(RTROM_EINVAL, "batch mixes 1D and 2D problems");
+    if (ps[i]->device != ps[0]->device) return fail(RTROM_EINVAL, "batch spans devices");
+  }
+  return RTROM_OK;
+}
+
+extern "C" rtrom_status rtrom_march_batch_noalloc(rtrom_problem *const *ps, int32_t n, int32_t nsteps) {
+  rtrom_status v = check_batch(ps, n, nsteps);
+  if (v != RTROM_OK) return v;
+  if (n > RTROM_NOALLOC_MAX_BATCH)
+    return fail(RTROM_EINVAL, "march_batch_noalloc: at most " + std::to_string(RTROM_NOALLOC_MAX_BATCH) +
+                                  " problems per call");
+  if (nsteps == 0) return RTROM_OK;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(RTROM_EDEVICE, "no current device");
+  if (cur != ps[0]->device && hipSetDevice(ps[0]->device) != hipSuccess)
+    return fail(RTROM_EDEVICE, "cannot select the problems' device");
+  rtrom_status r = march_one_kind(ps, n, nsteps, true);
+  if (cur != ps[0]->device) (void)hipSetDevice(cur);
+  return r;
+}
 
 extern "C" rtrom_status rtrom_march_batch(rtrom_problem *const *ps, int32_t n, int32_t nsteps) {
   if (!ps || n < 1) return fail(RTROM_EINVAL, "need at least one problem");

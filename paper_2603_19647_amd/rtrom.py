@@ -74,7 +74,7 @@ class RtromError(RuntimeError):
 
 # every symbol declared in include/rtrom.h
 EXPORTS = (
-    "rtrom_create_problem", "rtrom_step", "rtrom_march", "rtrom_march_batch",
+    "rtrom_create_problem", "rtrom_step", "rtrom_march", "rtrom_march_batch", "rtrom_march_batch_noalloc",
     "rtrom_get_scalar_flux", "rtrom_get_angular_flux", "rtrom_get_rhs", "rtrom_get_quadrature",
     "rtrom_gauss_legendre", "rtrom_cl_quadrature", "rtrom_stats_get", "rtrom_get_history",
     "rtrom_set_inflow", "rtrom_set_stream", "rtrom_device_bytes", "rtrom_estimate_bytes",
@@ -104,6 +104,7 @@ def lib():
     L.rtrom_step.argtypes = [vp]
     L.rtrom_march.argtypes = [vp, i32]
     L.rtrom_march_batch.argtypes = [ctypes.POINTER(ctypes.c_void_p), i32, i32]
+    L.rtrom_march_batch_noalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), i32, i32]
     L.rtrom_get_scalar_flux.argtypes = [vp, _D, i64]
     L.rtrom_get_angular_flux.argtypes = [vp, _D, i64]
     L.rtrom_get_rhs.argtypes = [vp, _D, i64]
@@ -290,6 +291,12 @@ def profile_read() -> dict:
 def march_batch(problems: Sequence[Problem], nsteps: int) -> int:
     arr = (ctypes.c_void_p * len(problems))(*[p.h.value for p in problems])
     return _check(lib().rtrom_march_batch(arr, len(problems), int(nsteps)), allow=(OK, ENOCONV))
+
+
+def march_batch_noalloc(problems: Sequence[Problem], nsteps: int) -> int:
+    """rtrom_march_batch_noalloc: the batch march without device allocation."""
+    arr = (ctypes.c_void_p * len(problems))(*[p.h.value for p in problems])
+    return _check(lib().rtrom_march_batch_noalloc(arr, len(problems), int(nsteps)), allow=(OK, ENOCONV))
 
 
 class Server:
