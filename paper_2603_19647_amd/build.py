@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librtrom.so")
-SOURCES = ["rt_capi.hip", "rt_slab.hip", "rt_rom.hip", "rt_plane.hip", "rt_server.hip"]
+SOURCES = ["rt_capi.hip", "rt_slab.hip", "rt_wave.hip", "rt_rom.hip", "rt_plane.hip", "rt_server.hip"]
 ARCH = os.environ.get("RTROM_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -342,6 +342,18 @@ static size_t slab_bytes(const rtrom_problem_desc *d, int nv) {
   return L.off;
 }
 
+// b~ of the next step from the stored f (creation, a new inflow).  The kernel
+// depends on the size only (the wave-per-pair f-pass up to RT_WAVE_MAX_CELLS
+// cells), never on how the problem is marched later, so a problem batched
+// and the same problem marched alone start from bitwise the same b~.
+static hipError_t slab_rhs(rtrom_problem *p) {
+  const Inst &I = p->hinst;
+  if (p->nc <= RT_WAVE_MAX_CELLS) return rt_launch_slab_fpass_wave(p->dinst, 1, 1, p->stream);
+  int cmax;
+  const int nt = slab_launch_threads(&I.nthr, &p->nc, 1, &cmax);
+  return rt_launch_slab_rhs(p->dinst, 1, nt, cmax, I.npair, p->nc, p->stream);
+}
+
 extern "C" rtrom_status rtrom_estimate_bytes(const rtrom_problem_desc *d, uint64_t *bytes) {
   if (!d || !bytes) return fail(RTROM_EINVAL, "null argument");
   if (d->dim != 1 && d->dim != 2) return fail(RTROM_EINVAL, "dim must be 1 or 2");
@@ -573,10 +585,7 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   if (d->dim == 1) {
     if (upload_inst(p) != RTROM_OK) return bail(RTROM_EDEVICE, "upload descriptor failed");
     if (rt_launch_slab_setup(p->dinst, 1, nc, p->stream) != hipSuccess) return bail(RTROM_EDEVICE, "setup launch failed");
-    int cmax;
-    int nt = slab_launch_threads(&I.nthr, &nc, 1, &cmax);
-    if (rt_launch_slab_rhs(p->dinst, 1, nt, cmax, I.npair, nc, p->stream) != hipSuccess)
-      return bail(RTROM_EDEVICE, "initial RHS launch failed");
+    if (slab_rhs(p) != hipSuccess) return bail(RTROM_EDEVICE, "initial RHS launch failed");
   } else {
     if (upload_inst(p) != RTROM_OK) return bail(RTROM_EDEVICE, "upload descriptor failed");
     int s = rt_plane_create(p);
@@ -636,13 +645,13 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
   // are dispatched in instance order, so the longest ones start first and
   // the launches' tails shorten.  Every instance computes the same thing
   // wherever it sits.
-  // Instances of more than 512 threads (four cells each) come first: a batch
-  // mixing them with instances of eight cells per thread runs the two kinds
-  // as two launches (no kernel holds eight cells a thread at 1024 threads).
+  // Instances of more than RT_WAVE_MAX_CELLS cells come first: they run the
+  // kernels with cells split over the threads in contiguous runs, the others
+  // the kernels with ordinate pairs spread over waves, as two launches.
   std::vector<rtrom_problem *> order(ps_in, ps_in + n);
   if (n > 1 && ps_in[0]->d.dim == 1)
     std::stable_sort(order.begin(), order.end(), [](const rtrom_problem *a, const rtrom_problem *b) {
-      const bool wa = a->hinst.nthr > 512, wb = b->hinst.nthr > 512;
+      const bool wa = a->nc > RT_WAVE_MAX_CELLS, wb = b->nc > RT_WAVE_MAX_CELLS;
       if (wa != wb) return wa;
       return (long long)a->nc * a->hinst.npair > (long long)b->nc * b->hinst.npair;
     });
@@ -710,18 +719,17 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
       ncs[i] = ps[i]->nc;
     }
     if (n == 1) dinsts = ps[0]->dinst;
-    // launch groups: [0, nA) wide instances (more than 512 threads), [nA, n)
-    // the rest; one group unless the rest need eight cells a thread
+    // launch groups: [0, nA) instances of more than RT_WAVE_MAX_CELLS cells
+    // (contiguous-run kernels), [nA, n) the rest (wave-per-pair kernels)
     int nA = 0;
-    while (nA < n && nthr[nA] > 512) ++nA;
-    bool split = false;
-    for (int i = nA; i < n && nA > 0; ++i) split |= (ncs[i] + nthr[i] - 1) / nthr[i] > 4;
+    while (nA < n && ncs[nA] > RT_WAVE_MAX_CELLS) ++nA;
     struct Group {
-      int off, cnt, nt, cmax, nc_max, npair_max, pairs_total;
+      int off, cnt, nt, cmax, nc_max, npair_max, pairs_total, wave;
     };
     std::vector<Group> groups;
-    for (int g = 0; g < (split ? 2 : 1); ++g) {
-      Group G{split && g ? nA : 0, split ? (g ? n - nA : nA) : n, 0, 0, 0, 1, 0};
+    for (int g = 0; g < 2; ++g) {
+      Group G{g ? nA : 0, g ? n - nA : nA, 0, 0, 0, 1, 0, g};
+      if (G.cnt == 0) continue;
       G.nt = slab_launch_threads(nthr.data() + G.off, ncs.data() + G.off, G.cnt, &G.cmax);
       for (int i = G.off; i < G.off + G.cnt; ++i) {
         G.nc_max = std::max(G.nc_max, ncs[i]);
@@ -759,8 +767,10 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
     }
     for (int k = 0; k < nsteps && !coop; ++k) {
       rt_prof_begin(RT_K_SLAB_SI, s);
-      for (const Group &G : groups)
-        RT_HIP(rt_launch_slab_si(dinsts + G.off, G.cnt, G.nt, G.cmax, s), "SI launch");
+      for (const Group &G : groups) {
+        if (G.wave) RT_HIP(rt_launch_slab_si_wave(dinsts + G.off, G.cnt, s), "SI launch");
+        else RT_HIP(rt_launch_slab_si(dinsts + G.off, G.cnt, G.nt, G.cmax, s), "SI launch");
+      }
       rt_prof_end(RT_K_SLAB_SI, s);
       if (s2 != s) {
         RT_HIP(hipEventRecord(ps[0]->ev_si, s), "event");
@@ -777,9 +787,12 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
         }
       }
       rt_prof_begin(RT_K_SLAB_FPASS, s);
-      for (const Group &G : groups)
-        RT_HIP(rt_launch_slab_fpass(dinsts + G.off, G.cnt, G.nt, G.cmax, G.npair_max, G.nc_max, G.pairs_total, s),
-               "f-pass launch");
+      for (const Group &G : groups) {
+        if (G.wave) RT_HIP(rt_launch_slab_fpass_wave(dinsts + G.off, G.cnt, 0, s), "f-pass launch");
+        else
+          RT_HIP(rt_launch_slab_fpass(dinsts + G.off, G.cnt, G.nt, G.cmax, G.npair_max, G.nc_max, G.pairs_total, s),
+                 "f-pass launch");
+      }
       rt_prof_end(RT_K_SLAB_FPASS, s);
       if (s2 != s) {
         RT_HIP(hipEventRecord(ps[0]->ev_rom, s2), "event");
@@ -964,9 +977,7 @@ extern "C" rtrom_status rtrom_set_inflow(rtrom_problem *p, const double *g) {
   rtrom_status e = upload_inst(p);
   if (e != RTROM_OK) return e;
   if (p->d.dim == 1) {
-    int cmax;
-    int nt = slab_launch_threads(&p->hinst.nthr, &p->nc, 1, &cmax);
-    RT_HIP(rt_launch_slab_rhs(p->dinst, 1, nt, cmax, p->hinst.npair, p->nc, p->stream), "RHS launch");
+    RT_HIP(slab_rhs(p), "RHS launch");
   } else {
     int s = rt_plane_rhs(p);
     if (s != RTROM_OK) return (rtrom_status)s;

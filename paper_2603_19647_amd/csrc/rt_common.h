@@ -29,6 +29,9 @@ struct RomPend {
 // instances up to RT_POST_FUSED_NC cells run the whole post in one workgroup
 // per ROM (one partial row).
 #define RT_POST_FUSED_NC 2048
+// slab instances up to this many cells run the SI solve one workgroup of
+// eight waves each, ordinate pairs spread over the waves (k_si_wave)
+#define RT_WAVE_MAX_CELLS 2048
 __host__ __device__ inline int rt_pass_blocks(int nc) {
   const int nb = (nc + 255) / 256;
   return nb < 64 ? nb : 64;

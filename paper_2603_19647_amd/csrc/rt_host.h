@@ -44,6 +44,8 @@ extern "C" hipError_t rt_launch_rom_slab(const Inst *dinsts, int ninst, int any_
 extern "C" hipError_t rt_launch_rom_update(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream);
 extern "C" hipError_t rt_launch_slab_rhs(const Inst *dinsts, int ninst, int nthreads, int cmax, int npair_max,
                                          int nc_max, hipStream_t stream);
+extern "C" hipError_t rt_launch_slab_si_wave(const Inst *dinsts, int ninst, hipStream_t stream);
+extern "C" hipError_t rt_launch_slab_fpass_wave(const Inst *dinsts, int ninst, int rhs_only, hipStream_t stream);
 extern "C" hipError_t rt_launch_slab_setup(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream);
 extern "C" hipError_t rt_launch_gather_states(const Inst *dinsts, int ninst, RtState *out, hipStream_t stream);
 

@@ -19,6 +19,7 @@
 #include <algorithm>
 
 #include "rt_common.h"
+#include "rt_dsa.h"
 #include "rt_rom.h"
 
 namespace {
@@ -419,61 +420,6 @@ __device__ inline void coop_pass2(const Inst &I, int z, int blk, int nb, int ran
     pass_wave_sums(acc, G.hw ? (int)(threadIdx.x >> 6) : i, red);
   }
   pass_rows(G.hw, red, R.work->part2, blk);
-}
-
-// DSA correction (eq. rho_residual): solve C d = rhs with the precomputed
-// Thomas factors written as two affine recurrences, z_i = fe_i z_{i-1} + rhs_i
-// forward and d_i = bg_i d_{i+1} + invd_i z_i backward.
-template <int CMAX>
-__device__ __forceinline__ void dsa_solve_slab(const Inst &I, int c0, int n, const double (&rhs)[CMAX],
-                                               double (&d)[CMAX], double *slots, int &parity) {
-  double fe[CMAX], z[CMAX];
-  double A = 1.0, B = 0.0;
-#pragma unroll
-  for (int t = 0; t < CMAX; ++t) {
-    if (t < n) {
-      fe[t] = ldg(&I.dsa_fe[c0 + t]);
-      B = rt_fma(fe[t], B, rhs[t]);
-      A *= fe[t];
-    }
-  }
-  double inF, inB;
-  wg_scan2<double>(A, B, 1.0, 0.0, 0.0, 0.0, inF, inB, slots, parity);
-  parity ^= 1;
-  double f = inF;
-#pragma unroll
-  for (int t = 0; t < CMAX; ++t) {
-    if (t < n) {
-      f = rt_fma(fe[t], f, rhs[t]);
-      z[t] = f;
-    }
-  }
-  double bg[CMAX];
-  A = 1.0;
-  B = 0.0;
-#pragma unroll
-  for (int t = CMAX - 1; t >= 0; --t) {
-    if (t < n) {
-      bg[t] = ldg(&I.dsa_bg[c0 + t]);
-      z[t] *= ldg(&I.dsa_invd[c0 + t]);
-      B = rt_fma(bg[t], B, z[t]);
-      A *= bg[t];
-    }
-  }
-  wg_scan2<double>(1.0, 0.0, A, B, 0.0, 0.0, inF, inB, slots, parity);
-  parity ^= 1;
-  f = inB;
-#pragma unroll
-  for (int t = CMAX - 1; t >= 0; --t) {
-    if (t < n) {
-      f = rt_fma(bg[t], f, z[t]);
-      d[t] = f;
-    }
-  }
-}
-
-__device__ __forceinline__ bool stop_test(double dn, double yn, double tol) {
-  return yn > 0.0 ? (dn < tol * yn) : (dn < tol);
 }
 
 }  // namespace
