@@ -188,6 +188,8 @@ rtrom_status rtrom_gauss_legendre(int32_t n, double *mu, double *w);
 rtrom_status rtrom_cl_quadrature(int32_t n_azim, int32_t n_polar, double *ox,
                                  double *oy, double *oz, double *w);
 
+/* Counters of the march so far (library bookkeeping; the counts are the
+ * quantities Sec. 4 reports: SI sweeps per step, N0, N1, ranks). */
 rtrom_status rtrom_stats_get(const rtrom_problem *p, rtrom_stats *out);
 
 /* Per-step records of the last min(n, steps) steps in order. *written gets the
@@ -200,10 +202,11 @@ rtrom_status rtrom_get_history(const rtrom_problem *p, rtrom_step_record *out,
 rtrom_status rtrom_set_inflow(rtrom_problem *p, const double *g);
 
 /* Launch on `hip_stream` (a hipStream_t, e.g. torch's current stream) from now
- * on; NULL selects the problem's own stream. */
+ * on; NULL selects the problem's own stream.  Library plumbing, no passage of
+ * the paper. */
 rtrom_status rtrom_set_stream(rtrom_problem *p, void *hip_stream);
 
-/* Bytes of device memory owned by the problem. */
+/* Bytes of device memory owned by the problem (library plumbing). */
 rtrom_status rtrom_device_bytes(const rtrom_problem *p, uint64_t *bytes);
 
 /* Bytes a problem with description d would own (for admission control). */
@@ -211,7 +214,7 @@ rtrom_status rtrom_estimate_bytes(const rtrom_problem_desc *d, uint64_t *bytes);
 
 void rtrom_destroy_problem(rtrom_problem *p); /* NULL -> no-op */
 
-/* Kernel timing.  While enabled, every kernel launch of every problem is
+/* Kernel timing (library instrumentation, no passage of the paper).  While enabled, every kernel launch of every problem is
  * bracketed by HIP events on the stream it runs on, and the device time and
  * launch count of each kernel kind accumulate process-wide (read after the
  * march returns).  Kinds: 0 slab SI solve, 1 slab f-pass, 2 ROM bookkeeping and

@@ -34,6 +34,10 @@
 #include "rt_host.h"
 #include "rt_rom.h"
 
+// Chebyshev iterations the 2D DSA solve may take (its coefficient table is
+// sized for them); a problem needing more is rejected at creation.
+#define RT_CHEB_MAX 20000
+
 namespace {
 
 constexpr int BAND = 64;   // rows of a band: one wave, lane = row
@@ -709,7 +713,7 @@ static size_t plane_bytes_for(const rtrom_problem_desc *d) {
   take(nc * 4);                     // src32
   take(nc * 8 * 3);                 // diag ax ay
   take(nblk * 2 * 8 + 64);          // blkmax, res
-  take(2 * 2000 * 8);               // Chebyshev coefficients
+  take(2 * (size_t)RT_CHEB_MAX * 8);               // Chebyshev coefficients
   take(nblk * RT_NPART * 8 + RT_RMAX * 8);  // DMD solve partials, coefficients
   take((size_t)g.ndf * 3 * 8);      // mx my w
   return b;
@@ -842,7 +846,7 @@ int rt_plane_create(rtrom_problem *p) {
   H->ay = H->ax + nc;
   H->blkmax = (double *)take((size_t)nblk * 2 * 8 + 64);
   H->res = H->blkmax + 2 * (size_t)nblk;
-  H->cheb_c = (double *)take(2 * 2000 * 8);
+  H->cheb_c = (double *)take(2 * (size_t)RT_CHEB_MAX * 8);
   H->rpart = (double *)take((size_t)nblk * RT_NPART * 8 + RT_RMAX * 8);
   H->rcoef = H->rpart + (size_t)nblk * RT_NPART;
   double *dmx = (double *)take((size_t)ndf * 3 * 8);
@@ -899,8 +903,14 @@ int rt_plane_create(rtrom_problem *p) {
   int K = 1;
   if (H->cheb_delta > 0.0) {
     // error bound 2 / T_K(sigma1) <= 1e-14
-    K = (int)std::ceil(std::acosh(2e14) / std::acosh(sigma1));
-    K = std::max(1, std::min(K, 2000));
+    const double kk = std::ceil(std::acosh(2e14) / std::acosh(sigma1));
+    if (!(kk <= RT_CHEB_MAX)) {
+      rt_set_error("2D DSA: the diffusion operator needs " + std::to_string(kk) +
+                   " Chebyshev iterations for a 1e-14 error bound, more than the " + std::to_string(RT_CHEB_MAX) +
+                   " this library runs (time step or mesh too fine for its diagonal dominance)");
+      return RTROM_EINVAL;
+    }
+    K = std::max(1, (int)kk);
   }
   H->cheb_iters = K;
   // d_{k+1} = rho_{k+1} rho_k d_k + (2 rho_{k+1} / delta) diag^{-1} r_{k+1}

@@ -268,3 +268,106 @@ def random_plane(seed: int, n: int, n_azim: int, n_polar: int, **kw) -> ProblemS
     kw.setdefault("dt", 0.01)
     return plane(n, n, n_azim, n_polar, ss.reshape(-1), sa, q.reshape(-1),
                  name=f"rplane{seed}_{n}", **kw)
+
+
+# --------------------------------------------------------------------------
+# The paper's numerical experiments (Sec. 4) in finite-volume form.  Cross
+# sections, sources, inflow and initial states as stated there; the paper's
+# default tolerances (Sec. 4 preamble: eps_SISA 1e-11, eps_IG 1e-9, eps_PC
+# 1e-6, eps_UP 1e-9) unless the experiment sets its own.  The discretisation
+# is this library's (first-order upwind finite volumes), not the paper's
+# DG-P1, so iteration counts are comparable in kind only.
+# --------------------------------------------------------------------------
+
+PAPER_EPS = dict(tol=1e-11, eps_ig=1e-9, eps_pc=1e-6, eps_up=1e-9)
+
+
+def sec41_two_material(method: str = "rom", precision: str = "fp64", nsteps: int = 100) -> ProblemSpec:
+    """Sec. 4.1: slab [0, 11], sigma_s = 0 / sigma_a = 1 on [0, 1] and
+    sigma_s = 100 / sigma_a = 0 on [1, 11], inflow 5 at x = 0 (mu > 0) and 0 at
+    x = 11, f0 = 0, no source, 6-point Gauss-Legendre, dx = 0.1 (110 cells),
+    dt = 10, t in [0, 1000] (100 steps)."""
+    nx = 110
+    x = _centres(nx, 11.0)
+    ss = np.where(x < 1.0, 0.0, 100.0)
+    sa = np.where(x < 1.0, 1.0, 0.0)
+    return slab(nx, 6, ss, sa, 0.0, lx=11.0, inflow=(5.0, 0.0, 0.0, 0.0), dt=10.0, method=method,
+                precision=precision, nsteps=nsteps, name="sec41_two_material", **PAPER_EPS)
+
+
+def sec42_gaussian_source(sigma_s: float = 1.0, cfl: float = 1.0, n: int = 81, n_azim: int = 40,
+                          n_polar: int = 6, method: str = "rom", precision: str = "fp64",
+                          nsteps: Optional[int] = None) -> ProblemSpec:
+    """Sec. 4.2: [-1, 1]^2, sigma_a = 0, constant sigma_s, Gaussian source
+    G = (10 / pi) exp(-100 (x^2 + y^2)), zero inflow and initial state,
+    81^2 cells, CL(40, 6), dt = CFL dx, t in [0, 2.5], eps_SISA = 1e-12 (IG and
+    UP 1e-9, PC 1e-6)."""
+    h = 2.0 / n
+    x = _centres(n, 2.0) - 1.0
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    G = (10.0 / np.pi) * np.exp(-100.0 * (X ** 2 + Y ** 2))
+    dt = cfl * h
+    steps = int(np.ceil(2.5 / dt - 1e-9)) if nsteps is None else nsteps
+    return plane(n, n, n_azim, n_polar, sigma_s, 0.0, G.reshape(-1), lx=2.0, ly=2.0, dt=dt, tol=1e-12,
+                 eps_ig=1e-9, eps_pc=1e-6, eps_up=1e-9, method=method, precision=precision, nsteps=steps,
+                 name=f"sec42_gauss_ss{sigma_s:g}_cfl{cfl:g}")
+
+
+def sec43_variable_scattering(n: int = 81, n_azim: int = 40, n_polar: int = 6, method: str = "rom",
+                              precision: str = "fp64", nsteps: Optional[int] = None) -> ProblemSpec:
+    """Sec. 4.3: [-1, 1]^2, G = 0, zero inflow, isotropic initial state
+    f0 = exp(-(x^2 + y^2) / (4 zeta^2)) / (4 pi zeta^2) with zeta = 1e-2,
+    sigma_s = 99.9 c^4 (c + sqrt 2)^2 (c - sqrt 2)^2 + 0.1 for c = |x| < 1 and
+    1 outside, sigma_a = 0, 81^2 cells, CL(40, 6), dt = dx, t in [0, 2.5]
+    (102 steps), the default tolerances."""
+    h = 2.0 / n
+    x = _centres(n, 2.0) - 1.0
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    c = np.sqrt(X ** 2 + Y ** 2)
+    r2 = np.sqrt(2.0)
+    ss = np.where(c < 1.0, 99.9 * c ** 4 * (c + r2) ** 2 * (c - r2) ** 2 + 0.1, 1.0)
+    zeta = 1e-2
+    f0 = np.exp(-(X ** 2 + Y ** 2) / (4.0 * zeta ** 2)) / (4.0 * np.pi * zeta ** 2)
+    dt = h
+    steps = int(np.ceil(2.5 / dt - 1e-9)) if nsteps is None else nsteps
+    sp = plane(n, n, n_azim, n_polar, ss.reshape(-1), 0.0, 0.0, lx=2.0, ly=2.0, dt=dt, method=method,
+               precision=precision, nsteps=steps, name="sec43_variable_scattering", **PAPER_EPS)
+    return sp.replace(f0=f0.reshape(-1))
+
+
+def sec44_lattice(n: int = 80, n_azim: int = 40, n_polar: int = 6, method: str = "rom",
+                  precision: str = "fp64", nsteps: int = 80) -> ProblemSpec:
+    """Sec. 4.4: [0, 5]^2 in unit blocks; absorbers (sigma_a, sigma_s) =
+    (100, 0) on the lattice's dark blocks, scatterers (0, 1) elsewhere; source
+    1 on the central block |x - 2.5|, |y - 2.5| < 0.5; zero inflow and initial
+    state; 80^2 cells, CL(40, 6), dt = 1/16, 80 steps (t in [0, 5]),
+    (eps_IG, eps_PC, eps_UP) = (1e-6, 1e-6, 1e-6), eps_SISA 1e-11.  The block
+    pattern is a reading (the paper shows it only in a figure): the inner 3 x 3
+    blocks alternate, the central one is the source and the four diagonal
+    neighbours of it are absorbers."""
+    x = _centres(n, 5.0)
+    bx = np.minimum(x.astype(np.int64), 4)
+    BX, BY = np.meshgrid(bx, bx, indexing="xy")
+    inner = (BX >= 1) & (BX <= 3) & (BY >= 1) & (BY <= 3)
+    absorber = inner & ((BX + BY) % 2 == 0) & ~((BX == 2) & (BY == 2))
+    ss = np.where(absorber, 0.0, 1.0)
+    sa = np.where(absorber, 100.0, 0.0)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    G = np.where((np.abs(X - 2.5) < 0.5) & (np.abs(Y - 2.5) < 0.5), 1.0, 0.0)
+    return plane(n, n, n_azim, n_polar, ss.reshape(-1), sa.reshape(-1), G.reshape(-1), lx=5.0, ly=5.0,
+                 dt=1.0 / 16.0, tol=1e-11, eps_ig=1e-6, eps_pc=1e-6, eps_up=1e-6, method=method,
+                 precision=precision, nsteps=nsteps, name="sec44_lattice")
+
+
+def phase_sweeps(phases, iters) -> dict:
+    """Average SI sweeps per step in each phase (1, 2, 3) and over the whole
+    march, from per-step phase labels and SI iteration counts (the layout of
+    Tables 3 and 5; bookkeeping only)."""
+    phases = np.asarray(phases)
+    iters = np.asarray(iters, dtype=np.float64)
+    out = {}
+    for ph in (1, 2, 3):
+        m = phases == ph
+        out[ph] = (int(m.sum()), float(iters[m].mean()) if m.any() else float("nan"))
+    out["all"] = (int(len(iters)), float(iters.mean()) if len(iters) else float("nan"))
+    return out
