@@ -169,17 +169,28 @@ def copy_probe(mib: int):
 
 def timed_batch(rtrom, specs, warmup, steps, profile=True):
     """Create the problems, march `warmup` steps untimed, then time `steps`
-    further steps of the same march (fused launches over all instances)."""
+    further steps of the same march (fused launches over all instances, the
+    step replayed from a HIP graph).  With `profile`, a second set of the same
+    problems marches the same window again with every launch bracketed by
+    events (eagerly), for the per-kernel durations; the march is
+    deterministic, so both windows do the same work."""
     probs = [rtrom.Problem(s) for s in specs]
     if warmup > 0:
         rtrom.march_batch(probs, warmup)
-    if profile:
-        rtrom.profile_enable(True)
     t0 = time.perf_counter()
     rtrom.march_batch(probs, steps)   # returns after the device finished
     t1 = time.perf_counter()
-    prof = rtrom.profile_read() if profile else {}
-    rtrom.profile_enable(False)
+    prof = {}
+    if profile:
+        twin = [rtrom.Problem(s) for s in specs]
+        if warmup > 0:
+            rtrom.march_batch(twin, warmup)
+        rtrom.profile_enable(True)
+        rtrom.march_batch(twin, steps)
+        prof = rtrom.profile_read()
+        rtrom.profile_enable(False)
+        for p in twin:
+            p.close()
     return t1 - t0, probs, prof
 
 

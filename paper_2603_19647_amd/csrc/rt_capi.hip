@@ -9,6 +9,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "rt_host.h"
@@ -57,8 +58,12 @@ hipEvent_t prof_event() {
 }
 }  // namespace
 
+namespace {
+std::mutex g_prof_mu;  // concurrent 2D batch members record from several threads
+}
 void rt_prof_begin(int kind, hipStream_t s) {
   if (!g_prof.on) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
   hipEvent_t e = prof_event();
   if (e) (void)hipEventRecord(e, s);
   g_prof.kinds.push_back(kind);
@@ -66,11 +71,14 @@ void rt_prof_begin(int kind, hipStream_t s) {
 void rt_prof_end(int kind, hipStream_t s) {
   (void)kind;
   if (!g_prof.on) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
   hipEvent_t e = prof_event();
   if (e) (void)hipEventRecord(e, s);
 }
+bool rt_prof_on() { return g_prof.on; }
 void rt_prof_collect() {
   if (!g_prof.on) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
   for (size_t k = 0; k < g_prof.kinds.size() && 2 * k + 1 < g_prof.used; ++k) {
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, g_prof.pool[2 * k], g_prof.pool[2 * k + 1]) == hipSuccess) {
@@ -669,6 +677,9 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
     rtrom_status e = ensure_hist(ps[i], ps[i]->steps + nsteps, s);
     if (e != RTROM_OK) return e;
   }
+  // descriptor uploads of grown histories went on s; members may launch on
+  // their own streams
+  RT_HIP(hipStreamSynchronize(s), "history sync");
   // phase-machine states before the march (for the non-convergence count)
   std::vector<RtState> before(n);
   Inst *dinsts = nullptr;
@@ -765,7 +776,10 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
       RT_HIP(rt_launch_slab_tail_coop(dinsts, ps[0]->hinst.npair, ps[0]->nc, nt, cmax, s), "cooperative tail launch");
       rt_prof_end(RT_K_POST, s);
     }
-    for (int k = 0; k < nsteps && !coop; ++k) {
+    // one step's launches on s (SI solve, f-pass) and s2 (ROM post), joined
+    // by events; every kernel takes its step from the device state, so the
+    // sequence is the same each step
+    auto enqueue_step = [&]() -> rtrom_status {
       rt_prof_begin(RT_K_SLAB_SI, s);
       for (const Group &G : groups) {
         if (G.wave) RT_HIP(rt_launch_slab_si_wave(dinsts + G.off, G.cnt, s), "SI launch");
@@ -798,12 +812,81 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
         RT_HIP(hipEventRecord(ps[0]->ev_rom, s2), "event");
         RT_HIP(hipStreamWaitEvent(s, ps[0]->ev_rom, 0), "event wait");
       }
+      return RTROM_OK;
+    };
+    // A march of several steps captures one step in a HIP graph and replays
+    // it: the per-step launch cost is paid once per march (kernel timing
+    // brackets every launch with events, so it runs the steps eagerly).
+    // RTROM_GRAPH=0 keeps eager launches; a capture the runtime refuses falls
+    // back to them as well, and so does the allocation-free march (building
+    // a graph allocates).
+    const char *genv = std::getenv("RTROM_GRAPH");
+    bool graph_done = false;
+    if (!coop && !noalloc && nsteps >= 2 && !rt_prof_on() && !(genv && std::atoi(genv) == 0)) {
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        const rtrom_status es = enqueue_step();
+        ok = hipStreamEndCapture(s, &graph) == hipSuccess && es == RTROM_OK && graph;
+      }
+      ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+      (void)hipGetLastError();  // a refused capture leaves the steps to the eager loop
+      if (ok) {
+        bool launched = true;
+        for (int k = 0; k < nsteps && launched; ++k) launched = hipGraphLaunch(exec, s) == hipSuccess;
+        const bool synced = hipStreamSynchronize(s) == hipSuccess;
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        if (!launched || !synced) return fail(RTROM_EDEVICE, "step graph launch failed");
+        graph_done = true;
+      } else {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+      }
     }
+    for (int k = 0; k < nsteps && !coop && !graph_done; ++k) {
+      const rtrom_status es = enqueue_step();
+      if (es != RTROM_OK) return es;
+    }
+  } else if (n == 1) {
+    int e = rt_plane_step(ps[0], nsteps);
+    if (e != RTROM_OK) return (rtrom_status)e;
   } else {
-    for (int i = 0; i < n; ++i) {
-      int e = rt_plane_step(ps[i], nsteps);
-      if (e != RTROM_OK) return (rtrom_status)e;
-    }
+    // 2D batch: every problem marches on its own streams, from up to eight
+    // host threads at once, so the members' kernels overlap on the device
+    // (each 2D step's loop is steered from the host by its residual norms).
+    // A problem's arithmetic does not depend on what runs beside it.
+    const int nt = std::min(n, 8);
+    std::vector<int> errs(nt, RTROM_OK);
+    std::vector<std::string> msgs(nt);
+    std::vector<std::thread> pool;
+    const int dev = ps[0]->device;
+    for (int t = 0; t < nt; ++t)
+      pool.emplace_back([&, t] {
+        if (hipSetDevice(dev) != hipSuccess) {
+          errs[t] = RTROM_EDEVICE;
+          msgs[t] = "cannot select the device";
+          return;
+        }
+        for (int i = t; i < n && errs[t] == RTROM_OK; i += nt) {
+          const int e = rt_plane_step(ps[i], nsteps);
+          if (e != RTROM_OK) {
+            errs[t] = e;
+            msgs[t] = g_err;  // thread-local message of the worker
+          }
+        }
+        if (errs[t] == RTROM_OK) {
+          for (int i = t; i < n; i += nt)
+            if (hipStreamSynchronize(ps[i]->stream) != hipSuccess) {
+              errs[t] = RTROM_EDEVICE;
+              msgs[t] = "member stream sync failed";
+            }
+        }
+      });
+    for (auto &th : pool) th.join();
+    for (int t = 0; t < nt; ++t)
+      if (errs[t] != RTROM_OK) return fail((rtrom_status)errs[t], msgs[t]);
   }
   RT_HIP(hipEventRecord(ps[0]->ev1, s), "event");
   RT_HIP(hipStreamSynchronize(s), "march sync");

@@ -69,3 +69,4 @@ enum { RT_K_SLAB_SI = 0, RT_K_SLAB_FPASS = 1, RT_K_POST = 2, RT_K_PLANE_SWEEP = 
 void rt_prof_begin(int kind, hipStream_t s);
 void rt_prof_end(int kind, hipStream_t s);
 void rt_prof_collect();  // after the stream(s) synchronised
+bool rt_prof_on();

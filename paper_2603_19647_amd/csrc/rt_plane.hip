@@ -31,6 +31,11 @@
 #include <type_traits>
 #include <vector>
 
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "rt_host.h"
 #include "rt_rom.h"
 
@@ -679,6 +684,7 @@ struct PlaneHost {
   double *blkmax = nullptr, *res = nullptr, *res_h = nullptr;
   double *rpart = nullptr, *rcoef = nullptr;
   int cheb_iters = 0;
+  int pd32 = 8, pd64 = 8;  // prefetch depth of the SI sweeps (FP32 / FP64), tuned per grid shape
   double cheb_theta = 1.0, cheb_delta = 0.0;
   double *cheb_c = nullptr;                 // device: c1[K], c2[K]
   size_t bytes = 0;
@@ -736,6 +742,106 @@ int rt_plane_needs_cyclic(int ny) { return (ny + BAND - 1) / BAND > MAXW; }
     }                                                                       \
   } while (0)
 
+// The SI sweep (MODE 0) with prefetch depth pd (2, 4, 8 or 16 steps of cell
+// data loaded ahead).  The depth changes only how far ahead the loads are
+// issued, never the arithmetic, so every depth gives bitwise the same result.
+template <typename R>
+static void launch_si_sweep(int pd, dim3 grid, dim3 block, hipStream_t s, const PlaneArgs &A) {
+  switch (pd) {
+    case 2: hipLaunchKernelGGL((k_plane_sweep<R, 0, 2>), grid, block, 0, s, A); break;
+    case 4: hipLaunchKernelGGL((k_plane_sweep<R, 0, 4>), grid, block, 0, s, A); break;
+    case 16: hipLaunchKernelGGL((k_plane_sweep<R, 0, 16>), grid, block, 0, s, A); break;
+    default: hipLaunchKernelGGL((k_plane_sweep<R, 0, 8>), grid, block, 0, s, A); break;
+  }
+}
+
+// Autotuner of the SI sweep's prefetch depth.  For each grid shape (nx, ny,
+// folded ordinates) the first problem created times the FP32 and FP64 SI
+// sweeps at every depth (one warm-up and three timed launches each, HIP
+// events on the problem's stream; the sweep writes only its scratch
+// partials, so the state is untouched) and keeps the fastest; later problems
+// of the same shape reuse the choice.  RTROM_TUNE=0 keeps depth 8;
+// RTROM_PLANE_PD="<fp32>,<fp64>" fixes both; RTROM_TUNE_LOG=1 prints the
+// timings.
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, std::pair<int, int>> g_tune;
+}  // namespace
+
+static int tune_si_sweep(rtrom_problem *p, PlaneHost *H) {
+  const char *fixed = std::getenv("RTROM_PLANE_PD");
+  if (fixed) {
+    int a = 8, b = 8;
+    if (std::sscanf(fixed, "%d,%d", &a, &b) == 2) {
+      auto ok = [](int v) { return v == 2 || v == 4 || v == 8 || v == 16; };
+      H->pd32 = ok(a) ? a : 8;
+      H->pd64 = ok(b) ? b : 8;
+    }
+    return RTROM_OK;
+  }
+  const char *tune = std::getenv("RTROM_TUNE");
+  if (tune && std::atoi(tune) == 0) return RTROM_OK;
+  const PlaneArgs &A = H->A;
+  const auto key = std::make_tuple(A.nx, A.ny, A.ndf);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      H->pd32 = it->second.first;
+      H->pd64 = it->second.second;
+      return RTROM_OK;
+    }
+  }
+  hipStream_t s = p->stream;
+  const dim3 grid(A.ndf), block(64 * A.nw);
+  hipEvent_t e0, e1;
+  PH(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    rt_set_error("plane: tuning event");
+    return RTROM_EDEVICE;
+  }
+  const int depths[4] = {2, 4, 8, 16};
+  int best[2] = {8, 8};
+  const bool log = std::getenv("RTROM_TUNE_LOG") && std::atoi(std::getenv("RTROM_TUNE_LOG"));
+  int rc = RTROM_OK;
+  for (int prec = 0; prec < 2 && rc == RTROM_OK; ++prec) {
+    float tbest = 1e30f;
+    for (int pd : depths) {
+      auto launch = [&] {
+        if (prec == 0) launch_si_sweep<float>(pd, grid, block, s, A);
+        else launch_si_sweep<double>(pd, grid, block, s, A);
+      };
+      launch();
+      float ms = 0.0f;
+      if (hipEventRecord(e0, s) != hipSuccess) rc = RTROM_EDEVICE;
+      for (int r = 0; r < 3; ++r) launch();
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess || hipGetLastError() != hipSuccess)
+        rc = RTROM_EDEVICE;
+      if (rc != RTROM_OK) break;
+      if (log)
+        std::fprintf(stderr, "rtrom tune: plane %dx%d, %d folded ordinates, %s SI sweep, depth %2d: %.1f us\n", A.nx,
+                     A.ny, A.ndf, prec ? "FP64" : "FP32", pd, 1e3f * ms / 3.0f);
+      if (ms < tbest) {
+        tbest = ms;
+        best[prec] = pd;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != RTROM_OK) {
+    rt_set_error("plane: sweep tuning failed");
+    return rc;
+  }
+  H->pd32 = best[0];
+  H->pd64 = best[1];
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = {best[0], best[1]};
+  return RTROM_OK;
+}
+
 // sweep + per-quadrant sums + un-skew into out
 static int sweep_moment(rtrom_problem *p, PlaneHost *H, int mode, int fp32, double *out, const double *add,
                         int accumulate, const double *rp, double *blkmax) {
@@ -744,8 +850,8 @@ static int sweep_moment(rtrom_problem *p, PlaneHost *H, int mode, int fp32, doub
   const dim3 grid(A.ndf), block(64 * A.nw), qgrid(A.nsblk, 4);
   const int kind = mode == 0 ? RT_K_PLANE_SWEEP : RT_K_PLANE_FPASS;
   rt_prof_begin(kind, s);
-  if (mode == 0 && fp32) hipLaunchKernelGGL((k_plane_sweep<float, 0, 8>), grid, block, 0, s, A);
-  else if (mode == 0) hipLaunchKernelGGL((k_plane_sweep<double, 0, 8>), grid, block, 0, s, A);
+  if (mode == 0 && fp32) launch_si_sweep<float>(H->pd32, grid, block, s, A);
+  else if (mode == 0) launch_si_sweep<double>(H->pd64, grid, block, s, A);
   else if (mode == 1) hipLaunchKernelGGL((k_plane_sweep<double, 1, 4>), grid, block, 0, s, A);
   else hipLaunchKernelGGL((k_plane_sweep<double, 2, 4>), grid, block, 0, s, A);
   rt_prof_end(kind, s);
@@ -923,6 +1029,11 @@ int rt_plane_create(rtrom_problem *p) {
     rho_k = rho_n;
   }
   PH(hipMemcpyAsync(H->cheb_c, cc.data(), cc.size() * 8, hipMemcpyHostToDevice, p->stream));
+  // the SI sweep's prefetch depth for this grid shape (the source is zero
+  // until the first step writes it)
+  PH(hipMemsetAsync(H->A.srcq, 0, 4 * (size_t)H->A.SQ * 8, p->stream));
+  const int tr = tune_si_sweep(p, H);
+  if (tr != RTROM_OK) return tr;
   // b~^0 from f^0
   return rt_plane_rhs(p);
 }

@@ -187,3 +187,35 @@ def test_serving_size_request_512():
         e = rel_l2(g.rho(), ref[k])
         say(f"  step {k + 1}: rel L2 {e:.3e}")
         assert e <= 1e-8
+
+
+def test_plane_batch_equals_alone_bitwise():
+    """A 2D batch marches its members concurrently (one host thread and
+    stream set each); every result is bitwise what the problem gets alone."""
+    specs = [W.random_plane(60 + k, n, na, npol, method=m, precision=pr, nsteps=12)
+             for k, (n, na, npol, m, pr) in enumerate([(32, 8, 4, "rom", "mixed"), (48, 16, 4, "si_dsa", "fp64"),
+                                                        (40, 8, 4, "rom", "fp64"), (24, 12, 6, "rom", "mixed"),
+                                                        (64, 8, 4, "rom", "mixed")])]
+    say(f"plane batch of {len(specs)}")
+    batch = [rtrom.Problem(s) for s in specs]
+    rtrom.march_batch(batch, 12)
+    for s, b in zip(specs, batch):
+        a = rtrom.Problem(s)
+        a.march(12)
+        assert np.array_equal(a.rho(), b.rho()), s.name
+        assert a.stats()["si_iters_total"] == b.stats()["si_iters_total"]
+
+
+def test_plane_sweep_prefetch_depth_does_not_change_results(monkeypatch):
+    """The autotuned prefetch depth of the SI sweep only schedules loads: the
+    same problem run at depths 2, 4, 8 and 16 gives bitwise the same march."""
+    spec = W.random_plane(71, 48, 8, 4, method="rom", precision="mixed", nsteps=10)
+    ref = None
+    for pd in (2, 4, 8, 16):
+        monkeypatch.setenv("RTROM_PLANE_PD", f"{pd},{pd}")
+        g = rtrom.Problem(spec)
+        g.march(spec.nsteps)
+        r = g.rho()
+        if ref is None:
+            ref = r
+        assert np.array_equal(r, ref), pd

@@ -210,6 +210,37 @@ def test_batch_equals_alone_bitwise():
         assert a.stats()["si_iters_total"] == b.stats()["si_iters_total"]
 
 
+def test_step_graph_replays_equal_eager_launches(monkeypatch):
+    """A march of several steps replays one captured step; its results, step
+    by step, equal eager launches bitwise (marched one step per call, which
+    never captures), for a batch that mixes the wave-per-pair and pair-group
+    kernels, both methods and both precisions, over several marches in a row
+    (every replay reads its step from the device state)."""
+    specs = [W.random_slab(40 + k, nx, nv, method=m, precision=pr)
+             for k, (nx, nv, m, pr) in enumerate([(300, 16, "rom", "mixed"), (2048, 32, "rom", "fp64"),
+                                                   (2600, 16, "rom", "mixed"), (90, 8, "si_dsa", "fp64")])]
+    say("graph replays vs eager launches")
+    g = [rtrom.Problem(s) for s in specs]
+    e = [rtrom.Problem(s) for s in specs]
+    for chunk in (7, 2, 16):
+        rtrom.march_batch(g, chunk)
+        for _ in range(chunk):
+            rtrom.march_batch(e, 1)
+        for a, b in zip(g, e):
+            np.testing.assert_array_equal(a.rho(), b.rho())
+    for a, b in zip(g, e):
+        np.testing.assert_array_equal(a.f(), b.f())
+        ha, hb = a.history(), b.history()
+        for k in ha:
+            np.testing.assert_array_equal(ha[k], hb[k])
+    # the same with graphs switched off: a multi-step eager march
+    monkeypatch.setenv("RTROM_GRAPH", "0")
+    x = rtrom.Problem(specs[1].replace(single_wg=True))  # a batch runs one workgroup per problem
+    x.march(25)
+    np.testing.assert_array_equal(x.rho(), g[1].rho())
+    assert g[0].stats()["phase"] >= 2
+
+
 def test_deterministic_reruns():
     spec = W.slab_random_regions(nx=2000, n_polar=32, nsteps=60)
     a, b = rtrom.Problem(spec), rtrom.Problem(spec)
