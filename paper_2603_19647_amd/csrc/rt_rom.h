@@ -8,7 +8,7 @@
 // LU run in one workgroup per ROM.  The O(N r^2) basis rotation
 // U <- [U q] U_c, W <- [W b] V_c applies the "pending update" the core leaves
 // behind: grid-wide (k_rom_update, the cooperative step tail) or, for a
-// small slab, by the same post workgroup (rom_rotate_own).  Cells are owned
+// small slab, by the same post workgroup (rom_rotate_own_lu).  Cells are owned
 // with a stride (c = tid, tid + NT, ...) so that every pass over a basis
 // column is a coalesced stream.
 #pragma once
@@ -125,10 +125,12 @@ __device__ __forceinline__ double lane_read(double v, int l) {
   return __hiloint2double(hi, lo);
 }
 
-__device__ inline int lu_factor_wave(double *A, int *perm_lds, int n, double *LUg, int *permg, int *flag) {
+// The factorisation itself, by wave 0 alone (no workgroup barrier): the
+// calling wave must be wave 0; returns 1 if singular (every lane).
+__device__ inline int lu_factor_rows(double *A, int n, double *LUg, int *permg) {
   static_assert(RT_RMAX <= 32, "rows live in the first two DPP rows of the wave");
-  (void)perm_lds;
-  if (threadIdx.x < 64) {
+  int bad;
+  {
     const int lane = threadIdx.x;
     const bool mine = lane < n;
     double row[RT_RMAX];
@@ -140,7 +142,7 @@ __device__ inline int lu_factor_wave(double *A, int *perm_lds, int n, double *LU
     }
     m = dpp_max16(m);
     const double amax = fmax(lane_read(m, 0), lane_read(m, 16));
-    int bad = (amax == 0.0);
+    bad = (amax == 0.0);
     bool active = mine;
     int pos = 0;
 #pragma unroll
@@ -190,7 +192,15 @@ __device__ inline int lu_factor_wave(double *A, int *perm_lds, int n, double *LU
         if (j < n) stg(&LUg[pos * RT_RMAX + j], row[j]);
       stg(&permg[pos], lane);
     }
-    if (lane == 0) *flag = bad;
+  }
+  return bad;
+}
+
+__device__ inline int lu_factor_wave(double *A, int *perm_lds, int n, double *LUg, int *permg, int *flag) {
+  (void)perm_lds;
+  if (threadIdx.x < 64) {
+    const int bad = lu_factor_rows(A, n, LUg, permg);
+    if (threadIdx.x == 0) *flag = bad;
   }
   __syncthreads();
   const int bad = *flag;
@@ -279,52 +289,122 @@ __device__ inline void lu_solve_wave(const double *LU, const int *perm, int n, d
 // global vectors; cells with a stride of NT <= blockDim (the instance's own
 // thread count, so the summation order does not depend on the launch).  Ends
 // with a barrier, so `out` is visible to the whole workgroup afterwards.
-__device__ inline void rom_apply(const RomDev &R, int rank, int ld, int nc, int NT, const double *rhs,
-                                 double *out, double *red, double *vec) {
+//
+// Loads go in batches: CPT cells of the thread (c, c + NT, ...) times KB1
+// basis columns for U^T rhs, CPT cells times KB2 columns for the expansion,
+// each batch in flight at once.  Every column's sum runs over the thread's
+// cells in increasing order and every cell's expansion over the columns in
+// order, whatever the batch shape, so the result does not depend on it.
+// Inside a batch, columns past the rank re-read column rank - 1 (finite, and
+// from cache): their sums are not used, and in the expansion they meet
+// c_k = 0.  luS (LDS, RT_RMAX^2 doubles followed by
+// RT_RMAX ints), when given: the factors and the permutation are loaded
+// beside the first basis batch and staged there, so the substitution reads
+// LDS instead of waiting on global loads (needs blockDim >= RT_RMAX^2 / 2).
+template <int CPT = 1, int KB1 = 4, int KB2 = 5>
+__device__ __forceinline__ void rom_apply(const RomDev &R, int rank, int ld, int nc, int NT, const double *rhs,
+                                 double *out, double *red, double *vec, double *luS = nullptr) {
+  static_assert(RT_RMAX % KB1 == 0 && RT_RMAX % KB2 == 0, "column batches tile the capacity");
+  rank = __builtin_amdgcn_readfirstlane(rank);  // uniform: column addresses in scalar registers
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const bool act = (int)threadIdx.x < NT;
-  // U^T rhs four columns at a time.  The basis keeps RT_RMAX + 1 allocated
-  // columns with finite entries, so the loads past the rank are unconditional
-  // (all in flight together) and their sums are simply not used.
-  for (int k0 = 0; k0 < rank; k0 += 4) {
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int c = threadIdx.x; c < nc && act; c += NT) {
-      const double v = ldg(&rhs[c]);
-      double u[4];
+  constexpr int NLU = RT_RMAX * RT_RMAX;
+  double lu_pre[2] = {0.0, 0.0};
+  int perm_pre = 0;
+  if (luS) {  // uniform
 #pragma unroll
-      for (int q = 0; q < 4; ++q) u[q] = ldg(&R.U[(size_t)(k0 + q) * ld + c]);
+    for (int h = 0; h < 2; ++h) {
+      const int e = threadIdx.x + h * (int)blockDim.x;
+      if (e < NLU) lu_pre[h] = ldg(&R.LU[e]);
+    }
+    if ((int)threadIdx.x < RT_RMAX) perm_pre = R.perm[threadIdx.x];
+  }
+  double s[RT_RMAX];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) s[q] = rt_fma(u[q], v, s[q]);
+  for (int k = 0; k < RT_RMAX; ++k) s[k] = 0.0;
+  for (int c0 = threadIdx.x; c0 < nc && act; c0 += CPT * NT) {
+    double v[CPT];
+    bool ok[CPT];
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      ok[i] = c0 + i * NT < nc;
+      v[i] = ok[i] ? ldg(&rhs[c0 + i * NT]) : 0.0;
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const double t = wave_sum_fast(s[q]);
-      if (lane == 0) red[wave * RT_RMAX + k0 + q] = t;
+    for (int k0 = 0; k0 < RT_RMAX; k0 += KB1) {
+      {
+        // columns past the rank read the last column again (cached: no
+        // further memory traffic) instead of branching between batches
+        double u[CPT][KB1];
+#pragma unroll
+        for (int q = 0; q < KB1; ++q) {
+          const double *col = R.U + (size_t)min(k0 + q, rank - 1) * ld + c0;
+#pragma unroll
+          for (int i = 0; i < CPT; ++i) u[i][q] = ok[i] ? ldg(&col[i * NT]) : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < CPT; ++i)
+          if (ok[i])
+#pragma unroll
+            for (int q = 0; q < KB1; ++q) s[k0 + q] = rt_fma(u[i][q], v[i], s[k0 + q]);
+      }
     }
+  }
+#pragma unroll
+  for (int k0 = 0; k0 < RT_RMAX; k0 += KB1)
+    if (k0 < rank)
+#pragma unroll
+      for (int q = 0; q < KB1; ++q) {
+        const double t = wave_sum_fast(s[k0 + q]);
+        if (lane == 0) red[wave * RT_RMAX + k0 + q] = t;
+      }
+  int *permS = reinterpret_cast<int *>(luS + NLU);
+  if (luS) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = threadIdx.x + h * (int)blockDim.x;
+      if (e < NLU) luS[e] = lu_pre[h];
+    }
+    if ((int)threadIdx.x < RT_RMAX) permS[threadIdx.x] = perm_pre;
   }
   __syncthreads();
   if ((int)threadIdx.x < RT_RMAX) {
-    double s = 0.0;
+    double t = 0.0;
     if ((int)threadIdx.x < rank)
-      for (int w = 0; w < nw; ++w) s += red[w * RT_RMAX + threadIdx.x];
-    vec[threadIdx.x] = s;  // zero past the rank
+      for (int w = 0; w < nw; ++w) t += red[w * RT_RMAX + threadIdx.x];
+    vec[threadIdx.x] = t;  // zero past the rank
   }
   __syncthreads();
-  lu_solve_wave(R.LU, R.perm, rank, vec);
-  // expansion U c, five columns per batch of loads (batches up to the rank;
-  // c_k = 0 past it); the batches stay a loop to keep the caller's
-  // registers free
-  for (int c = threadIdx.x; c < nc && act; c += NT) {
-    double v = 0.0;
-#pragma unroll 1
-    for (int k0 = 0; k0 < rank; k0 += 5) {
-      double u[5];
+  if (luS) lu_solve_wave(luS, permS, rank, vec);
+  else lu_solve_wave(R.LU, R.perm, rank, vec);
+  // expansion U c; the batches stay a loop to keep the caller's registers free
+  for (int c0 = threadIdx.x; c0 < nc && act; c0 += CPT * NT) {
+    bool ok[CPT];
+    double acc[CPT];
 #pragma unroll
-      for (int q = 0; q < 5; ++q) u[q] = ldg(&R.U[(size_t)(k0 + q) * ld + c]);
-#pragma unroll
-      for (int q = 0; q < 5; ++q) v = rt_fma(u[q], vec[k0 + q], v);
+    for (int i = 0; i < CPT; ++i) {
+      ok[i] = c0 + i * NT < nc;
+      acc[i] = 0.0;
     }
-    stg(&out[c], v);
+#pragma unroll 1
+    for (int k0 = 0; k0 < rank; k0 += KB2) {
+      double u[CPT][KB2];
+#pragma unroll
+      for (int q = 0; q < KB2; ++q) {
+        const double *col = R.U + (size_t)min(k0 + q, rank - 1) * ld + c0;  // c_k = 0 past the rank
+#pragma unroll
+        for (int i = 0; i < CPT; ++i) u[i][q] = ok[i] ? ldg(&col[i * NT]) : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < KB2; ++q) {
+        const double cq = vec[k0 + q];
+#pragma unroll
+        for (int i = 0; i < CPT; ++i) acc[i] = rt_fma(u[i][q], cq, acc[i]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < CPT; ++i)
+      if (ok[i]) stg(&out[c0 + i * NT], acc[i]);
   }
   __syncthreads();
 }
@@ -607,7 +687,10 @@ __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, in
   if (tid < RT_RMAX) stg(&P->a2[tid], tid < r ? sm.red[2 * RT_RMAX + 2 + tid] : 0.0);
   if (r == 0) {
     if (xn == 0.0) {
-      if (tid == 0) stg(&P->pending, 0);
+      if (tid == 0) {
+        stg(&P->pending, 0);
+        if constexpr (DEFER_LU) sm.ibuf[2] = 0;  // no LU to factor
+      }
       __syncthreads();
       return -1;
     }
@@ -734,10 +817,12 @@ __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, in
   return deficient;
 }
 
-// The LU of A_r that isvd_core<., true> left in sm; returns luok.
+// The LU of A_r that isvd_core<., true> left in sm; returns luok, or -1
+// when the core factored nothing (an empty ROM met a zero snapshot).
 __device__ inline int isvd_lu(const RomDev &R, RomSmem &sm) {
   __syncthreads();
   const int n = sm.ibuf[2];
+  if (n == 0) return -1;  // uniform
   return !lu_factor_wave(sm.A, sm.perm, n, R.LU, R.perm, &sm.ibuf[0]);
 }
 
@@ -795,43 +880,78 @@ __device__ __forceinline__ void rotate_block(const double (&old)[NCELL][RT_RMAX]
 }
 
 
-// The pending rotation of ROM R's two bases, applied by the workgroup whose
-// core just decided it (the fused post of a small instance): every cell of
-// the instance, U then W, with the same per-cell arithmetic as k_rom_update.
-// The rotation record was written by this workgroup in this launch, so it is
-// read with vector loads and the coefficients staged in LDS (sm.Mx, sm.av:
-// free once the core is done).  Each coefficient read from LDS serves two
-// cells of a thread (LDS bandwidth bounds this loop), in blocks of two
-// columns (registers).
-__device__ inline void rom_rotate_own(const Inst &I, const RomDev &R, const RomWork &W, RomSmem &sm) {
+// Cells per thread of the fused post's rotation (rom_rotate_own_lu).  Each
+// coefficient read from LDS there is a wave-wide broadcast serving this many
+// cells of a thread: the LDS return bandwidth, not the FMAs, bounds the loop,
+// so the cells per read go as high as the registers allow (one output column
+// at a time).
+constexpr int ROT_CELLS = 3;
+
+// The fused post's last stage after rom_core<., true>: the reduced
+// operator's LU and the pending rotation of both bases at once, by the
+// workgroup whose core just decided it.  The rotation record was written by
+// this workgroup in this launch, so it is read with vector loads and the
+// coefficients staged in LDS (sm.Mx, sm.T1, sm.av: free once the core is
+// done).  Wave 0
+// factors (lu_factor_rows) while the other waves start rotating; the cells
+// are handed out in chunks of 64 * ROT_CELLS (U's chunks, then W's) through
+// an LDS counter, so wave 0 takes what is left once its LU is done.  A cell's
+// arithmetic does not depend on which wave rotates it.  Ends with the LU flag
+// written to the state (z: 0 IG, 1 PC).
+__device__ inline void rom_rotate_own_lu(const Inst &I, const RomDev &R, const RomWork &W, RomSmem &sm, int z) {
   const RomPend *P = R.pend;
-  __syncthreads();
-  if (!xload(&P->pending)) return;  // uniform
-  const int r = xload(&P->r_old), k = xload(&P->k), nc = I.nc, ld = I.ld, NT = blockDim.x;
-  const double inv_nu = xload(&P->inv_nu);
-  double *cc = sm.Mx, *a2 = sm.av;
-  for (int mat = 0; mat < 2; ++mat) {
-    const double *src = mat ? P->Vc : P->Uc;
-    for (int e = threadIdx.x; e < RT_KC * RT_KC; e += NT) cc[e] = ldg(&src[e]);
-    if (threadIdx.x < RT_RMAX) a2[threadIdx.x] = ldg(&P->a2[threadIdx.x]);
-    __syncthreads();
-    double *X = mat ? R.W : R.U;
-    for (int c0 = 0; c0 < nc; c0 += 2 * NT) {
-      int cv[2];
-      bool ok[2];
-      double old[2][RT_RMAX], e[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        cv[i] = c0 + i * NT + (int)threadIdx.x;
-        ok[i] = cv[i] < nc;
-        const int cl = ok[i] ? cv[i] : nc - 1;
-#pragma unroll
-        for (int q = 0; q < RT_RMAX; ++q) old[i][q] = q < r ? ldg(&X[(size_t)q * ld + cl]) : 0.0;
-        e[i] = mat ? ldg(&W.b[cl]) : second_residual(ldg(&W.p[cl]), old[i], a2) * inv_nu;
-      }
-      rotate_block<2, double *, 2>(old, e, cc, r, k, X, ld, cv, ok);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, NT = blockDim.x;
+  __syncthreads();  // the core's results (sm.A, sm.ibuf[2], the rotation record) are complete
+  const int n_lu = sm.ibuf[2];
+  const int pending = xload(&P->pending);  // uniform
+  int r = 0, k = 0, nchunk = 0;
+  double inv_nu = 0.0;
+  if (pending) {
+    r = xload(&P->r_old);
+    k = xload(&P->k);
+    inv_nu = xload(&P->inv_nu);
+    for (int e = threadIdx.x; e < RT_KC * RT_KC; e += NT) {
+      sm.Mx[e] = ldg(&P->Uc[e]);
+      sm.T1[e] = ldg(&P->Vc[e]);
     }
-    __syncthreads();
+    if (threadIdx.x < RT_RMAX) sm.av[threadIdx.x] = ldg(&P->a2[threadIdx.x]);
+    nchunk = (I.nc + 64 * ROT_CELLS - 1) / (64 * ROT_CELLS);
+  }
+  if (threadIdx.x == 0) sm.ibuf[3] = 0;
+  __syncthreads();
+  if (wave == 0 && n_lu > 0) {
+    const int bad = lu_factor_rows(sm.A, n_lu, R.LU, R.perm);
+    if (lane == 0) sm.ibuf[0] = bad;
+  }
+  const int nc = I.nc, ld = I.ld;
+  for (;;) {
+    int t = 0;
+    if (lane == 0) t = atomicAdd(&sm.ibuf[3], 1);
+    t = __builtin_amdgcn_readfirstlane(t);
+    if (t >= 2 * nchunk) break;
+    const int mat = t >= nchunk;
+    const int cb = (t - mat * nchunk) * 64 * ROT_CELLS + lane;
+    const double *cc = mat ? sm.T1 : sm.Mx;
+    double *X = mat ? R.W : R.U;
+    int cv[ROT_CELLS];
+    bool ok[ROT_CELLS];
+    double old[ROT_CELLS][RT_RMAX], e[ROT_CELLS];
+#pragma unroll
+    for (int i = 0; i < ROT_CELLS; ++i) {
+      cv[i] = cb + 64 * i;
+      ok[i] = cv[i] < nc;
+      const int cl = ok[i] ? cv[i] : nc - 1;
+#pragma unroll
+      for (int q = 0; q < RT_RMAX; ++q) old[i][q] = q < r ? ldg(&X[(size_t)q * ld + cl]) : 0.0;
+      e[i] = mat ? ldg(&W.b[cl]) : second_residual(ldg(&W.p[cl]), old[i], sm.av) * inv_nu;
+    }
+    rotate_block<ROT_CELLS, const double *, 1>(old, e, cc, r, k, X, ld, cv, ok);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && n_lu > 0) {
+    const int luok = !sm.ibuf[0];
+    if (z == 0) I.st->lu_ok_ig = luok;
+    else I.st->lu_ok_pc = luok;
   }
 }
 
@@ -1123,7 +1243,7 @@ __device__ __forceinline__ void rom_core(const Inst &I, const RomDev &R, const R
 // The deferred LU of rom_core<., true> and its flag (every thread calls).
 __device__ __forceinline__ void rom_core_lu(const Inst &I, const RomDev &R, int z, RomSmem &sm) {
   const int luok = isvd_lu(R, sm);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && luok >= 0) {
     if (z == 0) I.st->lu_ok_ig = luok;
     else I.st->lu_ok_pc = luok;
   }

@@ -82,9 +82,10 @@ __global__ void __launch_bounds__(256) k_rom_core(const Inst *__restrict__ insts
 // k_rom_post_small: the whole incremental-SVD update of a small instance (the
 // slab path, whose SI kernel already took the step's decisions), one
 // workgroup per (instance, ROM): the two passes with workgroup reductions
-// (one partial row), the core, then the rotation of the ROM's two bases.  One
-// launch instead of four, no grid-wide partial sums, and the rotation's
-// traffic overlaps the f-pass that runs beside this launch.
+// (one partial row), the core, then the rotation of the ROM's two bases with
+// the reduced operator's LU factored beside it.  One launch instead of four,
+// no grid-wide partial sums, and the rotation's traffic overlaps the f-pass
+// that runs beside this launch.
 // ---------------------------------------------------------------------------
 // two workgroups per CU: the registers stay within half the file
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_rom_post_small(
@@ -102,8 +103,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   __syncthreads();
   rom_pass2<false>(I, R, W, 0, 1, red, out, av, scratch);
   __syncthreads();
-  rom_core<false>(I, R, W, z, sm);
-  rom_rotate_own(I, R, W, sm);
+  rom_core<false, true>(I, R, W, z, sm);
+  rom_rotate_own_lu(I, R, W, sm, z);  // the LU beside the rotation
 }
 
 // ---------------------------------------------------------------------------

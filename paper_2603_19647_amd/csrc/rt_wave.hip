@@ -243,7 +243,7 @@ __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts)
   // initial guess: DMD when the IG ROM is available (eq. dmd-ig), else rho^{n-1}
   int ig_fb = 0;
   if (rom && flag_ig && lu_ig) {
-    rom_apply(I.ig, rank_ig, I.ld, nc, WNT, bt, I.rho0, rred, rvec);
+    rom_apply<WOWN, 10, 10>(I.ig, rank_ig, I.ld, nc, WNT, bt, I.rho0, rred, rvec, redd);
   } else {
     ig_fb = rom && flag_ig;
     for (int c = c0; c < c0 + n; ++c) stg(&I.rho0[c], ldg(&I.rho[c]));
@@ -312,7 +312,7 @@ __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts)
       for (int t = 0; t < WOWN; ++t)
         if (t < n) stg(&I.work[c0 + t], y[t] - ldg(&I.rho0[c0 + t]));
       __syncthreads();
-      rom_apply(I.pc, rank_pc, I.ld, nc, WNT, I.work, I.dpc, rred, rvec);
+      rom_apply<WOWN, 10, 10>(I.pc, rank_pc, I.ld, nc, WNT, I.work, I.dpc, rred, rvec, redd);
 #pragma unroll
       for (int t = 0; t < WOWN; ++t) d[t] = (t < n) ? ldg(&I.dpc[c0 + t]) : 0.0;
       used_pc = 1;
