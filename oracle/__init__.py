@@ -17,6 +17,8 @@ _SRC = os.path.join(_HERE, "rtrom_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 METHOD = {"si_dsa": 0, "rom": 1, "si": 2}
+PRECOND = {"dsa": 0, "mh": 1}
+TIME_SCHEME = {"be": 0, "bdf2": 1}
 _D = ctypes.POINTER(ctypes.c_double)
 
 
@@ -31,6 +33,8 @@ class OrcDesc(ctypes.Structure):
         ("max_iter", ctypes.c_int32), ("method", ctypes.c_int32),
         ("eps_ig", ctypes.c_double), ("eps_pc", ctypes.c_double), ("eps_up", ctypes.c_double),
         ("r_max", ctypes.c_int32), ("abs_up_norm", ctypes.c_int32),
+        ("precond", ctypes.c_int32), ("time_scheme", ctypes.c_int32),
+        ("pc_levels", ctypes.c_int32), ("mh_rank", ctypes.c_int32),
     ]
 
 
@@ -98,6 +102,13 @@ def lib():
     L.orc_rom_get.argtypes = [vp, _D, _D, _D]
     L.orc_rom_reduced.argtypes = [vp, _D]
     L.orc_rom_solve.argtypes = [vp, _D, _D]
+    L.orc_mh_new.restype = vp
+    L.orc_mh_new.argtypes = [ctypes.c_int, ctypes.c_int]
+    L.orc_mh_delete.argtypes = [vp]
+    L.orc_mh_push.argtypes = [vp, _D, _D]
+    L.orc_mh_size.argtypes = [vp]
+    L.orc_mh_correct.argtypes = [vp, _D, _D]
+    L.orc_get_levels.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     assert L.orc_step_rec_size() == ctypes.sizeof(StepRec)
     assert L.orc_desc_size() == ctypes.sizeof(OrcDesc)
     _lib = L
@@ -189,6 +200,40 @@ class Rom:
             pass
 
 
+class MhModel:
+    """Standalone McClarren-Haut model (DMD of the sweep operator from
+    iteration pairs, Sec. 3.3)."""
+
+    def __init__(self, nc: int, cap: int):
+        self.nc = nc
+        self.h = lib().orc_mh_new(nc, cap)
+        if not self.h:
+            raise ValueError("bad McClarren-Haut model size")
+
+    def push(self, x, z) -> bool:
+        """Add (x, z = T Sigma_s x); False when the pair was skipped."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        z = np.ascontiguousarray(z, dtype=np.float64)
+        return lib().orc_mh_push(self.h, _p(x), _p(z)) == 0
+
+    @property
+    def size(self) -> int:
+        return lib().orc_mh_size(self.h)
+
+    def correct(self, r):
+        """(correction, applied) for the SI residual r."""
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        out = np.zeros(self.nc)
+        bad = lib().orc_mh_correct(self.h, _p(r), _p(out))
+        return out, bad == 0
+
+    def __del__(self):
+        try:
+            lib().orc_mh_delete(self.h)
+        except Exception:
+            pass
+
+
 class OracleProblem:
     """One oracle time-marching problem built from a ``ProblemSpec``."""
 
@@ -212,6 +257,10 @@ class OracleProblem:
         d.eps_ig, d.eps_pc, d.eps_up = spec.eps_ig, spec.eps_pc, spec.eps_up
         d.r_max = spec.r_max
         d.abs_up_norm = int(spec.abs_up_norm)
+        d.precond = PRECOND[spec.precond]
+        d.time_scheme = TIME_SCHEME[spec.time_scheme]
+        d.pc_levels = int(spec.pc_levels)
+        d.mh_rank = int(spec.mh_rank)
         self.h = lib().orc_create(ctypes.byref(d))
         if not self.h:
             raise ValueError("oracle rejected the problem description")
@@ -251,6 +300,13 @@ class OracleProblem:
                 "pc_updates", "n0", "n1", "flag_ig", "flag_pc", "rank_ig", "rank_pc")
         return dict(zip(keys, list(a)))
 
+    def levels(self):
+        """Per correction level: flag, N_k, rank, updates."""
+        a = (ctypes.c_int64 * 16)()
+        L = lib().orc_get_levels(self.h, a)
+        return [dict(flag=int(a[4 * k]), n=int(a[4 * k + 1]), rank=int(a[4 * k + 2]),
+                     updates=int(a[4 * k + 3])) for k in range(L)]
+
     def history(self):
         n = self.counters()["steps"]
         arr = (StepRec * max(n, 1))()
@@ -269,7 +325,7 @@ class OracleProblem:
     def rom(self, which: str):
         """(U, S, W) of the problem's IG (``"ig"``) or PC (``"pc"``) ROM, with
         the basis and W = B V as columns."""
-        z = {"ig": 0, "pc": 1}[which]
+        z = {"ig": 0, "pc": 1}[which] if isinstance(which, str) else int(which)
         r = lib().orc_get_rom(self.h, z, _D(), _D(), _D())
         U = np.zeros((max(r, 1), self.nc))
         Wm = np.zeros((max(r, 1), self.nc))

@@ -45,6 +45,16 @@
 #define ORC_ROM_SI_DSA 1
 #define ORC_SI_PLAIN 2
 
+/* correction used where DSA would be (Sec. 3.3, Sec. 4.5) */
+#define ORC_PC_DSA 0
+#define ORC_PC_MH 1
+
+/* time discretisation (Sec. 2.1) */
+#define ORC_BE 0
+#define ORC_BDF2 1
+
+#define ORC_MAX_LEVELS 4
+
 typedef struct {
   int32_t dim, nx, ny;
   double lx, ly;
@@ -57,6 +67,10 @@ typedef struct {
   double eps_ig, eps_pc, eps_up;
   int32_t r_max;
   int32_t abs_up_norm;
+  int32_t precond;     /* ORC_PC_DSA or ORC_PC_MH */
+  int32_t time_scheme; /* ORC_BE or ORC_BDF2 */
+  int32_t pc_levels;   /* sequential correction ROMs for iterations 1..pc_levels (0 = 1) */
+  int32_t mh_rank;     /* McClarren-Haut pairs per model (0 = r_max) */
 } orc_desc;
 
 typedef struct {
@@ -471,29 +485,172 @@ void orc_rom_solve(void *h, const double *rhs, double *out) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* McClarren-Haut DMD across iterations (Sec. 3.3)                          */
+/* ------------------------------------------------------------------------ */
+
+/* McClarren-Haut model of the sweep operator T Sigma_s built from the pairs
+ * of one time step's iterations (Sec. 3.3): input differences
+ * rho^{(k-1)} - rho^{(k-2)} and their images y_k - y_{k-1}, each pair scaled
+ * by the input's 2-norm.  Reading: the pairs' DMD is computed through a QR
+ * factorisation of the inputs (X = Q R, Gram-Schmidt applied twice) instead
+ * of an SVD; without truncation both give the same reduced operator
+ * Q^T T Sigma_s Q = Q^T Z R^{-1}. */
+typedef struct {
+  int nc, cap, m;
+  double *Q; /* orthonormal inputs, column k at Q + k*nc */
+  double *Z; /* scaled outputs, column k at Z + k*nc */
+  double *R; /* upper triangular, R[i*cap + j] */
+} orc_mh;
+
+/* Reading: a pair whose scaled input has an orthogonal remainder at or below
+ * this fraction of its norm adds no new direction and is skipped (its image
+ * would be dominated by rounding). */
+#define ORC_MH_DEP 1e-6
+
+static int mh_init(orc_mh *M, int nc, int cap) {
+  memset(M, 0, sizeof(*M));
+  M->nc = nc;
+  M->cap = cap;
+  M->Q = (double *)calloc((size_t)cap * nc, sizeof(double));
+  M->Z = (double *)calloc((size_t)cap * nc, sizeof(double));
+  M->R = (double *)calloc((size_t)cap * cap, sizeof(double));
+  return (M->Q && M->Z && M->R) ? ORC_OK : ORC_ENOMEM;
+}
+
+static void mh_free(orc_mh *M) {
+  free(M->Q);
+  free(M->Z);
+  free(M->R);
+}
+
+/* Add the pair (x, z = T Sigma_s x), both scaled by 1/||x||_2.  A full model
+ * (cap pairs) restarts from this pair.  Returns 1 when the pair was skipped. */
+static int mh_push(orc_mh *M, const double *x, const double *z, double *p) {
+  const int nc = M->nc;
+  const double xn = sqrt(dot(nc, x, x));
+  if (!(xn > 0.0)) return 1;
+  if (M->m == M->cap) M->m = 0;
+  const int m = M->m;
+  double a[64], a2[64];
+  for (int k = 0; k < m; ++k) a[k] = dot(nc, M->Q + (size_t)k * nc, x) / xn;
+  for (int i = 0; i < nc; ++i) {
+    double v = x[i] / xn;
+    for (int k = 0; k < m; ++k) v -= M->Q[(size_t)k * nc + i] * a[k];
+    p[i] = v;
+  }
+  for (int k = 0; k < m; ++k) a2[k] = dot(nc, M->Q + (size_t)k * nc, p);
+  for (int i = 0; i < nc; ++i) {
+    double v = p[i];
+    for (int k = 0; k < m; ++k) v -= M->Q[(size_t)k * nc + i] * a2[k];
+    p[i] = v;
+  }
+  const double nu = sqrt(dot(nc, p, p));
+  if (!(nu > ORC_MH_DEP)) return 1;
+  for (int i = 0; i < nc; ++i) {
+    M->Q[(size_t)m * nc + i] = p[i] / nu;
+    M->Z[(size_t)m * nc + i] = z[i] / xn;
+  }
+  for (int k = 0; k < m; ++k) M->R[k * M->cap + m] = a[k] + a2[k];
+  M->R[m * M->cap + m] = nu;
+  for (int k = m + 1; k < M->cap; ++k) M->R[k * M->cap + m] = 0.0;
+  M->m = m + 1;
+  return 0;
+}
+
+/* Correction from the model: with A~ = Q^T Z R^{-1} (the pairs' DMD of
+ * T Sigma_s on span(Q)), the ideal correction equation (I - T Sigma_s) d =
+ * T Sigma_s r (eq. ideal_correct) restricted to span(Q) gives
+ * d = Q (I - A~)^{-1} A~ Q^T r.  Returns 0 when applied, 1 when there is no
+ * model or I - A~ is singular (out = 0 then). */
+static int mh_correct(const orc_mh *M, const double *r, double *out) {
+  const int nc = M->nc, m = M->m, cap = M->cap;
+  memset(out, 0, sizeof(double) * nc);
+  if (m == 0) return 1;
+  double B[64 * 64], At[64 * 64], Mi[64 * 64], g[64], qr[64];
+  int piv[64];
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) B[i * m + j] = dot(nc, M->Q + (size_t)i * nc, M->Z + (size_t)j * nc);
+  /* A~ R = B, R upper triangular: column by column */
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      double v = B[i * m + j];
+      for (int k = 0; k < j; ++k) v -= At[i * m + k] * M->R[k * cap + j];
+      At[i * m + j] = v / M->R[j * cap + j];
+    }
+  for (int k = 0; k < m; ++k) qr[k] = dot(nc, M->Q + (size_t)k * nc, r);
+  for (int i = 0; i < m; ++i) {
+    double v = 0.0;
+    for (int k = 0; k < m; ++k) v += At[i * m + k] * qr[k];
+    g[i] = v;
+  }
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) Mi[i * m + j] = (i == j ? 1.0 : 0.0) - At[i * m + j];
+  if (orc_lu_factor(m, Mi, piv)) return 1;
+  orc_lu_solve(m, Mi, piv, g);
+  for (int i = 0; i < nc; ++i) {
+    double v = 0.0;
+    for (int k = 0; k < m; ++k) v += M->Q[(size_t)k * nc + i] * g[k];
+    out[i] = v;
+  }
+  return 0;
+}
+
+/* standalone model for the unit pins */
+void *orc_mh_new(int nc, int cap) {
+  orc_mh *M = (orc_mh *)malloc(sizeof(orc_mh));
+  if (!M) return NULL;
+  if (cap < 1 || cap > 64 || mh_init(M, nc, cap)) {
+    mh_free(M);
+    free(M);
+    return NULL;
+  }
+  return M;
+}
+void orc_mh_delete(void *h) {
+  if (!h) return;
+  mh_free((orc_mh *)h);
+  free(h);
+}
+int orc_mh_push(void *h, const double *x, const double *z) {
+  orc_mh *M = (orc_mh *)h;
+  double *p = (double *)malloc(sizeof(double) * M->nc);
+  int r = mh_push(M, x, z, p);
+  free(p);
+  return r;
+}
+int orc_mh_size(void *h) { return ((orc_mh *)h)->m; }
+int orc_mh_correct(void *h, const double *r, double *out) { return mh_correct((orc_mh *)h, r, out); }
+
+/* ------------------------------------------------------------------------ */
 /* Problem state                                                             */
 /* ------------------------------------------------------------------------ */
+
 
 typedef struct {
   orc_desc d;
   int nc, nv;
   double hx, hy;
   double *ox, *oy, *oz, *w; /* ordinates (1D: ox = mu) */
-  double *ss, *sa, *G, *ct; /* sigma_s, sigma_a, source, sigma_t + 1/dt */
+  double *ss, *sa, *G, *ct; /* sigma_s, sigma_a, source, sigma_t + alpha/dt */
+  double alpha;             /* time-derivative weight of the current operator:
+                               1 (backward Euler, and the first BDF2 step) or 3/2 */
   double *f;                /* f^n, [nv][nc] */
+  double *fold;             /* BDF2: f^{n-1}, [nv][nc] */
   double *rho;              /* rho^n */
   double *bt;               /* b~^{n-1}: right-hand side of the next step */
   /* DSA */
   double *dlo, *ddi, *dup;  /* 1D tridiagonal */
   double *band;             /* 2D: banded Cholesky factor, [nc][bw+1] */
   int bw;
-  /* ROM */
-  orc_rom ig, pc;
-  int flag_ig, flag_pc, n0, n1;
+  /* ROM: initial guess and the correction ROMs of iterations 1..L */
+  int nlev;
+  orc_rom ig, pc[ORC_MAX_LEVELS];
+  int flag_ig, flag_pc[ORC_MAX_LEVELS], n0, nl[ORC_MAX_LEVELS];
+  orc_mh mh;
   /* counters */
   int64_t steps, si_total, sweeps_total;
   int nonconv, fallbacks;
-  int64_t ig_updates, pc_updates;
+  int64_t ig_updates, pc_updates[ORC_MAX_LEVELS];
   orc_step_rec *hist;
   int64_t hist_cap;
   /* vectors of the last step, kept for the pins of Alg. 2: rho^{(0)},
@@ -503,6 +660,10 @@ typedef struct {
   int last_used_pc;
   /* work */
   double *w0, *w1, *w2, *w3, *w4, *w5, *w6, *fcol;
+  double *yl[ORC_MAX_LEVELS + 1];   /* rho^{(l-1/2)}, l = 1..L+1 */
+  double *rl[ORC_MAX_LEVELS + 1];   /* rho^{(l-1)}, l = 1..L+1 */
+  double *dl[ORC_MAX_LEVELS];       /* ROM corrections of iterations 1..L */
+  double *yprev, *rprev2;           /* McClarren-Haut: y_{l-1}, rho^{(l-2)} */
 } orc_problem;
 
 static int desc_valid(const orc_desc *d) {
@@ -515,6 +676,10 @@ static int desc_valid(const orc_desc *d) {
   if (d->dim == 2 && (d->n_azim < 4 || d->n_azim % 4)) return 0;
   if (d->method < 0 || d->method > 2) return 0;
   if (d->r_max < 1) return 0;
+  if (d->precond != ORC_PC_DSA && d->precond != ORC_PC_MH) return 0;
+  if (d->time_scheme != ORC_BE && d->time_scheme != ORC_BDF2) return 0;
+  if (d->pc_levels < 0 || d->pc_levels > ORC_MAX_LEVELS) return 0;
+  if (d->mh_rank < 0 || d->mh_rank > 64) return 0;
   if (!d->sigma_s || !d->sigma_a || !d->source) return 0;
   size_t nc = (size_t)d->nx * d->ny;
   for (size_t i = 0; i < nc; ++i) {
@@ -608,7 +773,7 @@ static double bdry_k(double Dp, double h) { return 2.0 * Dp / (h + 4.0 * Dp); }
 /* matrix entry of the DSA operator, used by both the 1D setup and 2D factor */
 static double dsa_entry(const orc_problem *P, int r, int c) {
   const int nx = P->d.nx, ny = P->d.ny;
-  double sat = P->sa[r] + 1.0 / P->d.dt;
+  double sat = P->sa[r] + P->alpha / P->d.dt;
   int rx = r % nx, ry = r / nx, cx = c % nx, cy = c / nx;
   double hx = P->hx, hy = P->hy;
   if (r == c) {
@@ -632,6 +797,11 @@ static double dsa_entry(const orc_problem *P, int r, int c) {
 
 static int dsa_setup(orc_problem *P) {
   int nc = P->nc;
+  free(P->dlo);
+  free(P->ddi);
+  free(P->dup);
+  free(P->band);
+  P->dlo = P->ddi = P->dup = P->band = NULL;
   if (P->d.dim == 1) {
     P->dlo = (double *)calloc(nc, sizeof(double));
     P->ddi = (double *)calloc(nc, sizeof(double));
@@ -706,26 +876,52 @@ static void dsa_solve(orc_problem *P, const double *rhs, double *x) {
 /* RHS and final sweeps                                                      */
 /* ------------------------------------------------------------------------ */
 
-/* b~ = sum_j w_j (M/dt + D_j + Sigma_t)^{-1} (f_j/dt + G~_j)  (Sec. 2.3) */
-static void compute_rhs(orc_problem *P, const double *f, double *bt) {
+/* Known part of the time derivative for the step about to be taken: f_j/dt
+ * (backward Euler, Sec. 2.1 eq. time_discrete), or (4 f^{n-1}_j - f^{n-2}_j)
+ * / (2 dt) for BDF2 (Sec. 2.1 names BDF as the alternative; its operator
+ * carries 3/(2 dt)).  Reading: BDF2 starts with one backward-Euler step. */
+static double hist_term(const orc_problem *P, int bdf2, size_t k) {
+  if (bdf2) return (4.0 * P->f[k] - P->fold[k]) / (2.0 * P->d.dt);
+  return P->f[k] / P->d.dt;
+}
+
+/* whether step number n (1-based) uses the BDF2 formula */
+static int bdf2_step(const orc_problem *P, int64_t n) {
+  return P->d.time_scheme == ORC_BDF2 && n >= 2;
+}
+
+/* b~ = sum_j w_j (alpha M/dt + D_j + Sigma_t)^{-1} (history_j + G~_j)
+ * (Sec. 2.3) for step number n */
+static void compute_rhs(orc_problem *P, int64_t n, double *bt) {
   int nc = P->nc;
+  const int b2 = bdf2_step(P, n);
   memset(bt, 0, sizeof(double) * nc);
   for (int j = 0; j < P->nv; ++j) {
-    for (int i = 0; i < nc; ++i) P->w0[i] = f[(size_t)j * nc + i] / P->d.dt + P->G[i];
+    for (int i = 0; i < nc; ++i) P->w0[i] = hist_term(P, b2, (size_t)j * nc + i) + P->G[i];
     sweep_one(P, j, P->w0, 0, P->fcol);
     for (int i = 0; i < nc; ++i) bt[i] += P->w[j] * P->fcol[i];
   }
 }
 
-/* f^n_j from rho^n (eq. sweep_to_obtain_f), in place over f^{n-1} */
-static void final_sweep(orc_problem *P, const double *rho) {
+/* f^n_j from rho^n (eq. sweep_to_obtain_f) for step number n; BDF2 keeps
+ * f^{n-1} as the older level */
+static void final_sweep(orc_problem *P, int64_t n, const double *rho) {
   int nc = P->nc;
+  const int b2 = bdf2_step(P, n);
   for (int j = 0; j < P->nv; ++j) {
     double *fj = P->f + (size_t)j * nc;
-    for (int i = 0; i < nc; ++i) P->w0[i] = P->ss[i] * rho[i] + fj[i] / P->d.dt + P->G[i];
+    for (int i = 0; i < nc; ++i) P->w0[i] = P->ss[i] * rho[i] + hist_term(P, b2, (size_t)j * nc + i) + P->G[i];
     sweep_one(P, j, P->w0, 0, P->fcol);
+    if (P->fold) memcpy(P->fold + (size_t)j * nc, fj, sizeof(double) * nc);
     memcpy(fj, P->fcol, sizeof(double) * nc);
   }
+}
+
+/* transport and DSA operators for the time weight alpha (1 or 3/2) */
+static int set_alpha(orc_problem *P, double alpha) {
+  P->alpha = alpha;
+  for (int i = 0; i < P->nc; ++i) P->ct[i] = P->ss[i] + P->sa[i] + alpha / P->d.dt;
+  return dsa_setup(P);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -765,6 +961,31 @@ void *orc_create(const orc_desc *d) {
   P->w5 = (double *)malloc(sizeof(double) * nc);
   P->w6 = (double *)malloc(sizeof(double) * nc);
   P->fcol = (double *)malloc(sizeof(double) * nc);
+  P->nlev = d->pc_levels > 0 ? d->pc_levels : 1;
+  for (int k = 0; k <= P->nlev; ++k) {
+    P->yl[k] = (double *)calloc(nc, sizeof(double));
+    P->rl[k] = (double *)calloc(nc, sizeof(double));
+    if (k < P->nlev) P->dl[k] = (double *)calloc(nc, sizeof(double));
+    if (!P->yl[k] || !P->rl[k] || (k < P->nlev && !P->dl[k])) {
+      orc_destroy(P);
+      return NULL;
+    }
+  }
+  if (d->precond == ORC_PC_MH) {
+    P->yprev = (double *)calloc(nc, sizeof(double));
+    P->rprev2 = (double *)calloc(nc, sizeof(double));
+    if (!P->yprev || !P->rprev2 || mh_init(&P->mh, nc, d->mh_rank > 0 ? d->mh_rank : d->r_max)) {
+      orc_destroy(P);
+      return NULL;
+    }
+  }
+  if (d->time_scheme == ORC_BDF2) {
+    P->fold = (double *)calloc((size_t)nv * nc, sizeof(double));
+    if (!P->fold) {
+      orc_destroy(P);
+      return NULL;
+    }
+  }
   P->last_rho0 = (double *)calloc(nc, sizeof(double));
   P->last_rhalf = (double *)calloc(nc, sizeof(double));
   P->last_dpc = (double *)calloc(nc, sizeof(double));
@@ -787,21 +1008,22 @@ void *orc_create(const orc_desc *d) {
     P->ss[i] = d->sigma_s[i];
     P->sa[i] = d->sigma_a[i];
     P->G[i] = d->source[i];
-    P->ct[i] = d->sigma_s[i] + d->sigma_a[i] + 1.0 / d->dt;
     P->rho[i] = d->f0 ? d->f0[i] : 0.0;
   }
   for (int j = 0; j < nv; ++j)
     for (int i = 0; i < nc; ++i) P->f[(size_t)j * nc + i] = P->rho[i];
-  if (dsa_setup(P) != ORC_OK) {
+  if (set_alpha(P, 1.0) != ORC_OK) {
     orc_destroy(P);
     return NULL;
   }
-  if (rom_init(&P->ig, nc, d->r_max) || rom_init(&P->pc, nc, d->r_max)) {
+  int bad = rom_init(&P->ig, nc, d->r_max);
+  for (int k = 0; k < P->nlev; ++k) bad |= rom_init(&P->pc[k], nc, d->r_max);
+  if (bad) {
     orc_destroy(P);
     return NULL;
   }
   /* b~^0 from f^0 (the RHS sweep of the first step) */
-  compute_rhs(P, P->f, P->bt);
+  compute_rhs(P, 1, P->bt);
   return P;
 }
 
@@ -815,7 +1037,16 @@ void orc_destroy(void *h) {
   free(P->w6); free(P->fcol);
   free(P->dlo); free(P->ddi); free(P->dup); free(P->band);
   rom_free(&P->ig);
-  rom_free(&P->pc);
+  for (int k = 0; k < ORC_MAX_LEVELS; ++k) rom_free(&P->pc[k]);
+  for (int k = 0; k <= ORC_MAX_LEVELS; ++k) {
+    free(P->yl[k]);
+    free(P->rl[k]);
+    if (k < ORC_MAX_LEVELS) free(P->dl[k]);
+  }
+  mh_free(&P->mh);
+  free(P->yprev);
+  free(P->rprev2);
+  free(P->fold);
   free(P->hist);
   free(P->last_rho0); free(P->last_rhalf); free(P->last_dpc); free(P->last_bt);
   free(P);
@@ -845,21 +1076,27 @@ static double diff_2(int n, const double *a, const double *b) {
 
 int orc_step(void *h) {
   orc_problem *P = (orc_problem *)h;
-  const int nc = P->nc;
+  const int nc = P->nc, L = P->nlev;
   const int rom = (P->d.method == ORC_ROM_SI_DSA);
+  const int mh = (P->d.precond == ORC_PC_MH);
+  const int64_t n = P->steps + 1;
   orc_step_rec rec;
   memset(&rec, 0, sizeof(rec));
   rec.e_ig = rec.e_pc = -1.0;
-  rec.phase = !P->flag_ig ? 1 : (!P->flag_pc ? 2 : 3);
+  /* phases 1 .. L+2: the ROMs are completed one after the other (Sec. 3.2,
+   * key feature 1); with one correction level these are phases 1-3 */
+  int flags0[ORC_MAX_LEVELS];
+  rec.phase = 1 + P->flag_ig;
+  for (int k = 0; k < L; ++k) {
+    flags0[k] = P->flag_pc[k];
+    rec.phase += P->flag_ig && flags0[k];
+  }
 
   double *rho0 = P->w1;     /* rho^{n,(0)} */
   double *rprev = P->w2;    /* rho^{n,(l-1)} */
   double *y = P->w3;        /* rho^{n,(l-1/2)} */
-  double *rhalf = P->w4;    /* rho^{n,(1/2)} kept for the ROM */
-  double *dpc = P->fcol;    /* scratch; copied out below */
-  double *dpc_keep = (double *)calloc(nc, sizeof(double));
   double *scratch = (double *)malloc(sizeof(double) * nc);
-  int used_pc = 0;
+  int applied[ORC_MAX_LEVELS] = {0};
 
   /* initial guess (Alg. 2: ROM-enhanced when Flag_IG, else rho^{n-1}) */
   if (rom && P->flag_ig && P->ig.lu_ok) {
@@ -872,6 +1109,7 @@ int orc_step(void *h) {
     memcpy(rho0, P->rho, sizeof(double) * nc);
   }
   memcpy(rprev, rho0, sizeof(double) * nc);
+  if (mh) P->mh.m = 0; /* the McClarren-Haut model lives within one step */
 
   /* Alg. 1 */
   int l, conv = 0;
@@ -879,7 +1117,10 @@ int orc_step(void *h) {
     for (int i = 0; i < nc; ++i) scratch[i] = P->ss[i] * rprev[i];
     apply_T(P, scratch, y);
     for (int i = 0; i < nc; ++i) y[i] += P->bt[i];
-    if (l == 1) memcpy(rhalf, y, sizeof(double) * nc);
+    if (l <= L + 1) { /* rho^{(l-1/2)} and rho^{(l-1)} for the correction ROMs */
+      memcpy(P->yl[l - 1], y, sizeof(double) * nc);
+      memcpy(P->rl[l - 1], rprev, sizeof(double) * nc);
+    }
     /* stop test; reading: relative to ||y||_inf (absolute when y = 0) */
     double dn = diff_inf(nc, y, rprev), yn = norm_inf(nc, y);
     rec.residual = yn > 0.0 ? dn / yn : dn;
@@ -888,20 +1129,40 @@ int orc_step(void *h) {
       break;
     }
     if (l == P->d.max_iter) break;
-    /* synthetic acceleration */
-    if (rom && l == 1 && P->flag_pc && P->pc.lu_ok) {
-      for (int i = 0; i < nc; ++i) P->w0[i] = y[i] - rho0[i];
-      rom_apply(&P->pc, P->w0, dpc);
-      memcpy(dpc_keep, dpc, sizeof(double) * nc);
-      used_pc = 1;
-      for (int i = 0; i < nc; ++i) rprev[i] = y[i] + dpc_keep[i];
+    /* McClarren-Haut pair of this iteration: (rho^{(l-1)} - rho^{(l-2)},
+     * y_l - y_{l-1}), the second the sweep image of the first */
+    if (mh && l >= 2) {
+      for (int i = 0; i < nc; ++i) {
+        P->w0[i] = rprev[i] - P->rprev2[i];
+        P->w5[i] = y[i] - P->yprev[i];
+      }
+      mh_push(&P->mh, P->w0, P->w5, P->w6);
+    }
+    if (mh) {
+      memcpy(P->yprev, y, sizeof(double) * nc);
+      memcpy(P->rprev2, rprev, sizeof(double) * nc);
+    }
+    /* synthetic acceleration: the ROM of iteration l (eq. dmd-sa for l = 1;
+     * a level l > 1 applies only after level l - 1 did in this step), else
+     * DSA (eq. rho_residual) or the McClarren-Haut correction */
+    const int lev = l - 1;
+    const int rom_here = rom && l <= L && flags0[lev] && (l == 1 || applied[lev - 1]);
+    if (rom_here && P->pc[lev].lu_ok) {
+      for (int i = 0; i < nc; ++i) P->w0[i] = y[i] - rprev[i];
+      rom_apply(&P->pc[lev], P->w0, P->dl[lev]);
+      applied[lev] = 1;
+      for (int i = 0; i < nc; ++i) rprev[i] = y[i] + P->dl[lev][i];
     } else {
-      if (rom && l == 1 && P->flag_pc) {
+      if (rom_here) {
         rec.fallback = 1;
         P->fallbacks++;
       }
       if (P->d.method == ORC_SI_PLAIN) {
         memcpy(rprev, y, sizeof(double) * nc);
+      } else if (mh) {
+        for (int i = 0; i < nc; ++i) P->w0[i] = y[i] - rprev[i];
+        mh_correct(&P->mh, P->w0, scratch);
+        for (int i = 0; i < nc; ++i) rprev[i] = y[i] + scratch[i];
       } else {
         for (int i = 0; i < nc; ++i) P->w0[i] = P->ss[i] * (y[i] - rprev[i]);
         dsa_solve(P, P->w0, scratch);
@@ -917,14 +1178,17 @@ int orc_step(void *h) {
    * iterate (Alg. 1 returns rho^{(l-1/2)}) */
   memcpy(P->rho, y, sizeof(double) * nc);
 
-  /* f^n and b~^n; keep b~^{n-1} for the IG snapshot pair */
+  /* f^n and b~^n; keep b~^{n-1} for the IG snapshot pair.  BDF2 switches to
+   * its own operator after the backward-Euler start */
   double *bt_prev = (double *)malloc(sizeof(double) * nc);
   memcpy(bt_prev, P->bt, sizeof(double) * nc);
-  final_sweep(P, P->rho);
-  compute_rhs(P, P->f, P->bt);
+  final_sweep(P, n, P->rho);
+  if (P->d.time_scheme == ORC_BDF2 && n == 1) set_alpha(P, 1.5);
+  compute_rhs(P, n + 1, P->bt);
 
-  /* ROM bookkeeping, Alg. 2 */
-  if (rom) {
+  /* ROM bookkeeping, Alg. 2.  Reading: under BDF2 the backward-Euler start
+   * step solves with another operator and is not a snapshot. */
+  if (rom && !(P->d.time_scheme == ORC_BDF2 && n == 1)) {
     double rn = sqrt(dot(nc, P->rho, P->rho));
     double scale = (P->d.abs_up_norm || rn == 0.0) ? 1.0 : 1.0 / rn;
     if (!P->flag_ig) {
@@ -934,48 +1198,63 @@ int orc_step(void *h) {
         P->ig_updates++;
         if (rom_tail_ratio(&P->ig) <= P->d.eps_ig || P->ig.rank >= P->d.r_max || dfc == 1) {
           P->flag_ig = 1;
-          P->n0 = (int)(P->steps + 1);
+          P->n0 = (int)n;
         }
       }
     } else {
-      int upd_ig = 0;
+      int lower_upd = 0;
       rec.e_ig = diff_2(nc, rho0, P->rho) * scale;
       if (rec.e_ig > P->d.eps_up) {
         orc_rom_add(&P->ig, P->rho, bt_prev, 1, P->d.eps_ig);
-        upd_ig = 1;
+        lower_upd = 1;
         rec.ig_update = 1;
         P->ig_updates++;
       }
-      /* correction snapshots: x = rho^n - rho^{(1/2)}, b = rho^{(1/2)} - rho^{(0)}
-       * (eq. correction_snapshot); none when the step converged at l = 1 */
-      if (l > 1) {
+      /* correction snapshots of iteration lev + 1: x = rho^n - rho^{(lev+1/2)},
+       * b = rho^{(lev+1/2)} - rho^{(lev)} (eq. correction_snapshot for lev = 0);
+       * none when the step converged at that iteration.  A level collects
+       * only once every level below it is complete. */
+      for (int lev = 0; lev < L; ++lev) {
+        if (lev > 0 && !flags0[lev - 1]) break;
+        if (l <= lev + 1) break;
         double *xs = P->w0, *bs = scratch;
         for (int i = 0; i < nc; ++i) {
-          xs[i] = P->rho[i] - rhalf[i];
-          bs[i] = rhalf[i] - rho0[i];
+          xs[i] = P->rho[i] - P->yl[lev][i];
+          bs[i] = P->yl[lev][i] - P->rl[lev][i];
         }
-        if (!P->flag_pc) {
-          int dfc = orc_rom_add(&P->pc, xs, bs, 0, P->d.eps_pc);
+        int upd = 0;
+        if (!flags0[lev]) {
+          int dfc = orc_rom_add(&P->pc[lev], xs, bs, 0, P->d.eps_pc);
           if (dfc >= 0) {
-            rec.pc_update = 1;
-            P->pc_updates++;
-            if (rom_tail_ratio(&P->pc) <= P->d.eps_pc || P->pc.rank >= P->d.r_max || dfc == 1) {
-              P->flag_pc = 1;
-              P->n1 = (int)(P->steps + 1) - P->n0;
+            upd = 1;
+            if (rom_tail_ratio(&P->pc[lev]) <= P->d.eps_pc || P->pc[lev].rank >= P->d.r_max || dfc == 1) {
+              P->flag_pc[lev] = 1;
+              int prior = P->n0;
+              for (int k = 0; k < lev; ++k) prior += P->nl[k];
+              P->nl[lev] = (int)n - prior;
             }
           }
         } else {
-          if (used_pc) rec.e_pc = diff_2(nc, dpc_keep, xs) * scale;
-          if (upd_ig || (used_pc && rec.e_pc > P->d.eps_up) || !used_pc) {
-            orc_rom_add(&P->pc, xs, bs, 1, P->d.eps_pc);
-            rec.pc_update = 1;
-            P->pc_updates++;
+          /* Alg. 2: update when a ROM below was updated or the indicator
+           * exceeds eps_UP.  Reading: a step that could not apply this
+           * level's correction (singular reduced system) also updates it. */
+          double e = -1.0;
+          if (applied[lev]) e = diff_2(nc, P->dl[lev], xs) * scale;
+          if (lev == 0) rec.e_pc = e;
+          if (lower_upd || !applied[lev] || e > P->d.eps_up) {
+            orc_rom_add(&P->pc[lev], xs, bs, 1, P->d.eps_pc);
+            upd = 1;
           }
+        }
+        if (upd) {
+          P->pc_updates[lev]++;
+          if (lev == 0) rec.pc_update = 1;
+          lower_upd = 1;
         }
       }
     }
     rec.rank_ig = P->ig.rank;
-    rec.rank_pc = P->pc.rank;
+    rec.rank_pc = P->pc[0].rank;
   }
 
   P->steps++;
@@ -992,12 +1271,14 @@ int orc_step(void *h) {
   }
   if (P->steps <= P->hist_cap) P->hist[P->steps - 1] = rec;
   memcpy(P->last_rho0, rho0, sizeof(double) * nc);
-  memcpy(P->last_rhalf, rhalf, sizeof(double) * nc);
-  memcpy(P->last_dpc, dpc_keep, sizeof(double) * nc);
+  memcpy(P->last_rhalf, P->yl[0], sizeof(double) * nc);
+  if (applied[0])
+    memcpy(P->last_dpc, P->dl[0], sizeof(double) * nc);
+  else
+    memset(P->last_dpc, 0, sizeof(double) * nc);
   memcpy(P->last_bt, bt_prev, sizeof(double) * nc);
-  P->last_used_pc = used_pc;
+  P->last_used_pc = applied[0];
   free(bt_prev);
-  free(dpc_keep);
   free(scratch);
   return conv ? ORC_OK : ORC_ENOCONV;
 }
@@ -1046,13 +1327,25 @@ void orc_get_counters(void *h, int64_t *out) {
   out[3] = P->nonconv;
   out[4] = P->fallbacks;
   out[5] = P->ig_updates;
-  out[6] = P->pc_updates;
+  out[6] = P->pc_updates[0];
   out[7] = P->n0;
-  out[8] = P->n1;
+  out[8] = P->nl[0];
   out[9] = P->flag_ig;
-  out[10] = P->flag_pc;
+  out[10] = P->flag_pc[0];
   out[11] = P->ig.rank;
-  out[12] = P->pc.rank;
+  out[12] = P->pc[0].rank;
+}
+/* per correction level k < L: flag, N_k (steps its construction took),
+ * rank, updates -- four values per level; returns L */
+int orc_get_levels(void *h, int64_t *out) {
+  orc_problem *P = (orc_problem *)h;
+  for (int k = 0; k < P->nlev; ++k) {
+    out[4 * k] = P->flag_pc[k];
+    out[4 * k + 1] = P->nl[k];
+    out[4 * k + 2] = P->pc[k].rank;
+    out[4 * k + 3] = P->pc_updates[k];
+  }
+  return P->nlev;
 }
 int orc_get_history(void *h, orc_step_rec *out, int64_t n) {
   orc_problem *P = (orc_problem *)h;
@@ -1068,7 +1361,7 @@ int orc_desc_size(void) { return (int)sizeof(orc_desc); }
 void orc_set_inflow(void *h, const double *g) {
   orc_problem *P = (orc_problem *)h;
   for (int k = 0; k < 4; ++k) P->d.inflow[k] = g[k];
-  compute_rhs(P, P->f, P->bt);
+  compute_rhs(P, P->steps + 1, P->bt);
 }
 /* out = T Sigma_s rho (zero inflow) */
 void orc_apply_TSs(void *h, const double *rho, double *out) {
@@ -1099,11 +1392,12 @@ int orc_get_step_vectors(void *h, double *rho0, double *rhalf, double *dpc, doub
   memcpy(bt_prev, P->last_bt, bytes);
   return P->last_used_pc;
 }
-/* the problem's ROM (which = 0: initial guess, 1: preconditioner): returns
+/* the problem's ROM (which = 0: initial guess, k >= 1: correction level k): returns
  * its rank; U, W get rank columns of nc values each, S rank values */
 int orc_get_rom(void *h, int which, double *U, double *S, double *W) {
   orc_problem *P = (orc_problem *)h;
-  const orc_rom *m = which ? &P->pc : &P->ig;
+  if (which < 0 || which > P->nlev) return 0;
+  const orc_rom *m = which ? &P->pc[which - 1] : &P->ig;
   if (U) memcpy(U, m->U, sizeof(double) * (size_t)m->rank * m->nc);
   if (W) memcpy(W, m->W, sizeof(double) * (size_t)m->rank * m->nc);
   if (S) memcpy(S, m->S, sizeof(double) * m->rank);

@@ -25,6 +25,8 @@ import numpy as np
 
 METHODS = ("si_dsa", "rom", "si")
 PRECISIONS = ("fp64", "mixed")
+PRECONDS = ("dsa", "mh")        # correction where DSA would be: DSA or McClarren-Haut
+TIME_SCHEMES = ("be", "bdf2")   # backward Euler or BDF2 (backward-Euler start)
 
 
 @dataclass
@@ -53,6 +55,10 @@ class ProblemSpec:
     eps_up: float = 1e-6
     r_max: int = 20
     abs_up_norm: bool = False
+    precond: str = "dsa"
+    time_scheme: str = "be"
+    pc_levels: int = 1  # sequential correction ROMs for iterations 1..pc_levels
+    mh_rank: int = 0  # McClarren-Haut pairs per model, 0 = r_max
     single_wg: bool = False  # 1D: one workgroup even when marched alone (device mode only)
     nsteps: int = 1
     name: str = ""
