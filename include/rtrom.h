@@ -60,6 +60,27 @@ typedef enum {
                       is accepted.  f, b~, rho and all ROM work stay FP64. */
 } rtrom_precision;
 
+/* Correction applied where Alg. 1 uses DSA. */
+typedef enum {
+  RTROM_PC_DSA = 0, /* diffusion synthetic acceleration (Sec. 2.3, eq. rho_residual) */
+  RTROM_PC_MH = 1   /* McClarren-Haut (Sec. 3.3): a DMD model of the sweep
+                       operator T Sigma_s built from the pairs of the current
+                       step's iterates, rho^{(l-1)} - rho^{(l-2)} and their
+                       images, gives d = Q (I - A~)^{-1} A~ Q^T (y - rho^{(l-1)})
+                       (eq. ideal_correct restricted to the pairs' span).  With
+                       RTROM_ROM_SI_DSA this is the hybrid of Sec. 4.5: the ROM
+                       initial guess and first correction, McClarren-Haut for
+                       the later iterations.  Slabs: at most 2048 cells. */
+} rtrom_precond;
+
+/* Time discretisation (Sec. 2.1). */
+typedef enum {
+  RTROM_BE = 0,  /* backward Euler (eq. time_discrete) */
+  RTROM_BDF2 = 1 /* BDF2, (3 f^n - 4 f^{n-1} + f^{n-2}) / (2 dt), started with
+                    one backward-Euler step (which is not a ROM snapshot: it
+                    solves with another operator).  Slabs: at most 2048 cells. */
+} rtrom_time_scheme;
+
 /* flags */
 #define RTROM_F_ABS_UP_NORM 0x1ull /* error indicators in the paper's absolute
                                       2-norm instead of relative to ||rho^n|| */
@@ -97,6 +118,17 @@ typedef struct {
   double eps_ig, eps_pc, eps_up; /* eq. ig_stop, eq. pc_stop, update threshold */
   int32_t r_max;      /* ROM rank cap, 1 .. 20 */
   uint64_t flags;     /* RTROM_F_* */
+  /* Fields added after the paper's default configuration; zero keeps it. */
+  int32_t precond;     /* rtrom_precond */
+  int32_t time_scheme; /* rtrom_time_scheme */
+  int32_t pc_levels;   /* correction ROMs for iterations 1..pc_levels, built
+                          one after the other (Sec. 3.2, key feature 1): the
+                          ROM of iteration l takes the pairs rho^n -
+                          rho^{(l-1/2)}, rho^{(l-1/2)} - rho^{(l-1)} once the
+                          ROMs below it are complete.  0 or 1: the paper's
+                          single level; at most 4 */
+  int32_t mh_rank;     /* McClarren-Haut pairs per model (a full model restarts
+                          from the newest pair), 0 = r_max; at most 20 */
 } rtrom_problem_desc;
 
 typedef struct {
@@ -191,6 +223,12 @@ rtrom_status rtrom_cl_quadrature(int32_t n_azim, int32_t n_polar, double *ox,
 /* Counters of the march so far (library bookkeeping; the counts are the
  * quantities Sec. 4 reports: SI sweeps per step, N0, N1, ranks). */
 rtrom_status rtrom_stats_get(const rtrom_problem *p, rtrom_stats *out);
+
+/* Correction ROMs of iterations 1..L (L = max(1, pc_levels); Sec. 3.2, key
+ * feature 1): for level l, out[4 (l-1) + 0..3] = complete (0/1), steps its
+ * construction took (N1 for l = 1), rank, snapshots added.  n: entries of
+ * out (at least 4 L); *levels receives L.  Errors: EINVAL. */
+rtrom_status rtrom_get_levels(const rtrom_problem *p, int64_t *out, int32_t n, int32_t *levels);
 
 /* Per-step records of the last min(n, steps) steps in order. *written gets the
  * number of records copied. */

@@ -234,6 +234,17 @@ static rtrom_status validate(const rtrom_problem_desc *d) {
   }
   for (int k = 0; k < 4; ++k)
     if (!std::isfinite(d->inflow[k])) return fail(RTROM_EINVAL, "inflow must be finite");
+  if (d->precond != RTROM_PC_DSA && d->precond != RTROM_PC_MH) return fail(RTROM_EINVAL, "unknown precond");
+  if (d->time_scheme != RTROM_BE && d->time_scheme != RTROM_BDF2) return fail(RTROM_EINVAL, "unknown time_scheme");
+  if (d->pc_levels < 0 || d->pc_levels > 4) return fail(RTROM_EINVAL, "pc_levels must be in 0..4");
+  if (d->mh_rank < 0 || d->mh_rank > RT_RMAX) return fail(RTROM_EINVAL, "mh_rank must be in 0..20");
+  const bool variant = d->precond == RTROM_PC_MH || d->time_scheme == RTROM_BDF2;
+  if (variant && d->dim == 1 && d->nx > RT_WAVE_MAX_CELLS)
+    return fail(RTROM_EINVAL, "McClarren-Haut and BDF2 run on slabs of at most 2048 cells");
+  if (variant && d->dim == 2)
+    return fail(RTROM_EINVAL, "McClarren-Haut and BDF2 run on slabs only");
+  if (d->pc_levels > 1 && !(d->dim == 1 && d->nx <= RT_WAVE_MAX_CELLS))
+    return fail(RTROM_EINVAL, "correction ROMs beyond the first iteration run on slabs of at most 2048 cells");
   return RTROM_OK;
 }
 
@@ -303,6 +314,8 @@ static void slab_groups(const rtrom_problem_desc *d, int nv, int *ng, int *pg) {
   *ng = 0;
   *pg = npair;
   if (d->dim != 1 || (d->flags & RTROM_F_SINGLE_WG) || npair < 2) return;
+  // the variants run in the one-workgroup kernels
+  if (d->precond == RTROM_PC_MH || d->time_scheme == RTROM_BDF2 || d->pc_levels > 1) return;
   const int g = std::min(16, npair);
   *pg = (npair + g - 1) / g;
   *ng = (npair + *pg - 1) / *pg;
@@ -312,6 +325,8 @@ static void slab_groups(const rtrom_problem_desc *d, int nv, int *ng, int *pg) {
 // 256-cell blocks, the cooperative 1D passes blocks of 64 cells per wave pair
 // (at least 64 cells).
 static size_t part_rows(int dim, size_t nc) { return dim == 1 ? (nc + 63) / 64 : (nc + 255) / 256; }
+
+static int mh_cap_of(const rtrom_problem_desc *d) { return d->mh_rank > 0 ? d->mh_rank : d->r_max; }
 
 static size_t slab_bytes(const rtrom_problem_desc *d, int nv) {
   const size_t nc = (size_t)d->nx * d->ny;
@@ -323,6 +338,14 @@ static size_t slab_bytes(const rtrom_problem_desc *d, int nv) {
   if (d->dim == 1) {  // 2D keeps its folded f in the plane buffers
     L.take((size_t)nv * nc * 8);
     L.take((size_t)(nv / 2) * nc * 8);
+    if (d->time_scheme == RTROM_BDF2) {  // f^{n-1}, sigma_t + 3/(2 dt), three DSA factor arrays
+      L.take((size_t)nv * nc * 8);
+      for (int k = 0; k < 4; ++k) L.take(nc * 8);
+    }
+    if (d->precond == RTROM_PC_MH) {  // Q, Z
+      L.take((size_t)mh_cap_of(d) * ld * 8);
+      L.take((size_t)mh_cap_of(d) * ld * 8);
+    }
     int ng, pg;
     slab_groups(d, nv, &ng, &pg);
     if (ng > 1) {
@@ -334,7 +357,8 @@ static size_t slab_bytes(const rtrom_problem_desc *d, int nv) {
       L.take(8 * 8);
     }
   }
-  for (int r = 0; r < 2; ++r) {
+  const int nrom = 1 + std::max(1, (int)d->pc_levels);
+  for (int r = 0; r < nrom; ++r) {
     L.take((RT_RMAX + 1) * ld * 8);
     L.take((RT_RMAX + 1) * ld * 8);
     L.take((RT_RMAX + 1) * 8);
@@ -344,6 +368,10 @@ static size_t slab_bytes(const rtrom_problem_desc *d, int nv) {
     L.take(sizeof(RomPend));
     L.take(sizeof(RomWork));
     L.take(3 * part_rows(d->dim, nc) * RT_NPART * 8);
+  }
+  for (int k = 0; k + 2 < nrom; ++k) {  // y_l, rho^{(l-1)}, the correction, three work rows
+    for (int q = 0; q < 3; ++q) L.take(nc * 8);
+    L.take(3 * nc * 8);
   }
   L.take(sizeof(RtState));
   L.take(sizeof(Inst));
@@ -356,7 +384,7 @@ static size_t slab_bytes(const rtrom_problem_desc *d, int nv) {
 // and the same problem marched alone start from bitwise the same b~.
 static hipError_t slab_rhs(rtrom_problem *p) {
   const Inst &I = p->hinst;
-  if (p->nc <= RT_WAVE_MAX_CELLS) return rt_launch_slab_fpass_wave(p->dinst, 1, 1, p->stream);
+  if (p->nc <= RT_WAVE_MAX_CELLS) return rt_launch_slab_fpass_wave(p->dinst, 1, 1, I.bdf2 ? 2 : 1, p->stream);
   int cmax;
   const int nt = slab_launch_threads(&I.nthr, &p->nc, 1, &cmax);
   return rt_launch_slab_rhs(p->dinst, 1, nt, cmax, I.npair, p->nc, p->stream);
@@ -481,6 +509,21 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   double *qbuf = D((size_t)nv * 8 * 6);
   I.f = d->dim == 1 ? D((size_t)nv * nc * 8) : nullptr;
   I.fpart = d->dim == 1 ? D((size_t)(nv / 2) * nc * 8) : nullptr;
+  double *ctb = nullptr;
+  if (d->dim == 1 && d->time_scheme == RTROM_BDF2) {
+    I.fb[0] = I.f;
+    I.fb[1] = D((size_t)nv * nc * 8);
+    ctb = D(nc * 8);
+    I.ct_b = ctb;
+    I.dsa_fe_b = D(nc * 8);
+    I.dsa_bg_b = D(nc * 8);
+    I.dsa_invd_b = D(nc * 8);
+  }
+  if (d->dim == 1 && d->precond == RTROM_PC_MH) {
+    I.mh_cap = mh_cap_of(d);
+    I.mhQ = D((size_t)I.mh_cap * ld * 8);
+    I.mhZ = D((size_t)I.mh_cap * ld * 8);
+  }
   slab_groups(d, nv, &I.ng, &I.pg);
   if (I.ng > 1) {
     I.sip = D(2 * (size_t)I.ng * nc * 8);
@@ -490,9 +533,11 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
     I.apx = D(2 * (size_t)I.ng * RT_RMAX * 8);
     I.bar = (unsigned long long *)D(8 * 8);
   }
-  RomDev *roms[2] = {&I.ig, &I.pc};
-  RomWork rom_work_init[2];
-  for (int r = 0; r < 2; ++r) {
+  const int nrom = 1 + std::max(1, (int)d->pc_levels);
+  RomDev *roms[2 + RT_XLEV] = {&I.ig, &I.pc, &I.pl[0], &I.pl[1], &I.pl[2]};
+  static_assert(RT_XLEV == 3, "one RomDev pointer per level");
+  RomWork rom_work_init[2 + RT_XLEV];
+  for (int r = 0; r < nrom; ++r) {
     roms[r]->U = D((RT_RMAX + 1) * ld * 8);
     roms[r]->W = D((RT_RMAX + 1) * ld * 8);
     roms[r]->S = D((RT_RMAX + 1) * 8);
@@ -512,6 +557,13 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
       rom_work_init[r] = wk;
     }
   }
+  for (int k = 0; k + 2 < nrom; ++k) {
+    I.ylev[k] = D(nc * 8);
+    I.rlev[k] = D(nc * 8);
+    I.dlev[k] = D(nc * 8);
+    I.wlev[k] = D(3 * (size_t)nc * 8);
+  }
+  I.nlev = nrom - 1;
   I.st = (RtState *)D(sizeof(RtState));
   p->dinst = (Inst *)D(sizeof(Inst));
 
@@ -548,6 +600,9 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   I.eps_ig = d->eps_ig;
   I.eps_pc = d->eps_pc;
   I.eps_up = d->eps_up;
+  I.precond = d->precond;
+  I.bdf2 = d->time_scheme == RTROM_BDF2;
+  I.adt_b = 1.5 / d->dt;
   for (int k = 0; k < 4; ++k) I.g[k] = d->inflow[k];
   I.ss = ss;
   I.sa = sa;
@@ -574,6 +629,12 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   };
   bool ok = H2D(ss, d->sigma_s, nc * 8) && H2D(sa, d->sigma_a, nc * 8) && H2D(G, d->source, nc * 8) &&
             H2D(ct, h_ct.data(), nc * 8) && H2D(qbuf, h_q.data(), h_q.size() * 8);
+  std::vector<double> h_ctb;
+  if (ctb) {  // the BDF2 operator: sigma_t + 3 / (2 dt)
+    h_ctb.resize(nc);
+    for (int i = 0; i < nc; ++i) h_ctb[i] = d->sigma_s[i] + d->sigma_a[i] + 1.5 / d->dt;
+    ok = ok && H2D(ctb, h_ctb.data(), nc * 8);
+  }
   std::vector<double> rho0(nc, 0.0);
   if (d->f0)
     for (int i = 0; i < nc; ++i) rho0[i] = d->f0[i];
@@ -584,7 +645,7 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   RtState st0;
   memset(&st0, 0, sizeof(st0));
   ok = ok && H2D(I.st, &st0, sizeof(st0));
-  ok = ok && H2D(I.ig.work, &rom_work_init[0], sizeof(RomWork)) && H2D(I.pc.work, &rom_work_init[1], sizeof(RomWork));
+  for (int r = 0; r < nrom && ok; ++r) ok = H2D(roms[r]->work, &rom_work_init[r], sizeof(RomWork));
   if (!ok) return bail(RTROM_EDEVICE, "upload failed");
   if (ensure_hist(p, 1024, p->stream) != RTROM_OK) {
     std::string m = g_err;
@@ -592,7 +653,9 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   }
   if (d->dim == 1) {
     if (upload_inst(p) != RTROM_OK) return bail(RTROM_EDEVICE, "upload descriptor failed");
-    if (rt_launch_slab_setup(p->dinst, 1, nc, p->stream) != hipSuccess) return bail(RTROM_EDEVICE, "setup launch failed");
+    if (rt_launch_slab_setup(p->dinst, 1, nc, 0, p->stream) != hipSuccess) return bail(RTROM_EDEVICE, "setup launch failed");
+    if (I.bdf2 && rt_launch_slab_setup(p->dinst, 1, nc, 1, p->stream) != hipSuccess)
+      return bail(RTROM_EDEVICE, "setup launch failed");
     if (slab_rhs(p) != hipSuccess) return bail(RTROM_EDEVICE, "initial RHS launch failed");
   } else {
     if (upload_inst(p) != RTROM_OK) return bail(RTROM_EDEVICE, "upload descriptor failed");
@@ -736,24 +799,28 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
     while (nA < n && ncs[nA] > RT_WAVE_MAX_CELLS) ++nA;
     struct Group {
       int off, cnt, nt, cmax, nc_max, npair_max, pairs_total, wave;
+      int si_kinds, fp_kinds;  // wave kernels: bit 0 default instances, bit 1 variants (MH; BDF2)
     };
     std::vector<Group> groups;
     for (int g = 0; g < 2; ++g) {
-      Group G{g ? nA : 0, g ? n - nA : nA, 0, 0, 0, 1, 0, g};
+      Group G{g ? nA : 0, g ? n - nA : nA, 0, 0, 0, 1, 0, g, 0, 0};
       if (G.cnt == 0) continue;
       G.nt = slab_launch_threads(nthr.data() + G.off, ncs.data() + G.off, G.cnt, &G.cmax);
       for (int i = G.off; i < G.off + G.cnt; ++i) {
         G.nc_max = std::max(G.nc_max, ncs[i]);
         G.npair_max = std::max(G.npair_max, ps[i]->hinst.npair);
         G.pairs_total += ps[i]->hinst.npair;
+        G.si_kinds |= ps[i]->hinst.precond == RT_PC_MH ? 2 : 1;
+        G.fp_kinds |= ps[i]->hinst.bdf2 ? 2 : 1;
       }
       groups.push_back(G);
     }
     const int nt = groups[0].nt, cmax = groups[0].cmax;  // a problem marched alone: one group
-    int any_rom = 0, any_fused = 0, nc_grid = 0;
+    int any_rom = 0, any_fused = 0, nc_grid = 0, nrom = 2;
     for (int i = 0; i < n; ++i) {
       const int rom_i = ps[i]->d.method == RTROM_ROM_SI_DSA;
       any_rom |= rom_i;
+      if (rom_i) nrom = std::max(nrom, 1 + ps[i]->hinst.nlev);
       if (rom_i && ps[i]->hinst.post_fused) any_fused = 1;
       if (rom_i && !ps[i]->hinst.post_fused) nc_grid = std::max(nc_grid, ncs[i]);
     }
@@ -782,7 +849,7 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
     auto enqueue_step = [&]() -> rtrom_status {
       rt_prof_begin(RT_K_SLAB_SI, s);
       for (const Group &G : groups) {
-        if (G.wave) RT_HIP(rt_launch_slab_si_wave(dinsts + G.off, G.cnt, s), "SI launch");
+        if (G.wave) RT_HIP(rt_launch_slab_si_wave(dinsts + G.off, G.cnt, G.si_kinds, s), "SI launch");
         else RT_HIP(rt_launch_slab_si(dinsts + G.off, G.cnt, G.nt, G.cmax, s), "SI launch");
       }
       rt_prof_end(RT_K_SLAB_SI, s);
@@ -792,7 +859,7 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
       }
       if (any_rom) {
         rt_prof_begin(RT_K_POST, s2);
-        RT_HIP(rt_launch_rom_slab(dinsts, n, any_fused, nc_grid, s2), "ROM launch");
+        RT_HIP(rt_launch_rom_slab(dinsts, n, any_fused, nc_grid, nrom, s2), "ROM launch");
         rt_prof_end(RT_K_POST, s2);
         if (nc_grid > 0) {  // instances without a fused post
           rt_prof_begin(RT_K_ROM_UPDATE, s2);
@@ -802,7 +869,7 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
       }
       rt_prof_begin(RT_K_SLAB_FPASS, s);
       for (const Group &G : groups) {
-        if (G.wave) RT_HIP(rt_launch_slab_fpass_wave(dinsts + G.off, G.cnt, 0, s), "f-pass launch");
+        if (G.wave) RT_HIP(rt_launch_slab_fpass_wave(dinsts + G.off, G.cnt, 0, G.fp_kinds, s), "f-pass launch");
         else
           RT_HIP(rt_launch_slab_fpass(dinsts + G.off, G.cnt, G.nt, G.cmax, G.npair_max, G.nc_max, G.pairs_total, s),
                  "f-pass launch");
@@ -995,7 +1062,8 @@ extern "C" rtrom_status rtrom_get_angular_flux(const rtrom_problem *p, double *f
   if (!p || !f) return fail(RTROM_EINVAL, "null argument");
   if (n < (int64_t)p->nc * p->nv) return fail(RTROM_EINVAL, "output buffer too small");
   if (p->d.dim == 2) return (rtrom_status)rt_plane_unfold(p, f);
-  return d2h(p, f, p->hinst.f, (size_t)p->nc * p->nv * 8);
+  const double *src = p->hinst.bdf2 ? p->hinst.fb[p->steps & 1] : p->hinst.f;  // BDF2: f^n in fb[n & 1]
+  return d2h(p, f, src, (size_t)p->nc * p->nv * 8);
 }
 
 extern "C" rtrom_status rtrom_get_quadrature(const rtrom_problem *p, double *ox, double *oy, double *oz,
@@ -1020,6 +1088,7 @@ extern "C" rtrom_status rtrom_stats_get(const rtrom_problem *p, rtrom_stats *out
   out->sweeps_total = st.sweeps_total;
   out->si_iters_last = st.iters;
   out->phase = !st.flag_ig ? 1 : (!st.flag_pc ? 2 : 3);
+  for (int k = 0; k + 2 <= p->hinst.nlev; ++k) out->phase += (out->phase == k + 3 && st.flag_pl[k]) ? 1 : 0;
   out->n0 = st.n0;
   out->n1 = st.n1;
   out->rank_ig = st.rank_ig;
@@ -1032,6 +1101,31 @@ extern "C" rtrom_status rtrom_stats_get(const rtrom_problem *p, rtrom_stats *out
   out->last_residual = st.residual;
   out->t_total_s = p->t_total;
   out->dsa_iters = p->d.dim == 2 ? rt_plane_dsa_iters(p) : 0;
+  return RTROM_OK;
+}
+
+extern "C" rtrom_status rtrom_get_levels(const rtrom_problem *p, int64_t *out, int32_t n, int32_t *levels) {
+  if (!p || !out || !levels) return fail(RTROM_EINVAL, "null argument");
+  const int L = std::max(1, p->hinst.nlev);
+  if (n < 4 * L) return fail(RTROM_EINVAL, "output buffer too small");
+  RtState st;
+  rtrom_status e = read_state(p, &st);
+  if (e != RTROM_OK) return e;
+  for (int l = 1; l <= L; ++l) {
+    int64_t *o = out + 4 * (l - 1);
+    if (l == 1) {
+      o[0] = st.flag_pc;
+      o[1] = st.n1;
+      o[2] = st.rank_pc;
+      o[3] = st.pc_updates;
+    } else {
+      o[0] = st.flag_pl[l - 2];
+      o[1] = st.n_pl[l - 2];
+      o[2] = st.rank_pl[l - 2];
+      o[3] = st.upd_pl[l - 2];
+    }
+  }
+  *levels = L;
   return RTROM_OK;
 }
 

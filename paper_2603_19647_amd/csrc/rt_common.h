@@ -7,6 +7,8 @@
 #define RT_RMAX 20     // largest ROM rank the kernels hold
 #define RT_KC 22       // padded column count of the incremental-SVD core (RMAX+1, even)
 #define RT_MAXWAVES 16 // 1024-thread workgroups at most
+#define RT_MAXLEV 4    // correction ROMs of iterations 1..RT_MAXLEV (Sec. 3.2, key feature 1)
+#define RT_XLEV (RT_MAXLEV - 1)  // the levels beyond the first
 
 // A basis rotation decided by the workgroup part of an incremental-SVD update
 // and applied to every cell by the grid-wide k_rom_update kernel:
@@ -73,6 +75,12 @@ struct RtState {
   int iters, conv, used_pc, ig_fb, pc_fb, phase, cur;  // cur: b~ buffer of the step
   int fault;  // a cooperative grid barrier gave up waiting (sticky)
   double residual;
+  // correction ROMs of iterations 2..RT_MAXLEV (index l - 2): flag, rank,
+  // LU status, steps their construction took, updates; the levels the SI
+  // kernel applied in the step in flight (bit l - 1)
+  int flag_pl[RT_XLEV], rank_pl[RT_XLEV], lu_ok_pl[RT_XLEV], n_pl[RT_XLEV];
+  long long upd_pl[RT_XLEV];
+  int used_mask, pad_l;
 };
 
 struct RtStepRec {
@@ -126,9 +134,27 @@ struct Inst {
   RomDev ig, pc;
   RtState *st;
   RtStepRec *hist;
+  // variants of the configuration (slabs up to RT_WAVE_MAX_CELLS cells)
+  int precond;   // RT_PC_DSA, or RT_PC_MH: McClarren-Haut where DSA would be
+  int bdf2;      // BDF2 time stepping after one backward-Euler step
+  int mh_cap;    // McClarren-Haut pairs per model
+  int pad_v;
+  double adt_b;  // 3 / (2 dt): time weight of the BDF2 operator
+  const double *ct_b;                             // sigma_t + 3 / (2 dt)
+  const double *dsa_fe_b, *dsa_bg_b, *dsa_invd_b;  // DSA factors of the BDF2 operator
+  double *fb[2];      // BDF2: f^n sits in fb[n & 1], f^{n-1} in the other
+  double *mhQ, *mhZ;  // [mh_cap][ld]: orthonormal pair inputs, scaled images
+  // correction ROMs of iterations 2..nlev (slabs up to RT_WAVE_MAX_CELLS
+  // cells): level l's ROM, y_l = rho^{(l-1/2)}, rho^{(l-1)} and the applied
+  // correction (index l - 2, [nc] each), and the rows its update works in
+  // (x, b, projection residual: [3][nc])
+  int nlev, pad_lv;
+  RomDev pl[RT_XLEV];
+  double *ylev[RT_XLEV], *rlev[RT_XLEV], *dlev[RT_XLEV], *wlev[RT_XLEV];
 };
 
 enum { RT_SI_DSA = 0, RT_ROM = 1, RT_SI_PLAIN = 2 };
+enum { RT_PC_DSA = 0, RT_PC_MH = 1 };
 enum { RT_FP64 = 0, RT_MIXED = 1 };
 
 // ---------------------------------------------------------------------------

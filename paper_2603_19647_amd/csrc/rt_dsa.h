@@ -6,16 +6,20 @@
 
 // DSA correction (eq. rho_residual): solve C d = rhs with the precomputed
 // Thomas factors written as two affine recurrences, z_i = fe_i z_{i-1} + rhs_i
-// forward and d_i = bg_i d_{i+1} + invd_i z_i backward.
+// forward and d_i = bg_i d_{i+1} + invd_i z_i backward.  alt: the factors of
+// the BDF2 operator.
 template <int CMAX>
 __device__ __forceinline__ void dsa_solve_slab(const Inst &I, int c0, int n, const double (&rhs)[CMAX],
-                                               double (&d)[CMAX], double *slots, int &parity) {
+                                               double (&d)[CMAX], double *slots, int &parity, bool alt = false) {
+  const double *__restrict__ dfe = alt ? I.dsa_fe_b : I.dsa_fe;
+  const double *__restrict__ dbg = alt ? I.dsa_bg_b : I.dsa_bg;
+  const double *__restrict__ dinvd = alt ? I.dsa_invd_b : I.dsa_invd;
   double fe[CMAX], z[CMAX];
   double A = 1.0, B = 0.0;
 #pragma unroll
   for (int t = 0; t < CMAX; ++t) {
     if (t < n) {
-      fe[t] = ldg(&I.dsa_fe[c0 + t]);
+      fe[t] = ldg(&dfe[c0 + t]);
       B = rt_fma(fe[t], B, rhs[t]);
       A *= fe[t];
     }
@@ -37,8 +41,8 @@ __device__ __forceinline__ void dsa_solve_slab(const Inst &I, int c0, int n, con
 #pragma unroll
   for (int t = CMAX - 1; t >= 0; --t) {
     if (t < n) {
-      bg[t] = ldg(&I.dsa_bg[c0 + t]);
-      z[t] *= ldg(&I.dsa_invd[c0 + t]);
+      bg[t] = ldg(&dbg[c0 + t]);
+      z[t] *= ldg(&dinvd[c0 + t]);
       B = rt_fma(bg[t], B, z[t]);
       A *= bg[t];
     }

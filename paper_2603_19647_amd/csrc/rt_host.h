@@ -40,13 +40,18 @@ extern "C" hipError_t rt_launch_slab_si(const Inst *dinsts, int ninst, int nthre
 extern "C" hipError_t rt_launch_slab_fpass(const Inst *dinsts, int ninst, int nthreads, int cmax, int npair_max,
                                            int nc_max, int pairs_total, hipStream_t stream);
 extern "C" hipError_t rt_launch_rom(const Inst *dinsts, int ninst, int nc_max, int any_rom, hipStream_t s);
-extern "C" hipError_t rt_launch_rom_slab(const Inst *dinsts, int ninst, int any_fused, int nc_grid, hipStream_t s);
+// nrom: 1 + the largest number of correction levels in the launch
+extern "C" hipError_t rt_launch_rom_slab(const Inst *dinsts, int ninst, int any_fused, int nc_grid, int nrom,
+                                         hipStream_t s);
 extern "C" hipError_t rt_launch_rom_update(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream);
 extern "C" hipError_t rt_launch_slab_rhs(const Inst *dinsts, int ninst, int nthreads, int cmax, int npair_max,
                                          int nc_max, hipStream_t stream);
-extern "C" hipError_t rt_launch_slab_si_wave(const Inst *dinsts, int ninst, hipStream_t stream);
-extern "C" hipError_t rt_launch_slab_fpass_wave(const Inst *dinsts, int ninst, int rhs_only, hipStream_t stream);
-extern "C" hipError_t rt_launch_slab_setup(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream);
+// kinds: bit 0 -- the launch holds instances of the default configuration,
+// bit 1 -- instances of the variant (SI: McClarren-Haut; f-pass: BDF2)
+extern "C" hipError_t rt_launch_slab_si_wave(const Inst *dinsts, int ninst, int kinds, hipStream_t stream);
+extern "C" hipError_t rt_launch_slab_fpass_wave(const Inst *dinsts, int ninst, int rhs_only, int kinds,
+                                                hipStream_t stream);
+extern "C" hipError_t rt_launch_slab_setup(const Inst *dinsts, int ninst, int nc_max, int alt, hipStream_t stream);
 extern "C" hipError_t rt_launch_gather_states(const Inst *dinsts, int ninst, RtState *out, hipStream_t stream);
 
 // 2D

@@ -100,6 +100,18 @@ __device__ __forceinline__ void wg_sum_fast(const double (&v)[NV], double *red, 
   __syncthreads();
 }
 
+// ROM z of an instance: 0 the initial guess, 1 the correction of iteration
+// 1, l the correction of iteration l
+__device__ __forceinline__ const RomDev &rom_of(const Inst &I, int z) {
+  return z == 0 ? I.ig : (z == 1 ? I.pc : I.pl[z - 2]);
+}
+__device__ __forceinline__ int *rom_rank_of(RtState *st, int z) {
+  return z == 0 ? &st->rank_ig : (z == 1 ? &st->rank_pc : &st->rank_pl[z - 2]);
+}
+__device__ __forceinline__ int *rom_luok_of(RtState *st, int z) {
+  return z == 0 ? &st->lu_ok_ig : (z == 1 ? &st->lu_ok_pc : &st->lu_ok_pl[z - 2]);
+}
+
 // ---------------------------------------------------------------------------
 // LU with partial pivoting of the n x n matrix in A (stride RT_KC, LDS), by
 // wave 0.  Lane i keeps row i in registers for the whole factorisation; rows
@@ -950,8 +962,7 @@ __device__ inline void rom_rotate_own_lu(const Inst &I, const RomDev &R, const R
   __syncthreads();
   if (threadIdx.x == 0 && n_lu > 0) {
     const int luok = !sm.ibuf[0];
-    if (z == 0) I.st->lu_ok_ig = luok;
-    else I.st->lu_ok_pc = luok;
+    *rom_luok_of(I.st, z) = luok;
   }
 }
 
@@ -982,10 +993,11 @@ __device__ __forceinline__ void rom_norm_parts(const Inst &I, int c0, int stride
 struct RomPlan {
   int ig_on, ig_trunc, pc_on, pc_trunc;
   double e_ig, e_pc;
+  int lv_on[RT_XLEV], lv_trunc[RT_XLEV];  // correction ROMs of iterations 2..nlev
 };
 __device__ __forceinline__ RomPlan rom_plan(const Inst &I, int flag_ig, int flag_pc, int used_pc, int iters,
                                             const double *vec) {
-  RomPlan P{0, 0, 0, 0, -1.0, -1.0};
+  RomPlan P{0, 0, 0, 0, -1.0, -1.0, {0}, {0}};
   const double rn = flag_ig ? sqrt(vec[0]) : 0.0;
   const double scale = (I.abs_up || rn == 0.0) ? 1.0 : 1.0 / rn;
   if (!flag_ig) {
@@ -1005,6 +1017,38 @@ __device__ __forceinline__ RomPlan rom_plan(const Inst &I, int flag_ig, int flag
   return P;
 }
 
+// The correction ROMs of iterations l = 2..nlev, after rom_plan decided the
+// initial guess and iteration 1: level l takes the pair of its iteration
+// (rho^n - rho^{(l-1/2)}, rho^{(l-1/2)} - rho^{(l-1)}) only once every level
+// below it was complete when the step started and the step needed more than
+// l iterations; while under construction every such pair is added
+// untruncated, afterwards (truncated) when a ROM below it was updated in
+// this step, when it could not apply its correction, or when its indicator
+// ||dlev - (rho^n - rho^{(l-1/2)})|| / ||rho^n|| exceeds eps_UP.  vec[3 + l - 2]
+// holds that indicator's square; used_mask bit l - 1 says level l applied.
+__device__ __forceinline__ void rom_plan_levels(const Inst &I, const RtState *st, int flag_pc, int used_mask,
+                                                int iters, const double *vec, RomPlan &P) {
+  if (P.e_ig < 0.0) return;  // the initial-guess ROM is still being built
+  const double rn = sqrt(vec[0]);
+  const double scale = (I.abs_up || rn == 0.0) ? 1.0 : 1.0 / rn;
+  int lower = P.ig_on || P.pc_on;
+  int below_done = flag_pc;
+  for (int l = 2; l <= I.nlev; ++l) {
+    const int k = l - 2;
+    if (!below_done || iters <= l) break;
+    const int done = st->flag_pl[k];
+    if (!done) {
+      P.lv_on[k] = 1;
+    } else {
+      const int used = (used_mask >> (l - 1)) & 1;
+      const double e = used ? sqrt(vec[3 + k]) * scale : -1.0;
+      P.lv_on[k] = P.lv_trunc[k] = lower || !used || e > I.eps_up;
+    }
+    lower |= P.lv_on[k];
+    below_done = done;
+  }
+}
+
 // What the end-of-step bookkeeping needs about the step just solved and the
 // state's counters as they were when it started.  The slab SI kernel fills it
 // from registers (no reloads of what it just wrote); step_in() reads it back
@@ -1014,11 +1058,13 @@ struct StepIn {
   int flag_ig, flag_pc, rank_ig, rank_pc, nonconv, fallbacks;
   double residual;
   long long steps, si_total, sweeps_total;
+  int used_mask = 0;  // correction ROMs applied (bit l - 1: level l), levels >= 2
+  int lv_fb = 0;      // levels >= 2 that were due but could not apply (singular)
 };
 __device__ inline StepIn step_in(const RtState *st) {
   return {st->iters,   st->conv,    st->used_pc, st->ig_fb,   st->pc_fb,    st->phase,    st->cur,
           st->flag_ig, st->flag_pc, st->rank_ig, st->rank_pc, st->nonconv, st->fallbacks, st->residual,
-          st->steps,   st->si_total, st->sweeps_total};
+          st->steps,   st->si_total, st->sweeps_total, 0, 0};
 }
 
 // ---------------------------------------------------------------------------
@@ -1033,7 +1079,11 @@ __device__ inline void rom_decide(const Inst &I, const double *vec, int nb, cons
   const long long step_no = S.steps + 1;
   double e_ig = -1.0, e_pc = -1.0;
   if (I.method == RT_ROM) {
-    const RomPlan P = rom_plan(I, S.flag_ig, S.flag_pc, S.used_pc, iters, vec);
+    // the backward-Euler start of a BDF2 march solves with another operator
+    // and is not a snapshot
+    const bool start = I.bdf2 && S.steps == 0;
+    RomPlan P = start ? RomPlan{0, 0, 0, 0, -1.0, -1.0, {0}, {0}} : rom_plan(I, S.flag_ig, S.flag_pc, S.used_pc, iters, vec);
+    if (!start && I.nlev > 1) rom_plan_levels(I, st, S.flag_pc, S.used_mask, iters, vec, P);
     e_ig = P.e_ig;
     e_pc = P.e_pc;
     if (threadIdx.x == 0) {
@@ -1064,10 +1114,23 @@ __device__ inline void rom_decide(const Inst &I, const double *vec, int nb, cons
       wp.p = I.work + I.nc;
       I.ig.pend->pending = 0;
       I.pc.pend->pending = 0;
+      for (int k = 0; k + 2 <= I.nlev; ++k) {
+        RomWork &wl = *I.pl[k].work;
+        wl.active = P.lv_on[k];
+        wl.truncate = P.lv_trunc[k];
+        wl.r = st->rank_pl[k];
+        wl.nblk = nb;
+        wl.step_no = step_no;
+        wl.eps = I.eps_pc;
+        wl.x = I.wlev[k];
+        wl.b = I.wlev[k] + I.nc;
+        wl.p = I.wlev[k] + 2 * (size_t)I.nc;
+        I.pl[k].pend->pending = 0;
+      }
     }
   }
   if (threadIdx.x == 0) {
-    const int fb = S.ig_fb + S.pc_fb;
+    const int fb = S.ig_fb + S.pc_fb + S.lv_fb;
     if (I.hist && step_no <= I.hist_cap) {
       RtStepRec &rec = I.hist[step_no - 1];
       rec.iters = iters;
@@ -1097,7 +1160,6 @@ __device__ inline double rom_tail_ratio(const RomDev &R, int rank) {
   return tot > 0.0 ? ldg(&R.S[rank - 1]) / tot : 0.0;
 }
 
-__device__ __forceinline__ const RomDev &rom_of(const Inst &I, int z) { return z ? I.pc : I.ig; }
 
 // ---------------------------------------------------------------------------
 // Projection passes (classical Gram-Schmidt applied twice).  Block b of nb
@@ -1118,10 +1180,10 @@ __device__ __forceinline__ void rom_pass1(const Inst &I, const RomDev &R, const 
 #pragma unroll 2
   for (int c = b * NT + threadIdx.x; c < I.nc; c += nb * NT) {
     double xv, bv;
-    if (z == 1) {  // x = rho^n - rho^(1/2), b = rho^(1/2) - rho^(0)
-      const double rh = ldg(&I.rhalf[c]);
+    if (z >= 1) {  // x = rho^n - rho^(l-1/2), b = rho^(l-1/2) - rho^(l-1) (l = z)
+      const double rh = z == 1 ? ldg(&I.rhalf[c]) : ldg(&I.ylev[z - 2][c]);
       xv = ldg(&I.rho[c]) - rh;
-      bv = rh - ldg(&I.rho0[c]);
+      bv = rh - (z == 1 ? ldg(&I.rho0[c]) : ldg(&I.rlev[z - 2][c]));
       // the PC ROM's x, b live in the work arrays (COH: read later by
       // workgroups on other XCDs)
       part_store<COH>(const_cast<double *>(W.x) + c, xv);
@@ -1192,8 +1254,8 @@ __device__ __forceinline__ void rom_pass2(const Inst &I, const RomDev &R, const 
 template <bool COH, bool DEFER_LU = false>
 __device__ __forceinline__ void rom_core(const Inst &I, const RomDev &R, const RomWork &W, int z, RomSmem &sm) {
   RtState *st = I.st;
-  int rank = z ? st->rank_pc : st->rank_ig;
-  int luok = z ? st->lu_ok_pc : st->lu_ok_ig;
+  int rank = *rom_rank_of(st, z);
+  int luok = *rom_luok_of(st, z);
   const int dfc = isvd_core<COH, DEFER_LU>(R, W, I.r_max, rank, luok, sm);
   if (threadIdx.x == 0) {
     const long long step_no = W.step_no;
@@ -1207,32 +1269,34 @@ __device__ __forceinline__ void rom_core(const Inst &I, const RomDev &R, const R
           if (z == 0) {
             st->flag_ig = 1;
             st->n0 = (int)step_no;
-          } else {
+          } else if (z == 1) {
             // PC snapshots start only after the IG construction ended in an
             // earlier step, so n0 is settled here
             st->flag_pc = 1;
             st->n1 = (int)step_no - st->n0;
+          } else {
+            // level z collects only after the levels below it completed
+            int prior = st->n0 + st->n1;
+            for (int k = 0; k < z - 2; ++k) prior += st->n_pl[k];
+            st->flag_pl[z - 2] = 1;
+            st->n_pl[z - 2] = (int)step_no - prior;
           }
         }
       }
     } else {
       updated = 1;
     }
-    if (z == 0) {
-      st->rank_ig = rank;
-      if (!DEFER_LU) st->lu_ok_ig = luok;
-      st->ig_updates += updated;
-    } else {
-      st->rank_pc = rank;
-      if (!DEFER_LU) st->lu_ok_pc = luok;
-      st->pc_updates += updated;
-    }
+    *rom_rank_of(st, z) = rank;
+    if (!DEFER_LU) *rom_luok_of(st, z) = luok;
+    if (z == 0) st->ig_updates += updated;
+    else if (z == 1) st->pc_updates += updated;
+    else st->upd_pl[z - 2] += updated;
     if (I.hist && step_no <= I.hist_cap) {
       RtStepRec &rec = I.hist[step_no - 1];
       if (z == 0) {
         rec.ig_update = updated;
         rec.rank_ig = rank;
-      } else {
+      } else if (z == 1) {
         rec.pc_update = updated;
         rec.rank_pc = rank;
       }
@@ -1243,8 +1307,5 @@ __device__ __forceinline__ void rom_core(const Inst &I, const RomDev &R, const R
 // The deferred LU of rom_core<., true> and its flag (every thread calls).
 __device__ __forceinline__ void rom_core_lu(const Inst &I, const RomDev &R, int z, RomSmem &sm) {
   const int luok = isvd_lu(R, sm);
-  if (threadIdx.x == 0 && luok >= 0) {
-    if (z == 0) I.st->lu_ok_ig = luok;
-    else I.st->lu_ok_pc = luok;
-  }
+  if (threadIdx.x == 0 && luok >= 0) *rom_luok_of(I.st, z) = luok;
 }

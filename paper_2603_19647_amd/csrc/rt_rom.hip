@@ -92,7 +92,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     const Inst *__restrict__ insts) {
   const Inst &I = insts[blockIdx.x];
   if (I.method != RT_ROM || !I.post_fused) return;
-  const int z = blockIdx.y;
+  const int z = blockIdx.y;  // 0: initial guess, l: correction of iteration l
+  if (z > I.nlev) return;
   const RomDev &R = rom_of(I, z);
   const RomWork &W = *R.work;
   if (!W.active) return;
@@ -165,8 +166,9 @@ extern "C" hipError_t rt_launch_rom(const Inst *dinsts, int ninst, int nc_max, i
 // Slab instances: the SI kernel took the decisions.  Fused instances take
 // one launch; the others the grid passes and the core.  nc_grid: the largest
 // non-fused instance (0: none).
-extern "C" hipError_t rt_launch_rom_slab(const Inst *dinsts, int ninst, int any_fused, int nc_grid, hipStream_t s) {
-  if (any_fused) hipLaunchKernelGGL(k_rom_post_small, dim3(ninst, 2), dim3(256), 0, s, dinsts);
+extern "C" hipError_t rt_launch_rom_slab(const Inst *dinsts, int ninst, int any_fused, int nc_grid, int nrom,
+                                         hipStream_t s) {
+  if (any_fused) hipLaunchKernelGGL(k_rom_post_small, dim3(ninst, nrom), dim3(256), 0, s, dinsts);
   if (nc_grid > 0) {
     const int nb = pass_blocks(nc_grid);
     hipLaunchKernelGGL(k_rom_pass1, dim3(nb, ninst, 2), dim3(BLK), 0, s, dinsts);

@@ -934,18 +934,21 @@ __global__ void __launch_bounds__(256) k_fpass_sum(const Inst *__restrict__ inst
 // in affine form (serial over cells, once per problem).
 // Reading of eq. rho_residual for FV: diffusion coefficient
 // D = 1/(3 sigma~_t) + h/4, harmonic face coupling, Marshak vacuum faces.
+// alt: the factors of the BDF2 operator (time weight 3 / (2 dt)).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_setup_dsa_slab(const Inst *__restrict__ insts) {
+__global__ void __launch_bounds__(1024) k_setup_dsa_slab(const Inst *__restrict__ insts, int alt) {
   const Inst &I = insts[blockIdx.x];
   extern __shared__ double lds[];
   const int nc = I.nc;
   const double h = I.hx;
   double *diag = lds;       // [nc] diagonal, then the Thomas pivots d'_i
   double *q = lds + nc;     // [nc] lo_i * up_{i-1}
-  double *fe = const_cast<double *>(I.dsa_fe);
-  double *bg = const_cast<double *>(I.dsa_bg);
-  double *invd = const_cast<double *>(I.dsa_invd);
-  auto Dof = [&](int i) { return 1.0 / (3.0 * I.ct[i]) + 0.25 * h; };
+  double *fe = const_cast<double *>(alt ? I.dsa_fe_b : I.dsa_fe);
+  double *bg = const_cast<double *>(alt ? I.dsa_bg_b : I.dsa_bg);
+  double *invd = const_cast<double *>(alt ? I.dsa_invd_b : I.dsa_invd);
+  const double *ct = alt ? I.ct_b : I.ct;
+  const double adt = alt ? I.adt_b : I.inv_dt;
+  auto Dof = [&](int i) { return 1.0 / (3.0 * ct[i]) + 0.25 * h; };
   auto face = [&](double Dp, double Dq) { return 2.0 * Dp * Dq / (h * (Dp + Dq)); };
   auto bdry = [&](double Dp) { return 2.0 * Dp / (h + 4.0 * Dp); };
   // entries of row i: lo_i = -k_{i-1/2}/h, up_i = -k_{i+1/2}/h, in parallel
@@ -953,7 +956,7 @@ __global__ void __launch_bounds__(1024) k_setup_dsa_slab(const Inst *__restrict_
     const double Di = Dof(i);
     const double kl = (i > 0) ? face(Di, Dof(i - 1)) : bdry(Di);
     const double kr = (i < nc - 1) ? face(Di, Dof(i + 1)) : bdry(Di);
-    diag[i] = I.sa[i] + I.inv_dt + (kl + kr) / h;
+    diag[i] = I.sa[i] + adt + (kl + kr) / h;
     // lo_i * up_{i-1}: both equal -k_{i-1/2}/h
     q[i] = (i > 0) ? (kl / h) * (kl / h) : 0.0;
     bg[i] = (i < nc - 1) ? -kr / h : 0.0;  // up_i for now
@@ -1070,7 +1073,7 @@ extern "C" hipError_t rt_launch_slab_tail_coop(const Inst *dinst, int npair, int
   return hipGetLastError();
 }
 
-extern "C" hipError_t rt_launch_slab_setup(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream) {
-  hipLaunchKernelGGL(k_setup_dsa_slab, dim3(ninst), dim3(1024), 2 * sizeof(double) * nc_max, stream, dinsts);
+extern "C" hipError_t rt_launch_slab_setup(const Inst *dinsts, int ninst, int nc_max, int alt, hipStream_t stream) {
+  hipLaunchKernelGGL(k_setup_dsa_slab, dim3(ninst), dim3(1024), 2 * sizeof(double) * nc_max, stream, dinsts, alt);
   return hipGetLastError();
 }

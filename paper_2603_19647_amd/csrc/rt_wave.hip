@@ -23,6 +23,7 @@
 // in the other slab SI kernel.
 #include "rt_common.h"
 #include "rt_dsa.h"
+#include "rt_mh.h"
 #include "rt_rom.h"
 
 namespace {
@@ -185,9 +186,23 @@ __device__ __forceinline__ void wave_reduce(const R (&acc)[WCM], int C, int P, R
 // workgroup each, nc <= RT_WAVE_MAX_CELLS), then the step's error indicators
 // and Alg. 2's decisions (rom_decide).  Writes rho^n, rho^{(0)}, rho^{(1/2)},
 // the PC correction and the per-step status, as k_si_slab does.
+// MH: the instantiation for instances whose correction is McClarren-Haut
+// instead of DSA (rt_mh.h); each instantiation skips the other instances.
+// BDF2 instances take the BDF2 operator (transport and DSA) from their second
+// step on.
 // ---------------------------------------------------------------------------
+template <bool MH>
+struct MhSlot {
+  MhLds s;
+};
+template <>
+struct MhSlot<false> {};
+
+template <bool MH>
 __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts) {
   const Inst &I = insts[blockIdx.x];
+  if ((I.precond == RT_PC_MH) != MH) return;
+  __shared__ MhSlot<MH> mhslot;
   __shared__ double ct64[64 * WPM];
   __shared__ float ct32[64 * WPM];
   __shared__ double src[64 * WPM];   // the sweep source: FP64 sweeps
@@ -219,17 +234,24 @@ __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts)
   const int flag_ig = st->flag_ig, flag_pc = st->flag_pc;
   const int lu_ig = st->lu_ok_ig, lu_pc = st->lu_ok_pc;
   const int rank_ig = st->rank_ig, rank_pc = st->rank_pc;
+  // correction ROMs of iterations 2..nlev (Sec. 3.2, key feature 1); their
+  // state is read where it is used (it does not change during the solve)
+  const int nlev = I.nlev;
+  int phase0 = !flag_ig ? 1 : (!flag_pc ? 2 : 3);
+  for (int k = 0; k + 2 <= nlev; ++k) phase0 += (phase0 == k + 3 && st->flag_pl[k]) ? 1 : 0;
   const int mixed = (I.precision == RT_MIXED);
   const long long steps0 = st->steps, si0 = st->si_total, sw0 = st->sweeps_total, f32_0 = st->fp32_sweeps;
   const int nonconv0 = st->nonconv, fb0 = st->fallbacks;
   const int cur = (int)(steps0 & 1);
   const double *__restrict__ bt = I.bt2[cur];
+  const bool alt = I.bdf2 && steps0 >= 1;  // BDF2 operator after the backward-Euler start
+  const double *__restrict__ ctp = alt ? I.ct_b : I.ct;
 
   // per-cell constants of the sweeps in LDS (cells past nc: sigma_t = 0 and a
   // zero source, i.e. identity maps), the pairs' |mu|/h and weights
   for (int i = tid; i < 64 * P; i += WNT) {
     const int l = i / P, t = i - l * P, c = l * C + t;
-    const double v = (t < C && c < nc) ? ldg(&I.ct[c]) : 0.0;
+    const double v = (t < C && c < nc) ? ldg(&ctp[c]) : 0.0;
     ct64[i] = v;
     ct32[i] = (float)v;
     src[i] = 0.0;
@@ -259,8 +281,17 @@ __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts)
   }
   int parity = 0;
   int nsweep = 0, n32 = 0, conv = 0, used_pc = 0, pc_fb = 0, exact = 0, first_corr = 1;
+  int ncorr = 0, used_mask = 0, lv_fb = 0;  // corrections so far; levels applied (bit l - 1)
   int need64 = 1;
   double resid = 0.0;
+  // McClarren-Haut: y_{l-1} and rho^{(l-2)}; the model lives within the step
+  double yp[WOWN], rp2[WOWN];
+  if constexpr (MH) {
+#pragma unroll
+    for (int t = 0; t < WOWN; ++t) yp[t] = rp2[t] = 0.0;
+    if (tid == 0) mhslot.s.m = 0;
+    __syncthreads();
+  }
   for (;;) {
     if (need64) {
       // rho^{(l-1/2)} = T Sigma_s rho^{(l-1)} + b~ (eq. SI_rho) in FP64
@@ -304,9 +335,55 @@ __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts)
       continue;
     }
     if (nsweep >= I.max_iter) break;
-    // synthetic acceleration
+    if constexpr (MH) {
+      // the pair of this iteration: (rho^{(l-1)} - rho^{(l-2)}, y_l - y_{l-1})
+      if (nsweep >= 2) {
+        double x[WOWN], z[WOWN];
+#pragma unroll
+        for (int t = 0; t < WOWN; ++t) {
+          x[t] = rp[t] - rp2[t];
+          z[t] = y[t] - yp[t];
+        }
+        mh_push<WOWN>(I, c0, n, x, z, mhslot.s);
+      }
+#pragma unroll
+      for (int t = 0; t < WOWN; ++t) {
+        yp[t] = y[t];
+        rp2[t] = rp[t];
+      }
+    }
+    // synthetic acceleration; correction l = ncorr + 1 of the step.  Level l
+    // of the correction ROMs keeps y_l = rho^{(l-1/2)} and rho^{(l-1)} for its
+    // pair, and applies when complete and level l - 1 applied before it.
+    const int lc = ncorr + 1;
+    const bool lev_here = rom && lc >= 2 && lc <= nlev;
+    bool lev_apply = false;
+    if (lev_here) {
+      const int k = lc - 2;
+#pragma unroll
+      for (int t = 0; t < WOWN; ++t)
+        if (t < n) {
+          stg(&I.ylev[k][c0 + t], y[t]);
+          stg(&I.rlev[k][c0 + t], rp[t]);
+        }
+      const bool due = st->flag_pl[k] && ((used_mask >> (lc - 2)) & 1);
+      const int luok = st->lu_ok_pl[k];
+      if (due && !luok) lv_fb++;
+      lev_apply = due && luok;
+    }
     double d[WOWN];
-    if (rom && first_corr && flag_pc && lu_pc) {
+    if (lev_apply) {
+      // ROM-enhanced correction of iteration lc (eq. dmd-sa at iteration lc)
+      const int k = lc - 2;
+#pragma unroll
+      for (int t = 0; t < WOWN; ++t)
+        if (t < n) stg(&I.wlev[k][c0 + t], y[t] - rp[t]);
+      __syncthreads();
+      rom_apply<WOWN, 10, 10>(I.pl[k], st->rank_pl[k], I.ld, nc, WNT, I.wlev[k], I.dlev[k], rred, rvec, redd);
+#pragma unroll
+      for (int t = 0; t < WOWN; ++t) d[t] = (t < n) ? ldg(&I.dlev[k][c0 + t]) : 0.0;
+      used_mask |= 1 << (lc - 1);
+    } else if (rom && first_corr && flag_pc && lu_pc) {
       // ROM-enhanced correction of the first iteration (eq. dmd-sa)
 #pragma unroll
       for (int t = 0; t < WOWN; ++t)
@@ -316,17 +393,26 @@ __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts)
 #pragma unroll
       for (int t = 0; t < WOWN; ++t) d[t] = (t < n) ? ldg(&I.dpc[c0 + t]) : 0.0;
       used_pc = 1;
+      used_mask |= 1;
     } else if (I.method == RT_SI_PLAIN) {
 #pragma unroll
       for (int t = 0; t < WOWN; ++t) d[t] = 0.0;
+    } else if constexpr (MH) {
+      // McClarren-Haut correction from the step's pairs (Sec. 3.3)
+      if (rom && first_corr && flag_pc) pc_fb = 1;
+      double r[WOWN];
+#pragma unroll
+      for (int t = 0; t < WOWN; ++t) r[t] = y[t] - rp[t];
+      mh_correct<WOWN>(I, c0, n, r, d, mhslot.s);
     } else {
       if (rom && first_corr && flag_pc) pc_fb = 1;
       double rhs[WOWN];
 #pragma unroll
       for (int t = 0; t < WOWN; ++t) rhs[t] = ss[t] * (y[t] - rp[t]);
-      dsa_solve_slab<WOWN>(I, c0, n, rhs, d, slots, parity);
+      dsa_solve_slab<WOWN>(I, c0, n, rhs, d, slots, parity, alt);
     }
     first_corr = 0;
+    ncorr++;
     if (mixed) {
       // y <- y + T32 Sigma_s (rho^{(l)} - rho^{(l-1)}): increment swept in FP32
 #pragma unroll
@@ -361,34 +447,62 @@ __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts)
     st->ig_fb = ig_fb;
     st->pc_fb = pc_fb;
     st->residual = resid;
-    st->phase = !flag_ig ? 1 : (!flag_pc ? 2 : 3);
+    st->phase = phase0;
     st->cur = cur;
     st->fp32_sweeps = f32_0 + n32;
+    st->used_mask = used_mask;
   }
   __syncthreads();
   // end of step: error indicators from the final iterate and Alg. 2's
   // decisions, so the ROM work that follows needs no launch of its own
   if (rom && flag_ig) {
-    double part[3] = {0.0, 0.0, 0.0};
+    if (nlev > 1) {
+      // also ||dlev - (rho^n - y_l)||^2 of the levels that applied
+      double part[3 + RT_XLEV];
 #pragma unroll
-    for (int t = 0; t < WOWN; ++t)
-      if (t < n) {
-        const double r = y[t];
-        part[0] = rt_fma(r, r, part[0]);
-        const double e1 = ldg(&I.rho0[c0 + t]) - r;
-        part[1] = rt_fma(e1, e1, part[1]);
-        const double e2 = ldg(&I.dpc[c0 + t]) - (r - ldg(&I.rhalf[c0 + t]));
-        part[2] = rt_fma(e2, e2, part[2]);
-      }
-    wg_sum_fast<3>(part, rred, rvec);
+      for (int k = 0; k < 3 + RT_XLEV; ++k) part[k] = 0.0;
+#pragma unroll
+      for (int t = 0; t < WOWN; ++t)
+        if (t < n) {
+          const double r = y[t];
+          part[0] = rt_fma(r, r, part[0]);
+          const double e1 = ldg(&I.rho0[c0 + t]) - r;
+          part[1] = rt_fma(e1, e1, part[1]);
+          const double e2 = ldg(&I.dpc[c0 + t]) - (r - ldg(&I.rhalf[c0 + t]));
+          part[2] = rt_fma(e2, e2, part[2]);
+#pragma unroll
+          for (int k = 0; k < RT_XLEV; ++k)
+            if ((used_mask >> (k + 1)) & 1) {
+              const double e = ldg(&I.dlev[k][c0 + t]) - (r - ldg(&I.ylev[k][c0 + t]));
+              part[3 + k] = rt_fma(e, e, part[3 + k]);
+            }
+        }
+      wg_sum_fast<3 + RT_XLEV>(part, rred, rvec);
+    } else {
+      double part[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int t = 0; t < WOWN; ++t)
+        if (t < n) {
+          const double r = y[t];
+          part[0] = rt_fma(r, r, part[0]);
+          const double e1 = ldg(&I.rho0[c0 + t]) - r;
+          part[1] = rt_fma(e1, e1, part[1]);
+          const double e2 = ldg(&I.dpc[c0 + t]) - (r - ldg(&I.rhalf[c0 + t]));
+          part[2] = rt_fma(e2, e2, part[2]);
+        }
+      wg_sum_fast<3>(part, rred, rvec);
+    }
   }
-  rom_decide(I, rvec, I.post_nb,
-             StepIn{nsweep, conv, used_pc, ig_fb, pc_fb, !flag_ig ? 1 : (!flag_pc ? 2 : 3), cur, flag_ig, flag_pc,
-                    rank_ig, rank_pc, nonconv0, fb0, resid, steps0, si0, sw0});
+  StepIn S{nsweep, conv, used_pc, ig_fb, pc_fb, phase0, cur, flag_ig, flag_pc,
+           rank_ig, rank_pc, nonconv0, fb0, resid, steps0, si0, sw0};
+  S.used_mask = used_mask;
+  S.lv_fb = lv_fb;
+  rom_decide(I, rvec, I.post_nb, S);
 }
 
-extern "C" hipError_t rt_launch_slab_si_wave(const Inst *dinsts, int ninst, hipStream_t stream) {
-  hipLaunchKernelGGL(k_si_wave, dim3(ninst), dim3(WNT), 0, stream, dinsts);
+extern "C" hipError_t rt_launch_slab_si_wave(const Inst *dinsts, int ninst, int kinds, hipStream_t stream) {
+  if (kinds & 1) hipLaunchKernelGGL(k_si_wave<false>, dim3(ninst), dim3(WNT), 0, stream, dinsts);
+  if (kinds & 2) hipLaunchKernelGGL(k_si_wave<true>, dim3(ninst), dim3(WNT), 0, stream, dinsts);
   return hipGetLastError();
 }
 
@@ -422,6 +536,7 @@ __device__ __forceinline__ int fidx(int c) { return c + (c >> 2); }  // one pad 
 
 __global__ void __launch_bounds__(WNT) k_fpass_wave(const Inst *__restrict__ insts, int rhs_only) {
   const Inst &I = insts[blockIdx.x];
+  if (I.bdf2) return;  // k_fpass_wave_bdf2
   __shared__ double big[4 * FROW];  // ct, srcc, G during the sweeps; then the moment rows
   double *ctS = big, *srcS = big + FROW, *gS = big + 2 * FROW;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -576,7 +691,204 @@ __global__ void __launch_bounds__(WNT) k_fpass_wave(const Inst *__restrict__ ins
   }
 }
 
-extern "C" hipError_t rt_launch_slab_fpass_wave(const Inst *dinsts, int ninst, int rhs_only, hipStream_t stream) {
-  hipLaunchKernelGGL(k_fpass_wave, dim3(ninst), dim3(WNT), 0, stream, dinsts, rhs_only);
+// ---------------------------------------------------------------------------
+// k_fpass_wave_bdf2: the f-pass of BDF2 instances, in k_fpass_wave's layout
+// and order.  For the step n just solved (n = the state's step count): f^n
+// from rho^n with the source sigma_s rho^n + (4 f^{n-1} - f^{n-2}) / (2 dt)
+// + G and the BDF2 operator (at n = 1 the backward-Euler start: f^{n-1} / dt
+// and the backward-Euler operator), written over f^{n-2}; then the
+// right-hand side of step n + 1, b~^n = sum_j w_j sweep_j((4 f^n - f^{n-1})
+// / (2 dt) + G; g), with the BDF2 operator.  rhs_only: b~ of step S + 1 from
+// the stored f^S (and f^{S-1}), S the state's step count.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(WNT) k_fpass_wave_bdf2(const Inst *__restrict__ insts, int rhs_only) {
+  const Inst &I = insts[blockIdx.x];
+  if (!I.bdf2) return;
+  __shared__ double big[4 * FROW];  // ct (solve), ct (rhs), srcc, G; then the moment rows
+  double *ctS = big, *srcS = big + FROW, *gS = big + 2 * FROW, *ct2S = big + 3 * FROW;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nc = I.nc, npair = I.npair, nv = I.nv;
+  const int NB = (nc + FB - 1) / FB;
+  const double idt = I.inv_dt, hidt = 0.5 * I.inv_dt;
+  const long long S = I.st->steps;
+  const bool now_b = !rhs_only && S >= 2;        // f^n from the BDF2 formula
+  const bool next_b = rhs_only ? S >= 1 : true;  // b~ of a BDF2 step
+  const double *__restrict__ ct_now = now_b ? I.ct_b : I.ct;
+  const double *__restrict__ ct_next = next_b ? I.ct_b : I.ct;
+  // rhs_only: fA = f^{S-1}, fB = f^S.  Otherwise fA = f^{n-1}, fB = f^{n-2},
+  // overwritten by f^n.
+  double *fA = I.fb[(S + 1) & 1];
+  double *fB = I.fb[S & 1];
+  for (int c = tid; c < NB * FB; c += WNT) {
+    const bool in = c < nc;
+    const double g = in ? ldg(&I.G[c]) : 0.0;
+    ctS[fidx(c)] = in ? ldg(&ct_now[c]) : 0.0;
+    ct2S[fidx(c)] = in ? ldg(&ct_next[c]) : 0.0;
+    gS[fidx(c)] = g;
+    srcS[fidx(c)] = (in && !rhs_only) ? rt_fma(ldg(&I.ss[c]), ldg(&I.rho[c]), g) : 0.0;
+  }
+  __syncthreads();
+  double acc[FNB][FK];
+#pragma unroll
+  for (int b = 0; b < FNB; ++b)
+#pragma unroll
+    for (int k = 0; k < FK; ++k) acc[b][k] = 0.0;
+  const double g0 = I.g[0], g1 = I.g[1];
+  for (int p = wave; p < npair; p += WNW) {
+    const double m = ldg(&I.pm[p]), w = ldg(&I.pw[p]);
+    const size_t on = (size_t)p * nc, op = (size_t)(nv - 1 - p) * nc;  // mu < 0, mu > 0
+    double cp1 = g0, cp2 = g0, cn1 = g1, cn2 = g1;  // values entering the next block
+#pragma unroll
+    for (int s = 0; s < FNB; ++s) {
+      if (s < NB) {
+        const int bp = s, bn = NB - 1 - s;
+        const int cpb = bp * FB + lane * FK, cnb = bn * FB + lane * FK;
+        // fp, fn: f of the newest level (f^n once solved); ap, an: the level
+        // before it, for the BDF2 source of the right-hand side
+        double fp[FK], fn[FK], ap[FK], an[FK], ip[FK], in_[FK], jp[FK], jn[FK];
+#pragma unroll
+        for (int k = 0; k < FK; ++k) {
+          const bool okp = cpb + k < nc, okn = cnb + k < nc;
+          if (rhs_only) {
+            fp[k] = okp ? ldg(&fB[op + cpb + k]) : 0.0;
+            fn[k] = okn ? ldg(&fB[on + cnb + k]) : 0.0;
+            ap[k] = (okp && next_b) ? ldg(&fA[op + cpb + k]) : 0.0;
+            an[k] = (okn && next_b) ? ldg(&fA[on + cnb + k]) : 0.0;
+          } else {
+            ap[k] = okp ? ldg(&fA[op + cpb + k]) : 0.0;
+            an[k] = okn ? ldg(&fA[on + cnb + k]) : 0.0;
+            fp[k] = (okp && now_b) ? ldg(&fB[op + cpb + k]) : 0.0;  // f^{n-2}
+            fn[k] = (okn && now_b) ? ldg(&fB[on + cnb + k]) : 0.0;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < FK; ++k) {
+          ip[k] = rt_rcp(ctS[fidx(cpb + k)] + m);
+          in_[k] = rt_rcp(ctS[fidx(cnb + k)] + m);
+          jp[k] = rt_rcp(ct2S[fidx(cpb + k)] + m);
+          jn[k] = rt_rcp(ct2S[fidx(cnb + k)] + m);
+        }
+        if (!rhs_only) {
+          // f^n: source sigma_s rho^n + history + G, history from f^{n-1}
+          // (ap, an) and f^{n-2} (fp, fn)
+          double hp[FK], hn[FK];
+#pragma unroll
+          for (int k = 0; k < FK; ++k) {
+            hp[k] = now_b ? rt_fma(4.0, ap[k], -fp[k]) * hidt : ap[k] * idt;
+            hn[k] = now_b ? rt_fma(4.0, an[k], -fn[k]) * hidt : an[k] * idt;
+          }
+          double Bf = 0.0, pf = 1.0, Bb = 0.0, pb = 1.0;
+#pragma unroll
+          for (int k = 0; k < FK; ++k) {
+            const double bk = (hp[k] + srcS[fidx(cpb + k)]) * ip[k];
+            Bf = rt_fma(m * ip[k], Bf, bk);
+            pf *= m * ip[k];
+            const double bkn = (hn[k] + srcS[fidx(cnb + k)]) * in_[k];
+            Bb = rt_fma(bkn, pb, Bb);
+            pb *= m * in_[k];
+          }
+          double inF, inB;
+          wave_scan2<double>(pf, Bf, pb, Bb, cp1, cn1, inF, inB);
+          double f = inF;
+#pragma unroll
+          for (int k = 0; k < FK; ++k) {
+            f = rt_fma(m * ip[k], f, (hp[k] + srcS[fidx(cpb + k)]) * ip[k]);
+            fp[k] = f;
+            if (cpb + k < nc) stg(&fB[op + cpb + k], f);
+          }
+          cp1 = lane_value(f, 63);
+          f = inB;
+#pragma unroll
+          for (int k = FK - 1; k >= 0; --k) {
+            f = rt_fma(m * in_[k], f, (hn[k] + srcS[fidx(cnb + k)]) * in_[k]);
+            fn[k] = f;
+            if (cnb + k < nc) stg(&fB[on + cnb + k], f);
+          }
+          cn1 = lane_value(f, 0);
+#pragma unroll
+          for (int k = 0; k < FK; ++k) {
+            if (cpb + k >= nc) fp[k] = 0.0;
+            if (cnb + k >= nc) fn[k] = 0.0;
+          }
+        }
+        // right-hand side of the next step: source (4 f^n - f^{n-1}) / (2 dt)
+        // + G (a backward-Euler step: f / dt + G), its operator
+        double sp[FK], sn[FK];
+#pragma unroll
+        for (int k = 0; k < FK; ++k) {
+          sp[k] = (next_b ? rt_fma(4.0, fp[k], -ap[k]) * hidt : fp[k] * idt) + gS[fidx(cpb + k)];
+          sn[k] = (next_b ? rt_fma(4.0, fn[k], -an[k]) * hidt : fn[k] * idt) + gS[fidx(cnb + k)];
+        }
+        double Bf = 0.0, pf = 1.0, Bb = 0.0, pb = 1.0;
+#pragma unroll
+        for (int k = 0; k < FK; ++k) {
+          Bf = rt_fma(m * jp[k], Bf, sp[k] * jp[k]);
+          pf *= m * jp[k];
+          Bb = rt_fma(sn[k] * jn[k], pb, Bb);
+          pb *= m * jn[k];
+        }
+        double inF, inB;
+        wave_scan2<double>(pf, Bf, pb, Bb, cp2, cn2, inF, inB);
+        double f = inF;
+#pragma unroll
+        for (int k = 0; k < FK; ++k) {
+          f = rt_fma(m * jp[k], f, sp[k] * jp[k]);
+          fp[k] = f;
+        }
+        cp2 = lane_value(f, 63);
+        f = inB;
+#pragma unroll
+        for (int k = FK - 1; k >= 0; --k) {
+          f = rt_fma(m * jn[k], f, sn[k] * jn[k]);
+          fn[k] = f;
+        }
+        cn2 = lane_value(f, 0);
+#pragma unroll
+        for (int b = 0; b < FNB; ++b) {
+          if (b == bp) {
+#pragma unroll
+            for (int k = 0; k < FK; ++k) acc[b][k] = rt_fma(w, fp[k], acc[b][k]);
+          }
+          if (b == bn) {
+#pragma unroll
+            for (int k = 0; k < FK; ++k) acc[b][k] = rt_fma(w, fn[k], acc[b][k]);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (wave >= WNW / 2) {
+    double *r = big + (wave - WNW / 2) * FROW;
+#pragma unroll
+    for (int b = 0; b < FNB; ++b)
+      if (b < NB)
+#pragma unroll
+        for (int k = 0; k < FK; ++k) r[fidx(b * FB + lane * FK + k)] = acc[b][k];
+  }
+  __syncthreads();
+  if (wave < WNW / 2) {
+    double *r = big + wave * FROW;
+#pragma unroll
+    for (int b = 0; b < FNB; ++b)
+      if (b < NB)
+#pragma unroll
+        for (int k = 0; k < FK; ++k) {
+          const int i = fidx(b * FB + lane * FK + k);
+          r[i] = acc[b][k] + r[i];
+        }
+  }
+  __syncthreads();
+  double *bt_out = rhs_only ? I.bt2[S & 1] : I.bt2[I.st->cur ^ 1];
+  for (int c = tid; c < nc; c += WNT) {
+    const int i = fidx(c);
+    stg(&bt_out[c], ((big[i] + big[FROW + i]) + big[2 * FROW + i]) + big[3 * FROW + i]);
+  }
+}
+
+extern "C" hipError_t rt_launch_slab_fpass_wave(const Inst *dinsts, int ninst, int rhs_only, int kinds,
+                                                hipStream_t stream) {
+  if (kinds & 1) hipLaunchKernelGGL(k_fpass_wave, dim3(ninst), dim3(WNT), 0, stream, dinsts, rhs_only);
+  if (kinds & 2) hipLaunchKernelGGL(k_fpass_wave_bdf2, dim3(ninst), dim3(WNT), 0, stream, dinsts, rhs_only);
   return hipGetLastError();
 }

@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "librtrom.so")
 OK, EINVAL, ENOMEM, ENOCONV, EDEVICE, EBUSY = 0, -1, -2, -3, -4, -5
 METHOD = {"si_dsa": 0, "rom": 1, "si": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
+PRECOND = {"dsa": 0, "mh": 1}
+TIME_SCHEME = {"be": 0, "bdf2": 1}
 F_ABS_UP_NORM = 0x1
 F_SINGLE_WG = 0x2
 
@@ -36,6 +38,8 @@ class Desc(ctypes.Structure):
         ("max_iter", ctypes.c_int32), ("method", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("eps_ig", ctypes.c_double), ("eps_pc", ctypes.c_double), ("eps_up", ctypes.c_double),
         ("r_max", ctypes.c_int32), ("flags", ctypes.c_uint64),
+        ("precond", ctypes.c_int32), ("time_scheme", ctypes.c_int32),
+        ("pc_levels", ctypes.c_int32), ("mh_rank", ctypes.c_int32),
     ]
 
 
@@ -76,7 +80,7 @@ class RtromError(RuntimeError):
 EXPORTS = (
     "rtrom_create_problem", "rtrom_step", "rtrom_march", "rtrom_march_batch", "rtrom_march_batch_noalloc",
     "rtrom_get_scalar_flux", "rtrom_get_angular_flux", "rtrom_get_rhs", "rtrom_get_quadrature",
-    "rtrom_gauss_legendre", "rtrom_cl_quadrature", "rtrom_stats_get", "rtrom_get_history",
+    "rtrom_gauss_legendre", "rtrom_cl_quadrature", "rtrom_stats_get", "rtrom_get_levels", "rtrom_get_history",
     "rtrom_set_inflow", "rtrom_set_stream", "rtrom_device_bytes", "rtrom_estimate_bytes",
     "rtrom_destroy_problem", "rtrom_last_error",
     "rtrom_server_create", "rtrom_server_submit", "rtrom_server_poll", "rtrom_server_drain",
@@ -113,6 +117,7 @@ def lib():
     L.rtrom_cl_quadrature.argtypes = [i32, i32, _D, _D, _D, _D]
     L.rtrom_stats_get.argtypes = [vp, ctypes.POINTER(Stats)]
     L.rtrom_get_history.argtypes = [vp, ctypes.POINTER(StepRecord), i64, ctypes.POINTER(i64)]
+    L.rtrom_get_levels.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), i32, ctypes.POINTER(i32)]
     L.rtrom_set_inflow.argtypes = [vp, _D]
     L.rtrom_set_stream.argtypes = [vp, vp]
     L.rtrom_device_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
@@ -169,6 +174,10 @@ def make_desc(spec, keep: list) -> Desc:
     d.eps_ig, d.eps_pc, d.eps_up = spec.eps_ig, spec.eps_pc, spec.eps_up
     d.r_max = spec.r_max
     d.flags = (F_ABS_UP_NORM if spec.abs_up_norm else 0) | (F_SINGLE_WG if spec.single_wg else 0)
+    d.precond = PRECOND[spec.precond]
+    d.time_scheme = TIME_SCHEME[spec.time_scheme]
+    d.pc_levels = int(spec.pc_levels)
+    d.mh_rank = int(spec.mh_rank)
     return d
 
 
@@ -240,6 +249,14 @@ class Problem:
         s = Stats()
         _check(lib().rtrom_stats_get(self.h, ctypes.byref(s)))
         return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def levels(self) -> List[dict]:
+        """Per correction ROM level: complete flag, N_l, rank, updates."""
+        a = (ctypes.c_int64 * 16)()
+        nl = ctypes.c_int32()
+        _check(lib().rtrom_get_levels(self.h, a, 16, ctypes.byref(nl)))
+        return [dict(flag=int(a[4 * k]), n=int(a[4 * k + 1]), rank=int(a[4 * k + 2]), updates=int(a[4 * k + 3]))
+                for k in range(nl.value)]
 
     def history(self, n: Optional[int] = None) -> dict:
         n = self.stats()["steps"] if n is None else n

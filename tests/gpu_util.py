@@ -60,6 +60,40 @@ def oracle_rounding_spread(spec, nsteps: int, method=None):
     return np.array(out)
 
 
+def count_horizon(spec, nsteps: int, method=None, eps=(1e-15, -1e-15, 1e-13)) -> int:
+    """First step (0-based) at which an oracle run with sigma_s scaled by
+    1 + e takes another number of SI iterations than the unperturbed run, for
+    any e in eps (nsteps if none): past it the per-step counts of two equally
+    valid FP64 evaluations of the method no longer coincide."""
+    def iters(sp):
+        o = oracle.OracleProblem(sp, method=method)
+        o.march(nsteps)
+        return o.history()["iters"]
+    base = iters(spec)
+    h = nsteps
+    for e in eps:
+        d = np.nonzero(iters(spec.replace(sigma_s=spec.sigma_s * (1 + e))) != base)[0]
+        if d.size:
+            h = min(h, int(d[0]))
+    return h
+
+
+def ensemble_distance(spec, nsteps: int, ref, method=None,
+                      eps=(0.0, 1e-15, -1e-15, 1e-14, -1e-14, 1e-13, -1e-13, 1e-12)):
+    """Per step, the largest rel. L2 distance to the converged reference over
+    oracle runs with sigma_s scaled by 1 + e: how far from the solution an
+    equally valid FP64 evaluation of the method lands once its SI counts
+    depend on rounding (the stop test accepts any iterate whose last
+    increment is below tol, and which one that is follows the rounding)."""
+    out = np.zeros(nsteps)
+    for e in eps:
+        o = oracle.OracleProblem(spec.replace(sigma_s=spec.sigma_s * (1 + e)), method=method)
+        for k in range(nsteps):
+            o.step()
+            out[k] = max(out[k], rel_l2(o.rho(), ref[k]))
+    return out
+
+
 def converged_reference(spec, nsteps: int, ref_tol: float = 1e-13):
     """Per-step rho of a tightly converged FP64 SI-DSA oracle run: the discrete
     backward-Euler solution to ~ref_tol."""
