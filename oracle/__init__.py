@@ -19,6 +19,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 METHOD = {"si_dsa": 0, "rom": 1, "si": 2}
 PRECOND = {"dsa": 0, "mh": 1}
 TIME_SCHEME = {"be": 0, "bdf2": 1}
+SCHEME = {"fv": 0, "dg1": 1}
 _D = ctypes.POINTER(ctypes.c_double)
 
 
@@ -35,6 +36,7 @@ class OrcDesc(ctypes.Structure):
         ("r_max", ctypes.c_int32), ("abs_up_norm", ctypes.c_int32),
         ("precond", ctypes.c_int32), ("time_scheme", ctypes.c_int32),
         ("pc_levels", ctypes.c_int32), ("mh_rank", ctypes.c_int32),
+        ("scheme", ctypes.c_int32),
     ]
 
 
@@ -261,6 +263,7 @@ class OracleProblem:
         d.time_scheme = TIME_SCHEME[spec.time_scheme]
         d.pc_levels = int(spec.pc_levels)
         d.mh_rank = int(spec.mh_rank)
+        d.scheme = SCHEME[spec.scheme]
         self.h = lib().orc_create(ctypes.byref(d))
         if not self.h:
             raise ValueError("oracle rejected the problem description")
@@ -351,9 +354,10 @@ class OracleProblem:
 
     def dsa_matrix(self):
         n = self.nc
+        bw = 3 if self.spec.scheme == "dg1" else self.spec.nx
         C = np.zeros((n, n))
         for r in range(n):
-            for c in range(max(0, r - self.spec.nx), min(n, r + self.spec.nx + 1)):
+            for c in range(max(0, r - bw), min(n, r + bw + 1)):
                 C[r, c] = lib().orc_dsa_entry(self.h, r, c)
         return C
 

@@ -55,6 +55,10 @@
 
 #define ORC_MAX_LEVELS 4
 
+/* spatial discretisation (Sec. 2.1, eq. DG) */
+#define ORC_FV 0   /* K = 0: piecewise constants = first-order upwind finite volume */
+#define ORC_DG1 1  /* K = 1: piecewise linear upwind DG (slabs) */
+
 typedef struct {
   int32_t dim, nx, ny;
   double lx, ly;
@@ -71,6 +75,7 @@ typedef struct {
   int32_t time_scheme; /* ORC_BE or ORC_BDF2 */
   int32_t pc_levels;   /* sequential correction ROMs for iterations 1..pc_levels (0 = 1) */
   int32_t mh_rank;     /* McClarren-Haut pairs per model (0 = r_max) */
+  int32_t scheme;      /* ORC_FV or ORC_DG1 */
 } orc_desc;
 
 typedef struct {
@@ -628,10 +633,13 @@ int orc_mh_correct(void *h, const double *r, double *out) { return mh_correct((o
 
 typedef struct {
   orc_desc d;
-  int nc, nv;
+  int nc, nv;   /* nc: unknowns of rho (N_x of Sec. 2.2: cells x DoFs per cell) */
+  int ncell, ndof;
   double hx, hy;
   double *ox, *oy, *oz, *w; /* ordinates (1D: ox = mu) */
-  double *ss, *sa, *G, *ct; /* sigma_s, sigma_a, source, sigma_t + alpha/dt */
+  double *ss, *sa, *G, *ct; /* per unknown: sigma_s, sigma_a, source, sigma_t + alpha/dt
+                               (DG: the cell's values on both DoFs; the source's
+                               slope DoF is zero) */
   double alpha;             /* time-derivative weight of the current operator:
                                1 (backward Euler, and the first BDF2 step) or 3/2 */
   double *f;                /* f^n, [nv][nc] */
@@ -680,6 +688,7 @@ static int desc_valid(const orc_desc *d) {
   if (d->time_scheme != ORC_BE && d->time_scheme != ORC_BDF2) return 0;
   if (d->pc_levels < 0 || d->pc_levels > ORC_MAX_LEVELS) return 0;
   if (d->mh_rank < 0 || d->mh_rank > 64) return 0;
+  if (d->scheme != ORC_FV && !(d->scheme == ORC_DG1 && d->dim == 1)) return 0;
   if (!d->sigma_s || !d->sigma_a || !d->source) return 0;
   size_t nc = (size_t)d->nx * d->ny;
   for (size_t i = 0; i < nc; ++i) {
@@ -709,6 +718,34 @@ static double inflow_y(const orc_problem *P, int j) {
 static void sweep_one(const orc_problem *P, int j, const double *s, int zero_inflow,
                       double *out) {
   const int nx = P->d.nx, ny = P->d.ny;
+  if (P->d.scheme == ORC_DG1) {
+    /* eq. DG with K = 1 on the slab: on each cell f = u0 + sqrt(3) u1 xi
+     * (xi in [-1, 1]; the basis 1, sqrt(3) xi is orthonormal for the cell
+     * average), tested with both basis functions, upwind flux H-hat.  For
+     * mu > 0, with c = sigma_t + alpha/dt, h the cell width, f_in the value
+     * entering from the upwind face and s = s0 + sqrt(3) s1 xi:
+     *   (c h + mu) u0 + sqrt(3) mu u1 = h s0 + mu f_in
+     *   -sqrt(3) mu u0 + (c h + 3 mu) u1 = h s1 - sqrt(3) mu f_in
+     * and the value leaving the cell is u0 + sqrt(3) u1.  mu < 0 is the
+     * mirror image (xi -> -xi, so u1 and s1 change sign). */
+    const double mu = fabs(P->ox[j]), h = P->hx, r3 = sqrt(3.0);
+    const int pos = P->ox[j] > 0.0;
+    double fin = zero_inflow ? 0.0 : inflow_x(P, j);
+    for (int k = 0; k < nx; ++k) {
+      const int i = pos ? k : nx - 1 - k;
+      const double c = P->ct[2 * i];
+      const double s0 = s[2 * i], s1 = pos ? s[2 * i + 1] : -s[2 * i + 1];
+      const double a11 = c * h + mu, a12 = r3 * mu, a21 = -r3 * mu, a22 = c * h + 3.0 * mu;
+      const double b1 = h * s0 + mu * fin, b2 = h * s1 - r3 * mu * fin;
+      const double det = a11 * a22 - a12 * a21;
+      const double u0 = (b1 * a22 - a12 * b2) / det;
+      const double u1 = (a11 * b2 - a21 * b1) / det;
+      out[2 * i] = u0;
+      out[2 * i + 1] = pos ? u1 : -u1;
+      fin = u0 + r3 * u1;
+    }
+    return;
+  }
   if (P->d.dim == 1) {
     double m = fabs(P->ox[j]) / P->hx;
     double fin = zero_inflow ? 0.0 : inflow_x(P, j);
@@ -795,6 +832,69 @@ static double dsa_entry(const orc_problem *P, int r, int c) {
   return 0.0;
 }
 
+/* DSA for upwind DG-P1 (slabs).  Reading: the paper's "fully consistent"
+ * DSA is defined in a reference outside the paper; here the correction
+ * equation's diffusion limit, -(D d')' + sigma~_a d = sigma_s (rho^{l-1/2} -
+ * rho^{l-1}) with D = 1/(3 sigma~_t), is discretised in the same DG-P1 space
+ * by the modified interior penalty method: symmetric interior penalty with
+ * the penalty max(D_L / h + D_R / h, 1/4) on interior faces, and Marshak
+ * vacuum faces (a boundary term u v / 2).  Entry (r, c) of the bilinear form
+ * a(phi_c, phi_r) divided by h, so that the right-hand side is sigma_s times
+ * the DoF-wise difference (the mass matrix of the orthonormal basis is h I).
+ * The matrix is SPD; the fixed point does not depend on it. */
+static double mip_entry(const orc_problem *P, int r, int c) {
+  const int N = P->ncell;
+  const double h = P->hx, r3 = sqrt(3.0);
+  const int ci = r / 2, k = r % 2, cj = c / 2, m = c % 2;
+  if (abs(ci - cj) > 1) return 0.0;
+  const double phiR[2] = {1.0, r3}, phiL[2] = {1.0, -r3};  /* values at xi = +1, -1 */
+  const double dphi[2] = {0.0, 2.0 * r3 / h};              /* derivatives d/dx */
+  double a = 0.0;
+  if (ci == cj) {
+    const double D = 1.0 / (3.0 * P->ct[2 * ci]);
+    const double sat = P->sa[2 * ci] + P->alpha / P->d.dt;
+    a += D * dphi[m] * dphi[k] * h + (k == m ? sat * h : 0.0);
+  }
+  /* faces f = p + 1/2 between cells p and p + 1 touching both rows' cells */
+  for (int p = -1; p < N; ++p) {
+    const int L = p, R = p + 1;
+    /* jump [u] = u_L(+1) - u_R(-1) and the mean flux {D u'} of a basis
+     * function of cell q */
+    double ju = 0.0, jv = 0.0, fu = 0.0, fv = 0.0;
+    const int touches_c = (cj == L || cj == R), touches_r = (ci == L || ci == R);
+    if (!touches_c || !touches_r) continue;
+    if (L < 0 || R >= N) {  /* vacuum face: Marshak, (1/2) u v */
+      const double uc = (cj == L) ? phiR[m] : phiL[m];
+      const double vr = (ci == L) ? phiR[k] : phiL[k];
+      a += 0.5 * uc * vr;
+      continue;
+    }
+    const double DL = 1.0 / (3.0 * P->ct[2 * L]), DR = 1.0 / (3.0 * P->ct[2 * R]);
+    double kap = DL / h + DR / h;
+    if (kap < 0.25) kap = 0.25;
+    if (cj == L) {
+      ju = phiR[m];
+      fu = 0.5 * DL * dphi[m];
+    } else {
+      ju = -phiL[m];
+      fu = 0.5 * DR * dphi[m];
+    }
+    if (ci == L) {
+      jv = phiR[k];
+      fv = 0.5 * DL * dphi[k];
+    } else {
+      jv = -phiL[k];
+      fv = 0.5 * DR * dphi[k];
+    }
+    a += kap * ju * jv - fu * jv - fv * ju;
+  }
+  return a / h;
+}
+
+static double dsa_matrix_entry(const orc_problem *P, int r, int c) {
+  return P->d.scheme == ORC_DG1 ? mip_entry(P, r, c) : dsa_entry(P, r, c);
+}
+
 static int dsa_setup(orc_problem *P) {
   int nc = P->nc;
   free(P->dlo);
@@ -802,7 +902,7 @@ static int dsa_setup(orc_problem *P) {
   free(P->dup);
   free(P->band);
   P->dlo = P->ddi = P->dup = P->band = NULL;
-  if (P->d.dim == 1) {
+  if (P->d.dim == 1 && P->d.scheme == ORC_FV) {
     P->dlo = (double *)calloc(nc, sizeof(double));
     P->ddi = (double *)calloc(nc, sizeof(double));
     P->dup = (double *)calloc(nc, sizeof(double));
@@ -814,8 +914,10 @@ static int dsa_setup(orc_problem *P) {
     }
     return ORC_OK;
   }
-  /* 2D: banded Cholesky of the SPD 5-point matrix, lower bandwidth nx */
-  int bw = P->d.nx;
+  /* 2D: banded Cholesky of the SPD 5-point matrix, lower bandwidth nx;
+   * DG-P1 slabs: of the MIP matrix, lower bandwidth 3 (two DoFs per cell,
+   * neighbouring cells coupled) */
+  int bw = P->d.scheme == ORC_DG1 ? 3 : P->d.nx;
   P->bw = bw;
   P->band = (double *)calloc((size_t)nc * (bw + 1), sizeof(double));
   if (!P->band) return ORC_ENOMEM;
@@ -823,7 +925,7 @@ static int dsa_setup(orc_problem *P) {
   for (int i = 0; i < nc; ++i) {
     int j0 = i - bw > 0 ? i - bw : 0;
     for (int j = j0; j <= i; ++j) {
-      double s = dsa_entry(P, i, j);
+      double s = dsa_matrix_entry(P, i, j);
       int k0 = (i - bw > j - bw ? i - bw : j - bw);
       if (k0 < 0) k0 = 0;
       for (int k = k0; k < j; ++k) s -= L(i, k) * L(j, k);
@@ -842,7 +944,7 @@ static int dsa_setup(orc_problem *P) {
 /* exact solve of C x = rhs (Thomas in 1D, banded Cholesky in 2D) */
 static void dsa_solve(orc_problem *P, const double *rhs, double *x) {
   int n = P->nc;
-  if (P->d.dim == 1) {
+  if (P->d.dim == 1 && P->d.scheme == ORC_FV) {
     double *cp = P->w5, *dp = P->w6;
     cp[0] = P->dup[0] / P->ddi[0];
     dp[0] = rhs[0] / P->ddi[0];
@@ -936,7 +1038,10 @@ void *orc_create(const orc_desc *d) {
   if (!P) return NULL;
   P->d = *d;
   P->d.sigma_s = P->d.sigma_a = P->d.source = P->d.f0 = NULL;
-  int nc = d->nx * d->ny;
+  const int ncell = d->nx * d->ny, ndof = d->scheme == ORC_DG1 ? 2 : 1;
+  int nc = ncell * ndof;
+  P->ncell = ncell;
+  P->ndof = ndof;
   P->nc = nc;
   P->hx = d->lx / d->nx;
   P->hy = d->dim == 2 ? d->ly / d->ny : 1.0;
@@ -1005,10 +1110,11 @@ void *orc_create(const orc_desc *d) {
   else
     orc_cl_quadrature(d->n_azim, d->n_polar, P->ox, P->oy, P->oz, P->w);
   for (int i = 0; i < nc; ++i) {
-    P->ss[i] = d->sigma_s[i];
-    P->sa[i] = d->sigma_a[i];
-    P->G[i] = d->source[i];
-    P->rho[i] = d->f0 ? d->f0[i] : 0.0;
+    const int cell = i / ndof, dof = i % ndof;
+    P->ss[i] = d->sigma_s[cell];
+    P->sa[i] = d->sigma_a[cell];
+    P->G[i] = dof == 0 ? d->source[cell] : 0.0;
+    P->rho[i] = (dof == 0 && d->f0) ? d->f0[cell] : 0.0;
   }
   for (int j = 0; j < nv; ++j)
     for (int i = 0; i < nc; ++i) P->f[(size_t)j * nc + i] = P->rho[i];
@@ -1376,7 +1482,7 @@ void orc_dsa_apply_inverse(void *h, const double *rhs, double *out) {
   dsa_solve((orc_problem *)h, rhs, out);
 }
 /* dense DSA matrix entry (for assembling it in tests) */
-double orc_dsa_entry(void *h, int r, int c) { return dsa_entry((orc_problem *)h, r, c); }
+double orc_dsa_entry(void *h, int r, int c) { return dsa_matrix_entry((orc_problem *)h, r, c); }
 /* one sweep of ordinate j with an arbitrary per-cell source */
 void orc_sweep(void *h, int j, const double *s, int zero_inflow, double *out) {
   sweep_one((orc_problem *)h, j, s, zero_inflow, out);

@@ -27,6 +27,7 @@ METHODS = ("si_dsa", "rom", "si")
 PRECISIONS = ("fp64", "mixed")
 PRECONDS = ("dsa", "mh")        # correction where DSA would be: DSA or McClarren-Haut
 TIME_SCHEMES = ("be", "bdf2")   # backward Euler or BDF2 (backward-Euler start)
+SCHEMES = ("fv", "dg1")         # upwind finite volume (DG-0) or piecewise-linear upwind DG (slabs)
 
 
 @dataclass
@@ -59,6 +60,7 @@ class ProblemSpec:
     time_scheme: str = "be"
     pc_levels: int = 1  # sequential correction ROMs for iterations 1..pc_levels
     mh_rank: int = 0  # McClarren-Haut pairs per model, 0 = r_max
+    scheme: str = "fv"  # spatial discretisation: "fv" or "dg1" (two unknowns per cell)
     single_wg: bool = False  # 1D: one workgroup even when marched alone (device mode only)
     nsteps: int = 1
     name: str = ""
