@@ -102,6 +102,16 @@ def roofline_sweep(prof, kind, dim, updates, kernel):
             "flops_per_launch": flops / launches}
 
 
+def roofline_hbm(prof, kind, nbytes, kernel):
+    """An HBM-bound kernel: algorithmic bytes of its launches / their
+    event-timed duration, against the 8 TB/s peak."""
+    sec, launches = prof[kind]
+    ach = nbytes / sec / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": None, "kernel": kernel, "kind": kind, "launches": launches,
+            "avg_launch_ms": sec / launches * 1e3, "bytes_per_launch": nbytes / launches}
+
+
 def roofline_dsa(prof, nc, cheb_iters):
     """Chebyshev DSA solve: algorithmic bytes of the unfused iteration (read
     d, r, x, diag, ax, ay; write d, r, x: 9 doubles per cell) per iteration."""
@@ -118,6 +128,9 @@ def roofline_dsa(prof, nc, cheb_iters):
 # while these files are unchanged.
 KERNEL_SOURCES = {
     "k_si_slab": ["rt_slab.hip", "rt_common.h", "rt_rom.h", "rt_arrow.h", "rt_capi.hip"],
+    "k_si_wave": ["rt_wave.hip", "rt_common.h", "rt_rom.h", "rt_dsa.h", "rt_mh.h", "rt_arrow.h"],
+    "k_fpass_wave": ["rt_wave.hip", "rt_common.h"],
+    "k_rom_post_small": ["rt_rom.hip", "rt_rom.h", "rt_arrow.h", "rt_common.h"],
     "k_plane_sweep": ["rt_plane.hip", "rt_common.h"],
 }
 
@@ -235,9 +248,18 @@ def bench_batch(rtrom, W, args):
     R, S = res["rom"], res["si_dsa"]
     value = n * steps / R["t"]
     si_val = n * steps / S["t"]
-    roof = roofline_sweep(R["prof"], "slab_si", 1, R["si_upd"], "k_si_slab")
-    kernels = kernel_table(R["prof"], steps * (FPASS_BYTES_PER_CELL_ANGLE * R["ca"] + FPASS_BYTES_PER_CELL * R["cells"]),
-                           steps * SI_BYTES_PER_CELL * R["cells"], ROM_BYTES_PER_CELL_COLUMN * R["rom_cc"])
+    fpass_bytes = steps * (FPASS_BYTES_PER_CELL_ANGLE * R["ca"] + FPASS_BYTES_PER_CELL * R["cells"])
+    rom_bytes = ROM_BYTES_PER_CELL_COLUMN * R["rom_cc"]
+    kernels = kernel_table(R["prof"], fpass_bytes, steps * SI_BYTES_PER_CELL * R["cells"], rom_bytes)
+    # the roofline line reports the kernel that takes the longest in the timed
+    # steps (every instance has at most 2048 cells: the wave-per-pair kernels)
+    dom = max(("slab_si", "slab_fpass", "post"), key=lambda k: R["prof"].get(k, (0.0, 0))[0])
+    if dom == "slab_si":
+        roof = roofline_sweep(R["prof"], "slab_si", 1, R["si_upd"], "k_si_wave")
+    elif dom == "slab_fpass":
+        roof = roofline_hbm(R["prof"], "slab_fpass", fpass_bytes, "k_fpass_wave")
+    else:
+        roof = roofline_hbm(R["prof"], "post", rom_bytes, "k_rom_post_small")
     # the whole configured march of both methods, on fresh problems
     full = {}
     for method in ("rom", "si_dsa"):
@@ -255,6 +277,32 @@ def bench_batch(rtrom, W, args):
             p.close()
     full["speedup_vs_si_dsa"] = full["rom"]["instance_steps_per_s"] / full["si_dsa"]["instance_steps_per_s"]
     full["steps"] = cfg_steps
+    # the same whole march with the variants of the method (every instance
+    # has at most 2048 cells): the McClarren-Haut preconditioner alone and as
+    # the hybrid with the ROM method (Sec. 3.3, 4.5), sequential correction
+    # ROMs for iterations 1-2 (Sec. 3.2), BDF2 (Sec. 2.1) for both methods,
+    # and the FP64 mode of both methods
+    variants = {}
+    for name, method, kw in (("si_mh", "si_dsa", dict(precond="mh")), ("rom_mh_hybrid", "rom", dict(precond="mh")),
+                             ("rom_levels2", "rom", dict(pc_levels=2)),
+                             ("si_dsa_bdf2", "si_dsa", dict(time_scheme="bdf2")),
+                             ("rom_bdf2", "rom", dict(time_scheme="bdf2")),
+                             ("si_dsa_fp64", "si_dsa", dict(precision="fp64")), ("rom_fp64", "rom", dict(precision="fp64"))):
+        if args.no_variants:
+            break
+        ms = [s.replace(method=method, **kw) for s in specs]
+        log(f"bench: batch512 variant {name}: full {cfg_steps}-step march")
+        t, probs, _ = timed_batch(rtrom, ms, 0, cfg_steps, profile=False)
+        hist = [p.history() for p in probs]
+        sts = [p.stats() for p in probs]
+        variants[name] = {"instance_steps_per_s": n * cfg_steps / t, "ms_per_step": t / cfg_steps * 1e3,
+                          "si_sweeps_per_step": sum(int(h["iters"].sum()) for h in hist) / (n * cfg_steps),
+                          "nonconverged_steps": sum(st["nonconverged_steps"] for st in sts)}
+        for p in probs:
+            p.close()
+    if variants:
+        for a, b in (("rom_bdf2", "si_dsa_bdf2"), ("rom_fp64", "si_dsa_fp64"), ("rom_mh_hybrid", "si_mh")):
+            variants[f"{a}_vs_{b}"] = variants[a]["instance_steps_per_s"] / variants[b]["instance_steps_per_s"]
     extra = {
         "si_dsa_instance_steps_per_s": si_val,
         "speedup_vs_si_dsa": value / si_val,
@@ -264,6 +312,7 @@ def bench_batch(rtrom, W, args):
         "kernel_ms": kernel_ms(R["prof"]), "si_dsa_kernel_ms": kernel_ms(S["prof"]),
         "kernels": kernels,
         "full_march": full,
+        "variants": variants,
     }
     config = {"workload": "batch512_slabs", "instances": n, "steps": steps, "timed_steps": f"{warm + 1}..{warm + steps}",
               "cells": "128..2048", "ordinates": "16/32/64", "dt": 0.01, "tol": 1e-8,
@@ -464,6 +513,7 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=4.0, help="serving: HBM admission budget")
     ap.add_argument("--slots", type=int, default=8, help="serving: concurrent problems")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="batch512: skip the variant marches")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device five times (a plain copy of known size, "
                          "against which hardware byte counters are scaled)")

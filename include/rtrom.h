@@ -81,6 +81,18 @@ typedef enum {
                     solves with another operator).  Slabs: at most 2048 cells. */
 } rtrom_time_scheme;
 
+/* Spatial discretisation (Sec. 2.1, eq. DG). */
+typedef enum {
+  RTROM_FV = 0,  /* piecewise constants (K = 0): first-order upwind finite volume */
+  RTROM_DG1 = 1  /* piecewise linears (K = 1) on slabs: two unknowns per cell
+                    (the cell average and the slope coefficient of the
+                    orthonormal basis 1, sqrt(3) xi), so rho, f and b~ hold
+                    2 nx values per ordinate, cell-major; DSA by the modified
+                    interior-penalty discretisation of the correction's
+                    diffusion limit.  Slabs of at most 1024 cells, with DSA
+                    and backward Euler. */
+} rtrom_scheme;
+
 /* flags */
 #define RTROM_F_ABS_UP_NORM 0x1ull /* error indicators in the paper's absolute
                                       2-norm instead of relative to ||rho^n|| */
@@ -129,6 +141,7 @@ typedef struct {
                           single level; at most 4 */
   int32_t mh_rank;     /* McClarren-Haut pairs per model (a full model restarts
                           from the newest pair), 0 = r_max; at most 20 */
+  int32_t scheme;      /* rtrom_scheme */
 } rtrom_problem_desc;
 
 typedef struct {

@@ -245,7 +245,19 @@ static rtrom_status validate(const rtrom_problem_desc *d) {
     return fail(RTROM_EINVAL, "McClarren-Haut and BDF2 run on slabs only");
   if (d->pc_levels > 1 && !(d->dim == 1 && d->nx <= RT_WAVE_MAX_CELLS))
     return fail(RTROM_EINVAL, "correction ROMs beyond the first iteration run on slabs of at most 2048 cells");
+  if (d->scheme != RTROM_FV && d->scheme != RTROM_DG1) return fail(RTROM_EINVAL, "unknown scheme");
+  if (d->scheme == RTROM_DG1) {
+    if (d->dim != 1) return fail(RTROM_EINVAL, "the DG-P1 scheme runs on slabs only");
+    if (d->nx > RT_DG_MAX_CELLS) return fail(RTROM_EINVAL, "DG-P1 slabs are limited to 1024 cells");
+    if (d->precond != RTROM_PC_DSA || d->time_scheme != RTROM_BE)
+      return fail(RTROM_EINVAL, "DG-P1 slabs run with DSA and backward Euler");
+  }
   return RTROM_OK;
+}
+
+// unknowns of the scalar flux: cells, or two per cell for DG-P1
+static size_t unknowns_of(const rtrom_problem_desc *d) {
+  return (size_t)d->nx * d->ny * (d->scheme == RTROM_DG1 ? 2 : 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -314,8 +326,9 @@ static void slab_groups(const rtrom_problem_desc *d, int nv, int *ng, int *pg) {
   *ng = 0;
   *pg = npair;
   if (d->dim != 1 || (d->flags & RTROM_F_SINGLE_WG) || npair < 2) return;
-  // the variants run in the one-workgroup kernels
-  if (d->precond == RTROM_PC_MH || d->time_scheme == RTROM_BDF2 || d->pc_levels > 1) return;
+  // the variants and DG run in the one-workgroup kernels
+  if (d->precond == RTROM_PC_MH || d->time_scheme == RTROM_BDF2 || d->pc_levels > 1 || d->scheme == RTROM_DG1)
+    return;
   const int g = std::min(16, npair);
   *pg = (npair + g - 1) / g;
   *ng = (npair + *pg - 1) / *pg;
@@ -329,7 +342,7 @@ static size_t part_rows(int dim, size_t nc) { return dim == 1 ? (nc + 63) / 64 :
 static int mh_cap_of(const rtrom_problem_desc *d) { return d->mh_rank > 0 ? d->mh_rank : d->r_max; }
 
 static size_t slab_bytes(const rtrom_problem_desc *d, int nv) {
-  const size_t nc = (size_t)d->nx * d->ny;
+  const size_t nc = unknowns_of(d);
   const size_t ld = (nc + 31) & ~size_t(31);
   Layout L;
   for (int k = 0; k < 13; ++k) L.take(nc * 8);
@@ -346,6 +359,7 @@ static size_t slab_bytes(const rtrom_problem_desc *d, int nv) {
       L.take((size_t)mh_cap_of(d) * ld * 8);
       L.take((size_t)mh_cap_of(d) * ld * 8);
     }
+    if (d->scheme == RTROM_DG1) L.take(12 * (size_t)d->nx * 8);  // block DSA factors
     int ng, pg;
     slab_groups(d, nv, &ng, &pg);
     if (ng > 1) {
@@ -384,7 +398,8 @@ static size_t slab_bytes(const rtrom_problem_desc *d, int nv) {
 // and the same problem marched alone start from bitwise the same b~.
 static hipError_t slab_rhs(rtrom_problem *p) {
   const Inst &I = p->hinst;
-  if (p->nc <= RT_WAVE_MAX_CELLS) return rt_launch_slab_fpass_wave(p->dinst, 1, 1, I.bdf2 ? 2 : 1, p->stream);
+  if (p->nc <= RT_WAVE_MAX_CELLS)
+    return rt_launch_slab_fpass_wave(p->dinst, 1, 1, I.dg ? 4 : (I.bdf2 ? 2 : 1), p->stream);
   int cmax;
   const int nt = slab_launch_threads(&I.nthr, &p->nc, 1, &cmax);
   return rt_launch_slab_rhs(p->dinst, 1, nt, cmax, I.npair, p->nc, p->stream);
@@ -460,7 +475,8 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   p->d = *d;
   p->d.sigma_s = p->d.sigma_a = p->d.source = p->d.f0 = nullptr;
   (void)hipGetDevice(&p->device);
-  const int nc = d->nx * d->ny;
+  const int nc = (int)unknowns_of(d);  // == cells except for DG-P1
+  const int ncell = d->nx * d->ny, ndof = nc / ncell;
   const int nv = d->dim == 1 ? d->n_polar : d->n_polar * d->n_azim;
   p->nc = nc;
   p->nv = nv;
@@ -524,6 +540,9 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
     I.mhQ = D((size_t)I.mh_cap * ld * 8);
     I.mhZ = D((size_t)I.mh_cap * ld * 8);
   }
+  if (d->dim == 1 && d->scheme == RTROM_DG1) I.dsa_blk = D(12 * (size_t)ncell * 8);
+  I.dg = d->scheme == RTROM_DG1;
+  I.ncell = ncell;
   slab_groups(d, nv, &I.ng, &I.pg);
   if (I.ng > 1) {
     I.sip = D(2 * (size_t)I.ng * nc * 8);
@@ -613,8 +632,16 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   I.dsa_invd = invd;
 
   // --- host-side staging of per-cell and per-ordinate data ----------------
-  std::vector<double> h_ct(nc), h_q((size_t)nv * 6, 0.0);
-  for (int i = 0; i < nc; ++i) h_ct[i] = d->sigma_s[i] + d->sigma_a[i] + 1.0 / d->dt;
+  // per unknown: the cell's value (DG-P1: both unknowns; the source and f0
+  // are constant on the cell, so their slope unknowns are zero)
+  std::vector<double> h_ss(nc), h_sa(nc), h_G(nc), h_ct(nc), h_q((size_t)nv * 6, 0.0);
+  for (int u = 0; u < nc; ++u) {
+    const int i = u / ndof;
+    h_ss[u] = d->sigma_s[i];
+    h_sa[u] = d->sigma_a[i];
+    h_G[u] = u % ndof == 0 ? d->source[i] : 0.0;
+    h_ct[u] = d->sigma_s[i] + d->sigma_a[i] + 1.0 / d->dt;
+  }
   if (d->dim == 1) {
     // ordinates sorted ascending: pair p = (p, nv-1-p) are mirrors
     for (int q = 0; q < nv / 2; ++q) {
@@ -627,7 +654,7 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   auto H2D = [&](void *dst, const void *src, size_t bytes) {
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, p->stream) == hipSuccess;
   };
-  bool ok = H2D(ss, d->sigma_s, nc * 8) && H2D(sa, d->sigma_a, nc * 8) && H2D(G, d->source, nc * 8) &&
+  bool ok = H2D(ss, h_ss.data(), nc * 8) && H2D(sa, h_sa.data(), nc * 8) && H2D(G, h_G.data(), nc * 8) &&
             H2D(ct, h_ct.data(), nc * 8) && H2D(qbuf, h_q.data(), h_q.size() * 8);
   std::vector<double> h_ctb;
   if (ctb) {  // the BDF2 operator: sigma_t + 3 / (2 dt)
@@ -637,7 +664,7 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   }
   std::vector<double> rho0(nc, 0.0);
   if (d->f0)
-    for (int i = 0; i < nc; ++i) rho0[i] = d->f0[i];
+    for (int u = 0; u < nc; u += ndof) rho0[u] = d->f0[u / ndof];
   ok = ok && H2D(I.rho, rho0.data(), nc * 8);
   if (d->f0)
     for (int j = 0; j < nv && ok && d->dim == 1; ++j) ok = H2D(I.f + (size_t)j * nc, rho0.data(), nc * 8);
@@ -653,7 +680,11 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   }
   if (d->dim == 1) {
     if (upload_inst(p) != RTROM_OK) return bail(RTROM_EDEVICE, "upload descriptor failed");
-    if (rt_launch_slab_setup(p->dinst, 1, nc, 0, p->stream) != hipSuccess) return bail(RTROM_EDEVICE, "setup launch failed");
+    if (I.dg) {
+      if (rt_launch_setup_dsa_dg(p->dinst, 1, p->stream) != hipSuccess) return bail(RTROM_EDEVICE, "setup launch failed");
+    } else if (rt_launch_slab_setup(p->dinst, 1, nc, 0, p->stream) != hipSuccess) {
+      return bail(RTROM_EDEVICE, "setup launch failed");
+    }
     if (I.bdf2 && rt_launch_slab_setup(p->dinst, 1, nc, 1, p->stream) != hipSuccess)
       return bail(RTROM_EDEVICE, "setup launch failed");
     if (slab_rhs(p) != hipSuccess) return bail(RTROM_EDEVICE, "initial RHS launch failed");
@@ -799,7 +830,7 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
     while (nA < n && ncs[nA] > RT_WAVE_MAX_CELLS) ++nA;
     struct Group {
       int off, cnt, nt, cmax, nc_max, npair_max, pairs_total, wave;
-      int si_kinds, fp_kinds;  // wave kernels: bit 0 default instances, bit 1 variants (MH; BDF2)
+      int si_kinds, fp_kinds;  // wave kernels: bit 0 default instances, bit 1 variants (MH; BDF2), bit 2 DG
     };
     std::vector<Group> groups;
     for (int g = 0; g < 2; ++g) {
@@ -810,8 +841,8 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
         G.nc_max = std::max(G.nc_max, ncs[i]);
         G.npair_max = std::max(G.npair_max, ps[i]->hinst.npair);
         G.pairs_total += ps[i]->hinst.npair;
-        G.si_kinds |= ps[i]->hinst.precond == RT_PC_MH ? 2 : 1;
-        G.fp_kinds |= ps[i]->hinst.bdf2 ? 2 : 1;
+        G.si_kinds |= ps[i]->hinst.dg ? 4 : (ps[i]->hinst.precond == RT_PC_MH ? 2 : 1);
+        G.fp_kinds |= ps[i]->hinst.dg ? 4 : (ps[i]->hinst.bdf2 ? 2 : 1);
       }
       groups.push_back(G);
     }

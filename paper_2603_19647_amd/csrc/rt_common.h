@@ -34,6 +34,8 @@ struct RomPend {
 // slab instances up to this many cells run the SI solve one workgroup of
 // eight waves each, ordinate pairs spread over the waves (k_si_wave)
 #define RT_WAVE_MAX_CELLS 2048
+// piecewise-linear DG slabs: at most this many cells (two unknowns each)
+#define RT_DG_MAX_CELLS 1024
 __host__ __device__ inline int rt_pass_blocks(int nc) {
   const int nb = (nc + 255) / 256;
   return nb < 64 ? nb : 64;
@@ -151,6 +153,14 @@ struct Inst {
   int nlev, pad_lv;
   RomDev pl[RT_XLEV];
   double *ylev[RT_XLEV], *rlev[RT_XLEV], *dlev[RT_XLEV], *wlev[RT_XLEV];
+  // piecewise-linear DG on slabs (dg = 1): nc = 2 ncell unknowns, cell-major
+  // (cell average, then the coefficient of sqrt(3) xi); the per-unknown
+  // arrays (ss, sa, ct) repeat the cell's value, G and f0 have zero slopes.
+  // dsa_blk: the block-tridiagonal DSA in affine form, [12][ncell]: F_i
+  // (forward multiplier), S_i^{-1} and B_i (backward multiplier), each 2x2
+  // row-major.
+  int dg, ncell;
+  const double *dsa_blk;
 };
 
 enum { RT_SI_DSA = 0, RT_ROM = 1, RT_SI_PLAIN = 2 };

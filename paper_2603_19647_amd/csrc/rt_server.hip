@@ -97,7 +97,7 @@ static void march_request(rtrom_server *s, Req *r) {
     }
   }
   if (worst == RTROM_OK || worst == RTROM_ENOCONV) {
-    r->rho.resize((size_t)r->d.nx * r->d.ny);
+    r->rho.resize((size_t)r->d.nx * r->d.ny * (r->d.scheme == RTROM_DG1 ? 2 : 1));  // unknowns
     st = rtrom_get_scalar_flux(p, r->rho.data(), (int64_t)r->rho.size());
     if (st == RTROM_OK) st = rtrom_stats_get(p, &r->stats);
     if (st != RTROM_OK) {

@@ -143,6 +143,265 @@ __device__ __forceinline__ void wave_sweep_cls(int CM, int npair, const R *ctL, 
   }
 }
 
+// Piecewise-linear DG (eq. DG with K = 1) on the slab: on a cell f = u0 +
+// sqrt(3) u1 xi, xi in [-1, 1] across the cell, tested with 1 and sqrt(3) xi
+// and upwinded at the faces.  With c = sigma_t + 1/dt, m = |mu| / h, the
+// cell's source s0 + sqrt(3) s1 xi and f_in the value entering through the
+// upwind face, the cell's 2x2 system for mu > 0 is
+//   (c + m) u0 + sqrt(3) m u1 = s0 + m f_in
+//   -sqrt(3) m u0 + (c + 3 m) u1 = s1 - sqrt(3) m f_in
+// with determinant det = c (c + 4 m) + 6 m^2.  Solved:
+//   u0 = [(c + 3 m) s0 - sqrt(3) m s1 + m (c + 6 m) f_in] / det
+//   u1 = [(c + m) s1 + sqrt(3) m s0 - sqrt(3) m c f_in] / det
+// and the value leaving through the downwind face, u0 + sqrt(3) u1, is
+// affine in f_in:  f_out = a f_in + b,  a = 2 m (3 m - c) / det,  b = [(c +
+// 6 m) s0 + sqrt(3) c s1] / det  (|a| < 1).  mu < 0 is the mirror image (xi
+// -> -xi: s1 and u1 change sign), so both directions share a and det and
+// differ in b.  The sweep is therefore the same affine recurrence as for
+// finite volumes, on face values, and each cell's two unknowns follow from
+// the value entering it.
+constexpr double kR3 = 1.7320508075688772;  // sqrt(3)
+
+template <typename R>
+struct DgCell {
+  R q, a, bf, bb;  // 1/det, face factor, forward and backward offsets
+};
+template <typename R>
+__device__ __forceinline__ DgCell<R> dg_cell(R c, R m, R s0, R s1) {
+  DgCell<R> z;
+  z.q = rt_rcp(rt_fma(c, c + R(4) * m, R(6) * m * m));
+  z.a = (R(2) * m * (R(3) * m - c)) * z.q;
+  // the same expressions as where the sweep applies the maps
+  const R v = (R(kR3) * c) * s1;
+  z.bf = rt_fma(c + R(6) * m, s0, v) * z.q;
+  z.bb = rt_fma(c + R(6) * m, s0, -v) * z.q;
+  return z;
+}
+// the cell's unknowns from the entering face value (fwd: mu > 0)
+template <typename R, bool FWD>
+__device__ __forceinline__ void dg_unknowns(R c, R m, R s0, R s1, R q, R fin, R &u0, R &u1) {
+  const R r3m = R(kR3) * m;
+  if (FWD) {
+    u0 = rt_fma(m * (c + R(6) * m), fin, rt_fma(c + R(3) * m, s0, -r3m * s1)) * q;
+    u1 = rt_fma(-r3m * c, fin, rt_fma(c + m, s1, r3m * s0)) * q;
+  } else {
+    u0 = rt_fma(m * (c + R(6) * m), fin, rt_fma(c + R(3) * m, s0, r3m * s1)) * q;
+    u1 = rt_fma(r3m * c, fin, rt_fma(c + m, s1, -r3m * s0)) * q;
+  }
+}
+
+// wave_sweep for DG slabs: a lane's run holds C <= CM cells, two unknowns
+// each, at slots 2 t, 2 t + 1 of its row (rows of 2 CM + 1); acc[2 t + k]
+// takes the moments.  Padding slots (c = 0, s = 0) are identity maps.
+template <typename R, int CM>
+__device__ __forceinline__ void wave_sweep_dg(int npair, const R *ctL, const R *sL, const double *pmS,
+                                              const double *pwS, R (&acc)[WCM]) {
+  static_assert(2 * CM <= WCM, "two unknowns per cell");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int base = lane * (2 * CM + 1);
+#pragma unroll
+  for (int t = 0; t < WCM; ++t) acc[t] = R(0);
+  for (int p = wave; p < npair; p += WNW) {
+    const R m = (R)pmS[p], w = (R)pwS[p];
+    R a[CM], q[CM];
+    R pi = R(1), Bf = R(0), Bb = R(0);
+#pragma unroll
+    for (int t = 0; t < CM; ++t) {
+      if (t % 8 == 0) __builtin_amdgcn_sched_barrier(0);
+      const DgCell<R> z = dg_cell<R>(ctL[base + 2 * t], m, sL[base + 2 * t], sL[base + 2 * t + 1]);
+      a[t] = z.a;
+      q[t] = z.q;
+      Bf = rt_fma(z.a, Bf, z.bf);
+      Bb = rt_fma(z.bb, pi, Bb);
+      pi *= z.a;
+    }
+    R inF, inB;
+    wave_scan2<R>(pi, Bf, pi, Bb, R(0), R(0), inF, inB);
+    R f = inF;
+#pragma unroll
+    for (int t = 0; t < CM; ++t) {
+      if (t % 8 == 0) __builtin_amdgcn_sched_barrier(0);
+      const R c = ctL[base + 2 * t], s0 = sL[base + 2 * t], s1 = sL[base + 2 * t + 1];
+      R u0, u1;
+      dg_unknowns<R, true>(c, m, s0, s1, q[t], f, u0, u1);
+      acc[2 * t] = rt_fma(w, u0, acc[2 * t]);
+      acc[2 * t + 1] = rt_fma(w, u1, acc[2 * t + 1]);
+      f = rt_fma(a[t], f, (rt_fma(c + R(6) * m, s0, (R(kR3) * c) * s1)) * q[t]);
+    }
+    f = inB;
+#pragma unroll
+    for (int t = CM - 1; t >= 0; --t) {
+      if (t % 8 == 7) __builtin_amdgcn_sched_barrier(0);
+      const R c = ctL[base + 2 * t], s0 = sL[base + 2 * t], s1 = sL[base + 2 * t + 1];
+      R u0, u1;
+      dg_unknowns<R, false>(c, m, s0, s1, q[t], f, u0, u1);
+      acc[2 * t] = rt_fma(w, u0, acc[2 * t]);
+      acc[2 * t + 1] = rt_fma(w, u1, acc[2 * t + 1]);
+      f = rt_fma(a[t], f, (rt_fma(c + R(6) * m, s0, -(R(kR3) * c) * s1)) * q[t]);
+    }
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void wave_sweep_dg_cls(int CM, int npair, const R *ctL, const R *sL, const double *pmS,
+                                                  const double *pwS, R (&acc)[WCM]) {
+  switch (CM) {
+    case 4: wave_sweep_dg<R, 4>(npair, ctL, sL, pmS, pwS, acc); break;
+    case 8: wave_sweep_dg<R, 8>(npair, ctL, sL, pmS, pwS, acc); break;
+    case 12: wave_sweep_dg<R, 12>(npair, ctL, sL, pmS, pwS, acc); break;
+    default: wave_sweep_dg<R, 16>(npair, ctL, sL, pmS, pwS, acc); break;
+  }
+}
+
+// DSA of DG slabs: C d = rhs with C block tridiagonal (2x2 blocks L_i, D_i,
+// L_{i+1}^T), by block elimination written as two recurrences of 2x2 affine
+// maps over the cells: z_i = F_i z_{i-1} + rhs_i forward, then d_i = B_i
+// d_{i+1} + S_i^{-1} z_i backward (F, S^{-1}, B from k_setup_dsa_dg).  Each
+// thread composes the maps of its cells, a workgroup scan of the composites
+// gives every thread the value entering its run, and the thread applies its
+// maps.
+struct Blk2 {
+  double a00, a01, a10, a11, b0, b1;  // x -> A x + b
+};
+__device__ __forceinline__ Blk2 blk_id() { return {1.0, 0.0, 0.0, 1.0, 0.0, 0.0}; }
+// X o Y: x -> X(Y(x))
+__device__ __forceinline__ Blk2 blk_after(const Blk2 &X, const Blk2 &Y) {
+  Blk2 r;
+  r.a00 = rt_fma(X.a00, Y.a00, X.a01 * Y.a10);
+  r.a01 = rt_fma(X.a00, Y.a01, X.a01 * Y.a11);
+  r.a10 = rt_fma(X.a10, Y.a00, X.a11 * Y.a10);
+  r.a11 = rt_fma(X.a10, Y.a01, X.a11 * Y.a11);
+  r.b0 = rt_fma(X.a00, Y.b0, rt_fma(X.a01, Y.b1, X.b0));
+  r.b1 = rt_fma(X.a10, Y.b0, rt_fma(X.a11, Y.b1, X.b1));
+  return r;
+}
+__device__ __forceinline__ void blk_apply(const Blk2 &X, double &v0, double &v1) {
+  const double t0 = rt_fma(X.a00, v0, rt_fma(X.a01, v1, X.b0));
+  const double t1 = rt_fma(X.a10, v0, rt_fma(X.a11, v1, X.b1));
+  v0 = t0;
+  v1 = t1;
+}
+template <int CTRL>
+__device__ __forceinline__ Blk2 blk_dpp(const Blk2 &v) {  // lanes without a source get the identity
+  return {dpp_fill<CTRL>(1.0, v.a00), dpp_fill<CTRL>(0.0, v.a01), dpp_fill<CTRL>(0.0, v.a10),
+          dpp_fill<CTRL>(1.0, v.a11), dpp_fill<CTRL>(0.0, v.b0),  dpp_fill<CTRL>(0.0, v.b1)};
+}
+__device__ __forceinline__ Blk2 blk_lane(const Blk2 &v, int l) {
+  return {lane_value(v.a00, l), lane_value(v.a01, l), lane_value(v.a10, l),
+          lane_value(v.a11, l), lane_value(v.b0, l),  lane_value(v.b1, l)};
+}
+
+// Exclusive scan of the threads' composite maps M over the workgroup (WNW
+// waves), applied to a zero boundary value: FWD, the maps of the threads
+// below in ascending order; otherwise those above in descending order.
+// slots: 2 x 64 doubles (parity halves, as wg_scan2).
+template <bool FWD>
+__device__ __forceinline__ void wg_scan_blk(Blk2 M, double &in0, double &in1, double *slots, int parity) {
+  const int lane = threadIdx.x & 63, row = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (FWD) {
+    M = blk_after(M, blk_dpp<0x111>(M));  // row_shr:1
+    M = blk_after(M, blk_dpp<0x112>(M));  // row_shr:2
+    M = blk_after(M, blk_dpp<0x114>(M));  // row_shr:4
+    M = blk_after(M, blk_dpp<0x118>(M));  // row_shr:8
+    const Blk2 r0 = blk_lane(M, 15), r1 = blk_lane(M, 31), r2 = blk_lane(M, 47);
+    const Blk2 p1 = r0, p2 = blk_after(r1, p1), p3 = blk_after(r2, p2);
+    if (row == 1) M = blk_after(M, p1);
+    if (row == 2) M = blk_after(M, p2);
+    if (row == 3) M = blk_after(M, p3);
+  } else {
+    M = blk_after(M, blk_dpp<0x101>(M));  // row_shl:1
+    M = blk_after(M, blk_dpp<0x102>(M));  // row_shl:2
+    M = blk_after(M, blk_dpp<0x104>(M));  // row_shl:4
+    M = blk_after(M, blk_dpp<0x108>(M));  // row_shl:8
+    const Blk2 r3 = blk_lane(M, 48), r2 = blk_lane(M, 32), r1 = blk_lane(M, 16);
+    const Blk2 q2 = r3, q1 = blk_after(r2, q2), q0 = blk_after(r1, q1);
+    if (row == 0) M = blk_after(M, q0);
+    if (row == 1) M = blk_after(M, q1);
+    if (row == 2) M = blk_after(M, q2);
+  }
+  const Blk2 E = FWD ? blk_dpp<0x138>(M) : blk_dpp<0x130>(M);  // wave_shr:1 / wave_shl:1
+  const Blk2 T = blk_lane(M, FWD ? 63 : 0);                    // the wave's composite
+  double *sl = slots + parity * 64;
+  if (lane == 0) {
+    sl[6 * wave + 0] = T.a00;
+    sl[6 * wave + 1] = T.a01;
+    sl[6 * wave + 2] = T.a10;
+    sl[6 * wave + 3] = T.a11;
+    sl[6 * wave + 4] = T.b0;
+    sl[6 * wave + 5] = T.b1;
+  }
+  __syncthreads();
+  double v0 = 0.0, v1 = 0.0;  // the value entering the wave
+  if (FWD) {
+    for (int k = 0; k < wave; ++k)
+      blk_apply({sl[6 * k], sl[6 * k + 1], sl[6 * k + 2], sl[6 * k + 3], sl[6 * k + 4], sl[6 * k + 5]}, v0, v1);
+  } else {
+    for (int k = WNW - 1; k > wave; --k)
+      blk_apply({sl[6 * k], sl[6 * k + 1], sl[6 * k + 2], sl[6 * k + 3], sl[6 * k + 4], sl[6 * k + 5]}, v0, v1);
+  }
+  blk_apply(E, v0, v1);
+  in0 = v0;
+  in1 = v1;
+}
+
+// d = C^{-1} rhs for the thread's unknowns [c0, c0 + n) (whole cells, n even)
+template <int CMAX>
+__device__ __forceinline__ void dsa_solve_dg(const Inst &I, int c0, int n, const double (&rhs)[CMAX],
+                                             double (&d)[CMAX], double *slots, int &parity) {
+  constexpr int NCL = CMAX / 2;
+  const int N = I.ncell, i0 = c0 / 2, ncl = n / 2;
+  const double *__restrict__ K = I.dsa_blk;
+#pragma unroll
+  for (int k = 0; k < CMAX; ++k) d[k] = 0.0;
+  Blk2 fw[NCL];
+  Blk2 T = blk_id();
+#pragma unroll
+  for (int k = 0; k < NCL; ++k) {
+    if (k < ncl) {
+      const int i = i0 + k;
+      fw[k] = {ldg(&K[i]), ldg(&K[N + i]), ldg(&K[2 * N + i]), ldg(&K[3 * N + i]), rhs[2 * k], rhs[2 * k + 1]};
+      T = blk_after(fw[k], T);
+    }
+  }
+  double z0, z1;
+  wg_scan_blk<true>(T, z0, z1, slots, parity);
+  parity ^= 1;
+  double z[CMAX];
+#pragma unroll
+  for (int k = 0; k < NCL; ++k) {
+    if (k < ncl) {
+      blk_apply(fw[k], z0, z1);
+      z[2 * k] = z0;
+      z[2 * k + 1] = z1;
+    }
+  }
+  Blk2 bw[NCL];
+  T = blk_id();
+#pragma unroll
+  for (int k = NCL - 1; k >= 0; --k) {
+    if (k < ncl) {
+      const int i = i0 + k;
+      const double s00 = ldg(&K[4 * N + i]), s01 = ldg(&K[5 * N + i]);
+      const double s10 = ldg(&K[6 * N + i]), s11 = ldg(&K[7 * N + i]);
+      bw[k] = {ldg(&K[8 * N + i]), ldg(&K[9 * N + i]), ldg(&K[10 * N + i]), ldg(&K[11 * N + i]),
+               rt_fma(s00, z[2 * k], s01 * z[2 * k + 1]), rt_fma(s10, z[2 * k], s11 * z[2 * k + 1])};
+      T = blk_after(bw[k], T);
+    }
+  }
+  double x0, x1;
+  wg_scan_blk<false>(T, x0, x1, slots, parity);
+  parity ^= 1;
+#pragma unroll
+  for (int k = NCL - 1; k >= 0; --k) {
+    if (k < ncl) {
+      blk_apply(bw[k], x0, x1);
+      d[2 * k] = x0;
+      d[2 * k + 1] = x1;
+    }
+  }
+}
+
 // Sum of the eight waves' moments at the calling thread's cells (sweep-layout
 // indices oidx[k], k < n), in a fixed order: waves 4..7 store theirs, waves
 // 0..3 add their own to wave w + 4's, and the four rows are added in order.
@@ -189,7 +448,9 @@ __device__ __forceinline__ void wave_reduce(const R (&acc)[WCM], int C, int P, R
 // MH: the instantiation for instances whose correction is McClarren-Haut
 // instead of DSA (rt_mh.h); each instantiation skips the other instances.
 // BDF2 instances take the BDF2 operator (transport and DSA) from their second
-// step on.
+// step on.  DG: the instantiation for piecewise-linear DG instances (two
+// unknowns per cell: the sweeps of wave_sweep_dg, the block DSA of
+// dsa_solve_dg); everything else works on the unknowns as on cells.
 // ---------------------------------------------------------------------------
 template <bool MH>
 struct MhSlot {
@@ -198,10 +459,10 @@ struct MhSlot {
 template <>
 struct MhSlot<false> {};
 
-template <bool MH>
+template <bool MH, bool DG>
 __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts) {
   const Inst &I = insts[blockIdx.x];
-  if ((I.precond == RT_PC_MH) != MH) return;
+  if ((I.precond == RT_PC_MH) != MH || (I.dg != 0) != DG) return;
   __shared__ MhSlot<MH> mhslot;
   __shared__ double ct64[64 * WPM];
   __shared__ float ct32[64 * WPM];
@@ -217,17 +478,22 @@ __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts)
   const int tid = threadIdx.x;
   const int nc = I.nc, npair = I.npair;
   // sweep layout: lane l's run is cells [l C, l C + C), row l of P = CM + 1
-  // slots (odd), CM = C rounded up to a multiple of four
-  const int C = (nc + 63) / 64;
-  const int CM = (C + 3) & ~3, P = CM + 1;
-  const int CW = (nc + WNT - 1) / WNT;
+  // slots (odd), CM = C rounded up to a multiple of four.  DG: the run's
+  // cells hold two slots each (rows of P = 2 CM + 1), and the threads own
+  // whole cells outside the sweeps.
+  const int ncl = DG ? nc / 2 : nc;  // cells
+  const int C = (ncl + 63) / 64;
+  const int CM = (C + 3) & ~3, P = DG ? 2 * CM + 1 : CM + 1;
+  const int CW = DG ? 2 * ((ncl + WNT - 1) / WNT) : (nc + WNT - 1) / WNT;
   const int c0 = tid * CW;
   const int n = max(0, min(CW, nc - c0));
   int oidx[WOWN];
 #pragma unroll
   for (int k = 0; k < WOWN; ++k) {
-    const int c = c0 + min(k, max(n - 1, 0));
-    oidx[k] = min((c / C) * P + c % C, 64 * WPM - 1);  // used only for k < n
+    const int u = c0 + min(k, max(n - 1, 0));  // unknown
+    const int c = DG ? u / 2 : u;
+    const int slot = DG ? 2 * (c % C) + (u & 1) : c % C;
+    oidx[k] = min((c / C) * P + slot, 64 * WPM - 1);  // used only for k < n
   }
   RtState *st = I.st;
   const int rom = (I.method == RT_ROM);
@@ -250,8 +516,8 @@ __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts)
   // per-cell constants of the sweeps in LDS (cells past nc: sigma_t = 0 and a
   // zero source, i.e. identity maps), the pairs' |mu|/h and weights
   for (int i = tid; i < 64 * P; i += WNT) {
-    const int l = i / P, t = i - l * P, c = l * C + t;
-    const double v = (t < C && c < nc) ? ldg(&ctp[c]) : 0.0;
+    const int l = i / P, t = i - l * P, tc = DG ? t / 2 : t, c = l * C + tc;
+    const double v = (tc < C && c < ncl) ? ldg(&ctp[DG ? 2 * c : c]) : 0.0;
     ct64[i] = v;
     ct32[i] = (float)v;
     src[i] = 0.0;
@@ -300,8 +566,9 @@ __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts)
         if (t < n) src[oidx[t]] = ss[t] * rp[t];
       __syncthreads();
       double acc[WCM], mom[WOWN];
-      wave_sweep_cls<double>(CM, npair, ct64, src, pmS, pwS, acc);
-      wave_reduce<double>(acc, C, P, redd, oidx, n, mom);
+      if constexpr (DG) wave_sweep_dg_cls<double>(CM, npair, ct64, src, pmS, pwS, acc);
+      else wave_sweep_cls<double>(CM, npair, ct64, src, pmS, pwS, acc);
+      wave_reduce<double>(acc, DG ? 2 * C : C, P, redd, oidx, n, mom);
 #pragma unroll
       for (int t = 0; t < WOWN; ++t) y[t] = mom[t] + b0[t];
       if (nsweep == 0) {
@@ -324,15 +591,40 @@ __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts)
     wg_max2(dl, yl, red, dn, yn);
     resid = yn > 0.0 ? dn / yn : dn;
     if (stop_test(dn, yn, exact ? I.tol_cert : I.tol32)) {
-      if (exact) {
+      if (!exact) {
+        // mixed precision: the FP32-accumulated iterate passed; re-check it
+        // on an FP64 sweep before accepting
+        if (nsweep >= I.max_iter) break;
+        need64 = 1;
+        continue;
+      }
+      // DG: an iterate refined by FP32 increments must also pass on an
+      // estimate of its error.  The stop test sees an error e of
+      // rho^{(l-1)} only through the residual (T Sigma_s - I) e, which is
+      // small for the slowly converging (diffusive) modes that DSA exists to
+      // remove, and the FP32 increments of DG sweeps leave errors in exactly
+      // those modes (uncaught, they accumulate over the steps).  The step to
+      // the next DSA-corrected iterate, y - rho + C^{-1} Sigma_s (y - rho),
+      // measures them and must pass the same test.  Finite-volume runs were
+      // not seen to fail this check, and skip its DSA solve.
+      bool accept = n32 == 0 || !DG;
+      if (!accept) {
+        double rhs[WOWN], dd[WOWN];
+#pragma unroll
+        for (int t = 0; t < WOWN; ++t) rhs[t] = ss[t] * (y[t] - rp[t]);
+        if constexpr (DG) dsa_solve_dg<WOWN>(I, c0, n, rhs, dd, slots, parity);
+        double el = 0.0;
+#pragma unroll
+        for (int t = 0; t < WOWN; ++t)
+          if (t < n) el = fmax(el, fabs((y[t] - rp[t]) + dd[t]));
+        double en, e2;
+        wg_max2(el, 0.0, red, en, e2);
+        accept = stop_test(en, yn, I.tol_cert);
+      }
+      if (accept) {
         conv = 1;
         break;
       }
-      // mixed precision: the FP32-accumulated iterate passed; re-check it on
-      // an FP64 sweep before accepting
-      if (nsweep >= I.max_iter) break;
-      need64 = 1;
-      continue;
     }
     if (nsweep >= I.max_iter) break;
     if constexpr (MH) {
@@ -409,7 +701,8 @@ __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts)
       double rhs[WOWN];
 #pragma unroll
       for (int t = 0; t < WOWN; ++t) rhs[t] = ss[t] * (y[t] - rp[t]);
-      dsa_solve_slab<WOWN>(I, c0, n, rhs, d, slots, parity, alt);
+      if constexpr (DG) dsa_solve_dg<WOWN>(I, c0, n, rhs, d, slots, parity);
+      else dsa_solve_slab<WOWN>(I, c0, n, rhs, d, slots, parity, alt);
     }
     first_corr = 0;
     ncorr++;
@@ -423,8 +716,9 @@ __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts)
       }
       __syncthreads();
       float acc[WCM], mom[WOWN];
-      wave_sweep_cls<float>(CM, npair, ct32, src32, pmS, pwS, acc);
-      wave_reduce<float>(acc, C, P, redf, oidx, n, mom);
+      if constexpr (DG) wave_sweep_dg_cls<float>(CM, npair, ct32, src32, pmS, pwS, acc);
+      else wave_sweep_cls<float>(CM, npair, ct32, src32, pmS, pwS, acc);
+      wave_reduce<float>(acc, DG ? 2 * C : C, P, redf, oidx, n, mom);
 #pragma unroll
       for (int t = 0; t < WOWN; ++t) y[t] += (double)mom[t];
       exact = 0;
@@ -501,8 +795,9 @@ __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts)
 }
 
 extern "C" hipError_t rt_launch_slab_si_wave(const Inst *dinsts, int ninst, int kinds, hipStream_t stream) {
-  if (kinds & 1) hipLaunchKernelGGL(k_si_wave<false>, dim3(ninst), dim3(WNT), 0, stream, dinsts);
-  if (kinds & 2) hipLaunchKernelGGL(k_si_wave<true>, dim3(ninst), dim3(WNT), 0, stream, dinsts);
+  if (kinds & 1) hipLaunchKernelGGL((k_si_wave<false, false>), dim3(ninst), dim3(WNT), 0, stream, dinsts);
+  if (kinds & 2) hipLaunchKernelGGL((k_si_wave<true, false>), dim3(ninst), dim3(WNT), 0, stream, dinsts);
+  if (kinds & 4) hipLaunchKernelGGL((k_si_wave<false, true>), dim3(ninst), dim3(WNT), 0, stream, dinsts);
   return hipGetLastError();
 }
 
@@ -536,7 +831,7 @@ __device__ __forceinline__ int fidx(int c) { return c + (c >> 2); }  // one pad 
 
 __global__ void __launch_bounds__(WNT) k_fpass_wave(const Inst *__restrict__ insts, int rhs_only) {
   const Inst &I = insts[blockIdx.x];
-  if (I.bdf2) return;  // k_fpass_wave_bdf2
+  if (I.bdf2 || I.dg) return;  // k_fpass_wave_bdf2, k_fpass_dg
   __shared__ double big[4 * FROW];  // ct, srcc, G during the sweeps; then the moment rows
   double *ctS = big, *srcS = big + FROW, *gS = big + 2 * FROW;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -886,9 +1181,279 @@ __global__ void __launch_bounds__(WNT) k_fpass_wave_bdf2(const Inst *__restrict_
   }
 }
 
+// ---------------------------------------------------------------------------
+// k_fpass_dg: the f-pass of piecewise-linear DG slabs in k_fpass_wave's
+// layout and order, on unknowns: in block b lane l takes the two cells 128 b
+// + 2 l, 128 b + 2 l + 1, i.e. the four unknowns 256 b + 4 l + k, so the
+// loads of f are those of k_fpass_wave.  A lane composes its two cells' face
+// maps (wave_sweep_dg), the wave scans them, and each cell's unknowns follow
+// from the face value entering it.  First sweep: f^n with source sigma_s
+// rho^n + f^{n-1} / dt + G and inflow g; second: b~^n from f^n / dt + G.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(WNT) k_fpass_dg(const Inst *__restrict__ insts, int rhs_only) {
+  const Inst &I = insts[blockIdx.x];
+  if (!I.dg) return;
+  __shared__ double big[4 * FROW];  // ct, srcc, G during the sweeps; then the moment rows
+  double *ctS = big, *srcS = big + FROW, *gS = big + 2 * FROW;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nc = I.nc, npair = I.npair, nv = I.nv;  // nc: unknowns
+  const int NB = (nc + FB - 1) / FB;
+  const double idt = I.inv_dt;
+  for (int c = tid; c < NB * FB; c += WNT) {
+    const bool in = c < nc;
+    const double g = in ? ldg(&I.G[c]) : 0.0;
+    ctS[fidx(c)] = in ? ldg(&I.ct[c]) : 0.0;
+    gS[fidx(c)] = g;
+    srcS[fidx(c)] = (in && !rhs_only) ? rt_fma(ldg(&I.ss[c]), ldg(&I.rho[c]), g) : 0.0;
+  }
+  __syncthreads();
+  double acc[FNB][FK];
+#pragma unroll
+  for (int b = 0; b < FNB; ++b)
+#pragma unroll
+    for (int k = 0; k < FK; ++k) acc[b][k] = 0.0;
+  const double g0 = I.g[0], g1 = I.g[1];
+  for (int p = wave; p < npair; p += WNW) {
+    const double m = ldg(&I.pm[p]), w = ldg(&I.pw[p]);
+    double *fneg = I.f + (size_t)p * nc;
+    double *fpos = I.f + (size_t)(nv - 1 - p) * nc;
+    double cp1 = g0, cp2 = g0, cn1 = g1, cn2 = g1;
+#pragma unroll
+    for (int s = 0; s < FNB; ++s) {
+      if (s < NB) {
+        const int bp = s, bn = NB - 1 - s;
+        const int cpb = bp * FB + lane * FK, cnb = bn * FB + lane * FK;
+        double fp[FK], fn[FK];
+#pragma unroll
+        for (int k = 0; k < FK; ++k) {
+          fp[k] = cpb + k < nc ? ldg(&fpos[cpb + k]) : 0.0;
+          fn[k] = cnb + k < nc ? ldg(&fneg[cnb + k]) : 0.0;
+        }
+        double cP[2], cN[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          cP[h] = ctS[fidx(cpb + 2 * h)];
+          cN[h] = ctS[fidx(cnb + 2 * h)];
+        }
+        if (!rhs_only) {
+          double sP[FK], sN[FK];
+#pragma unroll
+          for (int k = 0; k < FK; ++k) {
+            sP[k] = rt_fma(fp[k], idt, srcS[fidx(cpb + k)]);
+            sN[k] = rt_fma(fn[k], idt, srcS[fidx(cnb + k)]);
+          }
+          DgCell<double> zp[2], zn[2];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            zp[h] = dg_cell<double>(cP[h], m, sP[2 * h], sP[2 * h + 1]);
+            zn[h] = dg_cell<double>(cN[h], m, sN[2 * h], sN[2 * h + 1]);
+          }
+          const double pf = zp[0].a * zp[1].a, Bf = rt_fma(zp[1].a, zp[0].bf, zp[1].bf);
+          const double pb = zn[0].a * zn[1].a, Bb = rt_fma(zn[0].a, zn[1].bb, zn[0].bb);
+          double inF, inB;
+          wave_scan2<double>(pf, Bf, pb, Bb, cp1, cn1, inF, inB);
+          double f = inF;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            dg_unknowns<double, true>(cP[h], m, sP[2 * h], sP[2 * h + 1], zp[h].q, f, fp[2 * h], fp[2 * h + 1]);
+            f = rt_fma(zp[h].a, f, zp[h].bf);
+          }
+#pragma unroll
+          for (int k = 0; k < FK; ++k)
+            if (cpb + k < nc) stg(&fpos[cpb + k], fp[k]);
+          cp1 = lane_value(f, 63);
+          f = inB;
+#pragma unroll
+          for (int h = 1; h >= 0; --h) {
+            dg_unknowns<double, false>(cN[h], m, sN[2 * h], sN[2 * h + 1], zn[h].q, f, fn[2 * h], fn[2 * h + 1]);
+            f = rt_fma(zn[h].a, f, zn[h].bb);
+          }
+#pragma unroll
+          for (int k = 0; k < FK; ++k)
+            if (cnb + k < nc) stg(&fneg[cnb + k], fn[k]);
+          cn1 = lane_value(f, 0);
+          // cells past the last one: zero sources of the second sweep
+#pragma unroll
+          for (int k = 0; k < FK; ++k) {
+            if (cpb + k >= nc) fp[k] = 0.0;
+            if (cnb + k >= nc) fn[k] = 0.0;
+          }
+        }
+        // second sweep: source f^n / dt + G, the moments of b~^n
+        double sP[FK], sN[FK];
+#pragma unroll
+        for (int k = 0; k < FK; ++k) {
+          sP[k] = rt_fma(fp[k], idt, gS[fidx(cpb + k)]);
+          sN[k] = rt_fma(fn[k], idt, gS[fidx(cnb + k)]);
+        }
+        DgCell<double> zp[2], zn[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          zp[h] = dg_cell<double>(cP[h], m, sP[2 * h], sP[2 * h + 1]);
+          zn[h] = dg_cell<double>(cN[h], m, sN[2 * h], sN[2 * h + 1]);
+        }
+        const double pf = zp[0].a * zp[1].a, Bf = rt_fma(zp[1].a, zp[0].bf, zp[1].bf);
+        const double pb = zn[0].a * zn[1].a, Bb = rt_fma(zn[0].a, zn[1].bb, zn[0].bb);
+        double inF, inB;
+        wave_scan2<double>(pf, Bf, pb, Bb, cp2, cn2, inF, inB);
+        double f = inF;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          dg_unknowns<double, true>(cP[h], m, sP[2 * h], sP[2 * h + 1], zp[h].q, f, fp[2 * h], fp[2 * h + 1]);
+          f = rt_fma(zp[h].a, f, zp[h].bf);
+        }
+        cp2 = lane_value(f, 63);
+        f = inB;
+#pragma unroll
+        for (int h = 1; h >= 0; --h) {
+          dg_unknowns<double, false>(cN[h], m, sN[2 * h], sN[2 * h + 1], zn[h].q, f, fn[2 * h], fn[2 * h + 1]);
+          f = rt_fma(zn[h].a, f, zn[h].bb);
+        }
+        cn2 = lane_value(f, 0);
+#pragma unroll
+        for (int b = 0; b < FNB; ++b) {
+          if (b == bp) {
+#pragma unroll
+            for (int k = 0; k < FK; ++k) acc[b][k] = rt_fma(w, fp[k], acc[b][k]);
+          }
+          if (b == bn) {
+#pragma unroll
+            for (int k = 0; k < FK; ++k) acc[b][k] = rt_fma(w, fn[k], acc[b][k]);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (wave >= WNW / 2) {
+    double *r = big + (wave - WNW / 2) * FROW;
+#pragma unroll
+    for (int b = 0; b < FNB; ++b)
+      if (b < NB)
+#pragma unroll
+        for (int k = 0; k < FK; ++k) r[fidx(b * FB + lane * FK + k)] = acc[b][k];
+  }
+  __syncthreads();
+  if (wave < WNW / 2) {
+    double *r = big + wave * FROW;
+#pragma unroll
+    for (int b = 0; b < FNB; ++b)
+      if (b < NB)
+#pragma unroll
+        for (int k = 0; k < FK; ++k) {
+          const int i = fidx(b * FB + lane * FK + k);
+          r[i] = acc[b][k] + r[i];
+        }
+  }
+  __syncthreads();
+  double *bt_out = rhs_only ? I.bt2[I.st->steps & 1] : I.bt2[I.st->cur ^ 1];
+  for (int c = tid; c < nc; c += WNT) {
+    const int i = fidx(c);
+    stg(&bt_out[c], ((big[i] + big[FROW + i]) + big[2 * FROW + i]) + big[3 * FROW + i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_setup_dsa_dg: the DSA operator of DG slabs and its block elimination.
+// The operator: the correction equation's diffusion limit -(D d')' +
+// sigma~_a d (D = 1/(3 sigma~_t), sigma~_a = sigma_a + 1/dt) in the DG-P1
+// space by the modified interior penalty method -- symmetric interior
+// penalty with kappa = max((D_L + D_R) / h, 1/4) on interior faces and
+// Marshak vacuum faces (1/2 u v) -- divided by h, so that its right-hand
+// side is sigma_s times the unknown-wise residual (the orthonormal basis
+// has mass matrix h I).  Per cell, with e+ = (1, sqrt 3), e- = (1, -sqrt 3)
+// the basis at the right / left end and g = (0, 2 sqrt(3) / h) the
+// derivatives (all terms / h):
+//   D_i = h diag(sa~, sa~ + 12 D_i / h^2)
+//         + [left face]  kappa e- e-^T + (D_i / 2)(g e-^T + e- g^T)   (Marshak: e- e-^T / 2)
+//         + [right face] kappa e+ e+^T - (D_i / 2)(g e+^T + e+ g^T)   (Marshak: e+ e+^T / 2)
+//   L_i = -kappa e- e+^T + (D_{i-1} / 2) e- g^T - (D_i / 2) g e+^T      (row i, column i - 1)
+// Block elimination: S_0 = D_0, S_i = D_i - L_i S_{i-1}^{-1} L_i^T
+// (sequential, one thread), then F_i = -L_i S_{i-1}^{-1} and B_i =
+// -S_i^{-1} L_{i+1}^T.  One workgroup per instance; blocks in LDS.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_setup_dsa_dg(const Inst *__restrict__ insts) {
+  const Inst &I = insts[blockIdx.x];
+  if (!I.dg) return;
+  __shared__ double Dl[4 * RT_DG_MAX_CELLS], Ll[4 * RT_DG_MAX_CELLS], Sl[4 * RT_DG_MAX_CELLS];
+  const int N = I.ncell;
+  const double h = I.hx, r3 = kR3, dd = 2.0 * kR3 / h;
+  double *K = const_cast<double *>(I.dsa_blk);
+  auto Dif = [&](int i) { return 1.0 / (3.0 * ldg(&I.ct[2 * i])); };
+  auto kap = [&](double a, double b) { return fmax((a + b) / h, 0.25); };
+  const double ep[2] = {1.0, r3}, em[2] = {1.0, -r3}, gd[2] = {0.0, dd};
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    const double Di = Dif(i);
+    const double sat = ldg(&I.sa[2 * i]) + I.inv_dt;
+    double A[2][2] = {{sat * h, 0.0}, {0.0, sat * h + 12.0 * Di / h}};
+    const double kl = i > 0 ? kap(Dif(i - 1), Di) : 0.0;
+    const double kr = i < N - 1 ? kap(Di, Dif(i + 1)) : 0.0;
+    for (int r = 0; r < 2; ++r)
+      for (int c = 0; c < 2; ++c) {
+        A[r][c] += i > 0 ? kl * em[r] * em[c] + 0.5 * Di * (gd[r] * em[c] + em[r] * gd[c]) : 0.5 * em[r] * em[c];
+        A[r][c] += i < N - 1 ? kr * ep[r] * ep[c] - 0.5 * Di * (gd[r] * ep[c] + ep[r] * gd[c]) : 0.5 * ep[r] * ep[c];
+        Dl[4 * i + 2 * r + c] = A[r][c] / h;
+        Ll[4 * i + 2 * r + c] =
+            i > 0 ? (-kl * em[r] * ep[c] + 0.5 * Dif(i - 1) * em[r] * gd[c] - 0.5 * Di * gd[r] * ep[c]) / h : 0.0;
+      }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // S_i^{-1}, i = 0..N-1
+    double s00 = Dl[0], s01 = Dl[1], s10 = Dl[2], s11 = Dl[3];
+    for (int i = 0;; ++i) {
+      const double id = 1.0 / (s00 * s11 - s01 * s10);
+      const double i00 = s11 * id, i01 = -s01 * id, i10 = -s10 * id, i11 = s00 * id;
+      Sl[4 * i] = i00;
+      Sl[4 * i + 1] = i01;
+      Sl[4 * i + 2] = i10;
+      Sl[4 * i + 3] = i11;
+      if (i + 1 == N) break;
+      const double *L = Ll + 4 * (i + 1), *D = Dl + 4 * (i + 1);
+      // X = L S^{-1}; S' = D - X L^T
+      const double x00 = L[0] * i00 + L[1] * i10, x01 = L[0] * i01 + L[1] * i11;
+      const double x10 = L[2] * i00 + L[3] * i10, x11 = L[2] * i01 + L[3] * i11;
+      s00 = D[0] - (x00 * L[0] + x01 * L[1]);
+      s01 = D[1] - (x00 * L[2] + x01 * L[3]);
+      s10 = D[2] - (x10 * L[0] + x11 * L[1]);
+      s11 = D[3] - (x10 * L[2] + x11 * L[3]);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    const double *S = Sl + 4 * i;
+    double F[4] = {0.0, 0.0, 0.0, 0.0}, B[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i > 0) {  // F_i = -L_i S_{i-1}^{-1}
+      const double *L = Ll + 4 * i, *P = Sl + 4 * (i - 1);
+      F[0] = -(L[0] * P[0] + L[1] * P[2]);
+      F[1] = -(L[0] * P[1] + L[1] * P[3]);
+      F[2] = -(L[2] * P[0] + L[3] * P[2]);
+      F[3] = -(L[2] * P[1] + L[3] * P[3]);
+    }
+    if (i + 1 < N) {  // B_i = -S_i^{-1} L_{i+1}^T
+      const double *L = Ll + 4 * (i + 1);
+      B[0] = -(S[0] * L[0] + S[1] * L[1]);
+      B[1] = -(S[0] * L[2] + S[1] * L[3]);
+      B[2] = -(S[2] * L[0] + S[3] * L[1]);
+      B[3] = -(S[2] * L[2] + S[3] * L[3]);
+    }
+    for (int k = 0; k < 4; ++k) {
+      K[k * N + i] = F[k];
+      K[(4 + k) * N + i] = S[k];
+      K[(8 + k) * N + i] = B[k];
+    }
+  }
+}
+
+extern "C" hipError_t rt_launch_setup_dsa_dg(const Inst *dinsts, int ninst, hipStream_t stream) {
+  hipLaunchKernelGGL(k_setup_dsa_dg, dim3(ninst), dim3(256), 0, stream, dinsts);
+  return hipGetLastError();
+}
+
 extern "C" hipError_t rt_launch_slab_fpass_wave(const Inst *dinsts, int ninst, int rhs_only, int kinds,
                                                 hipStream_t stream) {
   if (kinds & 1) hipLaunchKernelGGL(k_fpass_wave, dim3(ninst), dim3(WNT), 0, stream, dinsts, rhs_only);
   if (kinds & 2) hipLaunchKernelGGL(k_fpass_wave_bdf2, dim3(ninst), dim3(WNT), 0, stream, dinsts, rhs_only);
+  if (kinds & 4) hipLaunchKernelGGL(k_fpass_dg, dim3(ninst), dim3(WNT), 0, stream, dinsts, rhs_only);
   return hipGetLastError();
 }

@@ -21,6 +21,7 @@ METHOD = {"si_dsa": 0, "rom": 1, "si": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
 PRECOND = {"dsa": 0, "mh": 1}
 TIME_SCHEME = {"be": 0, "bdf2": 1}
+SCHEME = {"fv": 0, "dg1": 1}
 F_ABS_UP_NORM = 0x1
 F_SINGLE_WG = 0x2
 
@@ -40,6 +41,7 @@ class Desc(ctypes.Structure):
         ("r_max", ctypes.c_int32), ("flags", ctypes.c_uint64),
         ("precond", ctypes.c_int32), ("time_scheme", ctypes.c_int32),
         ("pc_levels", ctypes.c_int32), ("mh_rank", ctypes.c_int32),
+        ("scheme", ctypes.c_int32),
     ]
 
 
@@ -178,6 +180,7 @@ def make_desc(spec, keep: list) -> Desc:
     d.time_scheme = TIME_SCHEME[spec.time_scheme]
     d.pc_levels = int(spec.pc_levels)
     d.mh_rank = int(spec.mh_rank)
+    d.scheme = SCHEME[spec.scheme]
     return d
 
 
@@ -214,7 +217,7 @@ class Problem:
         h = ctypes.c_void_p()
         _check(lib().rtrom_create_problem(ctypes.byref(d), ctypes.byref(h)))
         self.h = h
-        self.nc = spec.nx * spec.ny
+        self.nc = spec.nx * spec.ny * (2 if spec.scheme == "dg1" else 1)  # unknowns of rho
         self.nv = spec.nord
 
     # -- marching ----------------------------------------------------------
