@@ -46,6 +46,10 @@ VALU_PEAK_TFLOPS = 78.6     # MI355X FP64 vector; FP32 without packed math issue
 # moment accumulation: 1D  f = (s + m f_in) / (ct + m), rho += w f
 #                       2D  f = (s + mx f_l + my f_b) / (ct + mx + my), rho += w f
 SWEEP_FLOPS = {1: 6, 2: 8}
+# 1D piecewise-linear DG: per cell-angle the 2x2 upwind solve (determinant,
+# two right-hand sides, two unknowns), the outflow value and two moment
+# updates, 22 FLOPs, i.e. 11 per unknown-angle update
+SWEEP_FLOPS_DG1 = 11
 # algorithmic HBM bytes (FP64):
 FPASS_BYTES_PER_CELL_ANGLE = 16   # f^{n-1} read, f^n written
 FPASS_BYTES_PER_CELL = 40         # sigma_t, sigma_s, rho^n, G read; b~^n written
@@ -89,12 +93,12 @@ def kernel_table(prof, fpass_bytes, si_bytes, rom_bytes):
     return out
 
 
-def roofline_sweep(prof, kind, dim, updates, kernel):
+def roofline_sweep(prof, kind, dim, updates, kernel, flops_per_update=None):
     """The SI sweep kernel is bound by the vector ALU: FLOP rate of its
     cell-angle updates (algorithmic FLOPs / event-timed launch duration)
     against the FP64 vector peak."""
     sec, launches = prof[kind]
-    flops = SWEEP_FLOPS[dim] * updates
+    flops = (SWEEP_FLOPS[dim] if flops_per_update is None else flops_per_update) * updates
     ach = flops / sec / 1e12
     return {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": ach / VALU_PEAK_TFLOPS, "traffic": None, "kernel": kernel, "kind": kind,
@@ -130,6 +134,7 @@ KERNEL_SOURCES = {
     "k_si_slab": ["rt_slab.hip", "rt_common.h", "rt_rom.h", "rt_arrow.h", "rt_capi.hip"],
     "k_si_wave": ["rt_wave.hip", "rt_common.h", "rt_rom.h", "rt_dsa.h", "rt_mh.h", "rt_arrow.h"],
     "k_fpass_wave": ["rt_wave.hip", "rt_common.h"],
+    "k_fpass_dg": ["rt_wave.hip", "rt_common.h"],
     "k_rom_post_small": ["rt_rom.hip", "rt_rom.h", "rt_arrow.h", "rt_common.h"],
     "k_plane_sweep": ["rt_plane.hip", "rt_common.h"],
 }
@@ -225,8 +230,19 @@ def window_updates(probs, ca, first, steps):
     return si_upd, rom_cell_cols
 
 
-def bench_batch(rtrom, W, args):
+def dg_half(s):
+    """The instance in piecewise-linear DG form (Sec. 2.1 eq. DG, K = 1) on
+    half its cells (every other cell's data, the same slab): as many
+    unknowns as the finite-volume instance."""
+    return s.replace(scheme="dg1", nx=(s.nx + 1) // 2, sigma_s=s.sigma_s[::2].copy(),
+                     sigma_a=s.sigma_a[::2].copy(), source=s.source[::2].copy(),
+                     f0=None if s.f0 is None else s.f0[::2].copy())
+
+
+def bench_batch(rtrom, W, args, dg=False):
     specs = W.slab_batch()
+    if dg:
+        specs = [dg_half(s) for s in specs]
     cfg_steps = specs[0].nsteps
     steps = cfg_steps if args.steps is None else args.steps
     warm = 5 if args.warmup is None else args.warmup
@@ -255,9 +271,9 @@ def bench_batch(rtrom, W, args):
     # steps (every instance has at most 2048 cells: the wave-per-pair kernels)
     dom = max(("slab_si", "slab_fpass", "post"), key=lambda k: R["prof"].get(k, (0.0, 0))[0])
     if dom == "slab_si":
-        roof = roofline_sweep(R["prof"], "slab_si", 1, R["si_upd"], "k_si_wave")
+        roof = roofline_sweep(R["prof"], "slab_si", 1, R["si_upd"], "k_si_wave", SWEEP_FLOPS_DG1 if dg else None)
     elif dom == "slab_fpass":
-        roof = roofline_hbm(R["prof"], "slab_fpass", fpass_bytes, "k_fpass_wave")
+        roof = roofline_hbm(R["prof"], "slab_fpass", fpass_bytes, "k_fpass_dg" if dg else "k_fpass_wave")
     else:
         roof = roofline_hbm(R["prof"], "post", rom_bytes, "k_rom_post_small")
     # the whole configured march of both methods, on fresh problems
@@ -281,16 +297,20 @@ def bench_batch(rtrom, W, args):
     # has at most 2048 cells): the McClarren-Haut preconditioner alone and as
     # the hybrid with the ROM method (Sec. 3.3, 4.5), sequential correction
     # ROMs for iterations 1-2 (Sec. 3.2), BDF2 (Sec. 2.1) for both methods,
-    # and the FP64 mode of both methods
+    # the FP64 mode of both methods, and the piecewise-linear DG scheme on
+    # every instance (dg_half)
     variants = {}
     for name, method, kw in (("si_mh", "si_dsa", dict(precond="mh")), ("rom_mh_hybrid", "rom", dict(precond="mh")),
                              ("rom_levels2", "rom", dict(pc_levels=2)),
                              ("si_dsa_bdf2", "si_dsa", dict(time_scheme="bdf2")),
                              ("rom_bdf2", "rom", dict(time_scheme="bdf2")),
-                             ("si_dsa_fp64", "si_dsa", dict(precision="fp64")), ("rom_fp64", "rom", dict(precision="fp64"))):
-        if args.no_variants:
+                             ("si_dsa_fp64", "si_dsa", dict(precision="fp64")), ("rom_fp64", "rom", dict(precision="fp64")),
+                             ("si_dsa_dg1", "si_dsa", dict(scheme="dg1")), ("rom_dg1", "rom", dict(scheme="dg1"))):
+        if args.no_variants or dg:
             break
-        ms = [s.replace(method=method, **kw) for s in specs]
+        ms = [s.replace(method=method, **{k: v for k, v in kw.items() if k != "scheme"}) for s in specs]
+        if kw.get("scheme") == "dg1":
+            ms = [dg_half(s) for s in ms]
         log(f"bench: batch512 variant {name}: full {cfg_steps}-step march")
         t, probs, _ = timed_batch(rtrom, ms, 0, cfg_steps, profile=False)
         hist = [p.history() for p in probs]
@@ -301,7 +321,8 @@ def bench_batch(rtrom, W, args):
         for p in probs:
             p.close()
     if variants:
-        for a, b in (("rom_bdf2", "si_dsa_bdf2"), ("rom_fp64", "si_dsa_fp64"), ("rom_mh_hybrid", "si_mh")):
+        for a, b in (("rom_bdf2", "si_dsa_bdf2"), ("rom_fp64", "si_dsa_fp64"), ("rom_mh_hybrid", "si_mh"),
+                     ("rom_dg1", "si_dsa_dg1")):
             variants[f"{a}_vs_{b}"] = variants[a]["instance_steps_per_s"] / variants[b]["instance_steps_per_s"]
     extra = {
         "si_dsa_instance_steps_per_s": si_val,
@@ -314,8 +335,10 @@ def bench_batch(rtrom, W, args):
         "full_march": full,
         "variants": variants,
     }
-    config = {"workload": "batch512_slabs", "instances": n, "steps": steps, "timed_steps": f"{warm + 1}..{warm + steps}",
-              "cells": "128..2048", "ordinates": "16/32/64", "dt": 0.01, "tol": 1e-8,
+    config = {"workload": "batch512_slabs_dg1" if dg else "batch512_slabs", "instances": n, "steps": steps,
+              "timed_steps": f"{warm + 1}..{warm + steps}",
+              "cells": "64..1024 (DG-P1, two unknowns each)" if dg else "128..2048", "ordinates": "16/32/64",
+              "dt": 0.01, "tol": 1e-8,
               "method": "rom_si_dsa", "precision": "fp32 sweeps + fp64 refinement",
               "baseline_method": "si_dsa, same kernels and precision"}
     metric = "instance time steps/s (ROM-SI-DSA, 1e-8 rel tol)"
@@ -508,7 +531,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the configured march)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps before them (default 5)")
-    ap.add_argument("--workload", choices=("batch512", "slab4096", "checker256", "serving"), default="batch512")
+    ap.add_argument("--workload", choices=("batch512", "batch512_dg", "slab4096", "checker256", "serving"),
+                    default="batch512")
     ap.add_argument("--requests", type=int, default=24, help="serving: requests in the stream")
     ap.add_argument("--budget-gib", type=float, default=4.0, help="serving: HBM admission budget")
     ap.add_argument("--slots", type=int, default=8, help="serving: concurrent problems")
@@ -528,8 +552,8 @@ def main():
 
     if args.copy_probe > 0:
         copy_probe(args.copy_probe)
-    if args.workload == "batch512":
-        r = bench_batch(rtrom, W, args)
+    if args.workload in ("batch512", "batch512_dg"):
+        r = bench_batch(rtrom, W, args, dg=args.workload == "batch512_dg")
     elif args.workload == "serving":
         r = bench_serving(rtrom, W, args)
     else:
@@ -537,7 +561,7 @@ def main():
     metric, unit, value, t_timed, steps, warm, config, roof, extra, cpu = r
     if roof is not None:
         wl_name = {"slab4096_gl64_32regions": "slab4096", "checkerboard256_cl16x8": "checker256",
-                   "batch512_slabs": "batch512"}.get(config.get("workload"), "")
+                   "batch512_slabs": "batch512", "batch512_slabs_dg1": "batch512_dg"}.get(config.get("workload"), "")
         roof["traffic"] = stored_traffic(roof["kernel"], wl_name)
     out = {
         "metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warm,
