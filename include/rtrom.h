@@ -56,8 +56,10 @@ typedef enum {
 typedef enum {
   RTROM_FP64 = 0,  /* every sweep in FP64 */
   RTROM_MIXED = 1  /* SI increments swept in FP32, accumulated in FP64; the
-                      stop test is re-checked on an FP64 sweep before a step
-                      is accepted.  f, b~, rho and all ROM work stay FP64. */
+                      stop test runs at tol / 16 and is re-checked on an FP64
+                      sweep before a step is accepted (DG-P1: also on the
+                      step to the next DSA-corrected iterate).  f, b~, rho
+                      and all ROM work stay FP64. */
 } rtrom_precision;
 
 /* Correction applied where Alg. 1 uses DSA. */
@@ -212,14 +214,16 @@ rtrom_status rtrom_march_batch(rtrom_problem *const *ps, int32_t n, int32_t nste
 rtrom_status rtrom_march_batch_noalloc(rtrom_problem *const *ps, int32_t n, int32_t nsteps);
 
 /* rho^n (the converged density of the last step, Alg. 1's returned iterate),
- * n >= nx*ny doubles. */
+ * n >= the number of unknowns: nx*ny, or 2*nx for RTROM_DG1 (per cell the
+ * average, then the slope coefficient). */
 rtrom_status rtrom_get_scalar_flux(const rtrom_problem *p, double *rho, int64_t n);
 
-/* f^n, [ordinate][cell] with the ordinate order of rtrom_get_quadrature,
- * n >= n_ord * nx * ny doubles. */
+/* f^n, [ordinate][unknown] with the ordinate order of rtrom_get_quadrature,
+ * n >= n_ord * unknowns doubles. */
 rtrom_status rtrom_get_angular_flux(const rtrom_problem *p, double *f, int64_t n);
 
-/* Right-hand side b~ of the next step (eq. implicit_linear_system_rho). */
+/* Right-hand side b~ of the next step (eq. implicit_linear_system_rho),
+ * n >= unknowns doubles. */
 rtrom_status rtrom_get_rhs(const rtrom_problem *p, double *b, int64_t n);
 
 /* Quadrature used by the problem: n >= n_ord doubles each (oy, oz may be NULL
@@ -312,7 +316,7 @@ rtrom_status rtrom_server_submit(rtrom_server *s, const rtrom_problem_desc *d,
 rtrom_status rtrom_server_poll(rtrom_server *s, uint64_t ticket, int32_t *state);
 /* Blocks until every submitted request has finished. */
 rtrom_status rtrom_server_drain(rtrom_server *s);
-/* Copies out a finished request's rho (n >= cells), stats, per-step latencies
+/* Copies out a finished request's rho (n >= its unknowns), stats, per-step latencies
  * (seconds, up to nlat) and its march latency from admission to completion,
  * then forgets the ticket.  EBUSY if not finished; a failed request returns
  * its error.  Returns ENOCONV when some step hit max_iter (R8). */

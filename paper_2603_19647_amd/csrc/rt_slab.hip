@@ -962,11 +962,13 @@ __global__ void __launch_bounds__(1024) k_setup_dsa_slab(const Inst *__restrict_
     bg[i] = (i < nc - 1) ? -kr / h : 0.0;  // up_i for now
   }
   __syncthreads();
-  // pivots d'_i = diag_i - lo_i up_{i-1} / d'_{i-1} (sequential recurrence)
+  // pivots d'_i = diag_i - lo_i up_{i-1} / d'_{i-1} (sequential recurrence;
+  // the reciprocal of rt_rcp keeps the chain short: a prefix-product form of
+  // the recurrence loses accuracy where the matrix is barely dominant)
   if (threadIdx.x == 0) {
     double dp = diag[0];
     for (int i = 1; i < nc; ++i) {
-      dp = diag[i] - q[i] / dp;
+      dp = rt_fma(-q[i], rt_rcp(dp), diag[i]);
       diag[i] = dp;
     }
   }

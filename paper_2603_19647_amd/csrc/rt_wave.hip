@@ -628,8 +628,14 @@ __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts)
     }
     if (nsweep >= I.max_iter) break;
     if constexpr (MH) {
-      // the pair of this iteration: (rho^{(l-1)} - rho^{(l-2)}, y_l - y_{l-1})
-      if (nsweep >= 2) {
+      // the pair of this iteration: (rho^{(l-1)} - rho^{(l-2)}, y_l - y_{l-1}).
+      // Mixed precision: y_l - y_{l-1} is the image of the input difference
+      // only along one chain of FP32 increments; a y_l recomputed by an FP64
+      // sweep (the certification) replaces the accumulated value, and its
+      // difference to the accumulated y_{l-1} would carry that chain's
+      // rounding drift, not T Sigma_s x.  Such an iteration starts a new
+      // chain instead of adding a pair.
+      if (nsweep >= 2 && !(mixed && exact)) {
         double x[WOWN], z[WOWN];
 #pragma unroll
         for (int t = 0; t < WOWN; ++t) {
@@ -858,9 +864,10 @@ __global__ void __launch_bounds__(WNT) k_fpass_wave(const Inst *__restrict__ ins
     double *fneg = I.f + (size_t)p * nc;               // mu < 0: swept downwards
     double *fpos = I.f + (size_t)(nv - 1 - p) * nc;    // mu > 0: swept upwards
     double cp1 = g0, cp2 = g0, cn1 = g1, cn2 = g1;     // values entering the next block
-#pragma unroll
-    for (int s = 0; s < FNB; ++s) {
-      if (s < NB) {
+    // one block at a time: unrolled, the blocks' live ranges overlap (248 VGPRs, spills)
+#pragma unroll 1
+    for (int s = 0; s < NB; ++s) {
+      {
         const int bp = s, bn = NB - 1 - s;
         const int cpb = bp * FB + lane * FK, cnb = bn * FB + lane * FK;
         double fp[FK], fn[FK], ip[FK], in_[FK];
@@ -1033,7 +1040,8 @@ __global__ void __launch_bounds__(WNT) k_fpass_wave_bdf2(const Inst *__restrict_
     const double m = ldg(&I.pm[p]), w = ldg(&I.pw[p]);
     const size_t on = (size_t)p * nc, op = (size_t)(nv - 1 - p) * nc;  // mu < 0, mu > 0
     double cp1 = g0, cp2 = g0, cn1 = g1, cn2 = g1;  // values entering the next block
-#pragma unroll
+    // one block at a time: unrolled, the blocks' live ranges overlap (248 VGPRs, spills)
+#pragma unroll 1
     for (int s = 0; s < FNB; ++s) {
       if (s < NB) {
         const int bp = s, bn = NB - 1 - s;
@@ -1218,9 +1226,10 @@ __global__ void __launch_bounds__(WNT) k_fpass_dg(const Inst *__restrict__ insts
     double *fneg = I.f + (size_t)p * nc;
     double *fpos = I.f + (size_t)(nv - 1 - p) * nc;
     double cp1 = g0, cp2 = g0, cn1 = g1, cn2 = g1;
-#pragma unroll
-    for (int s = 0; s < FNB; ++s) {
-      if (s < NB) {
+    // one block at a time: unrolled, the blocks' live ranges overlap (248 VGPRs, spills)
+#pragma unroll 1
+    for (int s = 0; s < NB; ++s) {
+      {
         const int bp = s, bn = NB - 1 - s;
         const int cpb = bp * FB + lane * FK, cnb = bn * FB + lane * FK;
         double fp[FK], fn[FK];
@@ -1402,7 +1411,7 @@ __global__ void __launch_bounds__(256) k_setup_dsa_dg(const Inst *__restrict__ i
     // S_i^{-1}, i = 0..N-1
     double s00 = Dl[0], s01 = Dl[1], s10 = Dl[2], s11 = Dl[3];
     for (int i = 0;; ++i) {
-      const double id = 1.0 / (s00 * s11 - s01 * s10);
+      const double id = rt_rcp(s00 * s11 - s01 * s10);
       const double i00 = s11 * id, i01 = -s01 * id, i10 = -s10 * id, i11 = s00 * id;
       Sl[4 * i] = i00;
       Sl[4 * i + 1] = i01;

@@ -349,7 +349,7 @@ class Server:
 
     def fetch(self, ticket: int):
         spec, n = self._specs[ticket]
-        rho = np.zeros(spec.nx * spec.ny)
+        rho = np.zeros(spec.nx * spec.ny * (2 if spec.scheme == "dg1" else 1))  # unknowns
         lat = np.zeros(max(n, 1))
         mlat = ctypes.c_double()
         st = Stats()

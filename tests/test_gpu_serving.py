@@ -24,6 +24,7 @@ def _requests():
                                             (40, (16, 8), 6)])]
     reqs.append(W.random_slab(3, 300, 16, method="rom", precision="mixed", nsteps=15))
     reqs.append(W.random_plane(4, 24, 8, 4, method="rom", precision="fp64", nsteps=10))
+    reqs.append(W.random_slab(6, 200, 8, method="rom", precision="mixed", scheme="dg1", nsteps=12))
     return reqs
 
 
