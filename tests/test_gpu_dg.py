@@ -32,10 +32,11 @@ def _bar(spec, n):
 
 
 @pytest.mark.parametrize("method", ["si_dsa", "rom"])
-@pytest.mark.parametrize("nx,nv", [(5, 4), (64, 8), (129, 16), (300, 32), (1024, 64), (700, 256)])
+@pytest.mark.parametrize("nx,nv", [(1, 2), (2, 4), (5, 4), (64, 8), (129, 16), (300, 32), (1024, 64), (700, 256)])
 def test_dg_fp64_matches_oracle(method, nx, nv):
     """Sizes across the sweep row classes (up to 16 cells per lane run), a
-    ragged last run, the largest DG slab and the most ordinate pairs."""
+    ragged last run, the largest DG slab, the most ordinate pairs, and the
+    degenerate slabs of one and two cells (both faces vacuum boundaries)."""
     spec = W.random_slab(70 + nx, nx, nv, dt=0.02, tol=1e-8, method=method, scheme="dg1",
                          inflow=(0.8, 0.3, 0.0, 0.0), nsteps=25)
     n = spec.nsteps

@@ -43,6 +43,20 @@ def test_noalloc_batch_equals_allocating_batch_two_calls():
     _compare(small, 20)
 
 
+def test_noalloc_dg_and_variant_instances():
+    """Instances of every device configuration in one allocation-free batch:
+    piecewise-linear DG, McClarren-Haut, BDF2 and correction ROMs beside a
+    default instance."""
+    specs = [W.random_slab(95, 300, 16, method="rom", precision="mixed", scheme="dg1"),
+             W.random_slab(96, 200, 8, method="rom", precision="fp64", precond="mh"),
+             W.random_slab(97, 500, 32, method="rom", precision="mixed", time_scheme="bdf2"),
+             W.random_slab(98, 250, 16, method="rom", precision="fp64", pc_levels=2),
+             W.random_slab(99, 1024, 64, method="si_dsa", precision="mixed", scheme="dg1"),
+             W.random_slab(100, 640, 16, method="rom", precision="mixed")]
+    say("noalloc batch of the configurations, 25 steps")
+    _compare(specs, 25)
+
+
 def test_noalloc_limits():
     specs = _specs(90, [(100, 16, "si_dsa", "fp64"), (120, 16, "si_dsa", "fp64")])
     probs = [rtrom.Problem(s) for s in specs]
