@@ -91,8 +91,7 @@ typedef enum {
                     orthonormal basis 1, sqrt(3) xi), so rho, f and b~ hold
                     2 nx values per ordinate, cell-major; DSA by the modified
                     interior-penalty discretisation of the correction's
-                    diffusion limit.  Slabs of at most 1024 cells, with DSA
-                    and backward Euler. */
+                    diffusion limit.  Slabs of at most 1024 cells. */
 } rtrom_scheme;
 
 /* flags */

@@ -249,8 +249,6 @@ static rtrom_status validate(const rtrom_problem_desc *d) {
   if (d->scheme == RTROM_DG1) {
     if (d->dim != 1) return fail(RTROM_EINVAL, "the DG-P1 scheme runs on slabs only");
     if (d->nx > RT_DG_MAX_CELLS) return fail(RTROM_EINVAL, "DG-P1 slabs are limited to 1024 cells");
-    if (d->precond != RTROM_PC_DSA || d->time_scheme != RTROM_BE)
-      return fail(RTROM_EINVAL, "DG-P1 slabs run with DSA and backward Euler");
   }
   return RTROM_OK;
 }
@@ -364,6 +362,7 @@ static size_t slab_bytes(const rtrom_problem_desc *d, int nv) {
       L.take((size_t)mh_cap_of(d) * ld * 8);
     }
     if (d->scheme == RTROM_DG1) L.take(12 * (size_t)d->nx * 8);  // block DSA factors
+    if (d->scheme == RTROM_DG1 && d->time_scheme == RTROM_BDF2) L.take(12 * (size_t)d->nx * 8);  // of BDF2
     int ng, pg;
     slab_groups(d, nv, &ng, &pg);
     if (ng > 1) {
@@ -403,7 +402,7 @@ static size_t slab_bytes(const rtrom_problem_desc *d, int nv) {
 static hipError_t slab_rhs(rtrom_problem *p) {
   const Inst &I = p->hinst;
   if (p->nc <= RT_WAVE_MAX_CELLS)
-    return rt_launch_slab_fpass_wave(p->dinst, 1, 1, I.dg ? 4 : (I.bdf2 ? 2 : 1), p->stream);
+    return rt_launch_slab_fpass_wave(p->dinst, 1, 1, I.dg ? (I.bdf2 ? 16 : 4) : (I.bdf2 ? 2 : 1), p->stream);
   int cmax;
   const int nt = slab_launch_threads(&I.nthr, &p->nc, 1, &cmax);
   return rt_launch_slab_rhs(p->dinst, 1, nt, cmax, I.npair, p->nc, p->stream);
@@ -545,6 +544,7 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
     I.mhZ = D((size_t)I.mh_cap * ld * 8);
   }
   if (d->dim == 1 && d->scheme == RTROM_DG1) I.dsa_blk = D(12 * (size_t)ncell * 8);
+  if (d->dim == 1 && d->scheme == RTROM_DG1 && d->time_scheme == RTROM_BDF2) I.dsa_blk_b = D(12 * (size_t)ncell * 8);
   I.dg = d->scheme == RTROM_DG1;
   I.ncell = ncell;
   slab_groups(d, nv, &I.ng, &I.pg);
@@ -663,7 +663,7 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   std::vector<double> h_ctb;
   if (ctb) {  // the BDF2 operator: sigma_t + 3 / (2 dt)
     h_ctb.resize(nc);
-    for (int i = 0; i < nc; ++i) h_ctb[i] = d->sigma_s[i] + d->sigma_a[i] + 1.5 / d->dt;
+    for (int u = 0; u < nc; ++u) h_ctb[u] = h_ss[u] + h_sa[u] + 1.5 / d->dt;
     ok = ok && H2D(ctb, h_ctb.data(), nc * 8);
   }
   std::vector<double> rho0(nc, 0.0);
@@ -684,13 +684,11 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   }
   if (d->dim == 1) {
     if (upload_inst(p) != RTROM_OK) return bail(RTROM_EDEVICE, "upload descriptor failed");
-    if (I.dg) {
-      if (rt_launch_setup_dsa_dg(p->dinst, 1, p->stream) != hipSuccess) return bail(RTROM_EDEVICE, "setup launch failed");
-    } else if (rt_launch_slab_setup(p->dinst, 1, nc, 0, p->stream) != hipSuccess) {
-      return bail(RTROM_EDEVICE, "setup launch failed");
+    for (int alt = 0; alt <= (I.bdf2 ? 1 : 0); ++alt) {  // alt: the BDF2 operator's factors
+      const hipError_t e = I.dg ? rt_launch_setup_dsa_dg(p->dinst, 1, alt, p->stream)
+                                : rt_launch_slab_setup(p->dinst, 1, nc, alt, p->stream);
+      if (e != hipSuccess) return bail(RTROM_EDEVICE, "setup launch failed");
     }
-    if (I.bdf2 && rt_launch_slab_setup(p->dinst, 1, nc, 1, p->stream) != hipSuccess)
-      return bail(RTROM_EDEVICE, "setup launch failed");
     if (slab_rhs(p) != hipSuccess) return bail(RTROM_EDEVICE, "initial RHS launch failed");
   } else {
     if (upload_inst(p) != RTROM_OK) return bail(RTROM_EDEVICE, "upload descriptor failed");
@@ -834,7 +832,8 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
     while (nA < n && ncs[nA] > RT_WAVE_MAX_CELLS) ++nA;
     struct Group {
       int off, cnt, nt, cmax, nc_max, npair_max, pairs_total, wave;
-      int si_kinds, fp_kinds;  // wave kernels: bit 0 default instances, bit 1 variants (MH; BDF2), bit 2 DG
+      int si_kinds, fp_kinds;  // wave kernels: bit 0 default instances, bit 1 variants (MH; BDF2), bit 2 DG,
+                               // bit 3 DG with McClarren-Haut (SI only), bit 4 DG with BDF2 (f-pass only)
     };
     std::vector<Group> groups;
     for (int g = 0; g < 2; ++g) {
@@ -845,8 +844,9 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
         G.nc_max = std::max(G.nc_max, ncs[i]);
         G.npair_max = std::max(G.npair_max, ps[i]->hinst.npair);
         G.pairs_total += ps[i]->hinst.npair;
-        G.si_kinds |= ps[i]->hinst.dg ? 4 : (ps[i]->hinst.precond == RT_PC_MH ? 2 : 1);
-        G.fp_kinds |= ps[i]->hinst.dg ? 4 : (ps[i]->hinst.bdf2 ? 2 : 1);
+        const bool mh = ps[i]->hinst.precond == RT_PC_MH;
+        G.si_kinds |= ps[i]->hinst.dg ? (mh ? 8 : 4) : (mh ? 2 : 1);
+        G.fp_kinds |= ps[i]->hinst.dg ? (ps[i]->hinst.bdf2 ? 16 : 4) : (ps[i]->hinst.bdf2 ? 2 : 1);
       }
       groups.push_back(G);
     }

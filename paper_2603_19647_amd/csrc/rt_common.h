@@ -161,6 +161,7 @@ struct Inst {
   // row-major.
   int dg, ncell;
   const double *dsa_blk;
+  const double *dsa_blk_b;  // DG with BDF2: the same for the BDF2 operator
 };
 
 enum { RT_SI_DSA = 0, RT_ROM = 1, RT_SI_PLAIN = 2 };

@@ -48,12 +48,14 @@ extern "C" hipError_t rt_launch_slab_rhs(const Inst *dinsts, int ninst, int nthr
                                          int nc_max, hipStream_t stream);
 // kinds: bit 0 -- the launch holds instances of the default configuration,
 // bit 1 -- instances of the variant (SI: McClarren-Haut; f-pass: BDF2),
-// bit 2 -- piecewise-linear DG instances
+// bit 2 -- piecewise-linear DG instances, bit 3 -- DG instances with
+// McClarren-Haut (SI launch only), bit 4 -- DG instances with BDF2 (f-pass
+// only)
 extern "C" hipError_t rt_launch_slab_si_wave(const Inst *dinsts, int ninst, int kinds, hipStream_t stream);
 extern "C" hipError_t rt_launch_slab_fpass_wave(const Inst *dinsts, int ninst, int rhs_only, int kinds,
                                                 hipStream_t stream);
 extern "C" hipError_t rt_launch_slab_setup(const Inst *dinsts, int ninst, int nc_max, int alt, hipStream_t stream);
-extern "C" hipError_t rt_launch_setup_dsa_dg(const Inst *dinsts, int ninst, hipStream_t stream);
+extern "C" hipError_t rt_launch_setup_dsa_dg(const Inst *dinsts, int ninst, int alt, hipStream_t stream);
 extern "C" hipError_t rt_launch_gather_states(const Inst *dinsts, int ninst, RtState *out, hipStream_t stream);
 
 // 2D

@@ -348,10 +348,10 @@ __device__ __forceinline__ void wg_scan_blk(Blk2 M, double &in0, double &in1, do
 // d = C^{-1} rhs for the thread's unknowns [c0, c0 + n) (whole cells, n even)
 template <int CMAX>
 __device__ __forceinline__ void dsa_solve_dg(const Inst &I, int c0, int n, const double (&rhs)[CMAX],
-                                             double (&d)[CMAX], double *slots, int &parity) {
+                                             double (&d)[CMAX], double *slots, int &parity, bool alt = false) {
   constexpr int NCL = CMAX / 2;
   const int N = I.ncell, i0 = c0 / 2, ncl = n / 2;
-  const double *__restrict__ K = I.dsa_blk;
+  const double *__restrict__ K = alt ? I.dsa_blk_b : I.dsa_blk;
 #pragma unroll
   for (int k = 0; k < CMAX; ++k) d[k] = 0.0;
   Blk2 fw[NCL];
@@ -612,7 +612,7 @@ __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts)
         double rhs[WOWN], dd[WOWN];
 #pragma unroll
         for (int t = 0; t < WOWN; ++t) rhs[t] = ss[t] * (y[t] - rp[t]);
-        if constexpr (DG) dsa_solve_dg<WOWN>(I, c0, n, rhs, dd, slots, parity);
+        if constexpr (DG) dsa_solve_dg<WOWN>(I, c0, n, rhs, dd, slots, parity, alt);
         double el = 0.0;
 #pragma unroll
         for (int t = 0; t < WOWN; ++t)
@@ -707,7 +707,7 @@ __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts)
       double rhs[WOWN];
 #pragma unroll
       for (int t = 0; t < WOWN; ++t) rhs[t] = ss[t] * (y[t] - rp[t]);
-      if constexpr (DG) dsa_solve_dg<WOWN>(I, c0, n, rhs, d, slots, parity);
+      if constexpr (DG) dsa_solve_dg<WOWN>(I, c0, n, rhs, d, slots, parity, alt);
       else dsa_solve_slab<WOWN>(I, c0, n, rhs, d, slots, parity, alt);
     }
     first_corr = 0;
@@ -804,6 +804,7 @@ extern "C" hipError_t rt_launch_slab_si_wave(const Inst *dinsts, int ninst, int 
   if (kinds & 1) hipLaunchKernelGGL((k_si_wave<false, false>), dim3(ninst), dim3(WNT), 0, stream, dinsts);
   if (kinds & 2) hipLaunchKernelGGL((k_si_wave<true, false>), dim3(ninst), dim3(WNT), 0, stream, dinsts);
   if (kinds & 4) hipLaunchKernelGGL((k_si_wave<false, true>), dim3(ninst), dim3(WNT), 0, stream, dinsts);
+  if (kinds & 8) hipLaunchKernelGGL((k_si_wave<true, true>), dim3(ninst), dim3(WNT), 0, stream, dinsts);
   return hipGetLastError();
 }
 
@@ -1005,7 +1006,7 @@ __global__ void __launch_bounds__(WNT) k_fpass_wave(const Inst *__restrict__ ins
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(WNT) k_fpass_wave_bdf2(const Inst *__restrict__ insts, int rhs_only) {
   const Inst &I = insts[blockIdx.x];
-  if (!I.bdf2) return;
+  if (!I.bdf2 || I.dg) return;
   __shared__ double big[4 * FROW];  // ct (solve), ct (rhs), srcc, G; then the moment rows
   double *ctS = big, *srcS = big + FROW, *gS = big + 2 * FROW, *ct2S = big + 3 * FROW;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1200,7 +1201,7 @@ __global__ void __launch_bounds__(WNT) k_fpass_wave_bdf2(const Inst *__restrict_
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(WNT) k_fpass_dg(const Inst *__restrict__ insts, int rhs_only) {
   const Inst &I = insts[blockIdx.x];
-  if (!I.dg) return;
+  if (!I.dg || I.bdf2) return;  // DG with BDF2: k_fpass_dg_bdf2
   __shared__ double big[4 * FROW];  // ct, srcc, G during the sweeps; then the moment rows
   double *ctS = big, *srcS = big + FROW, *gS = big + 2 * FROW;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1363,6 +1364,200 @@ __global__ void __launch_bounds__(WNT) k_fpass_dg(const Inst *__restrict__ insts
 }
 
 // ---------------------------------------------------------------------------
+// k_fpass_dg_bdf2: the f-pass of DG slabs with BDF2, k_fpass_dg's cell maps in
+// k_fpass_wave_bdf2's order of levels: for the step n just solved, f^n from
+// rho^n with the source sigma_s rho^n + (4 f^{n-1} - f^{n-2}) / (2 dt) + G
+// and the BDF2 operator (n = 1: the backward-Euler start), written over
+// f^{n-2}; then b~^n of step n + 1 from (4 f^n - f^{n-1}) / (2 dt) + G with the
+// BDF2 operator.  rhs_only: b~ of step S + 1 from the stored f^S, f^{S-1}.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(WNT) k_fpass_dg_bdf2(const Inst *__restrict__ insts, int rhs_only) {
+  const Inst &I = insts[blockIdx.x];
+  if (!I.dg || !I.bdf2) return;
+  __shared__ double big[4 * FROW];  // ct (solve), ct (rhs), srcc, G; then the moment rows
+  double *ctS = big, *srcS = big + FROW, *gS = big + 2 * FROW, *ct2S = big + 3 * FROW;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nc = I.nc, npair = I.npair, nv = I.nv;  // nc: unknowns
+  const int NB = (nc + FB - 1) / FB;
+  const double idt = I.inv_dt, hidt = 0.5 * I.inv_dt;
+  const long long S = I.st->steps;
+  const bool now_b = !rhs_only && S >= 2;
+  const bool next_b = rhs_only ? S >= 1 : true;
+  const double *__restrict__ ct_now = now_b ? I.ct_b : I.ct;
+  const double *__restrict__ ct_next = next_b ? I.ct_b : I.ct;
+  double *fA = I.fb[(S + 1) & 1];
+  double *fB = I.fb[S & 1];
+  for (int c = tid; c < NB * FB; c += WNT) {
+    const bool in = c < nc;
+    const double g = in ? ldg(&I.G[c]) : 0.0;
+    ctS[fidx(c)] = in ? ldg(&ct_now[c]) : 0.0;
+    ct2S[fidx(c)] = in ? ldg(&ct_next[c]) : 0.0;
+    gS[fidx(c)] = g;
+    srcS[fidx(c)] = (in && !rhs_only) ? rt_fma(ldg(&I.ss[c]), ldg(&I.rho[c]), g) : 0.0;
+  }
+  __syncthreads();
+  double acc[FNB][FK];
+#pragma unroll
+  for (int b = 0; b < FNB; ++b)
+#pragma unroll
+    for (int k = 0; k < FK; ++k) acc[b][k] = 0.0;
+  const double g0 = I.g[0], g1 = I.g[1];
+  for (int p = wave; p < npair; p += WNW) {
+    const double m = ldg(&I.pm[p]), w = ldg(&I.pw[p]);
+    const size_t on = (size_t)p * nc, op = (size_t)(nv - 1 - p) * nc;  // mu < 0, mu > 0
+    double cp1 = g0, cp2 = g0, cn1 = g1, cn2 = g1;
+    // one block at a time: unrolled, the blocks' live ranges overlap
+#pragma unroll 1
+    for (int s = 0; s < NB; ++s) {
+      const int bp = s, bn = NB - 1 - s;
+      const int cpb = bp * FB + lane * FK, cnb = bn * FB + lane * FK;
+      // fp, fn: the newest level (f^n once solved); ap, an: the level before
+      double fp[FK], fn[FK], ap[FK], an[FK];
+#pragma unroll
+      for (int k = 0; k < FK; ++k) {
+        const bool okp = cpb + k < nc, okn = cnb + k < nc;
+        if (rhs_only) {
+          fp[k] = okp ? ldg(&fB[op + cpb + k]) : 0.0;
+          fn[k] = okn ? ldg(&fB[on + cnb + k]) : 0.0;
+          ap[k] = (okp && next_b) ? ldg(&fA[op + cpb + k]) : 0.0;
+          an[k] = (okn && next_b) ? ldg(&fA[on + cnb + k]) : 0.0;
+        } else {
+          ap[k] = okp ? ldg(&fA[op + cpb + k]) : 0.0;
+          an[k] = okn ? ldg(&fA[on + cnb + k]) : 0.0;
+          fp[k] = (okp && now_b) ? ldg(&fB[op + cpb + k]) : 0.0;  // f^{n-2}
+          fn[k] = (okn && now_b) ? ldg(&fB[on + cnb + k]) : 0.0;
+        }
+      }
+      if (!rhs_only) {
+        double cP[2], cN[2], sP[FK], sN[FK];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          cP[h] = ctS[fidx(cpb + 2 * h)];
+          cN[h] = ctS[fidx(cnb + 2 * h)];
+        }
+#pragma unroll
+        for (int k = 0; k < FK; ++k) {
+          const double hp = now_b ? rt_fma(4.0, ap[k], -fp[k]) * hidt : ap[k] * idt;
+          const double hn = now_b ? rt_fma(4.0, an[k], -fn[k]) * hidt : an[k] * idt;
+          sP[k] = hp + srcS[fidx(cpb + k)];
+          sN[k] = hn + srcS[fidx(cnb + k)];
+        }
+        DgCell<double> zp[2], zn[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          zp[h] = dg_cell<double>(cP[h], m, sP[2 * h], sP[2 * h + 1]);
+          zn[h] = dg_cell<double>(cN[h], m, sN[2 * h], sN[2 * h + 1]);
+        }
+        const double pf = zp[0].a * zp[1].a, Bf = rt_fma(zp[1].a, zp[0].bf, zp[1].bf);
+        const double pb = zn[0].a * zn[1].a, Bb = rt_fma(zn[0].a, zn[1].bb, zn[0].bb);
+        double inF, inB;
+        wave_scan2<double>(pf, Bf, pb, Bb, cp1, cn1, inF, inB);
+        double f = inF;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          dg_unknowns<double, true>(cP[h], m, sP[2 * h], sP[2 * h + 1], zp[h].q, f, fp[2 * h], fp[2 * h + 1]);
+          f = rt_fma(zp[h].a, f, zp[h].bf);
+        }
+#pragma unroll
+        for (int k = 0; k < FK; ++k)
+          if (cpb + k < nc) stg(&fB[op + cpb + k], fp[k]);
+        cp1 = lane_value(f, 63);
+        f = inB;
+#pragma unroll
+        for (int h = 1; h >= 0; --h) {
+          dg_unknowns<double, false>(cN[h], m, sN[2 * h], sN[2 * h + 1], zn[h].q, f, fn[2 * h], fn[2 * h + 1]);
+          f = rt_fma(zn[h].a, f, zn[h].bb);
+        }
+#pragma unroll
+        for (int k = 0; k < FK; ++k)
+          if (cnb + k < nc) stg(&fB[on + cnb + k], fn[k]);
+        cn1 = lane_value(f, 0);
+#pragma unroll
+        for (int k = 0; k < FK; ++k) {
+          if (cpb + k >= nc) fp[k] = 0.0;
+          if (cnb + k >= nc) fn[k] = 0.0;
+        }
+      }
+      // right-hand side of the next step: source (4 f^n - f^{n-1}) / (2 dt) + G
+      // (a backward-Euler step: f / dt + G), its operator
+      double cP[2], cN[2], sP[FK], sN[FK];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        cP[h] = ct2S[fidx(cpb + 2 * h)];
+        cN[h] = ct2S[fidx(cnb + 2 * h)];
+      }
+#pragma unroll
+      for (int k = 0; k < FK; ++k) {
+        sP[k] = (next_b ? rt_fma(4.0, fp[k], -ap[k]) * hidt : fp[k] * idt) + gS[fidx(cpb + k)];
+        sN[k] = (next_b ? rt_fma(4.0, fn[k], -an[k]) * hidt : fn[k] * idt) + gS[fidx(cnb + k)];
+      }
+      DgCell<double> zp[2], zn[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        zp[h] = dg_cell<double>(cP[h], m, sP[2 * h], sP[2 * h + 1]);
+        zn[h] = dg_cell<double>(cN[h], m, sN[2 * h], sN[2 * h + 1]);
+      }
+      const double pf = zp[0].a * zp[1].a, Bf = rt_fma(zp[1].a, zp[0].bf, zp[1].bf);
+      const double pb = zn[0].a * zn[1].a, Bb = rt_fma(zn[0].a, zn[1].bb, zn[0].bb);
+      double inF, inB;
+      wave_scan2<double>(pf, Bf, pb, Bb, cp2, cn2, inF, inB);
+      double f = inF;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        dg_unknowns<double, true>(cP[h], m, sP[2 * h], sP[2 * h + 1], zp[h].q, f, fp[2 * h], fp[2 * h + 1]);
+        f = rt_fma(zp[h].a, f, zp[h].bf);
+      }
+      cp2 = lane_value(f, 63);
+      f = inB;
+#pragma unroll
+      for (int h = 1; h >= 0; --h) {
+        dg_unknowns<double, false>(cN[h], m, sN[2 * h], sN[2 * h + 1], zn[h].q, f, fn[2 * h], fn[2 * h + 1]);
+        f = rt_fma(zn[h].a, f, zn[h].bb);
+      }
+      cn2 = lane_value(f, 0);
+#pragma unroll
+      for (int b = 0; b < FNB; ++b) {
+        if (b == bp) {
+#pragma unroll
+          for (int k = 0; k < FK; ++k) acc[b][k] = rt_fma(w, fp[k], acc[b][k]);
+        }
+        if (b == bn) {
+#pragma unroll
+          for (int k = 0; k < FK; ++k) acc[b][k] = rt_fma(w, fn[k], acc[b][k]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (wave >= WNW / 2) {
+    double *r = big + (wave - WNW / 2) * FROW;
+#pragma unroll
+    for (int b = 0; b < FNB; ++b)
+      if (b < NB)
+#pragma unroll
+        for (int k = 0; k < FK; ++k) r[fidx(b * FB + lane * FK + k)] = acc[b][k];
+  }
+  __syncthreads();
+  if (wave < WNW / 2) {
+    double *r = big + wave * FROW;
+#pragma unroll
+    for (int b = 0; b < FNB; ++b)
+      if (b < NB)
+#pragma unroll
+        for (int k = 0; k < FK; ++k) {
+          const int i = fidx(b * FB + lane * FK + k);
+          r[i] = acc[b][k] + r[i];
+        }
+  }
+  __syncthreads();
+  double *bt_out = rhs_only ? I.bt2[S & 1] : I.bt2[I.st->cur ^ 1];
+  for (int c = tid; c < nc; c += WNT) {
+    const int i = fidx(c);
+    stg(&bt_out[c], ((big[i] + big[FROW + i]) + big[2 * FROW + i]) + big[3 * FROW + i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // k_setup_dsa_dg: the DSA operator of DG slabs and its block elimination.
 // The operator: the correction equation's diffusion limit -(D d')' +
 // sigma~_a d (D = 1/(3 sigma~_t), sigma~_a = sigma_a + 1/dt) in the DG-P1
@@ -1381,19 +1576,22 @@ __global__ void __launch_bounds__(WNT) k_fpass_dg(const Inst *__restrict__ insts
 // (sequential, one thread), then F_i = -L_i S_{i-1}^{-1} and B_i =
 // -S_i^{-1} L_{i+1}^T.  One workgroup per instance; blocks in LDS.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_setup_dsa_dg(const Inst *__restrict__ insts) {
+__global__ void __launch_bounds__(256) k_setup_dsa_dg(const Inst *__restrict__ insts, int alt) {
   const Inst &I = insts[blockIdx.x];
   if (!I.dg) return;
   __shared__ double Dl[4 * RT_DG_MAX_CELLS], Ll[4 * RT_DG_MAX_CELLS], Sl[4 * RT_DG_MAX_CELLS];
   const int N = I.ncell;
   const double h = I.hx, r3 = kR3, dd = 2.0 * kR3 / h;
-  double *K = const_cast<double *>(I.dsa_blk);
-  auto Dif = [&](int i) { return 1.0 / (3.0 * ldg(&I.ct[2 * i])); };
+  // alt: the BDF2 operator (time weight 3 / (2 dt))
+  double *K = const_cast<double *>(alt ? I.dsa_blk_b : I.dsa_blk);
+  const double *__restrict__ ctp = alt ? I.ct_b : I.ct;
+  const double adt = alt ? I.adt_b : I.inv_dt;
+  auto Dif = [&](int i) { return 1.0 / (3.0 * ldg(&ctp[2 * i])); };
   auto kap = [&](double a, double b) { return fmax((a + b) / h, 0.25); };
   const double ep[2] = {1.0, r3}, em[2] = {1.0, -r3}, gd[2] = {0.0, dd};
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     const double Di = Dif(i);
-    const double sat = ldg(&I.sa[2 * i]) + I.inv_dt;
+    const double sat = ldg(&I.sa[2 * i]) + adt;
     double A[2][2] = {{sat * h, 0.0}, {0.0, sat * h + 12.0 * Di / h}};
     const double kl = i > 0 ? kap(Dif(i - 1), Di) : 0.0;
     const double kr = i < N - 1 ? kap(Di, Dif(i + 1)) : 0.0;
@@ -1454,8 +1652,8 @@ __global__ void __launch_bounds__(256) k_setup_dsa_dg(const Inst *__restrict__ i
   }
 }
 
-extern "C" hipError_t rt_launch_setup_dsa_dg(const Inst *dinsts, int ninst, hipStream_t stream) {
-  hipLaunchKernelGGL(k_setup_dsa_dg, dim3(ninst), dim3(256), 0, stream, dinsts);
+extern "C" hipError_t rt_launch_setup_dsa_dg(const Inst *dinsts, int ninst, int alt, hipStream_t stream) {
+  hipLaunchKernelGGL(k_setup_dsa_dg, dim3(ninst), dim3(256), 0, stream, dinsts, alt);
   return hipGetLastError();
 }
 
@@ -1464,5 +1662,6 @@ extern "C" hipError_t rt_launch_slab_fpass_wave(const Inst *dinsts, int ninst, i
   if (kinds & 1) hipLaunchKernelGGL(k_fpass_wave, dim3(ninst), dim3(WNT), 0, stream, dinsts, rhs_only);
   if (kinds & 2) hipLaunchKernelGGL(k_fpass_wave_bdf2, dim3(ninst), dim3(WNT), 0, stream, dinsts, rhs_only);
   if (kinds & 4) hipLaunchKernelGGL(k_fpass_dg, dim3(ninst), dim3(WNT), 0, stream, dinsts, rhs_only);
+  if (kinds & 16) hipLaunchKernelGGL(k_fpass_dg_bdf2, dim3(ninst), dim3(WNT), 0, stream, dinsts, rhs_only);
   return hipGetLastError();
 }

@@ -1,6 +1,7 @@
 """GPU parity of the piecewise-linear upwind DG scheme (eq. DG with K = 1,
 Sec. 2.1) with its modified-interior-penalty DSA against the FP64 oracle,
-through the C ABI, on slabs.
+through the C ABI, on slabs; also with McClarren-Haut (alone and in the
+hybrid) and with BDF2 time stepping.
 
 Bars as for finite volumes: FP64 runs agree with the oracle to rel. L2 <=
 1e-10 at every step (cell averages and slopes, also cell by cell) with
@@ -164,6 +165,110 @@ def test_dg_batched_with_fv_bitwise():
                           method=("rom", "si_dsa")[k % 2 == 1 and k > 4], precision=("fp64", "mixed")[(k // 2) % 2])
         specs.append(s.replace(scheme="dg1") if k % 2 == 0 else s)
     say("dg/fv batch")
+    alone = []
+    for s in specs:
+        p = rtrom.Problem(s.replace(single_wg=True))
+        p.march(s.nsteps)
+        alone.append(p.rho())
+        p.close()
+    probs = [rtrom.Problem(s) for s in specs]
+    rtrom.march_batch(probs, specs[0].nsteps)
+    for a, p in zip(alone, probs):
+        np.testing.assert_array_equal(p.rho(), a)
+        p.close()
+
+
+@pytest.mark.parametrize("method", ["si_dsa", "rom"])
+def test_dg_mcclarren_haut_fp64_matches_oracle(method):
+    """McClarren-Haut on DG unknowns, alone and as the hybrid with the ROM
+    method (Sec. 3.3, Sec. 4.5): per-step results within 10x the oracle's own
+    rounding spread (its small reduced systems amplify rounding), counts,
+    phases and ranks identical up to the first step where perturbed oracle
+    runs disagree."""
+    spec = W.slab_two_region(nx=128, nsteps=12).replace(scheme="dg1", method=method, precond="mh")
+    n = spec.nsteps
+    say(f"dg mh fp64 {method}")
+    horizon = count_horizon(spec, n)
+    errs, o, g = step_both(spec, n)
+    bar = np.maximum(FP64_TOL, 10.0 * oracle_rounding_spread(spec, n))
+    assert (errs <= bar).all(), errs.max()
+    ho, hg = o.history(), g.history()
+    for key in ("iters", "phase", "ig_update", "pc_update", "rank_ig", "rank_pc"):
+        np.testing.assert_array_equal(hg[key][:horizon], ho[key][:horizon], err_msg=key)
+    assert g.stats()["nonconverged_steps"] == 0
+
+
+def test_dg_mcclarren_haut_mixed_meets_fp64_bar():
+    spec = W.slab_two_region(nx=128, nsteps=20).replace(scheme="dg1", method="rom", precond="mh",
+                                                        precision="mixed")
+    say("dg mh mixed")
+    ref = converged_reference(spec, spec.nsteps)
+    bars = mixed_bars(spec, spec.nsteps, ref, method="rom")
+    g = rtrom.Problem(spec)
+    for k in range(spec.nsteps):
+        g.step()
+        e = rel_l2(g.rho(), ref[k])
+        assert e <= bars[k], (k, e, bars[k])
+    assert g.stats()["nonconverged_steps"] == 0
+
+
+@pytest.mark.parametrize("method,nx,nv", [("si_dsa", 200, 16), ("rom", 300, 32), ("rom", 1024, 16)])
+def test_dg_bdf2_fp64_matches_oracle(method, nx, nv):
+    """BDF2 on DG unknowns (a backward-Euler start, then the BDF2 transport
+    and DSA operators): results, f and b~ as the oracle's at every step."""
+    spec = W.random_slab(60 + nx, nx, nv, dt=0.01, tol=1e-8, method=method, scheme="dg1", time_scheme="bdf2",
+                         inflow=(0.8, 0.3, 0.0, 0.0), nsteps=30)
+    n = spec.nsteps
+    say(f"dg bdf2 fp64 {method} nx={nx} nv={nv}")
+    horizon = count_horizon(spec, n) if method == "rom" else n
+    errs, o, g = step_both(spec, n)
+    assert (errs <= _bar(spec, n)).all(), errs.max()
+    ho, hg = o.history(), g.history()
+    for key in ("iters", "phase", "ig_update", "pc_update", "rank_ig", "rank_pc"):
+        np.testing.assert_array_equal(hg[key][:horizon], ho[key][:horizon], err_msg=key)
+    assert rel_l2(g.f(), o.f()) <= 1e-9
+    assert rel_l2(g.rhs(), o.bt()) <= 1e-9
+
+
+def test_dg_bdf2_infinite_medium_closed_form():
+    sa, dt = 0.7, 0.2
+    spec = W.infinite_medium(dim=1, n=40, n_polar=8, sigma_a=sa, dt=dt, tol=1e-12).replace(
+        scheme="dg1", time_scheme="bdf2")
+    say("dg bdf2 infinite medium")
+    g = rtrom.Problem(spec)
+    u = [1.0, 1.0 / (1.0 + dt * sa)]
+    for n in range(1, 8):
+        g.step()
+        np.testing.assert_allclose(g.rho()[::2], u[n], rtol=1e-10)
+        np.testing.assert_allclose(g.rho()[1::2], 0.0, atol=1e-12)
+        u.append((4.0 * u[n] - u[n - 1]) / (3.0 + 2.0 * dt * sa))
+        g.set_inflow([u[n + 1]] * 4)
+
+
+def test_dg_bdf2_mixed_meets_fp64_bar():
+    spec = W.random_slab(87, 400, 32, dt=0.01, tol=1e-8, method="rom", precision="mixed", scheme="dg1",
+                         time_scheme="bdf2", inflow=(1.0, 0.0, 0.0, 0.0), nsteps=40)
+    say("dg bdf2 mixed")
+    ref = converged_reference(spec, spec.nsteps)
+    bars = mixed_bars(spec, spec.nsteps, ref, method="rom")
+    g = rtrom.Problem(spec)
+    for k in range(spec.nsteps):
+        g.step()
+        e = rel_l2(g.rho(), ref[k])
+        assert e <= bars[k], (k, e, bars[k])
+    assert g.stats()["nonconverged_steps"] == 0
+
+
+def test_dg_variants_batched_bitwise():
+    """A batch of DG instances with DSA, McClarren-Haut and BDF2 beside finite
+    volumes: every instance marches to bitwise the result it reaches alone."""
+    kinds = [dict(), dict(precond="mh"), dict(time_scheme="bdf2"), dict(precond="mh", time_scheme="bdf2")]
+    specs = []
+    for k in range(8):
+        s = W.random_slab(110 + k, 80 + 111 * k, (8, 16, 32)[k % 3], dt=0.01, nsteps=20, method="rom",
+                          precision=("fp64", "mixed")[(k // 4) % 2])
+        specs.append(s.replace(scheme="dg1", **kinds[k % 4]) if k < 6 else s.replace(**kinds[k % 4]))
+    say("dg variants batch")
     alone = []
     for s in specs:
         p = rtrom.Problem(s.replace(single_wg=True))

@@ -17,7 +17,8 @@ closed-form cell solves:
 * particle balance of every step;
 * the paper's Sec. 4.1 two-material slab (its own DG-P1 setup): SI-DSA needs
   15-31 sweeps per step (the paper: at least 17, above 20 early on), the ROM
-  method 2-5 on average in phase 3, both reaching the same solution.
+  method 2-5 on average in phase 3, both reaching the same solution;
+* McClarren-Haut on DG unknowns reaching the SI-DSA fixed point.
 """
 import numpy as np
 import pytest
@@ -32,12 +33,14 @@ def _basis(k, xi):
     return np.ones_like(xi) if k == 0 else R3 * xi
 
 
-def _dg_dense_step(sp, mu, w, fprev):
+def _dg_dense_step(sp, mu, w, fprev, alpha=1.0, hist=None):
     """One backward-Euler step of eq. DG (K = 1) assembled from the weak form:
     for ordinate j, cell i and test function phi_k,
       int (1/dt + sigma_t) phi_k f - mu int phi_k' f + sum_faces mu.n phi_k f^ =
       int phi_k (sigma_s rho + f_prev / dt + G)  (+ inflow terms),
-    integrals by 3-point Gauss quadrature.  fprev, return: [nv][nc][2] DoFs."""
+    integrals by 3-point Gauss quadrature.  fprev, return: [nv][nc][2] DoFs.
+    A BDF2 step: alpha = 3/2 in the operator and hist = (4 f^{n-1} - f^{n-2})
+    / 2 in place of f_prev."""
     nx, nv = sp.nx, len(mu)
     h = sp.lx / nx
     gx, gw = np.polynomial.legendre.leggauss(3)
@@ -59,7 +62,7 @@ def _dg_dense_step(sp, mu, w, fprev):
             for k in range(2):
                 r = idx(j, i, k)
                 for m in range(2):
-                    A[r, idx(j, i, m)] += (1.0 / sp.dt + st[i]) * M[k, m] - mu[j] * S[k, m]
+                    A[r, idx(j, i, m)] += (alpha / sp.dt + st[i]) * M[k, m] - mu[j] * S[k, m]
                     # outflow face: upwind value is the cell's own
                     A[r, idx(j, i, m)] += m_ * at[out_side][k] * at[out_side][m]
                     # inflow face: upwind value from the neighbour's outflow side
@@ -70,7 +73,8 @@ def _dg_dense_step(sp, mu, w, fprev):
                 if not (0 <= up < nx):
                     g = sp.inflow[0] if mu[j] > 0 else sp.inflow[1]
                     b[r] += m_ * at[in_side][k] * g
-                b[r] += sum(M[k, m] * fprev[j, i, m] for m in range(2)) / sp.dt
+                hj = fprev if hist is None else hist
+                b[r] += sum(M[k, m] * hj[j, i, m] for m in range(2)) / sp.dt
                 b[r] += sp.source[i] * M[k, 0]
     return np.linalg.solve(A, b).reshape(nv, nx, 2)
 
@@ -199,3 +203,53 @@ def test_sec41_two_material_slab_in_dg():
     ph3 = r["phase"] == 3
     assert ph3.sum() >= 50 and 2.0 <= r["iters"][ph3].mean() <= 5.0
     assert np.linalg.norm(rho["rom"] - rho["si_dsa"]) <= 1e-7 * np.linalg.norm(rho["si_dsa"])
+
+
+def test_dg_mcclarren_haut_same_fixed_point_fewer_sweeps():
+    """McClarren-Haut (Sec. 3.3) on DG unknowns: the same fixed point as
+    SI-DSA (it only preconditions), in fewer sweeps than plain SI."""
+    sp = W.slab_two_region(nx=64, nsteps=6).replace(scheme="dg1", tol=1e-12)
+    runs = {}
+    for name, kw in (("si_dsa", dict(method="si_dsa")), ("mh", dict(method="si_dsa", precond="mh")),
+                     ("si", dict(method="si", max_iter=3000))):
+        o = oracle.OracleProblem(sp.replace(**kw))
+        assert o.march(6) == 0
+        runs[name] = (o.rho(), o.history()["iters"])
+    ref = runs["si_dsa"][0]
+    for name in ("mh", "si"):
+        assert np.linalg.norm(runs[name][0] - ref) <= 1e-10 * np.linalg.norm(ref), name
+    assert runs["mh"][1].sum() < 0.75 * runs["si"][1].sum()
+
+
+@pytest.mark.parametrize("method", ["si_dsa", "rom"])
+def test_dense_dg_bdf2(method):
+    """BDF2 on DG unknowns against the dense weak-form system: one
+    backward-Euler start step, then (3 f^n - 4 f^{n-1} + f^{n-2}) / (2 dt)."""
+    sp = W.random_slab(8, 16, 4, inflow=(1.0, 0.3, 0, 0), dt=0.05, tol=1e-12, method=method, scheme="dg1",
+                       time_scheme="bdf2")
+    o = oracle.OracleProblem(sp)
+    mu, _, _, w = o.quadrature()
+    f_old = np.zeros((4, 16, 2))
+    f = _dg_dense_step(sp, mu, w, f_old)
+    o.step()
+    np.testing.assert_allclose(o.f(), f.reshape(4, -1), rtol=1e-9, atol=1e-12)
+    for _ in range(4):
+        o.step()
+        f_new = _dg_dense_step(sp, mu, w, None, alpha=1.5, hist=(4.0 * f - f_old) / 2.0)
+        f_old, f = f, f_new
+        np.testing.assert_allclose(o.f(), f.reshape(4, -1), rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(o.rho(), np.einsum("j,jik->ik", w, f).reshape(-1), rtol=1e-9, atol=1e-12)
+
+
+def test_dg_bdf2_infinite_medium_recurrence():
+    sa, dt = 0.7, 0.2
+    spec = W.infinite_medium(dim=1, n=12, n_polar=4, sigma_a=sa, dt=dt, tol=1e-12).replace(
+        scheme="dg1", time_scheme="bdf2")
+    o = oracle.OracleProblem(spec)
+    u = [1.0, 1.0 / (1.0 + dt * sa)]
+    for n in range(1, 7):
+        o.step()
+        np.testing.assert_allclose(o.rho()[::2], u[n], rtol=1e-10)
+        np.testing.assert_allclose(o.rho()[1::2], 0.0, atol=1e-12)
+        u.append((4.0 * u[n] - u[n - 1]) / (3.0 + 2.0 * dt * sa))
+        o.set_inflow([u[n + 1]] * 4)
