@@ -241,8 +241,7 @@ static rtrom_status validate(const rtrom_problem_desc *d) {
   const bool variant = d->precond == RTROM_PC_MH || d->time_scheme == RTROM_BDF2;
   if (variant && d->dim == 1 && d->nx > RT_WAVE_MAX_CELLS)
     return fail(RTROM_EINVAL, "McClarren-Haut and BDF2 run on slabs of at most 2048 cells");
-  if (variant && d->dim == 2)
-    return fail(RTROM_EINVAL, "McClarren-Haut and BDF2 run on slabs only");
+  if (d->time_scheme == RTROM_BDF2 && d->dim == 2) return fail(RTROM_EINVAL, "BDF2 runs on slabs only");
   if (d->pc_levels > 1 && !(d->dim == 1 && d->nx <= RT_WAVE_MAX_CELLS))
     return fail(RTROM_EINVAL, "correction ROMs beyond the first iteration run on slabs of at most 2048 cells");
   if (d->scheme != RTROM_FV && d->scheme != RTROM_DG1) return fail(RTROM_EINVAL, "unknown scheme");
@@ -357,10 +356,12 @@ static size_t slab_bytes(const rtrom_problem_desc *d, int nv) {
       L.take((size_t)nv * nc * 8);
       for (int k = 0; k < 4; ++k) L.take(nc * 8);
     }
-    if (d->precond == RTROM_PC_MH) {  // Q, Z
-      L.take((size_t)mh_cap_of(d) * ld * 8);
-      L.take((size_t)mh_cap_of(d) * ld * 8);
-    }
+  }
+  if (d->precond == RTROM_PC_MH) {  // Q, Z
+    L.take((size_t)mh_cap_of(d) * ld * 8);
+    L.take((size_t)mh_cap_of(d) * ld * 8);
+  }
+  if (d->dim == 1) {
     if (d->scheme == RTROM_DG1) L.take(12 * (size_t)d->nx * 8);  // block DSA factors
     if (d->scheme == RTROM_DG1 && d->time_scheme == RTROM_BDF2) L.take(12 * (size_t)d->nx * 8);  // of BDF2
     int ng, pg;
@@ -538,7 +539,7 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
     I.dsa_bg_b = D(nc * 8);
     I.dsa_invd_b = D(nc * 8);
   }
-  if (d->dim == 1 && d->precond == RTROM_PC_MH) {
+  if (d->precond == RTROM_PC_MH) {
     I.mh_cap = mh_cap_of(d);
     I.mhQ = D((size_t)I.mh_cap * ld * 8);
     I.mhZ = D((size_t)I.mh_cap * ld * 8);

@@ -37,6 +37,7 @@
 #include <tuple>
 
 #include "rt_host.h"
+#include "rt_mh.h"
 #include "rt_rom.h"
 
 // Chebyshev iterations the 2D DSA solve may take (its coefficient table is
@@ -665,6 +666,234 @@ __global__ void __launch_bounds__(BLK) k_romapply_expand(RomDev R, const int *ra
   }
 }
 
+// ---------------------------------------------------------------------------
+// McClarren-Haut (Sec. 3.3) over the grid: the model of the one-workgroup
+// slab kernel (rt_mh.h) with its cell-wise passes as grid kernels (block
+// partial sums, summed in a fixed order by one workgroup) and its O(m^2) /
+// O(m^3) work in one workgroup, the state in global memory.  Pair l
+// (iterations l >= 2): x = rho^{(l-1)} - rho^{(l-2)}, z = y_l - y_{l-1},
+// both scaled by 1/||x||_2, inputs orthonormalised by classical Gram-Schmidt
+// applied twice into Q (X = Q R), B = Q^T Z, A~ = B R^{-1}; the correction
+// d = Q (I - A~)^{-1} A~ Q^T (y - rho^{(l-1)}).  A pair whose scaled input
+// keeps an orthogonal remainder of at most 1e-6 is skipped; a full model
+// (mh_cap pairs) restarts from the newest pair.  The model lives within one
+// time step.
+// ---------------------------------------------------------------------------
+struct MhGrid {
+  int m, m0, skip, bad;
+  double xn, nu;
+  double R[RT_RMAX * RT_RMAX];  // R[i * RT_RMAX + j], upper triangular
+  double B[RT_RMAX * RT_RMAX];  // B = Q^T Z
+  double a1[RT_RMAX], ac[RT_RMAX], qz[RT_RMAX], c[RT_RMAX];
+};
+
+__global__ void k_mh_reset(MhGrid *M) {
+  if (threadIdx.x == 0) M->m = 0;
+}
+
+// pass 1 of a pair: partials of Q^T x, Q^T z, x.x (m0: the model's size
+// after a restart of a full one)
+__global__ void __launch_bounds__(BLK) k_mh_pass1(Inst I, int nc, const double *rp, const double *rp2,
+                                                  const double *y, const double *yp, MhGrid *M, double *part) {
+  const int m = M->m, m0 = m == I.mh_cap ? 0 : m, ld = I.ld;
+  const int c = blockIdx.x * BLK + threadIdx.x;
+  double p[RT_MH_NP];
+#pragma unroll
+  for (int k = 0; k < RT_MH_NP; ++k) p[k] = 0.0;
+  if (c < nc) {
+    const double x = rp[c] - rp2[c], z = y[c] - yp[c];
+    p[2 * RT_RMAX] = x * x;
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k)
+      if (k < m0) {
+        const double q = I.mhQ[(size_t)k * ld + c];
+        p[k] = q * x;
+        p[RT_RMAX + k] = q * z;
+      }
+  }
+  __shared__ double red[(BLK / 64) * RT_MH_NP], out[RT_MH_NP];
+  wg_sum_fast<RT_MH_NP>(p, red, out);
+  if (threadIdx.x < RT_MH_NP) part[blockIdx.x * RT_NPART + threadIdx.x] = out[threadIdx.x];
+}
+__global__ void __launch_bounds__(256) k_mh_small1(Inst I, int nblk, const double *part, MhGrid *M) {
+  __shared__ double vec[RT_MH_NP], scratch[256];
+  sum_partials<false>(part, nblk, RT_MH_NP, vec, scratch);
+  const int m = M->m, m0 = m == I.mh_cap ? 0 : m;
+  const double xx = vec[2 * RT_RMAX];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    M->m0 = m0;
+    M->skip = !(xx > 0.0);  // no input difference: nothing to learn
+    M->xn = sqrt(fmax(xx, 0.0));
+  }
+  if ((int)threadIdx.x < RT_RMAX) {
+    const int k = threadIdx.x;
+    const double ixn = xx > 0.0 ? 1.0 / sqrt(xx) : 0.0;
+    M->a1[k] = k < m0 ? vec[k] * ixn : 0.0;
+    M->qz[k] = k < m0 ? vec[RT_RMAX + k] : 0.0;
+  }
+}
+// pass 2: p = x / ||x|| - Q a1; partials of Q^T p, p.p
+__global__ void __launch_bounds__(BLK) k_mh_pass2(Inst I, int nc, const double *rp, const double *rp2,
+                                                  const MhGrid *M, double *part) {
+  if (M->skip) return;
+  const int m0 = M->m0, ld = I.ld;
+  const double ixn = 1.0 / M->xn;
+  const int c = blockIdx.x * BLK + threadIdx.x;
+  double p[RT_RMAX + 1];
+#pragma unroll
+  for (int k = 0; k <= RT_RMAX; ++k) p[k] = 0.0;
+  if (c < nc) {
+    double q[RT_RMAX];
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k) q[k] = k < m0 ? I.mhQ[(size_t)k * ld + c] : 0.0;
+    double v = (rp[c] - rp2[c]) * ixn;
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k) v = rt_fma(-q[k], M->a1[k], v);
+    p[RT_RMAX] = v * v;
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k) p[k] = q[k] * v;
+  }
+  __shared__ double red[(BLK / 64) * (RT_RMAX + 1)], out[RT_RMAX + 1];
+  wg_sum_fast<RT_RMAX + 1>(p, red, out);
+  if (threadIdx.x <= RT_RMAX) part[blockIdx.x * RT_NPART + threadIdx.x] = out[threadIdx.x];
+}
+__global__ void __launch_bounds__(256) k_mh_small2(int nblk, const double *part, MhGrid *M) {
+  if (M->skip) return;
+  __shared__ double vec[RT_RMAX + 1], scratch[256];
+  sum_partials<false>(part, nblk, RT_RMAX + 1, vec, scratch);
+  if (threadIdx.x == 0) {
+    const int m0 = M->m0;
+    double a2s = 0.0;
+    for (int k = 0; k < m0; ++k) a2s = rt_fma(vec[k], vec[k], a2s);
+    const double nu = sqrt(fmax(vec[RT_RMAX] - a2s, 0.0));
+    M->nu = nu;
+    if (!(nu > RT_MH_DEP)) {
+      M->skip = 1;  // in span already
+    } else {
+      const double ixn = 1.0 / M->xn;
+      for (int k = 0; k < m0; ++k) {
+        M->ac[k] = M->a1[k] + vec[k];
+        M->R[k * RT_RMAX + m0] = M->ac[k];
+        M->B[k * RT_RMAX + m0] = M->qz[k] * ixn;
+      }
+      for (int k = m0; k < RT_RMAX; ++k) M->ac[k] = 0.0;
+      M->R[m0 * RT_RMAX + m0] = nu;
+    }
+  }
+}
+// pass 3: the new columns of Q and Z; partials of the new row of B,
+// q . Z_k and q . z^ as direct dot products
+__global__ void __launch_bounds__(BLK) k_mh_pass3(Inst I, int nc, const double *rp, const double *rp2,
+                                                  const double *y, const double *yp, const MhGrid *M, double *part) {
+  if (M->skip) return;
+  const int m0 = M->m0, ld = I.ld;
+  const double ixn = 1.0 / M->xn, inu = 1.0 / M->nu;
+  const int c = blockIdx.x * BLK + threadIdx.x;
+  double p[RT_RMAX + 1];
+#pragma unroll
+  for (int k = 0; k <= RT_RMAX; ++k) p[k] = 0.0;
+  if (c < nc) {
+    double v = (rp[c] - rp2[c]) * ixn;
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k)
+      if (k < m0) v = rt_fma(-I.mhQ[(size_t)k * ld + c], M->ac[k], v);
+    v *= inu;
+    const double zh = (y[c] - yp[c]) * ixn;
+    I.mhQ[(size_t)m0 * ld + c] = v;
+    I.mhZ[(size_t)m0 * ld + c] = zh;
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k)
+      if (k < m0) p[k] = v * I.mhZ[(size_t)k * ld + c];
+    p[RT_RMAX] = v * zh;
+  }
+  __shared__ double red[(BLK / 64) * (RT_RMAX + 1)], out[RT_RMAX + 1];
+  wg_sum_fast<RT_RMAX + 1>(p, red, out);
+  if (threadIdx.x <= RT_RMAX) part[blockIdx.x * RT_NPART + threadIdx.x] = out[threadIdx.x];
+}
+__global__ void __launch_bounds__(256) k_mh_small3(int nblk, const double *part, MhGrid *M) {
+  if (M->skip) return;
+  __shared__ double vec[RT_RMAX + 1], scratch[256];
+  sum_partials<false>(part, nblk, RT_RMAX + 1, vec, scratch);
+  const int m0 = M->m0;
+  if ((int)threadIdx.x < m0) M->B[m0 * RT_RMAX + threadIdx.x] = vec[threadIdx.x];
+  if (threadIdx.x == 0) {
+    M->B[m0 * RT_RMAX + m0] = vec[RT_RMAX];
+    M->m = m0 + 1;
+  }
+}
+// the correction: partials of Q^T r, r = y - rho
+__global__ void __launch_bounds__(BLK) k_mh_cpass(Inst I, int nc, const double *y, const double *rp,
+                                                  const MhGrid *M, double *part) {
+  const int m = M->m, ld = I.ld;
+  if (m == 0) return;
+  const int c = blockIdx.x * BLK + threadIdx.x;
+  double p[RT_RMAX];
+#pragma unroll
+  for (int k = 0; k < RT_RMAX; ++k) p[k] = 0.0;
+  if (c < nc) {
+    const double r = y[c] - rp[c];
+#pragma unroll
+    for (int k = 0; k < RT_RMAX; ++k)
+      if (k < m) p[k] = I.mhQ[(size_t)k * ld + c] * r;
+  }
+  __shared__ double red[(BLK / 64) * RT_RMAX], out[RT_RMAX];
+  wg_sum_fast<RT_RMAX>(p, red, out);
+  if (threadIdx.x < RT_RMAX) part[blockIdx.x * RT_NPART + threadIdx.x] = out[threadIdx.x];
+}
+// A~ = B R^{-1}, g = A~ Q^T r, and (I - A~) c = g on wave 0 (mh_solve_wave);
+// c = 0 for an empty model or a singular system
+__global__ void __launch_bounds__(256) k_mh_csolve(int nblk, const double *part, MhGrid *M) {
+  __shared__ MhLds S;
+  __shared__ double vec[RT_RMAX], scratch[256];
+  const int m = M->m;
+  if (m == 0) {
+    if ((int)threadIdx.x < RT_RMAX) M->c[threadIdx.x] = 0.0;
+    return;
+  }
+  sum_partials<false>(part, nblk, RT_RMAX, vec, scratch);
+  if (threadIdx.x < 64) {
+    const int i = threadIdx.x;
+    if (i < m) {
+      double at[RT_RMAX];
+#pragma unroll
+      for (int j = 0; j < RT_RMAX; ++j) {
+        if (j < m) {
+          double v = M->B[i * RT_RMAX + j];
+#pragma unroll
+          for (int k = 0; k < RT_RMAX; ++k)
+            if (k < j) v = rt_fma(-at[k], M->R[k * RT_RMAX + j], v);
+          at[j] = v / M->R[j * RT_RMAX + j];
+        } else {
+          at[j] = 0.0;
+        }
+      }
+      double g = 0.0;
+#pragma unroll
+      for (int j = 0; j < RT_RMAX; ++j)
+        if (j < m) g = rt_fma(at[j], vec[j], g);
+      S.vec[i] = g;
+#pragma unroll
+      for (int j = 0; j < RT_RMAX; ++j)
+        if (j < m) S.A[i * RT_KC + j] = (i == j ? 1.0 : 0.0) - at[j];
+    }
+  }
+  __syncthreads();
+  const int bad = mh_solve_wave(S, m);
+  if ((int)threadIdx.x < RT_RMAX) M->c[threadIdx.x] = (!bad && (int)threadIdx.x < m) ? S.vec[threadIdx.x] : 0.0;
+}
+// d = Q c
+__global__ void __launch_bounds__(BLK) k_mh_expand(Inst I, int nc, const MhGrid *M, double *d) {
+  const int m = M->m, ld = I.ld;
+  const int c = blockIdx.x * BLK + threadIdx.x;
+  if (c >= nc) return;
+  double v = 0.0;
+#pragma unroll
+  for (int k = 0; k < RT_RMAX; ++k)
+    if (k < m) v = rt_fma(I.mhQ[(size_t)k * ld + c], M->c[k], v);
+  d[c] = v;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -683,6 +912,8 @@ struct PlaneHost {
   double *diag = nullptr, *ax = nullptr, *ay = nullptr;
   double *blkmax = nullptr, *res = nullptr, *res_h = nullptr;
   double *rpart = nullptr, *rcoef = nullptr;
+  double *yp = nullptr, *rp2 = nullptr;  // McClarren-Haut: y_{l-1}, rho^{(l-2)}
+  MhGrid *mh = nullptr;                  // McClarren-Haut model state
   int cheb_iters = 0;
   int pd32 = 8, pd64 = 8;  // prefetch depth of the SI sweeps (FP32 / FP64), tuned per grid shape
   double cheb_theta = 1.0, cheb_delta = 0.0;
@@ -722,6 +953,10 @@ static size_t plane_bytes_for(const rtrom_problem_desc *d) {
   take(2 * (size_t)RT_CHEB_MAX * 8);               // Chebyshev coefficients
   take(nblk * RT_NPART * 8 + RT_RMAX * 8);  // DMD solve partials, coefficients
   take((size_t)g.ndf * 3 * 8);      // mx my w
+  if (d->precond == RTROM_PC_MH) {  // McClarren-Haut: y_{l-1}, rho^{(l-2)}, model state
+    take(nc * 8 * 2);
+    take(sizeof(MhGrid));
+  }
   return b;
 }
 
@@ -956,6 +1191,11 @@ int rt_plane_create(rtrom_problem *p) {
   H->rpart = (double *)take((size_t)nblk * RT_NPART * 8 + RT_RMAX * 8);
   H->rcoef = H->rpart + (size_t)nblk * RT_NPART;
   double *dmx = (double *)take((size_t)ndf * 3 * 8);
+  if (d->precond == RTROM_PC_MH) {
+    H->yp = (double *)take((size_t)nc * 8 * 2);
+    H->rp2 = H->yp + nc;
+    H->mh = (MhGrid *)take(sizeof(MhGrid));
+  }
   Inst &I = p->hinst;
   PH(hipMemcpyAsync(dmx, hm.data(), hm.size() * 8, hipMemcpyHostToDevice, p->stream));
   PH(hipHostMalloc((void **)&H->res_h, 64, hipHostMallocDefault));
@@ -1135,6 +1375,7 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
     hipLaunchKernelGGL(k_plane_copy, dim3(nblk), dim3(BLK), 0, s, nc, (const double *)I.rho, I.rho0);
   }
   hipLaunchKernelGGL(k_plane_copy, dim3(nblk), dim3(BLK), 0, s, nc, (const double *)I.rho0, H->rp);
+  if (H->mh) hipLaunchKernelGGL(k_mh_reset, dim3(1), dim3(64), 0, s, H->mh);  // a model per step
   int nsweep = 0, n32 = 0, conv = 0, used_pc = 0, pc_fb = 0, exact = 0, first_corr = 1, need64 = 1;
   double resid = 0.0;
   for (;;) {
@@ -1165,6 +1406,27 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
       continue;
     }
     if (nsweep >= I.max_iter) break;
+    if (H->mh) {
+      // McClarren-Haut: the pair of this iteration, (rho^{(l-1)} - rho^{(l-2)},
+      // y_l - y_{l-1}); in mixed precision an iterate recomputed by an FP64
+      // sweep starts a new chain of FP32 increments instead (its difference
+      // to the accumulated y_{l-1} would carry that chain's drift)
+      if (nsweep >= 2 && !(mixed && exact)) {
+        const double *rp_ = H->rp, *y_ = H->y;
+        hipLaunchKernelGGL(k_mh_pass1, dim3(nblk), dim3(BLK), 0, s, I, nc, rp_, (const double *)H->rp2, y_,
+                           (const double *)H->yp, H->mh, H->rpart);
+        hipLaunchKernelGGL(k_mh_small1, dim3(1), dim3(256), 0, s, I, nblk, (const double *)H->rpart, H->mh);
+        hipLaunchKernelGGL(k_mh_pass2, dim3(nblk), dim3(BLK), 0, s, I, nc, rp_, (const double *)H->rp2,
+                           (const MhGrid *)H->mh, H->rpart);
+        hipLaunchKernelGGL(k_mh_small2, dim3(1), dim3(256), 0, s, nblk, (const double *)H->rpart, H->mh);
+        hipLaunchKernelGGL(k_mh_pass3, dim3(nblk), dim3(BLK), 0, s, I, nc, rp_, (const double *)H->rp2, y_,
+                           (const double *)H->yp, (const MhGrid *)H->mh, H->rpart);
+        hipLaunchKernelGGL(k_mh_small3, dim3(1), dim3(256), 0, s, nblk, (const double *)H->rpart, H->mh);
+      }
+      hipLaunchKernelGGL(k_plane_copy, dim3(nblk), dim3(BLK), 0, s, nc, (const double *)H->y, H->yp);
+      hipLaunchKernelGGL(k_plane_copy, dim3(nblk), dim3(BLK), 0, s, nc, (const double *)H->rp, H->rp2);
+      PH(hipGetLastError());
+    }
     const double *dcorr = nullptr;
     if (rom && first_corr && st.flag_pc && st.lu_ok_pc) {
       rt_prof_begin(RT_K_PLANE_OTHER, s);
@@ -1177,10 +1439,21 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
       used_pc = 1;
     } else if (I.method != RT_SI_PLAIN) {
       if (rom && first_corr && st.flag_pc) pc_fb = 1;
-      rt_prof_begin(RT_K_PLANE_DSA, s);
-      e = dsa_solve(p, H, H->y, H->rp);
-      rt_prof_end(RT_K_PLANE_DSA, s);
-      if (e) return e;
+      if (H->mh) {
+        // McClarren-Haut correction from the step's pairs (Sec. 3.3)
+        rt_prof_begin(RT_K_PLANE_OTHER, s);
+        hipLaunchKernelGGL(k_mh_cpass, dim3(nblk), dim3(BLK), 0, s, I, nc, (const double *)H->y,
+                           (const double *)H->rp, (const MhGrid *)H->mh, H->rpart);
+        hipLaunchKernelGGL(k_mh_csolve, dim3(1), dim3(256), 0, s, nblk, (const double *)H->rpart, H->mh);
+        hipLaunchKernelGGL(k_mh_expand, dim3(nblk), dim3(BLK), 0, s, I, nc, (const MhGrid *)H->mh, H->cx);
+        rt_prof_end(RT_K_PLANE_OTHER, s);
+        PH(hipGetLastError());
+      } else {
+        rt_prof_begin(RT_K_PLANE_DSA, s);
+        e = dsa_solve(p, H, H->y, H->rp);
+        rt_prof_end(RT_K_PLANE_DSA, s);
+        if (e) return e;
+      }
       dcorr = H->cx;
     }
     first_corr = 0;

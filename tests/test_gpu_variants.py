@@ -1,6 +1,8 @@
 """GPU parity of the variants against the FP64 oracle, through the C ABI:
 the McClarren-Haut preconditioner alone and as the hybrid with the ROM method
-(Sec. 3.3, Sec. 4.5) and BDF2 time stepping (Sec. 2.1), on slabs.
+(Sec. 3.3, Sec. 4.5; on slabs and X-Y grids, including the paper's Sec. 4.5
+setup), BDF2 time stepping (Sec. 2.1) and sequential correction ROMs, on
+slabs.
 
 Bars as for the default configuration: FP64 runs agree with the oracle to
 rel. L2 <= 1e-10 at every step with identical SI counts, phases, ROM
@@ -229,3 +231,56 @@ def test_correction_levels_batched_bitwise():
         np.testing.assert_array_equal(p.rho(), a)
         assert p.levels() == la
         p.close()
+
+
+@pytest.mark.parametrize("method", ["si_dsa", "rom"])
+def test_mh_plane_fp64_matches_oracle(method):
+    """McClarren-Haut on an X-Y grid (its passes as grid kernels), alone and
+    as the hybrid: per-step results, counts, phases, updates and ranks as
+    the oracle's."""
+    spec = W.random_plane(31, 48, 8, 4, method=method, precond="mh", dt=0.05, tol=1e-8, nsteps=15)
+    say(f"mh plane fp64 {method}")
+    errs, o, g = step_both(spec, spec.nsteps)
+    assert (errs <= _rom_bar(spec, spec.nsteps)).all(), errs.max()
+    assert_same_decisions(o, g)
+    assert elementwise_err(g.rho(), o.rho()) <= 1e-8
+
+
+def test_sec45_mcclarren_haut_and_hybrid():
+    """The paper's Sec. 4.5 setup (Sec. 4.2's Gaussian source, sigma_s = 1,
+    CFL = 1, tol 1e-8, eps_IG = eps_PC = eps_UP = 1e-6) in FV form, 40 of its
+    102 steps in FP64: McClarren-Haut alone and the hybrid with the ROM method
+    as the oracle's at every step (counts and results); sweeps per step
+    printed beside plain SI and the ROM method with DSA.  As in the paper's
+    Fig. 10, the hybrid needs fewer sweeps than McClarren-Haut alone, which
+    needs fewer than plain SI."""
+    base = W.sec42_gaussian_source(nsteps=40).replace(tol=1e-8, eps_ig=1e-6, eps_pc=1e-6, eps_up=1e-6)
+    runs = {}
+    for name, kw in (("mh", dict(method="si_dsa", precond="mh")), ("hybrid_mh", dict(method="rom", precond="mh"))):
+        spec = base.replace(**kw)
+        say(f"sec45 {name}")
+        errs, o, g = step_both(spec, spec.nsteps)
+        assert (errs <= _rom_bar(spec, spec.nsteps)).all(), (name, errs.max())
+        assert_same_decisions(o, g)
+        runs[name] = g.history()["iters"]
+    for name, kw in (("si", dict(method="si", max_iter=500)), ("hybrid_dsa", dict(method="rom"))):
+        g = rtrom.Problem(base.replace(**kw))
+        g.march(base.nsteps)
+        runs[name] = g.history()["iters"]
+    for name, it in runs.items():
+        say(f"  {name}: {it.mean():.2f} sweeps per step, {it.tolist()}")
+    assert runs["hybrid_mh"].sum() < runs["mh"].sum() < runs["si"].sum()
+
+
+def test_mh_plane_mixed_meets_fp64_bar():
+    spec = W.random_plane(32, 48, 8, 4, method="rom", precond="mh", precision="mixed", dt=0.05, tol=1e-8,
+                          nsteps=20)
+    say("mh plane mixed")
+    ref = converged_reference(spec, spec.nsteps)
+    bars = mixed_bars(spec, spec.nsteps, ref, method="rom")
+    g = rtrom.Problem(spec)
+    for k in range(spec.nsteps):
+        g.step()
+        e = rel_l2(g.rho(), ref[k])
+        assert e <= bars[k], (k, e, bars[k])
+    assert g.stats()["nonconverged_steps"] == 0
