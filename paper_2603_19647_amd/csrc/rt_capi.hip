@@ -242,7 +242,7 @@ static rtrom_status validate(const rtrom_problem_desc *d) {
   if (variant && d->dim == 1 && d->nx > RT_WAVE_MAX_CELLS)
     return fail(RTROM_EINVAL, "McClarren-Haut and BDF2 run on slabs of at most 2048 cells");
   if (d->time_scheme == RTROM_BDF2 && d->dim == 2) return fail(RTROM_EINVAL, "BDF2 runs on slabs only");
-  if (d->pc_levels > 1 && !(d->dim == 1 && d->nx <= RT_WAVE_MAX_CELLS))
+  if (d->pc_levels > 1 && d->dim == 1 && d->nx > RT_WAVE_MAX_CELLS)
     return fail(RTROM_EINVAL, "correction ROMs beyond the first iteration run on slabs of at most 2048 cells");
   if (d->scheme != RTROM_FV && d->scheme != RTROM_DG1) return fail(RTROM_EINVAL, "unknown scheme");
   if (d->scheme == RTROM_DG1) {
@@ -899,7 +899,7 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
         rt_prof_end(RT_K_POST, s2);
         if (nc_grid > 0) {  // instances without a fused post
           rt_prof_begin(RT_K_ROM_UPDATE, s2);
-          RT_HIP(rt_launch_rom_update(dinsts, n, nc_grid, s2), "ROM update launch");
+          RT_HIP(rt_launch_rom_update(dinsts, n, nc_grid, 2, s2), "ROM update launch");
           rt_prof_end(RT_K_ROM_UPDATE, s2);
         }
       }

@@ -39,11 +39,12 @@ extern "C" hipError_t rt_launch_slab_si(const Inst *dinsts, int ninst, int nthre
                                         hipStream_t stream);
 extern "C" hipError_t rt_launch_slab_fpass(const Inst *dinsts, int ninst, int nthreads, int cmax, int npair_max,
                                            int nc_max, int pairs_total, hipStream_t stream);
-extern "C" hipError_t rt_launch_rom(const Inst *dinsts, int ninst, int nc_max, int any_rom, hipStream_t s);
+// nrom: 1 + the largest number of correction levels in the launch
+extern "C" hipError_t rt_launch_rom(const Inst *dinsts, int ninst, int nc_max, int any_rom, int nrom, hipStream_t s);
 // nrom: 1 + the largest number of correction levels in the launch
 extern "C" hipError_t rt_launch_rom_slab(const Inst *dinsts, int ninst, int any_fused, int nc_grid, int nrom,
                                          hipStream_t s);
-extern "C" hipError_t rt_launch_rom_update(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream);
+extern "C" hipError_t rt_launch_rom_update(const Inst *dinsts, int ninst, int nc_max, int nrom, hipStream_t stream);
 extern "C" hipError_t rt_launch_slab_rhs(const Inst *dinsts, int ninst, int nthreads, int cmax, int npair_max,
                                          int nc_max, hipStream_t stream);
 // kinds: bit 0 -- the launch holds instances of the default configuration,

@@ -608,14 +608,20 @@ __global__ void k_plane_setup(DsaArgs D, const double *ct, const double *sa, dou
 
 // per-step status for the ROM kernels and the counters
 __global__ void k_plane_status(RtState *st, int iters, int conv, int used_pc, int ig_fb, int pc_fb, double resid,
-                               int n32) {
+                               int n32, int used_mask, int lv_fb) {
   st->iters = iters;
+  st->used_mask = used_mask;
+  st->lv_fb = lv_fb;
   st->conv = conv;
   st->used_pc = used_pc;
   st->ig_fb = ig_fb;
   st->pc_fb = pc_fb;
   st->residual = resid;
-  st->phase = !st->flag_ig ? 1 : (!st->flag_pc ? 2 : 3);
+  // phases 1, 2, 3 and, with correction ROMs of later iterations, one more
+  // for each complete level (as the slab kernels count them)
+  int ph = !st->flag_ig ? 1 : (!st->flag_pc ? 2 : 3);
+  for (int k = 0; k < RT_XLEV; ++k) ph += (ph == k + 3 && st->flag_pl[k]) ? 1 : 0;
+  st->phase = ph;
   st->cur = (int)(st->steps & 1);
   st->fp32_sweeps += n32;
 }
@@ -1377,6 +1383,7 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
   hipLaunchKernelGGL(k_plane_copy, dim3(nblk), dim3(BLK), 0, s, nc, (const double *)I.rho0, H->rp);
   if (H->mh) hipLaunchKernelGGL(k_mh_reset, dim3(1), dim3(64), 0, s, H->mh);  // a model per step
   int nsweep = 0, n32 = 0, conv = 0, used_pc = 0, pc_fb = 0, exact = 0, first_corr = 1, need64 = 1;
+  int ncorr = 0, used_mask = 0, lv_fb = 0;  // corrections so far; levels applied (bit l - 1)
   double resid = 0.0;
   for (;;) {
     if (need64) {  // y = T (sigma_s rp) + b~ in FP64
@@ -1428,7 +1435,32 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
       PH(hipGetLastError());
     }
     const double *dcorr = nullptr;
-    if (rom && first_corr && st.flag_pc && st.lu_ok_pc) {
+    // correction l = ncorr + 1 of the step.  Level l of the correction ROMs
+    // (Sec. 3.2, key feature 1) keeps y_l = rho^{(l-1/2)} and rho^{(l-1)}
+    // for its pair, and applies when complete and level l - 1 applied
+    // before it.
+    const int lc = ncorr + 1;
+    bool lev_apply = false;
+    if (rom && lc >= 2 && lc <= I.nlev) {
+      const int k = lc - 2;
+      hipLaunchKernelGGL(k_plane_copy, dim3(nblk), dim3(BLK), 0, s, nc, (const double *)H->y, I.ylev[k]);
+      hipLaunchKernelGGL(k_plane_copy, dim3(nblk), dim3(BLK), 0, s, nc, (const double *)H->rp, I.rlev[k]);
+      const bool due = st.flag_pl[k] && ((used_mask >> (lc - 2)) & 1);
+      if (due && !st.lu_ok_pl[k]) lv_fb++;
+      lev_apply = due && st.lu_ok_pl[k];
+    }
+    if (lev_apply) {
+      // ROM-enhanced correction of iteration lc (eq. dmd-sa at iteration lc)
+      const int k = lc - 2;
+      rt_prof_begin(RT_K_PLANE_OTHER, s);
+      hipLaunchKernelGGL(k_plane_sub, dim3(nblk), dim3(BLK), 0, s, nc, (const double *)H->y,
+                         (const double *)H->rp, I.wlev[k]);
+      e = rom_apply_grid(p, H, I.pl[k], &I.st->rank_pl[k], I.wlev[k], I.dlev[k]);
+      rt_prof_end(RT_K_PLANE_OTHER, s);
+      if (e) return e;
+      dcorr = I.dlev[k];
+      used_mask |= 1 << (lc - 1);
+    } else if (rom && first_corr && st.flag_pc && st.lu_ok_pc) {
       rt_prof_begin(RT_K_PLANE_OTHER, s);
       hipLaunchKernelGGL(k_plane_sub, dim3(nblk), dim3(BLK), 0, s, nc, (const double *)H->y,
                          (const double *)I.rho0, I.work);
@@ -1437,6 +1469,7 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
       if (e) return e;
       dcorr = I.dpc;
       used_pc = 1;
+      used_mask |= 1;
     } else if (I.method != RT_SI_PLAIN) {
       if (rom && first_corr && st.flag_pc) pc_fb = 1;
       if (H->mh) {
@@ -1457,6 +1490,7 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
       dcorr = H->cx;
     }
     first_corr = 0;
+    ncorr++;
     if (mixed) {  // y += T (sigma_s (rp_new - rp)) with the increment in FP32
       hipLaunchKernelGGL(k_plane_increment, dim3(nblk), dim3(BLK), 0, s, nc, I.ss, (const double *)H->y, dcorr,
                          H->rp, H->src32);
@@ -1473,7 +1507,8 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
     }
   }
   hipLaunchKernelGGL(k_plane_copy, dim3(nblk), dim3(BLK), 0, s, nc, (const double *)H->y, I.rho);
-  hipLaunchKernelGGL(k_plane_status, dim3(1), dim3(1), 0, s, I.st, nsweep, conv, used_pc, ig_fb, pc_fb, resid, n32);
+  hipLaunchKernelGGL(k_plane_status, dim3(1), dim3(1), 0, s, I.st, nsweep, conv, used_pc, ig_fb, pc_fb, resid, n32,
+                     used_mask, lv_fb);
   PH(hipGetLastError());
   // ROM bookkeeping on the auxiliary stream, concurrent with the f-pass
   hipStream_t s2 = rom ? p->aux_stream : s;
@@ -1482,11 +1517,11 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
     PH(hipStreamWaitEvent(s2, p->ev_si, 0));
   }
   rt_prof_begin(RT_K_POST, s2);
-  PH(rt_launch_rom(p->dinst, 1, nc, rom, s2));
+  PH(rt_launch_rom(p->dinst, 1, nc, rom, 1 + I.nlev, s2));
   rt_prof_end(RT_K_POST, s2);
   if (rom) {
     rt_prof_begin(RT_K_ROM_UPDATE, s2);
-    PH(rt_launch_rom_update(p->dinst, 1, nc, s2));
+    PH(rt_launch_rom_update(p->dinst, 1, nc, 1 + I.nlev, s2));
     rt_prof_end(RT_K_ROM_UPDATE, s2);
   }
   hipLaunchKernelGGL((k_skew<double, 2>), qgrid, dim3(BLK), 0, s, A, I.ss, (const double *)I.rho, I.G, A.s1q);

@@ -971,8 +971,10 @@ __device__ inline void rom_rotate_own_lu(const Inst &I, const RomDev &R, const R
 // ||dpc - (rho^n - rho^(1/2))||^2 (the error indicators of Sec. 3.2) over
 // cells c0, c0 + stride, ...
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void rom_norm_parts(const Inst &I, int c0, int stride, double (&part)[3]) {
-  part[0] = part[1] = part[2] = 0.0;
+__device__ __forceinline__ void rom_norm_parts(const Inst &I, int c0, int stride, double (&part)[3 + RT_XLEV]) {
+#pragma unroll
+  for (int k = 0; k < 3 + RT_XLEV; ++k) part[k] = 0.0;
+  const int used = I.nlev > 1 ? I.st->used_mask : 0;
   for (int c = c0; c < I.nc; c += stride) {
     const double r = I.rho[c];
     part[0] = rt_fma(r, r, part[0]);
@@ -980,6 +982,13 @@ __device__ __forceinline__ void rom_norm_parts(const Inst &I, int c0, int stride
     part[1] = rt_fma(e1, e1, part[1]);
     const double e2 = I.dpc[c] - (r - I.rhalf[c]);
     part[2] = rt_fma(e2, e2, part[2]);
+    // correction ROMs of iterations l >= 2 that applied: ||dlev - (rho^n - y_l)||^2
+#pragma unroll
+    for (int k = 0; k < RT_XLEV; ++k)
+      if ((used >> (k + 1)) & 1) {
+        const double e = I.dlev[k][c] - (r - I.ylev[k][c]);
+        part[3 + k] = rt_fma(e, e, part[3 + k]);
+      }
   }
 }
 
@@ -1064,7 +1073,7 @@ struct StepIn {
 __device__ inline StepIn step_in(const RtState *st) {
   return {st->iters,   st->conv,    st->used_pc, st->ig_fb,   st->pc_fb,    st->phase,    st->cur,
           st->flag_ig, st->flag_pc, st->rank_ig, st->rank_pc, st->nonconv, st->fallbacks, st->residual,
-          st->steps,   st->si_total, st->sweeps_total, 0, 0};
+          st->steps,   st->si_total, st->sweeps_total, st->used_mask, st->lv_fb};
 }
 
 // ---------------------------------------------------------------------------

@@ -25,11 +25,11 @@ __global__ void __launch_bounds__(BLK) k_rom_norms(const Inst *__restrict__ inst
   if (I.method != RT_ROM || !I.st->flag_ig) return;
   const int nb = pass_blocks(I.nc);
   if ((int)blockIdx.x >= nb) return;
-  __shared__ double red[(BLK / 64) * 3], out[3];
-  double part[3];
+  __shared__ double red[(BLK / 64) * (3 + RT_XLEV)], out[3 + RT_XLEV];
+  double part[3 + RT_XLEV];
   rom_norm_parts(I, blockIdx.x * BLK + threadIdx.x, nb * BLK, part);
-  wg_sum_fast<3>(part, red, out);
-  if (threadIdx.x < 3) I.ig.work->part3[blockIdx.x * RT_NPART + threadIdx.x] = out[threadIdx.x];
+  wg_sum_fast<3 + RT_XLEV>(part, red, out);
+  if (threadIdx.x < 3 + RT_XLEV) I.ig.work->part3[blockIdx.x * RT_NPART + threadIdx.x] = out[threadIdx.x];
 }
 
 // ---------------------------------------------------------------------------
@@ -39,15 +39,15 @@ __global__ void __launch_bounds__(BLK) k_rom_norms(const Inst *__restrict__ inst
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_rom_decide(const Inst *__restrict__ insts) {
   const Inst &I = insts[blockIdx.x];
-  __shared__ double scratch[256], vec[4];
+  __shared__ double scratch[256], vec[3 + RT_XLEV];
   const int nb = pass_blocks(I.nc);
-  if (I.method == RT_ROM && I.st->flag_ig) sum_partials<false>(I.ig.work->part3, nb, 3, vec, scratch);
+  if (I.method == RT_ROM && I.st->flag_ig) sum_partials<false>(I.ig.work->part3, nb, 3 + RT_XLEV, vec, scratch);
   rom_decide(I, vec, I.post_nb, step_in(I.st));
 }
 
 __global__ void __launch_bounds__(BLK) k_rom_pass1(const Inst *__restrict__ insts) {
   const Inst &I = insts[blockIdx.y];
-  if (I.method != RT_ROM || I.post_fused) return;
+  if (I.method != RT_ROM || I.post_fused || (int)blockIdx.z > I.nlev) return;
   const RomDev &R = rom_of(I, blockIdx.z);
   const RomWork &W = *R.work;
   if (!W.active || (int)blockIdx.x >= W.nblk) return;
@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(BLK) k_rom_pass1(const Inst *__restrict__ inst
 
 __global__ void __launch_bounds__(BLK) k_rom_pass2(const Inst *__restrict__ insts) {
   const Inst &I = insts[blockIdx.y];
-  if (I.method != RT_ROM || I.post_fused) return;
+  if (I.method != RT_ROM || I.post_fused || (int)blockIdx.z > I.nlev) return;
   const RomDev &R = rom_of(I, blockIdx.z);
   const RomWork &W = *R.work;
   if (!W.active || (int)blockIdx.x >= W.nblk) return;
@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(BLK) k_rom_pass2(const Inst *__restrict__ inst
 // k_rom_core: rom_core after the grid passes, grid (instance, ROM).
 __global__ void __launch_bounds__(256) k_rom_core(const Inst *__restrict__ insts) {
   const Inst &I = insts[blockIdx.x];
-  if (I.method != RT_ROM || I.post_fused) return;
+  if (I.method != RT_ROM || I.post_fused || (int)blockIdx.y > I.nlev) return;
   const int z = blockIdx.y;
   const RomDev &R = rom_of(I, z);
   const RomWork &W = *R.work;
@@ -125,7 +125,8 @@ __global__ void __launch_bounds__(UPD_BLK) k_rom_update(const Inst *__restrict__
   const int cb = blockIdx.x * UPD_BLK * UPD_CPT;
   if (cb >= I.nc) return;
   const int rom = blockIdx.z >> 1, mat = blockIdx.z & 1;
-  const RomDev &R = rom ? I.pc : I.ig;
+  if (rom > I.nlev) return;
+  const RomDev &R = rom_of(I, rom);
   const RomPend &P = *R.pend;
   if (!P.pending) return;
   const RT_CONST double *cc = (const RT_CONST double *)(mat ? P.Vc : P.Uc);
@@ -151,14 +152,15 @@ __global__ void __launch_bounds__(UPD_BLK) k_rom_update(const Inst *__restrict__
   rotate_block<UPD_CPT>(old, e, cc, r, P.k, X, ld, c, ok);
 }
 
-extern "C" hipError_t rt_launch_rom(const Inst *dinsts, int ninst, int nc_max, int any_rom, hipStream_t s) {
+extern "C" hipError_t rt_launch_rom(const Inst *dinsts, int ninst, int nc_max, int any_rom, int nrom,
+                                    hipStream_t s) {
   const int nb = pass_blocks(nc_max);
   if (any_rom) hipLaunchKernelGGL(k_rom_norms, dim3(nb, ninst), dim3(BLK), 0, s, dinsts);
   hipLaunchKernelGGL(k_rom_decide, dim3(ninst), dim3(256), 0, s, dinsts);
   if (any_rom) {
-    hipLaunchKernelGGL(k_rom_pass1, dim3(nb, ninst, 2), dim3(BLK), 0, s, dinsts);
-    hipLaunchKernelGGL(k_rom_pass2, dim3(nb, ninst, 2), dim3(BLK), 0, s, dinsts);
-    hipLaunchKernelGGL(k_rom_core, dim3(ninst, 2), dim3(256), 0, s, dinsts);
+    hipLaunchKernelGGL(k_rom_pass1, dim3(nb, ninst, nrom), dim3(BLK), 0, s, dinsts);
+    hipLaunchKernelGGL(k_rom_pass2, dim3(nb, ninst, nrom), dim3(BLK), 0, s, dinsts);
+    hipLaunchKernelGGL(k_rom_core, dim3(ninst, nrom), dim3(256), 0, s, dinsts);
   }
   return hipGetLastError();
 }
@@ -178,12 +180,14 @@ extern "C" hipError_t rt_launch_rom_slab(const Inst *dinsts, int ninst, int any_
   return hipGetLastError();
 }
 
-extern "C" hipError_t rt_launch_rom_update(const Inst *dinsts, int ninst, int nc_max, hipStream_t stream) {
+extern "C" hipError_t rt_launch_rom_update(const Inst *dinsts, int ninst, int nc_max, int nrom, hipStream_t stream) {
   if ((long long)nc_max * ninst <= 65536) {
     // small: one cell per thread in narrow blocks, spread over many CUs
-    hipLaunchKernelGGL((k_rom_update<64, 1>), dim3((nc_max + 63) / 64, ninst, 4), dim3(64), 0, stream, dinsts);
+    hipLaunchKernelGGL((k_rom_update<64, 1>), dim3((nc_max + 63) / 64, ninst, 2 * nrom), dim3(64), 0, stream,
+                       dinsts);
   } else {
-    hipLaunchKernelGGL((k_rom_update<256, 1>), dim3((nc_max + 255) / 256, ninst, 4), dim3(256), 0, stream, dinsts);
+    hipLaunchKernelGGL((k_rom_update<256, 1>), dim3((nc_max + 255) / 256, ninst, 2 * nrom), dim3(256), 0, stream,
+                       dinsts);
   }
   return hipGetLastError();
 }

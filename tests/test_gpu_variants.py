@@ -233,6 +233,49 @@ def test_correction_levels_batched_bitwise():
         p.close()
 
 
+def _levels_plane(seed, n, levels, **kw):
+    sp = W.random_plane(seed, n, 8, 4, method="rom", dt=0.05, eps_ig=1e-9, eps_pc=1e-4, eps_up=1e-9, r_max=8,
+                        pc_levels=levels, **kw)
+    return sp.replace(sigma_s=np.maximum(sp.sigma_s, 0.5))
+
+
+@pytest.mark.parametrize("levels,n", [(2, 32), (3, 40)])
+def test_correction_levels_plane_fp64_match_oracle(levels, n):
+    """Sequential correction ROMs on an X-Y grid (grid passes of the same
+    ROM kernels, one per level): phases 1..L+2, counts, updates and ranks as
+    the oracle's up to the count horizon, each level's completion step and
+    rank as the oracle's when the counts agree throughout."""
+    spec = _levels_plane(30 + n, n, levels, tol=1e-10, nsteps=60)
+    nst = spec.nsteps
+    say(f"levels plane {levels} n={n}")
+    horizon = count_horizon(spec, nst)
+    errs, o, g = step_both(spec, nst)
+    assert (errs <= _rom_bar(spec, nst)).all(), errs.max()
+    ho, hg = o.history(), g.history()
+    for key in ("iters", "phase", "ig_update", "pc_update", "rank_ig", "rank_pc"):
+        np.testing.assert_array_equal(hg[key][:horizon], ho[key][:horizon], err_msg=key)
+    lo, lg = o.levels(), g.levels()
+    say(f"  horizon {horizon}; oracle levels {lo}; device {lg}")
+    assert len(lg) == levels
+    if horizon == nst:
+        assert lg == lo
+    assert hg["phase"].max() == ho["phase"].max() >= 4
+
+
+def test_correction_levels_plane_mixed_meet_fp64_bar():
+    spec = _levels_plane(35, 40, 2, tol=1e-8, precision="mixed", nsteps=40)
+    say("levels plane mixed")
+    ref = converged_reference(spec, spec.nsteps)
+    bars = mixed_bars(spec, spec.nsteps, ref, method="rom")
+    g = rtrom.Problem(spec)
+    for k in range(spec.nsteps):
+        g.step()
+        e = rel_l2(g.rho(), ref[k])
+        assert e <= bars[k], (k, e, bars[k])
+    assert g.levels()[0]["flag"] == 1
+    assert g.stats()["nonconverged_steps"] == 0
+
+
 @pytest.mark.parametrize("method", ["si_dsa", "rom"])
 def test_mh_plane_fp64_matches_oracle(method):
     """McClarren-Haut on an X-Y grid (its passes as grid kernels), alone and
