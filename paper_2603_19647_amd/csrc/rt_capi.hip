@@ -241,7 +241,6 @@ static rtrom_status validate(const rtrom_problem_desc *d) {
   const bool variant = d->precond == RTROM_PC_MH || d->time_scheme == RTROM_BDF2;
   if (variant && d->dim == 1 && d->nx > RT_WAVE_MAX_CELLS)
     return fail(RTROM_EINVAL, "McClarren-Haut and BDF2 run on slabs of at most 2048 cells");
-  if (d->time_scheme == RTROM_BDF2 && d->dim == 2) return fail(RTROM_EINVAL, "BDF2 runs on slabs only");
   if (d->pc_levels > 1 && d->dim == 1 && d->nx > RT_WAVE_MAX_CELLS)
     return fail(RTROM_EINVAL, "correction ROMs beyond the first iteration run on slabs of at most 2048 cells");
   if (d->scheme != RTROM_FV && d->scheme != RTROM_DG1) return fail(RTROM_EINVAL, "unknown scheme");
@@ -352,11 +351,12 @@ static size_t slab_bytes(const rtrom_problem_desc *d, int nv) {
   if (d->dim == 1) {  // 2D keeps its folded f in the plane buffers
     L.take((size_t)nv * nc * 8);
     L.take((size_t)(nv / 2) * nc * 8);
-    if (d->time_scheme == RTROM_BDF2) {  // f^{n-1}, sigma_t + 3/(2 dt), three DSA factor arrays
+    if (d->time_scheme == RTROM_BDF2) {  // f^{n-1}, three DSA factor arrays
       L.take((size_t)nv * nc * 8);
-      for (int k = 0; k < 4; ++k) L.take(nc * 8);
+      for (int k = 0; k < 3; ++k) L.take(nc * 8);
     }
   }
+  if (d->time_scheme == RTROM_BDF2) L.take(nc * 8);  // sigma_t + 3/(2 dt)
   if (d->precond == RTROM_PC_MH) {  // Q, Z
     L.take((size_t)mh_cap_of(d) * ld * 8);
     L.take((size_t)mh_cap_of(d) * ld * 8);
@@ -530,11 +530,13 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   I.f = d->dim == 1 ? D((size_t)nv * nc * 8) : nullptr;
   I.fpart = d->dim == 1 ? D((size_t)(nv / 2) * nc * 8) : nullptr;
   double *ctb = nullptr;
+  if (d->time_scheme == RTROM_BDF2) {
+    ctb = D(nc * 8);
+    I.ct_b = ctb;
+  }
   if (d->dim == 1 && d->time_scheme == RTROM_BDF2) {
     I.fb[0] = I.f;
     I.fb[1] = D((size_t)nv * nc * 8);
-    ctb = D(nc * 8);
-    I.ct_b = ctb;
     I.dsa_fe_b = D(nc * 8);
     I.dsa_bg_b = D(nc * 8);
     I.dsa_invd_b = D(nc * 8);

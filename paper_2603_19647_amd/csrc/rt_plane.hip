@@ -64,6 +64,7 @@ struct PlaneArgs {
   double *s1q;                // [4][SQ] sigma_s rho^n + G (skewed, f-pass)
   void *srcq;                 // [4][SQ] SI sweep source (skewed, sweep type)
   double *f;                  // [ndf][SQ] folded f, skewed in its quadrant
+  double *fo;                 // BDF2: [ndf][SQ] the older level f^{n-1} (null otherwise)
   void *partial;              // [ndf][SQ] w f per ordinate (skewed)
   double *quadsum;            // [4][SQ] per-quadrant sums (skewed)
 };
@@ -125,9 +126,9 @@ __device__ __forceinline__ void lds_publish(int *p, int v, bool writer) {
 // per-step prefetched cell data
 template <typename R>
 struct Slot {
-  R ct;               // sigma~_t
-  double a1, a2, a3;  // the mode's other per-cell inputs
-  R s;                // MODE 0 source
+  R ct;                   // sigma~_t
+  double a1, a2, a3, a4;  // the mode's other per-cell inputs (a4: BDF2's older level)
+  R s;                    // MODE 0 source
 };
 
 // MODE 0: SI sweep of the source srcq (zero inflow) -> per-ordinate w f.
@@ -135,6 +136,13 @@ struct Slot {
 //         written over f, then the right-hand-side sweep (source f^n/dt + G,
 //         inflow g) -> per-ordinate w h.
 // MODE 2: right-hand-side sweep only, from the stored f.
+// MODE 3: the BDF2 f-pass (Sec. 2.1's BDF alternative): f^n from the source
+//         sigma_s rho^n + G + (4 f^{n-1} - f^{n-2}) / (2 dt), with f^{n-1} in
+//         f and f^{n-2} in fo, written over fo (the caller then swaps f and
+//         fo), then the right-hand side of the next step from the source
+//         (4 f^n - f^{n-1}) / (2 dt) + G.
+// MODE 4: the BDF2 right-hand-side sweep only, from f (f^n) and fo (f^{n-1}).
+// The operator (sigma~_t in ctq / ctf) is the caller's: 1/dt or 3/(2 dt).
 // Ring traffic moves CH columns at a time: the top row's values are gathered
 // into lanes 0..CH-1 of a register, the consumer reads a chunk into lanes
 // 0..CH-1 and feeds its lane 0 with readlane.
@@ -142,6 +150,9 @@ template <typename R, int MODE, int PD>
 __global__ void __launch_bounds__(1024) k_plane_sweep(PlaneArgs A) {
   static_assert(CH % PD == 0, "prefetch slots rotate within a chunk");
   constexpr int NF = MODE == 0 ? 1 : 2;
+  constexpr bool FP = MODE == 1 || MODE == 3;  // computes f^n
+  constexpr bool RH = MODE == 2 || MODE == 4;  // right-hand side from the stored f
+  constexpr bool B2 = MODE >= 3;               // BDF2 history
   typedef typename std::conditional<MODE == 0, R, double>::type PT;
   __shared__ R ring[MAXW][RING][NF];
   __shared__ int prod[MAXW], cons[MAXW];
@@ -167,6 +178,8 @@ __global__ void __launch_bounds__(1024) k_plane_sweep(PlaneArgs A) {
   const R mxyr = (R)mxy;
   const R *srcq = (const R *)A.srcq + qoff;
   double *fd = A.f + doff;
+  double *fod = B2 ? A.fo + doff : nullptr;
+  const double hdt = 0.5 * A.inv_dt;  // 1 / (2 dt)
   PT *part = (PT *)A.partial + doff;
   const int wout = wv, win = (wv + NW - 1) % NW;
   int seen_prod = 0, seen_cons = 0;  // last counter values read (monotone)
@@ -184,20 +197,18 @@ __global__ void __launch_bounds__(1024) k_plane_sweep(PlaneArgs A) {
     const R *ctb = std::is_same<R, float>::value ? (const R *)(ctf + sbase) : (const R *)(ctq + sbase);
     const double *s1b = s1q + sbase, *Gb = Gq + sbase;
     double *fb0 = fd + sbase;
+    double *fob0 = B2 ? fod + sbase : nullptr;
     PT *pb0 = part + sbase;
     auto fetch = [&](Slot<R> &sl, int t) {
       const int o = t * BAND;
       sl.ct = ctb[o];
       if (MODE == 0) sl.s = srcb[o];
-      if (MODE == 1) {
-        sl.a1 = s1b[o];
+      if (FP) sl.a1 = s1b[o];
+      if (FP || RH) {
         sl.a2 = Gb[o];
         sl.a3 = fb0[o];
       }
-      if (MODE == 2) {
-        sl.a2 = Gb[o];
-        sl.a3 = fb0[o];
-      }
+      if (B2) sl.a4 = fob0[o];
     };
     // hand the top row's columns (last - cnt, last] to the band above; lane i
     // of rout holds column last - i
@@ -238,6 +249,7 @@ __global__ void __launch_bounds__(1024) k_plane_sweep(PlaneArgs A) {
       const R *srcc = srcb + t0 * BAND, *ctc = ctb + t0 * BAND;
       const double *s1c = s1b + t0 * BAND, *Gc = Gb + t0 * BAND;
       double *fc = fb0 + t0 * BAND;
+      double *foc = B2 ? fob0 + t0 * BAND : nullptr;
       PT *pc = pb0 + t0 * BAND;
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
@@ -260,14 +272,17 @@ __global__ void __launch_bounds__(1024) k_plane_sweep(PlaneArgs A) {
           fl = f;
         } else {
           const bool on = rowok && (unsigned)(t - lane) < unx;
-          if (MODE == 1) {
-            const R s1 = (R)(c.a1 + c.a3 * A.inv_dt);
+          if (FP) {
+            const R s1 = B2 ? (R)(c.a1 + (4.0 * c.a3 - c.a4) * hdt) : (R)(c.a1 + c.a3 * A.inv_dt);
             f = (s1 + my * fb + mx * fl) * inv;
-            fc[k * BAND] = (double)f;
+            (B2 ? foc : fc)[k * BAND] = (double)f;  // BDF2: f^n over f^{n-2}
           } else {
             f = (R)c.a3;
           }
-          const R s2 = rt_fma(f, idt, (R)c.a2);
+          // history of the next step: f^n / dt, or (4 f^n - f^{n-1}) / (2 dt)
+          R s2;
+          if (!B2) s2 = rt_fma(f, idt, (R)c.a2);
+          else s2 = (R)((4.0 * (double)f - (FP ? c.a3 : c.a4)) * hdt + c.a2);
           h = (s2 + my * hb + mx * hl) * inv;
           v = (PT)(w * h);
           fl = on ? f : gx;
@@ -293,15 +308,12 @@ __global__ void __launch_bounds__(1024) k_plane_sweep(PlaneArgs A) {
           const int o = (k + PD) * BAND;
           n.ct = ctc[o];
           if (MODE == 0) n.s = srcc[o];
-          if (MODE == 1) {
-            n.a1 = s1c[o];
+          if (FP) n.a1 = s1c[o];
+          if (FP || RH) {
             n.a2 = Gc[o];
             n.a3 = fc[o];
           }
-          if (MODE == 2) {
-            n.a2 = Gc[o];
-            n.a3 = fc[o];
-          }
+          if (B2) n.a4 = foc[o];
         }
       }
     }
@@ -950,6 +962,7 @@ static size_t plane_bytes_for(const rtrom_problem_desc *d) {
   auto take = [&](size_t x) { b += (x + 255) & ~size_t(255); };
   take((size_t)g.ndf * SQ * 8);     // per-ordinate partials
   take((size_t)g.ndf * SQ * 8);     // folded f
+  if (d->time_scheme == RTROM_BDF2) take((size_t)g.ndf * SQ * 8);  // BDF2: the older level
   take(4 * SQ * 8 * 5);             // ctq, Gq, s1q, srcq, quadsum
   take(4 * SQ * 4);                 // ctf
   take(nc * 8 * 7);                 // y rp dvec cr cx cd0 cd1
@@ -1094,7 +1107,9 @@ static int sweep_moment(rtrom_problem *p, PlaneHost *H, int mode, int fp32, doub
   if (mode == 0 && fp32) launch_si_sweep<float>(H->pd32, grid, block, s, A);
   else if (mode == 0) launch_si_sweep<double>(H->pd64, grid, block, s, A);
   else if (mode == 1) hipLaunchKernelGGL((k_plane_sweep<double, 1, 4>), grid, block, 0, s, A);
-  else hipLaunchKernelGGL((k_plane_sweep<double, 2, 4>), grid, block, 0, s, A);
+  else if (mode == 2) hipLaunchKernelGGL((k_plane_sweep<double, 2, 4>), grid, block, 0, s, A);
+  else if (mode == 3) hipLaunchKernelGGL((k_plane_sweep<double, 3, 4>), grid, block, 0, s, A);
+  else hipLaunchKernelGGL((k_plane_sweep<double, 4, 4>), grid, block, 0, s, A);
   rt_prof_end(kind, s);
   rt_prof_begin(RT_K_PLANE_OTHER, s);
   if (mode == 0 && fp32) hipLaunchKernelGGL(k_quad_sum<float>, qgrid, dim3(BLK), 0, s, A);
@@ -1172,6 +1187,7 @@ int rt_plane_create(rtrom_problem *p) {
   memset(&A, 0, sizeof(A));
   A.partial = take((size_t)ndf * SQ * 8);
   A.f = (double *)take((size_t)ndf * SQ * 8);
+  A.fo = d->time_scheme == RTROM_BDF2 ? (double *)take((size_t)ndf * SQ * 8) : nullptr;
   double *q5 = (double *)take(4 * SQ * 8 * 5);
   A.ctq = q5;
   A.Gq = q5 + 4 * SQ;
@@ -1294,10 +1310,31 @@ void rt_plane_destroy(rtrom_problem *p) {
   p->plane = nullptr;
 }
 
+// BDF2 after its backward-Euler start step: sigma~_t = sigma_t + 3/(2 dt)
+// in the sweeps and the DSA coefficients with the same weight.  The
+// Chebyshev interval taken at creation still holds: a larger time weight
+// only strengthens the diagonal dominance it was derived from.
+static int plane_bdf2_operator(rtrom_problem *p, PlaneHost *H) {
+  const Inst &I = p->hinst;
+  PlaneArgs &A = H->A;
+  hipStream_t s = p->stream;
+  const dim3 qgrid(A.nsblk, 4);
+  hipLaunchKernelGGL((k_skew<double, 0>), qgrid, dim3(BLK), 0, s, A, (const double *)nullptr, I.ct_b,
+                     (const double *)nullptr, (double *)A.ctq);
+  hipLaunchKernelGGL((k_skew<float, 0>), qgrid, dim3(BLK), 0, s, A, (const double *)nullptr, I.ct_b,
+                     (const double *)nullptr, (float *)A.ctf);
+  hipLaunchKernelGGL(k_plane_setup, dim3(A.nblk), dim3(BLK), 0, s, H->D, I.ct_b, I.sa, 1.5 / p->d.dt,
+                     p->d.lx / A.nx, p->d.ly / A.ny, H->diag, H->ax, H->ay, H->blkmax);
+  PH(hipGetLastError());
+  return RTROM_OK;
+}
+
 int rt_plane_rhs(rtrom_problem *p) {
   PlaneHost *H = (PlaneHost *)p->plane;
   for (int k = 0; k < 4; ++k) H->A.g[k] = p->d.inflow[k];
-  return sweep_moment(p, H, 2, 0, p->hinst.bt2[p->steps & 1], nullptr, 0, nullptr, nullptr);
+  // BDF2 after its start step: the history (4 f^n - f^{n-1}) / (2 dt)
+  const int mode = p->hinst.bdf2 && p->steps >= 1 ? 4 : 2;
+  return sweep_moment(p, H, mode, 0, p->hinst.bt2[p->steps & 1], nullptr, 0, nullptr, nullptr);
 }
 
 static int dsa_solve(rtrom_problem *p, PlaneHost *H, const double *y, const double *rp) {
@@ -1525,7 +1562,20 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
     rt_prof_end(RT_K_ROM_UPDATE, s2);
   }
   hipLaunchKernelGGL((k_skew<double, 2>), qgrid, dim3(BLK), 0, s, A, I.ss, (const double *)I.rho, I.G, A.s1q);
-  int e = sweep_moment(p, H, 1, 0, I.bt2[cur ^ 1], nullptr, 0, nullptr, nullptr);
+  int e;
+  if (I.bdf2 && st.steps == 0) {
+    // BDF2's backward-Euler start: f^1 over f with f^0 kept as the older
+    // level, then the BDF2 operator and the right-hand side of step 2
+    PH(hipMemcpyAsync(A.fo, A.f, (size_t)A.ndf * A.SQ * 8, hipMemcpyDeviceToDevice, s));
+    e = sweep_moment(p, H, 1, 0, I.bt2[cur ^ 1], nullptr, 0, nullptr, nullptr);
+    if (!e) e = plane_bdf2_operator(p, H);
+    if (!e) e = sweep_moment(p, H, 4, 0, I.bt2[cur ^ 1], nullptr, 0, nullptr, nullptr);
+  } else if (I.bdf2) {
+    e = sweep_moment(p, H, 3, 0, I.bt2[cur ^ 1], nullptr, 0, nullptr, nullptr);
+    std::swap(A.f, A.fo);  // f^n was written over f^{n-2}
+  } else {
+    e = sweep_moment(p, H, 1, 0, I.bt2[cur ^ 1], nullptr, 0, nullptr, nullptr);
+  }
   if (e) return e;
   if (s2 != s) {
     PH(hipEventRecord(p->ev_rom, s2));

@@ -153,6 +153,75 @@ def test_bdf2_mixed_meets_fp64_bar():
         assert rel_l2(g.rho(), ref[k]) <= bars[k], k
 
 
+@pytest.mark.parametrize("method,n,na,npl", [("si_dsa", 40, 8, 4), ("rom", 48, 8, 4), ("si_dsa", 70, 12, 6),
+                                             ("rom", 33, 4, 2)])
+def test_bdf2_plane_fp64_matches_oracle(method, n, na, npl):
+    """BDF2 on X-Y grids (the f-pass and right-hand-side sweeps with the
+    history (4 f^{n-1} - f^{n-2}) / (2 dt), the operator switched after the
+    backward-Euler start): per-step results, counts and ROM decisions as the
+    oracle's, f and the next right-hand side too."""
+    spec = W.random_plane(52 + n, n, na, npl, dt=0.01, tol=1e-8, method=method, time_scheme="bdf2", nsteps=30)
+    say(f"bdf2 plane fp64 {method} n={n} {na}x{npl}")
+    errs, o, g = step_both(spec, spec.nsteps)
+    bar = FP64_TOL if method == "si_dsa" else _rom_bar(spec, spec.nsteps)
+    assert (errs <= bar).all(), errs.max()
+    assert_same_decisions(o, g)
+    assert rel_l2(g.f(), o.f()) <= 1e-9
+    assert rel_l2(g.rhs(), o.bt()) <= 1e-9
+    if method == "rom":
+        assert g.history()["ig_update"][0] == 0 and g.stats()["phase"] >= 2
+
+
+def test_bdf2_plane_infinite_medium_closed_form():
+    """Infinite medium on an X-Y grid: rho^n follows the BDF2 recurrence
+    (3 + 2 dt sigma_a) u^{n+1} = 4 u^n - u^{n-1} after one backward-Euler
+    step, with the inflow set to the exact solution before each step (which
+    rebuilds the BDF2 right-hand side)."""
+    sa, dt = 0.7, 0.2
+    spec = W.infinite_medium(dim=2, n=20, n_polar=4, n_azim=8, sigma_a=sa, dt=dt, tol=1e-12).replace(
+        time_scheme="bdf2")
+    say("bdf2 plane infinite medium")
+    g = rtrom.Problem(spec)
+    u = [1.0, 1.0 / (1.0 + dt * sa)]
+    g.set_inflow([u[1]] * 4)
+    for n in range(1, 8):
+        g.step()
+        np.testing.assert_allclose(g.rho(), u[n], rtol=1e-10)
+        np.testing.assert_allclose(g.f(), u[n], rtol=1e-10)
+        u.append((4.0 * u[n] - u[n - 1]) / (3.0 + 2.0 * dt * sa))
+        g.set_inflow([u[n + 1]] * 4)
+
+
+def test_bdf2_plane_set_inflow_rebuilds_rhs():
+    spec = W.random_plane(57, 21, 8, 4, dt=0.02, tol=1e-10, time_scheme="bdf2")
+    say("bdf2 plane set_inflow")
+    o = oracle.OracleProblem(spec)
+    g = rtrom.Problem(spec)
+    for _ in range(3):
+        o.step()
+        g.step()
+    o.set_inflow((0.1, 0.9, 0.3, 0.6))
+    g.set_inflow((0.1, 0.9, 0.3, 0.6))
+    assert rel_l2(g.rhs(), o.bt()) <= FP64_TOL
+    o.step()
+    g.step()
+    assert rel_l2(g.rho(), o.rho()) <= FP64_TOL
+
+
+def test_bdf2_plane_mixed_meets_fp64_bar():
+    spec = W.random_plane(58, 48, 8, 4, method="rom", dt=0.01, tol=1e-8, time_scheme="bdf2", precision="mixed",
+                          nsteps=30)
+    say("bdf2 plane mixed rom")
+    ref = converged_reference(spec, spec.nsteps)
+    bars = mixed_bars(spec, spec.nsteps, ref, method="rom")
+    g = rtrom.Problem(spec)
+    for k in range(spec.nsteps):
+        g.step()
+        e = rel_l2(g.rho(), ref[k])
+        assert e <= bars[k], (k, e, bars[k])
+    assert g.stats()["nonconverged_steps"] == 0
+
+
 def test_variants_batched_with_default_instances_bitwise():
     """A batch mixing default, McClarren-Haut, BDF2 and combined instances:
     every instance marches to bitwise the result it reaches alone."""
