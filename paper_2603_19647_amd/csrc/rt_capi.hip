@@ -2,8 +2,12 @@
 // device arena layout, the time-marching driver and accessors.
 #include <hip/hip_runtime.h>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -16,8 +20,36 @@
 
 namespace {
 thread_local std::string g_err;
+std::atomic<int> g_next_id{0};
 }
-void rt_set_error(const std::string &m) { g_err = m; }
+
+int rt_log_level() {
+  static const int level = [] {
+    const char *e = std::getenv("RTROM_LOG");
+    return e ? std::max(0, std::atoi(e)) : 0;
+  }();
+  return level;
+}
+
+void rt_log(int level, const char *fmt, ...) {
+  if (rt_log_level() < level) return;
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  std::fprintf(stderr, "rtrom: %s\n", buf);
+  std::fflush(stderr);
+}
+
+void rt_mark(const char *msg) { roctxMarkA(msg); }
+RtRange::RtRange(const char *name) { roctxRangePushA(name); }
+RtRange::~RtRange() { roctxRangePop(); }
+
+void rt_set_error(const std::string &m) {
+  g_err = m;
+  rt_log(1, "error: %s", m.c_str());
+}
 
 extern "C" const char *rtrom_last_error(void) { return g_err.c_str(); }
 
@@ -426,6 +458,7 @@ static rtrom_status upload_inst(rtrom_problem *p) {
 
 extern "C" void rtrom_destroy_problem(rtrom_problem *p) {
   if (!p) return;
+  rt_log(2, "problem %d destroyed after %lld steps", p->id, (long long)p->steps);
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   if (p->d.dim == 2) rt_plane_destroy(p);
   if (p->arena) (void)hipFree(p->arena);
@@ -702,6 +735,15 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
     }
   }
   if (hipStreamSynchronize(p->stream) != hipSuccess) return bail(RTROM_EDEVICE, "create sync failed");
+  p->id = g_next_id.fetch_add(1);
+  if (rt_log_level() >= 2) {
+    static const char *methods[] = {"si_dsa", "rom", "si"};  // rtrom_method order
+    rt_log(2, "problem %d created: %dD, %d x %d cells, %d ordinates, %s, %s precision, %s, %s, %s, %.1f MiB",
+           p->id, d->dim, d->nx, d->dim == 2 ? d->ny : 1, p->nv,
+           methods[std::min(2, std::max(0, (int)d->method))], d->precision == RTROM_FP64 ? "fp64" : "mixed",
+           d->precond == RTROM_PC_MH ? "McClarren-Haut" : "DSA", d->time_scheme == RTROM_BDF2 ? "BDF2" : "BE",
+           d->scheme == RTROM_DG1 ? "DG-P1" : "FV", (double)(p->arena_bytes + (d->dim == 2 ? rt_plane_extra_bytes(d) : 0)) / (1 << 20));
+  }
   *out = p;
   return RTROM_OK;
 }
@@ -747,6 +789,7 @@ static rtrom_status scratch_address(int device, void **out) {
 // noalloc: take the descriptor table and states from the device scratch array
 // instead of allocating them, and never grow a step history.
 static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nsteps, bool noalloc = false) {
+  const RtRange range(n == 1 ? "rtrom_march" : "rtrom_march_batch");
   // all handles of one dimension; 1D: fused launches over the instance array.
   // A 1D batch is laid out largest first (cells x ordinate pairs): workgroups
   // are dispatched in instance order, so the longest ones start first and
@@ -1017,6 +1060,28 @@ static rtrom_status march_one_kind(rtrom_problem *const *ps_in, int n, int nstep
     if (after[i].fault) {
       rt_set_error("a cooperative grid barrier timed out; the problem's state is invalid");
       return RTROM_EDEVICE;
+    }
+  }
+  // diagnostics: ROM phase changes (roctx marks, RTROM_LOG >= 2) and one
+  // line per step (RTROM_LOG >= 3)
+  for (int i = 0; i < n; ++i) {
+    if (after[i].phase != before[i].phase) {
+      char msg[160];
+      std::snprintf(msg, sizeof(msg), "problem %d: ROM phase %d -> %d within steps %lld..%lld (N0 %d, N1 %d)",
+                    ps[i]->id, before[i].phase, after[i].phase, (long long)(ps[i]->steps - nsteps + 1),
+                    (long long)ps[i]->steps, after[i].n0, after[i].n1);
+      rt_mark(msg);
+      rt_log(2, "%s", msg);
+    }
+    if (rt_log_level() >= 3 && ps[i]->steps <= ps[i]->hist_cap) {
+      std::vector<RtStepRec> rec(nsteps);
+      RT_HIP(hipMemcpy(rec.data(), ps[i]->dhist + (ps[i]->steps - nsteps), nsteps * sizeof(RtStepRec),
+                       hipMemcpyDeviceToHost), "read step records");
+      for (int k = 0; k < nsteps; ++k)
+        rt_log(3, "problem %d step %lld: %d sweeps, phase %d, %s, residual %.3e, ranks %d / %d%s", ps[i]->id,
+               (long long)(ps[i]->steps - nsteps + k + 1), rec[k].iters, rec[k].phase,
+               rec[k].converged ? "converged" : "NOT converged", rec[k].residual, rec[k].rank_ig, rec[k].rank_pc,
+               rec[k].fallback ? ", ROM fallback" : "");
     }
   }
   if (res == RTROM_ENOCONV) rt_set_error("a time step reached max_iter without meeting the tolerance");

@@ -10,6 +10,7 @@
 
 struct rtrom_problem {
   rtrom_problem_desc d;  // copy; array pointers cleared
+  int id = 0;            // creation order in the process (diagnostics)
   int device = 0;
   int nc = 0, nv = 0;
   std::vector<double> ox, oy, oz, w;  // quadrature (host copy)
@@ -71,6 +72,21 @@ int rt_plane_needs_cyclic(int ny);
 int rt_plane_unfold(const rtrom_problem *p, double *f_host);  // folded f -> full ordinate order
 
 void rt_set_error(const std::string &msg);
+
+// Diagnostics.  RTROM_LOG (read once per process) sets what goes to stderr:
+// 0 nothing (default), 1 errors, 2 also problem creation / destruction and
+// ROM phase changes, 3 also one line per time step.  Phases and marches are
+// marked with roctx ranges and marks for rocprofv3 (--marker-trace); these
+// cost nothing measurable when no profiler is attached.
+int rt_log_level();
+void rt_log(int level, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void rt_mark(const char *msg);
+struct RtRange {
+  explicit RtRange(const char *name);
+  ~RtRange();
+  RtRange(const RtRange &) = delete;
+  RtRange &operator=(const RtRange &) = delete;
+};
 rtrom_status rt_validate(const rtrom_problem_desc *d);  // host-only checks of a description
 
 // Kernel timing (rtrom_profile_*): bracket a launch with events when enabled.

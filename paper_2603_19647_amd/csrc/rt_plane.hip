@@ -1407,6 +1407,10 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
   const int mixed = (I.precision == RT_MIXED);
   const int cur = (int)(st.steps & 1);
   const double *bt = I.bt2[cur];
+  static const char *const phase_names[] = {"rtrom_step phase 0", "rtrom_step phase 1", "rtrom_step phase 2",
+                                            "rtrom_step phase 3", "rtrom_step phase 4", "rtrom_step phase 5",
+                                            "rtrom_step phase 6"};
+  const RtRange range(phase_names[std::min(6, std::max(0, st.phase))]);
   int ig_fb = 0;
   if (rom && st.flag_ig && st.lu_ok_ig) {
     rt_prof_begin(RT_K_PLANE_OTHER, s);

@@ -150,3 +150,31 @@ def test_variant_limits_rejected_on_the_host():
         with pytest.raises(rtrom.RtromError) as e:
             rtrom.Problem(s)
         assert e.value.status == rtrom.EINVAL, s.name
+
+
+def _run_logged(code, level):
+    import subprocess
+    import sys
+    env = dict(os.environ)
+    if level is None:
+        env.pop("RTROM_LOG", None)
+    else:
+        env["RTROM_LOG"] = str(level)
+    return subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                          timeout=120)
+
+
+def test_log_level_reports_errors_on_stderr():
+    """RTROM_LOG=1 prints every error the library records (here a rejected
+    description, before any device call) to stderr; unset, it prints nothing."""
+    code = ("from paper_2603_19647_amd import rtrom, workloads as W\n"
+            "try:\n"
+            "    rtrom.Problem(W.random_slab(1, 64, 8, pc_levels=5))\n"
+            "except rtrom.RtromError as e:\n"
+            "    print('status', e.status)\n")
+    r = _run_logged(code, 1)
+    assert r.returncode == 0, r.stderr
+    assert "status" in r.stdout
+    assert "rtrom: error: pc_levels must be in 0..4" in r.stderr
+    r = _run_logged(code, None)
+    assert r.returncode == 0 and "rtrom:" not in r.stderr

@@ -1,0 +1,58 @@
+"""Diagnostics of the device path: with RTROM_LOG=3 the library prints a line
+when a problem is created, one per time step (sweeps, phase, convergence,
+residual, ranks), one per ROM phase change within a march, and one when the
+problem is destroyed.  Run in a child process so the level is read fresh."""
+import os
+import re
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+pytestmark = pytest.mark.gpu
+
+CODE = """
+from paper_2603_19647_amd import rtrom, workloads as W
+s = W.random_slab(3, 64, 8, method='rom', precision='mixed', dt=0.01, tol=1e-10, nsteps=40)
+p = rtrom.Problem(s)
+for _ in range(4):
+    p.march(10)
+h = p.history()
+st = p.stats()
+print('phases', ' '.join(map(str, h['phase'].tolist())))
+print('iters', ' '.join(map(str, h['iters'].tolist())))
+print('n0n1', st['n0'], st['n1'])
+p.close()
+"""
+
+
+def test_log_level_three_traces_a_rom_march():
+    print("diagnostics: RTROM_LOG=3 child march", flush=True)
+    env = dict(os.environ, RTROM_LOG="3")
+    r = subprocess.run([sys.executable, "-c", CODE], cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    out = dict(line.split(" ", 1) for line in r.stdout.strip().splitlines())
+    phases = list(map(int, out["phases"].split()))
+    iters = list(map(int, out["iters"].split()))
+    n0, n1 = map(int, out["n0n1"].split())
+    err = r.stderr
+    m = re.search(r"rtrom: problem (\d+) created: 1D, 64 x 1 cells, 8 ordinates, rom, mixed precision, DSA, BE, FV",
+                  err)
+    assert m, err[:2000]
+    pid = int(m.group(1))
+    steps = re.findall(rf"rtrom: problem {pid} step (\d+): (\d+) sweeps, phase (\d+), converged", err)
+    assert [int(k) for k, _, _ in steps] == list(range(1, 41))
+    assert [int(i) for _, i, _ in steps] == iters
+    assert [int(ph) for _, _, ph in steps] == phases
+    # a phase change is reported for each march whose last step's phase
+    # differs from the previous march's
+    changes = re.findall(rf"rtrom: problem {pid}: ROM phase (\d+) -> (\d+) within steps (\d+)\.\.(\d+) "
+                         rf"\(N0 (\d+), N1 (\d+)\)", err)
+    want = [(phases[a - 2], phases[a + 8], a, a + 9) for a in (11, 21, 31) if phases[a - 2] != phases[a + 8]]
+    got = [(int(a), int(b), int(c), int(d)) for a, b, c, d, _, _ in changes if int(c) > 1]
+    assert got == want and len(want) >= 1, (changes, phases)
+    assert int(changes[-1][4]) == n0 and int(changes[-1][5]) == n1
+    assert f"rtrom: problem {pid} destroyed after 40 steps" in err
