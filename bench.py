@@ -388,6 +388,29 @@ def bench_single(rtrom, W, args):
         p.close()
     full["speedup_vs_si_dsa"] = full["rom"]["steps_per_s"] / full["si_dsa"]["steps_per_s"]
     full["steps"] = cfg_steps
+    # X-Y grid: the same whole march with the variants of the method
+    # (McClarren-Haut alone and as the hybrid, Sec. 3.3 / 4.5; correction ROMs
+    # for iterations 1-2, Sec. 3.2; BDF2, Sec. 2.1; the FP64 mode)
+    variants = {}
+    for name, method, kw in (("si_mh", "si_dsa", dict(precond="mh")), ("rom_mh_hybrid", "rom", dict(precond="mh")),
+                             ("rom_levels2", "rom", dict(pc_levels=2)),
+                             ("si_dsa_bdf2", "si_dsa", dict(time_scheme="bdf2")),
+                             ("rom_bdf2", "rom", dict(time_scheme="bdf2")),
+                             ("si_dsa_fp64", "si_dsa", dict(precision="fp64")), ("rom_fp64", "rom", dict(precision="fp64"))):
+        if args.no_variants or spec.dim != 2:
+            break
+        log(f"bench: {args.workload} variant {name}: full {cfg_steps}-step march")
+        p = rtrom.Problem(spec.replace(method=method, **kw))
+        t0 = time.perf_counter()
+        p.march(cfg_steps)
+        t = time.perf_counter() - t0
+        st = p.stats()
+        variants[name] = {"steps_per_s": cfg_steps / t, "si_sweeps_per_step": st["si_iters_total"] / cfg_steps,
+                          "nonconverged_steps": st["nonconverged_steps"]}
+        p.close()
+    if variants:
+        for a, b in (("rom_bdf2", "si_dsa_bdf2"), ("rom_fp64", "si_dsa_fp64"), ("rom_mh_hybrid", "si_mh")):
+            variants[f"{a}_vs_{b}"] = variants[a]["steps_per_s"] / variants[b]["steps_per_s"]
     R, S = res["rom"], res["si_dsa"]
     value = steps / R["t"]
     nfold = nv if spec.dim == 1 else nv // 2   # 2D sweeps the Omega_z > 0 half
@@ -408,6 +431,8 @@ def bench_single(rtrom, W, args):
         "kernel_ms": kernel_ms(R["prof"]), "si_dsa_kernel_ms": kernel_ms(S["prof"]),
         "full_march": full,
     }
+    if variants:
+        extra["variants"] = variants
     name = "slab4096_gl64_32regions" if spec.dim == 1 else "checkerboard256_cl16x8"
     config = {"workload": name, "cells": nc, "ordinates": nv, "dt": spec.dt, "steps": steps,
               "timed_steps": f"{warm + 1}..{warm + steps}", "tol": spec.tol, "method": "rom_si_dsa",
@@ -544,7 +569,7 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=4.0, help="serving: HBM admission budget")
     ap.add_argument("--slots", type=int, default=8, help="serving: concurrent problems")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-variants", action="store_true", help="batch512: skip the variant marches")
+    ap.add_argument("--no-variants", action="store_true", help="batch512, checker256: skip the variant marches")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device five times (a plain copy of known size, "
                          "against which hardware byte counters are scaled)")
