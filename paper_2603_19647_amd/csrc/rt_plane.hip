@@ -1392,6 +1392,16 @@ static int read_residual(rtrom_problem *p, PlaneHost *H, double *dn, double *yn)
   return RTROM_OK;
 }
 
+// Mixed precision near convergence.  An FP32 increment sweep costs about 3/4
+// of an FP64 sweep here (the 2D sweep is bound by its dependency chain, not
+// by arithmetic width), and an FP32-refined iterate still needs an FP64
+// certification sweep, so FP32 increments only pay while several more
+// corrections are to come.  Once an FP64-swept iterate is within this factor
+// of the tolerance the step continues in FP64 (the correction updates rho and
+// the next sweep is FP64), and a step that ran no FP32 sweep stops at tol, as
+// the FP64 mode does.
+constexpr double kFp64Band = 1000.0;
+
 // One backward-Euler step: Alg. 1 with the ROM hooks of Alg. 2 (initial guess
 // and first correction), the loop driven from the host on the residual norms.
 static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
@@ -1425,6 +1435,7 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
   if (H->mh) hipLaunchKernelGGL(k_mh_reset, dim3(1), dim3(64), 0, s, H->mh);  // a model per step
   int nsweep = 0, n32 = 0, conv = 0, used_pc = 0, pc_fb = 0, exact = 0, first_corr = 1, need64 = 1;
   int ncorr = 0, used_mask = 0, lv_fb = 0;  // corrections so far; levels applied (bit l - 1)
+  int last_exact = 0;                       // whether the previous checked iterate came from an FP64 sweep
   double resid = 0.0;
   for (;;) {
     if (need64) {  // y = T (sigma_s rp) + b~ in FP64
@@ -1442,7 +1453,9 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
     int e = read_residual(p, H, &dn, &yn);
     if (e) return e;
     resid = yn > 0.0 ? dn / yn : dn;
-    const double tt = exact ? I.tol_cert : I.tol32;
+    // an FP64-swept iterate of a step that ran no FP32 sweep is an FP64-mode
+    // iterate and stops at tol
+    const double tt = exact ? (n32 > 0 ? I.tol_cert : I.tol) : I.tol32;
     const bool pass = yn > 0.0 ? (dn < tt * yn) : (dn < tt);
     if (pass) {
       if (exact) {
@@ -1457,9 +1470,9 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
     if (H->mh) {
       // McClarren-Haut: the pair of this iteration, (rho^{(l-1)} - rho^{(l-2)},
       // y_l - y_{l-1}); in mixed precision an iterate recomputed by an FP64
-      // sweep starts a new chain of FP32 increments instead (its difference
-      // to the accumulated y_{l-1} would carry that chain's drift)
-      if (nsweep >= 2 && !(mixed && exact)) {
+      // sweep after FP32 increments starts a new chain instead (its
+      // difference to the accumulated y_{l-1} would carry that chain's drift)
+      if (nsweep >= 2 && !(mixed && exact && !last_exact)) {
         const double *rp_ = H->rp, *y_ = H->y;
         hipLaunchKernelGGL(k_mh_pass1, dim3(nblk), dim3(BLK), 0, s, I, nc, rp_, (const double *)H->rp2, y_,
                            (const double *)H->yp, H->mh, H->rpart);
@@ -1475,6 +1488,7 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
       hipLaunchKernelGGL(k_plane_copy, dim3(nblk), dim3(BLK), 0, s, nc, (const double *)H->rp, H->rp2);
       PH(hipGetLastError());
     }
+    last_exact = exact;
     const double *dcorr = nullptr;
     // correction l = ncorr + 1 of the step.  Level l of the correction ROMs
     // (Sec. 3.2, key feature 1) keeps y_l = rho^{(l-1/2)} and rho^{(l-1)}
@@ -1532,7 +1546,7 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
     }
     first_corr = 0;
     ncorr++;
-    if (mixed) {  // y += T (sigma_s (rp_new - rp)) with the increment in FP32
+    if (mixed && !(exact && resid < kFp64Band * I.tol)) {  // y += T (sigma_s (rp_new - rp)), increment in FP32
       hipLaunchKernelGGL(k_plane_increment, dim3(nblk), dim3(BLK), 0, s, nc, I.ss, (const double *)H->y, dcorr,
                          H->rp, H->src32);
       hipLaunchKernelGGL((k_skew<float, 0, float>), qgrid, dim3(BLK), 0, s, A, (const double *)nullptr,
