@@ -36,6 +36,15 @@ struct RomPend {
 #define RT_WAVE_MAX_CELLS 2048
 // piecewise-linear DG slabs: at most this many cells (two unknowns each)
 #define RT_DG_MAX_CELLS 1024
+// Mixed precision near convergence.  An FP32 increment sweep costs a large
+// share of an FP64 sweep (the sweeps are bound by their dependency chains,
+// not by arithmetic width: about 3/4 in 2D), and an FP32-refined iterate
+// still needs an FP64 certification sweep, so FP32 increments only pay while
+// several more corrections are to come.  Once an FP64-swept iterate is within
+// this factor of the tolerance the step continues in FP64 (the correction
+// updates rho and the next sweep is FP64).  Every FP64-swept iterate of the
+// mixed mode is still tested at the tightened certification tolerance.
+#define RT_FP64_BAND 1000.0
 __host__ __device__ inline int rt_pass_blocks(int nc) {
   const int nb = (nc + 255) / 256;
   return nb < 64 ? nb : 64;

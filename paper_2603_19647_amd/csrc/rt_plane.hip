@@ -1392,16 +1392,6 @@ static int read_residual(rtrom_problem *p, PlaneHost *H, double *dn, double *yn)
   return RTROM_OK;
 }
 
-// Mixed precision near convergence.  An FP32 increment sweep costs about 3/4
-// of an FP64 sweep here (the 2D sweep is bound by its dependency chain, not
-// by arithmetic width), and an FP32-refined iterate still needs an FP64
-// certification sweep, so FP32 increments only pay while several more
-// corrections are to come.  Once an FP64-swept iterate is within this factor
-// of the tolerance the step continues in FP64 (the correction updates rho and
-// the next sweep is FP64), and a step that ran no FP32 sweep stops at tol, as
-// the FP64 mode does.
-constexpr double kFp64Band = 1000.0;
-
 // One backward-Euler step: Alg. 1 with the ROM hooks of Alg. 2 (initial guess
 // and first correction), the loop driven from the host on the residual norms.
 static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
@@ -1453,9 +1443,7 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
     int e = read_residual(p, H, &dn, &yn);
     if (e) return e;
     resid = yn > 0.0 ? dn / yn : dn;
-    // an FP64-swept iterate of a step that ran no FP32 sweep is an FP64-mode
-    // iterate and stops at tol
-    const double tt = exact ? (n32 > 0 ? I.tol_cert : I.tol) : I.tol32;
+    const double tt = exact ? I.tol_cert : I.tol32;
     const bool pass = yn > 0.0 ? (dn < tt * yn) : (dn < tt);
     if (pass) {
       if (exact) {
@@ -1546,7 +1534,7 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
     }
     first_corr = 0;
     ncorr++;
-    if (mixed && !(exact && resid < kFp64Band * I.tol)) {  // y += T (sigma_s (rp_new - rp)), increment in FP32
+    if (mixed && !(exact && resid < RT_FP64_BAND * I.tol)) {  // y += T (sigma_s (rp_new - rp)), increment in FP32
       hipLaunchKernelGGL(k_plane_increment, dim3(nblk), dim3(BLK), 0, s, nc, I.ss, (const double *)H->y, dcorr,
                          H->rp, H->src32);
       hipLaunchKernelGGL((k_skew<float, 0, float>), qgrid, dim3(BLK), 0, s, A, (const double *)nullptr,

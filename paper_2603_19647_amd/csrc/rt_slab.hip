@@ -565,7 +565,7 @@ __global__ void __launch_bounds__(MAXT) k_si_slab(const Inst *__restrict__ insts
       dsa_solve_slab<CMAX>(I, c0, n, rhs, d, slots, parity);
     }
     first_corr = 0;
-    if (mixed) {
+    if (mixed && !(exact && resid < RT_FP64_BAND * I.tol)) {
       // y <- y + T32 Sigma_s (rho^{(l)} - rho^{(l-1)}): increment swept in FP32
       float s32[CMAX], acc32[CMAX], ctf[CMAX];
 #pragma unroll

@@ -548,7 +548,7 @@ __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts)
   int parity = 0;
   int nsweep = 0, n32 = 0, conv = 0, used_pc = 0, pc_fb = 0, exact = 0, first_corr = 1;
   int ncorr = 0, used_mask = 0, lv_fb = 0;  // corrections so far; levels applied (bit l - 1)
-  int need64 = 1;
+  int need64 = 1, last_exact = 0;  // last_exact: whether the previous checked iterate came from an FP64 sweep
   double resid = 0.0;
   // McClarren-Haut: y_{l-1} and rho^{(l-2)}; the model lives within the step
   double yp[WOWN], rp2[WOWN];
@@ -635,7 +635,7 @@ __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts)
       // difference to the accumulated y_{l-1} would carry that chain's
       // rounding drift, not T Sigma_s x.  Such an iteration starts a new
       // chain instead of adding a pair.
-      if (nsweep >= 2 && !(mixed && exact)) {
+      if (nsweep >= 2 && !(mixed && exact && !last_exact)) {
         double x[WOWN], z[WOWN];
 #pragma unroll
         for (int t = 0; t < WOWN; ++t) {
@@ -650,6 +650,7 @@ __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts)
         rp2[t] = rp[t];
       }
     }
+    last_exact = exact;
     // synthetic acceleration; correction l = ncorr + 1 of the step.  Level l
     // of the correction ROMs keeps y_l = rho^{(l-1/2)} and rho^{(l-1)} for its
     // pair, and applies when complete and level l - 1 applied before it.
@@ -712,7 +713,7 @@ __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts)
     }
     first_corr = 0;
     ncorr++;
-    if (mixed) {
+    if (mixed && !(exact && resid < RT_FP64_BAND * I.tol)) {
       // y <- y + T32 Sigma_s (rho^{(l)} - rho^{(l-1)}): increment swept in FP32
 #pragma unroll
       for (int t = 0; t < WOWN; ++t) {
