@@ -1014,12 +1014,42 @@ static void launch_si_sweep(int pd, dim3 grid, dim3 block, hipStream_t s, const 
 // sweeps at every depth (one warm-up and three timed launches each, HIP
 // events on the problem's stream; the sweep writes only its scratch
 // partials, so the state is untouched) and keeps the fastest; later problems
-// of the same shape reuse the choice.  RTROM_TUNE=0 keeps depth 8;
-// RTROM_PLANE_PD="<fp32>,<fp64>" fixes both; RTROM_TUNE_LOG=1 prints the
-// timings.
+// of the same shape reuse the choice.  RTROM_TUNE_CACHE names a text file
+// that keeps the choices across processes (one line per shape,
+// "plane_sweep_pd nx ny ndf pd32 pd64", read at the first tuning, appended
+// after each new one; lines that do not parse are ignored).  RTROM_TUNE=0
+// keeps depth 8; RTROM_PLANE_PD="<fp32>,<fp64>" fixes both; RTROM_TUNE_LOG=1
+// prints the timings.
 namespace {
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, std::pair<int, int>> g_tune;
+bool g_tune_file_read = false;
+bool valid_depth(int v) { return v == 2 || v == 4 || v == 8 || v == 16; }
+// with g_tune_mu held
+void tune_cache_load() {
+  if (g_tune_file_read) return;
+  g_tune_file_read = true;
+  const char *path = std::getenv("RTROM_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return;
+  char line[256];
+  while (std::fgets(line, sizeof(line), f)) {
+    int nx, ny, ndf, a, b;
+    if (std::sscanf(line, "plane_sweep_pd %d %d %d %d %d", &nx, &ny, &ndf, &a, &b) == 5 && valid_depth(a) &&
+        valid_depth(b))
+      g_tune[std::make_tuple(nx, ny, ndf)] = {a, b};
+  }
+  std::fclose(f);
+}
+void tune_cache_append(int nx, int ny, int ndf, int a, int b) {
+  const char *path = std::getenv("RTROM_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "plane_sweep_pd %d %d %d %d %d\n", nx, ny, ndf, a, b);
+  std::fclose(f);
+}
 }  // namespace
 
 static int tune_si_sweep(rtrom_problem *p, PlaneHost *H) {
@@ -1027,9 +1057,8 @@ static int tune_si_sweep(rtrom_problem *p, PlaneHost *H) {
   if (fixed) {
     int a = 8, b = 8;
     if (std::sscanf(fixed, "%d,%d", &a, &b) == 2) {
-      auto ok = [](int v) { return v == 2 || v == 4 || v == 8 || v == 16; };
-      H->pd32 = ok(a) ? a : 8;
-      H->pd64 = ok(b) ? b : 8;
+      H->pd32 = valid_depth(a) ? a : 8;
+      H->pd64 = valid_depth(b) ? b : 8;
     }
     return RTROM_OK;
   }
@@ -1039,10 +1068,13 @@ static int tune_si_sweep(rtrom_problem *p, PlaneHost *H) {
   const auto key = std::make_tuple(A.nx, A.ny, A.ndf);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache_load();
     auto it = g_tune.find(key);
     if (it != g_tune.end()) {
       H->pd32 = it->second.first;
       H->pd64 = it->second.second;
+      rt_log(2, "plane %dx%d, %d folded ordinates: SI sweep prefetch depths %d (FP32) / %d (FP64), cached", A.nx,
+             A.ny, A.ndf, H->pd32, H->pd64);
       return RTROM_OK;
     }
   }
@@ -1091,8 +1123,11 @@ static int tune_si_sweep(rtrom_problem *p, PlaneHost *H) {
   }
   H->pd32 = best[0];
   H->pd64 = best[1];
+  rt_log(2, "plane %dx%d, %d folded ordinates: SI sweep prefetch depths %d (FP32) / %d (FP64), tuned", A.nx, A.ny,
+         A.ndf, H->pd32, H->pd64);
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune[key] = {best[0], best[1]};
+  if (g_tune.emplace(key, std::make_pair(best[0], best[1])).second)
+    tune_cache_append(A.nx, A.ny, A.ndf, best[0], best[1]);
   return RTROM_OK;
 }
 

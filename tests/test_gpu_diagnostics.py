@@ -56,3 +56,47 @@ def test_log_level_three_traces_a_rom_march():
     assert got == want and len(want) >= 1, (changes, phases)
     assert int(changes[-1][4]) == n0 and int(changes[-1][5]) == n1
     assert f"rtrom: problem {pid} destroyed after 40 steps" in err
+
+
+TUNE_CODE = """
+import sys
+import numpy as np
+from paper_2603_19647_amd import rtrom, workloads as W
+s = W.random_plane(3, 40, 8, 4, method='rom', precision='mixed', nsteps=4)
+p = rtrom.Problem(s)
+p.march(4)
+np.save(sys.argv[1], p.rho())
+p.close()
+"""
+
+
+def test_tune_cache_file_round_trip(tmp_path):
+    """RTROM_TUNE_CACHE: the first process tunes the 2D sweep's prefetch
+    depths for the grid shape and appends them to the file; a later process
+    takes the file's choice without tuning, and (the depth changes only how
+    far ahead loads are issued) reaches bitwise the same result."""
+    cache = tmp_path / "tune.txt"
+    print("diagnostics: tuning cache, first process", flush=True)
+    env = dict(os.environ, RTROM_LOG="2", RTROM_TUNE_CACHE=str(cache))
+    env.pop("RTROM_PLANE_PD", None)
+    env.pop("RTROM_TUNE", None)
+    a = tmp_path / "a.npy"
+    r = subprocess.run([sys.executable, "-c", TUNE_CODE, str(a)], cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert re.search(r"plane 40x40, 16 folded ordinates: SI sweep prefetch depths \d+ \(FP32\) / \d+ \(FP64\), tuned",
+                     r.stderr), r.stderr[-2000:]
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and re.fullmatch(r"plane_sweep_pd 40 40 16 (2|4|8|16) (2|4|8|16)", lines[0]), lines
+    # a cached choice other than the tuned one is taken as it is
+    cache.write_text("not a cache line\nplane_sweep_pd 40 40 16 2 16\n")
+    print("diagnostics: tuning cache, second process", flush=True)
+    b = tmp_path / "b.npy"
+    r = subprocess.run([sys.executable, "-c", TUNE_CODE, str(b)], cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "SI sweep prefetch depths 2 (FP32) / 16 (FP64), cached" in r.stderr, r.stderr[-2000:]
+    assert "tuned" not in r.stderr
+    assert cache.read_text().splitlines()[-1] == "plane_sweep_pd 40 40 16 2 16"
+    import numpy as np
+    np.testing.assert_array_equal(np.load(a), np.load(b))
