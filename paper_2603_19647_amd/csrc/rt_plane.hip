@@ -464,18 +464,22 @@ __device__ __forceinline__ double dsa_Ax(const DsaArgs &D, const double *x, int 
 }
 
 // Chebyshev DSA solve in blocks of DS iterations, one launch per block.
-// Tiles of DT x DT cells, one workgroup of DTHR threads per tile.  A launch
-// reads the tile's directions and residuals over a halo of DS cells and
-// iterates DS times with the directions in LDS and everything pointwise
-// (residual, solution, operator coefficients) in registers; the valid region
-// shrinks by one cell per iteration.  Each cell sees exactly the arithmetic of
-// one global iteration, so the result does not depend on the tiling.  Kernel
+// Tiles of TE x TE cells (TE = 32 or 16, chosen per grid shape by the
+// autotuner: the smaller tile gives four times the workgroups for twice the
+// halo work), one workgroup of DTHR threads per tile.  A launch reads the
+// tile's directions and residuals over a halo of DS cells and iterates DS
+// times with the directions in LDS and everything pointwise (residual,
+// solution, operator coefficients) in registers; the valid region shrinks by
+// one cell per iteration.  Each cell sees exactly the arithmetic of one
+// global iteration, so the result does not depend on the tiling.  Kernel
 // boundaries order the blocks: no grid-wide synchronisation inside a launch.
-constexpr int DT = 32;               // interior tile edge
 constexpr int DS = 8;                // iterations per launch (halo)
-constexpr int DE = DT + 2 * DS;      // extended tile edge
-constexpr int DTHR = 1024;           // threads per workgroup
-constexpr int DPT = (DE * DE + DTHR - 1) / DTHR;  // extended cells per thread
+constexpr int DTHR = 1024;           // threads per workgroup of k_dsa_block
+template <int TE>
+struct DsaTile {
+  static constexpr int E = TE + 2 * DS;                      // extended tile edge
+  static constexpr int PT = (E * E + DTHR - 1) / DTHR;       // extended cells per thread
+};
 
 struct DsaSolve {
   DsaArgs D;
@@ -487,12 +491,13 @@ struct DsaSolve {
   double inv_theta;
 };
 
-// r = sigma_s (y - rp), x = 0, d = r / (theta diag)
-__global__ void __launch_bounds__(DTHR) k_dsa_init(DsaSolve S) {
+// r = sigma_s (y - rp), x = 0, d = r / (theta diag); TE x TE threads per tile
+template <int TE>
+__global__ void __launch_bounds__(TE * TE) k_dsa_init(DsaSolve S) {
   const DsaArgs &D = S.D;
   const int tile = blockIdx.x;
   const int tx = tile % S.ntx, ty = tile / S.ntx;
-  const int ix = tx * DT + (int)threadIdx.x % DT, iy = ty * DT + (int)threadIdx.x / DT;
+  const int ix = tx * TE + (int)threadIdx.x % TE, iy = ty * TE + (int)threadIdx.x / TE;
   if (ix < D.nx && iy < D.ny) {
     const int c = iy * D.nx + ix;
     const double rhs = S.ss[c] * (S.y[c] - S.rp[c]);
@@ -504,7 +509,9 @@ __global__ void __launch_bounds__(DTHR) k_dsa_init(DsaSolve S) {
 
 // iterations done .. done + nit - 1, reading buffer cur and writing cur ^ 1;
 // the last block closes x with the final direction
+template <int TE>
 __global__ void __launch_bounds__(DTHR) k_dsa_block(DsaSolve S, int done, int nit, int last, int cur) {
+  constexpr int DT = TE, DE = DsaTile<TE>::E, DPT = DsaTile<TE>::PT;
   __shared__ double sd[DE * DE];
   const DsaArgs &D = S.D;
   const int nx = D.nx, ny = D.ny;
@@ -512,7 +519,7 @@ __global__ void __launch_bounds__(DTHR) k_dsa_block(DsaSolve S, int done, int ni
   double *dout = cur ? S.d0 : S.d1, *rout = cur ? S.r0 : S.r1;
   const int tile = blockIdx.x;
   const int tx = tile % S.ntx, ty = tile / S.ntx;
-  double dg[DPT], ar[DPT], al[DPT], au[DPT], ad[DPT], r[DPT], xr[DPT];
+  double dg[DPT], idg[DPT], ar[DPT], al[DPT], au[DPT], ad[DPT], r[DPT], xr[DPT];
 #pragma unroll
   for (int i = 0; i < DPT; ++i) {
     const int e = threadIdx.x + DTHR * i;
@@ -522,6 +529,7 @@ __global__ void __launch_bounds__(DTHR) k_dsa_block(DsaSolve S, int done, int ni
     const int c = in ? iy * nx + ix : 0;
     // links to out-of-grid neighbours are zero; those cells carry d = 0
     dg[i] = in ? D.diag[c] : 1.0;
+    idg[i] = rt_rcp(dg[i]);  // the Jacobi scaling, once per launch
     ar[i] = in ? D.ax[c] : 0.0;
     au[i] = in ? D.ay[c] : 0.0;
     al[i] = in && ix > 0 ? D.ax[c - 1] : 0.0;
@@ -548,7 +556,7 @@ __global__ void __launch_bounds__(DTHR) k_dsa_block(DsaSolve S, int done, int ni
         v -= au[i] * sd[e + DE];
         v -= ad[i] * sd[e - DE];
         r[i] = r[i] - v;
-        dn[i] = c1 * dc + c2 * r[i] / dg[i];
+        dn[i] = c1 * dc + c2 * r[i] * idg[i];
       }
     }
     __syncthreads();
@@ -934,6 +942,7 @@ struct PlaneHost {
   MhGrid *mh = nullptr;                  // McClarren-Haut model state
   int cheb_iters = 0;
   int pd32 = 8, pd64 = 8;  // prefetch depth of the SI sweeps (FP32 / FP64), tuned per grid shape
+  int dsa_tile = 32;       // tile edge of the Chebyshev DSA kernels (32 or 16), tuned per grid shape
   double cheb_theta = 1.0, cheb_delta = 0.0;
   double *cheb_c = nullptr;                 // device: c1[K], c2[K]
   size_t bytes = 0;
@@ -1009,22 +1018,31 @@ static void launch_si_sweep(int pd, dim3 grid, dim3 block, hipStream_t s, const 
   }
 }
 
-// Autotuner of the SI sweep's prefetch depth.  For each grid shape (nx, ny,
-// folded ordinates) the first problem created times the FP32 and FP64 SI
-// sweeps at every depth (one warm-up and three timed launches each, HIP
-// events on the problem's stream; the sweep writes only its scratch
-// partials, so the state is untouched) and keeps the fastest; later problems
-// of the same shape reuse the choice.  RTROM_TUNE_CACHE names a text file
-// that keeps the choices across processes (one line per shape,
-// "plane_sweep_pd nx ny ndf pd32 pd64", read at the first tuning, appended
-// after each new one; lines that do not parse are ignored).  RTROM_TUNE=0
-// keeps depth 8; RTROM_PLANE_PD="<fp32>,<fp64>" fixes both; RTROM_TUNE_LOG=1
-// prints the timings.
+static int dsa_solve(rtrom_problem *p, PlaneHost *H, const double *y, const double *rp);
+
+// Autotuner of the X-Y shapes: the SI sweep's prefetch depth and the tile
+// edge of the Chebyshev DSA kernels.  For each grid shape (nx, ny, folded
+// ordinates) the first problem created times the FP32 and FP64 SI sweeps at
+// every depth and the DSA solve at both tile edges (one warm-up and three
+// timed launches each, HIP events on the problem's stream; the sweeps write
+// only their scratch partials and the DSA only its scratch vectors, so the
+// state is untouched) and keeps the fastest; later problems of the same
+// shape reuse the choice.  Neither choice changes the arithmetic of any cell,
+// so results are bitwise the same whatever is chosen.  RTROM_TUNE_CACHE
+// names a text file that keeps the choices across processes (one line per
+// shape, "plane_tune nx ny ndf pd32 pd64 dsa_tile", read at the first tuning,
+// appended after each new one; lines that do not parse are ignored).
+// RTROM_TUNE=0 keeps depth 8 and tile 32; RTROM_PLANE_PD="<fp32>,<fp64>" and
+// RTROM_DSA_TILE=<16|32> fix them; RTROM_TUNE_LOG=1 prints the timings.
 namespace {
+struct PlaneTune {
+  int pd32, pd64, tile;
+};
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int>, std::pair<int, int>> g_tune;
+std::map<std::tuple<int, int, int>, PlaneTune> g_tune;
 bool g_tune_file_read = false;
 bool valid_depth(int v) { return v == 2 || v == 4 || v == 8 || v == 16; }
+bool valid_tile(int v) { return v == 16 || v == 32; }
 // with g_tune_mu held
 void tune_cache_load() {
   if (g_tune_file_read) return;
@@ -1035,24 +1053,27 @@ void tune_cache_load() {
   if (!f) return;
   char line[256];
   while (std::fgets(line, sizeof(line), f)) {
-    int nx, ny, ndf, a, b;
-    if (std::sscanf(line, "plane_sweep_pd %d %d %d %d %d", &nx, &ny, &ndf, &a, &b) == 5 && valid_depth(a) &&
-        valid_depth(b))
-      g_tune[std::make_tuple(nx, ny, ndf)] = {a, b};
+    int nx, ny, ndf, a, b, t;
+    if (std::sscanf(line, "plane_tune %d %d %d %d %d %d", &nx, &ny, &ndf, &a, &b, &t) == 6 && valid_depth(a) &&
+        valid_depth(b) && valid_tile(t))
+      g_tune[std::make_tuple(nx, ny, ndf)] = {a, b, t};
   }
   std::fclose(f);
 }
-void tune_cache_append(int nx, int ny, int ndf, int a, int b) {
+void tune_cache_append(int nx, int ny, int ndf, const PlaneTune &c) {
   const char *path = std::getenv("RTROM_TUNE_CACHE");
   if (!path || !*path) return;
   FILE *f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "plane_sweep_pd %d %d %d %d %d\n", nx, ny, ndf, a, b);
+  std::fprintf(f, "plane_tune %d %d %d %d %d %d\n", nx, ny, ndf, c.pd32, c.pd64, c.tile);
   std::fclose(f);
 }
 }  // namespace
 
-static int tune_si_sweep(rtrom_problem *p, PlaneHost *H) {
+static int tune_plane(rtrom_problem *p, PlaneHost *H) {
+  const char *ftile = std::getenv("RTROM_DSA_TILE");
+  const int fixed_tile = ftile && valid_tile(std::atoi(ftile)) ? std::atoi(ftile) : 0;
+  H->dsa_tile = fixed_tile ? fixed_tile : 32;
   const char *fixed = std::getenv("RTROM_PLANE_PD");
   if (fixed) {
     int a = 8, b = 8;
@@ -1071,10 +1092,11 @@ static int tune_si_sweep(rtrom_problem *p, PlaneHost *H) {
     tune_cache_load();
     auto it = g_tune.find(key);
     if (it != g_tune.end()) {
-      H->pd32 = it->second.first;
-      H->pd64 = it->second.second;
-      rt_log(2, "plane %dx%d, %d folded ordinates: SI sweep prefetch depths %d (FP32) / %d (FP64), cached", A.nx,
-             A.ny, A.ndf, H->pd32, H->pd64);
+      H->pd32 = it->second.pd32;
+      H->pd64 = it->second.pd64;
+      H->dsa_tile = fixed_tile ? fixed_tile : it->second.tile;
+      rt_log(2, "plane %dx%d, %d folded ordinates: SI sweep prefetch depths %d (FP32) / %d (FP64), DSA tile %d, cached",
+             A.nx, A.ny, A.ndf, H->pd32, H->pd64, H->dsa_tile);
       return RTROM_OK;
     }
   }
@@ -1087,47 +1109,71 @@ static int tune_si_sweep(rtrom_problem *p, PlaneHost *H) {
     rt_set_error("plane: tuning event");
     return RTROM_EDEVICE;
   }
-  const int depths[4] = {2, 4, 8, 16};
-  int best[2] = {8, 8};
   const bool log = std::getenv("RTROM_TUNE_LOG") && std::atoi(std::getenv("RTROM_TUNE_LOG"));
   int rc = RTROM_OK;
+  // one warm-up and three timed runs of f; the average in ms, or -1 on error
+  auto timed = [&](auto &&f) -> float {
+    f();
+    float ms = 0.0f;
+    if (hipEventRecord(e0, s) != hipSuccess) return -1.0f;
+    for (int r = 0; r < 3; ++r) f();
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess || hipGetLastError() != hipSuccess)
+      return -1.0f;
+    return ms / 3.0f;
+  };
+  const int depths[4] = {2, 4, 8, 16};
+  PlaneTune best{8, 8, 32};
   for (int prec = 0; prec < 2 && rc == RTROM_OK; ++prec) {
     float tbest = 1e30f;
     for (int pd : depths) {
-      auto launch = [&] {
+      const float ms = timed([&] {
         if (prec == 0) launch_si_sweep<float>(pd, grid, block, s, A);
         else launch_si_sweep<double>(pd, grid, block, s, A);
-      };
-      launch();
-      float ms = 0.0f;
-      if (hipEventRecord(e0, s) != hipSuccess) rc = RTROM_EDEVICE;
-      for (int r = 0; r < 3; ++r) launch();
-      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-          hipEventElapsedTime(&ms, e0, e1) != hipSuccess || hipGetLastError() != hipSuccess)
+      });
+      if (ms < 0.0f) {
         rc = RTROM_EDEVICE;
-      if (rc != RTROM_OK) break;
+        break;
+      }
       if (log)
         std::fprintf(stderr, "rtrom tune: plane %dx%d, %d folded ordinates, %s SI sweep, depth %2d: %.1f us\n", A.nx,
-                     A.ny, A.ndf, prec ? "FP64" : "FP32", pd, 1e3f * ms / 3.0f);
+                     A.ny, A.ndf, prec ? "FP64" : "FP32", pd, 1e3f * ms);
       if (ms < tbest) {
         tbest = ms;
-        best[prec] = pd;
+        (prec ? best.pd64 : best.pd32) = pd;
       }
+    }
+  }
+  float tbest = 1e30f;
+  for (int te : {32, 16}) {
+    if (rc != RTROM_OK) break;
+    H->dsa_tile = te;
+    const float ms = timed([&] { (void)dsa_solve(p, H, H->y, H->rp); });
+    if (ms < 0.0f) {
+      rc = RTROM_EDEVICE;
+      break;
+    }
+    if (log)
+      std::fprintf(stderr, "rtrom tune: plane %dx%d, DSA (%d Chebyshev iterations), tile %d: %.1f us\n", A.nx, A.ny,
+                   H->cheb_iters, te, 1e3f * ms);
+    if (ms < tbest) {
+      tbest = ms;
+      best.tile = te;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != RTROM_OK) {
-    rt_set_error("plane: sweep tuning failed");
+    rt_set_error("plane: tuning failed");
     return rc;
   }
-  H->pd32 = best[0];
-  H->pd64 = best[1];
-  rt_log(2, "plane %dx%d, %d folded ordinates: SI sweep prefetch depths %d (FP32) / %d (FP64), tuned", A.nx, A.ny,
-         A.ndf, H->pd32, H->pd64);
+  H->pd32 = best.pd32;
+  H->pd64 = best.pd64;
+  H->dsa_tile = fixed_tile ? fixed_tile : best.tile;
+  rt_log(2, "plane %dx%d, %d folded ordinates: SI sweep prefetch depths %d (FP32) / %d (FP64), DSA tile %d, tuned",
+         A.nx, A.ny, A.ndf, H->pd32, H->pd64, best.tile);
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  if (g_tune.emplace(key, std::make_pair(best[0], best[1])).second)
-    tune_cache_append(A.nx, A.ny, A.ndf, best[0], best[1]);
+  if (g_tune.emplace(key, best).second) tune_cache_append(A.nx, A.ny, A.ndf, best);
   return RTROM_OK;
 }
 
@@ -1329,7 +1375,7 @@ int rt_plane_create(rtrom_problem *p) {
   // the SI sweep's prefetch depth for this grid shape (the source is zero
   // until the first step writes it)
   PH(hipMemsetAsync(H->A.srcq, 0, 4 * (size_t)H->A.SQ * 8, p->stream));
-  const int tr = tune_si_sweep(p, H);
+  const int tr = tune_plane(p, H);
   if (tr != RTROM_OK) return tr;
   // b~^0 from f^0
   return rt_plane_rhs(p);
@@ -1387,15 +1433,19 @@ static int dsa_solve(rtrom_problem *p, PlaneHost *H, const double *y, const doub
   S.K = H->cheb_iters;
   S.c1 = H->cheb_c;
   S.c2 = H->cheb_c + S.K;
-  S.ntx = (H->A.nx + DT - 1) / DT;
-  S.ntiles = S.ntx * ((H->A.ny + DT - 1) / DT);
+  const int te = H->dsa_tile;
+  S.ntx = (H->A.nx + te - 1) / te;
+  S.ntiles = S.ntx * ((H->A.ny + te - 1) / te);
   S.inv_theta = 1.0 / H->cheb_theta;
   hipStream_t s = p->stream;
-  hipLaunchKernelGGL(k_dsa_init, dim3(S.ntiles), dim3(DTHR), 0, s, S);
+  if (te == 16) hipLaunchKernelGGL(k_dsa_init<16>, dim3(S.ntiles), dim3(256), 0, s, S);
+  else hipLaunchKernelGGL(k_dsa_init<32>, dim3(S.ntiles), dim3(1024), 0, s, S);
   int cur = 0;
   for (int done = 0; done < S.K; done += DS) {
     const int nit = std::min(DS, S.K - done);
-    hipLaunchKernelGGL(k_dsa_block, dim3(S.ntiles), dim3(DTHR), 0, s, S, done, nit, (int)(done + nit >= S.K), cur);
+    const int last = done + nit >= S.K;
+    if (te == 16) hipLaunchKernelGGL(k_dsa_block<16>, dim3(S.ntiles), dim3(DTHR), 0, s, S, done, nit, last, cur);
+    else hipLaunchKernelGGL(k_dsa_block<32>, dim3(S.ntiles), dim3(DTHR), 0, s, S, done, nit, last, cur);
     cur ^= 1;
   }
   PH(hipGetLastError());

@@ -72,31 +72,33 @@ p.close()
 
 def test_tune_cache_file_round_trip(tmp_path):
     """RTROM_TUNE_CACHE: the first process tunes the 2D sweep's prefetch
-    depths for the grid shape and appends them to the file; a later process
-    takes the file's choice without tuning, and (the depth changes only how
-    far ahead loads are issued) reaches bitwise the same result."""
+    depths and the DSA tile for the grid shape and appends them to the file;
+    a later process takes the file's choice without tuning, and (neither
+    choice changes any cell's arithmetic) reaches bitwise the same result."""
     cache = tmp_path / "tune.txt"
     print("diagnostics: tuning cache, first process", flush=True)
     env = dict(os.environ, RTROM_LOG="2", RTROM_TUNE_CACHE=str(cache))
-    env.pop("RTROM_PLANE_PD", None)
-    env.pop("RTROM_TUNE", None)
+    for k in ("RTROM_PLANE_PD", "RTROM_TUNE", "RTROM_DSA_TILE"):
+        env.pop(k, None)
     a = tmp_path / "a.npy"
     r = subprocess.run([sys.executable, "-c", TUNE_CODE, str(a)], cwd=ROOT, env=env, capture_output=True, text=True,
                        timeout=240)
     assert r.returncode == 0, r.stderr[-2000:]
-    assert re.search(r"plane 40x40, 16 folded ordinates: SI sweep prefetch depths \d+ \(FP32\) / \d+ \(FP64\), tuned",
-                     r.stderr), r.stderr[-2000:]
+    assert re.search(r"plane 40x40, 16 folded ordinates: SI sweep prefetch depths \d+ \(FP32\) / \d+ \(FP64\), "
+                     r"DSA tile (16|32), tuned", r.stderr), r.stderr[-2000:]
     lines = cache.read_text().splitlines()
-    assert len(lines) == 1 and re.fullmatch(r"plane_sweep_pd 40 40 16 (2|4|8|16) (2|4|8|16)", lines[0]), lines
+    assert len(lines) == 1 and re.fullmatch(r"plane_tune 40 40 16 (2|4|8|16) (2|4|8|16) (16|32)", lines[0]), lines
+    tuned_tile = int(lines[0].split()[-1])
+    other = 48 - tuned_tile
     # a cached choice other than the tuned one is taken as it is
-    cache.write_text("not a cache line\nplane_sweep_pd 40 40 16 2 16\n")
+    cache.write_text(f"not a cache line\nplane_tune 40 40 16 2 16 {other}\n")
     print("diagnostics: tuning cache, second process", flush=True)
     b = tmp_path / "b.npy"
     r = subprocess.run([sys.executable, "-c", TUNE_CODE, str(b)], cwd=ROOT, env=env, capture_output=True, text=True,
                        timeout=240)
     assert r.returncode == 0, r.stderr[-2000:]
-    assert "SI sweep prefetch depths 2 (FP32) / 16 (FP64), cached" in r.stderr, r.stderr[-2000:]
+    assert f"SI sweep prefetch depths 2 (FP32) / 16 (FP64), DSA tile {other}, cached" in r.stderr, r.stderr[-2000:]
     assert "tuned" not in r.stderr
-    assert cache.read_text().splitlines()[-1] == "plane_sweep_pd 40 40 16 2 16"
+    assert cache.read_text().splitlines()[-1] == f"plane_tune 40 40 16 2 16 {other}"
     import numpy as np
     np.testing.assert_array_equal(np.load(a), np.load(b))

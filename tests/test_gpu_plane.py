@@ -206,6 +206,24 @@ def test_plane_batch_equals_alone_bitwise():
         assert a.stats()["si_iters_total"] == b.stats()["si_iters_total"]
 
 
+@pytest.mark.parametrize("n", [40, 70])
+def test_plane_dsa_tile_does_not_change_results(monkeypatch, n):
+    """The autotuned tile edge of the Chebyshev DSA kernels (16 or 32 cells,
+    each launch recomputing its halo) leaves every cell's arithmetic as it
+    is: the same march at both tiles is bitwise the same (a grid of several
+    tiles with a ragged edge at either size)."""
+    spec = W.random_plane(72, n, 8, 4, method="rom", precision="mixed", nsteps=10)
+    monkeypatch.setenv("RTROM_PLANE_PD", "8,8")
+    out = []
+    for tile in (32, 16):
+        monkeypatch.setenv("RTROM_DSA_TILE", str(tile))
+        g = rtrom.Problem(spec)
+        g.march(spec.nsteps)
+        out.append(g.rho())
+        g.close()
+    assert np.array_equal(out[0], out[1])
+
+
 def test_plane_sweep_prefetch_depth_does_not_change_results(monkeypatch):
     """The autotuned prefetch depth of the SI sweep only schedules loads: the
     same problem run at depths 2, 4, 8 and 16 gives bitwise the same march."""
