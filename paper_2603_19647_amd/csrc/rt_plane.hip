@@ -936,7 +936,12 @@ struct PlaneHost {
   float *src32 = nullptr;
   double *cr = nullptr, *cx = nullptr, *cd0 = nullptr, *cd1 = nullptr;
   double *diag = nullptr, *ax = nullptr, *ay = nullptr;
-  double *blkmax = nullptr, *res = nullptr, *res_h = nullptr;
+  double *blkmax = nullptr, *res = nullptr;
+  // the stop test's two norms, written by the reduce kernel straight into
+  // coherent pinned host memory (res_hd: its device address), and a pinned
+  // copy of the step state: a round trip per SI iteration without a copy
+  double *res_h = nullptr, *res_hd = nullptr;
+  RtState *st_h = nullptr;
   double *rpart = nullptr, *rcoef = nullptr;
   double *yp = nullptr, *rp2 = nullptr;  // McClarren-Haut: y_{l-1}, rho^{(l-2)}
   MhGrid *mh = nullptr;                  // McClarren-Haut model state
@@ -1301,7 +1306,9 @@ int rt_plane_create(rtrom_problem *p) {
   }
   Inst &I = p->hinst;
   PH(hipMemcpyAsync(dmx, hm.data(), hm.size() * 8, hipMemcpyHostToDevice, p->stream));
-  PH(hipHostMalloc((void **)&H->res_h, 64, hipHostMallocDefault));
+  PH(hipHostMalloc((void **)&H->res_h, 64, hipHostMallocCoherent | hipHostMallocMapped));
+  PH(hipHostGetDevicePointer((void **)&H->res_hd, H->res_h, 0));
+  PH(hipHostMalloc((void **)&H->st_h, sizeof(RtState), hipHostMallocDefault));
   A.nx = nx;
   A.ny = ny;
   A.nc = nc;
@@ -1387,6 +1394,7 @@ void rt_plane_destroy(rtrom_problem *p) {
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   if (H->mem) (void)hipFree(H->mem);
   if (H->res_h) (void)hipHostFree(H->res_h);
+  if (H->st_h) (void)hipHostFree(H->st_h);
   delete H;
   p->plane = nullptr;
 }
@@ -1468,12 +1476,12 @@ static int rom_apply_grid(rtrom_problem *p, PlaneHost *H, const RomDev &R, const
 // residual of the current y against rp: ||y - rp||_inf, ||y||_inf
 static int read_residual(rtrom_problem *p, PlaneHost *H, double *dn, double *yn) {
   hipLaunchKernelGGL(k_plane_maxreduce, dim3(1), dim3(256), 0, p->stream, (const double *)H->blkmax, H->A.nblk,
-                     H->res);
+                     H->res_hd);
   PH(hipGetLastError());
-  PH(hipMemcpyAsync(H->res_h, H->res, 16, hipMemcpyDeviceToHost, p->stream));
   PH(hipStreamSynchronize(p->stream));
-  *dn = H->res_h[0];
-  *yn = H->res_h[1];
+  const volatile double *r = H->res_h;
+  *dn = r[0];
+  *yn = r[1];
   return RTROM_OK;
 }
 
@@ -1485,9 +1493,9 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
   const int nc = A.nc, nblk = A.nblk;
   const dim3 qgrid(A.nsblk, 4);
   hipStream_t s = p->stream;
-  RtState st;
-  PH(hipMemcpyAsync(&st, I.st, sizeof(RtState), hipMemcpyDeviceToHost, s));
+  PH(hipMemcpyAsync(H->st_h, I.st, sizeof(RtState), hipMemcpyDeviceToHost, s));
   PH(hipStreamSynchronize(s));
+  const RtState st = *H->st_h;
   const int rom = (I.method == RT_ROM);
   const int mixed = (I.precision == RT_MIXED);
   const int cur = (int)(st.steps & 1);
