@@ -143,6 +143,14 @@ typedef struct {
   int32_t mh_rank;     /* McClarren-Haut pairs per model (a full model restarts
                           from the newest pair), 0 = r_max; at most 20 */
   int32_t scheme;      /* rtrom_scheme */
+  int32_t pad_;        /* zero */
+  double lu_tol;       /* a reduced ROM system (Sec. 3.2, eq. dmd-ig / dmd-sa)
+                          whose LU meets a pivot below lu_tol times its largest
+                          entry is singular, and the step falls back to the
+                          plain initial guess or DSA for that ROM (counted in
+                          rom_fallbacks).  0 = 1e-14; must be finite and >= 0.
+                          A value >= 1 makes every reduced system singular,
+                          which forces the fallback path (a test of it) */
 } rtrom_problem_desc;
 
 typedef struct {
@@ -154,8 +162,10 @@ typedef struct {
   int32_t n0, n1;             /* eq. ig_stop step N0; eq. pc_stop count N1 */
   int32_t rank_ig, rank_pc;   /* current ROM ranks */
   int32_t nonconverged_steps;
-  int32_t rom_fallbacks;      /* steps where a singular reduced system forced
-                                 the plain initial guess or DSA */
+  int32_t rom_fallbacks;      /* times a ROM due to apply (initial guess,
+                                 correction, correction level) met a singular
+                                 reduced system, so that its step took the
+                                 plain initial guess or DSA instead */
   int64_t ig_updates, pc_updates; /* snapshots added to each ROM */
   int64_t fp32_sweeps;        /* mixed mode: SI sweeps done in FP32 */
   double last_residual;       /* ||y - rho||_inf / ||y||_inf of the last step */

@@ -36,7 +36,7 @@ class OrcDesc(ctypes.Structure):
         ("r_max", ctypes.c_int32), ("abs_up_norm", ctypes.c_int32),
         ("precond", ctypes.c_int32), ("time_scheme", ctypes.c_int32),
         ("pc_levels", ctypes.c_int32), ("mh_rank", ctypes.c_int32),
-        ("scheme", ctypes.c_int32),
+        ("scheme", ctypes.c_int32), ("pad_", ctypes.c_int32), ("lu_tol", ctypes.c_double),
     ]
 
 
@@ -264,6 +264,7 @@ class OracleProblem:
         d.pc_levels = int(spec.pc_levels)
         d.mh_rank = int(spec.mh_rank)
         d.scheme = SCHEME[spec.scheme]
+        d.lu_tol = float(spec.lu_tol)
         self.h = lib().orc_create(ctypes.byref(d))
         if not self.h:
             raise ValueError("oracle rejected the problem description")

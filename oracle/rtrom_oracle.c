@@ -76,6 +76,9 @@ typedef struct {
   int32_t pc_levels;   /* sequential correction ROMs for iterations 1..pc_levels (0 = 1) */
   int32_t mh_rank;     /* McClarren-Haut pairs per model (0 = r_max) */
   int32_t scheme;      /* ORC_FV or ORC_DG1 */
+  int32_t pad_;
+  double lu_tol;       /* singular-pivot threshold of the reduced ROM systems
+                          relative to their largest entry (0 = 1e-14) */
 } orc_desc;
 
 typedef struct {
@@ -237,8 +240,8 @@ void orc_jacobi_svd(int rows, int cols, const double *K, double *Uc, double *s,
 }
 
 /* LU factorisation with partial pivoting, in place (row-major n x n).
- * Returns 0 on success, 1 if a pivot is below 1e-14 * max|A| (singular). */
-int orc_lu_factor(int n, double *A, int *piv) {
+ * Returns 0 on success, 1 if a pivot is below tol * max|A| (singular). */
+static int lu_factor_tol(int n, double *A, int *piv, double tol) {
   double amax = 0.0;
   for (int i = 0; i < n * n; ++i)
     if (fabs(A[i]) > amax) amax = fabs(A[i]);
@@ -255,7 +258,7 @@ int orc_lu_factor(int n, double *A, int *piv) {
         A[p * n + j] = t;
       }
     double akk = A[k * n + k];
-    if (fabs(akk) < 1e-14 * amax || akk == 0.0) {
+    if (fabs(akk) < tol * amax || akk == 0.0) {
       bad = 1;
       continue;
     }
@@ -267,6 +270,8 @@ int orc_lu_factor(int n, double *A, int *piv) {
   }
   return bad;
 }
+
+int orc_lu_factor(int n, double *A, int *piv) { return lu_factor_tol(n, A, piv, 1e-14); }
 
 void orc_lu_solve(int n, const double *LU, const int *piv, double *b) {
   for (int k = 0; k < n; ++k) {
@@ -298,12 +303,14 @@ typedef struct {
   int *piv;
   int lu_ok;
   int last_deficient;
+  double lu_tol; /* singular-pivot threshold of the reduced system (R17) */
 } orc_rom;
 
 static int rom_init(orc_rom *m, int nc, int rmax) {
   memset(m, 0, sizeof(*m));
   m->nc = nc;
   m->rmax = rmax;
+  m->lu_tol = 1e-14;
   m->U = (double *)calloc((size_t)(rmax + 1) * nc, sizeof(double));
   m->W = (double *)calloc((size_t)(rmax + 1) * nc, sizeof(double));
   m->S = (double *)calloc(rmax + 1, sizeof(double));
@@ -333,7 +340,7 @@ static void rom_refresh(orc_rom *m) {
   for (int i = 0; i < r; ++i)
     for (int j = 0; j < r; ++j)
       m->Ar[i * r + j] = dot(nc, m->U + (size_t)i * nc, m->W + (size_t)j * nc) / m->S[j];
-  m->lu_ok = (r > 0) && !orc_lu_factor(r, m->Ar, m->piv);
+  m->lu_ok = (r > 0) && !lu_factor_tol(r, m->Ar, m->piv, m->lu_tol);
 }
 
 /* Add snapshot pair (x, b) per App. B.  truncate: keep s_i / sum(s) > eps.
@@ -688,6 +695,7 @@ static int desc_valid(const orc_desc *d) {
   if (d->time_scheme != ORC_BE && d->time_scheme != ORC_BDF2) return 0;
   if (d->pc_levels < 0 || d->pc_levels > ORC_MAX_LEVELS) return 0;
   if (d->mh_rank < 0 || d->mh_rank > 64) return 0;
+  if (!(d->lu_tol >= 0.0) || !isfinite(d->lu_tol)) return 0;
   if (d->scheme != ORC_FV && !(d->scheme == ORC_DG1 && d->dim == 1)) return 0;
   if (!d->sigma_s || !d->sigma_a || !d->source) return 0;
   size_t nc = (size_t)d->nx * d->ny;
@@ -1124,6 +1132,10 @@ void *orc_create(const orc_desc *d) {
   }
   int bad = rom_init(&P->ig, nc, d->r_max);
   for (int k = 0; k < P->nlev; ++k) bad |= rom_init(&P->pc[k], nc, d->r_max);
+  if (d->lu_tol > 0.0) {
+    P->ig.lu_tol = d->lu_tol;
+    for (int k = 0; k < P->nlev; ++k) P->pc[k].lu_tol = d->lu_tol;
+  }
   if (bad) {
     orc_destroy(P);
     return NULL;

@@ -270,6 +270,7 @@ static rtrom_status validate(const rtrom_problem_desc *d) {
   if (d->time_scheme != RTROM_BE && d->time_scheme != RTROM_BDF2) return fail(RTROM_EINVAL, "unknown time_scheme");
   if (d->pc_levels < 0 || d->pc_levels > 4) return fail(RTROM_EINVAL, "pc_levels must be in 0..4");
   if (d->mh_rank < 0 || d->mh_rank > RT_RMAX) return fail(RTROM_EINVAL, "mh_rank must be in 0..20");
+  if (!(d->lu_tol >= 0.0) || !std::isfinite(d->lu_tol)) return fail(RTROM_EINVAL, "lu_tol must be finite and >= 0");
   const bool variant = d->precond == RTROM_PC_MH || d->time_scheme == RTROM_BDF2;
   if (variant && d->dim == 1 && d->nx > RT_WAVE_MAX_CELLS)
     return fail(RTROM_EINVAL, "McClarren-Haut and BDF2 run on slabs of at most 2048 cells");
@@ -605,6 +606,7 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
     roms[r]->perm = (int *)D(RT_RMAX * 4);
     roms[r]->pend = (RomPend *)D(sizeof(RomPend));
     roms[r]->work = (RomWork *)D(sizeof(RomWork));
+    roms[r]->lu_tol = d->lu_tol > 0.0 ? d->lu_tol : 1e-14;
     {
       const size_t nb = part_rows(d->dim, nc);
       double *parts = D(3 * nb * RT_NPART * 8);

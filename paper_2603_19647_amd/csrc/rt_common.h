@@ -74,6 +74,7 @@ struct RomDev {
   int *perm;    // [RT_RMAX]
   RomPend *pend;
   RomWork *work;
+  double lu_tol;  // pivot threshold of the reduced system's LU, relative to its largest entry
 };
 
 // Device-resident state of the phase machine (Alg. 2) and counters.

@@ -118,8 +118,8 @@ __device__ __forceinline__ int *rom_luok_of(RtState *st, int z) {
 // are not moved: step k picks the pivot among the rows not yet used (largest
 // |a_ik|, lowest row on ties), reads the pivot row with lane reads and
 // eliminates below it in place, so every row keeps its own multipliers, as in
-// a factorisation with row interchanges.  A pivot below 1e-14 max|A| marks
-// the system singular.  Writes the factors in pivot order (stride RT_RMAX)
+// a factorisation with row interchanges.  A pivot below tol max|A| marks the
+// system singular (tol: the ROM's lu_tol, 1e-14 unless the caller set it).  Writes the factors in pivot order (stride RT_RMAX)
 // and the row permutation to global memory and returns 1 if singular.  Must
 // be called by the whole workgroup; A's first row is overwritten (it carries
 // the pivot rows once the matrix is in registers).
@@ -139,7 +139,7 @@ __device__ __forceinline__ double lane_read(double v, int l) {
 
 // The factorisation itself, by wave 0 alone (no workgroup barrier): the
 // calling wave must be wave 0; returns 1 if singular (every lane).
-__device__ inline int lu_factor_rows(double *A, int n, double *LUg, int *permg) {
+__device__ inline int lu_factor_rows(double *A, int n, double *LUg, int *permg, double tol) {
   static_assert(RT_RMAX <= 32, "rows live in the first two DPP rows of the wave");
   int bad;
   {
@@ -186,7 +186,7 @@ __device__ inline int lu_factor_rows(double *A, int n, double *LUg, int *permg) 
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         const double akk = prow[k];
-        if (akk == 0.0 || fabs(akk) < 1e-14 * amax) {
+        if (akk == 0.0 || fabs(akk) < tol * amax) {
           bad = 1;
           continue;
         }
@@ -208,10 +208,11 @@ __device__ inline int lu_factor_rows(double *A, int n, double *LUg, int *permg) 
   return bad;
 }
 
-__device__ inline int lu_factor_wave(double *A, int *perm_lds, int n, double *LUg, int *permg, int *flag) {
+__device__ inline int lu_factor_wave(double *A, int *perm_lds, int n, double *LUg, int *permg, int *flag,
+                                     double tol) {
   (void)perm_lds;
   if (threadIdx.x < 64) {
-    const int bad = lu_factor_rows(A, n, LUg, permg);
+    const int bad = lu_factor_rows(A, n, LUg, permg, tol);
     if (threadIdx.x == 0) *flag = bad;
   }
   __syncthreads();
@@ -726,7 +727,7 @@ __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, in
     if constexpr (DEFER_LU) {
       if (tid == 0) sm.ibuf[2] = 1;
     } else {
-      luok = !lu_factor_wave(sm.A, sm.perm, 1, R.LU, R.perm, &sm.ibuf[0]);
+      luok = !lu_factor_wave(sm.A, sm.perm, 1, R.LU, R.perm, &sm.ibuf[0], R.lu_tol);
     }
     rank = 1;
     return 0;
@@ -823,7 +824,7 @@ __device__ inline int isvd_core(const RomDev &R, const RomWork &Wk, int rmax, in
   if constexpr (DEFER_LU) {
     if (tid == 0) sm.ibuf[2] = k;
   } else {
-    luok = !lu_factor_wave(sm.A, sm.perm, k, R.LU, R.perm, &sm.ibuf[0]);
+    luok = !lu_factor_wave(sm.A, sm.perm, k, R.LU, R.perm, &sm.ibuf[0], R.lu_tol);
   }
   rank = k;
   return deficient;
@@ -835,7 +836,7 @@ __device__ inline int isvd_lu(const RomDev &R, RomSmem &sm) {
   __syncthreads();
   const int n = sm.ibuf[2];
   if (n == 0) return -1;  // uniform
-  return !lu_factor_wave(sm.A, sm.perm, n, R.LU, R.perm, &sm.ibuf[0]);
+  return !lu_factor_wave(sm.A, sm.perm, n, R.LU, R.perm, &sm.ibuf[0], R.lu_tol);
 }
 
 // p = v - U a2 for one cell from its old basis row (the second Gram-Schmidt
@@ -932,7 +933,7 @@ __device__ inline void rom_rotate_own_lu(const Inst &I, const RomDev &R, const R
   if (threadIdx.x == 0) sm.ibuf[3] = 0;
   __syncthreads();
   if (wave == 0 && n_lu > 0) {
-    const int bad = lu_factor_rows(sm.A, n_lu, R.LU, R.perm);
+    const int bad = lu_factor_rows(sm.A, n_lu, R.LU, R.perm, R.lu_tol);
     if (lane == 0) sm.ibuf[0] = bad;
   }
   const int nc = I.nc, ld = I.ld;

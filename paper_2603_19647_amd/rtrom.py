@@ -41,7 +41,7 @@ class Desc(ctypes.Structure):
         ("r_max", ctypes.c_int32), ("flags", ctypes.c_uint64),
         ("precond", ctypes.c_int32), ("time_scheme", ctypes.c_int32),
         ("pc_levels", ctypes.c_int32), ("mh_rank", ctypes.c_int32),
-        ("scheme", ctypes.c_int32),
+        ("scheme", ctypes.c_int32), ("pad_", ctypes.c_int32), ("lu_tol", ctypes.c_double),
     ]
 
 
@@ -181,6 +181,7 @@ def make_desc(spec, keep: list) -> Desc:
     d.pc_levels = int(spec.pc_levels)
     d.mh_rank = int(spec.mh_rank)
     d.scheme = SCHEME[spec.scheme]
+    d.lu_tol = float(spec.lu_tol)
     return d
 
 

@@ -61,6 +61,7 @@ class ProblemSpec:
     pc_levels: int = 1  # sequential correction ROMs for iterations 1..pc_levels
     mh_rank: int = 0  # McClarren-Haut pairs per model, 0 = r_max
     scheme: str = "fv"  # spatial discretisation: "fv" or "dg1" (two unknowns per cell)
+    lu_tol: float = 0.0  # singular-pivot threshold of the reduced ROM systems (0 = 1e-14)
     single_wg: bool = False  # 1D: one workgroup even when marched alone (device mode only)
     nsteps: int = 1
     name: str = ""

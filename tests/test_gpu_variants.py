@@ -222,6 +222,28 @@ def test_bdf2_plane_mixed_meets_fp64_bar():
     assert g.stats()["nonconverged_steps"] == 0
 
 
+@pytest.mark.parametrize("kind", ["wave", "contiguous", "plane"])
+def test_singular_reduced_systems_fall_back_like_the_oracle(kind):
+    """The R17 fallback, forced from the host by a pivot threshold at which
+    every reduced ROM system is singular: each step takes the plain initial
+    guess and DSA, the ROMs still collect snapshots and change phase, and the
+    device's iterates, decisions and fallback count are the oracle's (FP64),
+    in the wave kernels, the contiguous-run kernels (more than 2048 cells)
+    and on an X-Y grid."""
+    if kind == "wave":
+        spec = W.random_slab(81, 256, 16, dt=0.01, tol=1e-10, method="rom", lu_tol=10.0, nsteps=30)
+    elif kind == "contiguous":
+        spec = W.random_slab(82, 3000, 16, dt=0.01, tol=1e-10, method="rom", lu_tol=10.0, nsteps=20)
+    else:
+        spec = W.random_plane(81, 24, 8, 4, dt=0.02, tol=1e-10, method="rom", lu_tol=10.0, nsteps=30)
+    say(f"forced ROM fallback, {kind}")
+    errs, o, g = step_both(spec, spec.nsteps)
+    assert (errs <= FP64_TOL).all(), errs.max()
+    assert_same_decisions(o, g)
+    np.testing.assert_array_equal(g.history()["fallback"], o.history()["fallback"])
+    assert g.stats()["rom_fallbacks"] == o.counters()["fallbacks"] > 0
+
+
 def test_variants_batched_with_default_instances_bitwise():
     """A batch mixing default, McClarren-Haut, BDF2 and combined instances:
     every instance marches to bitwise the result it reaches alone."""

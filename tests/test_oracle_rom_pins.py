@@ -188,3 +188,37 @@ def test_sec41_two_material_rom_matches_si_dsa_every_step():
     assert worst <= 1000 * sp.tol, worst
     assert set(b.history()["phase"]) == {1, 2, 3}
     assert b.counters()["si_total"] < a.counters()["si_total"]
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_singular_reduced_systems_fall_back_to_si_dsa(dim):
+    """R17 (a reduced ROM system whose LU meets a pivot below the threshold is
+    singular; the step then takes the plain initial guess and DSA for that
+    ROM).  With the threshold raised so that every reduced system is
+    singular, the ROM march IS the SI-DSA march: the same iterates, bitwise,
+    and the same sweep counts, while its ROMs still collect snapshots, change
+    phase and count a fallback on every step that had a ROM to apply."""
+    if dim == 1:
+        base = W.random_slab(81, 64, 8, dt=0.01, tol=1e-10, nsteps=30)
+    else:
+        base = W.random_plane(81, 12, 4, 2, dt=0.02, tol=1e-10, nsteps=30)
+    rom = oracle.OracleProblem(base.replace(method="rom", lu_tol=10.0))
+    ref = oracle.OracleProblem(base.replace(method="si_dsa"))
+    for _ in range(base.nsteps):
+        rom.step()
+        ref.step()
+        np.testing.assert_array_equal(rom.rho(), ref.rho())
+    hr, hs = rom.history(), ref.history()
+    np.testing.assert_array_equal(hr["iters"], hs["iters"])
+    c = rom.counters()
+    assert c["flag_ig"] == 1 and c["n0"] > 0, c
+    # every step after N0 fell back for the IG ROM, every step after N0 + N1
+    # for the PC ROM as well
+    assert c["flag_pc"] == 1, c
+    assert c["fallbacks"] == (base.nsteps - c["n0"]) + (base.nsteps - c["n0"] - c["n1"]), c
+    assert hr["fallback"][c["n0"]:].all() and not hr["fallback"][:c["n0"]].any()
+    # the same march at the default threshold uses its ROMs and differs
+    plain = oracle.OracleProblem(base.replace(method="rom"))
+    plain.march(base.nsteps)
+    assert plain.counters()["fallbacks"] == 0
+    assert plain.history()["iters"].sum() < hs["iters"].sum()
