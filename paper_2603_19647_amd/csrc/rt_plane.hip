@@ -936,7 +936,7 @@ struct PlaneHost {
   float *src32 = nullptr;
   double *cr = nullptr, *cx = nullptr, *cd0 = nullptr, *cd1 = nullptr;
   double *diag = nullptr, *ax = nullptr, *ay = nullptr;
-  double *blkmax = nullptr, *res = nullptr;
+  double *blkmax = nullptr;
   // the stop test's two norms, written by the reduce kernel straight into
   // coherent pinned host memory (res_hd: its device address), and a pinned
   // copy of the step state: a round trip per SI iteration without a copy
@@ -982,7 +982,7 @@ static size_t plane_bytes_for(const rtrom_problem_desc *d) {
   take(nc * 8 * 7);                 // y rp dvec cr cx cd0 cd1
   take(nc * 4);                     // src32
   take(nc * 8 * 3);                 // diag ax ay
-  take(nblk * 2 * 8 + 64);          // blkmax, res
+  take(nblk * 2 * 8 + 64);          // blkmax
   take(2 * (size_t)RT_CHEB_MAX * 8);               // Chebyshev coefficients
   take(nblk * RT_NPART * 8 + RT_RMAX * 8);  // DMD solve partials, coefficients
   take((size_t)g.ndf * 3 * 8);      // mx my w
@@ -1294,7 +1294,6 @@ int rt_plane_create(rtrom_problem *p) {
   H->ax = H->diag + nc;
   H->ay = H->ax + nc;
   H->blkmax = (double *)take((size_t)nblk * 2 * 8 + 64);
-  H->res = H->blkmax + 2 * (size_t)nblk;
   H->cheb_c = (double *)take(2 * (size_t)RT_CHEB_MAX * 8);
   H->rpart = (double *)take((size_t)nblk * RT_NPART * 8 + RT_RMAX * 8);
   H->rcoef = H->rpart + (size_t)nblk * RT_NPART;
