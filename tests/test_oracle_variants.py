@@ -330,3 +330,56 @@ def test_bdf2_rom_skips_the_start_step_and_matches_si_dsa():
     assert h["phase"].max() == 3
     err = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
     assert err.max() < 1e-9
+
+
+def _dense_step_2d(sp, ox, oy, w, fprev, fprev2, bdf2):
+    """The full X-Y upwind system of one step, assembled cell by cell from the
+    finite-volume balance of each ordinate and solved densely."""
+    n, nv = sp.nx, len(w)
+    h = sp.lx / n
+    N = n * n * nv
+    A = np.zeros((N, N))
+    b = np.zeros(N)
+    st = sp.sigma_s + sp.sigma_a
+    g = sp.inflow
+    for j in range(nv):
+        mx, my = abs(ox[j]) / h, abs(oy[j]) / h
+        sx, sy = (1 if ox[j] > 0 else -1), (1 if oy[j] > 0 else -1)
+        for iy in range(n):
+            for ix in range(n):
+                c = iy * n + ix
+                r = j * n * n + c
+                A[r, r] += (1.5 if bdf2 else 1.0) / sp.dt + st[c] + mx + my
+                ux, uy = ix - sx, iy - sy
+                if 0 <= ux < n:
+                    A[r, j * n * n + iy * n + ux] -= mx
+                else:
+                    b[r] += mx * (g[0] if sx > 0 else g[1])
+                if 0 <= uy < n:
+                    A[r, j * n * n + uy * n + ix] -= my
+                else:
+                    b[r] += my * (g[2] if sy > 0 else g[3])
+                for k in range(nv):
+                    A[r, k * n * n + c] -= sp.sigma_s[c] * w[k]
+                hist = (2.0 * fprev[j, c] - 0.5 * fprev2[j, c]) / sp.dt if bdf2 else fprev[j, c] / sp.dt
+                b[r] += hist + sp.source[c]
+    return np.linalg.solve(A, b).reshape(nv, n * n)
+
+
+@pytest.mark.parametrize("method", ["si_dsa", "rom"])
+def test_bdf2_dense_2d(method):
+    """On an X-Y grid: the full (N_c N_v)^2 BDF2 system (Sec. 2.1's BDF
+    alternative, (3 f^n - 4 f^{n-1} + f^{n-2}) / (2 dt)) assembled and solved
+    densely each step, backward Euler for the first; the oracle's rho and f
+    match it at every step, for both methods."""
+    sp = W.random_plane(8, 6, 4, 2, inflow=(0.5, 0.0, 0.2, 0.1), dt=0.05, tol=1e-12, method=method,
+                        time_scheme="bdf2")
+    o = oracle.OracleProblem(sp)
+    ox, oy, _, w = o.quadrature()
+    nv = len(w)
+    f2, f = np.zeros((nv, 36)), np.zeros((nv, 36))
+    for n in range(1, 7):
+        o.step()
+        f2, f = f, _dense_step_2d(sp, ox, oy, w, f, f2, n >= 2)
+        np.testing.assert_allclose(o.rho(), w @ f, rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(o.f(), f, rtol=1e-9, atol=1e-12)
