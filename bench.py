@@ -490,7 +490,7 @@ def cpu_baseline_batch(specs, steps):
 # --------------------------------------------------------------------------
 
 def run_serving(rtrom, W, count, budget, slots, seed=5):
-    """C5: closed-loop saturation run (everything submitted at once) gives the
+    """The serving stream: a closed-loop saturation run (everything submitted at once) gives the
     capacity; then Poisson arrivals at 80 % of it, with per-step and per-march
     latencies and the queueing delay seen by the client."""
     import numpy as np
