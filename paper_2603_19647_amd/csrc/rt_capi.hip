@@ -710,9 +710,10 @@ extern "C" rtrom_status rtrom_create_problem(const rtrom_problem_desc *d, rtrom_
   ok = ok && H2D(I.rho, rho0.data(), nc * 8);
   if (d->f0)
     for (int j = 0; j < nv && ok && d->dim == 1; ++j) ok = H2D(I.f + (size_t)j * nc, rho0.data(), nc * 8);
-  // initial phase-machine state: everything zero
+  // initial phase-machine state: everything zero, Phase I ahead
   RtState st0;
   memset(&st0, 0, sizeof(st0));
+  st0.phase = 1;
   ok = ok && H2D(I.st, &st0, sizeof(st0));
   for (int r = 0; r < nrom && ok; ++r) ok = H2D(roms[r]->work, &rom_work_init[r], sizeof(RomWork));
   if (!ok) return bail(RTROM_EDEVICE, "upload failed");
