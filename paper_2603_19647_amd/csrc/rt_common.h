@@ -92,7 +92,7 @@ struct RtState {
   // kernel applied in the step in flight (bit l - 1)
   int flag_pl[RT_XLEV], rank_pl[RT_XLEV], lu_ok_pl[RT_XLEV], n_pl[RT_XLEV];
   long long upd_pl[RT_XLEV];
-  int used_mask;
+  int used_mask;  // bit l - 1: level l applied; bit 8 + l - 2: level l's stored iterate was FP64-swept
   int lv_fb;  // levels >= 2 that were due but could not apply (X-Y loop; the slab kernels pass it directly)
 };
 

@@ -1580,7 +1580,10 @@ static int plane_one_step(rtrom_problem *p, PlaneHost *H) {
       const int k = lc - 2;
       hipLaunchKernelGGL(k_plane_copy, dim3(nblk), dim3(BLK), 0, s, nc, (const double *)H->y, I.ylev[k]);
       hipLaunchKernelGGL(k_plane_copy, dim3(nblk), dim3(BLK), 0, s, nc, (const double *)H->rp, I.rlev[k]);
-      const bool due = st.flag_pl[k] && ((used_mask >> (lc - 2)) & 1);
+      // mixed precision: a level ROM is built from and applied to FP64-swept
+      // iterates only (an FP32-refined one carries its increments' rounding)
+      if (exact) used_mask |= 1 << (8 + k);
+      const bool due = st.flag_pl[k] && ((used_mask >> (lc - 2)) & 1) && (!mixed || exact);
       if (due && !st.lu_ok_pl[k]) lv_fb++;
       lev_apply = due && st.lu_ok_pl[k];
     }

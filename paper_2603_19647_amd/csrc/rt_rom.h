@@ -1046,6 +1046,8 @@ __device__ __forceinline__ void rom_plan_levels(const Inst &I, const RtState *st
   for (int l = 2; l <= I.nlev; ++l) {
     const int k = l - 2;
     if (!below_done || iters <= l) break;
+    // mixed precision: no pair from an FP32-refined iterate of level l
+    if (I.precision == RT_MIXED && !((used_mask >> (8 + k)) & 1)) break;
     const int done = st->flag_pl[k];
     if (!done) {
       P.lv_on[k] = 1;

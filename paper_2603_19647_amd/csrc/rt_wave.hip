@@ -665,7 +665,10 @@ __global__ void __launch_bounds__(WNT) k_si_wave(const Inst *__restrict__ insts)
           stg(&I.ylev[k][c0 + t], y[t]);
           stg(&I.rlev[k][c0 + t], rp[t]);
         }
-      const bool due = st->flag_pl[k] && ((used_mask >> (lc - 2)) & 1);
+      // mixed precision: a level ROM is built from and applied to FP64-swept
+      // iterates only (an FP32-refined one carries its increments' rounding)
+      if (exact) used_mask |= 1 << (8 + k);
+      const bool due = st->flag_pl[k] && ((used_mask >> (lc - 2)) & 1) && (!mixed || exact);
       const int luok = st->lu_ok_pl[k];
       if (due && !luok) lv_fb++;
       lev_apply = due && luok;
